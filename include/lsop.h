@@ -1,0 +1,194 @@
+/*
+ * lsop: preconditioned Lippmann-Schwinger solver for the 2D Helmholtz equation
+ * on one MI355X (gfx950).  C ABI of liblsop.so.
+ *
+ * Method: Eikrem, Naevdal & Jakobsen, "Iterative solution of the
+ * Lippmann-Schwinger equation in strongly scattering acoustic media by
+ * randomized construction of preconditioners" (arXiv 2005.01372).
+ *
+ * Conventions shared by every entry point
+ *  - Grid: nx x nz cells of size h (metres); cell (i, j), i horizontal,
+ *    j depth (j = 0 is the top row).  Vectors are stored cell-major with j
+ *    fastest, n = i * nz + j (the column-wise ordering of Section 2.4).
+ *  - Complex data is interleaved (re, im).  A batch of nvec vectors is
+ *    [nvec][nx][nz] contiguous.  The element type of device vectors is the
+ *    operator's dtype: float2 for LSOP_C64, double2 for LSOP_C128 and
+ *    LSOP_MIXED.
+ *  - Pointers named *_dev are device pointers (caller-owned, e.g. torch
+ *    tensors), *_host are host pointers.  `stream` is a hipStream_t (NULL =
+ *    default stream).  Calls enqueue work asynchronously on `stream` unless
+ *    stated otherwise.
+ *  - Every call returns an lsop_status.  Arguments are validated on the host
+ *    before any launch; on LSOP_EINVAL / LSOP_EUNSUPPORTED outputs are left
+ *    untouched.  lsop_last_error() describes the last failure of the calling
+ *    thread.  No C++ exception crosses this boundary.
+ *  - Handles own their device state (allocated at *_create, freed at
+ *    *_destroy).  A handle must not be used from two streams at once.
+ */
+#ifndef LSOP_H
+#define LSOP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LSOP_OK = 0,
+  LSOP_EINVAL = 1,        /* bad argument (sizes, NaN/non-positive velocity, f <= 0, ...) */
+  LSOP_ENOMEM = 2,        /* device allocation failed or batch exceeds capacity */
+  LSOP_EHIP = 3,          /* HIP runtime error */
+  LSOP_NOT_CONVERGED = 4, /* series hit max_iter; best iterate and info are written */
+  LSOP_DIVERGED = 5,      /* residual non-finite or rising for 5 consecutive iterations */
+  LSOP_ESINGULAR = 6,     /* I_r - W^H U is numerically singular (eq. 12) */
+  LSOP_EUNSUPPORTED = 7   /* grid larger than the largest supported FFT length, bad dtype */
+} lsop_status;
+
+typedef enum { LSOP_C64 = 0, LSOP_C128 = 1, LSOP_MIXED = 2 } lsop_dtype;
+
+/* Operator modes (x, y are [nvec][nx][nz]):
+ *  LSOP_MODE_A      y = x - G0 V x            (I - G0 V of eq. 5)
+ *  LSOP_MODE_G0V    y = G0 V x                (the product of Section 2.2)
+ *  LSOP_MODE_AH     y = x - V^H G0^H x        (adjoint of A)
+ *  LSOP_MODE_VHG0H  y = V^H G0^H x            (Alg. 2 steps 4-5, T read as conjugate transpose)
+ * G0 V acts as (G0 V x)_m = sum_n K(m - n) chi_n x_n with K the integral of
+ * (i/4) H0^(1)(k0 |x|) over the (equal-area disk of the) source cell, chi the
+ * contrast of eq. (1).  It is evaluated by a zero-padded FFT convolution with
+ * the symmetric circulant extension of the first row of G0 (Section 2.2). */
+typedef enum { LSOP_MODE_A = 0, LSOP_MODE_G0V = 1, LSOP_MODE_AH = 2, LSOP_MODE_VHG0H = 3 } lsop_mode;
+
+typedef struct lsop_op lsop_op;
+typedef struct lsop_precond lsop_precond;
+
+typedef struct {
+  int nx, nz;      /* grid */
+  int lx, lz;      /* FFT lengths: padded extent is 2*lx x 2*lz >= (2nx-1) x (2nz-1) */
+  int dtype;       /* lsop_dtype */
+  int max_vec;     /* vectors per internal batch */
+  size_t state_bytes;  /* device bytes held by the handle */
+} lsop_op_info;
+
+/* Plan an operator for an nx x nz grid and allocate its device state.
+ * dtype: LSOP_C64 (complex float, FP32 accumulation), LSOP_C128 (complex
+ * double) or LSOP_MIXED (complex double interface and outer residuals, with
+ * complex-float inner solves; see series_solve).  max_vec bounds the
+ * vectors processed per internal batch (larger calls are chunked).
+ * Errors: EINVAL (nx, nz < 1, max_vec < 1), EUNSUPPORTED (nx or nz > 1024
+ * for C128/MIXED, > 2048 for C64), ENOMEM. */
+int lsop_create(int nx, int nz, int dtype, int max_vec, lsop_op** out);
+
+/* Set the medium (Section 2.1): contrast chi = w^2 (1/c^2 - 1/c0^2) (eq. 1),
+ * the FP64 kernel table K (cell-integrated Green's function) and its
+ * circulant spectrum.  vel_dev: nx*nz doubles (m/s) on the device.
+ * Synchronises `stream` (to validate the velocity).  Errors: EINVAL if
+ * h <= 0, freq_hz <= 0, c0 <= 0, any velocity NaN/inf/<= 0, or k0 h / sqrt(pi) > 2
+ * (fewer than ~3.5 cells per background wavelength). */
+int lsop_set_problem(lsop_op* op, const double* vel_dev, double h, double freq_hz, double c0,
+                     void* stream);
+
+/* y = op(x) for nvec vectors (mode: lsop_mode).  x and y may alias. */
+int lsop_apply(lsop_op* op, int mode, const void* x_dev, void* y_dev, int nvec, void* stream);
+
+/* r = A psi - rhs and, if rnorm2_dev != NULL, rnorm2_dev[k] = ||r_k||_2^2
+ * (double, overwritten).  Any of psi, rhs, r may alias.  (Eq. 13.) */
+int lsop_residual(lsop_op* op, const void* psi_dev, const void* rhs_dev, void* r_dev,
+                  double* rnorm2_dev, int nvec, void* stream);
+
+/* Incident fields of point sources (Section 2.1 source representation): a
+ * source of amplitude amp in cell s has density amp / h^2 in that cell, so
+ * psi0_m = amp * K(m - s) / h^2.  src_i, src_j: nsrc cell indices (host);
+ * amp_reim: 2*nsrc doubles (re, im) or NULL for unit amplitudes.
+ * psi0_dev: [nsrc][nx][nz].  Errors: EINVAL for a source outside the grid. */
+int lsop_incident(lsop_op* op, const int* src_i_host, const int* src_j_host,
+                  const double* amp_reim_host, int nsrc, void* psi0_dev, void* stream);
+
+/* Copy the FP64 kernel table K[p][q] (p < nx, q < nz; complex double,
+ * [nx][nz]) to table_dev.  Diagnostic. */
+int lsop_kernel_table(const lsop_op* op, void* table_dev, void* stream);
+
+int lsop_info(const lsop_op* op, lsop_op_info* info);
+void lsop_destroy(lsop_op* op);
+const char* lsop_last_error(void);
+
+/* ----------------------------------------------------------------------
+ * Preconditioners H for the series of eq. (11).
+ *  LSOP_PC_IDENTITY  H = I (the Born series, Section 2.2).
+ *  LSOP_PC_LOWRANK   H = I + U Z W^H with G0 V ~= U W^H from the randomized
+ *                    range finder of Alg. 2 (power_iters = q) and
+ *                    Z = (I_r - W^H U)^{-1} by Sherman-Morrison-Woodbury
+ *                    (eq. 12).  `rank` probe vectors.
+ * ---------------------------------------------------------------------- */
+typedef enum { LSOP_PC_IDENTITY = 0, LSOP_PC_LOWRANK = 1 } lsop_pc_kind;
+
+typedef struct {
+  int kind;         /* lsop_pc_kind */
+  int rank;         /* number of Gaussian probes r (LOWRANK), 1 <= rank <= 256 */
+  int power_iters;  /* q >= 0 */
+  uint64_t seed;    /* Philox4x32-10 key when no probe block is supplied */
+} lsop_precond_params;
+
+/* Allocate a preconditioner for `op` (U, W: rank x n complex in the inner
+ * dtype of op; Z: rank x rank).  Errors: EINVAL, ENOMEM. */
+int precond_create(lsop_op* op, const lsop_precond_params* params, lsop_precond** out);
+
+/* Build H (Alg. 2 then eq. 12).  omega_dev: rank x nx*nz real doubles, probe
+ * k contiguous, or NULL to draw standard normals on the device with
+ * Philox4x32-10 (counter = (pair index lo, hi, k, 0), key = seed) and
+ * Box-Muller.  Columns of the range basis that are numerically dependent are
+ * dropped (zero columns of U), so chi = 0 gives H = I exactly.  Synchronises
+ * `stream`.  Errors: ESINGULAR if I - W^H U is singular. */
+int precond_build(lsop_precond* pc, const void* omega_dev, void* stream);
+
+/* y = H x for nvec vectors (x, y in the inner dtype of the op). */
+int precond_apply(lsop_precond* pc, const void* x_dev, void* y_dev, int nvec, void* stream);
+
+/* rank kept, compression 2 r / n (Section 3.1.1), device bytes held. */
+int precond_info(const lsop_precond* pc, int* rank, double* compression, size_t* bytes);
+void precond_destroy(lsop_precond* pc);
+
+/* ----------------------------------------------------------------------
+ * The preconditioned scattering series (eqs. 10-11, 13-14).
+ *   psi_0 = H psi0 (init = LSOP_INIT_H_RHS, the paper's phi_0), or psi_dev
+ *   as given (LSOP_INIT_USER), or 0 (LSOP_INIT_ZERO);
+ *   repeat: a = A psi - psi0 (eq. 13); stop when ||a|| / ||psi0|| <= tol;
+ *           psi <- psi - H a (eq. 11; eq. 14 read as psi - (a + U Z W^H a)).
+ * Each right-hand side stops on its own; the returned iterate is the one whose
+ * residual passed.  Cap max_iter (default 30, Section 3.1).  DIVERGED if the
+ * residual is non-finite or rises 5 times in a row.
+ * LSOP_MIXED operators run iterative refinement: outer residuals and the
+ * accumulated solution in complex double, inner series in complex float to
+ * inner_tol, until the FP64 relative residual <= tol (at most refine_max
+ * outer steps).  pc may be NULL (Born series).  Synchronises `stream` once
+ * per iteration (convergence test on the host).
+ * rhs_dev, psi_dev: [nvec][nx][nz]; info_host: nvec entries.  Returns OK if
+ * every right-hand side converged, else the first failing status. */
+typedef enum { LSOP_INIT_H_RHS = 0, LSOP_INIT_ZERO = 1, LSOP_INIT_USER = 2 } lsop_init;
+
+typedef struct {
+  double tol;        /* relative residual target */
+  int max_iter;      /* per series (inner series for MIXED) */
+  int init;          /* lsop_init */
+  int refine_max;    /* MIXED only: outer refinement steps (default 8) */
+  double inner_tol;  /* MIXED only: inner relative tolerance (default 1e-5) */
+} lsop_solve_params;
+
+typedef struct {
+  int iters;            /* series updates performed (summed over refinement steps) */
+  int refine_steps;     /* outer steps (MIXED) */
+  double rel_residual;  /* ||A psi - psi0|| / ||psi0|| of the returned iterate */
+  int status;           /* lsop_status of this right-hand side */
+} lsop_solve_info;
+
+int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_dev, int nvec,
+                 const lsop_solve_params* params, lsop_solve_info* info_host, void* stream);
+
+/* Diagnostics: FP64 Bessel evaluations used for the kernel table, on the host
+ * (kind 0: (J0, Y0) at x > 0; kind 1: (J1, Y1) at 0 < x <= 2). */
+int lsop_bessel_host(int kind, double x, double* out2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSOP_H */

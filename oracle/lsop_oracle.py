@@ -247,32 +247,33 @@ def series_solve(prob, apply_H, psi0, tol, max_iter=30, phi0=None, diverge_windo
     """Eq. (11) for one source: psi_j = psi_{j-1} - H (psi_{j-1} - G0 V psi_{j-1} - psi0).
 
     Starts from psi_0 = H psi0 (the paper's choice of phi0) unless ``phi0`` is
-    given.  Returns (psi, iterations, relative residual, status) where the
-    returned iterate is the first whose relative residual is <= tol.
+    given.  Returns (psi, iterations, relative residual, status) for the last
+    iterate whose residual was evaluated: the first one with relative
+    residual <= tol (OK), the one at max_iter (NOT_CONVERGED), or the one at
+    which the residual was non-finite or had risen ``diverge_window`` times in
+    a row (DIVERGED).
     """
     psi0 = np.asarray(psi0, np.complex128)
     nb = np.linalg.norm(psi0)
     psi = apply_H(psi0) if phi0 is None else np.array(phi0, np.complex128)
-    best = (psi, np.inf)
     rising = 0
     prev = np.inf
-    for it in range(max_iter + 1):
+    it = 0
+    while True:
         a = prob.apply(psi, "A") - psi0          # eq. (13)
         rel = np.linalg.norm(a) / nb if nb > 0 else np.linalg.norm(a)
         if not np.isfinite(rel):
-            return best[0], it, best[1], DIVERGED
-        if rel < best[1]:
-            best = (psi, rel)
+            return psi, it, rel, DIVERGED
         if rel <= tol:
             return psi, it, rel, OK
         rising = rising + 1 if rel > prev else 0
-        if rising >= diverge_window:
-            return best[0], it, best[1], DIVERGED
         prev = rel
+        if rising >= diverge_window:
+            return psi, it, rel, DIVERGED
         if it == max_iter:
-            break
+            return psi, it, rel, NOT_CONVERGED
         psi = psi - apply_H(a)                   # eq. (11) / (14) as read
-    return best[0], max_iter, best[1], NOT_CONVERGED
+        it += 1
 
 
 # --------------------------------------------------------------------------

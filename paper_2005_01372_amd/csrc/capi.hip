@@ -1,0 +1,708 @@
+// C ABI of liblsop.so: operator, preconditioner and series solver handles.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "bessel.hpp"
+#include "internal.hpp"
+
+namespace lsop {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int status, const std::string& msg) {
+  g_err = msg;
+  return status;
+}
+
+namespace {
+
+hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+template <typename P>
+int dev_alloc(std::vector<void*>& owned, size_t& bytes, P** out, size_t nbytes) {
+  void* p = nullptr;
+  if (nbytes == 0) nbytes = 16;
+  if (hipMalloc(&p, nbytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LSOP_ENOMEM, "hipMalloc of " + std::to_string(nbytes) + " bytes failed");
+  }
+  owned.push_back(p);
+  bytes += nbytes;
+  *out = reinterpret_cast<P*>(p);
+  return LSOP_OK;
+}
+
+void free_all(std::vector<void*>& owned) {
+  for (void* p : owned) (void)hipFree(p);
+  owned.clear();
+}
+
+// w_{2L}^t = exp(-2 pi i t / (2L)) for t < 2L, evaluated in long double
+std::vector<Cx<double>> twiddles(int L) {
+  std::vector<Cx<double>> w(2 * L);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int t = 0; t < 2 * L; ++t) {
+    const long double a = pi * (long double)t / (long double)L;
+    w[t] = Cx<double>{(double)cosl(a), (double)(-sinl(a))};
+  }
+  return w;
+}
+
+int grow_scratch(lsop_op* op, size_t need) {
+  if (need <= op->scratch_bytes) return LSOP_OK;
+  if (op->scratch) {
+    LSOP_HIP(hipDeviceSynchronize());
+    (void)hipFree(op->scratch);
+    op->scratch = nullptr;
+    op->scratch_bytes = 0;
+  }
+  if (hipMalloc(&op->scratch, need) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LSOP_ENOMEM, "scratch allocation of " + std::to_string(need) + " bytes failed");
+  }
+  op->scratch_bytes = need;
+  return LSOP_OK;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+template <typename T>
+struct Dt;
+template <>
+struct Dt<float> {
+  static const float* chi(const lsop_op* op) { return op->chi32; }
+  static const Cx<float>* gs(const lsop_op* op) { return op->gs32; }
+  static const Cx<float>* twx(const lsop_op* op) { return op->tw2x32; }
+  static const Cx<float>* twz(const lsop_op* op) { return op->tw2z32; }
+};
+template <>
+struct Dt<double> {
+  static const double* chi(const lsop_op* op) { return op->chi64; }
+  static const Cx<double>* gs(const lsop_op* op) { return op->gs64; }
+  static const Cx<double>* twx(const lsop_op* op) { return op->tw2x64; }
+  static const Cx<double>* twz(const lsop_op* op) { return op->tw2z64; }
+};
+
+// y = op(x) (mode), or r = A x - rhs with norms when rhs != NULL.  Vectors are
+// addressed through vidx (device, nvec entries) when given, else 0..nvec-1.
+template <typename T>
+int apply_impl(lsop_op* op, int mode, const Cx<T>* x, Cx<T>* y, const Cx<T>* rhs, double* rnorm, const int* vidx,
+               int nvec, hipStream_t s) {
+  const size_t n = op->n();
+  Cx<T>* tmp = reinterpret_cast<Cx<T>*>(op->tmp);
+  const bool mulchi = (mode == LSOP_MODE_A || mode == LSOP_MODE_G0V);
+  const bool adj = !mulchi;
+  for (int c = 0; c < nvec; c += op->max_vec) {
+    const int m = std::min(op->max_vec, nvec - c);
+    const int* vc = vidx ? vidx + c : nullptr;
+    const size_t off = vidx ? 0 : (size_t)c * n;
+    double* rn = rnorm ? rnorm + c : nullptr;
+    LSOP_HIP(launch_rows_fwd<T>(op->lz, x + off, Dt<T>::chi(op), tmp, vc, op->nx, op->nz, m, mulchi, Dt<T>::twz(op),
+                                s));
+    LSOP_HIP(launch_cols<T>(op->lx, tmp, Dt<T>::gs(op), op->nx, op->pz(), m, adj, Dt<T>::twx(op), s));
+    LSOP_HIP(launch_rows_inv<T>(op->lz, tmp, x + off, Dt<T>::chi(op), rhs ? rhs + off : nullptr, y + off, rn, vc,
+                                op->nx, op->nz, m, mode, Dt<T>::twz(op), s));
+  }
+  return LSOP_OK;
+}
+
+int check_op(const lsop_op* op) {
+  if (!op) return fail(LSOP_EINVAL, "null operator handle");
+  if (!op->ready) return fail(LSOP_EINVAL, "lsop_set_problem has not been called");
+  return LSOP_OK;
+}
+
+// ---------------------------------------------------------- preconditioner
+template <typename T>
+int orth_impl(lsop_precond* pc, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s) {
+  // Cholesky-QR twice in the Gram metric: Q1 = Y X1, Q = Q1 X2.
+  const int r = pc->rank;
+  const size_t n = pc->op->n();
+  Cx<double>* G = pc->small;
+  Cx<double>* X = G + (size_t)r * r;
+  const double tol = std::is_same<T, float>::value ? 1e-9 : 1e-24;
+  for (int pass = 0; pass < 2; ++pass) {
+    const Cx<T>* src = pass == 0 ? Yin : Qout;
+    Cx<T>* dst = pass == 0 ? Qout : Yin;
+    LSOP_HIP(launch_gemm_ah_b<T>(src, r, src, nullptr, r, n, G, pc->part, pc->ksplit, s));
+    LSOP_HIP(launch_gram_orth(G, X, r, pass == 0 ? tol : 1e-6, pc->dflag, s));
+    LSOP_HIP(launch_gemm_update<T>(src, r, X, r, nullptr, nullptr, 0.0, dst, nullptr, n, s));
+  }
+  // result of pass 2 is in Yin; move it to Qout
+  LSOP_HIP(hipMemcpyAsync(Qout, Yin, sizeof(Cx<T>) * (size_t)r * n, hipMemcpyDeviceToDevice, s));
+  return LSOP_OK;
+}
+
+template <typename T>
+int build_impl(lsop_precond* pc, const double* omega, hipStream_t s) {
+  lsop_op* op = pc->op;
+  const int r = pc->rank;
+  const size_t n = op->n();
+  Cx<T>* U = reinterpret_cast<Cx<T>*>(pc->U);
+  Cx<T>* W = reinterpret_cast<Cx<T>*>(pc->W);
+  Cx<T>* Y = reinterpret_cast<Cx<T>*>(pc->Y);
+  // Alg. 2 step 1: Gaussian probes
+  if (omega) LSOP_HIP(launch_real_to_complex<T>(omega, Y, (size_t)r * n, s));
+  else LSOP_HIP(launch_philox_normal<T>(Y, r, n, pc->seed, s));
+  // step 2: Y0 = G0 (V Omega)
+  int st = apply_impl<T>(op, LSOP_MODE_G0V, Y, Y, nullptr, nullptr, nullptr, r, s);
+  if (st) return st;
+  // step 3: Q0 = orth(Y0)
+  if ((st = orth_impl<T>(pc, Y, U, s))) return st;
+  // step 4: power iterations with the adjoint
+  for (int j = 0; j < pc->q; ++j) {
+    if ((st = apply_impl<T>(op, LSOP_MODE_VHG0H, U, Y, nullptr, nullptr, nullptr, r, s))) return st;
+    if ((st = orth_impl<T>(pc, Y, W, s))) return st;  // W holds Q~_j
+    if ((st = apply_impl<T>(op, LSOP_MODE_G0V, W, Y, nullptr, nullptr, nullptr, r, s))) return st;
+    if ((st = orth_impl<T>(pc, Y, U, s))) return st;
+  }
+  // step 5: W = V^H G0^H Q_q, U = Q_q
+  if ((st = apply_impl<T>(op, LSOP_MODE_VHG0H, U, W, nullptr, nullptr, nullptr, r, s))) return st;
+  // eq. (12): Z = (I_r - W^H U)^{-1}
+  Cx<double>* M = pc->small;
+  Cx<double>* work = M + (size_t)r * r;
+  LSOP_HIP(launch_gemm_ah_b<T>(W, r, U, nullptr, r, n, M, pc->part, pc->ksplit, s));
+  LSOP_HIP(launch_lu_inverse_i_minus(M, pc->Z, work, r, pc->dflag + 1, s));
+  int flags[2] = {0, 0};
+  LSOP_HIP(hipMemcpyAsync(flags, pc->dflag, sizeof(flags), hipMemcpyDeviceToHost, s));
+  LSOP_HIP(hipStreamSynchronize(s));
+  pc->kept = flags[0];
+  if (flags[1]) return fail(LSOP_ESINGULAR, "I - W^H U is numerically singular");
+  pc->built = true;
+  return LSOP_OK;
+}
+
+// y = x + U Z W^H x  (or, when series_update, psi <- psi - r - U Z W^H r with x = r, y = psi)
+template <typename T>
+int pc_apply_impl(lsop_precond* pc, const Cx<T>* x, Cx<T>* y, const int* vidx, int nvec, bool series_update,
+                  hipStream_t s) {
+  const size_t n = pc->op->n();
+  if (pc->kind == LSOP_PC_IDENTITY) {
+    if (series_update) return launch_axpby<T>(x, y, -1.0, 1.0, vidx, nvec, n, s) == hipSuccess
+                                  ? LSOP_OK
+                                  : fail(LSOP_EHIP, "axpby launch failed");
+    if (x != y) {
+      if (vidx) {
+        LSOP_HIP(launch_axpby<T>(x, y, 1.0, 0.0, vidx, nvec, n, s));
+      } else {
+        LSOP_HIP(hipMemcpyAsync(y, x, sizeof(Cx<T>) * n * nvec, hipMemcpyDeviceToDevice, s));
+      }
+    }
+    return LSOP_OK;
+  }
+  const int r = pc->rank;
+  const Cx<T>* U = reinterpret_cast<const Cx<T>*>(pc->U);
+  const Cx<T>* W = reinterpret_cast<const Cx<T>*>(pc->W);
+  Cx<double>* T1 = pc->small + 3 * (size_t)r * r;
+  Cx<double>* T2 = T1 + (size_t)r * pc->tcap;
+  for (int c = 0; c < nvec; c += pc->tcap) {
+    const int m = std::min(pc->tcap, nvec - c);
+    const int* vc = vidx ? vidx + c : nullptr;
+    const size_t off = vidx ? 0 : (size_t)c * n;
+    LSOP_HIP(launch_gemm_ah_b<T>(W, r, x + off, vc, m, n, T1, pc->part, pc->ksplit, s));
+    LSOP_HIP(launch_small_gemm(pc->Z, T1, T2, r, m, series_update ? -1.0 : 1.0, s));
+    if (series_update)
+      LSOP_HIP(launch_gemm_update<T>(U, r, T2, m, y + off, x + off, -1.0, y + off, vc, n, s));
+    else
+      LSOP_HIP(launch_gemm_update<T>(U, r, T2, m, x + off, nullptr, 0.0, y + off, vc, n, s));
+  }
+  return LSOP_OK;
+}
+
+// --------------------------------------------------------------- series
+struct SeriesState {
+  std::vector<int> active;  // vector indices still iterating
+  std::vector<double> prev;
+  std::vector<int> rising;
+};
+
+// Runs eq. (11) on the vectors listed in `start` (all if empty).  rhs, psi, r
+// are [nvec][n] buffers of T.  Per-vector results go to info[vi].
+template <typename T>
+int series_impl(lsop_op* op, lsop_precond* pc, const Cx<T>* rhs, Cx<T>* psi, int nvec, double tol, int max_iter,
+                int init, const std::vector<int>& start, lsop_solve_info* info, Cx<T>* r, double* dnorm,
+                int* dvidx, hipStream_t s) {
+  const size_t n = op->n();
+  std::vector<int> active = start;
+  if (active.empty())
+    for (int v = 0; v < nvec; ++v) active.push_back(v);
+  const int na0 = (int)active.size();
+  LSOP_HIP(hipMemcpyAsync(dvidx, active.data(), sizeof(int) * na0, hipMemcpyHostToDevice, s));
+  // ||rhs||^2
+  std::vector<double> b2(nvec, 0.0), rn(nvec, 0.0);
+  LSOP_HIP(launch_norm2<T>(rhs, dnorm, dvidx, na0, n, s));
+  LSOP_HIP(hipMemcpyAsync(rn.data(), dnorm, sizeof(double) * na0, hipMemcpyDeviceToHost, s));
+  LSOP_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < na0; ++k) b2[active[k]] = rn[k];
+  // psi_0
+  if (init == LSOP_INIT_H_RHS) {
+    if (pc) {
+      int st = pc_apply_impl<T>(pc, rhs, psi, dvidx, na0, false, s);
+      if (st) return st;
+    } else {
+      LSOP_HIP(launch_axpby<T>(rhs, psi, 1.0, 0.0, dvidx, na0, n, s));
+    }
+  } else if (init == LSOP_INIT_ZERO) {
+    LSOP_HIP(launch_axpby<T>(rhs, psi, 0.0, 0.0, dvidx, na0, n, s));
+  }
+  std::vector<double> prev(nvec, INFINITY);
+  std::vector<int> rising(nvec, 0);
+  for (int v : active) {
+    info[v].iters = 0;
+    info[v].status = LSOP_NOT_CONVERGED;
+    info[v].rel_residual = INFINITY;
+  }
+  for (int it = 0;; ++it) {
+    const int na = (int)active.size();
+    LSOP_HIP(hipMemcpyAsync(dvidx, active.data(), sizeof(int) * na, hipMemcpyHostToDevice, s));
+    LSOP_HIP(hipMemsetAsync(dnorm, 0, sizeof(double) * na, s));
+    // eq. (13): a = psi - G0 V psi - psi0, with ||a||^2
+    int st = apply_impl<T>(op, LSOP_MODE_A, psi, r, rhs, dnorm, dvidx, na, s);
+    if (st) return st;
+    LSOP_HIP(hipMemcpyAsync(rn.data(), dnorm, sizeof(double) * na, hipMemcpyDeviceToHost, s));
+    LSOP_HIP(hipStreamSynchronize(s));
+    std::vector<int> next;
+    for (int k = 0; k < na; ++k) {
+      const int v = active[k];
+      const double rel = b2[v] > 0 ? std::sqrt(rn[k] / b2[v]) : std::sqrt(rn[k]);
+      info[v].iters = it;
+      info[v].rel_residual = rel;
+      if (!std::isfinite(rel)) {
+        info[v].status = LSOP_DIVERGED;
+        continue;
+      }
+      if (rel <= tol) {
+        info[v].status = LSOP_OK;
+        continue;
+      }
+      rising[v] = rel > prev[v] ? rising[v] + 1 : 0;
+      prev[v] = rel;
+      if (rising[v] >= 5) {
+        info[v].status = LSOP_DIVERGED;
+        continue;
+      }
+      if (it == max_iter) {
+        info[v].status = LSOP_NOT_CONVERGED;
+        continue;
+      }
+      next.push_back(v);
+    }
+    active.swap(next);
+    if (active.empty()) break;
+    const int nn = (int)active.size();
+    LSOP_HIP(hipMemcpyAsync(dvidx, active.data(), sizeof(int) * nn, hipMemcpyHostToDevice, s));
+    // eq. (11): psi <- psi - H a
+    if (pc) {
+      st = pc_apply_impl<T>(pc, r, psi, dvidx, nn, true, s);
+      if (st) return st;
+    } else {
+      LSOP_HIP(launch_axpby<T>(r, psi, -1.0, 1.0, dvidx, nn, n, s));
+    }
+  }
+  return LSOP_OK;
+}
+
+int overall_status(const lsop_solve_info* info, int nvec) {
+  for (int v = 0; v < nvec; ++v)
+    if (info[v].status != LSOP_OK) return info[v].status;
+  return LSOP_OK;
+}
+
+}  // namespace
+}  // namespace lsop
+
+using namespace lsop;
+
+extern "C" {
+
+const char* lsop_last_error(void) { return g_err.c_str(); }
+
+int lsop_create(int nx, int nz, int dtype, int max_vec, lsop_op** out) {
+  if (!out) return fail(LSOP_EINVAL, "null output handle");
+  *out = nullptr;
+  if (nx < 1 || nz < 1 || max_vec < 1) return fail(LSOP_EINVAL, "nx, nz and max_vec must be >= 1");
+  if (dtype != LSOP_C64 && dtype != LSOP_C128 && dtype != LSOP_MIXED) return fail(LSOP_EUNSUPPORTED, "bad dtype");
+  const int lx = fft_length_for(nx), lz = fft_length_for(nz);
+  if (lx < 0 || lz < 0) return fail(LSOP_EUNSUPPORTED, "grid side exceeds the largest FFT length (2048)");
+  if ((size_t)nx * nz > (size_t)INT32_MAX / 2) return fail(LSOP_EUNSUPPORTED, "grid too large");
+  lsop_op* op = new lsop_op();
+  op->nx = nx;
+  op->nz = nz;
+  op->lx = lx;
+  op->lz = lz;
+  op->dtype = dtype;
+  op->max_vec = max_vec;
+  const size_t n = op->n();
+  const size_t px = op->px(), pz = op->pz();
+  int st = 0;
+  auto& o = op->owned;
+  auto& b = op->bytes;
+  st |= dev_alloc(o, b, &op->chi64, sizeof(double) * n);
+  if (op->has32()) st |= dev_alloc(o, b, &op->chi32, sizeof(float) * n);
+  st |= dev_alloc(o, b, &op->ktab, sizeof(Cx<double>) * n);
+  if (op->has64()) st |= dev_alloc(o, b, &op->gs64, sizeof(Cx<double>) * px * pz);
+  if (op->has32()) st |= dev_alloc(o, b, &op->gs32, sizeof(Cx<float>) * px * pz);
+  st |= dev_alloc(o, b, &op->tw2x64, sizeof(Cx<double>) * 2 * lx);
+  st |= dev_alloc(o, b, &op->tw2z64, sizeof(Cx<double>) * 2 * lz);
+  if (op->has32()) {
+    st |= dev_alloc(o, b, &op->tw2x32, sizeof(Cx<float>) * 2 * lx);
+    st |= dev_alloc(o, b, &op->tw2z32, sizeof(Cx<float>) * 2 * lz);
+  }
+  const size_t esz = op->has64() ? sizeof(Cx<double>) : sizeof(Cx<float>);
+  st |= dev_alloc(o, b, &op->tmp, esz * (size_t)max_vec * nx * pz);
+  st |= dev_alloc(o, b, &op->flag, 256);
+  op->src_cap = 4096;
+  st |= dev_alloc(o, b, &op->dsrc, sizeof(int) * 2 * op->src_cap);
+  st |= dev_alloc(o, b, &op->damp, sizeof(Cx<double>) * op->src_cap);
+  if (st) {
+    free_all(op->owned);
+    delete op;
+    return LSOP_ENOMEM;
+  }
+  // twiddle tables
+  for (int axis = 0; axis < 2; ++axis) {
+    const int L = axis == 0 ? lx : lz;
+    std::vector<Cx<double>> w = twiddles(L);
+    Cx<double>* d64 = axis == 0 ? op->tw2x64 : op->tw2z64;
+    if (hipMemcpy(d64, w.data(), sizeof(Cx<double>) * w.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      free_all(op->owned);
+      delete op;
+      return fail(LSOP_EHIP, "twiddle upload failed");
+    }
+    if (op->has32()) {
+      std::vector<Cx<float>> w32(w.size());
+      for (size_t t = 0; t < w.size(); ++t) w32[t] = ccast<float>(w[t]);
+      Cx<float>* d32 = axis == 0 ? op->tw2x32 : op->tw2z32;
+      if (hipMemcpy(d32, w32.data(), sizeof(Cx<float>) * w32.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        free_all(op->owned);
+        delete op;
+        return fail(LSOP_EHIP, "twiddle upload failed");
+      }
+    }
+  }
+  *out = op;
+  return LSOP_OK;
+}
+
+int lsop_set_problem(lsop_op* op, const double* vel_dev, double h, double freq_hz, double c0, void* stream) {
+  if (!op) return fail(LSOP_EINVAL, "null operator handle");
+  if (!vel_dev) return fail(LSOP_EINVAL, "null velocity");
+  if (!(h > 0) || !(freq_hz > 0) || !(c0 > 0) || !std::isfinite(h) || !std::isfinite(freq_hz) || !std::isfinite(c0))
+    return fail(LSOP_EINVAL, "h, freq_hz and c0 must be positive and finite");
+  const double pi = lsop_bessel::kPi;
+  const double w = 2.0 * pi * freq_hz;
+  const double k0 = w / c0;
+  const double a = h / std::sqrt(pi);
+  const double ka = k0 * a;
+  if (ka > 2.0) return fail(LSOP_EINVAL, "grid too coarse: k0 h / sqrt(pi) > 2");
+  hipStream_t s = S(stream);
+  const size_t n = op->n();
+  LSOP_HIP(hipMemsetAsync(op->flag, 0, sizeof(unsigned), s));
+  LSOP_HIP(launch_contrast(vel_dev, op->chi64, op->chi32, (int)n, w * w, 1.0 / (c0 * c0), op->flag, s));
+  unsigned bad = 0;
+  LSOP_HIP(hipMemcpyAsync(&bad, op->flag, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  LSOP_HIP(hipStreamSynchronize(s));
+  if (bad) {
+    op->ready = false;
+    return fail(LSOP_EINVAL, "velocity must be finite and positive");
+  }
+  // self cell and the J1 factor of the disk-integrated kernel
+  double j1 = 0, y1 = 0;
+  lsop_bessel::bessel1_small(ka, &j1, &y1);
+  const Cx<double> c{0.0, pi * a / (2.0 * k0)};
+  const Cx<double> cj1 = c * Cx<double>{j1, 0.0};
+  const Cx<double> self = c * Cx<double>{j1, y1} - Cx<double>{1.0 / (k0 * k0), 0.0};
+  LSOP_HIP(launch_table(op->ktab, op->nx, op->nz, k0 * h, cj1, self, s));
+  // spectrum: the row pass writes a transposed px x pz FP64 intermediate
+  const size_t s1 = sizeof(Cx<double>) * (size_t)op->px() * op->pz();
+  int st = grow_scratch(op, s1);
+  if (st) return st;
+  LSOP_HIP(launch_spectrum(op->lx, op->lz, op->ktab, op->nx, op->nz, reinterpret_cast<Cx<double>*>(op->scratch),
+                           op->gs64, op->gs32, op->tw2x64, op->tw2z64, s));
+  op->h = h;
+  op->freq = freq_hz;
+  op->c0 = c0;
+  op->k0 = k0;
+  op->ready = true;
+  return LSOP_OK;
+}
+
+int lsop_apply(lsop_op* op, int mode, const void* x_dev, void* y_dev, int nvec, void* stream) {
+  int st = check_op(op);
+  if (st) return st;
+  if (mode < 0 || mode > 3) return fail(LSOP_EINVAL, "bad mode");
+  if (nvec < 0 || (nvec > 0 && (!x_dev || !y_dev))) return fail(LSOP_EINVAL, "bad vectors");
+  if (op->dtype == LSOP_C64)
+    return apply_impl<float>(op, mode, (const Cx<float>*)x_dev, (Cx<float>*)y_dev, nullptr, nullptr, nullptr, nvec,
+                             S(stream));
+  return apply_impl<double>(op, mode, (const Cx<double>*)x_dev, (Cx<double>*)y_dev, nullptr, nullptr, nullptr, nvec,
+                            S(stream));
+}
+
+int lsop_residual(lsop_op* op, const void* psi_dev, const void* rhs_dev, void* r_dev, double* rnorm2_dev, int nvec,
+                  void* stream) {
+  int st = check_op(op);
+  if (st) return st;
+  if (nvec < 0 || (nvec > 0 && (!psi_dev || !rhs_dev || !r_dev))) return fail(LSOP_EINVAL, "bad vectors");
+  hipStream_t s = S(stream);
+  if (rnorm2_dev && nvec > 0) LSOP_HIP(hipMemsetAsync(rnorm2_dev, 0, sizeof(double) * nvec, s));
+  if (op->dtype == LSOP_C64)
+    return apply_impl<float>(op, LSOP_MODE_A, (const Cx<float>*)psi_dev, (Cx<float>*)r_dev,
+                             (const Cx<float>*)rhs_dev, rnorm2_dev, nullptr, nvec, s);
+  return apply_impl<double>(op, LSOP_MODE_A, (const Cx<double>*)psi_dev, (Cx<double>*)r_dev,
+                            (const Cx<double>*)rhs_dev, rnorm2_dev, nullptr, nvec, s);
+}
+
+int lsop_incident(lsop_op* op, const int* src_i_host, const int* src_j_host, const double* amp_reim_host, int nsrc,
+                  void* psi0_dev, void* stream) {
+  int st = check_op(op);
+  if (st) return st;
+  if (nsrc < 0 || (nsrc > 0 && (!src_i_host || !src_j_host || !psi0_dev))) return fail(LSOP_EINVAL, "bad sources");
+  if (nsrc > op->src_cap) return fail(LSOP_EINVAL, "too many sources in one call (max 4096)");
+  for (int k = 0; k < nsrc; ++k)
+    if (src_i_host[k] < 0 || src_i_host[k] >= op->nx || src_j_host[k] < 0 || src_j_host[k] >= op->nz)
+      return fail(LSOP_EINVAL, "source outside the grid");
+  if (nsrc == 0) return LSOP_OK;
+  hipStream_t s = S(stream);
+  std::vector<int> ij(2 * (size_t)nsrc);
+  std::vector<Cx<double>> amp(nsrc);
+  for (int k = 0; k < nsrc; ++k) {
+    ij[k] = src_i_host[k];
+    ij[nsrc + k] = src_j_host[k];
+    amp[k] = amp_reim_host ? Cx<double>{amp_reim_host[2 * k], amp_reim_host[2 * k + 1]} : Cx<double>{1.0, 0.0};
+  }
+  // synchronous copies: the staging buffers are reused by later calls
+  LSOP_HIP(hipStreamSynchronize(s));
+  LSOP_HIP(hipMemcpy(op->dsrc, ij.data(), sizeof(int) * ij.size(), hipMemcpyHostToDevice));
+  LSOP_HIP(hipMemcpy(op->damp, amp.data(), sizeof(Cx<double>) * nsrc, hipMemcpyHostToDevice));
+  const double inv_dv = 1.0 / (op->h * op->h);
+  if (op->dtype == LSOP_C64)
+    LSOP_HIP(launch_incident<float>(op->ktab, op->dsrc, op->dsrc + nsrc, op->damp, (Cx<float>*)psi0_dev, op->nx,
+                                    op->nz, nsrc, inv_dv, s));
+  else
+    LSOP_HIP(launch_incident<double>(op->ktab, op->dsrc, op->dsrc + nsrc, op->damp, (Cx<double>*)psi0_dev, op->nx,
+                                     op->nz, nsrc, inv_dv, s));
+  return LSOP_OK;
+}
+
+int lsop_kernel_table(const lsop_op* op, void* table_dev, void* stream) {
+  int st = check_op(op);
+  if (st) return st;
+  if (!table_dev) return fail(LSOP_EINVAL, "null table");
+  LSOP_HIP(hipMemcpyAsync(table_dev, op->ktab, sizeof(Cx<double>) * op->n(), hipMemcpyDeviceToDevice, S(stream)));
+  return LSOP_OK;
+}
+
+int lsop_info(const lsop_op* op, lsop_op_info* info) {
+  if (!op || !info) return fail(LSOP_EINVAL, "null argument");
+  info->nx = op->nx;
+  info->nz = op->nz;
+  info->lx = op->lx;
+  info->lz = op->lz;
+  info->dtype = op->dtype;
+  info->max_vec = op->max_vec;
+  info->state_bytes = op->bytes + op->scratch_bytes;
+  return LSOP_OK;
+}
+
+void lsop_destroy(lsop_op* op) {
+  if (!op) return;
+  (void)hipDeviceSynchronize();
+  free_all(op->owned);
+  if (op->scratch) (void)hipFree(op->scratch);
+  delete op;
+}
+
+// ------------------------------------------------------------ preconditioner
+int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out) {
+  if (!out) return fail(LSOP_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!op || !p) return fail(LSOP_EINVAL, "null argument");
+  if (p->kind != LSOP_PC_IDENTITY && p->kind != LSOP_PC_LOWRANK) return fail(LSOP_EINVAL, "bad preconditioner kind");
+  if (p->kind == LSOP_PC_LOWRANK && (p->rank < 1 || p->rank > 256 || p->power_iters < 0))
+    return fail(LSOP_EINVAL, "rank must be in [1, 256] and power_iters >= 0");
+  lsop_precond* pc = new lsop_precond();
+  pc->op = op;
+  pc->kind = p->kind;
+  pc->seed = p->seed;
+  pc->dt = op->dtype == LSOP_C128 ? LSOP_C128 : LSOP_C64;
+  if (p->kind == LSOP_PC_IDENTITY) {
+    pc->built = true;
+    *out = pc;
+    return LSOP_OK;
+  }
+  pc->rank = p->rank;
+  pc->q = p->power_iters;
+  const size_t n = op->n();
+  const size_t esz = pc->dt == LSOP_C128 ? sizeof(Cx<double>) : sizeof(Cx<float>);
+  const int r = pc->rank;
+  pc->tcap = std::max(op->max_vec, r);
+  size_t ks = n / 4096;
+  pc->ksplit = (int)std::max<size_t>(1, std::min<size_t>(ks, 256));
+  int st = 0;
+  auto& o = pc->owned;
+  auto& b = pc->bytes;
+  st |= dev_alloc(o, b, &pc->U, esz * r * n);
+  st |= dev_alloc(o, b, &pc->W, esz * r * n);
+  st |= dev_alloc(o, b, &pc->Y, esz * r * n);
+  st |= dev_alloc(o, b, &pc->Z, sizeof(Cx<double>) * r * r);
+  // small: G / M (r*r), X / LU work (2 r*r), T1, T2 (r * tcap each)
+  st |= dev_alloc(o, b, &pc->small, sizeof(Cx<double>) * ((size_t)3 * r * r + (size_t)2 * r * pc->tcap));
+  st |= dev_alloc(o, b, &pc->part, sizeof(Cx<double>) * (size_t)pc->ksplit * r * pc->tcap);
+  st |= dev_alloc(o, b, &pc->dflag, 256);
+  if (st) {
+    free_all(pc->owned);
+    delete pc;
+    return LSOP_ENOMEM;
+  }
+  *out = pc;
+  return LSOP_OK;
+}
+
+int precond_build(lsop_precond* pc, const void* omega_dev, void* stream) {
+  if (!pc) return fail(LSOP_EINVAL, "null preconditioner");
+  int st = check_op(pc->op);
+  if (st) return st;
+  if (pc->kind == LSOP_PC_IDENTITY) return LSOP_OK;
+  pc->built = false;
+  if (pc->dt == LSOP_C128) return build_impl<double>(pc, (const double*)omega_dev, S(stream));
+  return build_impl<float>(pc, (const double*)omega_dev, S(stream));
+}
+
+int precond_apply(lsop_precond* pc, const void* x_dev, void* y_dev, int nvec, void* stream) {
+  if (!pc) return fail(LSOP_EINVAL, "null preconditioner");
+  if (!pc->built) return fail(LSOP_EINVAL, "preconditioner not built");
+  if (nvec < 0 || (nvec > 0 && (!x_dev || !y_dev))) return fail(LSOP_EINVAL, "bad vectors");
+  if (pc->dt == LSOP_C128)
+    return pc_apply_impl<double>(pc, (const Cx<double>*)x_dev, (Cx<double>*)y_dev, nullptr, nvec, false, S(stream));
+  return pc_apply_impl<float>(pc, (const Cx<float>*)x_dev, (Cx<float>*)y_dev, nullptr, nvec, false, S(stream));
+}
+
+int precond_info(const lsop_precond* pc, int* rank, double* compression, size_t* bytes) {
+  if (!pc) return fail(LSOP_EINVAL, "null preconditioner");
+  const int r = pc->kind == LSOP_PC_IDENTITY ? 0 : pc->kept;
+  if (rank) *rank = r;
+  if (compression) *compression = 2.0 * r / (double)pc->op->n();
+  if (bytes) *bytes = pc->bytes;
+  return LSOP_OK;
+}
+
+void precond_destroy(lsop_precond* pc) {
+  if (!pc) return;
+  (void)hipDeviceSynchronize();
+  free_all(pc->owned);
+  delete pc;
+}
+
+// ------------------------------------------------------------------ series
+int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_dev, int nvec,
+                 const lsop_solve_params* p, lsop_solve_info* info, void* stream) {
+  int st = check_op(op);
+  if (st) return st;
+  if (!p || !info) return fail(LSOP_EINVAL, "null params or info");
+  if (nvec < 1 || !rhs_dev || !psi_dev) return fail(LSOP_EINVAL, "bad vectors");
+  if (!(p->tol > 0) || p->max_iter < 0) return fail(LSOP_EINVAL, "tol must be > 0 and max_iter >= 0");
+  if (p->init < 0 || p->init > 2) return fail(LSOP_EINVAL, "bad init");
+  if (pc && pc->op != op) return fail(LSOP_EINVAL, "preconditioner belongs to another operator");
+  if (pc && !pc->built) return fail(LSOP_EINVAL, "preconditioner not built");
+  lsop_precond* pcu = (pc && pc->kind == LSOP_PC_LOWRANK) ? pc : nullptr;
+  hipStream_t s = S(stream);
+  const size_t n = op->n();
+  for (int v = 0; v < nvec; ++v) info[v] = lsop_solve_info{0, 0, INFINITY, LSOP_NOT_CONVERGED};
+  if (op->dtype != LSOP_MIXED) {
+    const size_t esz = op->dtype == LSOP_C64 ? sizeof(Cx<float>) : sizeof(Cx<double>);
+    const size_t need = align_up(esz * n * nvec) + align_up(sizeof(double) * nvec) + align_up(sizeof(int) * nvec);
+    if ((st = grow_scratch(op, need))) return st;
+    char* base = (char*)op->scratch;
+    void* r = base;
+    double* dn = (double*)(base + align_up(esz * n * nvec));
+    int* dv = (int*)((char*)dn + align_up(sizeof(double) * nvec));
+    if (op->dtype == LSOP_C64)
+      st = series_impl<float>(op, pcu, (const Cx<float>*)rhs_dev, (Cx<float>*)psi_dev, nvec, p->tol, p->max_iter,
+                              p->init, {}, info, (Cx<float>*)r, dn, dv, s);
+    else
+      st = series_impl<double>(op, pcu, (const Cx<double>*)rhs_dev, (Cx<double>*)psi_dev, nvec, p->tol, p->max_iter,
+                               p->init, {}, info, (Cx<double>*)r, dn, dv, s);
+    if (st) return st;
+    return overall_status(info, nvec);
+  }
+  // ---- mixed precision: iterative refinement (outer FP64, inner FP32 series)
+  const int refine_max = p->refine_max > 0 ? p->refine_max : 8;
+  const double inner_tol = p->inner_tol > 0 ? p->inner_tol : 1e-5;
+  const size_t b64 = align_up(sizeof(Cx<double>) * n * nvec), b32 = align_up(sizeof(Cx<float>) * n * nvec);
+  const size_t need = b64 + 3 * b32 + align_up(sizeof(double) * nvec) + align_up(sizeof(int) * nvec);
+  if ((st = grow_scratch(op, need))) return st;
+  char* base = (char*)op->scratch;
+  Cx<double>* r64 = (Cx<double>*)base;
+  Cx<float>* rhs32 = (Cx<float>*)(base + b64);
+  Cx<float>* d32 = (Cx<float>*)(base + b64 + b32);
+  Cx<float>* w32 = (Cx<float>*)(base + b64 + 2 * b32);
+  double* dn = (double*)(base + b64 + 3 * b32);
+  int* dv = (int*)((char*)dn + align_up(sizeof(double) * nvec));
+  const Cx<double>* rhs = (const Cx<double>*)rhs_dev;
+  Cx<double>* psi = (Cx<double>*)psi_dev;
+  std::vector<int> active(nvec);
+  for (int v = 0; v < nvec; ++v) active[v] = v;
+  std::vector<double> b2(nvec), rn(nvec);
+  LSOP_HIP(hipMemcpyAsync(dv, active.data(), sizeof(int) * nvec, hipMemcpyHostToDevice, s));
+  LSOP_HIP(launch_norm2<double>(rhs, dn, dv, nvec, n, s));
+  LSOP_HIP(hipMemcpyAsync(b2.data(), dn, sizeof(double) * nvec, hipMemcpyDeviceToHost, s));
+  LSOP_HIP(hipStreamSynchronize(s));
+  if (p->init != LSOP_INIT_USER) LSOP_HIP(hipMemsetAsync(psi, 0, sizeof(Cx<double>) * n * nvec, s));
+  std::vector<lsop_solve_info> inner(nvec);
+  std::vector<int> total_iters(nvec, 0);
+  for (int k = 0;; ++k) {
+    const int na = (int)active.size();
+    LSOP_HIP(hipMemcpyAsync(dv, active.data(), sizeof(int) * na, hipMemcpyHostToDevice, s));
+    LSOP_HIP(hipMemsetAsync(dn, 0, sizeof(double) * na, s));
+    // FP64 residual r = A psi - psi0
+    if ((st = apply_impl<double>(op, LSOP_MODE_A, psi, r64, rhs, dn, dv, na, s))) return st;
+    LSOP_HIP(hipMemcpyAsync(rn.data(), dn, sizeof(double) * na, hipMemcpyDeviceToHost, s));
+    LSOP_HIP(hipStreamSynchronize(s));
+    std::vector<int> next;
+    for (int j = 0; j < na; ++j) {
+      const int v = active[j];
+      const double rel = b2[v] > 0 ? std::sqrt(rn[j] / b2[v]) : std::sqrt(rn[j]);
+      info[v].rel_residual = rel;
+      info[v].refine_steps = k;
+      info[v].iters = total_iters[v];
+      if (!std::isfinite(rel)) info[v].status = LSOP_DIVERGED;
+      else if (rel <= p->tol) info[v].status = LSOP_OK;
+      else if (k == refine_max) info[v].status = LSOP_NOT_CONVERGED;
+      else if (k > 0 && inner[v].status == LSOP_DIVERGED) info[v].status = LSOP_DIVERGED;
+      else next.push_back(v);
+    }
+    active.swap(next);
+    if (active.empty()) break;
+    // inner FP32 series on A d = r; psi <- psi - d
+    LSOP_HIP(launch_convert<float, double>(r64, rhs32, n * nvec, s));
+    if ((st = series_impl<float>(op, pcu, rhs32, d32, nvec, inner_tol, p->max_iter, LSOP_INIT_H_RHS, active,
+                                 inner.data(), w32, dn, dv, s)))
+      return st;
+    const int nn = (int)active.size();
+    LSOP_HIP(hipMemcpyAsync(dv, active.data(), sizeof(int) * nn, hipMemcpyHostToDevice, s));
+    LSOP_HIP(launch_accumulate<float>(d32, psi, -1.0, dv, nn, n, s));
+    for (int v : active) total_iters[v] += inner[v].iters;
+  }
+  return overall_status(info, nvec);
+}
+
+int lsop_bessel_host(int kind, double x, double* out2) {
+  if (!out2 || !(x > 0)) return fail(LSOP_EINVAL, "x must be > 0");
+  if (kind == 0) {
+    lsop_bessel::hankel0(x, &out2[0], &out2[1]);
+    return LSOP_OK;
+  }
+  if (kind == 1) {
+    if (x > 2.0) return fail(LSOP_EINVAL, "series valid for x <= 2");
+    lsop_bessel::bessel1_small(x, &out2[0], &out2[1]);
+    return LSOP_OK;
+  }
+  return fail(LSOP_EINVAL, "bad kind");
+}
+
+}  // extern "C"

@@ -1,0 +1,469 @@
+// FFT-convolution kernels of the LS operator (Section 2.2) and its set-up
+// (contrast of eq. 1, cell-integrated kernel table, circulant spectrum).
+//
+// The product G0 V x is a linear convolution of the nx x nz grid with the
+// lag table K, evaluated as a circular convolution on the padded 2 lx x 2 lz
+// array (lx >= nx, lz >= nz).  Because the input occupies only the first
+// half of each padded axis, a length-2L transform splits into two length-L
+// transforms:
+//   X[2m]   = FFT_L(u)[m],       X[2m+1] = FFT_L(u . w_{2L}^n)[m],
+// and because only the first half of the output is kept, the inverse is
+//   y[n] = IFFT_L(Y_even)[n] + w_{2L}^{-n} IFFT_L(Y_odd)[n].
+// Three passes over HBM implement one application:
+//   1. rows (fixed i, j contiguous): u = chi . x (or x), two FFTs -> tmp[i][0..2lz)
+//   2. columns of tmp (fixed c, i strided): both x-halves: FFT, multiply by
+//      the spectrum, inverse FFT, recombine -> tmp (only rows i < nx kept)
+//   3. rows: two inverse FFTs, recombine, crop to j < nz, epilogue
+//      (x - conv, conv, x - chi conv, chi conv; optional residual and norm).
+// The spectrum gs[h][c][m] holds F(K~)[2m + h][kz(c)] / (px pz) with the
+// column index c in the split order of pass 1 (kz(c) = 2 (c mod lz) + c / lz).
+#include "fft_engine.hpp"
+#include "bessel.hpp"
+#include "internal.hpp"
+
+namespace lsop {
+
+int fft_length_for(int n) {
+  static const int lens[] = {32, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 2048};
+  for (int L : lens)
+    if (L >= n) return L;
+  return -1;
+}
+
+// ------------------------------------------------------------------ pass 1
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_rows_fwd(const Cx<T>* __restrict__ x, const T* __restrict__ chi,
+                                                   Cx<T>* __restrict__ tmp, const int* __restrict__ vidx, int nx,
+                                                   int nz, int nitems, int mulchi, const Cx<T>* __restrict__ tw2) {
+  using P = FftPlan<L>;
+  constexpr int G = P::G, E = P::E, GPW = 256 / G;
+  __shared__ Cx<T> sbuf[GPW][lds_len<L>()];
+  const int grp = threadIdx.x / G, g = threadIdx.x % G;
+  const size_t vstride = (size_t)nx * nz;
+  for (int base = blockIdx.x * GPW; base < nitems; base += gridDim.x * GPW) {
+    const int item = base + grp;
+    const bool valid = item < nitems;
+    const int it = valid ? item : nitems - 1;
+    const int slot = it / nx, i = it % nx;
+    const int vi = vidx ? vidx[slot] : slot;
+    const Cx<T>* xr = x + (size_t)vi * vstride + (size_t)i * nz;
+    const T* cr = chi + (size_t)i * nz;
+    Cx<T> u[E], v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int p = fft_elem<L>(g, e);
+      Cx<T> val = czero<T>();
+      if (p < nz) {
+        val = xr[p];
+        if (mulchi) val = cr[p] * val;
+      }
+      u[e] = val;
+      v[e] = val;
+    }
+    Cx<T>* tr = tmp + ((size_t)slot * nx + i) * (2 * L);
+    fft_regs<T, L, false>(v, g, sbuf[grp], tw2);
+    if (valid) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) tr[fft_elem<L>(g, e)] = v[e];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = u[e] * tw2[fft_elem<L>(g, e)];
+    fft_regs<T, L, false>(v, g, sbuf[grp], tw2);
+    if (valid) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) tr[L + fft_elem<L>(g, e)] = v[e];
+    }
+    wave_sync();
+  }
+}
+
+// ------------------------------------------------------------------ pass 2
+template <typename T, int L>
+struct ColTile {
+  // columns per workgroup: 128-byte row segments where the LDS budget allows
+  static constexpr int lds_cap = (144 * 1024) / (lds_len<L>() * (int)sizeof(Cx<T>));
+  static constexpr int want = 128 / (int)sizeof(Cx<T>);
+  static constexpr int c0 = want < lds_cap ? want : lds_cap;
+  static constexpr int thr_cap = 1024 / FftPlan<L>::G;
+  static constexpr int c1 = c0 < thr_cap ? c0 : thr_cap;
+  static constexpr int C = c1 >= 16 ? 16 : c1 >= 8 ? 8 : c1 >= 4 ? 4 : c1 >= 2 ? 2 : 1;
+};
+
+// blockIdx -> logical id so that consecutive logical ids run on the same XCD
+// (workgroups are dispatched round-robin over the 8 XCDs).
+__device__ __forceinline__ int xcd_logical_block(int b, int nb) {
+  const int per = nb / 8, rem = nb % 8, x = b % 8;
+  return x * per + (x < rem ? x : rem) + b / 8;
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__((ColTile<T, L>::C * FftPlan<L>::G)) void k_cols(Cx<T>* __restrict__ tmp,
+                                                                            const Cx<T>* __restrict__ gs, int nx,
+                                                                            int pz, int nslots, int adj,
+                                                                            const Cx<T>* __restrict__ tw2) {
+  using P = FftPlan<L>;
+  constexpr int G = P::G, E = P::E, C = ColTile<T, L>::C, NT = C * G;
+  __shared__ Cx<T> tile[C][lds_len<L>()];
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int tid = lb / nslots, slot = lb % nslots;
+  const int c0 = tid * C;
+  Cx<T>* tb = tmp + (size_t)slot * nx * pz + c0;
+  for (int idx = threadIdx.x; idx < L * C; idx += NT) {
+    const int i = idx / C, c = idx % C;
+    tile[c][lds_pad(i)] = (i < nx) ? tb[(size_t)i * pz + c] : czero<T>();
+  }
+  __syncthreads();
+  const int c = threadIdx.x / G, g = threadIdx.x % G;
+  Cx<T> xin[E], acc[E], v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    xin[e] = tile[c][lds_pad(fft_elem<L>(g, e))];
+    v[e] = xin[e];
+  }
+  const Cx<T>* g0 = gs + (size_t)(c0 + c) * L;
+  const Cx<T>* g1 = gs + ((size_t)pz + c0 + c) * L;
+  fft_regs<T, L, false>(v, g, tile[c], tw2);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const Cx<T> s = g0[fft_elem<L>(g, e)];
+    v[e] = adj ? cmul_conj(s, v[e]) : s * v[e];
+  }
+  fft_regs<T, L, true>(v, g, tile[c], tw2);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    acc[e] = v[e];
+    v[e] = xin[e] * tw2[fft_elem<L>(g, e)];
+  }
+  fft_regs<T, L, false>(v, g, tile[c], tw2);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const Cx<T> s = g1[fft_elem<L>(g, e)];
+    v[e] = adj ? cmul_conj(s, v[e]) : s * v[e];
+  }
+  fft_regs<T, L, true>(v, g, tile[c], tw2);
+  wave_sync();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int p = fft_elem<L>(g, e);
+    tile[c][lds_pad(p)] = acc[e] + cmul_conj(tw2[p], v[e]);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nx * C; idx += NT) {
+    const int i = idx / C, cc = idx % C;
+    tb[(size_t)i * pz + cc] = tile[cc][lds_pad(i)];
+  }
+}
+
+// ------------------------------------------------------------------ pass 3
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_rows_inv(const Cx<T>* __restrict__ tmp, const Cx<T>* x,
+                                                   const T* __restrict__ chi, const Cx<T>* rhs, Cx<T>* y,
+                                                   double* __restrict__ rnorm, const int* __restrict__ vidx, int nx,
+                                                   int nz, int nitems, int epi, const Cx<T>* __restrict__ tw2) {
+  using P = FftPlan<L>;
+  constexpr int G = P::G, E = P::E, GPW = 256 / G;
+  __shared__ Cx<T> sbuf[GPW][lds_len<L>()];
+  const int grp = threadIdx.x / G, g = threadIdx.x % G;
+  const size_t vstride = (size_t)nx * nz;
+  for (int base = blockIdx.x * GPW; base < nitems; base += gridDim.x * GPW) {
+    const int item = base + grp;
+    const bool valid = item < nitems;
+    const int it = valid ? item : nitems - 1;
+    const int slot = it / nx, i = it % nx;
+    const int vi = vidx ? vidx[slot] : slot;
+    const Cx<T>* tr = tmp + ((size_t)slot * nx + i) * (2 * L);
+    Cx<T> v[E], acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = tr[fft_elem<L>(g, e)];
+    fft_regs<T, L, true>(v, g, sbuf[grp], tw2);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      acc[e] = v[e];
+      v[e] = tr[L + fft_elem<L>(g, e)];
+    }
+    fft_regs<T, L, true>(v, g, sbuf[grp], tw2);
+    const size_t off = (size_t)vi * vstride + (size_t)i * nz;
+    double nrm = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int p = fft_elem<L>(g, e);
+      if (p < nz) {
+        const Cx<T> conv = acc[e] + cmul_conj(tw2[p], v[e]);
+        Cx<T> out;
+        switch (epi) {
+          case 0: out = x[off + p] - conv; break;
+          case 1: out = conv; break;
+          case 2: out = x[off + p] - chi[(size_t)i * nz + p] * conv; break;
+          default: out = chi[(size_t)i * nz + p] * conv; break;
+        }
+        if (rhs) {
+          out = out - rhs[off + p];
+          nrm += (double)out.re * (double)out.re + (double)out.im * (double)out.im;
+        }
+        if (valid) y[off + p] = out;
+      }
+    }
+    if (rnorm) {
+#pragma unroll
+      for (int o = G / 2; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o);
+      if (valid && g == 0) atomicAdd(&rnorm[slot], nrm);
+    }
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------- spectrum set-up
+// Row pass: row p of the circulant table (length pz = 2 lz, full input),
+// written transposed to s1t[c][p] in the split column order.
+template <int L>
+__global__ __launch_bounds__(256) void k_spec_rows(const Cx<double>* __restrict__ ktab, int nx, int nz, int px,
+                                                    Cx<double>* __restrict__ s1t, const Cx<double>* __restrict__ tw2) {
+  using P = FftPlan<L>;
+  constexpr int G = P::G, E = P::E, GPW = 256 / G;
+  __shared__ Cx<double> sbuf[GPW][lds_len<L>()];
+  const int grp = threadIdx.x / G, g = threadIdx.x % G;
+  const int pz = 2 * L;
+  for (int base = blockIdx.x * GPW; base < px; base += gridDim.x * GPW) {
+    const int p = base + grp;
+    const bool valid = p < px;
+    const int pp = valid ? p : px - 1;
+    const int lxp = pp < px - pp ? pp : px - pp;
+    Cx<double> a[E], b[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = fft_elem<L>(g, e);
+      // lags of q and q + L
+      const int l1 = q, l2 = pz - (q + L);  // q < L so min(q, pz - q) = q; q + L >= L
+      const int lz2 = (q + L) < l2 ? (q + L) : l2;
+      Cx<double> k1 = czero<double>(), k2 = czero<double>();
+      if (lxp < nx && l1 < nz) k1 = ktab[(size_t)lxp * nz + l1];
+      if (lxp < nx && lz2 < nz) k2 = ktab[(size_t)lxp * nz + lz2];
+      a[e] = k1 + k2;
+      b[e] = (k1 - k2) * tw2[q];
+    }
+    fft_regs<double, L, false>(a, g, sbuf[grp], tw2);
+    fft_regs<double, L, false>(b, g, sbuf[grp], tw2);
+    if (valid) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int m = fft_elem<L>(g, e);
+        s1t[(size_t)m * px + p] = a[e];
+        s1t[(size_t)(L + m) * px + p] = b[e];
+      }
+    }
+    wave_sync();
+  }
+}
+
+// Column pass: full-length transform of s1t[c][0..px) -> gs[h][c][m] scaled.
+template <int L>
+__global__ __launch_bounds__(256) void k_spec_cols(const Cx<double>* __restrict__ s1t, int pz,
+                                                    Cx<double>* __restrict__ gs64, Cx<float>* __restrict__ gs32,
+                                                    double scale, const Cx<double>* __restrict__ tw2) {
+  using P = FftPlan<L>;
+  constexpr int G = P::G, E = P::E, GPW = 256 / G;
+  __shared__ Cx<double> sbuf[GPW][lds_len<L>()];
+  const int grp = threadIdx.x / G, g = threadIdx.x % G;
+  const int px = 2 * L;
+  for (int base = blockIdx.x * GPW; base < pz; base += gridDim.x * GPW) {
+    const int c = base + grp;
+    const bool valid = c < pz;
+    const int cc = valid ? c : pz - 1;
+    const Cx<double>* col = s1t + (size_t)cc * px;
+    Cx<double> a[E], b[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int p = fft_elem<L>(g, e);
+      const Cx<double> k1 = col[p], k2 = col[p + L];
+      a[e] = k1 + k2;
+      b[e] = (k1 - k2) * tw2[p];
+    }
+    fft_regs<double, L, false>(a, g, sbuf[grp], tw2);
+    fft_regs<double, L, false>(b, g, sbuf[grp], tw2);
+    if (valid) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int m = fft_elem<L>(g, e);
+        const Cx<double> va = scale * a[e], vb = scale * b[e];
+        if (gs64) {
+          gs64[(size_t)cc * L + m] = va;
+          gs64[((size_t)pz + cc) * L + m] = vb;
+        }
+        if (gs32) {
+          gs32[(size_t)cc * L + m] = ccast<float>(va);
+          gs32[((size_t)pz + cc) * L + m] = ccast<float>(vb);
+        }
+      }
+    }
+    wave_sync();
+  }
+}
+
+__global__ void k_contrast(const double* __restrict__ vel, double* __restrict__ chi64, float* __restrict__ chi32,
+                           int n, double w2, double inv_c02, unsigned* bad) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const double c = vel[k];
+    if (!(c > 0.0) || !isfinite(c)) atomicOr(bad, 1u);
+    const double chi = w2 * (1.0 / (c * c) - inv_c02);
+    if (chi64) chi64[k] = chi;
+    if (chi32) chi32[k] = (float)chi;
+  }
+}
+
+__global__ void k_table(Cx<double>* __restrict__ ktab, int nx, int nz, double k0h, Cx<double> cj1,
+                        Cx<double> self) {
+  const int n = nx * nz;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const int p = k / nz, q = k % nz;
+    if (p == 0 && q == 0) {
+      ktab[k] = self;
+      continue;
+    }
+    const double x = k0h * sqrt((double)(p * p + q * q));
+    double j0, y0;
+    lsop_bessel::hankel0(x, &j0, &y0);
+    ktab[k] = cj1 * Cx<double>{j0, y0};
+  }
+}
+
+template <typename T>
+__global__ void k_incident(const Cx<double>* __restrict__ ktab, const int* __restrict__ si,
+                           const int* __restrict__ sj, const Cx<double>* __restrict__ amp, Cx<T>* __restrict__ out,
+                           int nx, int nz, int nsrc, double inv_dv) {
+  const size_t n = (size_t)nx * nz, total = n * nsrc;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x) {
+    const int s = (int)(k / n);
+    const int r = (int)(k % n);
+    const int i = r / nz, j = r % nz;
+    const int di = abs(i - si[s]), dj = abs(j - sj[s]);
+    const Cx<double> v = inv_dv * (amp[s] * ktab[(size_t)di * nz + dj]);
+    out[k] = ccast<T>(v);
+  }
+}
+
+// -------------------------------------------------------------- launchers
+namespace {
+int grid_for_rows(int nitems, int gpw) {
+  const int need = (nitems + gpw - 1) / gpw;
+  const int cap = 256 * 8;
+  return need < cap ? need : cap;
+}
+}  // namespace
+
+#define LSOP_DISPATCH_L(L, ...)                                \
+  switch (L) {                                                 \
+    case 32: { constexpr int LL = 32; __VA_ARGS__; } break;     \
+    case 64: { constexpr int LL = 64; __VA_ARGS__; } break;     \
+    case 96: { constexpr int LL = 96; __VA_ARGS__; } break;     \
+    case 128: { constexpr int LL = 128; __VA_ARGS__; } break;   \
+    case 192: { constexpr int LL = 192; __VA_ARGS__; } break;   \
+    case 256: { constexpr int LL = 256; __VA_ARGS__; } break;   \
+    case 384: { constexpr int LL = 384; __VA_ARGS__; } break;   \
+    case 512: { constexpr int LL = 512; __VA_ARGS__; } break;   \
+    case 768: { constexpr int LL = 768; __VA_ARGS__; } break;   \
+    case 1024: { constexpr int LL = 1024; __VA_ARGS__; } break; \
+    case 2048: { constexpr int LL = 2048; __VA_ARGS__; } break; \
+    default: return hipErrorInvalidValue;                      \
+  }
+
+template <typename T>
+hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, const int* vidx, int nx, int nz,
+                           int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s) {
+  const int nitems = nslots * nx;
+  if (nitems <= 0) return hipSuccess;
+  LSOP_DISPATCH_L(L, {
+    constexpr int GPW = 256 / FftPlan<LL>::G;
+    hipLaunchKernelGGL((k_rows_fwd<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(256), 0, s, x, chi, tmp, vidx,
+                       nx, nz, nitems, (int)mulchi, tw2);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int nslots, bool adj, const Cx<T>* tw2,
+                       hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  LSOP_DISPATCH_L(L, {
+    constexpr int C = ColTile<T, LL>::C;
+    const int ntiles = pz / C;
+    hipLaunchKernelGGL((k_cols<T, LL>), dim3(ntiles * nslots), dim3(C * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz,
+                       nslots, (int)adj, tw2);
+  });
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rows_inv(int L, const Cx<T>* tmp, const Cx<T>* x, const T* chi, const Cx<T>* rhs, Cx<T>* y,
+                           double* rnorm, const int* vidx, int nx, int nz, int nslots, int epi, const Cx<T>* tw2,
+                           hipStream_t s) {
+  const int nitems = nslots * nx;
+  if (nitems <= 0) return hipSuccess;
+  LSOP_DISPATCH_L(L, {
+    constexpr int GPW = 256 / FftPlan<LL>::G;
+    hipLaunchKernelGGL((k_rows_inv<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(256), 0, s, tmp, x, chi, rhs, y,
+                       rnorm, vidx, nx, nz, nitems, epi, tw2);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_spectrum(int lx, int lz, const Cx<double>* ktab, int nx, int nz, Cx<double>* s1t,
+                           Cx<double>* gs64, Cx<float>* gs32, const Cx<double>* tw2x, const Cx<double>* tw2z,
+                           hipStream_t s) {
+  const int px = 2 * lx, pz = 2 * lz;
+  LSOP_DISPATCH_L(lz, {
+    constexpr int GPW = 256 / FftPlan<LL>::G;
+    hipLaunchKernelGGL((k_spec_rows<LL>), dim3(grid_for_rows(px, GPW)), dim3(256), 0, s, ktab, nx, nz, px, s1t,
+                       tw2z);
+  });
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const double scale = 1.0 / ((double)px * (double)pz);
+  LSOP_DISPATCH_L(lx, {
+    constexpr int GPW = 256 / FftPlan<LL>::G;
+    hipLaunchKernelGGL((k_spec_cols<LL>), dim3(grid_for_rows(pz, GPW)), dim3(256), 0, s, s1t, pz, gs64, gs32, scale,
+                       tw2x);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_contrast(const double* vel, double* chi64, float* chi32, int n, double w2, double inv_c02,
+                           unsigned* bad, hipStream_t s) {
+  int grid = (n + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_contrast, dim3(grid), dim3(256), 0, s, vel, chi64, chi32, n, w2, inv_c02, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_table(Cx<double>* ktab, int nx, int nz, double k0h, Cx<double> cj1, Cx<double> self,
+                        hipStream_t s) {
+  const int n = nx * nz;
+  int grid = (n + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_table, dim3(grid), dim3(256), 0, s, ktab, nx, nz, k0h, cj1, self);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_incident(const Cx<double>* ktab, const int* si, const int* sj, const Cx<double>* amp, Cx<T>* out,
+                           int nx, int nz, int nsrc, double inv_dv, hipStream_t s) {
+  const size_t total = (size_t)nx * nz * nsrc;
+  size_t grid = (total + 255) / 256;
+  if (grid > 16384) grid = 16384;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_incident<T>), dim3((unsigned)grid), dim3(256), 0, s, ktab, si, sj, amp, out, nx, nz, nsrc,
+                     inv_dv);
+  return hipGetLastError();
+}
+
+#define LSOP_INST(T)                                                                                               \
+  template hipError_t launch_rows_fwd<T>(int, const Cx<T>*, const T*, Cx<T>*, const int*, int, int, int, bool,    \
+                                         const Cx<T>*, hipStream_t);                                              \
+  template hipError_t launch_cols<T>(int, Cx<T>*, const Cx<T>*, int, int, int, bool, const Cx<T>*, hipStream_t);  \
+  template hipError_t launch_rows_inv<T>(int, const Cx<T>*, const Cx<T>*, const T*, const Cx<T>*, Cx<T>*,        \
+                                         double*, const int*, int, int, int, int, const Cx<T>*, hipStream_t);     \
+  template hipError_t launch_incident<T>(const Cx<double>*, const int*, const int*, const Cx<double>*, Cx<T>*,    \
+                                         int, int, int, double, hipStream_t);
+LSOP_INST(float)
+LSOP_INST(double)
+
+}  // namespace lsop

@@ -1,0 +1,267 @@
+"""ctypes binding of liblsop.so (argument marshalling only).
+
+Every numerical step runs in the HIP library; this module checks tensor
+shapes/dtypes, passes raw device pointers and the current HIP stream, and
+turns status codes into exceptions.  torch supplies device memory and
+streams.  Importing this module does not load the library; the first call
+does, and raises if ``liblsop.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblsop.so")
+
+# status codes (include/lsop.h)
+OK, EINVAL, ENOMEM, EHIP, NOT_CONVERGED, DIVERGED, ESINGULAR, EUNSUPPORTED = range(8)
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", NOT_CONVERGED: "NOT_CONVERGED",
+                DIVERGED: "DIVERGED", ESINGULAR: "ESINGULAR", EUNSUPPORTED: "EUNSUPPORTED"}
+C64, C128, MIXED = 0, 1, 2
+MODES = {"A": 0, "G0V": 1, "AH": 2, "VHG0H": 3}
+PC_IDENTITY, PC_LOWRANK = 0, 1
+INIT = {"h_rhs": 0, "zero": 1, "user": 2}
+
+EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident",
+           "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "precond_create",
+           "precond_build", "precond_apply", "precond_info", "precond_destroy", "series_solve",
+           "lsop_bessel_host")
+
+
+class LsopError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class OpInfo(C.Structure):
+    _fields_ = [("nx", C.c_int), ("nz", C.c_int), ("lx", C.c_int), ("lz", C.c_int), ("dtype", C.c_int),
+                ("max_vec", C.c_int), ("state_bytes", C.c_size_t)]
+
+
+class PrecondParams(C.Structure):
+    _fields_ = [("kind", C.c_int), ("rank", C.c_int), ("power_iters", C.c_int), ("seed", C.c_uint64)]
+
+
+class SolveParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("init", C.c_int), ("refine_max", C.c_int),
+                ("inner_tol", C.c_double)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int), ("refine_steps", C.c_int), ("rel_residual", C.c_double), ("status", C.c_int)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load liblsop.so and declare its signatures (no GPU call is made)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2005_01372_amd.build`")
+    lib = C.CDLL(path)
+    vp, ip, dp = C.c_void_p, C.c_int, C.c_double
+    sig = {
+        "lsop_create": (ip, [ip, ip, ip, ip, C.POINTER(vp)]),
+        "lsop_set_problem": (ip, [vp, vp, dp, dp, dp, vp]),
+        "lsop_apply": (ip, [vp, ip, vp, vp, ip, vp]),
+        "lsop_residual": (ip, [vp, vp, vp, vp, vp, ip, vp]),
+        "lsop_incident": (ip, [vp, vp, vp, vp, ip, vp, vp]),
+        "lsop_kernel_table": (ip, [vp, vp, vp]),
+        "lsop_info": (ip, [vp, C.POINTER(OpInfo)]),
+        "lsop_destroy": (None, [vp]),
+        "lsop_last_error": (C.c_char_p, []),
+        "precond_create": (ip, [vp, C.POINTER(PrecondParams), C.POINTER(vp)]),
+        "precond_build": (ip, [vp, vp, vp]),
+        "precond_apply": (ip, [vp, vp, vp, ip, vp]),
+        "precond_info": (ip, [vp, C.POINTER(ip), C.POINTER(dp), C.POINTER(C.c_size_t)]),
+        "precond_destroy": (None, [vp]),
+        "series_solve": (ip, [vp, vp, vp, vp, ip, C.POINTER(SolveParams), C.POINTER(SolveInfo), vp]),
+        "lsop_bessel_host": (ip, [ip, dp, C.POINTER(dp)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status, allow=()):
+    if status != OK and status not in allow:
+        raise LsopError(status, _lib.lsop_last_error().decode())
+    return status
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def bessel_host(kind, x):
+    lib = load_library()
+    out = (C.c_double * 2)()
+    _check(lib.lsop_bessel_host(int(kind), float(x), out))
+    return out[0], out[1]
+
+
+class Operator:
+    """The LS operator of one grid and medium (lsop_create + lsop_set_problem)."""
+
+    def __init__(self, nx, nz, dtype=C128, max_vec=64):
+        self.lib = load_library()
+        self.nx, self.nz, self.dtype, self.max_vec = int(nx), int(nz), int(dtype), int(max_vec)
+        h = C.c_void_p()
+        _check(self.lib.lsop_create(self.nx, self.nz, self.dtype, self.max_vec, C.byref(h)))
+        self.handle = h
+        self.vec_dtype = torch.complex64 if self.dtype == C64 else torch.complex128
+        self.inner_dtype = torch.complex64 if self.dtype in (C64, MIXED) else torch.complex128
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.lsop_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        inf = OpInfo()
+        _check(self.lib.lsop_info(self.handle, C.byref(inf)))
+        return inf
+
+    def set_problem(self, vel, h, freq, c0=2000.0):
+        vel = torch.as_tensor(vel, dtype=torch.float64)
+        if not vel.is_cuda:
+            vel = vel.cuda()
+        vel = vel.contiguous()
+        if tuple(vel.shape) != (self.nx, self.nz):
+            raise ValueError(f"velocity must be {(self.nx, self.nz)}")
+        self._vel = vel
+        _check(self.lib.lsop_set_problem(self.handle, _ptr(vel), float(h), float(freq), float(c0), _stream()))
+        self.h, self.freq, self.c0 = float(h), float(freq), float(c0)
+        return self
+
+    def _vecs(self, x, dtype=None):
+        dtype = dtype or self.vec_dtype
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dtype and x.is_contiguous()):
+            raise TypeError(f"expected a contiguous CUDA tensor of {dtype}")
+        if x.shape[-2:] != (self.nx, self.nz):
+            raise ValueError(f"vectors must end in {(self.nx, self.nz)}")
+        return x.numel() // (self.nx * self.nz)
+
+    def apply(self, x, mode="A", out=None):
+        nv = self._vecs(x)
+        out = torch.empty_like(x) if out is None else out
+        self._vecs(out)
+        _check(self.lib.lsop_apply(self.handle, MODES[mode], _ptr(x), _ptr(out), nv, _stream()))
+        return out
+
+    def residual(self, psi, rhs, out=None):
+        nv = self._vecs(psi)
+        self._vecs(rhs)
+        out = torch.empty_like(psi) if out is None else out
+        nrm = torch.empty(nv, dtype=torch.float64, device=psi.device)
+        _check(self.lib.lsop_residual(self.handle, _ptr(psi), _ptr(rhs), _ptr(out), _ptr(nrm), nv, _stream()))
+        return out, nrm
+
+    def incident(self, src_i, src_j, amp=None):
+        si = (C.c_int * len(src_i))(*[int(v) for v in src_i])
+        sj = (C.c_int * len(src_j))(*[int(v) for v in src_j])
+        if amp is not None:
+            a = []
+            for v in amp:
+                a += [complex(v).real, complex(v).imag]
+            ap = (C.c_double * len(a))(*a)
+        else:
+            ap = None
+        out = torch.empty((len(src_i), self.nx, self.nz), dtype=self.vec_dtype, device="cuda")
+        _check(self.lib.lsop_incident(self.handle, si, sj, ap, len(src_i), _ptr(out), _stream()))
+        return out
+
+    def kernel_table(self):
+        out = torch.empty((self.nx, self.nz), dtype=torch.complex128, device="cuda")
+        _check(self.lib.lsop_kernel_table(self.handle, _ptr(out), _stream()))
+        return out
+
+
+class Preconditioner:
+    """H for the series: identity (Born) or the randomized low-rank SMW form (Alg. 2 + eq. 12)."""
+
+    def __init__(self, op, kind=PC_LOWRANK, rank=32, power_iters=0, seed=0):
+        self.op, self.lib = op, op.lib
+        p = PrecondParams(int(kind), int(rank), int(power_iters), int(seed))
+        h = C.c_void_p()
+        _check(self.lib.precond_create(op.handle, C.byref(p), C.byref(h)))
+        self.handle = h
+        self.kind, self.rank = kind, rank
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.precond_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build(self, omega=None):
+        if omega is not None:
+            omega = torch.as_tensor(omega, dtype=torch.float64)
+            omega = (omega if omega.is_cuda else omega.cuda()).contiguous()
+            if omega.numel() != self.rank * self.op.nx * self.op.nz:
+                raise ValueError("omega must hold rank x nx*nz values")
+            self._omega = omega
+        return _check(self.lib.precond_build(self.handle, _ptr(omega) if omega is not None else None, _stream()))
+
+    def apply(self, x, out=None):
+        nv = self.op._vecs(x, self.op.inner_dtype)
+        out = torch.empty_like(x) if out is None else out
+        _check(self.lib.precond_apply(self.handle, _ptr(x), _ptr(out), nv, _stream()))
+        return out
+
+    def info(self):
+        r, comp, nb = C.c_int(), C.c_double(), C.c_size_t()
+        _check(self.lib.precond_info(self.handle, C.byref(r), C.byref(comp), C.byref(nb)))
+        return r.value, comp.value, nb.value
+
+
+@dataclass
+class SolveResult:
+    iters: int
+    refine_steps: int
+    rel_residual: float
+    status: int
+
+    @property
+    def status_name(self):
+        return STATUS_NAMES.get(self.status, str(self.status))
+
+
+def series_solve(op, pc, rhs, psi=None, tol=1e-10, max_iter=30, init="h_rhs", refine_max=8, inner_tol=1e-5,
+                 raise_on_failure=False):
+    """Preconditioned scattering series (eq. 11); returns (psi, [SolveResult per right-hand side])."""
+    nv = op._vecs(rhs)
+    psi = torch.empty_like(rhs) if psi is None else psi
+    op._vecs(psi)
+    p = SolveParams(float(tol), int(max_iter), INIT[init], int(refine_max), float(inner_tol))
+    info = (SolveInfo * nv)()
+    st = op.lib.series_solve(op.handle, pc.handle if pc is not None else None, _ptr(rhs), _ptr(psi), nv,
+                             C.byref(p), info, _stream())
+    _check(st, allow=() if raise_on_failure else (NOT_CONVERGED, DIVERGED))
+    return psi, [SolveResult(i.iters, i.refine_steps, i.rel_residual, i.status) for i in info]
