@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark of the preconditioned Lippmann-Schwinger solver on one MI355X.
+
+One step is one pass of the whole path over one batch: set the medium
+(contrast, FP64 kernel table, circulant spectrum), form the incident fields of
+all sources, build the randomized low-rank preconditioner (Alg. 2 + eq. 12),
+and run the preconditioned scattering series (eq. 11) for every source to the
+relative residual target.  Inputs (velocity grid, source positions) are
+resident before the timed region.  The default workload is the 1024 x 1024
+grid at h = 5 m and 25 Hz with 128 sources on the top row and 64 probes,
+computed in complex FP32 (QR / LU in FP64).
+
+Printed: one JSON line with the solves/s of sources that reached the target,
+the dominant kernel's roofline position (event-timed inside the timed
+region), the batched operator throughput, and the FP64 oracle timed on a
+bounded sample of the same workload on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LS solves/s to rel. residual 1e-6 at 1024^2 x128 src; FFT-conv HBM GB/s"
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1024, help="grid side (default: the 1024^2 workload)")
+    ap.add_argument("--nsrc", type=int, default=128)
+    ap.add_argument("--rank", type=int, default=64)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--max-iter", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sources", type=int, default=2, help="sources in the oracle's timed sample")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run only a 1 GiB device copy and a few batched applies (for rocprofv3 --pmc)")
+    return ap.parse_args()
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("kernels_fft.hip", "kernels_la.hip", "fft_engine.hpp"):
+        with open(os.path.join(ROOT, "paper_2005_01372_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel):
+    """Counter-measured HBM bytes per launch from the committed summary, if it matches the current source."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    k = d.get("kernels", {}).get(kernel)
+    if not k or d.get("source_sha") != kernel_source_sha():
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, rank, iterations, converged, nsrc_sample=2, nprobe_sample=2):
+    """The FP64 oracle (numpy / scipy, as written) timed on a bounded sample of the same step.
+
+    Sample: the full problem set-up; the two operator applications of Alg. 2
+    (G0 V Omega and V^H G0^H Q) for nprobe_sample of the `rank` probes,
+    extrapolated linearly; one n x rank Householder QR and the SMW core at
+    full size; one series iteration (residual + update with a rank-`rank` H)
+    for nsrc_sample sources, scaled by the number of source-iterations the
+    GPU run of the same method needed.  `converged` sources count as solves.
+    """
+    import numpy as np
+
+    from oracle import lsop_oracle as O
+    from paper_2005_01372_amd import synth
+
+    cores = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+    prob.workers = cores
+    t_setup = time.perf_counter() - t0
+    om = synth.gaussian_probes(prob.n, rank, 3)
+    t1 = time.perf_counter()
+    Y = prob.apply(om[:nprobe_sample].reshape(nprobe_sample, prob.nx, prob.nz).astype(np.complex128), "G0V")
+    prob.apply(Y, "VHG0H")
+    t_apply = (time.perf_counter() - t1) * rank / nprobe_sample
+    t2 = time.perf_counter()
+    Q = O.orth(om.T.astype(np.complex128))
+    H = O.LowRankPreconditioner(Q, 1e-3 * Q)   # a rank-`rank` H of the right shapes (SMW core included)
+    t_qr = time.perf_counter() - t2
+    del Y
+    # one series iteration (eq. 13 residual + eq. 11 update) on nsrc_sample sources, timed per source-iteration
+    psi0 = prob.incident(w.src_i[:nsrc_sample], w.src_j[:nsrc_sample])
+    t3 = time.perf_counter()
+    for k in range(nsrc_sample):
+        psi = H.apply(psi0[k])
+        a = prob.apply(psi, "A") - psi0[k]
+        psi = psi - H.apply(a)
+    t_iter = (time.perf_counter() - t3) / nsrc_sample
+    it_total = sum(i + 1 for i in iterations)  # residual evaluations the GPU run needed, all sources
+    step_s = t_setup + t_apply + t_qr + t_iter * it_total
+    return {
+        "value": converged / step_s, "unit": "solves/s", "cores": cores, "kind": "oracle",
+        "sample": f"set-up; Alg. 2 applications for {nprobe_sample} of {rank} probes (x{rank // nprobe_sample}); "
+                  f"one {prob.n}x{rank} QR + SMW core; one series iteration for {nsrc_sample} sources, scaled by the "
+                  f"{it_total} source-iterations of the GPU run (same method, same stopping rule); "
+                  f"scipy.fft workers={cores}",
+        "step_seconds_extrapolated": round(step_s, 2), "setup_s": round(t_setup, 2),
+        "build_s_extrapolated": round(t_apply + t_qr, 2), "seconds_per_source_iteration": round(t_iter, 3),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in the design "
+                                   "notes but not implemented", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2005_01372_amd import lsop, synth
+
+    torch.cuda.init()
+    w = synth.model_random_ellipses(n=args.n, nsrc=args.nsrc)
+    vel = torch.as_tensor(w.vel, device="cuda")
+    op = lsop.Operator(w.nx, w.nz, lsop.C64, max_vec=max(args.nsrc, args.rank))
+    pc = lsop.Preconditioner(op, lsop.PC_LOWRANK, rank=args.rank, seed=3)
+    psi = torch.empty((w.nsrc, w.nx, w.nz), dtype=torch.complex64, device="cuda")
+    op.set_problem(vel, w.h, w.freq, w.c0)
+    op.autotune(w.nsrc)
+
+    if args.pmc_probe:
+        a = torch.ones(1 << 27, dtype=torch.complex64, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        op.set_problem(vel, w.h, w.freq, w.c0)
+        x = torch.ones((args.nsrc, w.nx, w.nz), dtype=torch.complex64, device="cuda")
+        for _ in range(3):
+            op.apply(x, "A", out=psi)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": True, "copy_bytes": 2 * a.numel() * 8}))
+        return
+
+    def step():
+        op.set_problem(vel, w.h, w.freq, w.c0)
+        rhs = op.incident(w.src_i, w.src_j)
+        pc.build(None)
+        _, info = lsop.series_solve(op, pc, rhs, psi=psi, tol=args.tol, max_iter=args.max_iter)
+        return info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lsop.profile_reset()
+    lsop.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        info = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lsop.profile_enable(False)
+    stats = lsop.profile_read()
+    lsop.profile_reset()
+    step_s = (t1 - t0) / args.steps
+    converged = sum(i.status == lsop.OK for i in info)
+    statuses = {}
+    for i in info:
+        statuses[i.status_name] = statuses.get(i.status_name, 0) + 1
+    iters = [i.iters for i in info]
+
+    # dominant kernel (largest share of event-timed GPU time in the timed region)
+    dom = max(stats, key=lambda k: stats[k]["ms"])
+    d = stats[dom]
+    avg_s = d["ms"] / d["launches"] / 1e3
+    bpl = d["bytes"] / d["launches"]
+    achieved = bpl / avg_s / 1e9
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": load_traffic(dom),
+                "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_bytes_per_launch": bpl,
+                "launches": d["launches"]}
+    kernels = {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4),
+                   "share": round(v["ms"] / sum(s["ms"] for s in stats.values()), 4),
+                   "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)} for k, v in stats.items()}
+
+    # FFT-convolution throughput inside the timed region: the three passes together
+    passes = [k for k in ("lsop_rows_fwd", "lsop_cols", "lsop_rows_inv") if k in stats]
+    fft_bytes = sum(stats[k]["bytes"] for k in passes)
+    fft_ms = sum(stats[k]["ms"] for k in passes)
+    fft_gbps = fft_bytes / (fft_ms / 1e3) / 1e9
+    vec_applies = stats["lsop_cols"]["items"] if "lsop_cols" in stats else 0
+    # growth factor of the residual per iteration (an estimate of rho(M) when the series diverges)
+    growth = [(i.rel_residual / i.rel_residual0) ** (1.0 / i.iters) for i in info if i.iters > 0
+              and i.rel_residual0 > 0 and np.isfinite(i.rel_residual)]
+
+    line = {
+        "metric": METRIC, "value": converged / step_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"smooth random 1500-5000 m/s + 6 ellipses, {w.nx}x{w.nz}, h={w.h} m, {w.freq} Hz, "
+                               f"c0={w.c0} m/s, {w.nsrc} top-row sources, low-rank H rank {args.rank} (q=0), "
+                               f"series to rel. residual {args.tol}, cap {args.max_iter}",
+                   "grid": [w.nx, w.nz], "sources": w.nsrc, "rank": args.rank, "tol": args.tol},
+        "converged": converged, "statuses": statuses, "iterations": [min(iters), max(iters)],
+        "residual_growth_per_iter": round(float(np.median(growth)), 3) if growth else None,
+        "fft_conv_GBps": round(fft_gbps, 1), "fft_conv_frac_of_peak": round(fft_gbps / HBM_PEAK_GBPS, 4),
+        "operator_applications_per_s": round(vec_applies / (fft_ms / 1e3), 1),
+        "col_tile": op.info().col_tile,
+        "roofline": roofline, "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, args.rank, iters, converged, args.cpu_sources)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -40,7 +40,7 @@ typedef enum {
   LSOP_EINVAL = 1,        /* bad argument (sizes, NaN/non-positive velocity, f <= 0, ...) */
   LSOP_ENOMEM = 2,        /* device allocation failed or batch exceeds capacity */
   LSOP_EHIP = 3,          /* HIP runtime error */
-  LSOP_NOT_CONVERGED = 4, /* series hit max_iter; best iterate and info are written */
+  LSOP_NOT_CONVERGED = 4, /* series hit max_iter; last iterate and info are written */
   LSOP_DIVERGED = 5,      /* residual non-finite or rising for 5 consecutive iterations */
   LSOP_ESINGULAR = 6,     /* I_r - W^H U is numerically singular (eq. 12) */
   LSOP_EUNSUPPORTED = 7   /* grid larger than the largest supported FFT length, bad dtype */
@@ -68,6 +68,7 @@ typedef struct {
   int dtype;       /* lsop_dtype */
   int max_vec;     /* vectors per internal batch */
   size_t state_bytes;  /* device bytes held by the handle */
+  int col_tile;    /* columns per workgroup in the column FFT pass (0 = widest that fits) */
 } lsop_op_info;
 
 /* Plan an operator for an nx x nz grid and allocate its device state.
@@ -75,8 +76,8 @@ typedef struct {
  * double) or LSOP_MIXED (complex double interface and outer residuals, with
  * complex-float inner solves; see series_solve).  max_vec bounds the
  * vectors processed per internal batch (larger calls are chunked).
- * Errors: EINVAL (nx, nz < 1, max_vec < 1), EUNSUPPORTED (nx or nz > 1024
- * for C128/MIXED, > 2048 for C64), ENOMEM. */
+ * Errors: EINVAL (nx, nz < 1, max_vec < 1), EUNSUPPORTED (nx or nz > 2048),
+ * ENOMEM. */
 int lsop_create(int nx, int nz, int dtype, int max_vec, lsop_op** out);
 
 /* Set the medium (Section 2.1): contrast chi = w^2 (1/c^2 - 1/c0^2) (eq. 1),
@@ -103,6 +104,13 @@ int lsop_residual(lsop_op* op, const void* psi_dev, const void* rhs_dev, void* r
  * psi0_dev: [nsrc][nx][nz].  Errors: EINVAL for a source outside the grid. */
 int lsop_incident(lsop_op* op, const int* src_i_host, const int* src_j_host,
                   const double* amp_reim_host, int nsrc, void* psi0_dev, void* stream);
+
+/* Autotune the FFT tile shape for batches of nvec vectors: times the
+ * column-pass kernel for each supported tile width (16, 8, 4, 2 columns per
+ * workgroup) on this operator's grid with HIP events and keeps the fastest for
+ * later calls.  Requires lsop_set_problem.  Synchronises `stream`; overwrites
+ * the operator's internal intermediate buffer only. */
+int lsop_autotune(lsop_op* op, int nvec, void* stream);
 
 /* Copy the FP64 kernel table K[p][q] (p < nx, q < nz; complex double,
  * [nx][nz]) to table_dev.  Diagnostic. */
@@ -179,6 +187,7 @@ typedef struct {
   int refine_steps;     /* outer steps (MIXED) */
   double rel_residual;  /* ||A psi - psi0|| / ||psi0|| of the returned iterate */
   int status;           /* lsop_status of this right-hand side */
+  double rel_residual0; /* relative residual of the initial iterate (first series for MIXED) */
 } lsop_solve_info;
 
 int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_dev, int nvec,
@@ -187,6 +196,25 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
 /* Diagnostics: FP64 Bessel evaluations used for the kernel table, on the host
  * (kind 0: (J0, Y0) at x > 0; kind 1: (J1, Y1) at 0 < x <= 2). */
 int lsop_bessel_host(int kind, double x, double* out2);
+
+/* Per-kernel timing (diagnostics).  While enabled, every kernel launch of the
+ * library is bracketed by HIP events recorded on its launch stream, and the
+ * kernel's algorithmic HBM bytes (compulsory reads + writes of that launch,
+ * by the formulas documented with each kernel) are accumulated by name.
+ * lsop_profile_read synchronises the device and returns up to max_stats
+ * entries (count = number of distinct kernels).  Not thread-safe. */
+typedef struct {
+  char name[48];
+  int launches;
+  double total_ms;      /* sum of event-measured launch durations */
+  double bytes;         /* sum of algorithmic bytes */
+  double flops;         /* sum of algorithmic floating-point operations */
+  double items;         /* vectors processed (FFT passes) or output columns (GEMMs) */
+} lsop_kernel_stat;
+
+int lsop_profile_enable(int on);
+int lsop_profile_reset(void);
+int lsop_profile_read(lsop_kernel_stat* stats, int max_stats, int* count);
 
 #ifdef __cplusplus
 }

@@ -1,6 +1,7 @@
 // C ABI of liblsop.so: operator, preconditioner and series solver handles.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -21,6 +22,41 @@ int fail(int status, const std::string& msg) {
 namespace {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ------------------------------------------------------------ profiler
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+  double bytes, flops, items;
+};
+bool g_prof = false;
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t ev_get() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Runs `launch` (returning hipError_t); while profiling, brackets it with events.
+template <typename F>
+hipError_t prof(const char* name, double bytes, double flops, double items, hipStream_t s, F&& launch) {
+  if (!g_prof) return launch();
+  ProfRec r{name, ev_get(), ev_get(), bytes, flops, items};
+  (void)hipEventRecord(r.a, s);
+  hipError_t e = launch();
+  (void)hipEventRecord(r.b, s);
+  g_recs.push_back(r);
+  return e;
+}
+
+double fft_flops(int L) { return 5.0 * L * std::log2((double)L); }
 
 template <typename P>
 int dev_alloc(std::vector<void*>& owned, size_t& bytes, P** out, size_t nbytes) {
@@ -101,12 +137,76 @@ int apply_impl(lsop_op* op, int mode, const Cx<T>* x, Cx<T>* y, const Cx<T>* rhs
     const int* vc = vidx ? vidx + c : nullptr;
     const size_t off = vidx ? 0 : (size_t)c * n;
     double* rn = rnorm ? rnorm + c : nullptr;
-    LSOP_HIP(launch_rows_fwd<T>(op->lz, x + off, Dt<T>::chi(op), tmp, vc, op->nx, op->nz, m, mulchi, Dt<T>::twz(op),
-                                s));
-    LSOP_HIP(launch_cols<T>(op->lx, tmp, Dt<T>::gs(op), op->nx, op->pz(), m, adj, Dt<T>::twx(op), s));
-    LSOP_HIP(launch_rows_inv<T>(op->lz, tmp, x + off, Dt<T>::chi(op), rhs ? rhs + off : nullptr, y + off, rn, vc,
-                                op->nx, op->nz, m, mode, Dt<T>::twz(op), s));
+    // algorithmic bytes: compulsory reads + writes of each pass (see the kernel file header)
+    const double e = sizeof(Cx<T>), t = sizeof(T), nn = (double)n, np = (double)op->nx * op->pz();
+    const double frow = 2.0 * fft_flops(op->lz) + 6.0 * op->lz;
+    const double fcol = 4.0 * fft_flops(op->lx) + 18.0 * op->lx;
+    const bool xin = (mode == LSOP_MODE_A || mode == LSOP_MODE_AH);
+    const bool chi_out = (mode == LSOP_MODE_AH || mode == LSOP_MODE_VHG0H);
+    LSOP_HIP(prof("lsop_rows_fwd", m * (nn * e + np * e) + (mulchi ? nn * t : 0.0), (double)m * op->nx * frow, m, s,
+                  [&] {
+                    return launch_rows_fwd<T>(op->lz, x + off, Dt<T>::chi(op), tmp, vc, op->nx, op->nz, m, mulchi,
+                                              Dt<T>::twz(op), s);
+                  }));
+    LSOP_HIP(prof("lsop_cols", m * 2.0 * np * e + 2.0 * op->pz() * op->lx * e, (double)m * op->pz() * fcol, m, s, [&] {
+      return launch_cols<T>(op->lx, tmp, Dt<T>::gs(op), op->nx, op->pz(), m, adj, Dt<T>::twx(op), s, op->col_tile);
+    }));
+    LSOP_HIP(prof("lsop_rows_inv",
+                  m * (np * e + nn * e + (xin ? nn * e : 0.0) + (rhs ? nn * e : 0.0)) + (chi_out ? nn * t : 0.0),
+                  (double)m * op->nx * frow, m, s, [&] {
+                    return launch_rows_inv<T>(op->lz, tmp, x + off, Dt<T>::chi(op), rhs ? rhs + off : nullptr,
+                                              y + off, rn, vc, op->nx, op->nz, m, mode, Dt<T>::twz(op), s);
+                  }));
   }
+  return LSOP_OK;
+}
+
+template <typename T>
+hipError_t p_gemm_ah_b(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n, Cx<double>* C,
+                       Cx<double>* part, int ksplit, hipStream_t s) {
+  const double e = sizeof(Cx<T>), nab = (double)na * nb * sizeof(Cx<double>);
+  return prof("lsop_gemm_ah_b", (double)(na + nb) * n * e + 2.0 * ksplit * nab + nab, 8.0 * na * nb * (double)n, nb,
+              s,
+              [&] { return launch_gemm_ah_b<T>(A, na, B, vidx, nb, n, C, part, ksplit, s); });
+}
+
+template <typename T>
+hipError_t p_gemm_update(const Cx<T>* A, int na, const Cx<double>* M, int nb, const Cx<T>* X1, const Cx<T>* X2,
+                         double beta, Cx<T>* Y, const int* vidx, size_t n, hipStream_t s) {
+  const double e = sizeof(Cx<T>);
+  const double vecs = 1.0 + (X1 ? 1.0 : 0.0) + (X2 ? 1.0 : 0.0);
+  return prof("lsop_gemm_update", (double)na * n * e + vecs * nb * (double)n * e + (double)na * nb * 16.0,
+              8.0 * na * nb * (double)n, nb, s,
+              [&] { return launch_gemm_update<T>(A, na, M, nb, X1, X2, beta, Y, vidx, n, s); });
+}
+
+// Times the column pass for each tile width on the operator's shape (m vectors
+// of whatever the intermediate buffer holds) and keeps the fastest.
+template <typename T>
+int autotune_cols(lsop_op* op, int m, hipStream_t s) {
+  Cx<T>* tmp = reinterpret_cast<Cx<T>*>(op->tmp);
+  hipEvent_t a, b;
+  LSOP_HIP(hipEventCreate(&a));
+  LSOP_HIP(hipEventCreate(&b));
+  float best = 1e30f;
+  int best_tile = 0;
+  for (int tile : {16, 8, 4, 2}) {
+    LSOP_HIP(launch_cols<T>(op->lx, tmp, Dt<T>::gs(op), op->nx, op->pz(), m, false, Dt<T>::twx(op), s, tile));
+    LSOP_HIP(hipEventRecord(a, s));
+    for (int rep = 0; rep < 3; ++rep)
+      LSOP_HIP(launch_cols<T>(op->lx, tmp, Dt<T>::gs(op), op->nx, op->pz(), m, false, Dt<T>::twx(op), s, tile));
+    LSOP_HIP(hipEventRecord(b, s));
+    LSOP_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    LSOP_HIP(hipEventElapsedTime(&ms, a, b));
+    if (ms < best * 0.98f) {
+      best = ms;
+      best_tile = tile;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  op->col_tile = best_tile;
   return LSOP_OK;
 }
 
@@ -128,9 +228,9 @@ int orth_impl(lsop_precond* pc, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s) {
   for (int pass = 0; pass < 2; ++pass) {
     const Cx<T>* src = pass == 0 ? Yin : Qout;
     Cx<T>* dst = pass == 0 ? Qout : Yin;
-    LSOP_HIP(launch_gemm_ah_b<T>(src, r, src, nullptr, r, n, G, pc->part, pc->ksplit, s));
+    LSOP_HIP(p_gemm_ah_b<T>(src, r, src, nullptr, r, n, G, pc->part, pc->ksplit, s));
     LSOP_HIP(launch_gram_orth(G, X, r, pass == 0 ? tol : 1e-6, pc->dflag, s));
-    LSOP_HIP(launch_gemm_update<T>(src, r, X, r, nullptr, nullptr, 0.0, dst, nullptr, n, s));
+    LSOP_HIP(p_gemm_update<T>(src, r, X, r, nullptr, nullptr, 0.0, dst, nullptr, n, s));
   }
   // result of pass 2 is in Yin; move it to Qout
   LSOP_HIP(hipMemcpyAsync(Qout, Yin, sizeof(Cx<T>) * (size_t)r * n, hipMemcpyDeviceToDevice, s));
@@ -165,7 +265,7 @@ int build_impl(lsop_precond* pc, const double* omega, hipStream_t s) {
   // eq. (12): Z = (I_r - W^H U)^{-1}
   Cx<double>* M = pc->small;
   Cx<double>* work = M + (size_t)r * r;
-  LSOP_HIP(launch_gemm_ah_b<T>(W, r, U, nullptr, r, n, M, pc->part, pc->ksplit, s));
+  LSOP_HIP(p_gemm_ah_b<T>(W, r, U, nullptr, r, n, M, pc->part, pc->ksplit, s));
   LSOP_HIP(launch_lu_inverse_i_minus(M, pc->Z, work, r, pc->dflag + 1, s));
   int flags[2] = {0, 0};
   LSOP_HIP(hipMemcpyAsync(flags, pc->dflag, sizeof(flags), hipMemcpyDeviceToHost, s));
@@ -203,12 +303,12 @@ int pc_apply_impl(lsop_precond* pc, const Cx<T>* x, Cx<T>* y, const int* vidx, i
     const int m = std::min(pc->tcap, nvec - c);
     const int* vc = vidx ? vidx + c : nullptr;
     const size_t off = vidx ? 0 : (size_t)c * n;
-    LSOP_HIP(launch_gemm_ah_b<T>(W, r, x + off, vc, m, n, T1, pc->part, pc->ksplit, s));
+    LSOP_HIP(p_gemm_ah_b<T>(W, r, x + off, vc, m, n, T1, pc->part, pc->ksplit, s));
     LSOP_HIP(launch_small_gemm(pc->Z, T1, T2, r, m, series_update ? -1.0 : 1.0, s));
     if (series_update)
-      LSOP_HIP(launch_gemm_update<T>(U, r, T2, m, y + off, x + off, -1.0, y + off, vc, n, s));
+      LSOP_HIP(p_gemm_update<T>(U, r, T2, m, y + off, x + off, -1.0, y + off, vc, n, s));
     else
-      LSOP_HIP(launch_gemm_update<T>(U, r, T2, m, x + off, nullptr, 0.0, y + off, vc, n, s));
+      LSOP_HIP(p_gemm_update<T>(U, r, T2, m, x + off, nullptr, 0.0, y + off, vc, n, s));
   }
   return LSOP_OK;
 }
@@ -271,6 +371,7 @@ int series_impl(lsop_op* op, lsop_precond* pc, const Cx<T>* rhs, Cx<T>* psi, int
       const double rel = b2[v] > 0 ? std::sqrt(rn[k] / b2[v]) : std::sqrt(rn[k]);
       info[v].iters = it;
       info[v].rel_residual = rel;
+      if (it == 0) info[v].rel_residual0 = rel;
       if (!std::isfinite(rel)) {
         info[v].status = LSOP_DIVERGED;
         continue;
@@ -336,6 +437,7 @@ int lsop_create(int nx, int nz, int dtype, int max_vec, lsop_op** out) {
   op->lz = lz;
   op->dtype = dtype;
   op->max_vec = max_vec;
+  if (const char* ct = getenv("LSOP_COL_TILE")) op->col_tile = atoi(ct);
   const size_t n = op->n();
   const size_t px = op->px(), pz = op->pz();
   int st = 0;
@@ -489,6 +591,16 @@ int lsop_incident(lsop_op* op, const int* src_i_host, const int* src_j_host, con
   return LSOP_OK;
 }
 
+int lsop_autotune(lsop_op* op, int nvec, void* stream) {
+  int st = check_op(op);
+  if (st) return st;
+  if (nvec < 1) return fail(LSOP_EINVAL, "nvec must be >= 1");
+  const int m = std::min(nvec, op->max_vec);
+  if (op->dtype == LSOP_C64) return autotune_cols<float>(op, m, S(stream));
+  if ((st = autotune_cols<double>(op, m, S(stream)))) return st;
+  return LSOP_OK;
+}
+
 int lsop_kernel_table(const lsop_op* op, void* table_dev, void* stream) {
   int st = check_op(op);
   if (st) return st;
@@ -506,6 +618,7 @@ int lsop_info(const lsop_op* op, lsop_op_info* info) {
   info->dtype = op->dtype;
   info->max_vec = op->max_vec;
   info->state_bytes = op->bytes + op->scratch_bytes;
+  info->col_tile = op->col_tile;
   return LSOP_OK;
 }
 
@@ -612,7 +725,7 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
   lsop_precond* pcu = (pc && pc->kind == LSOP_PC_LOWRANK) ? pc : nullptr;
   hipStream_t s = S(stream);
   const size_t n = op->n();
-  for (int v = 0; v < nvec; ++v) info[v] = lsop_solve_info{0, 0, INFINITY, LSOP_NOT_CONVERGED};
+  for (int v = 0; v < nvec; ++v) info[v] = lsop_solve_info{0, 0, INFINITY, LSOP_NOT_CONVERGED, INFINITY};
   if (op->dtype != LSOP_MIXED) {
     const size_t esz = op->dtype == LSOP_C64 ? sizeof(Cx<float>) : sizeof(Cx<double>);
     const size_t need = align_up(esz * n * nvec) + align_up(sizeof(double) * nvec) + align_up(sizeof(int) * nvec);
@@ -668,6 +781,7 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
       const int v = active[j];
       const double rel = b2[v] > 0 ? std::sqrt(rn[j] / b2[v]) : std::sqrt(rn[j]);
       info[v].rel_residual = rel;
+      if (k == 0) info[v].rel_residual0 = rel;
       info[v].refine_steps = k;
       info[v].iters = total_iters[v];
       if (!std::isfinite(rel)) info[v].status = LSOP_DIVERGED;
@@ -689,6 +803,46 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
     for (int v : active) total_iters[v] += inner[v].iters;
   }
   return overall_status(info, nvec);
+}
+
+int lsop_profile_enable(int on) {
+  g_prof = on != 0;
+  return LSOP_OK;
+}
+
+int lsop_profile_reset(void) {
+  (void)hipDeviceSynchronize();
+  for (auto& r : g_recs) {
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  return LSOP_OK;
+}
+
+int lsop_profile_read(lsop_kernel_stat* stats, int max_stats, int* count) {
+  if (!count || (max_stats > 0 && !stats)) return fail(LSOP_EINVAL, "null argument");
+  LSOP_HIP(hipDeviceSynchronize());
+  std::vector<lsop_kernel_stat> agg;
+  for (const auto& r : g_recs) {
+    float ms = 0.f;
+    LSOP_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    auto it = std::find_if(agg.begin(), agg.end(), [&](const lsop_kernel_stat& k) { return !strcmp(k.name, r.name); });
+    if (it == agg.end()) {
+      lsop_kernel_stat k{};
+      snprintf(k.name, sizeof(k.name), "%s", r.name);
+      agg.push_back(k);
+      it = agg.end() - 1;
+    }
+    it->launches += 1;
+    it->total_ms += ms;
+    it->bytes += r.bytes;
+    it->flops += r.flops;
+    it->items += r.items;
+  }
+  *count = (int)agg.size();
+  for (int i = 0; i < (int)agg.size() && i < max_stats; ++i) stats[i] = agg[i];
+  return LSOP_OK;
 }
 
 int lsop_bessel_host(int kind, double x, double* out2) {

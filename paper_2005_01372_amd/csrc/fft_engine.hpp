@@ -175,7 +175,21 @@ __device__ __forceinline__ int fft_elem(int g, int e) {
   return g + P::G * (e / R1) + (e % R1) * (L / R1);
 }
 
-// tw2 is the table w_{2L}^t = exp(-2 pi i t / (2L)), t < 2L (global memory).
+// Twiddle table: tw[t] = w_{2L}^t = exp(-2 pi i t / (2L)) for t < L (the
+// other half follows from w_{2L}^{t+L} = -w_{2L}^t).  Usually staged in LDS.
+template <typename T, int L>
+__device__ __forceinline__ Cx<T> tw_2l(const Cx<T>* __restrict__ tw, int t) {
+  const bool hi = t >= L;
+  const Cx<T> w = tw[hi ? t - L : t];
+  return hi ? Cx<T>{-w.re, -w.im} : w;
+}
+
+// Copy the L-entry twiddle table into LDS (whole workgroup; caller syncs).
+template <typename T, int L>
+__device__ __forceinline__ void stage_twiddles(Cx<T>* __restrict__ dst, const Cx<T>* __restrict__ src) {
+  for (int t = threadIdx.x; t < L; t += blockDim.x) dst[t] = src[t];
+}
+
 template <typename T, int L, bool INV, int S>
 struct FftStage {
   using P = FftPlan<L>;
@@ -194,7 +208,7 @@ struct FftStage {
         const int j = b % Ns;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          Cx<T> w = tw2[2 * (r * j * (L / (Ns * R)))];
+          Cx<T> w = tw_2l<T, L>(tw2, 2 * (r * j * (L / (Ns * R))));
           if constexpr (INV) w.im = -w.im;
           v[u * R + r] = v[u * R + r] * w;
         }

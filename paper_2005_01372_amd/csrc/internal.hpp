@@ -32,9 +32,10 @@ int fail(int status, const std::string& msg);
 template <typename T>
 hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, const int* vidx, int nx, int nz,
                            int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s);
+// tile: columns per workgroup (0 = widest that fits; narrower tiles allow more workgroups per CU)
 template <typename T>
 hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int nslots, bool adj, const Cx<T>* tw2,
-                       hipStream_t s);
+                       hipStream_t s, int tile = 0);
 // epi: 0 y = x - c, 1 y = c, 2 y = x - chi c, 3 y = chi c; rhs != NULL: y -= rhs and rnorm[slot] += |y|^2
 template <typename T>
 hipError_t launch_rows_inv(int L, const Cx<T>* tmp, const Cx<T>* x, const T* chi, const Cx<T>* rhs, Cx<T>* y,
@@ -95,6 +96,7 @@ hipError_t launch_small_gemm(const Cx<double>* A, const Cx<double>* B, Cx<double
 // ------------------------------------------------------------------ handles
 struct lsop_op {
   int nx = 0, nz = 0, lx = 0, lz = 0, dtype = 0, max_vec = 0;
+  int col_tile = 0;  // column-pass tile width (0 = widest that fits)
   bool ready = false;
   double h = 0, freq = 0, c0 = 0, k0 = 0;
   size_t n() const { return (size_t)nx * nz; }

@@ -30,14 +30,28 @@ int fft_length_for(int n) {
   return -1;
 }
 
+// Threads per workgroup of the row kernels: 256 unless the groups' exchange
+// buffers plus the twiddle table would not fit in 144 KiB of LDS.
+template <typename T, int L>
+constexpr int rows_threads() {
+  int t = 256;
+  while (t > FftPlan<L>::G &&
+         (t / FftPlan<L>::G) * lds_len<L>() * (int)sizeof(Cx<T>) + L * (int)sizeof(Cx<T>) > 144 * 1024)
+    t /= 2;
+  return t;
+}
+
 // ------------------------------------------------------------------ pass 1
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_rows_fwd(const Cx<T>* __restrict__ x, const T* __restrict__ chi,
+__global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>* __restrict__ x, const T* __restrict__ chi,
                                                    Cx<T>* __restrict__ tmp, const int* __restrict__ vidx, int nx,
                                                    int nz, int nitems, int mulchi, const Cx<T>* __restrict__ tw2) {
   using P = FftPlan<L>;
-  constexpr int G = P::G, E = P::E, GPW = 256 / G;
+  constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
   __shared__ Cx<T> sbuf[GPW][lds_len<L>()];
+  __shared__ Cx<T> stw[L];
+  stage_twiddles<T, L>(stw, tw2);
+  __syncthreads();
   const int grp = threadIdx.x / G, g = threadIdx.x % G;
   const size_t vstride = (size_t)nx * nz;
   for (int base = blockIdx.x * GPW; base < nitems; base += gridDim.x * GPW) {
@@ -61,14 +75,14 @@ __global__ __launch_bounds__(256) void k_rows_fwd(const Cx<T>* __restrict__ x, c
       v[e] = val;
     }
     Cx<T>* tr = tmp + ((size_t)slot * nx + i) * (2 * L);
-    fft_regs<T, L, false>(v, g, sbuf[grp], tw2);
+    fft_regs<T, L, false>(v, g, sbuf[grp], stw);
     if (valid) {
 #pragma unroll
       for (int e = 0; e < E; ++e) tr[fft_elem<L>(g, e)] = v[e];
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = u[e] * tw2[fft_elem<L>(g, e)];
-    fft_regs<T, L, false>(v, g, sbuf[grp], tw2);
+    for (int e = 0; e < E; ++e) v[e] = u[e] * stw[fft_elem<L>(g, e)];
+    fft_regs<T, L, false>(v, g, sbuf[grp], stw);
     if (valid) {
 #pragma unroll
       for (int e = 0; e < E; ++e) tr[L + fft_elem<L>(g, e)] = v[e];
@@ -78,10 +92,15 @@ __global__ __launch_bounds__(256) void k_rows_fwd(const Cx<T>* __restrict__ x, c
 }
 
 // ------------------------------------------------------------------ pass 2
+// A workgroup owns C adjacent columns of tmp (C * sizeof(Cx<T>) contiguous
+// bytes per row) and one wavefront group per column.  The tile is staged in
+// LDS column-major with an odd column stride (conflict-free transposition);
+// each column's LDS slot then doubles as that group's FFT exchange buffer.
 template <typename T, int L>
 struct ColTile {
-  // columns per workgroup: 128-byte row segments where the LDS budget allows
-  static constexpr int lds_cap = (144 * 1024) / (lds_len<L>() * (int)sizeof(Cx<T>));
+  // widest tile that keeps 128-byte row segments and fits the LDS and thread budgets
+  static constexpr int stride = lds_len<L>() + 1;
+  static constexpr int lds_cap = (144 * 1024 - L * (int)sizeof(Cx<T>)) / (stride * (int)sizeof(Cx<T>));
   static constexpr int want = 128 / (int)sizeof(Cx<T>);
   static constexpr int c0 = want < lds_cap ? want : lds_cap;
   static constexpr int thr_cap = 1024 / FftPlan<L>::G;
@@ -96,73 +115,78 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nb) {
   return x * per + (x < rem ? x : rem) + b / 8;
 }
 
-template <typename T, int L>
-__global__ __launch_bounds__((ColTile<T, L>::C * FftPlan<L>::G)) void k_cols(Cx<T>* __restrict__ tmp,
-                                                                            const Cx<T>* __restrict__ gs, int nx,
-                                                                            int pz, int nslots, int adj,
-                                                                            const Cx<T>* __restrict__ tw2) {
+template <typename T, int L, int C>
+__global__ __launch_bounds__(C * FftPlan<L>::G) void k_cols(Cx<T>* __restrict__ tmp, const Cx<T>* __restrict__ gs,
+                                                            int nx, int pz, int nslots, int adj,
+                                                            const Cx<T>* __restrict__ tw2) {
   using P = FftPlan<L>;
-  constexpr int G = P::G, E = P::E, C = ColTile<T, L>::C, NT = C * G;
-  __shared__ Cx<T> tile[C][lds_len<L>()];
+  constexpr int G = P::G, E = P::E, NT = C * G, ST = ColTile<T, L>::stride;
+  __shared__ Cx<T> tile[C * ST];
+  __shared__ Cx<T> stw[L];
+  stage_twiddles<T, L>(stw, tw2);
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int tid = lb / nslots, slot = lb % nslots;
   const int c0 = tid * C;
   Cx<T>* tb = tmp + (size_t)slot * nx * pz + c0;
   for (int idx = threadIdx.x; idx < L * C; idx += NT) {
     const int i = idx / C, c = idx % C;
-    tile[c][lds_pad(i)] = (i < nx) ? tb[(size_t)i * pz + c] : czero<T>();
+    tile[c * ST + lds_pad(i)] = (i < nx) ? tb[(size_t)i * pz + c] : czero<T>();
   }
   __syncthreads();
   const int c = threadIdx.x / G, g = threadIdx.x % G;
+  Cx<T>* col = tile + c * ST;
   Cx<T> xin[E], acc[E], v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    xin[e] = tile[c][lds_pad(fft_elem<L>(g, e))];
+    xin[e] = col[lds_pad(fft_elem<L>(g, e))];
     v[e] = xin[e];
   }
   const Cx<T>* g0 = gs + (size_t)(c0 + c) * L;
   const Cx<T>* g1 = gs + ((size_t)pz + c0 + c) * L;
-  fft_regs<T, L, false>(v, g, tile[c], tw2);
+  fft_regs<T, L, false>(v, g, col, stw);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const Cx<T> s = g0[fft_elem<L>(g, e)];
-    v[e] = adj ? cmul_conj(s, v[e]) : s * v[e];
+    const Cx<T> sp = g0[fft_elem<L>(g, e)];
+    v[e] = adj ? cmul_conj(sp, v[e]) : sp * v[e];
   }
-  fft_regs<T, L, true>(v, g, tile[c], tw2);
+  fft_regs<T, L, true>(v, g, col, stw);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     acc[e] = v[e];
-    v[e] = xin[e] * tw2[fft_elem<L>(g, e)];
+    v[e] = xin[e] * stw[fft_elem<L>(g, e)];
   }
-  fft_regs<T, L, false>(v, g, tile[c], tw2);
+  fft_regs<T, L, false>(v, g, col, stw);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const Cx<T> s = g1[fft_elem<L>(g, e)];
-    v[e] = adj ? cmul_conj(s, v[e]) : s * v[e];
+    const Cx<T> sp = g1[fft_elem<L>(g, e)];
+    v[e] = adj ? cmul_conj(sp, v[e]) : sp * v[e];
   }
-  fft_regs<T, L, true>(v, g, tile[c], tw2);
+  fft_regs<T, L, true>(v, g, col, stw);
   wave_sync();
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int p = fft_elem<L>(g, e);
-    tile[c][lds_pad(p)] = acc[e] + cmul_conj(tw2[p], v[e]);
+    col[lds_pad(p)] = acc[e] + cmul_conj(stw[p], v[e]);
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < nx * C; idx += NT) {
     const int i = idx / C, cc = idx % C;
-    tb[(size_t)i * pz + cc] = tile[cc][lds_pad(i)];
+    tb[(size_t)i * pz + cc] = tile[cc * ST + lds_pad(i)];
   }
 }
 
 // ------------------------------------------------------------------ pass 3
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_rows_inv(const Cx<T>* __restrict__ tmp, const Cx<T>* x,
+__global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>* __restrict__ tmp, const Cx<T>* x,
                                                    const T* __restrict__ chi, const Cx<T>* rhs, Cx<T>* y,
                                                    double* __restrict__ rnorm, const int* __restrict__ vidx, int nx,
                                                    int nz, int nitems, int epi, const Cx<T>* __restrict__ tw2) {
   using P = FftPlan<L>;
-  constexpr int G = P::G, E = P::E, GPW = 256 / G;
+  constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
   __shared__ Cx<T> sbuf[GPW][lds_len<L>()];
+  __shared__ Cx<T> stw[L];
+  stage_twiddles<T, L>(stw, tw2);
+  __syncthreads();
   const int grp = threadIdx.x / G, g = threadIdx.x % G;
   const size_t vstride = (size_t)nx * nz;
   for (int base = blockIdx.x * GPW; base < nitems; base += gridDim.x * GPW) {
@@ -175,20 +199,20 @@ __global__ __launch_bounds__(256) void k_rows_inv(const Cx<T>* __restrict__ tmp,
     Cx<T> v[E], acc[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) v[e] = tr[fft_elem<L>(g, e)];
-    fft_regs<T, L, true>(v, g, sbuf[grp], tw2);
+    fft_regs<T, L, true>(v, g, sbuf[grp], stw);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       acc[e] = v[e];
       v[e] = tr[L + fft_elem<L>(g, e)];
     }
-    fft_regs<T, L, true>(v, g, sbuf[grp], tw2);
+    fft_regs<T, L, true>(v, g, sbuf[grp], stw);
     const size_t off = (size_t)vi * vstride + (size_t)i * nz;
     double nrm = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int p = fft_elem<L>(g, e);
       if (p < nz) {
-        const Cx<T> conv = acc[e] + cmul_conj(tw2[p], v[e]);
+        const Cx<T> conv = acc[e] + cmul_conj(stw[p], v[e]);
         Cx<T> out;
         switch (epi) {
           case 0: out = x[off + p] - conv; break;
@@ -216,11 +240,14 @@ __global__ __launch_bounds__(256) void k_rows_inv(const Cx<T>* __restrict__ tmp,
 // Row pass: row p of the circulant table (length pz = 2 lz, full input),
 // written transposed to s1t[c][p] in the split column order.
 template <int L>
-__global__ __launch_bounds__(256) void k_spec_rows(const Cx<double>* __restrict__ ktab, int nx, int nz, int px,
+__global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_rows(const Cx<double>* __restrict__ ktab, int nx, int nz, int px,
                                                     Cx<double>* __restrict__ s1t, const Cx<double>* __restrict__ tw2) {
   using P = FftPlan<L>;
-  constexpr int G = P::G, E = P::E, GPW = 256 / G;
+  constexpr int G = P::G, E = P::E, GPW = rows_threads<double, L>() / G;
   __shared__ Cx<double> sbuf[GPW][lds_len<L>()];
+  __shared__ Cx<double> stw[L];
+  stage_twiddles<double, L>(stw, tw2);
+  __syncthreads();
   const int grp = threadIdx.x / G, g = threadIdx.x % G;
   const int pz = 2 * L;
   for (int base = blockIdx.x * GPW; base < px; base += gridDim.x * GPW) {
@@ -239,10 +266,10 @@ __global__ __launch_bounds__(256) void k_spec_rows(const Cx<double>* __restrict_
       if (lxp < nx && l1 < nz) k1 = ktab[(size_t)lxp * nz + l1];
       if (lxp < nx && lz2 < nz) k2 = ktab[(size_t)lxp * nz + lz2];
       a[e] = k1 + k2;
-      b[e] = (k1 - k2) * tw2[q];
+      b[e] = (k1 - k2) * stw[q];
     }
-    fft_regs<double, L, false>(a, g, sbuf[grp], tw2);
-    fft_regs<double, L, false>(b, g, sbuf[grp], tw2);
+    fft_regs<double, L, false>(a, g, sbuf[grp], stw);
+    fft_regs<double, L, false>(b, g, sbuf[grp], stw);
     if (valid) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -257,12 +284,15 @@ __global__ __launch_bounds__(256) void k_spec_rows(const Cx<double>* __restrict_
 
 // Column pass: full-length transform of s1t[c][0..px) -> gs[h][c][m] scaled.
 template <int L>
-__global__ __launch_bounds__(256) void k_spec_cols(const Cx<double>* __restrict__ s1t, int pz,
+__global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_cols(const Cx<double>* __restrict__ s1t, int pz,
                                                     Cx<double>* __restrict__ gs64, Cx<float>* __restrict__ gs32,
                                                     double scale, const Cx<double>* __restrict__ tw2) {
   using P = FftPlan<L>;
-  constexpr int G = P::G, E = P::E, GPW = 256 / G;
+  constexpr int G = P::G, E = P::E, GPW = rows_threads<double, L>() / G;
   __shared__ Cx<double> sbuf[GPW][lds_len<L>()];
+  __shared__ Cx<double> stw[L];
+  stage_twiddles<double, L>(stw, tw2);
+  __syncthreads();
   const int grp = threadIdx.x / G, g = threadIdx.x % G;
   const int px = 2 * L;
   for (int base = blockIdx.x * GPW; base < pz; base += gridDim.x * GPW) {
@@ -276,10 +306,10 @@ __global__ __launch_bounds__(256) void k_spec_cols(const Cx<double>* __restrict_
       const int p = fft_elem<L>(g, e);
       const Cx<double> k1 = col[p], k2 = col[p + L];
       a[e] = k1 + k2;
-      b[e] = (k1 - k2) * tw2[p];
+      b[e] = (k1 - k2) * stw[p];
     }
-    fft_regs<double, L, false>(a, g, sbuf[grp], tw2);
-    fft_regs<double, L, false>(b, g, sbuf[grp], tw2);
+    fft_regs<double, L, false>(a, g, sbuf[grp], stw);
+    fft_regs<double, L, false>(b, g, sbuf[grp], stw);
     if (valid) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -372,22 +402,49 @@ hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, cons
   const int nitems = nslots * nx;
   if (nitems <= 0) return hipSuccess;
   LSOP_DISPATCH_L(L, {
-    constexpr int GPW = 256 / FftPlan<LL>::G;
-    hipLaunchKernelGGL((k_rows_fwd<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(256), 0, s, x, chi, tmp, vidx,
+    constexpr int NT = rows_threads<T, LL>(), GPW = NT / FftPlan<LL>::G;
+    hipLaunchKernelGGL((k_rows_fwd<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(NT), 0, s, x, chi, tmp, vidx,
                        nx, nz, nitems, (int)mulchi, tw2);
   });
   return hipGetLastError();
 }
 
+// Column-tile width: the default is the widest tile that fits (ColTile); a
+// narrower tile (more workgroups per CU) can be selected per call (tile > 0).
 template <typename T>
 hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int nslots, bool adj, const Cx<T>* tw2,
-                       hipStream_t s) {
+                       hipStream_t s, int tile) {
   if (nslots <= 0) return hipSuccess;
   LSOP_DISPATCH_L(L, {
-    constexpr int C = ColTile<T, LL>::C;
+    constexpr int CMAX = ColTile<T, LL>::C;
+    int C = (tile > 0 && tile < CMAX) ? tile : CMAX;
+    if (C >= 16 && CMAX >= 16) C = 16;
+    else if (C >= 8 && CMAX >= 8) C = 8;
+    else if (C >= 4 && CMAX >= 4) C = 4;
+    else C = CMAX < 2 ? CMAX : 2;
     const int ntiles = pz / C;
-    hipLaunchKernelGGL((k_cols<T, LL>), dim3(ntiles * nslots), dim3(C * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz,
-                       nslots, (int)adj, tw2);
+    const dim3 grid(ntiles * nslots);
+    switch (C) {
+      case 16:
+        if constexpr (CMAX >= 16)
+          hipLaunchKernelGGL((k_cols<T, LL, 16>), grid, dim3(16 * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz, nslots,
+                             (int)adj, tw2);
+        break;
+      case 8:
+        if constexpr (CMAX >= 8)
+          hipLaunchKernelGGL((k_cols<T, LL, 8>), grid, dim3(8 * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz, nslots,
+                             (int)adj, tw2);
+        break;
+      case 4:
+        if constexpr (CMAX >= 4)
+          hipLaunchKernelGGL((k_cols<T, LL, 4>), grid, dim3(4 * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz, nslots,
+                             (int)adj, tw2);
+        break;
+      default:
+        hipLaunchKernelGGL((k_cols<T, LL, (CMAX < 2 ? CMAX : 2)>), grid, dim3((CMAX < 2 ? CMAX : 2) * FftPlan<LL>::G),
+                           0, s, tmp, gs, nx, pz, nslots, (int)adj, tw2);
+        break;
+    }
   });
   return hipGetLastError();
 }
@@ -399,8 +456,8 @@ hipError_t launch_rows_inv(int L, const Cx<T>* tmp, const Cx<T>* x, const T* chi
   const int nitems = nslots * nx;
   if (nitems <= 0) return hipSuccess;
   LSOP_DISPATCH_L(L, {
-    constexpr int GPW = 256 / FftPlan<LL>::G;
-    hipLaunchKernelGGL((k_rows_inv<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(256), 0, s, tmp, x, chi, rhs, y,
+    constexpr int NT = rows_threads<T, LL>(), GPW = NT / FftPlan<LL>::G;
+    hipLaunchKernelGGL((k_rows_inv<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(NT), 0, s, tmp, x, chi, rhs, y,
                        rnorm, vidx, nx, nz, nitems, epi, tw2);
   });
   return hipGetLastError();
@@ -411,16 +468,16 @@ hipError_t launch_spectrum(int lx, int lz, const Cx<double>* ktab, int nx, int n
                            hipStream_t s) {
   const int px = 2 * lx, pz = 2 * lz;
   LSOP_DISPATCH_L(lz, {
-    constexpr int GPW = 256 / FftPlan<LL>::G;
-    hipLaunchKernelGGL((k_spec_rows<LL>), dim3(grid_for_rows(px, GPW)), dim3(256), 0, s, ktab, nx, nz, px, s1t,
+    constexpr int NT = rows_threads<double, LL>(), GPW = NT / FftPlan<LL>::G;
+    hipLaunchKernelGGL((k_spec_rows<LL>), dim3(grid_for_rows(px, GPW)), dim3(NT), 0, s, ktab, nx, nz, px, s1t,
                        tw2z);
   });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double scale = 1.0 / ((double)px * (double)pz);
   LSOP_DISPATCH_L(lx, {
-    constexpr int GPW = 256 / FftPlan<LL>::G;
-    hipLaunchKernelGGL((k_spec_cols<LL>), dim3(grid_for_rows(pz, GPW)), dim3(256), 0, s, s1t, pz, gs64, gs32, scale,
+    constexpr int NT = rows_threads<double, LL>(), GPW = NT / FftPlan<LL>::G;
+    hipLaunchKernelGGL((k_spec_cols<LL>), dim3(grid_for_rows(pz, GPW)), dim3(NT), 0, s, s1t, pz, gs64, gs32, scale,
                        tw2x);
   });
   return hipGetLastError();
@@ -458,7 +515,8 @@ hipError_t launch_incident(const Cx<double>* ktab, const int* si, const int* sj,
 #define LSOP_INST(T)                                                                                               \
   template hipError_t launch_rows_fwd<T>(int, const Cx<T>*, const T*, Cx<T>*, const int*, int, int, int, bool,    \
                                          const Cx<T>*, hipStream_t);                                              \
-  template hipError_t launch_cols<T>(int, Cx<T>*, const Cx<T>*, int, int, int, bool, const Cx<T>*, hipStream_t);  \
+  template hipError_t launch_cols<T>(int, Cx<T>*, const Cx<T>*, int, int, int, bool, const Cx<T>*, hipStream_t,    \
+                                     int);                                                                        \
   template hipError_t launch_rows_inv<T>(int, const Cx<T>*, const Cx<T>*, const T*, const Cx<T>*, Cx<T>*,        \
                                          double*, const int*, int, int, int, int, const Cx<T>*, hipStream_t);     \
   template hipError_t launch_incident<T>(const Cx<double>*, const int*, const int*, const Cx<double>*, Cx<T>*,    \

@@ -216,13 +216,12 @@ __global__ __launch_bounds__(256) void k_gemm_update(const Cx<T>* __restrict__ A
 // G = Y^H Y: column k of X is e_k projected twice (classical Gram-Schmidt in
 // the G inner product) against the kept columns, then normalised; columns
 // whose remaining G-norm^2 is <= drop_tol * G_kk are zeroed (dropped).
-__global__ __launch_bounds__(256) void k_gram_orth(const Cx<double>* __restrict__ G, Cx<double>* __restrict__ X,
-                                                    int na, double drop_tol, int* kept) {
-  extern __shared__ unsigned char smem_raw[];
-  Cx<double>* x = reinterpret_cast<Cx<double>*>(smem_raw);  // [na]
-  Cx<double>* w = x + na;                                    // [na] = G x
-  Cx<double>* cf = w + na;                                   // [na] projections
-  __shared__ double red[4];
+// G and X point to LDS copies (na <= SMALL_NA) or to global memory.
+constexpr int SMALL_NA = 64;
+
+__device__ __forceinline__ void gram_orth_body(const Cx<double>* G, Cx<double>* X, int na, double drop_tol,
+                                               Cx<double>* x, Cx<double>* w, Cx<double>* cf, double* red,
+                                               int* nkept_out) {
   const int t = threadIdx.x;
   for (int i = t; i < na * na; i += blockDim.x) X[i] = czero<double>();
   __syncthreads();
@@ -269,18 +268,39 @@ __global__ __launch_bounds__(256) void k_gram_orth(const Cx<double>* __restrict_
     nkept += keep ? 1 : 0;
     __syncthreads();
   }
-  if (t == 0) *kept = nkept;
+  *nkept_out = nkept;
 }
 
-// Z = (I - M)^{-1}, Gauss-Jordan with partial pivoting on work = [I - M | I].
-__global__ __launch_bounds__(256) void k_lu_inverse_i_minus(const Cx<double>* __restrict__ M,
-                                                             Cx<double>* __restrict__ Z, Cx<double>* __restrict__ work,
-                                                             int na, int* singular) {
+__global__ __launch_bounds__(256) void k_gram_orth_lds(const Cx<double>* __restrict__ Gg, Cx<double>* __restrict__ Xg,
+                                                        int na, double drop_tol, int* kept) {
+  __shared__ Cx<double> G[SMALL_NA * SMALL_NA], X[SMALL_NA * SMALL_NA];
+  __shared__ Cx<double> x[SMALL_NA], w[SMALL_NA], cf[SMALL_NA];
+  __shared__ double red[4];
+  for (int i = threadIdx.x; i < na * na; i += blockDim.x) G[i] = Gg[i];
+  __syncthreads();
+  int nk = 0;
+  gram_orth_body(G, X, na, drop_tol, x, w, cf, red, &nk);
+  for (int i = threadIdx.x; i < na * na; i += blockDim.x) Xg[i] = X[i];
+  if (threadIdx.x == 0) *kept = nk;
+}
+
+__global__ __launch_bounds__(256) void k_gram_orth(const Cx<double>* __restrict__ G, Cx<double>* __restrict__ X,
+                                                    int na, double drop_tol, int* kept) {
   extern __shared__ unsigned char smem_raw[];
-  Cx<double>* fcol = reinterpret_cast<Cx<double>*>(smem_raw);  // [na]
-  __shared__ double best[256];
-  __shared__ int bidx[256];
-  __shared__ double scale;
+  Cx<double>* x = reinterpret_cast<Cx<double>*>(smem_raw);  // [na]
+  Cx<double>* w = x + na;                                    // [na] = G x
+  Cx<double>* cf = w + na;                                   // [na] projections
+  __shared__ double red[4];
+  int nk = 0;
+  gram_orth_body(G, X, na, drop_tol, x, w, cf, red, &nk);
+  if (threadIdx.x == 0) *kept = nk;
+}
+
+// Z = (I - M)^{-1}, Gauss-Jordan with partial pivoting on work = [I - M | I]
+// (work in LDS for na <= SMALL_NA, else in global memory).
+__device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, Cx<double>* Z, Cx<double>* work, int na,
+                                                int* singular, Cx<double>* fcol, double* best, int* bidx,
+                                                double* scale_s) {
   const int t = threadIdx.x, w2 = 2 * na;
   double amax = 0.0;
   for (int idx = t; idx < na * w2; idx += blockDim.x) {
@@ -296,10 +316,11 @@ __global__ __launch_bounds__(256) void k_lu_inverse_i_minus(const Cx<double>* __
   if (t == 0) {
     double m = 0.0;
     for (int i = 0; i < (int)blockDim.x; ++i) m = fmax(m, best[i]);
-    scale = m;
+    *scale_s = m;
     *singular = 0;
   }
   __syncthreads();
+  const double scale = *scale_s;
   for (int k = 0; k < na; ++k) {
     double bv = -1.0;
     int bi = k;
@@ -356,6 +377,27 @@ __global__ __launch_bounds__(256) void k_lu_inverse_i_minus(const Cx<double>* __
     const int i = idx / na, j = idx % na;
     Z[idx] = work[(size_t)i * w2 + na + j];
   }
+}
+
+__global__ __launch_bounds__(256) void k_lu_inverse_lds(const Cx<double>* __restrict__ M, Cx<double>* __restrict__ Z,
+                                                         int na, int* singular) {
+  __shared__ Cx<double> work[SMALL_NA * 2 * SMALL_NA];
+  __shared__ Cx<double> fcol[SMALL_NA];
+  __shared__ double best[256];
+  __shared__ int bidx[256];
+  __shared__ double scale;
+  lu_inverse_body(M, Z, work, na, singular, fcol, best, bidx, &scale);
+}
+
+__global__ __launch_bounds__(256) void k_lu_inverse_i_minus(const Cx<double>* __restrict__ M,
+                                                             Cx<double>* __restrict__ Z, Cx<double>* __restrict__ work,
+                                                             int na, int* singular) {
+  extern __shared__ unsigned char smem_raw[];
+  Cx<double>* fcol = reinterpret_cast<Cx<double>*>(smem_raw);  // [na]
+  __shared__ double best[256];
+  __shared__ int bidx[256];
+  __shared__ double scale;
+  lu_inverse_body(M, Z, work, na, singular, fcol, best, bidx, &scale);
 }
 
 __global__ void k_small_gemm(const Cx<double>* __restrict__ A, const Cx<double>* __restrict__ B,
@@ -452,14 +494,20 @@ hipError_t launch_gemm_update(const Cx<T>* A, int na, const Cx<double>* M, int n
 
 hipError_t launch_gram_orth(const Cx<double>* G, Cx<double>* X, int na, double drop_tol, int* kept,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_gram_orth, dim3(1), dim3(256), sizeof(Cx<double>) * 3 * na, s, G, X, na, drop_tol, kept);
+  if (na <= SMALL_NA)
+    hipLaunchKernelGGL(k_gram_orth_lds, dim3(1), dim3(256), 0, s, G, X, na, drop_tol, kept);
+  else
+    hipLaunchKernelGGL(k_gram_orth, dim3(1), dim3(256), sizeof(Cx<double>) * 3 * na, s, G, X, na, drop_tol, kept);
   return hipGetLastError();
 }
 
 hipError_t launch_lu_inverse_i_minus(const Cx<double>* M, Cx<double>* Z, Cx<double>* work, int na, int* singular,
                                      hipStream_t s) {
-  hipLaunchKernelGGL(k_lu_inverse_i_minus, dim3(1), dim3(256), sizeof(Cx<double>) * na, s, M, Z, work, na,
-                     singular);
+  if (na <= SMALL_NA)
+    hipLaunchKernelGGL(k_lu_inverse_lds, dim3(1), dim3(256), 0, s, M, Z, na, singular);
+  else
+    hipLaunchKernelGGL(k_lu_inverse_i_minus, dim3(1), dim3(256), sizeof(Cx<double>) * na, s, M, Z, work, na,
+                       singular);
   return hipGetLastError();
 }
 

@@ -26,10 +26,10 @@ MODES = {"A": 0, "G0V": 1, "AH": 2, "VHG0H": 3}
 PC_IDENTITY, PC_LOWRANK = 0, 1
 INIT = {"h_rhs": 0, "zero": 1, "user": 2}
 
-EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident",
+EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident", "lsop_autotune",
            "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "precond_create",
            "precond_build", "precond_apply", "precond_info", "precond_destroy", "series_solve",
-           "lsop_bessel_host")
+           "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read")
 
 
 class LsopError(RuntimeError):
@@ -40,7 +40,7 @@ class LsopError(RuntimeError):
 
 class OpInfo(C.Structure):
     _fields_ = [("nx", C.c_int), ("nz", C.c_int), ("lx", C.c_int), ("lz", C.c_int), ("dtype", C.c_int),
-                ("max_vec", C.c_int), ("state_bytes", C.c_size_t)]
+                ("max_vec", C.c_int), ("state_bytes", C.c_size_t), ("col_tile", C.c_int)]
 
 
 class PrecondParams(C.Structure):
@@ -52,8 +52,14 @@ class SolveParams(C.Structure):
                 ("inner_tol", C.c_double)]
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("launches", C.c_int), ("total_ms", C.c_double), ("bytes", C.c_double),
+                ("flops", C.c_double), ("items", C.c_double)]
+
+
 class SolveInfo(C.Structure):
-    _fields_ = [("iters", C.c_int), ("refine_steps", C.c_int), ("rel_residual", C.c_double), ("status", C.c_int)]
+    _fields_ = [("iters", C.c_int), ("refine_steps", C.c_int), ("rel_residual", C.c_double), ("status", C.c_int),
+                ("rel_residual0", C.c_double)]
 
 
 _lib = None
@@ -75,6 +81,7 @@ def load_library(path=LIB_PATH):
         "lsop_residual": (ip, [vp, vp, vp, vp, vp, ip, vp]),
         "lsop_incident": (ip, [vp, vp, vp, vp, ip, vp, vp]),
         "lsop_kernel_table": (ip, [vp, vp, vp]),
+        "lsop_autotune": (ip, [vp, ip, vp]),
         "lsop_info": (ip, [vp, C.POINTER(OpInfo)]),
         "lsop_destroy": (None, [vp]),
         "lsop_last_error": (C.c_char_p, []),
@@ -85,6 +92,9 @@ def load_library(path=LIB_PATH):
         "precond_destroy": (None, [vp]),
         "series_solve": (ip, [vp, vp, vp, vp, ip, C.POINTER(SolveParams), C.POINTER(SolveInfo), vp]),
         "lsop_bessel_host": (ip, [ip, dp, C.POINTER(dp)]),
+        "lsop_profile_enable": (ip, [ip]),
+        "lsop_profile_reset": (ip, []),
+        "lsop_profile_read": (ip, [C.POINTER(KernelStat), ip, C.POINTER(ip)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -113,6 +123,24 @@ def bessel_host(kind, x):
     out = (C.c_double * 2)()
     _check(lib.lsop_bessel_host(int(kind), float(x), out))
     return out[0], out[1]
+
+
+def profile_enable(on=True):
+    _check(load_library().lsop_profile_enable(int(bool(on))))
+
+
+def profile_reset():
+    _check(load_library().lsop_profile_reset())
+
+
+def profile_read():
+    """Per-kernel totals since the last reset: {name: dict(launches, ms, bytes, flops)}."""
+    lib = load_library()
+    arr = (KernelStat * 64)()
+    cnt = C.c_int()
+    _check(lib.lsop_profile_read(arr, 64, C.byref(cnt)))
+    return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].total_ms, bytes=arr[i].bytes,
+                                       flops=arr[i].flops, items=arr[i].items) for i in range(min(cnt.value, 64))}
 
 
 class Operator:
@@ -192,6 +220,11 @@ class Operator:
         _check(self.lib.lsop_incident(self.handle, si, sj, ap, len(src_i), _ptr(out), _stream()))
         return out
 
+    def autotune(self, nvec):
+        """Pick the fastest column-pass tile for batches of nvec vectors; returns the chosen width."""
+        _check(self.lib.lsop_autotune(self.handle, int(nvec), _stream()))
+        return self.info().col_tile
+
     def kernel_table(self):
         out = torch.empty((self.nx, self.nz), dtype=torch.complex128, device="cuda")
         _check(self.lib.lsop_kernel_table(self.handle, _ptr(out), _stream()))
@@ -247,6 +280,7 @@ class SolveResult:
     refine_steps: int
     rel_residual: float
     status: int
+    rel_residual0: float
 
     @property
     def status_name(self):
@@ -264,4 +298,4 @@ def series_solve(op, pc, rhs, psi=None, tol=1e-10, max_iter=30, init="h_rhs", re
     st = op.lib.series_solve(op.handle, pc.handle if pc is not None else None, _ptr(rhs), _ptr(psi), nv,
                              C.byref(p), info, _stream())
     _check(st, allow=() if raise_on_failure else (NOT_CONVERGED, DIVERGED))
-    return psi, [SolveResult(i.iters, i.refine_steps, i.rel_residual, i.status) for i in info]
+    return psi, [SolveResult(i.iters, i.refine_steps, i.rel_residual, i.status, i.rel_residual0) for i in info]
