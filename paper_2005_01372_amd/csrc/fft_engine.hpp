@@ -175,19 +175,27 @@ __device__ __forceinline__ int fft_elem(int g, int e) {
   return g + P::G * (e / R1) + (e % R1) * (L / R1);
 }
 
-// Twiddle table: tw[t] = w_{2L}^t = exp(-2 pi i t / (2L)) for t < L (the
-// other half follows from w_{2L}^{t+L} = -w_{2L}^t).  Usually staged in LDS.
+// Twiddle table: w_{2L}^t = exp(-2 pi i t / (2L)) for t < L, stored at LDS
+// slot lds_pad(t) (the padding spreads the strided stage-twiddle reads over
+// the banks); the other half follows from w_{2L}^{t+L} = -w_{2L}^t.
 template <typename T, int L>
 __device__ __forceinline__ Cx<T> tw_2l(const Cx<T>* __restrict__ tw, int t) {
   const bool hi = t >= L;
-  const Cx<T> w = tw[hi ? t - L : t];
+  const Cx<T> w = tw[lds_pad(hi ? t - L : t)];
   return hi ? Cx<T>{-w.re, -w.im} : w;
 }
 
-// Copy the L-entry twiddle table into LDS (whole workgroup; caller syncs).
+// w_{2L}^t for t < L
+template <typename T, int L>
+__device__ __forceinline__ Cx<T> tw_lo(const Cx<T>* __restrict__ tw, int t) {
+  return tw[lds_pad(t)];
+}
+
+// Copy the L-entry twiddle table into LDS (lds_len<L>() slots; whole
+// workgroup; caller syncs).
 template <typename T, int L>
 __device__ __forceinline__ void stage_twiddles(Cx<T>* __restrict__ dst, const Cx<T>* __restrict__ src) {
-  for (int t = threadIdx.x; t < L; t += blockDim.x) dst[t] = src[t];
+  for (int t = threadIdx.x; t < L; t += blockDim.x) dst[lds_pad(t)] = src[t];
 }
 
 template <typename T, int L, bool INV, int S>
@@ -245,4 +253,69 @@ template <typename T, int L, bool INV>
 __device__ __forceinline__ void fft_regs(Cx<T> (&v)[FftPlan<L>::E], int g, Cx<T>* __restrict__ buf,
                                          const Cx<T>* __restrict__ tw2) {
   FftStage<T, L, INV, 0>::run(v, g, buf, tw2);
+}
+
+// Two independent FFTs of length L interleaved stage by stage in one group
+// (separate exchange buffers; each twiddle is loaded once for both), which
+// doubles the independent work available between LDS round trips.
+template <typename T, int L, bool INV, int S>
+struct FftStage2 {
+  using P = FftPlan<L>;
+  static constexpr int R = P::R[S];
+  static constexpr int Ns = FftSpan<L, S>::value;
+  static constexpr int E = P::E;
+  static constexpr int U = E / R;
+
+  __device__ __forceinline__ static void run(Cx<T> (&a)[E], Cx<T> (&b)[E], int g, Cx<T>* __restrict__ bufa,
+                                             Cx<T>* __restrict__ bufb, const Cx<T>* __restrict__ tw2) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if constexpr (Ns > 1) {
+        const int bb = g + P::G * u;
+        const int j = bb % Ns;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          Cx<T> w = tw_2l<T, L>(tw2, 2 * (r * j * (L / (Ns * R))));
+          if constexpr (INV) w.im = -w.im;
+          a[u * R + r] = a[u * R + r] * w;
+          b[u * R + r] = b[u * R + r] * w;
+        }
+      }
+      dft<T, R, INV>(&a[u * R]);
+      dft<T, R, INV>(&b[u * R]);
+    }
+    if constexpr (S + 1 < P::NST) {
+      constexpr int Rn = P::R[S + 1];
+      constexpr int Un = E / Rn;
+      wave_sync();
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int bb = g + P::G * u;
+        const int base = (bb / Ns) * Ns * R + (bb % Ns);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          bufa[lds_pad(base + r * Ns)] = a[u * R + r];
+          bufb[lds_pad(base + r * Ns)] = b[u * R + r];
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int u = 0; u < Un; ++u) {
+        const int bb = g + P::G * u;
+#pragma unroll
+        for (int r = 0; r < Rn; ++r) {
+          a[u * Rn + r] = bufa[lds_pad(bb + r * (L / Rn))];
+          b[u * Rn + r] = bufb[lds_pad(bb + r * (L / Rn))];
+        }
+      }
+      FftStage2<T, L, INV, S + 1>::run(a, b, g, bufa, bufb, tw2);
+    }
+  }
+};
+
+template <typename T, int L, bool INV>
+__device__ __forceinline__ void fft2_regs(Cx<T> (&a)[FftPlan<L>::E], Cx<T> (&b)[FftPlan<L>::E], int g,
+                                          Cx<T>* __restrict__ bufa, Cx<T>* __restrict__ bufb,
+                                          const Cx<T>* __restrict__ tw2) {
+  FftStage2<T, L, INV, 0>::run(a, b, g, bufa, bufb, tw2);
 }

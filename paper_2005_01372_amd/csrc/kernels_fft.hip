@@ -30,62 +30,78 @@ int fft_length_for(int n) {
   return -1;
 }
 
-// Threads per workgroup of the row kernels: 256 unless the groups' exchange
-// buffers plus the twiddle table would not fit in 144 KiB of LDS.
+// Threads per workgroup of the row kernels: 256 unless the groups' two
+// exchange buffers plus the twiddle table would not fit in 144 KiB of LDS.
 template <typename T, int L>
 constexpr int rows_threads() {
   int t = 256;
   while (t > FftPlan<L>::G &&
-         (t / FftPlan<L>::G) * lds_len<L>() * (int)sizeof(Cx<T>) + L * (int)sizeof(Cx<T>) > 144 * 1024)
+         (t / FftPlan<L>::G) * 2 * lds_len<L>() * (int)sizeof(Cx<T>) + lds_len<L>() * (int)sizeof(Cx<T>) >
+             144 * 1024)
     t /= 2;
   return t;
 }
 
 // ------------------------------------------------------------------ pass 1
+// One group per row; the even and odd halves are transformed together
+// (fft2_regs), and the next row's input is prefetched into registers while
+// the current row is transformed.
 template <typename T, int L>
-__global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>* __restrict__ x, const T* __restrict__ chi,
-                                                   Cx<T>* __restrict__ tmp, const int* __restrict__ vidx, int nx,
-                                                   int nz, int nitems, int mulchi, const Cx<T>* __restrict__ tw2) {
+__global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>* __restrict__ x,
+                                                                     const T* __restrict__ chi,
+                                                                     Cx<T>* __restrict__ tmp,
+                                                                     const int* __restrict__ vidx, int nx, int nz,
+                                                                     int nitems, int mulchi,
+                                                                     const Cx<T>* __restrict__ tw2) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
-  __shared__ Cx<T> sbuf[GPW][lds_len<L>()];
-  __shared__ Cx<T> stw[L];
+  __shared__ Cx<T> sbuf[GPW][2][lds_len<L>()];
+  __shared__ Cx<T> stw[lds_len<L>()];
   stage_twiddles<T, L>(stw, tw2);
   __syncthreads();
   const int grp = threadIdx.x / G, g = threadIdx.x % G;
   const size_t vstride = (size_t)nx * nz;
-  for (int base = blockIdx.x * GPW; base < nitems; base += gridDim.x * GPW) {
+  const int step = gridDim.x * GPW;
+  Cx<T> px[E];
+  T pc[E];
+  auto fetch = [&](int base) {
     const int item = base + grp;
-    const bool valid = item < nitems;
-    const int it = valid ? item : nitems - 1;
+    const int it = item < nitems ? item : nitems - 1;
     const int slot = it / nx, i = it % nx;
     const int vi = vidx ? vidx[slot] : slot;
     const Cx<T>* xr = x + (size_t)vi * vstride + (size_t)i * nz;
     const T* cr = chi + (size_t)i * nz;
-    Cx<T> u[E], v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int p = fft_elem<L>(g, e);
-      Cx<T> val = czero<T>();
-      if (p < nz) {
-        val = xr[p];
-        if (mulchi) val = cr[p] * val;
-      }
-      u[e] = val;
-      v[e] = val;
+      px[e] = p < nz ? xr[p] : czero<T>();
+      pc[e] = (mulchi && p < nz) ? cr[p] : T(1);
     }
+  };
+  int base = blockIdx.x * GPW;
+  if (base < nitems) fetch(base);
+  for (; base < nitems; base += step) {
+    const int item = base + grp;
+    const bool valid = item < nitems;
+    const int it = valid ? item : nitems - 1;
+    const int slot = it / nx, i = it % nx;
+    Cx<T> a[E], b[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int p = fft_elem<L>(g, e);
+      a[e] = pc[e] * px[e];
+      b[e] = a[e] * tw_lo<T, L>(stw, p);
+    }
+    if (base + step < nitems) fetch(base + step);
     Cx<T>* tr = tmp + ((size_t)slot * nx + i) * (2 * L);
-    fft_regs<T, L, false>(v, g, sbuf[grp], stw);
+    fft2_regs<T, L, false>(a, b, g, sbuf[grp][0], sbuf[grp][1], stw);
     if (valid) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) tr[fft_elem<L>(g, e)] = v[e];
-    }
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = u[e] * stw[fft_elem<L>(g, e)];
-    fft_regs<T, L, false>(v, g, sbuf[grp], stw);
-    if (valid) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) tr[L + fft_elem<L>(g, e)] = v[e];
+      for (int e = 0; e < E; ++e) {
+        const int p = fft_elem<L>(g, e);
+        tr[p] = a[e];
+        tr[L + p] = b[e];
+      }
     }
     wave_sync();
   }
@@ -95,12 +111,14 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
 // A workgroup owns C adjacent columns of tmp (C * sizeof(Cx<T>) contiguous
 // bytes per row) and one wavefront group per column.  The tile is staged in
 // LDS column-major with an odd column stride (conflict-free transposition);
-// each column's LDS slot then doubles as that group's FFT exchange buffer.
+// each column's LDS slot then serves as one of the two exchange buffers of
+// that group's interleaved even/odd FFT pair, xbuf as the other.
 template <typename T, int L>
 struct ColTile {
   // widest tile that keeps 128-byte row segments and fits the LDS and thread budgets
   static constexpr int stride = lds_len<L>() + 1;
-  static constexpr int lds_cap = (144 * 1024 - L * (int)sizeof(Cx<T>)) / (stride * (int)sizeof(Cx<T>));
+  static constexpr int lds_cap =
+      (156 * 1024 - lds_len<L>() * (int)sizeof(Cx<T>)) / ((stride + lds_len<L>()) * (int)sizeof(Cx<T>));
   static constexpr int want = 128 / (int)sizeof(Cx<T>);
   static constexpr int c0 = want < lds_cap ? want : lds_cap;
   static constexpr int thr_cap = 1024 / FftPlan<L>::G;
@@ -122,11 +140,18 @@ __global__ __launch_bounds__(C * FftPlan<L>::G) void k_cols(Cx<T>* __restrict__ 
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, NT = C * G, ST = ColTile<T, L>::stride;
   __shared__ Cx<T> tile[C * ST];
-  __shared__ Cx<T> stw[L];
+  __shared__ Cx<T> xbuf[C][lds_len<L>()];
+  __shared__ Cx<T> stw[lds_len<L>()];
   stage_twiddles<T, L>(stw, tw2);
+  // Tiles narrower than a 128-byte line are grouped PAIR at a time; the PAIR
+  // tiles of one line and one vector take consecutive logical ids, so the
+  // second half of every line is an L2 hit, and all vectors of a tile group
+  // follow each other (spectrum reuse in L2).
+  constexpr int PAIR = (C * (int)sizeof(Cx<T>) >= 128) ? 1 : 128 / (C * (int)sizeof(Cx<T>));
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-  const int tid = lb / nslots, slot = lb % nslots;
-  const int c0 = tid * C;
+  const int grp_id = lb / (nslots * PAIR), rem = lb % (nslots * PAIR);
+  const int slot = rem / PAIR;
+  const int c0 = (grp_id * PAIR + rem % PAIR) * C;
   Cx<T>* tb = tmp + (size_t)slot * nx * pz + c0;
   for (int idx = threadIdx.x; idx < L * C; idx += NT) {
     const int i = idx / C, c = idx % C;
@@ -135,38 +160,30 @@ __global__ __launch_bounds__(C * FftPlan<L>::G) void k_cols(Cx<T>* __restrict__ 
   __syncthreads();
   const int c = threadIdx.x / G, g = threadIdx.x % G;
   Cx<T>* col = tile + c * ST;
-  Cx<T> xin[E], acc[E], v[E];
+  // even (h = 0) and odd (h = 1) frequency halves along x
+  Cx<T> ve[E], vo[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    xin[e] = col[lds_pad(fft_elem<L>(g, e))];
-    v[e] = xin[e];
+    const int p = fft_elem<L>(g, e);
+    ve[e] = col[lds_pad(p)];
+    vo[e] = ve[e] * tw_lo<T, L>(stw, p);
   }
   const Cx<T>* g0 = gs + (size_t)(c0 + c) * L;
   const Cx<T>* g1 = gs + ((size_t)pz + c0 + c) * L;
-  fft_regs<T, L, false>(v, g, col, stw);
+  fft2_regs<T, L, false>(ve, vo, g, col, xbuf[c], stw);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const Cx<T> sp = g0[fft_elem<L>(g, e)];
-    v[e] = adj ? cmul_conj(sp, v[e]) : sp * v[e];
+    const int p = fft_elem<L>(g, e);
+    const Cx<T> s0 = g0[p], s1 = g1[p];
+    ve[e] = adj ? cmul_conj(s0, ve[e]) : s0 * ve[e];
+    vo[e] = adj ? cmul_conj(s1, vo[e]) : s1 * vo[e];
   }
-  fft_regs<T, L, true>(v, g, col, stw);
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    acc[e] = v[e];
-    v[e] = xin[e] * stw[fft_elem<L>(g, e)];
-  }
-  fft_regs<T, L, false>(v, g, col, stw);
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const Cx<T> sp = g1[fft_elem<L>(g, e)];
-    v[e] = adj ? cmul_conj(sp, v[e]) : sp * v[e];
-  }
-  fft_regs<T, L, true>(v, g, col, stw);
+  fft2_regs<T, L, true>(ve, vo, g, col, xbuf[c], stw);
   wave_sync();
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int p = fft_elem<L>(g, e);
-    col[lds_pad(p)] = acc[e] + cmul_conj(stw[p], v[e]);
+    col[lds_pad(p)] = ve[e] + cmul_conj(tw_lo<T, L>(stw, p), vo[e]);
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < nx * C; idx += NT) {
@@ -178,13 +195,15 @@ __global__ __launch_bounds__(C * FftPlan<L>::G) void k_cols(Cx<T>* __restrict__ 
 // ------------------------------------------------------------------ pass 3
 template <typename T, int L>
 __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>* __restrict__ tmp, const Cx<T>* x,
-                                                   const T* __restrict__ chi, const Cx<T>* rhs, Cx<T>* y,
-                                                   double* __restrict__ rnorm, const int* __restrict__ vidx, int nx,
-                                                   int nz, int nitems, int epi, const Cx<T>* __restrict__ tw2) {
+                                                                     const T* __restrict__ chi, const Cx<T>* rhs,
+                                                                     Cx<T>* y, double* __restrict__ rnorm,
+                                                                     const int* __restrict__ vidx, int nx, int nz,
+                                                                     int nitems, int epi,
+                                                                     const Cx<T>* __restrict__ tw2) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
-  __shared__ Cx<T> sbuf[GPW][lds_len<L>()];
-  __shared__ Cx<T> stw[L];
+  __shared__ Cx<T> sbuf[GPW][2][lds_len<L>()];
+  __shared__ Cx<T> stw[lds_len<L>()];
   stage_twiddles<T, L>(stw, tw2);
   __syncthreads();
   const int grp = threadIdx.x / G, g = threadIdx.x % G;
@@ -196,23 +215,21 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
     const int slot = it / nx, i = it % nx;
     const int vi = vidx ? vidx[slot] : slot;
     const Cx<T>* tr = tmp + ((size_t)slot * nx + i) * (2 * L);
-    Cx<T> v[E], acc[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = tr[fft_elem<L>(g, e)];
-    fft_regs<T, L, true>(v, g, sbuf[grp], stw);
+    Cx<T> acc[E], v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      acc[e] = v[e];
-      v[e] = tr[L + fft_elem<L>(g, e)];
+      const int p = fft_elem<L>(g, e);
+      acc[e] = tr[p];
+      v[e] = tr[L + p];
     }
-    fft_regs<T, L, true>(v, g, sbuf[grp], stw);
+    fft2_regs<T, L, true>(acc, v, g, sbuf[grp][0], sbuf[grp][1], stw);
     const size_t off = (size_t)vi * vstride + (size_t)i * nz;
     double nrm = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int p = fft_elem<L>(g, e);
       if (p < nz) {
-        const Cx<T> conv = acc[e] + cmul_conj(stw[p], v[e]);
+        const Cx<T> conv = acc[e] + cmul_conj(tw_lo<T, L>(stw, p), v[e]);
         Cx<T> out;
         switch (epi) {
           case 0: out = x[off + p] - conv; break;
@@ -240,12 +257,14 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
 // Row pass: row p of the circulant table (length pz = 2 lz, full input),
 // written transposed to s1t[c][p] in the split column order.
 template <int L>
-__global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_rows(const Cx<double>* __restrict__ ktab, int nx, int nz, int px,
-                                                    Cx<double>* __restrict__ s1t, const Cx<double>* __restrict__ tw2) {
+__global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_rows(const Cx<double>* __restrict__ ktab,
+                                                                           int nx, int nz, int px,
+                                                                           Cx<double>* __restrict__ s1t,
+                                                                           const Cx<double>* __restrict__ tw2) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<double, L>() / G;
-  __shared__ Cx<double> sbuf[GPW][lds_len<L>()];
-  __shared__ Cx<double> stw[L];
+  __shared__ Cx<double> sbuf[GPW][2][lds_len<L>()];
+  __shared__ Cx<double> stw[lds_len<L>()];
   stage_twiddles<double, L>(stw, tw2);
   __syncthreads();
   const int grp = threadIdx.x / G, g = threadIdx.x % G;
@@ -259,17 +278,15 @@ __global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_rows(const
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int q = fft_elem<L>(g, e);
-      // lags of q and q + L
-      const int l1 = q, l2 = pz - (q + L);  // q < L so min(q, pz - q) = q; q + L >= L
-      const int lz2 = (q + L) < l2 ? (q + L) : l2;
+      // lags of columns q and q + L: q (q < L) and min(q + L, L - q) = L - q
+      const int l2 = L - q;
       Cx<double> k1 = czero<double>(), k2 = czero<double>();
-      if (lxp < nx && l1 < nz) k1 = ktab[(size_t)lxp * nz + l1];
-      if (lxp < nx && lz2 < nz) k2 = ktab[(size_t)lxp * nz + lz2];
+      if (lxp < nx && q < nz) k1 = ktab[(size_t)lxp * nz + q];
+      if (lxp < nx && l2 < nz) k2 = ktab[(size_t)lxp * nz + l2];
       a[e] = k1 + k2;
-      b[e] = (k1 - k2) * stw[q];
+      b[e] = (k1 - k2) * tw_lo<double, L>(stw, q);
     }
-    fft_regs<double, L, false>(a, g, sbuf[grp], stw);
-    fft_regs<double, L, false>(b, g, sbuf[grp], stw);
+    fft2_regs<double, L, false>(a, b, g, sbuf[grp][0], sbuf[grp][1], stw);
     if (valid) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -284,13 +301,15 @@ __global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_rows(const
 
 // Column pass: full-length transform of s1t[c][0..px) -> gs[h][c][m] scaled.
 template <int L>
-__global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_cols(const Cx<double>* __restrict__ s1t, int pz,
-                                                    Cx<double>* __restrict__ gs64, Cx<float>* __restrict__ gs32,
-                                                    double scale, const Cx<double>* __restrict__ tw2) {
+__global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_cols(const Cx<double>* __restrict__ s1t,
+                                                                           int pz, Cx<double>* __restrict__ gs64,
+                                                                           Cx<float>* __restrict__ gs32,
+                                                                           double scale,
+                                                                           const Cx<double>* __restrict__ tw2) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<double, L>() / G;
-  __shared__ Cx<double> sbuf[GPW][lds_len<L>()];
-  __shared__ Cx<double> stw[L];
+  __shared__ Cx<double> sbuf[GPW][2][lds_len<L>()];
+  __shared__ Cx<double> stw[lds_len<L>()];
   stage_twiddles<double, L>(stw, tw2);
   __syncthreads();
   const int grp = threadIdx.x / G, g = threadIdx.x % G;
@@ -306,10 +325,9 @@ __global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_cols(const
       const int p = fft_elem<L>(g, e);
       const Cx<double> k1 = col[p], k2 = col[p + L];
       a[e] = k1 + k2;
-      b[e] = (k1 - k2) * stw[p];
+      b[e] = (k1 - k2) * tw_lo<double, L>(stw, p);
     }
-    fft_regs<double, L, false>(a, g, sbuf[grp], stw);
-    fft_regs<double, L, false>(b, g, sbuf[grp], stw);
+    fft2_regs<double, L, false>(a, b, g, sbuf[grp][0], sbuf[grp][1], stw);
     if (valid) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -415,6 +433,7 @@ template <typename T>
 hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int nslots, bool adj, const Cx<T>* tw2,
                        hipStream_t s, int tile) {
   if (nslots <= 0) return hipSuccess;
+  if (pz % 16 != 0) return hipErrorInvalidValue;  // tile groups of one 128-byte line must divide the row
   LSOP_DISPATCH_L(L, {
     constexpr int CMAX = ColTile<T, LL>::C;
     int C = (tile > 0 && tile < CMAX) ? tile : CMAX;
