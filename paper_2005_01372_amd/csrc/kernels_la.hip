@@ -108,49 +108,6 @@ __global__ void k_philox_normal(Cx<T>* __restrict__ out, size_t n, uint64_t seed
 }
 
 // ---------------------------------------------------------- C = A^H B (split over n)
-constexpr int GA_T = 32;   // output tile (a and b)
-constexpr int GA_K = 32;   // k step staged in LDS
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_ah_b(const Cx<T>* __restrict__ A, int na, const Cx<T>* __restrict__ B,
-                                                    const int* __restrict__ vidx, int nb, size_t n, size_t chunk,
-                                                    Cx<double>* __restrict__ part) {
-  __shared__ Cx<T> sa[GA_T][GA_K + 1];
-  __shared__ Cx<T> sb[GA_T][GA_K + 1];
-  const int a0 = blockIdx.x * GA_T, b0 = blockIdx.y * GA_T, ks = blockIdx.z;
-  const size_t k_begin = (size_t)ks * chunk;
-  const size_t k_end = k_begin + chunk < n ? k_begin + chunk : n;
-  const int ta = (threadIdx.x / 16) * 2, tb = (threadIdx.x % 16) * 2;
-  Cx<double> acc[2][2] = {};
-  for (size_t kk = k_begin; kk < k_end; kk += GA_K) {
-    for (int idx = threadIdx.x; idx < GA_T * GA_K; idx += 256) {
-      const int r = idx / GA_K, c = idx % GA_K;
-      const size_t k = kk + c;
-      const bool kin = k < k_end;
-      sa[r][c] = (kin && a0 + r < na) ? A[(size_t)(a0 + r) * n + k] : czero<T>();
-      int vb = b0 + r;
-      sb[r][c] = (kin && vb < nb) ? B[(size_t)(vidx ? vidx[vb] : vb) * n + k] : czero<T>();
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int c = 0; c < GA_K; ++c) {
-      const Cx<double> x0 = ccast<double>(sa[ta][c]), x1 = ccast<double>(sa[ta + 1][c]);
-      const Cx<double> y0 = ccast<double>(sb[tb][c]), y1 = ccast<double>(sb[tb + 1][c]);
-      acc[0][0] = acc[0][0] + cmul_conj(x0, y0);
-      acc[0][1] = acc[0][1] + cmul_conj(x0, y1);
-      acc[1][0] = acc[1][0] + cmul_conj(x1, y0);
-      acc[1][1] = acc[1][1] + cmul_conj(x1, y1);
-    }
-    __syncthreads();
-  }
-  Cx<double>* p = part + (size_t)ks * na * nb;
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      if (a0 + ta + i < na && b0 + tb + j < nb) p[(size_t)(a0 + ta + i) * nb + b0 + tb + j] = acc[i][j];
-}
-
 __global__ void k_reduce_parts(const Cx<double>* __restrict__ part, int nparts, size_t count,
                                Cx<double>* __restrict__ C) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
@@ -160,53 +117,183 @@ __global__ void k_reduce_parts(const Cx<double>* __restrict__ part, int nparts, 
   }
 }
 
-// ---------------------------------------------------------- Y = X1 + beta X2 + A M
-constexpr int GU_B = 16;  // b columns per pass
-constexpr int GU_A = 16;  // a rows per register block
+// ---------------------------------------------------------------- MFMA tiles
+// v_mfma_*_16x16x4: A operand lane l = A[l % 16][l / 16], B operand lane l =
+// B[l / 16][l % 16]; the 16 x 16 result row held in register r of lane l is
+// 4 (l / 16) + r for f32 and 4 r + l / 16 for f64 (checked on gfx950), the
+// column is l % 16.  A complex product is two real chains over interleaved
+// (re, im) operands: with A'[.][2k + p] the p-th component of a_k,
+//   conj(a) b:  re = sum_kk A'[kk] (br, bi)[kk],  im = sum_kk A'[kk] (bi, -br)[kk]
+//   m a (no conj, m on the left):  re = (mr, -mi) . (ar, ai),  im = (mi, mr) . (ar, ai).
+typedef float lsop_f4 __attribute__((ext_vector_type(4)));
+typedef double lsop_d4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_update(const Cx<T>* __restrict__ A, int na,
-                                                      const Cx<double>* __restrict__ M, int nb,
-                                                      const Cx<T>* X1, const Cx<T>* X2, T beta, Cx<T>* Y,
-                                                      const int* __restrict__ vidx, size_t n) {
-  extern __shared__ unsigned char smem_raw[];
-  Cx<T>* sm = reinterpret_cast<Cx<T>*>(smem_raw);  // [na][GU_B]
-  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool kin = k < n;
-  for (int b0 = 0; b0 < nb; b0 += GU_B) {
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < na * GU_B; idx += blockDim.x) {
-      const int a = idx / GU_B, bb = idx % GU_B;
-      sm[idx] = (b0 + bb < nb) ? ccast<T>(M[(size_t)a * nb + b0 + bb]) : czero<T>();
+struct Mfma;
+template <>
+struct Mfma<float> {
+  using acc = lsop_f4;
+  __device__ __forceinline__ static acc mma(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <>
+struct Mfma<double> {
+  using acc = lsop_d4;
+  __device__ __forceinline__ static acc mma(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ __forceinline__ static int row(int l, int r) { return 4 * r + (l >> 4); }
+};
+
+// C[a][b] partials = sum_k conj(A[a][k]) B[vb][k] over one k-chunk.  Tile
+// 64 (a) x 64 (b) per workgroup of four waves (each 32 x 32 = 2 x 2 MFMA
+// tiles, real and imaginary chains); operands staged in LDS 16 complex k at a time.
+constexpr int GM_T = 64, GM_K = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict__ A, int na,
+                                                        const Cx<T>* __restrict__ B, const int* __restrict__ vidx,
+                                                        int nb, size_t n, size_t chunk,
+                                                        Cx<double>* __restrict__ part) {
+  using M = Mfma<T>;
+  constexpr int SROW = 2 * GM_K + 1;  // reals per LDS row (odd stride)
+  __shared__ T sa[GM_T * SROW];
+  __shared__ T sb[GM_T * SROW];
+  const int a0 = blockIdx.x * GM_T, b0 = blockIdx.y * GM_T, ks = blockIdx.z;
+  const size_t k_begin = (size_t)ks * chunk;
+  const size_t k_end = k_begin + chunk < n ? k_begin + chunk : n;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wa = (w >> 1) * 32, wb = (w & 1) * 32;
+  typename M::acc cre[2][2], cim[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = typename M::acc{0, 0, 0, 0};
+      cim[i][j] = typename M::acc{0, 0, 0, 0};
+    }
+  // loader: thread t -> row t / 4, complex k (t % 4) * 4 .. +4
+  const int lr = threadIdx.x >> 2, lk = (threadIdx.x & 3) * 4;
+  const Cx<T>* arow = (a0 + lr < na) ? A + (size_t)(a0 + lr) * n : nullptr;
+  const int vb = b0 + lr;
+  const Cx<T>* brow = (vb < nb) ? B + (size_t)(vidx ? vidx[vb] : vb) * n : nullptr;
+  const int kk = l >> 4, c16 = l & 15;
+  for (size_t kb = k_begin; kb < k_end; kb += GM_K) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const size_t k = kb + lk + q;
+      const bool kin = k < k_end;
+      const Cx<T> va = (arow && kin) ? arow[k] : czero<T>();
+      const Cx<T> vb2 = (brow && kin) ? brow[k] : czero<T>();
+      sa[lr * SROW + 2 * (lk + q)] = va.re;
+      sa[lr * SROW + 2 * (lk + q) + 1] = va.im;
+      sb[lr * SROW + 2 * (lk + q)] = vb2.re;
+      sb[lr * SROW + 2 * (lk + q) + 1] = vb2.im;
     }
     __syncthreads();
-    Cx<T> acc[GU_B];
 #pragma unroll
-    for (int bb = 0; bb < GU_B; ++bb) acc[bb] = czero<T>();
-    for (int a0 = 0; a0 < na; a0 += GU_A) {
-      Cx<T> av[GU_A];
+    for (int st = 0; st < GM_K / 2; ++st) {
+      const int col = 4 * st + kk;
+      T av[2], bre[2], bim[2];
 #pragma unroll
-      for (int j = 0; j < GU_A; ++j) av[j] = (kin && a0 + j < na) ? A[(size_t)(a0 + j) * n + k] : czero<T>();
+      for (int i = 0; i < 2; ++i) av[i] = sa[(wa + i * 16 + c16) * SROW + col];
 #pragma unroll
-      for (int j = 0; j < GU_A; ++j) {
-        if (a0 + j < na) {
+      for (int j = 0; j < 2; ++j) {
+        const int rb = (wb + j * 16 + c16) * SROW;
+        bre[j] = sb[rb + col];
+        bim[j] = (kk & 1) ? -sb[rb + col - 1] : sb[rb + col + 1];
+      }
 #pragma unroll
-          for (int bb = 0; bb < GU_B; ++bb) acc[bb] = acc[bb] + av[j] * sm[(a0 + j) * GU_B + bb];
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cre[i][j] = M::mma(av[i], bre[j], cre[i][j]);
+          cim[i][j] = M::mma(av[i], bim[j], cim[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+  Cx<double>* p = part + (size_t)ks * na * nb;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = a0 + wa + i * 16 + M::row(l, r);
+        const int b = b0 + wb + j * 16 + c16;
+        if (a < na && b < nb) p[(size_t)a * nb + b] = Cx<double>{(double)cre[i][j][r], (double)cim[i][j][r]};
+      }
+}
+
+// Y[vy(b)][k] = X1 + beta X2 + sum_a A[a][k] M[a][b] as out[b][k] = M^T A:
+// each wave owns 16 consecutive k (coalesced B-operand loads and stores) and
+// up to NBT * 16 b (MFMA row tiles, real and imaginary chains); M is staged in
+// LDS GU2_A rows (a) at a time; the next A element is loaded while the current
+// step's MFMAs run.
+constexpr int GU2_A = 16;
+
+template <typename T, int NBT>
+__global__ __launch_bounds__(256) void k_gemm_update_mfma(const Cx<T>* __restrict__ A, int na,
+                                                          const Cx<double>* __restrict__ Mm, int nb,
+                                                          const Cx<T>* X1, const Cx<T>* X2, T beta, Cx<T>* Y,
+                                                          const int* __restrict__ vidx, size_t n) {
+  using MF = Mfma<T>;
+  constexpr int BW = NBT * 16;
+  __shared__ Cx<T> sm[GU2_A * BW];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const size_t k0 = ((size_t)blockIdx.x * 4 + w) * 16;
+  const int kk = l >> 4, c16 = l & 15, pp = kk & 1;
+  const size_t kcol = k0 + c16;
+  const bool kin = kcol < n;
+  for (int b0 = 0; b0 < nb; b0 += BW) {
+    typename MF::acc cre[NBT], cim[NBT];
+#pragma unroll
+    for (int j = 0; j < NBT; ++j) {
+      cre[j] = typename MF::acc{0, 0, 0, 0};
+      cim[j] = typename MF::acc{0, 0, 0, 0};
+    }
+    int a_next = kk >> 1;
+    Cx<T> av = (kin && a_next < na) ? A[(size_t)a_next * n + kcol] : czero<T>();
+    for (int a0 = 0; a0 < na; a0 += GU2_A) {
+      __syncthreads();
+      for (int idx = threadIdx.x; idx < GU2_A * BW; idx += blockDim.x) {
+        const int a = a0 + idx / BW, b = b0 + idx % BW;
+        sm[idx] = (a < na && b < nb) ? ccast<T>(Mm[(size_t)a * nb + b]) : czero<T>();
+      }
+      __syncthreads();
+#pragma unroll
+      for (int st = 0; st < GU2_A / 2; ++st) {
+        const T bop = pp ? av.im : av.re;
+        a_next += 2;
+        av = (kin && a_next < na) ? A[(size_t)a_next * n + kcol] : czero<T>();
+        const int al = 2 * st + (kk >> 1);
+#pragma unroll
+        for (int j = 0; j < NBT; ++j) {
+          const Cx<T> m = sm[al * BW + j * 16 + c16];
+          const T ore = pp ? -m.im : m.re;
+          const T oim = pp ? m.re : m.im;
+          cre[j] = MF::mma(ore, bop, cre[j]);
+          cim[j] = MF::mma(oim, bop, cim[j]);
         }
       }
     }
     if (kin) {
 #pragma unroll
-      for (int bb = 0; bb < GU_B; ++bb) {
-        const int b = b0 + bb;
-        if (b < nb) {
-          const size_t off = (size_t)(vidx ? vidx[b] : b) * n + k;
-          Cx<T> out = acc[bb];
-          if (X1) out = out + X1[off];
-          if (X2) out = out + beta * X2[off];
-          Y[off] = out;
+      for (int j = 0; j < NBT; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int b = b0 + j * 16 + MF::row(l, r);
+          if (b < nb) {
+            const size_t off = (size_t)(vidx ? vidx[b] : b) * n + kcol;
+            Cx<T> out{cre[j][r], cim[j][r]};
+            if (X1) out = out + X1[off];
+            if (X2) out = out + beta * X2[off];
+            Y[off] = out;
+          }
         }
-      }
     }
   }
 }
@@ -471,10 +558,10 @@ hipError_t launch_gemm_ah_b(const Cx<T>* A, int na, const Cx<T>* B, const int* v
                             Cx<double>* C, Cx<double>* part, int ksplit, hipStream_t s) {
   if (na <= 0 || nb <= 0) return hipSuccess;
   size_t chunk = (n + ksplit - 1) / ksplit;
-  chunk = (chunk + GA_K - 1) / GA_K * GA_K;
+  chunk = (chunk + GM_K - 1) / GM_K * GM_K;
   const int parts = (int)((n + chunk - 1) / chunk);
-  dim3 grid((na + GA_T - 1) / GA_T, (nb + GA_T - 1) / GA_T, parts);
-  hipLaunchKernelGGL((k_gemm_ah_b<T>), grid, dim3(256), 0, s, A, na, B, vidx, nb, n, chunk, part);
+  dim3 grid((na + GM_T - 1) / GM_T, (nb + GM_T - 1) / GM_T, parts);
+  hipLaunchKernelGGL((k_gemm_ah_b_mfma<T>), grid, dim3(256), 0, s, A, na, B, vidx, nb, n, chunk, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((size_t)na * nb, 64)), dim3(256), 0, s, part, parts,
@@ -486,9 +573,11 @@ template <typename T>
 hipError_t launch_gemm_update(const Cx<T>* A, int na, const Cx<double>* M, int nb, const Cx<T>* X1,
                               const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-  const size_t shm = sizeof(Cx<T>) * (size_t)na * GU_B;
-  hipLaunchKernelGGL((k_gemm_update<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), shm, s, A, na, M, nb, X1, X2,
-                     (T)beta, Y, vidx, n);
+  const dim3 grid((unsigned)((n + 63) / 64));
+  if (nb > 32)
+    hipLaunchKernelGGL((k_gemm_update_mfma<T, 4>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y, vidx, n);
+  else
+    hipLaunchKernelGGL((k_gemm_update_mfma<T, 2>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y, vidx, n);
   return hipGetLastError();
 }
 
