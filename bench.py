@@ -16,7 +16,6 @@ region), the batched operator throughput, and the FP64 oracle timed on a
 bounded sample of the same workload on the host cores.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -41,17 +40,9 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sources", type=int, default=2, help="sources in the oracle's timed sample")
-    ap.add_argument("--pmc-probe", action="store_true",
-                    help="run only a 1 GiB device copy and a few batched applies (for rocprofv3 --pmc)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB device-to-device (a plain copy of known size for rocprofv3 --pmc scaling)")
     return ap.parse_args()
-
-
-def kernel_source_sha():
-    h = hashlib.sha256()
-    for f in ("kernels_fft.hip", "kernels_la.hip", "fft_engine.hpp"):
-        with open(os.path.join(ROOT, "paper_2005_01372_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def load_traffic(kernel):
@@ -62,9 +53,10 @@ def load_traffic(kernel):
     with open(path) as f:
         d = json.load(f)
     k = d.get("kernels", {}).get(kernel)
+    from paper_2005_01372_amd.profiling import kernel_source_sha
     if not k or d.get("source_sha") != kernel_source_sha():
         return None
-    return k.get("hbm_bytes_per_launch")
+    return k.get("hbm_over_algorithmic")
 
 
 def cpu_baseline(w, rank, iterations, converged, nsrc_sample=2, nprobe_sample=2):
@@ -130,6 +122,12 @@ def main():
     from paper_2005_01372_amd import lsop, synth
 
     torch.cuda.init()
+    if args.copy_probe:
+        a = torch.ones(1 << 27, dtype=torch.complex64, device="cuda")   # 1 GiB
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+        del a
+
     w = synth.model_random_ellipses(n=args.n, nsrc=args.nsrc)
     vel = torch.as_tensor(w.vel, device="cuda")
     op = lsop.Operator(w.nx, w.nz, lsop.C64, max_vec=max(args.nsrc, args.rank))
@@ -137,18 +135,6 @@ def main():
     psi = torch.empty((w.nsrc, w.nx, w.nz), dtype=torch.complex64, device="cuda")
     op.set_problem(vel, w.h, w.freq, w.c0)
     op.autotune(w.nsrc)
-
-    if args.pmc_probe:
-        a = torch.ones(1 << 27, dtype=torch.complex64, device="cuda")   # 1 GiB
-        b = torch.empty_like(a)
-        b.copy_(a)
-        op.set_problem(vel, w.h, w.freq, w.c0)
-        x = torch.ones((args.nsrc, w.nx, w.nz), dtype=torch.complex64, device="cuda")
-        for _ in range(3):
-            op.apply(x, "A", out=psi)
-        torch.cuda.synchronize()
-        print(json.dumps({"pmc_probe": True, "copy_bytes": 2 * a.numel() * 8}))
-        return
 
     def step():
         op.set_problem(vel, w.h, w.freq, w.c0)
@@ -184,7 +170,8 @@ def main():
     bpl = d["bytes"] / d["launches"]
     achieved = bpl / avg_s / 1e9
     roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": load_traffic(dom),
+                "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": (lambda r: None if r is None else round(r * bpl))(load_traffic(dom)),
                 "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_bytes_per_launch": bpl,
                 "launches": d["launches"]}
     kernels = {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4),
