@@ -1,0 +1,85 @@
+"""Pins for the dense-based HODLR oracle (Section 2.4, Fig. 1)."""
+import numpy as np
+
+from oracle import hodlr as HD
+from oracle import lsop_oracle as O
+from paper_2005_01372_amd import synth
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def small(n=24, freq=15.0):
+    w = synth.model_layered_salt(n=n, h=10.0, freq=freq, seed=2, nsrc=1)
+    return w, O.Problem(w.vel, w.h, w.freq, w.c0)
+
+
+def test_tree_is_column_strips():
+    """Nodes are ranges of whole grid columns (multiples of nz cells), halved at each level."""
+    t = HD.split_tree(ncols=13, nz=5, levels=3)
+    leaves = []
+
+    def walk(node, depth):
+        assert node.lo % 5 == 0 and node.hi % 5 == 0
+        if hasattr(node, "children_cols"):
+            assert node.c1.lo == node.lo and node.c2.hi == node.hi and node.c1.hi == node.c2.lo
+            walk(node.c1, depth + 1)
+            walk(node.c2, depth + 1)
+        else:
+            leaves.append((node.lo, node.hi, depth))
+    walk(t, 0)
+    assert leaves[0][0] == 0 and leaves[-1][1] == 65 and max(d for *_, d in leaves) == 3
+
+
+def test_full_rank_hodlr_is_exact_and_inverts():
+    """With rank >= block size the HODLR approximation equals A and both inverses equal A^{-1} (P11)."""
+    w, prob = small(12)
+    A = O.operator_matrix(prob.K, prob.chi)
+    tree = HD.split_tree(prob.nx, prob.nz, levels=2)
+    H = HD.build(A, tree, r=prob.n, seed=1)
+    assert rel(H.to_dense(), A) < 1e-12
+    Ai = np.linalg.inv(A)
+    assert rel(HD.invert(H, r=prob.n).to_dense(), Ai) < 1e-10
+    x = synth.random_vectors((prob.n, 3), 3)
+    hs = HD.HodlrSolve(prob, rank=prob.n, levels=2, seed=1)
+    assert rel(hs.solve_node(hs.approx, x), Ai @ x) < 1e-10
+
+
+def test_matvec_and_adjoint_match_dense():
+    w, prob = small(16)
+    A = O.operator_matrix(prob.K, prob.chi)
+    H = HD.build(A, HD.split_tree(prob.nx, prob.nz, levels=3), r=6, seed=2)
+    D = H.to_dense()
+    x = synth.random_vectors((prob.n, 2), 4)
+    assert rel(H.matvec(x), D @ x) < 1e-13
+    assert rel(H.rmatvec(x), D.conj().T @ x) < 1e-13
+
+
+def test_truncation_is_best_rank_r():
+    """Recompression returns the SVD-optimal rank-r approximation of the factored sum (Eckart-Young)."""
+    rng = np.random.default_rng(0)
+    U = rng.standard_normal((40, 8)) + 1j * rng.standard_normal((40, 8))
+    V = rng.standard_normal((30, 8)) + 1j * rng.standard_normal((30, 8))
+    Ut, Vt = HD.truncate(U, V, 3)
+    s = np.linalg.svd(U @ V.conj().T, compute_uv=False)
+    assert abs(np.linalg.norm(U @ V.conj().T - Ut @ Vt.conj().T, 2) - s[3]) <= 1e-10 * s[0]
+
+
+def test_solve_variant_inverts_its_own_hodlr_matrix():
+    """The nested-SMW solve applies the exact inverse of the (truncated-rank) HODLR approximation."""
+    w, prob = small(16)
+    hs = HD.HodlrSolve(prob, rank=5, levels=3, seed=3)
+    D = hs.approx.to_dense()
+    x = synth.random_vectors((prob.n, 2), 5)
+    assert rel(D @ hs.solve_node(hs.approx, x), x) < 1e-11
+
+
+def test_hodlr_series_reaches_lu_solution():
+    """The HODLR-preconditioned series converges to the dense-LU solution where rank-r simple H does not."""
+    w, prob = small(48)
+    psi0 = prob.incident(w.src_i, w.src_j)[0]
+    ref = O.solve_direct(prob, psi0)
+    for H in (HD.HodlrPreconditioner(prob, 20, 3, seed=4), HD.HodlrSolve(prob, 20, 3, seed=4)):
+        psi, it, r, st = O.series_solve(prob, H.apply, psi0, 1e-12, 60)
+        assert st == O.OK and rel(psi, ref) < 1e-10
