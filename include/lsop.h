@@ -127,14 +127,30 @@ const char* lsop_last_error(void);
  *                    range finder of Alg. 2 (power_iters = q) and
  *                    Z = (I_r - W^H U)^{-1} by Sherman-Morrison-Woodbury
  *                    (eq. 12).  `rank` probe vectors.
+ *  LSOP_PC_HODLR     H = A_h^{-1}, A_h the hierarchically off-diagonal
+ *                    low-rank approximation of A = I - G0 V (Section 2.4,
+ *                    Fig. 1): cells in column-wise order, a binary tree of
+ *                    `levels` levels of vertical strips (node of level l:
+ *                    nx / 2^l grid columns, split into equal halves), dense
+ *                    diagonal leaves of nx / 2^levels columns, and both
+ *                    off-diagonal blocks of every node approximated by Alg. 1
+ *                    with q = 0 and `rank` probes, the block products done as
+ *                    FFT convolutions on the node's sub-domain.  A_h is
+ *                    inverted exactly, level by level, by Sherman-Morrison-
+ *                    Woodbury on the off-diagonal factors (the 2 x 2 block
+ *                    inverse of Section 2.4 kept in factored form, with no
+ *                    recompression); the leaves by the recursive 2 x 2 block
+ *                    formula in FP64.  Requires nx divisible by 2^levels,
+ *                    (nx / 2^levels) * nz a multiple of 64 and at most 8192.
  * ---------------------------------------------------------------------- */
-typedef enum { LSOP_PC_IDENTITY = 0, LSOP_PC_LOWRANK = 1 } lsop_pc_kind;
+typedef enum { LSOP_PC_IDENTITY = 0, LSOP_PC_LOWRANK = 1, LSOP_PC_HODLR = 2 } lsop_pc_kind;
 
 typedef struct {
   int kind;         /* lsop_pc_kind */
-  int rank;         /* number of Gaussian probes r (LOWRANK), 1 <= rank <= 256 */
-  int power_iters;  /* q >= 0 */
+  int rank;         /* number of Gaussian probes r (LOWRANK, HODLR), 1 <= rank <= 256 */
+  int power_iters;  /* q >= 0 (LOWRANK; HODLR uses q = 0) */
   uint64_t seed;    /* Philox4x32-10 key when no probe block is supplied */
+  int levels;       /* HODLR tree depth, >= 1 (ignored otherwise) */
 } lsop_precond_params;
 
 /* Allocate a preconditioner for `op` (U, W: rank x n complex in the inner
@@ -146,13 +162,20 @@ int precond_create(lsop_op* op, const lsop_precond_params* params, lsop_precond*
  * Philox4x32-10 (counter = (pair index lo, hi, k, 0), key = seed) and
  * Box-Muller.  Columns of the range basis that are numerically dependent are
  * dropped (zero columns of U), so chi = 0 gives H = I exactly.  Synchronises
- * `stream`.  Errors: ESINGULAR if I - W^H U is singular. */
+ * `stream`.  Errors: ESINGULAR if I - W^H U is singular.
+ * HODLR: omega_dev holds levels * rank probes (or Philox probes k = l * rank
+ * .. (l + 1) * rank - 1 for tree level l); the probes of level l restricted to
+ * the cells of a node's second half sample its upper off-diagonal block, to
+ * the first half its lower block.  Each half's samples are orthonormalised
+ * separately (Cholesky-QR twice, FP64 small factors).  Errors: ESINGULAR if a
+ * leaf block or a node's Woodbury core is singular. */
 int precond_build(lsop_precond* pc, const void* omega_dev, void* stream);
 
 /* y = H x for nvec vectors (x, y in the inner dtype of the op). */
 int precond_apply(lsop_precond* pc, const void* x_dev, void* y_dev, int nvec, void* stream);
 
-/* rank kept, compression 2 r / n (Section 3.1.1), device bytes held. */
+/* rank kept, compression 2 r / n (Section 3.1.1), device bytes held.
+ * HODLR: rank = r, compression = stored complex entries / n^2. */
 int precond_info(const lsop_precond* pc, int* rank, double* compression, size_t* bytes);
 void precond_destroy(lsop_precond* pc);
 

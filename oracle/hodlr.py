@@ -103,9 +103,10 @@ def split_tree(ncols, nz, levels, min_width=1):
     return build(0, ncols, 0)
 
 
-def lowrank_from_block(B, r, rng):
-    """Alg. 1 with q = 0 on an explicit block: B ~= Q (B^H Q)^H with r Gaussian probes."""
-    om = rng.standard_normal((B.shape[1], r))
+def lowrank_from_block(B, r, rng, om=None):
+    """Alg. 1 with q = 0 on an explicit block: B ~= Q (B^H Q)^H with r Gaussian probes (or the given om)."""
+    if om is None:
+        om = rng.standard_normal((B.shape[1], r))
     Q, _ = np.linalg.qr(B @ om)
     return Q, B.conj().T @ Q
 
@@ -120,21 +121,28 @@ def truncate(U, V, r):
     return qu @ (w[:, :r] * s[:r]), qv @ zh.conj().T[:, :r]
 
 
-def build(A, tree, r, seed=0):
-    """HODLR approximation of the dense matrix A on the given tree (off-diagonal blocks by Alg. 1, q = 0)."""
+def build(A, tree, r, seed=0, probes=None):
+    """HODLR approximation of the dense matrix A on the given tree (off-diagonal blocks by Alg. 1, q = 0).
+
+    probes: optional callable depth -> real [r, n] block; a node at that depth
+    samples its upper block A[I1, I2] with the probe rows restricted to I2 and
+    its lower block A[I2, I1] with them restricted to I1.  Without it, the
+    probes are drawn from numpy's PCG64 with `seed`.
+    """
     rng = np.random.default_rng(seed)
 
-    def fill(node):
+    def fill(node, depth):
         if not hasattr(node, "children_cols"):
             node.dense = A[node.lo:node.hi, node.lo:node.hi].copy()
             return node
-        node.a11, node.a22 = fill(node.c1), fill(node.c2)
+        node.a11, node.a22 = fill(node.c1, depth + 1), fill(node.c2, depth + 1)
         i1 = slice(node.a11.lo, node.a11.hi)
         i2 = slice(node.a22.lo, node.a22.hi)
-        node.u12, node.v12 = lowrank_from_block(A[i1, i2], r, rng)
-        node.u21, node.v21 = lowrank_from_block(A[i2, i1], r, rng)
+        om = probes(depth) if probes is not None else None
+        node.u12, node.v12 = lowrank_from_block(A[i1, i2], r, rng, None if om is None else om[:, i2].T)
+        node.u21, node.v21 = lowrank_from_block(A[i2, i1], r, rng, None if om is None else om[:, i1].T)
         return node
-    return fill(tree)
+    return fill(tree, 0)
 
 
 def add_lowrank(H, P, Q, r):
@@ -203,10 +211,10 @@ class HodlrSolve:
     inverted without the rank truncation of the H-arithmetic inverse.
     """
 
-    def __init__(self, prob, rank, levels, min_width=1, seed=0):
+    def __init__(self, prob, rank, levels, min_width=1, seed=0, probes=None):
         A = operator_matrix(prob.K, prob.chi)
         self.tree = split_tree(prob.nx, prob.nz, levels, min_width)
-        self.approx = build(A, self.tree, rank, seed)
+        self.approx = build(A, self.tree, rank, seed, probes)
         self.n = prob.n
         self._prepare(self.approx)
 

@@ -266,6 +266,7 @@ int build_impl(lsop_precond* pc, const double* omega, hipStream_t s) {
   Cx<double>* M = pc->small;
   Cx<double>* work = M + (size_t)r * r;
   LSOP_HIP(p_gemm_ah_b<T>(W, r, U, nullptr, r, n, M, pc->part, pc->ksplit, s));
+  LSOP_HIP(hipMemsetAsync(pc->dflag + 1, 0, sizeof(int), s));
   LSOP_HIP(launch_lu_inverse_i_minus(M, pc->Z, work, r, pc->dflag + 1, s));
   int flags[2] = {0, 0};
   LSOP_HIP(hipMemcpyAsync(flags, pc->dflag, sizeof(flags), hipMemcpyDeviceToHost, s));
@@ -276,7 +277,12 @@ int build_impl(lsop_precond* pc, const double* omega, hipStream_t s) {
   return LSOP_OK;
 }
 
-// y = x + U Z W^H x  (or, when series_update, psi <- psi - r - U Z W^H r with x = r, y = psi)
+template <typename T>
+int hodlr_apply(lsop_precond* pc, const Cx<T>* x, const int* xidx, Cx<T>* y, const int* yidx, int nvec, int upto,
+                hipStream_t s);
+
+// y = x + U Z W^H x  (or, when series_update, psi <- psi - r - U Z W^H r with x = r, y = psi);
+// HODLR: y = A_h^{-1} x (or psi <- psi - A_h^{-1} r)
 template <typename T>
 int pc_apply_impl(lsop_precond* pc, const Cx<T>* x, Cx<T>* y, const int* vidx, int nvec, bool series_update,
                   hipStream_t s) {
@@ -291,6 +297,21 @@ int pc_apply_impl(lsop_precond* pc, const Cx<T>* x, Cx<T>* y, const int* vidx, i
       } else {
         LSOP_HIP(hipMemcpyAsync(y, x, sizeof(Cx<T>) * n * nvec, hipMemcpyDeviceToDevice, s));
       }
+    }
+    return LSOP_OK;
+  }
+  if (pc->kind == LSOP_PC_HODLR) {
+    if (!series_update) return hodlr_apply<T>(pc, x, vidx, y, vidx, nvec, 0, s);
+    // psi <- psi - H r, H r into the compact temporary chunk by chunk
+    Cx<T>* hy = reinterpret_cast<Cx<T>*>(pc->hy);
+    for (int c = 0; c < nvec; c += pc->tcap) {
+      const int m = std::min(pc->tcap, nvec - c);
+      const int* vc = vidx ? vidx + c : nullptr;
+      const Cx<T>* xc = vidx ? x : x + (size_t)c * n;
+      Cx<T>* yc = vidx ? y : y + (size_t)c * n;
+      int st = hodlr_apply<T>(pc, xc, vc, hy, nullptr, m, 0, s);
+      if (st) return st;
+      LSOP_HIP(launch_axpy_map<T>(hy, yc, vc, -1.0, m, n, s));
     }
     return LSOP_OK;
   }
@@ -310,6 +331,275 @@ int pc_apply_impl(lsop_precond* pc, const Cx<T>* x, Cx<T>* y, const int* vidx, i
     else
       LSOP_HIP(p_gemm_update<T>(U, r, T2, m, x + off, nullptr, 0.0, y + off, vc, n, s));
   }
+  return LSOP_OK;
+}
+
+// ------------------------------------------------------------------ HODLR
+// Section 2.4.  Level l (0 = root) has 2^l nodes of width nx >> l grid
+// columns; a node's halves are segments of (width / 2) * nz consecutive cells.
+// A_l = A_{l+1} - Ut_l Vt_l^H, where A_levels is the block diagonal of dense
+// leaves and Ut_l Vt_l^H holds the off-diagonal blocks of the level's nodes:
+// with G0 V[I1, I2] ~= Q12 v12^H (Alg. 1, q = 0; v12 = (G0 V[I1, I2])^H Q12),
+// Ut = diag(Q12, Q21) and Vt^H = [[0, v12^H], [v21^H, 0]].  Both are stored
+// packed as full-grid arrays (Q: Q12 on I1 cells and Q21 on I2 cells; V: v12
+// on I2 and v21 on I1).  Woodbury gives
+//   A_l^{-1} y = A_{l+1}^{-1} y + Wp K^{-1} Vt^H A_{l+1}^{-1} y,
+//   Wp = A_{l+1}^{-1} Ut,  K = I - Vt^H Wp = [[I, -v12^H w2], [-v21^H w1, I]],
+// applied bottom-up from the leaf solve.
+
+template <typename T>
+const Cx<T>* lev_gs(const hodlr_level& L);
+template <>
+const Cx<float>* lev_gs<float>(const hodlr_level& L) { return L.gs32; }
+template <>
+const Cx<double>* lev_gs<double>(const hodlr_level& L) { return L.gs64; }
+template <typename T>
+const Cx<T>* lev_tw(const hodlr_level& L);
+template <>
+const Cx<float>* lev_tw<float>(const hodlr_level& L) { return L.tw32; }
+template <>
+const Cx<double>* lev_tw<double>(const hodlr_level& L) { return L.tw64; }
+
+// partial chunks per segment for the block-diagonal inner products
+int hodlr_ksub(const lsop_precond* pc, size_t seg, int nseg) {
+  const int want = (int)std::max<size_t>(1, (seg + 4095) / 4096);
+  return std::max(1, std::min(want, pc->ksub_cap / nseg));
+}
+
+// Sub-domain convolution at level lv: y = G0 V x (adj = false) or
+// V^H G0^H x (adj = true) on each node's strip alone, input restricted to the
+// half in_half of every node, only the half out_half of y written.
+template <typename T>
+int hodlr_subconv(lsop_precond* pc, int lv, bool adj, const Cx<T>* x, Cx<T>* y, int nvec, int in_half, int out_half,
+                  hipStream_t s) {
+  lsop_op* op = pc->op;
+  const hodlr_level& L = pc->lev[lv];
+  const int W = L.width, nodes = op->nx / W, half = W / 2;
+  const int in_lo = in_half ? half : 0, in_hi = in_half ? W : half;
+  const int out_lo = out_half ? half : 0, out_hi = out_half ? W : half;
+  const size_t n = op->n();
+  Cx<T>* tmp = reinterpret_cast<Cx<T>*>(op->tmp);
+  const double e = sizeof(Cx<T>), nn = (double)n, np = (double)op->nx * op->pz();
+  for (int c = 0; c < nvec; c += op->max_vec) {
+    const int m = std::min(op->max_vec, nvec - c);
+    const size_t off = (size_t)c * n;
+    LSOP_HIP(prof("hodlr_rows_fwd", m * (0.5 * nn * e + np * e), 0.0, m, s, [&] {
+      return launch_rows_fwd<T>(op->lz, x + off, Dt<T>::chi(op), tmp, nullptr, W, op->nz, m * nodes, !adj,
+                                Dt<T>::twz(op), s, nodes, in_lo, in_hi);
+    }));
+    LSOP_HIP(prof("hodlr_cols", m * 2.0 * np * e + 2.0 * op->pz() * L.lx * e, 0.0, m, s, [&] {
+      return launch_cols<T>(L.lx, tmp, lev_gs<T>(L), W, op->pz(), m * nodes, adj, lev_tw<T>(L), s, 0);
+    }));
+    LSOP_HIP(prof("hodlr_rows_inv", m * (np * e + 0.5 * nn * e), 0.0, m, s, [&] {
+      return launch_rows_inv<T>(op->lz, tmp, x + off, Dt<T>::chi(op), nullptr, y + off, nullptr, nullptr, W, op->nz,
+                                m * nodes, adj ? 3 : 1, Dt<T>::twz(op), s, nodes, out_lo, out_hi);
+    }));
+  }
+  return LSOP_OK;
+}
+
+// Cholesky-QR twice, separately on every half-node segment of level lv.
+template <typename T>
+int hodlr_orth(lsop_precond* pc, int lv, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s) {
+  const int r = pc->rank;
+  const size_t n = pc->op->n();
+  const int W = pc->lev[lv].width, nseg = 2 * (pc->op->nx / W);
+  const size_t seg = (size_t)(W / 2) * pc->op->nz;
+  const int ksub = hodlr_ksub(pc, seg, nseg);
+  Cx<double>* G = pc->hG;
+  Cx<double>* X = pc->hX;
+  const double tol = std::is_same<T, float>::value ? 1e-9 : 1e-24;
+  const double e = sizeof(Cx<T>);
+  for (int pass = 0; pass < 2; ++pass) {
+    const Cx<T>* src = pass == 0 ? Yin : Qout;
+    Cx<T>* dst = pass == 0 ? Qout : Yin;
+    LSOP_HIP(prof("hodlr_gemm_ah_b", 2.0 * r * n * e, 8.0 * r * r * (double)n, r, s, [&] {
+      return launch_gemm_ah_b_seg<T>(src, r, src, nullptr, r, n, seg, G, pc->part, ksub, s);
+    }));
+    LSOP_HIP(launch_gram_orth(G, X, r, pass == 0 ? tol : 1e-6, pc->hflag, s, nseg));
+    LSOP_HIP(prof("hodlr_gemm_update", 2.0 * r * n * e, 8.0 * r * r * (double)n, r, s, [&] {
+      return launch_gemm_update_seg<T>(src, r, X, (size_t)r * r, r, nullptr, nullptr, 0.0, dst, nullptr, n, seg, s);
+    }));
+  }
+  LSOP_HIP(hipMemcpyAsync(Qout, Yin, sizeof(Cx<T>) * (size_t)r * n, hipMemcpyDeviceToDevice, s));
+  return LSOP_OK;
+}
+
+// In-place inverse of the m x m diagonal block at offset o of each of cnt
+// FP64 leaf matrices (leading dimension and batch stride nl, nl^2) by the
+// 2 x 2 block formula of Section 2.4: with X = A^{-1} and S = D - C X B,
+//   [[A, B], [C, D]]^{-1} = [[X + X B S^{-1} C X, -X B S^{-1}], [-S^{-1} C X, S^{-1}]],
+// recursing on A and S down to 64 x 64 blocks (Gauss-Jordan with pivoting).
+int hodlr_block_inverse(lsop_precond* pc, Cx<double>* M, int nl, int cnt, size_t o, int m, int depth,
+                        const std::vector<size_t>& toff, hipStream_t s) {
+  const size_t ld = nl, st = (size_t)nl * nl;
+  if (m <= 64) {
+    LSOP_HIP(prof("hodlr_leaf_base_inv", 0.0, 8.0 * m * m * (double)m * cnt, cnt, s, [&] {
+      return launch_lu_inverse(M + o, ld, st, M + o, ld, st, nullptr, m, true, pc->hflag, cnt, s);
+    }));
+    return LSOP_OK;
+  }
+  const int h = m / 2, h2 = m - h;
+  const size_t A = o, B = o + h, C = o + (size_t)h * ld, D = C + h;
+  Cx<double>* T1 = pc->lwork + toff[depth];                       // h x h2
+  Cx<double>* T2 = T1 + (size_t)cnt * h * h2;                      // h2 x h
+  const size_t s1 = (size_t)h * h2;
+  int rc = hodlr_block_inverse(pc, M, nl, cnt, A, h, depth + 1, toff, s);
+  if (rc) return rc;
+  auto gemm = [&](const Cx<double>* a, size_t lda, size_t sa, const Cx<double>* b, size_t ldb, size_t sb,
+                  Cx<double>* c, size_t ldc, size_t sc, int mm, int nn, int kk, double alpha, double beta) {
+    return prof("hodlr_leaf_gemm", 0.0, 8.0 * mm * nn * (double)kk * cnt, cnt, s, [&] {
+      return launch_bgemm<double>(a, lda, sa, b, ldb, sb, c, ldc, sc, nullptr, nullptr, mm, nn, kk, alpha, beta, cnt,
+                                  s);
+    });
+  };
+  LSOP_HIP(gemm(M + A, ld, st, M + B, ld, st, T1, h2, s1, h, h2, h, 1.0, 0.0));      // T1 = X B
+  LSOP_HIP(gemm(M + C, ld, st, T1, h2, s1, M + D, ld, st, h2, h2, h, -1.0, 1.0));    // D <- S = D - C X B
+  rc = hodlr_block_inverse(pc, M, nl, cnt, D, h2, depth + 1, toff, s);              // D <- S^{-1}
+  if (rc) return rc;
+  LSOP_HIP(gemm(M + C, ld, st, M + A, ld, st, T2, h, s1, h2, h, h, 1.0, 0.0));      // T2 = C X
+  LSOP_HIP(gemm(T1, h2, s1, M + D, ld, st, M + B, ld, st, h, h2, h2, -1.0, 0.0));   // B <- -X B S^{-1}
+  LSOP_HIP(gemm(M + B, ld, st, T2, h, s1, M + A, ld, st, h, h, h2, -1.0, 1.0));     // A <- X + X B S^{-1} C X
+  LSOP_HIP(gemm(M + D, ld, st, T2, h, s1, M + C, ld, st, h2, h, h2, -1.0, 0.0));    // C <- -S^{-1} C X
+  return LSOP_OK;
+}
+
+// temporaries of each recursion depth after the cnt leaf matrices
+std::vector<size_t> hodlr_temp_offsets(int nl, int cnt, size_t* total) {
+  std::vector<size_t> off;
+  size_t at = (size_t)cnt * nl * nl;
+  for (int m = nl; m > 64; m = (m + 1) / 2) {
+    off.push_back(at);
+    const size_t h2 = (size_t)(m - m / 2);
+    at += 2 * (size_t)cnt * h2 * h2;
+  }
+  off.push_back(at);
+  *total = at;
+  return off;
+}
+
+template <typename T>
+int hodlr_leaves(lsop_precond* pc, hipStream_t s) {
+  lsop_op* op = pc->op;
+  const int nl = pc->leaf_w * op->nz;
+  Cx<T>* dinv = reinterpret_cast<Cx<T>*>(pc->dinv);
+  for (int l0 = 0; l0 < pc->nleaf; l0 += pc->leaf_chunk) {
+    const int cnt = std::min(pc->leaf_chunk, pc->nleaf - l0);
+    size_t total = 0;
+    const std::vector<size_t> toff = hodlr_temp_offsets(nl, cnt, &total);
+    LSOP_HIP(hipMemsetAsync(pc->hflag, 0, sizeof(int) * cnt, s));
+    LSOP_HIP(launch_leaf_form(op->ktab, op->chi64, pc->lwork, op->nz, nl, l0, cnt, s));
+    int rc = hodlr_block_inverse(pc, pc->lwork, nl, cnt, 0, nl, 0, toff, s);
+    if (rc) return rc;
+    std::vector<int> flags(cnt, 0);
+    LSOP_HIP(hipMemcpyAsync(flags.data(), pc->hflag, sizeof(int) * cnt, hipMemcpyDeviceToHost, s));
+    LSOP_HIP(hipStreamSynchronize(s));
+    for (int f : flags)
+      if (f) return fail(LSOP_ESINGULAR, "a HODLR leaf block is numerically singular");
+    LSOP_HIP(launch_transpose_convert<T>(pc->lwork, dinv + (size_t)l0 * nl * nl, nl, cnt, s));
+  }
+  return LSOP_OK;
+}
+
+// y = A_upto^{-1} x for nvec vectors: x rows through xidx, y rows through yidx
+// (NULL: consecutive).  upto = 0 is the full preconditioner.
+template <typename T>
+int hodlr_apply(lsop_precond* pc, const Cx<T>* x, const int* xidx, Cx<T>* y, const int* yidx, int nvec, int upto,
+                hipStream_t s) {
+  lsop_op* op = pc->op;
+  const size_t n = op->n();
+  const int r = pc->rank, nl = pc->leaf_w * op->nz;
+  const Cx<T>* dinv = reinterpret_cast<const Cx<T>*>(pc->dinv);
+  const double e = sizeof(Cx<T>);
+  for (int c = 0; c < nvec; c += pc->tcap) {
+    const int m = std::min(pc->tcap, nvec - c);
+    const int* xc = xidx ? xidx + c : nullptr;
+    const int* yc = yidx ? yidx + c : nullptr;
+    const Cx<T>* xb = xidx ? x : x + (size_t)c * n;
+    Cx<T>* yb = yidx ? y : y + (size_t)c * n;
+    // leaves: y_k = D_k^{-1} x_k (D_k^{-1} stored transposed: y = x D^{-T})
+    LSOP_HIP(prof("hodlr_leaf_apply", (double)pc->nleaf * nl * nl * e + 2.0 * m * (double)n * e,
+                  8.0 * m * (double)nl * n, m, s, [&] {
+                    return launch_bgemm<T>(xb, n, nl, dinv, nl, (size_t)nl * nl, yb, n, nl, xc, yc, m, nl, nl, 1.0,
+                                           0.0, pc->nleaf, s);
+                  }));
+    for (int lv = pc->levels - 1; lv >= upto; --lv) {
+      const hodlr_level& L = pc->lev[lv];
+      const int nodes = op->nx / L.width, nseg = 2 * nodes;
+      const size_t seg = (size_t)(L.width / 2) * op->nz;
+      const int ksub = hodlr_ksub(pc, seg, nseg);
+      const Cx<T>* V = reinterpret_cast<const Cx<T>*>(L.V);
+      const Cx<T>* Wp = reinterpret_cast<const Cx<T>*>(L.Wp);
+      LSOP_HIP(prof("hodlr_gemm_ah_b", (double)(r + m) * n * e, 8.0 * r * m * (double)n, m, s, [&] {
+        return launch_gemm_ah_b_seg<T>(V, r, yb, yc, m, n, seg, pc->hG, pc->part, ksub, s);
+      }));
+      LSOP_HIP(launch_small_gemm(L.kinv, pc->hG, pc->hX, 2 * r, m, 1.0, s, nodes));
+      LSOP_HIP(prof("hodlr_gemm_update", (double)r * n * e + 2.0 * m * (double)n * e, 8.0 * r * m * (double)n, m, s,
+                    [&] {
+                      return launch_gemm_update_seg<T>(Wp, r, pc->hX, (size_t)r * m, m, yb, nullptr, 0.0, yb, yc, n,
+                                                       seg, s);
+                    }));
+    }
+  }
+  return LSOP_OK;
+}
+
+template <typename T>
+int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
+  lsop_op* op = pc->op;
+  const int r = pc->rank;
+  const size_t n = op->n();
+  Cx<T>* Y = reinterpret_cast<Cx<T>*>(pc->Y);
+  Cx<T>* Q = reinterpret_cast<Cx<T>*>(pc->U);
+  // sub-domain spectra (depend on k0 and h)
+  for (int lv = 0; lv < pc->levels; ++lv) {
+    hodlr_level& L = pc->lev[lv];
+    const size_t s1 = sizeof(Cx<double>) * (size_t)(2 * L.lx) * op->pz();
+    int st = grow_scratch(op, s1);
+    if (st) return st;
+    LSOP_HIP(launch_spectrum(L.lx, op->lz, op->ktab, L.width, op->nz, reinterpret_cast<Cx<double>*>(op->scratch),
+                             L.gs64, L.gs32, L.tw64, op->tw2z64, s));
+  }
+  int st = hodlr_leaves<T>(pc, s);
+  if (st) return st;
+  for (int lv = pc->levels - 1; lv >= 0; --lv) {
+    hodlr_level& L = pc->lev[lv];
+    const int nodes = op->nx / L.width, nseg = 2 * nodes;
+    const size_t seg = (size_t)(L.width / 2) * op->nz;
+    Cx<T>* V = reinterpret_cast<Cx<T>*>(L.V);
+    Cx<T>* Wp = reinterpret_cast<Cx<T>*>(L.Wp);
+    // Alg. 1 step 1: Gaussian probes of this level
+    if (omega) LSOP_HIP(launch_real_to_complex<T>(omega + (size_t)lv * r * n, Y, (size_t)r * n, s));
+    else LSOP_HIP(launch_philox_normal<T>(Y, r, n, pc->seed, s, lv * r));
+    // step 2: samples of both off-diagonal blocks of every node, G0 V[I1, I2] Om
+    // on the I1 cells and G0 V[I2, I1] Om on the I2 cells
+    if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 1, 0, s))) return st;
+    if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 0, 1, s))) return st;
+    // step 3: orthonormal bases per half-node (result in Y)
+    if ((st = hodlr_orth<T>(pc, lv, Q, Y, s))) return st;
+    // right factors v12 = (G0 V[I1, I2])^H Q12 on I2, v21 on I1
+    if ((st = hodlr_subconv<T>(pc, lv, true, Y, V, r, 0, 1, s))) return st;
+    if ((st = hodlr_subconv<T>(pc, lv, true, Y, V, r, 1, 0, s))) return st;
+    // Wp = A_{lv+1}^{-1} Ut
+    if ((st = hodlr_apply<T>(pc, Y, nullptr, Wp, nullptr, r, lv + 1, s))) return st;
+    // K per node from the per-half products V^H Wp; kinv = (P K)^{-1}
+    const int ksub = hodlr_ksub(pc, seg, nseg);
+    LSOP_HIP(launch_gemm_ah_b_seg<T>(V, r, Wp, nullptr, r, n, seg, pc->hG, pc->part, ksub, s));
+    LSOP_HIP(launch_pk_assemble(pc->hG, pc->hK, r, nodes, s));
+    LSOP_HIP(hipMemsetAsync(pc->hflag, 0, sizeof(int) * nodes, s));
+    const size_t m2 = (size_t)4 * r * r;
+    LSOP_HIP(prof("hodlr_core_inv", 0.0, 64.0 * r * r * (double)r * nodes, nodes, s, [&] {
+      return launch_lu_inverse(pc->hK, 2 * r, m2, L.kinv, 2 * r, m2, pc->hK + m2 * nodes, 2 * r, true, pc->hflag,
+                               nodes, s);
+    }));
+    std::vector<int> flags(nodes, 0);
+    LSOP_HIP(hipMemcpyAsync(flags.data(), pc->hflag, sizeof(int) * nodes, hipMemcpyDeviceToHost, s));
+    LSOP_HIP(hipStreamSynchronize(s));
+    for (int f : flags)
+      if (f) return fail(LSOP_ESINGULAR, "a HODLR Woodbury core is numerically singular");
+  }
+  pc->kept = r;
+  pc->built = true;
   return LSOP_OK;
 }
 
@@ -635,9 +925,17 @@ int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out
   if (!out) return fail(LSOP_EINVAL, "null output handle");
   *out = nullptr;
   if (!op || !p) return fail(LSOP_EINVAL, "null argument");
-  if (p->kind != LSOP_PC_IDENTITY && p->kind != LSOP_PC_LOWRANK) return fail(LSOP_EINVAL, "bad preconditioner kind");
-  if (p->kind == LSOP_PC_LOWRANK && (p->rank < 1 || p->rank > 256 || p->power_iters < 0))
+  if (p->kind != LSOP_PC_IDENTITY && p->kind != LSOP_PC_LOWRANK && p->kind != LSOP_PC_HODLR)
+    return fail(LSOP_EINVAL, "bad preconditioner kind");
+  if (p->kind != LSOP_PC_IDENTITY && (p->rank < 1 || p->rank > 256 || p->power_iters < 0))
     return fail(LSOP_EINVAL, "rank must be in [1, 256] and power_iters >= 0");
+  if (p->kind == LSOP_PC_HODLR) {
+    if (p->levels < 1 || p->levels > 16 || op->nx % (1 << p->levels) != 0)
+      return fail(LSOP_EINVAL, "HODLR levels must be >= 1 with nx divisible by 2^levels");
+    const size_t nl = (size_t)(op->nx >> p->levels) * op->nz;
+    if (nl % 64 != 0 || nl > 8192)
+      return fail(LSOP_EINVAL, "HODLR leaf size (nx / 2^levels) * nz must be a multiple of 64 and at most 8192");
+  }
   lsop_precond* pc = new lsop_precond();
   pc->op = op;
   pc->kind = p->kind;
@@ -659,18 +957,76 @@ int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out
   int st = 0;
   auto& o = pc->owned;
   auto& b = pc->bytes;
-  st |= dev_alloc(o, b, &pc->U, esz * r * n);
-  st |= dev_alloc(o, b, &pc->W, esz * r * n);
-  st |= dev_alloc(o, b, &pc->Y, esz * r * n);
-  st |= dev_alloc(o, b, &pc->Z, sizeof(Cx<double>) * r * r);
-  // small: G / M (r*r), X / LU work (2 r*r), T1, T2 (r * tcap each)
-  st |= dev_alloc(o, b, &pc->small, sizeof(Cx<double>) * ((size_t)3 * r * r + (size_t)2 * r * pc->tcap));
-  st |= dev_alloc(o, b, &pc->part, sizeof(Cx<double>) * (size_t)pc->ksplit * r * pc->tcap);
-  st |= dev_alloc(o, b, &pc->dflag, 256);
+  if (p->kind == LSOP_PC_LOWRANK) {
+    st |= dev_alloc(o, b, &pc->U, esz * r * n);
+    st |= dev_alloc(o, b, &pc->W, esz * r * n);
+    st |= dev_alloc(o, b, &pc->Y, esz * r * n);
+    st |= dev_alloc(o, b, &pc->Z, sizeof(Cx<double>) * r * r);
+    // small: G / M (r*r), X / LU work (2 r*r), T1, T2 (r * tcap each)
+    st |= dev_alloc(o, b, &pc->small, sizeof(Cx<double>) * ((size_t)3 * r * r + (size_t)2 * r * pc->tcap));
+    st |= dev_alloc(o, b, &pc->part, sizeof(Cx<double>) * (size_t)pc->ksplit * r * pc->tcap);
+    st |= dev_alloc(o, b, &pc->dflag, 256);
+  } else {
+    // HODLR
+    pc->levels = p->levels;
+    pc->leaf_w = op->nx >> p->levels;
+    pc->nleaf = 1 << p->levels;
+    const int nl = pc->leaf_w * op->nz;
+    pc->maxseg = pc->nleaf;
+    pc->ksub_cap = std::max(512, pc->maxseg);
+    // FP64 leaf workspace: up to 2 GiB of leaf matrices per chunk plus the recursion temporaries
+    const size_t per_leaf = (size_t)nl * nl * sizeof(Cx<double>);
+    pc->leaf_chunk = (int)std::max<size_t>(1, std::min<size_t>(pc->nleaf, ((size_t)2 << 30) / per_leaf));
+    if (const char* lc = getenv("LSOP_HODLR_LEAF_CHUNK"))  // smaller chunks (exercises the chunked leaf build)
+      pc->leaf_chunk = std::max(1, std::min(pc->leaf_chunk, atoi(lc)));
+    size_t lw = 0;
+    (void)hodlr_temp_offsets(nl, pc->leaf_chunk, &lw);
+    pc->lwork_elems = lw;
+    st |= dev_alloc(o, b, &pc->lwork, sizeof(Cx<double>) * lw);
+    st |= dev_alloc(o, b, &pc->dinv, esz * (size_t)pc->nleaf * nl * nl);
+    st |= dev_alloc(o, b, &pc->U, esz * r * n);
+    st |= dev_alloc(o, b, &pc->Y, esz * r * n);
+    st |= dev_alloc(o, b, &pc->hy, esz * (size_t)pc->tcap * n);
+    const size_t small = (size_t)pc->maxseg * r * pc->tcap;
+    st |= dev_alloc(o, b, &pc->hG, sizeof(Cx<double>) * small);
+    st |= dev_alloc(o, b, &pc->hX, sizeof(Cx<double>) * small);
+    // node cores (2r x 2r) and, for 2r > 64, the Gauss-Jordan work (2 (2r)^2 each)
+    st |= dev_alloc(o, b, &pc->hK, sizeof(Cx<double>) * (size_t)(pc->maxseg / 2) * 4 * r * r * 3);
+    st |= dev_alloc(o, b, &pc->part, sizeof(Cx<double>) * (size_t)pc->ksub_cap * r * pc->tcap);
+    st |= dev_alloc(o, b, &pc->hflag, sizeof(int) * std::max(pc->maxseg, pc->leaf_chunk));
+    pc->lev.resize(p->levels);
+    for (int lv = 0; lv < p->levels && !st; ++lv) {
+      hodlr_level& L = pc->lev[lv];
+      L.width = op->nx >> lv;
+      L.lx = fft_length_sub(L.width);
+      if (L.lx < 0) {
+        st = LSOP_EUNSUPPORTED;
+        break;
+      }
+      const int nodes = 1 << lv;
+      st |= dev_alloc(o, b, &L.V, esz * r * n);
+      st |= dev_alloc(o, b, &L.Wp, esz * r * n);
+      st |= dev_alloc(o, b, &L.kinv, sizeof(Cx<double>) * (size_t)nodes * 4 * r * r);
+      const size_t gsz = (size_t)2 * op->pz() * L.lx;
+      if (pc->dt == LSOP_C128) st |= dev_alloc(o, b, &L.gs64, sizeof(Cx<double>) * gsz);
+      else st |= dev_alloc(o, b, &L.gs32, sizeof(Cx<float>) * gsz);
+      st |= dev_alloc(o, b, &L.tw64, sizeof(Cx<double>) * 2 * L.lx);
+      st |= dev_alloc(o, b, &L.tw32, sizeof(Cx<float>) * 2 * L.lx);
+      if (!st) {
+        std::vector<Cx<double>> w = twiddles(L.lx);
+        std::vector<Cx<float>> w32(w.size());
+        for (size_t t = 0; t < w.size(); ++t) w32[t] = ccast<float>(w[t]);
+        if (hipMemcpy(L.tw64, w.data(), sizeof(Cx<double>) * w.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(L.tw32, w32.data(), sizeof(Cx<float>) * w32.size(), hipMemcpyHostToDevice) != hipSuccess)
+          st = LSOP_EHIP;
+      }
+    }
+  }
   if (st) {
     free_all(pc->owned);
     delete pc;
-    return LSOP_ENOMEM;
+    return st == LSOP_EUNSUPPORTED ? fail(st, "unsupported HODLR level width")
+                                   : (st == LSOP_EHIP ? fail(st, "twiddle upload failed") : LSOP_ENOMEM);
   }
   *out = pc;
   return LSOP_OK;
@@ -682,6 +1038,10 @@ int precond_build(lsop_precond* pc, const void* omega_dev, void* stream) {
   if (st) return st;
   if (pc->kind == LSOP_PC_IDENTITY) return LSOP_OK;
   pc->built = false;
+  if (pc->kind == LSOP_PC_HODLR) {
+    if (pc->dt == LSOP_C128) return hodlr_build<double>(pc, (const double*)omega_dev, S(stream));
+    return hodlr_build<float>(pc, (const double*)omega_dev, S(stream));
+  }
   if (pc->dt == LSOP_C128) return build_impl<double>(pc, (const double*)omega_dev, S(stream));
   return build_impl<float>(pc, (const double*)omega_dev, S(stream));
 }
@@ -699,7 +1059,15 @@ int precond_info(const lsop_precond* pc, int* rank, double* compression, size_t*
   if (!pc) return fail(LSOP_EINVAL, "null preconditioner");
   const int r = pc->kind == LSOP_PC_IDENTITY ? 0 : pc->kept;
   if (rank) *rank = r;
-  if (compression) *compression = 2.0 * r / (double)pc->op->n();
+  const double n = (double)pc->op->n();
+  if (compression) {
+    if (pc->kind == LSOP_PC_HODLR) {
+      const double nl = (double)pc->leaf_w * pc->op->nz;
+      *compression = (pc->nleaf * nl * nl + 2.0 * pc->levels * pc->rank * n) / (n * n);
+    } else {
+      *compression = 2.0 * r / n;
+    }
+  }
   if (bytes) *bytes = pc->bytes;
   return LSOP_OK;
 }
@@ -722,7 +1090,7 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
   if (p->init < 0 || p->init > 2) return fail(LSOP_EINVAL, "bad init");
   if (pc && pc->op != op) return fail(LSOP_EINVAL, "preconditioner belongs to another operator");
   if (pc && !pc->built) return fail(LSOP_EINVAL, "preconditioner not built");
-  lsop_precond* pcu = (pc && pc->kind == LSOP_PC_LOWRANK) ? pc : nullptr;
+  lsop_precond* pcu = (pc && pc->kind != LSOP_PC_IDENTITY) ? pc : nullptr;
   hipStream_t s = S(stream);
   const size_t n = op->n();
   for (int v = 0; v < nvec; ++v) info[v] = lsop_solve_info{0, 0, INFINITY, LSOP_NOT_CONVERGED, INFINITY};

@@ -30,6 +30,11 @@ struct FftPlan;
     static constexpr int NST = sizeof(R) / sizeof(int);              \
     static constexpr int E = Lv / Gv;                                \
   };
+// short lengths: the x-transforms of narrow sub-domains (hierarchical build)
+LSOP_FFT_PLAN(2, 1, 2)
+LSOP_FFT_PLAN(4, 1, 4)
+LSOP_FFT_PLAN(8, 1, 8)
+LSOP_FFT_PLAN(16, 4, 4, 4)
 LSOP_FFT_PLAN(32, 8, 4, 2, 4)
 LSOP_FFT_PLAN(64, 8, 8, 8)
 LSOP_FFT_PLAN(96, 8, 4, 3, 2, 4)

@@ -14,6 +14,8 @@ namespace lsop {
 
 // Supported FFT lengths (each padded axis is 2 L >= 2 N).
 int fft_length_for(int n);
+// Also the short x-lengths 2, 4, 8, 16 of narrow sub-domains.
+int fft_length_sub(int n);
 
 // Error reporting (per thread).
 void set_error(const std::string& msg);
@@ -29,18 +31,23 @@ int fail(int status, const std::string& msg);
 // ----------------------------------------------------------------- FFT path
 // All launchers take the stream and return hipError_t of the launch.
 // T = float or double.
+// Sub-domain batches (nodes > 1): each stored vector holds `nodes` strips of nx
+// rows, transformed independently (slot = vector * nodes + node, chi sliced per
+// strip); rows outside [lo, hi) of a strip are read as zero (hi < 0: nx).
 template <typename T>
 hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, const int* vidx, int nx, int nz,
-                           int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s);
+                           int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s, int nodes = 1, int lo = 0,
+                           int hi = -1);
 // tile: columns per workgroup (0 = widest that fits; narrower tiles allow more workgroups per CU)
 template <typename T>
 hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int nslots, bool adj, const Cx<T>* tw2,
                        hipStream_t s, int tile = 0);
 // epi: 0 y = x - c, 1 y = c, 2 y = x - chi c, 3 y = chi c; rhs != NULL: y -= rhs and rnorm[slot] += |y|^2
+// Sub-domain batches as in pass 1; rows outside [lo, hi) of a strip are not written.
 template <typename T>
 hipError_t launch_rows_inv(int L, const Cx<T>* tmp, const Cx<T>* x, const T* chi, const Cx<T>* rhs, Cx<T>* y,
                            double* rnorm, const int* vidx, int nx, int nz, int nslots, int epi, const Cx<T>* tw2,
-                           hipStream_t s);
+                           hipStream_t s, int nodes = 1, int lo = 0, int hi = -1);
 // spectrum of the circulant-extended kernel table (FP64), written as gs[2][pz][lx] in T
 hipError_t launch_spectrum(int lx, int lz, const Cx<double>* ktab, int nx, int nz, Cx<double>* s1t,
                            Cx<double>* gs64, Cx<float>* gs32, const Cx<double>* tw2x, const Cx<double>* tw2z,
@@ -69,27 +76,60 @@ hipError_t launch_accumulate(const Cx<T>* x, Cx<double>* y, double alpha, const 
 // real FP64 probes [l][n] -> complex T
 template <typename T>
 hipError_t launch_real_to_complex(const double* in, Cx<T>* out, size_t count, hipStream_t s);
+// probes k0 .. k0 + nvec - 1 of the Philox stream with key `seed`
 template <typename T>
-hipError_t launch_philox_normal(Cx<T>* out, int nvec, size_t n, uint64_t seed, hipStream_t s);
+hipError_t launch_philox_normal(Cx<T>* out, int nvec, size_t n, uint64_t seed, hipStream_t s, int k0 = 0);
 
 // C[a][b] = sum_k conj(A[a][k]) B[vb][k], FP64 result (na x nb, ldc = nb).  B vectors through vidx.
 // part: workspace for split-K partials (ksplit * na * nb complex doubles).
 template <typename T>
 hipError_t launch_gemm_ah_b(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n,
                             Cx<double>* C, Cx<double>* part, int ksplit, hipStream_t s);
+// Segmented form: one na x nb result per segment of `seg` elements of k, at
+// C + sg * na * nb; each segment split into ksub partial chunks (part holds
+// nseg * ksub * na * nb complex doubles).
+template <typename T>
+hipError_t launch_gemm_ah_b_seg(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n, size_t seg,
+                                Cx<double>* C, Cx<double>* part, int ksub, hipStream_t s);
 // Y[vy(b)][k] = X1[vy(b)][k] + beta * X2[vy(b)][k] + sum_a A[a][k] M[a][b]   (M FP64, na x nb)
 // X1 / X2 may be NULL (treated as 0).
 template <typename T>
 hipError_t launch_gemm_update(const Cx<T>* A, int na, const Cx<double>* M, int nb, const Cx<T>* X1,
                               const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n, hipStream_t s);
-// small FP64 dense kernels (one workgroup)
-hipError_t launch_gram_orth(const Cx<double>* G, Cx<double>* X, int na, double drop_tol, int* kept,
-                            hipStream_t s);
+// Segmented form: element k uses M + (k / seg) * mstride; seg must be a multiple of 64.
+template <typename T>
+hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<double>* M, size_t mstride, int nb,
+                                  const Cx<T>* X1, const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n,
+                                  size_t seg, hipStream_t s);
+// small FP64 dense kernels (one workgroup per batch entry, entries na * na apart)
+hipError_t launch_gram_orth(const Cx<double>* G, Cx<double>* X, int na, double drop_tol, int* kept, hipStream_t s,
+                            int batch = 1);
+// Z_b = (I - M_b)^{-1} (plain = false) or M_b^{-1} (plain = true); M_b = M + b * sm (leading dimension ldm),
+// Z_b likewise (may alias M_b); work: batch * 2 na^2 complex doubles when na > 64; singular[b] set to 1 on
+// failure (the caller clears it).
+hipError_t launch_lu_inverse(const Cx<double>* M, size_t ldm, size_t sm, Cx<double>* Z, size_t ldz, size_t sz,
+                             Cx<double>* work, int na, bool plain, int* singular, int batch, hipStream_t s);
 hipError_t launch_lu_inverse_i_minus(const Cx<double>* M, Cx<double>* Z, Cx<double>* work, int na, int* singular,
                                      hipStream_t s);
-// C = alpha * A (na x na) * B (na x nb)
+// C_b = alpha * A_b (na x na) * B_b (na x nb)
 hipError_t launch_small_gemm(const Cx<double>* A, const Cx<double>* B, Cx<double>* C, int na, int nb, double alpha,
-                             hipStream_t s);
+                             hipStream_t s, int batch = 1);
+// HODLR: dense leaf blocks of I - G0 V (FP64), leaves leaf0 .. leaf0 + nleaf - 1 of nl cells
+hipError_t launch_leaf_form(const Cx<double>* ktab, const double* chi, Cx<double>* out, int nz, int nl, int leaf0,
+                            int nleaf, hipStream_t s);
+// out_b = transpose(in_b) converted to T (m x m each)
+template <typename T>
+hipError_t launch_transpose_convert(const Cx<double>* in, Cx<T>* out, int m, int batch, hipStream_t s);
+// node couplings [[-G_2k, I], [I, -G_2k+1]] from per-half inner products G (r x r each)
+hipError_t launch_pk_assemble(const Cx<double>* G, Cx<double>* out, int r, int nodes, hipStream_t s);
+// batched complex GEMM C_b = alpha A_b B_b + beta C_b (rows of A / C through mapa / mapc when given)
+template <typename T>
+hipError_t launch_bgemm(const Cx<T>* A, size_t lda, size_t sA, const Cx<T>* B, size_t ldb, size_t sB, Cx<T>* C,
+                        size_t ldc, size_t sC, const int* mapa, const int* mapc, int M, int N, int K, double alpha,
+                        double beta, int batch, hipStream_t s);
+// y[yidx[v]] += a * x[v] for v < nvec (x compact)
+template <typename T>
+hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, int nvec, size_t n, hipStream_t s);
 
 }  // namespace lsop
 
@@ -124,9 +164,32 @@ struct lsop_op {
   std::vector<void*> owned;
 };
 
+// One level of the HODLR preconditioner (nodes of `width` grid columns).
+struct hodlr_level {
+  int width = 0, lx = 0;                  // node width and its x-FFT length
+  void* V = nullptr;                      // [rank][n] packed right factors (per half-node)
+  void* Wp = nullptr;                     // [rank][n] A_{l+1}^{-1} U, packed
+  Cx<double>* kinv = nullptr;             // [nodes][2 rank][2 rank] (P K)^{-1}
+  Cx<double>* gs64 = nullptr;             // sub-domain spectrum [2][pz][lx]
+  Cx<float>* gs32 = nullptr;
+  Cx<double>* tw64 = nullptr;             // x twiddles w_{2 lx}
+  Cx<float>* tw32 = nullptr;
+};
+
 struct lsop_precond {
   lsop_op* op = nullptr;
   int kind = 0, rank = 0, q = 0, kept = 0;
+  // HODLR (kind LSOP_PC_HODLR)
+  int levels = 0, leaf_w = 0, nleaf = 0, leaf_chunk = 0;
+  std::vector<hodlr_level> lev;
+  void* dinv = nullptr;                   // [nleaf][nl][nl] transposed leaf inverses
+  Cx<double>* lwork = nullptr;            // FP64 leaf workspace (leaf_chunk matrices + recursion temporaries)
+  size_t lwork_elems = 0;
+  void* hy = nullptr;                     // [tcap][n] apply / series temporary
+  Cx<double>*hG = nullptr, *hX = nullptr;  // per-segment products [maxseg][rank][tcap]
+  Cx<double>* hK = nullptr;               // node cores and their Gauss-Jordan work
+  int* hflag = nullptr;                   // per-node / per-segment flags
+  int maxseg = 0, ksub_cap = 0;
   uint64_t seed = 0;
   int dt = 0;              // storage dtype of U, W (LSOP_C64 or LSOP_C128)
   void* U = nullptr;       // [rank][n]

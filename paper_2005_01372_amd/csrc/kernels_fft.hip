@@ -30,6 +30,13 @@ int fft_length_for(int n) {
   return -1;
 }
 
+int fft_length_sub(int n) {
+  static const int lens[] = {2, 4, 8, 16};
+  for (int L : lens)
+    if (L >= n) return L;
+  return fft_length_for(n);
+}
+
 // Threads per workgroup of the row kernels: 256 unless the groups' two
 // exchange buffers plus the twiddle table would not fit in 144 KiB of LDS.
 template <typename T, int L>
@@ -46,13 +53,19 @@ constexpr int rows_threads() {
 // One group per row; the even and odd halves are transformed together
 // (fft2_regs), and the next row's input is prefetched into registers while
 // the current row is transformed.
+//
+// Sub-domain batches: with nodes > 1 every stored vector of nodes * nx rows is
+// treated as `nodes` independent nx-row strips (slot = vector * nodes + node),
+// each with its own slice of chi; rows i outside [lo, hi) of a strip read as
+// zero (pass 1) or are not written (pass 3).
 template <typename T, int L>
 __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>* __restrict__ x,
                                                                      const T* __restrict__ chi,
                                                                      Cx<T>* __restrict__ tmp,
                                                                      const int* __restrict__ vidx, int nx, int nz,
                                                                      int nitems, int mulchi,
-                                                                     const Cx<T>* __restrict__ tw2) {
+                                                                     const Cx<T>* __restrict__ tw2, int nodes, int lo,
+                                                                     int hi) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
   __shared__ Cx<T> sbuf[GPW][2][lds_len<L>()];
@@ -60,7 +73,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
   stage_twiddles<T, L>(stw, tw2);
   __syncthreads();
   const int grp = threadIdx.x / G, g = threadIdx.x % G;
-  const size_t vstride = (size_t)nx * nz;
+  const size_t vstride = (size_t)nodes * nx * nz;
   const int step = gridDim.x * GPW;
   Cx<T> px[E];
   T pc[E];
@@ -68,14 +81,17 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
     const int item = base + grp;
     const int it = item < nitems ? item : nitems - 1;
     const int slot = it / nx, i = it % nx;
-    const int vi = vidx ? vidx[slot] : slot;
-    const Cx<T>* xr = x + (size_t)vi * vstride + (size_t)i * nz;
-    const T* cr = chi + (size_t)i * nz;
+    const int node = slot % nodes, vs = slot / nodes;
+    const int vi = vidx ? vidx[vs] : vs;
+    const size_t row = (size_t)node * nx + i;
+    const Cx<T>* xr = x + (size_t)vi * vstride + row * nz;
+    const T* cr = chi + row * nz;
+    const bool in = i >= lo && i < hi;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int p = fft_elem<L>(g, e);
-      px[e] = p < nz ? xr[p] : czero<T>();
-      pc[e] = (mulchi && p < nz) ? cr[p] : T(1);
+      px[e] = (in && p < nz) ? xr[p] : czero<T>();
+      pc[e] = (mulchi && in && p < nz) ? cr[p] : T(1);
     }
   };
   int base = blockIdx.x * GPW;
@@ -199,7 +215,8 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
                                                                      Cx<T>* y, double* __restrict__ rnorm,
                                                                      const int* __restrict__ vidx, int nx, int nz,
                                                                      int nitems, int epi,
-                                                                     const Cx<T>* __restrict__ tw2) {
+                                                                     const Cx<T>* __restrict__ tw2, int nodes, int lo,
+                                                                     int hi) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
   __shared__ Cx<T> sbuf[GPW][2][lds_len<L>()];
@@ -207,13 +224,15 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
   stage_twiddles<T, L>(stw, tw2);
   __syncthreads();
   const int grp = threadIdx.x / G, g = threadIdx.x % G;
-  const size_t vstride = (size_t)nx * nz;
+  const size_t vstride = (size_t)nodes * nx * nz;
   for (int base = blockIdx.x * GPW; base < nitems; base += gridDim.x * GPW) {
     const int item = base + grp;
-    const bool valid = item < nitems;
-    const int it = valid ? item : nitems - 1;
+    const int it = item < nitems ? item : nitems - 1;
     const int slot = it / nx, i = it % nx;
-    const int vi = vidx ? vidx[slot] : slot;
+    const bool valid = item < nitems && i >= lo && i < hi;
+    const int node = slot % nodes, vs = slot / nodes;
+    const int vi = vidx ? vidx[vs] : vs;
+    const size_t row = (size_t)node * nx + i;
     const Cx<T>* tr = tmp + ((size_t)slot * nx + i) * (2 * L);
     Cx<T> acc[E], v[E];
 #pragma unroll
@@ -223,7 +242,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
       v[e] = tr[L + p];
     }
     fft2_regs<T, L, true>(acc, v, g, sbuf[grp][0], sbuf[grp][1], stw);
-    const size_t off = (size_t)vi * vstride + (size_t)i * nz;
+    const size_t off = (size_t)vi * vstride + row * nz;
     double nrm = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -234,8 +253,8 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
         switch (epi) {
           case 0: out = x[off + p] - conv; break;
           case 1: out = conv; break;
-          case 2: out = x[off + p] - chi[(size_t)i * nz + p] * conv; break;
-          default: out = chi[(size_t)i * nz + p] * conv; break;
+          case 2: out = x[off + p] - chi[row * nz + p] * conv; break;
+          default: out = chi[row * nz + p] * conv; break;
         }
         if (rhs) {
           out = out - rhs[off + p];
@@ -414,15 +433,27 @@ int grid_for_rows(int nitems, int gpw) {
     default: return hipErrorInvalidValue;                      \
   }
 
+// x-direction lengths also include the short sub-domain transforms
+#define LSOP_DISPATCH_LX(L, ...)                           \
+  switch (L) {                                             \
+    case 2: { constexpr int LL = 2; __VA_ARGS__; } break;   \
+    case 4: { constexpr int LL = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int LL = 8; __VA_ARGS__; } break;   \
+    case 16: { constexpr int LL = 16; __VA_ARGS__; } break; \
+    default: LSOP_DISPATCH_L(L, __VA_ARGS__);              \
+  }
+
 template <typename T>
 hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, const int* vidx, int nx, int nz,
-                           int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s) {
+                           int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s, int nodes, int lo, int hi) {
   const int nitems = nslots * nx;
   if (nitems <= 0) return hipSuccess;
+  if (nodes < 1 || nslots % nodes != 0) return hipErrorInvalidValue;
+  if (hi < 0) hi = nx;
   LSOP_DISPATCH_L(L, {
     constexpr int NT = rows_threads<T, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_rows_fwd<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(NT), 0, s, x, chi, tmp, vidx,
-                       nx, nz, nitems, (int)mulchi, tw2);
+                       nx, nz, nitems, (int)mulchi, tw2, nodes, lo, hi);
   });
   return hipGetLastError();
 }
@@ -434,7 +465,7 @@ hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int n
                        hipStream_t s, int tile) {
   if (nslots <= 0) return hipSuccess;
   if (pz % 16 != 0) return hipErrorInvalidValue;  // tile groups of one 128-byte line must divide the row
-  LSOP_DISPATCH_L(L, {
+  LSOP_DISPATCH_LX(L, {
     constexpr int CMAX = ColTile<T, LL>::C;
     int C = (tile > 0 && tile < CMAX) ? tile : CMAX;
     if (C >= 16 && CMAX >= 16) C = 16;
@@ -471,13 +502,15 @@ hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int n
 template <typename T>
 hipError_t launch_rows_inv(int L, const Cx<T>* tmp, const Cx<T>* x, const T* chi, const Cx<T>* rhs, Cx<T>* y,
                            double* rnorm, const int* vidx, int nx, int nz, int nslots, int epi, const Cx<T>* tw2,
-                           hipStream_t s) {
+                           hipStream_t s, int nodes, int lo, int hi) {
   const int nitems = nslots * nx;
   if (nitems <= 0) return hipSuccess;
+  if (nodes < 1 || nslots % nodes != 0 || (nodes > 1 && rnorm)) return hipErrorInvalidValue;
+  if (hi < 0) hi = nx;
   LSOP_DISPATCH_L(L, {
     constexpr int NT = rows_threads<T, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_rows_inv<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(NT), 0, s, tmp, x, chi, rhs, y,
-                       rnorm, vidx, nx, nz, nitems, epi, tw2);
+                       rnorm, vidx, nx, nz, nitems, epi, tw2, nodes, lo, hi);
   });
   return hipGetLastError();
 }
@@ -494,7 +527,7 @@ hipError_t launch_spectrum(int lx, int lz, const Cx<double>* ktab, int nx, int n
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double scale = 1.0 / ((double)px * (double)pz);
-  LSOP_DISPATCH_L(lx, {
+  LSOP_DISPATCH_LX(lx, {
     constexpr int NT = rows_threads<double, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_spec_cols<LL>), dim3(grid_for_rows(pz, GPW)), dim3(NT), 0, s, s1t, pz, gs64, gs32, scale,
                        tw2x);
@@ -533,11 +566,12 @@ hipError_t launch_incident(const Cx<double>* ktab, const int* si, const int* sj,
 
 #define LSOP_INST(T)                                                                                               \
   template hipError_t launch_rows_fwd<T>(int, const Cx<T>*, const T*, Cx<T>*, const int*, int, int, int, bool,    \
-                                         const Cx<T>*, hipStream_t);                                              \
+                                         const Cx<T>*, hipStream_t, int, int, int);                               \
   template hipError_t launch_cols<T>(int, Cx<T>*, const Cx<T>*, int, int, int, bool, const Cx<T>*, hipStream_t,    \
                                      int);                                                                        \
   template hipError_t launch_rows_inv<T>(int, const Cx<T>*, const Cx<T>*, const T*, const Cx<T>*, Cx<T>*,        \
-                                         double*, const int*, int, int, int, int, const Cx<T>*, hipStream_t);     \
+                                         double*, const int*, int, int, int, int, const Cx<T>*, hipStream_t, int, \
+                                         int, int);                                                               \
   template hipError_t launch_incident<T>(const Cx<double>*, const int*, const int*, const Cx<double>*, Cx<T>*,    \
                                          int, int, int, double, hipStream_t);
 LSOP_INST(float)

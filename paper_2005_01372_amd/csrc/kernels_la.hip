@@ -51,6 +51,20 @@ __global__ void k_axpby(const Cx<T>* __restrict__ x, Cx<T>* __restrict__ y, T a,
   }
 }
 
+// y[yidx[v]] += a * x[v] (x compact, y through the index list)
+template <typename T>
+__global__ void k_axpy_map(const Cx<T>* __restrict__ x, Cx<T>* __restrict__ y, const int* __restrict__ yidx, T a,
+                           size_t n) {
+  const int v = blockIdx.y;
+  const Cx<T>* xv = x + (size_t)v * n;
+  Cx<T>* yv = y + (size_t)(yidx ? yidx[v] : v) * n;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
+    const Cx<T> xx = xv[k];
+    const Cx<T> yy = yv[k];
+    yv[k] = Cx<T>{yy.re + a * xx.re, yy.im + a * xx.im};
+  }
+}
+
 template <typename T>
 __global__ void k_accumulate(const Cx<T>* __restrict__ x, Cx<double>* __restrict__ y, double alpha,
                              const int* __restrict__ vidx, size_t n) {
@@ -90,8 +104,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 // Probe k, pair t (elements 2t, 2t+1): counter (t lo, t hi, k, 0), key = seed;
 // u1 = (x0 + 1/2) 2^-32, u2 = (x1 + 1/2) 2^-32, Box-Muller in FP64.
 template <typename T>
-__global__ void k_philox_normal(Cx<T>* __restrict__ out, size_t n, uint64_t seed) {
-  const int k = blockIdx.y;
+__global__ void k_philox_normal(Cx<T>* __restrict__ out, size_t n, uint64_t seed, int k0) {
+  const int k = k0 + blockIdx.y;
   const size_t npairs = (n + 1) / 2;
   for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < npairs; t += (size_t)gridDim.x * blockDim.x) {
     uint32_t c[4] = {(uint32_t)(t & 0xffffffffu), (uint32_t)(t >> 32), (uint32_t)k, 0u};
@@ -101,19 +115,24 @@ __global__ void k_philox_normal(Cx<T>* __restrict__ out, size_t n, uint64_t seed
     const double r = sqrt(-2.0 * log(u1));
     double sn, cs;
     sincospi(2.0 * u2, &sn, &cs);
-    Cx<T>* o = out + (size_t)k * n;
+    Cx<T>* o = out + (size_t)blockIdx.y * n;
     o[2 * t] = Cx<T>{(T)(r * cs), T(0)};
     if (2 * t + 1 < n) o[2 * t + 1] = Cx<T>{(T)(r * sn), T(0)};
   }
 }
 
 // ---------------------------------------------------------- C = A^H B (split over n)
-__global__ void k_reduce_parts(const Cx<double>* __restrict__ part, int nparts, size_t count,
+// C[sg][k] = sum over the ksub partials of segment sg (part[sg * ksub + p][k]).
+__global__ void k_reduce_parts(const Cx<double>* __restrict__ part, int ksub, int nseg, size_t count,
                                Cx<double>* __restrict__ C) {
-  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x) {
+  const size_t total = count * nseg;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t sg = idx / count, k = idx % count;
+    const Cx<double>* p0 = part + sg * ksub * count + k;
     Cx<double> s = czero<double>();
-    for (int p = 0; p < nparts; ++p) s = s + part[(size_t)p * count + k];
-    C[k] = s;
+    for (int p = 0; p < ksub; ++p) s = s + p0[(size_t)p * count];
+    C[idx] = s;
   }
 }
 
@@ -150,20 +169,25 @@ struct Mfma<double> {
 // C[a][b] partials = sum_k conj(A[a][k]) B[vb][k] over one k-chunk.  Tile
 // 64 (a) x 64 (b) per workgroup of four waves (each 32 x 32 = 2 x 2 MFMA
 // tiles, real and imaginary chains); operands staged in LDS 16 complex k at a time.
+// The k range is cut into segments of `seg` elements (block-diagonal inner
+// products: one result per segment), each into ksub chunks; z-block ks covers
+// chunk ks % ksub of segment ks / ksub.
 constexpr int GM_T = 64, GM_K = 16;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict__ A, int na,
                                                         const Cx<T>* __restrict__ B, const int* __restrict__ vidx,
-                                                        int nb, size_t n, size_t chunk,
+                                                        int nb, size_t n, size_t seg, size_t chunk, int ksub,
                                                         Cx<double>* __restrict__ part) {
   using M = Mfma<T>;
   constexpr int SROW = 2 * GM_K + 1;  // reals per LDS row (odd stride)
   __shared__ T sa[GM_T * SROW];
   __shared__ T sb[GM_T * SROW];
   const int a0 = blockIdx.x * GM_T, b0 = blockIdx.y * GM_T, ks = blockIdx.z;
-  const size_t k_begin = (size_t)ks * chunk;
-  const size_t k_end = k_begin + chunk < n ? k_begin + chunk : n;
+  const size_t seg_b = (size_t)(ks / ksub) * seg;
+  const size_t seg_e = seg_b + seg < n ? seg_b + seg : n;
+  const size_t k_begin = seg_b + (size_t)(ks % ksub) * chunk;
+  const size_t k_end = k_begin + chunk < seg_e ? k_begin + chunk : seg_e;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wa = (w >> 1) * 32, wb = (w & 1) * 32;
   typename M::acc cre[2][2], cim[2][2];
@@ -228,7 +252,8 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
       }
 }
 
-// Y[vy(b)][k] = X1 + beta X2 + sum_a A[a][k] M[a][b] as out[b][k] = M^T A:
+// Y[vy(b)][k] = X1 + beta X2 + sum_a A[a][k] M[a][b] as out[b][k] = M^T A
+// (segmented form: M for element k is M + (k / seg) * mstride):
 // each wave owns 16 consecutive k (coalesced B-operand loads and stores) and
 // up to NBT * 16 b (MFMA row tiles, real and imaginary chains); M is staged in
 // LDS GU2_A rows (a) at a time; the next A element is loaded while the current
@@ -239,12 +264,15 @@ template <typename T, int NBT>
 __global__ __launch_bounds__(256) void k_gemm_update_mfma(const Cx<T>* __restrict__ A, int na,
                                                           const Cx<double>* __restrict__ Mm, int nb,
                                                           const Cx<T>* X1, const Cx<T>* X2, T beta, Cx<T>* Y,
-                                                          const int* __restrict__ vidx, size_t n) {
+                                                          const int* __restrict__ vidx, size_t n, size_t seg,
+                                                          size_t mstride) {
   using MF = Mfma<T>;
   constexpr int BW = NBT * 16;
   __shared__ Cx<T> sm[GU2_A * BW];
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const size_t k0 = ((size_t)blockIdx.x * 4 + w) * 16;
+  // segmented form: the workgroup's 64 elements lie in one segment (seg % 64 == 0)
+  Mm += ((size_t)blockIdx.x * 64 / seg) * mstride;
   const int kk = l >> 4, c16 = l & 15, pp = kk & 1;
   const size_t kcol = k0 + c16;
   const bool kin = kcol < n;
@@ -358,17 +386,19 @@ __device__ __forceinline__ void gram_orth_body(const Cx<double>* G, Cx<double>* 
   *nkept_out = nkept;
 }
 
+// One workgroup per batch entry b: G_b, X_b at b * na * na, kept[b].
 __global__ __launch_bounds__(256) void k_gram_orth_lds(const Cx<double>* __restrict__ Gg, Cx<double>* __restrict__ Xg,
                                                         int na, double drop_tol, int* kept) {
   __shared__ Cx<double> G[SMALL_NA * SMALL_NA], X[SMALL_NA * SMALL_NA];
   __shared__ Cx<double> x[SMALL_NA], w[SMALL_NA], cf[SMALL_NA];
   __shared__ double red[4];
-  for (int i = threadIdx.x; i < na * na; i += blockDim.x) G[i] = Gg[i];
+  const size_t off = (size_t)blockIdx.x * na * na;
+  for (int i = threadIdx.x; i < na * na; i += blockDim.x) G[i] = Gg[off + i];
   __syncthreads();
   int nk = 0;
   gram_orth_body(G, X, na, drop_tol, x, w, cf, red, &nk);
-  for (int i = threadIdx.x; i < na * na; i += blockDim.x) Xg[i] = X[i];
-  if (threadIdx.x == 0) *kept = nk;
+  for (int i = threadIdx.x; i < na * na; i += blockDim.x) Xg[off + i] = X[i];
+  if (threadIdx.x == 0) kept[blockIdx.x] = nk;
 }
 
 __global__ __launch_bounds__(256) void k_gram_orth(const Cx<double>* __restrict__ G, Cx<double>* __restrict__ X,
@@ -378,23 +408,31 @@ __global__ __launch_bounds__(256) void k_gram_orth(const Cx<double>* __restrict_
   Cx<double>* w = x + na;                                    // [na] = G x
   Cx<double>* cf = w + na;                                   // [na] projections
   __shared__ double red[4];
+  const size_t off = (size_t)blockIdx.x * na * na;
   int nk = 0;
-  gram_orth_body(G, X, na, drop_tol, x, w, cf, red, &nk);
-  if (threadIdx.x == 0) *kept = nk;
+  gram_orth_body(G + off, X + off, na, drop_tol, x, w, cf, red, &nk);
+  if (threadIdx.x == 0) kept[blockIdx.x] = nk;
 }
 
-// Z = (I - M)^{-1}, Gauss-Jordan with partial pivoting on work = [I - M | I]
-// (work in LDS for na <= SMALL_NA, else in global memory).
-__device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, Cx<double>* Z, Cx<double>* work, int na,
-                                                int* singular, Cx<double>* fcol, double* best, int* bidx,
-                                                double* scale_s) {
+// Inverse by Gauss-Jordan with partial pivoting on work = [B | I], where
+// B = I - M (plain = 0, eq. 12) or B = M (plain = 1).  M has leading dimension
+// ldm, Z ldz (Z may alias M).  work is in LDS for na <= SMALL_NA, else in
+// global memory.  *singular is set to 1 on a vanishing pivot (never cleared
+// here, so one flag can collect several calls).
+__device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, size_t ldm, Cx<double>* Z, size_t ldz,
+                                                Cx<double>* work, int na, int plain, int* singular, Cx<double>* fcol,
+                                                double* best, int* bidx, double* scale_s) {
   const int t = threadIdx.x, w2 = 2 * na;
   double amax = 0.0;
   for (int idx = t; idx < na * w2; idx += blockDim.x) {
     const int i = idx / w2, j = idx % w2;
     Cx<double> v;
-    if (j < na) v = Cx<double>{(i == j ? 1.0 : 0.0) - M[(size_t)i * na + j].re, -M[(size_t)i * na + j].im};
-    else v = Cx<double>{(i == j - na) ? 1.0 : 0.0, 0.0};
+    if (j < na) {
+      const Cx<double> m = M[(size_t)i * ldm + j];
+      v = plain ? m : Cx<double>{(i == j ? 1.0 : 0.0) - m.re, -m.im};
+    } else {
+      v = Cx<double>{(i == j - na) ? 1.0 : 0.0, 0.0};
+    }
     work[idx] = v;
     if (j < na) amax = fmax(amax, sqrt(norm2(v)));
   }
@@ -404,7 +442,6 @@ __device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, Cx<double>*
     double m = 0.0;
     for (int i = 0; i < (int)blockDim.x; ++i) m = fmax(m, best[i]);
     *scale_s = m;
-    *singular = 0;
   }
   __syncthreads();
   const double scale = *scale_s;
@@ -462,39 +499,199 @@ __device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, Cx<double>*
   }
   for (int idx = t; idx < na * na; idx += blockDim.x) {
     const int i = idx / na, j = idx % na;
-    Z[idx] = work[(size_t)i * w2 + na + j];
+    Z[(size_t)i * ldz + j] = work[(size_t)i * w2 + na + j];
   }
 }
 
-__global__ __launch_bounds__(256) void k_lu_inverse_lds(const Cx<double>* __restrict__ M, Cx<double>* __restrict__ Z,
-                                                         int na, int* singular) {
+// Batch entry b = blockIdx.x: M + b * sm, Z + b * sz, singular[b].
+__global__ __launch_bounds__(256) void k_lu_inverse_lds(const Cx<double>* __restrict__ M, size_t ldm, size_t sm,
+                                                         Cx<double>* Z, size_t ldz, size_t sz, int na, int plain,
+                                                         int* singular) {
   __shared__ Cx<double> work[SMALL_NA * 2 * SMALL_NA];
   __shared__ Cx<double> fcol[SMALL_NA];
   __shared__ double best[256];
   __shared__ int bidx[256];
   __shared__ double scale;
-  lu_inverse_body(M, Z, work, na, singular, fcol, best, bidx, &scale);
+  const size_t b = blockIdx.x;
+  lu_inverse_body(M + b * sm, ldm, Z + b * sz, ldz, work, na, plain, singular + b, fcol, best, bidx, &scale);
 }
 
-__global__ __launch_bounds__(256) void k_lu_inverse_i_minus(const Cx<double>* __restrict__ M,
-                                                             Cx<double>* __restrict__ Z, Cx<double>* __restrict__ work,
-                                                             int na, int* singular) {
+__global__ __launch_bounds__(256) void k_lu_inverse_i_minus(const Cx<double>* __restrict__ M, size_t ldm, size_t sm,
+                                                             Cx<double>* Z, size_t ldz, size_t sz,
+                                                             Cx<double>* __restrict__ work, int na, int plain,
+                                                             int* singular) {
   extern __shared__ unsigned char smem_raw[];
   Cx<double>* fcol = reinterpret_cast<Cx<double>*>(smem_raw);  // [na]
   __shared__ double best[256];
   __shared__ int bidx[256];
   __shared__ double scale;
-  lu_inverse_body(M, Z, work, na, singular, fcol, best, bidx, &scale);
+  const size_t b = blockIdx.x;
+  lu_inverse_body(M + b * sm, ldm, Z + b * sz, ldz, work + b * 2 * (size_t)na * na, na, plain, singular + b, fcol,
+                  best, bidx, &scale);
 }
 
+// C_b = alpha * A_b (na x na) B_b (na x nb); batch entry b = blockIdx.y.
 __global__ void k_small_gemm(const Cx<double>* __restrict__ A, const Cx<double>* __restrict__ B,
                              Cx<double>* __restrict__ C, int na, int nb, double alpha) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= na * nb) return;
+  const size_t b = blockIdx.y;
+  A += b * na * na;
+  B += b * na * nb;
+  C += b * na * nb;
   const int i = idx / nb, j = idx % nb;
   Cx<double> s = czero<double>();
   for (int l = 0; l < na; ++l) s = s + A[(size_t)i * na + l] * B[(size_t)l * nb + j];
   C[idx] = alpha * s;
+}
+
+// ------------------------------------------------- hierarchical (HODLR) kernels
+// Dense diagonal leaf blocks of A = I - G0 V (eq. 5) for leaves of w grid
+// columns (nl = w nz cells, column-wise order): out[b][a][c] =
+// delta_ac - K(|ia - ic|, |ja - jc|) chi[c] for leaf leaf0 + b.
+__global__ void k_leaf_form(const Cx<double>* __restrict__ ktab, const double* __restrict__ chi,
+                            Cx<double>* __restrict__ out, int nz, int nl, int leaf0, int nleaf) {
+  const size_t per = (size_t)nl * nl, total = per * nleaf;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int b = (int)(idx / per);
+    const size_t rem = idx % per;
+    const int a = (int)(rem / nl), c = (int)(rem % nl);
+    const int ia = a / nz, ja = a % nz, ic = c / nz, jc = c % nz;
+    const int di = ia > ic ? ia - ic : ic - ia, dj = ja > jc ? ja - jc : jc - ja;
+    const double x = chi[(size_t)(leaf0 + b) * nl + c];
+    const Cx<double> k = ktab[(size_t)di * nz + dj];
+    out[idx] = Cx<double>{(a == c ? 1.0 : 0.0) - x * k.re, -x * k.im};
+  }
+}
+
+// out[b][j][i] = in[b][i][j] (FP64 -> T), 32 x 32 tiles through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_convert(const Cx<double>* __restrict__ in, Cx<T>* __restrict__ out,
+                                                            int m) {
+  __shared__ Cx<double> tile[32][33];
+  const size_t b = blockIdx.z;
+  const Cx<double>* src = in + b * m * m;
+  Cx<T>* dst = out + b * m * m;
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+  for (int r = ty; r < 32; r += 8)
+    if (i0 + r < m && j0 + tx < m) tile[r][tx] = src[(size_t)(i0 + r) * m + j0 + tx];
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8)
+    if (j0 + r < m && i0 + tx < m) dst[(size_t)(j0 + r) * m + i0 + tx] = ccast<T>(tile[tx][r]);
+}
+
+// Row-permuted coupling matrix of one node: with G[sg] = V_sg^H W_sg (r x r)
+// for the node's halves sg = 2k (first) and 2k + 1 (second), the Woodbury
+// core K = [[I, -G[2k+1]], [-G[2k], I]] with its two row blocks swapped:
+// out[k] = [[-G[2k], I], [I, -G[2k+1]]] (2r x 2r).  Its inverse is K^{-1} P
+// (P the half swap), which applies K^{-1} to the segment-ordered products.
+__global__ void k_pk_assemble(const Cx<double>* __restrict__ G, Cx<double>* __restrict__ out, int r, int nodes) {
+  const int m = 2 * r;
+  const size_t per = (size_t)m * m, total = per * nodes;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t k = idx / per;
+    const int i = (int)(idx % per) / m, j = (int)(idx % per) % m;
+    const int hi = i >= r, hj = j >= r, ii = i % r, jj = j % r;
+    Cx<double> v;
+    if (hi == hj) {
+      const Cx<double> g = G[((2 * k + hi) * r + ii) * r + jj];
+      v = Cx<double>{-g.re, -g.im};
+    } else {
+      v = Cx<double>{ii == jj ? 1.0 : 0.0, 0.0};
+    }
+    out[idx] = v;
+  }
+}
+
+// Batched complex GEMM on MFMA: C_b = alpha A_b B_b + beta C_b, row-major,
+// A_b: M x K, B_b: K x N, C_b: M x N.  Row m of A is found at
+// (mapa ? mapa[m] : m) * lda + b * sA, row m of C likewise through mapc (the
+// maps address vectors of a batch through an index list).  Tile 64 x 64 per workgroup of four waves
+// (2 x 2 MFMA tiles each, real and imaginary chains over interleaved (re, im)
+// operands: re = sum (ar br - ai bi), im = sum (ar bi + ai br)).
+template <typename T>
+__global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, size_t sA, const Cx<T>* B,
+                                                    size_t ldb, size_t sB, Cx<T>* C, size_t ldc, size_t sC,
+                                                    const int* __restrict__ mapa, const int* __restrict__ mapc, int M,
+                                                    int N, int K, T alpha, T beta) {
+  using MF = Mfma<T>;
+  constexpr int SROW = 2 * GM_K + 1;
+  __shared__ T sa[GM_T * SROW];
+  __shared__ T sb[GM_T * SROW];
+  const size_t bt = blockIdx.z;
+  const int n0 = blockIdx.x * GM_T, m0 = blockIdx.y * GM_T;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  typename MF::acc cre[2][2], cim[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = typename MF::acc{0, 0, 0, 0};
+      cim[i][j] = typename MF::acc{0, 0, 0, 0};
+    }
+  // A loader: thread t -> row t / 4, k (t % 4) * 4 .. +4 ; B loader: k t / 16, n (t % 16) * 4 .. +4
+  const int ar = threadIdx.x >> 2, ak = (threadIdx.x & 3) * 4;
+  const int bk = threadIdx.x >> 4, bn = (threadIdx.x & 15) * 4;
+  const Cx<T>* arow = nullptr;
+  if (m0 + ar < M) arow = A + bt * sA + (size_t)(mapa ? mapa[m0 + ar] : m0 + ar) * lda;
+  const Cx<T>* bbase = B + bt * sB;
+  const int kk = l >> 4, c16 = l & 15;
+  for (int kb = 0; kb < K; kb += GM_K) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = kb + ak + q;
+      const Cx<T> va = (arow && k < K) ? arow[k] : czero<T>();
+      sa[ar * SROW + 2 * (ak + q)] = va.re;
+      sa[ar * SROW + 2 * (ak + q) + 1] = va.im;
+      const int kb2 = kb + bk, nn = n0 + bn + q;
+      const Cx<T> vb = (kb2 < K && nn < N) ? bbase[(size_t)kb2 * ldb + nn] : czero<T>();
+      sb[(bn + q) * SROW + 2 * bk] = vb.re;
+      sb[(bn + q) * SROW + 2 * bk + 1] = vb.im;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < GM_K / 2; ++st) {
+      const int col = 4 * st + kk;
+      T av[2], bre[2], bim[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = sa[(wm + i * 16 + c16) * SROW + col];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int rb = (wn + j * 16 + c16) * SROW;
+        bre[j] = (kk & 1) ? -sb[rb + col] : sb[rb + col];
+        bim[j] = (kk & 1) ? sb[rb + col - 1] : sb[rb + col + 1];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cre[i][j] = MF::mma(av[i], bre[j], cre[i][j]);
+          cim[i][j] = MF::mma(av[i], bim[j], cim[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm + i * 16 + MF::row(l, r);
+      if (m >= M) continue;
+      Cx<T>* crow = C + bt * sC + (size_t)(mapc ? mapc[m] : m) * ldc;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int nn = n0 + wn + j * 16 + c16;
+        if (nn < N) {
+          Cx<T> out{alpha * cre[i][j][r], alpha * cim[i][j][r]};
+          if (beta != T(0)) out = out + beta * crow[nn];
+          crow[nn] = out;
+        }
+      }
+    }
 }
 
 // -------------------------------------------------------------- launchers
@@ -547,62 +744,137 @@ hipError_t launch_real_to_complex(const double* in, Cx<T>* out, size_t count, hi
 }
 
 template <typename T>
-hipError_t launch_philox_normal(Cx<T>* out, int nvec, size_t n, uint64_t seed, hipStream_t s) {
+hipError_t launch_philox_normal(Cx<T>* out, int nvec, size_t n, uint64_t seed, hipStream_t s, int k0) {
   if (nvec <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_philox_normal<T>), dim3(grid1((n + 1) / 2, 1024), nvec), dim3(256), 0, s, out, n, seed);
+  hipLaunchKernelGGL((k_philox_normal<T>), dim3(grid1((n + 1) / 2, 1024), nvec), dim3(256), 0, s, out, n, seed, k0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gemm_ah_b_seg(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n, size_t seg,
+                                Cx<double>* C, Cx<double>* part, int ksub, hipStream_t s) {
+  if (na <= 0 || nb <= 0) return hipSuccess;
+  if (seg == 0 || seg > n) seg = n;
+  const int nseg = (int)((n + seg - 1) / seg);
+  if (ksub < 1) ksub = 1;
+  size_t chunk = (seg + ksub - 1) / ksub;
+  chunk = (chunk + GM_K - 1) / GM_K * GM_K;
+  ksub = (int)((seg + chunk - 1) / chunk);
+  dim3 grid((na + GM_T - 1) / GM_T, (nb + GM_T - 1) / GM_T, (unsigned)(nseg * ksub));
+  hipLaunchKernelGGL((k_gemm_ah_b_mfma<T>), grid, dim3(256), 0, s, A, na, B, vidx, nb, n, seg, chunk, ksub, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((size_t)na * nb * nseg, 2048)), dim3(256), 0, s, part, ksub, nseg,
+                     (size_t)na * nb, C);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gemm_ah_b(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n,
                             Cx<double>* C, Cx<double>* part, int ksplit, hipStream_t s) {
-  if (na <= 0 || nb <= 0) return hipSuccess;
-  size_t chunk = (n + ksplit - 1) / ksplit;
-  chunk = (chunk + GM_K - 1) / GM_K * GM_K;
-  const int parts = (int)((n + chunk - 1) / chunk);
-  dim3 grid((na + GM_T - 1) / GM_T, (nb + GM_T - 1) / GM_T, parts);
-  hipLaunchKernelGGL((k_gemm_ah_b_mfma<T>), grid, dim3(256), 0, s, A, na, B, vidx, nb, n, chunk, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((size_t)na * nb, 64)), dim3(256), 0, s, part, parts,
-                     (size_t)na * nb, C);
+  return launch_gemm_ah_b_seg<T>(A, na, B, vidx, nb, n, n, C, part, ksplit, s);
+}
+
+template <typename T>
+hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<double>* M, size_t mstride, int nb,
+                                  const Cx<T>* X1, const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n,
+                                  size_t seg, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  if (seg == 0 || seg >= n) {
+    seg = n;
+    mstride = 0;
+  } else if (seg % 64 != 0) {
+    return hipErrorInvalidValue;  // a workgroup's 64 elements must share one segment
+  }
+  const dim3 grid((unsigned)((n + 63) / 64));
+  if (nb > 32)
+    hipLaunchKernelGGL((k_gemm_update_mfma<T, 4>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y, vidx, n,
+                       seg, mstride);
+  else
+    hipLaunchKernelGGL((k_gemm_update_mfma<T, 2>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y, vidx, n,
+                       seg, mstride);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gemm_update(const Cx<T>* A, int na, const Cx<double>* M, int nb, const Cx<T>* X1,
                               const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n, hipStream_t s) {
-  if (nb <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((n + 63) / 64));
-  if (nb > 32)
-    hipLaunchKernelGGL((k_gemm_update_mfma<T, 4>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y, vidx, n);
+  return launch_gemm_update_seg<T>(A, na, M, 0, nb, X1, X2, beta, Y, vidx, n, n, s);
+}
+
+hipError_t launch_gram_orth(const Cx<double>* G, Cx<double>* X, int na, double drop_tol, int* kept, hipStream_t s,
+                            int batch) {
+  if (batch <= 0) return hipSuccess;
+  if (na <= SMALL_NA)
+    hipLaunchKernelGGL(k_gram_orth_lds, dim3(batch), dim3(256), 0, s, G, X, na, drop_tol, kept);
   else
-    hipLaunchKernelGGL((k_gemm_update_mfma<T, 2>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y, vidx, n);
+    hipLaunchKernelGGL(k_gram_orth, dim3(batch), dim3(256), sizeof(Cx<double>) * 3 * na, s, G, X, na, drop_tol,
+                       kept);
   return hipGetLastError();
 }
 
-hipError_t launch_gram_orth(const Cx<double>* G, Cx<double>* X, int na, double drop_tol, int* kept,
-                            hipStream_t s) {
+hipError_t launch_lu_inverse(const Cx<double>* M, size_t ldm, size_t sm, Cx<double>* Z, size_t ldz, size_t sz,
+                             Cx<double>* work, int na, bool plain, int* singular, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
   if (na <= SMALL_NA)
-    hipLaunchKernelGGL(k_gram_orth_lds, dim3(1), dim3(256), 0, s, G, X, na, drop_tol, kept);
+    hipLaunchKernelGGL(k_lu_inverse_lds, dim3(batch), dim3(256), 0, s, M, ldm, sm, Z, ldz, sz, na, (int)plain,
+                       singular);
   else
-    hipLaunchKernelGGL(k_gram_orth, dim3(1), dim3(256), sizeof(Cx<double>) * 3 * na, s, G, X, na, drop_tol, kept);
+    hipLaunchKernelGGL(k_lu_inverse_i_minus, dim3(batch), dim3(256), sizeof(Cx<double>) * na, s, M, ldm, sm, Z, ldz,
+                       sz, work, na, (int)plain, singular);
   return hipGetLastError();
 }
 
 hipError_t launch_lu_inverse_i_minus(const Cx<double>* M, Cx<double>* Z, Cx<double>* work, int na, int* singular,
                                      hipStream_t s) {
-  if (na <= SMALL_NA)
-    hipLaunchKernelGGL(k_lu_inverse_lds, dim3(1), dim3(256), 0, s, M, Z, na, singular);
-  else
-    hipLaunchKernelGGL(k_lu_inverse_i_minus, dim3(1), dim3(256), sizeof(Cx<double>) * na, s, M, Z, work, na,
-                       singular);
-  return hipGetLastError();
+  return launch_lu_inverse(M, na, 0, Z, na, 0, work, na, false, singular, 1, s);
 }
 
 hipError_t launch_small_gemm(const Cx<double>* A, const Cx<double>* B, Cx<double>* C, int na, int nb, double alpha,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_small_gemm, dim3(grid1((size_t)na * nb)), dim3(256), 0, s, A, B, C, na, nb, alpha);
+                             hipStream_t s, int batch) {
+  if (batch <= 0 || na <= 0 || nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_small_gemm, dim3((na * nb + 255) / 256, batch), dim3(256), 0, s, A, B, C, na, nb, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_leaf_form(const Cx<double>* ktab, const double* chi, Cx<double>* out, int nz, int nl, int leaf0,
+                            int nleaf, hipStream_t s) {
+  const size_t total = (size_t)nl * nl * nleaf;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_leaf_form, dim3(grid1(total, 16384)), dim3(256), 0, s, ktab, chi, out, nz, nl, leaf0, nleaf);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_transpose_convert(const Cx<double>* in, Cx<T>* out, int m, int batch, hipStream_t s) {
+  if (batch <= 0 || m <= 0) return hipSuccess;
+  const dim3 grid((m + 31) / 32, (m + 31) / 32, batch);
+  hipLaunchKernelGGL((k_transpose_convert<T>), grid, dim3(256), 0, s, in, out, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_pk_assemble(const Cx<double>* G, Cx<double>* out, int r, int nodes, hipStream_t s) {
+  const size_t total = (size_t)4 * r * r * nodes;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pk_assemble, dim3(grid1(total, 8192)), dim3(256), 0, s, G, out, r, nodes);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_bgemm(const Cx<T>* A, size_t lda, size_t sA, const Cx<T>* B, size_t ldb, size_t sB, Cx<T>* C,
+                        size_t ldc, size_t sC, const int* mapa, const int* mapc, int M, int N, int K, double alpha,
+                        double beta, int batch, hipStream_t s) {
+  if (batch <= 0 || M <= 0 || N <= 0) return hipSuccess;
+  const dim3 grid((N + GM_T - 1) / GM_T, (M + GM_T - 1) / GM_T, batch);
+  hipLaunchKernelGGL((k_bgemm_mfma<T>), grid, dim3(256), 0, s, A, lda, sA, B, ldb, sB, C, ldc, sC, mapa, mapc, M, N,
+                     K, (T)alpha, (T)beta);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, int nvec, size_t n, hipStream_t s) {
+  if (nvec <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_axpy_map<T>), dim3(grid1(n, 512), nvec), dim3(256), 0, s, x, y, yidx, (T)a, n);
   return hipGetLastError();
 }
 
@@ -612,11 +884,21 @@ hipError_t launch_small_gemm(const Cx<double>* A, const Cx<double>* B, Cx<double
   template hipError_t launch_accumulate<T>(const Cx<T>*, Cx<double>*, double, const int*, int, size_t,          \
                                            hipStream_t);        \
   template hipError_t launch_real_to_complex<T>(const double*, Cx<T>*, size_t, hipStream_t);                        \
-  template hipError_t launch_philox_normal<T>(Cx<T>*, int, size_t, uint64_t, hipStream_t);                          \
+  template hipError_t launch_philox_normal<T>(Cx<T>*, int, size_t, uint64_t, hipStream_t, int);                     \
   template hipError_t launch_gemm_ah_b<T>(const Cx<T>*, int, const Cx<T>*, const int*, int, size_t, Cx<double>*,    \
                                           Cx<double>*, int, hipStream_t);                                           \
+  template hipError_t launch_gemm_ah_b_seg<T>(const Cx<T>*, int, const Cx<T>*, const int*, int, size_t, size_t,     \
+                                              Cx<double>*, Cx<double>*, int, hipStream_t);                          \
   template hipError_t launch_gemm_update<T>(const Cx<T>*, int, const Cx<double>*, int, const Cx<T>*, const Cx<T>*, \
-                                            double, Cx<T>*, const int*, size_t, hipStream_t);
+                                            double, Cx<T>*, const int*, size_t, hipStream_t);                       \
+  template hipError_t launch_gemm_update_seg<T>(const Cx<T>*, int, const Cx<double>*, size_t, int, const Cx<T>*,   \
+                                                const Cx<T>*, double, Cx<T>*, const int*, size_t, size_t,          \
+                                                hipStream_t);                                                       \
+  template hipError_t launch_transpose_convert<T>(const Cx<double>*, Cx<T>*, int, int, hipStream_t);               \
+  template hipError_t launch_bgemm<T>(const Cx<T>*, size_t, size_t, const Cx<T>*, size_t, size_t, Cx<T>*, size_t,  \
+                                      size_t, const int*, const int*, int, int, int, double, double, int,          \
+                                      hipStream_t);                                                                 \
+  template hipError_t launch_axpy_map<T>(const Cx<T>*, Cx<T>*, const int*, double, int, size_t, hipStream_t);
 LSOP_INST_LA(float)
 LSOP_INST_LA(double)
 template hipError_t launch_convert<float, double>(const Cx<double>*, Cx<float>*, size_t, hipStream_t);

@@ -23,7 +23,7 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", NOT_
                 DIVERGED: "DIVERGED", ESINGULAR: "ESINGULAR", EUNSUPPORTED: "EUNSUPPORTED"}
 C64, C128, MIXED = 0, 1, 2
 MODES = {"A": 0, "G0V": 1, "AH": 2, "VHG0H": 3}
-PC_IDENTITY, PC_LOWRANK = 0, 1
+PC_IDENTITY, PC_LOWRANK, PC_HODLR = 0, 1, 2
 INIT = {"h_rhs": 0, "zero": 1, "user": 2}
 
 EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident", "lsop_autotune",
@@ -44,7 +44,8 @@ class OpInfo(C.Structure):
 
 
 class PrecondParams(C.Structure):
-    _fields_ = [("kind", C.c_int), ("rank", C.c_int), ("power_iters", C.c_int), ("seed", C.c_uint64)]
+    _fields_ = [("kind", C.c_int), ("rank", C.c_int), ("power_iters", C.c_int), ("seed", C.c_uint64),
+                ("levels", C.c_int)]
 
 
 class SolveParams(C.Structure):
@@ -232,15 +233,16 @@ class Operator:
 
 
 class Preconditioner:
-    """H for the series: identity (Born) or the randomized low-rank SMW form (Alg. 2 + eq. 12)."""
+    """H for the series: identity (Born), the randomized low-rank SMW form (Alg. 2 + eq. 12), or the
+    inverse of the HODLR approximation of I - G0 V (Section 2.4, ``levels`` tree levels)."""
 
-    def __init__(self, op, kind=PC_LOWRANK, rank=32, power_iters=0, seed=0):
+    def __init__(self, op, kind=PC_LOWRANK, rank=32, power_iters=0, seed=0, levels=0):
         self.op, self.lib = op, op.lib
-        p = PrecondParams(int(kind), int(rank), int(power_iters), int(seed))
+        p = PrecondParams(int(kind), int(rank), int(power_iters), int(seed), int(levels))
         h = C.c_void_p()
         _check(self.lib.precond_create(op.handle, C.byref(p), C.byref(h)))
         self.handle = h
-        self.kind, self.rank = kind, rank
+        self.kind, self.rank, self.levels = kind, rank, levels
 
     def close(self):
         if getattr(self, "handle", None):
@@ -257,8 +259,9 @@ class Preconditioner:
         if omega is not None:
             omega = torch.as_tensor(omega, dtype=torch.float64)
             omega = (omega if omega.is_cuda else omega.cuda()).contiguous()
-            if omega.numel() != self.rank * self.op.nx * self.op.nz:
-                raise ValueError("omega must hold rank x nx*nz values")
+            blocks = self.levels if self.kind == PC_HODLR else 1
+            if omega.numel() != blocks * self.rank * self.op.nx * self.op.nz:
+                raise ValueError("omega must hold (levels x) rank x nx*nz values")
             self._omega = omega
         return _check(self.lib.precond_build(self.handle, _ptr(omega) if omega is not None else None, _stream()))
 

@@ -83,3 +83,20 @@ def test_hodlr_series_reaches_lu_solution():
     for H in (HD.HodlrPreconditioner(prob, 20, 3, seed=4), HD.HodlrSolve(prob, 20, 3, seed=4)):
         psi, it, r, st = O.series_solve(prob, H.apply, psi0, 1e-12, 60)
         assert st == O.OK and rel(psi, ref) < 1e-10
+
+
+def test_explicit_probes_match_seeded_draws():
+    """Passing the probe rows explicitly reproduces the same approximation as drawing them per node."""
+    w, prob = small(16)
+    r, L, n = 5, 2, prob.n
+    rng = np.random.default_rng(11)
+    blocks = {d: rng.standard_normal((r, n)) for d in range(L)}
+    hs = HD.HodlrSolve(prob, r, L, probes=lambda d: blocks[d])
+    A = O.operator_matrix(prob.K, prob.chi)
+    # the root's upper block is sampled by the level-0 probes on its second half
+    root = hs.approx
+    i1, i2 = slice(root.a11.lo, root.a11.hi), slice(root.a22.lo, root.a22.hi)
+    Y = A[i1, i2] @ blocks[0][:, i2].T
+    P = root.u12 @ root.u12.conj().T
+    assert np.linalg.norm(P @ Y - Y) <= 1e-12 * np.linalg.norm(Y)
+    assert rel(root.u12 @ root.v12.conj().T, P @ A[i1, i2]) < 1e-13
