@@ -134,7 +134,8 @@ const char* lsop_last_error(void);
  *                    nx / 2^l grid columns, split into equal halves), dense
  *                    diagonal leaves of nx / 2^levels columns, and both
  *                    off-diagonal blocks of every node approximated by Alg. 1
- *                    with q = 0 and `rank` probes, the block products done as
+ *                    (q = power_iters, 0 in the paper) with `rank` probes,
+ *                    the block products done as
  *                    FFT convolutions on the node's sub-domain.  A_h is
  *                    inverted exactly, level by level, by Sherman-Morrison-
  *                    Woodbury on the off-diagonal factors (the 2 x 2 block
@@ -148,7 +149,7 @@ typedef enum { LSOP_PC_IDENTITY = 0, LSOP_PC_LOWRANK = 1, LSOP_PC_HODLR = 2 } ls
 typedef struct {
   int kind;         /* lsop_pc_kind */
   int rank;         /* number of Gaussian probes r (LOWRANK, HODLR), 1 <= rank <= 256 */
-  int power_iters;  /* q >= 0 (LOWRANK; HODLR uses q = 0) */
+  int power_iters;  /* q >= 0 (Alg. 1 power iterations; the paper's HODLR uses q = 0) */
   uint64_t seed;    /* Philox4x32-10 key when no probe block is supplied */
   int levels;       /* HODLR tree depth, >= 1 (ignored otherwise) */
 } lsop_precond_params;

@@ -35,7 +35,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .lsop_oracle import operator_matrix
+from .lsop_oracle import operator_matrix, range_finder_generic
 
 
 class Node:
@@ -103,10 +103,12 @@ def split_tree(ncols, nz, levels, min_width=1):
     return build(0, ncols, 0)
 
 
-def lowrank_from_block(B, r, rng, om=None):
-    """Alg. 1 with q = 0 on an explicit block: B ~= Q (B^H Q)^H with r Gaussian probes (or the given om)."""
+def lowrank_from_block(B, r, rng, om=None, q=0):
+    """Alg. 1 on an explicit block (q = 0 in Section 2.4): B ~= Q (B^H Q)^H with r Gaussian probes (or om)."""
     if om is None:
         om = rng.standard_normal((B.shape[1], r))
+    if q:
+        return range_finder_generic(B, om, q)
     Q, _ = np.linalg.qr(B @ om)
     return Q, B.conj().T @ Q
 
@@ -121,7 +123,7 @@ def truncate(U, V, r):
     return qu @ (w[:, :r] * s[:r]), qv @ zh.conj().T[:, :r]
 
 
-def build(A, tree, r, seed=0, probes=None):
+def build(A, tree, r, seed=0, probes=None, q=0):
     """HODLR approximation of the dense matrix A on the given tree (off-diagonal blocks by Alg. 1, q = 0).
 
     probes: optional callable depth -> real [r, n] block; a node at that depth
@@ -139,8 +141,8 @@ def build(A, tree, r, seed=0, probes=None):
         i1 = slice(node.a11.lo, node.a11.hi)
         i2 = slice(node.a22.lo, node.a22.hi)
         om = probes(depth) if probes is not None else None
-        node.u12, node.v12 = lowrank_from_block(A[i1, i2], r, rng, None if om is None else om[:, i2].T)
-        node.u21, node.v21 = lowrank_from_block(A[i2, i1], r, rng, None if om is None else om[:, i1].T)
+        node.u12, node.v12 = lowrank_from_block(A[i1, i2], r, rng, None if om is None else om[:, i2].T, q)
+        node.u21, node.v21 = lowrank_from_block(A[i2, i1], r, rng, None if om is None else om[:, i1].T, q)
         return node
     return fill(tree, 0)
 
@@ -211,10 +213,10 @@ class HodlrSolve:
     inverted without the rank truncation of the H-arithmetic inverse.
     """
 
-    def __init__(self, prob, rank, levels, min_width=1, seed=0, probes=None):
+    def __init__(self, prob, rank, levels, min_width=1, seed=0, probes=None, q=0):
         A = operator_matrix(prob.K, prob.chi)
         self.tree = split_tree(prob.nx, prob.nz, levels, min_width)
-        self.approx = build(A, self.tree, rank, seed, probes)
+        self.approx = build(A, self.tree, rank, seed, probes, q)
         self.n = prob.n
         self._prepare(self.approx)
 

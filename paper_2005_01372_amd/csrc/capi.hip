@@ -217,24 +217,57 @@ int check_op(const lsop_op* op) {
 }
 
 // ---------------------------------------------------------- preconditioner
+// Orthonormal basis of the r columns (probe-major rows of n elements) of Y,
+// independently on each segment of `seg` elements (seg = n: the whole range),
+// written to Q; Y is overwritten.  Columns are taken in blocks of 64: each
+// block is first projected out of the previous blocks' basis twice (block
+// classical Gram-Schmidt), then orthonormalised by Cholesky-QR run twice in the
+// metric of its FP64 Gram matrix, numerically dependent columns dropped.
+// G, X: FP64 scratch of nseg * r * 64 entries each; kept[(block) * nseg + sg]
+// receives the kept column counts of the final pass.
+template <typename T>
+int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int ksub, Cx<double>* G, Cx<double>* X,
+                Cx<double>* part, int* kept, hipStream_t s) {
+  constexpr int B = 64;
+  const double tol = std::is_same<T, float>::value ? 1e-9 : 1e-24;
+  const double e = sizeof(Cx<T>);
+  for (int c0 = 0; c0 < r; c0 += B) {
+    const int kb = std::min(B, r - c0);
+    Cx<T>* Yb = Y + (size_t)c0 * n;
+    Cx<T>* Qb = Q + (size_t)c0 * n;
+    for (int pass = 0; pass < 2 && c0 > 0; ++pass) {
+      LSOP_HIP(prof("orth_project_ah_b", (double)(c0 + kb) * n * e, 8.0 * c0 * kb * (double)n, kb, s, [&] {
+        return launch_gemm_ah_b_seg<T>(Q, c0, Yb, nullptr, kb, n, seg, G, part, ksub, s, -1.0);
+      }));
+      LSOP_HIP(prof("orth_project_update", (double)(c0 + 2 * kb) * n * e, 8.0 * c0 * kb * (double)n, kb, s, [&] {
+        return launch_gemm_update_seg<T>(Q, c0, G, (size_t)c0 * kb, kb, Yb, nullptr, 0.0, Yb, nullptr, n, seg, s);
+      }));
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      const Cx<T>* src = pass == 0 ? Yb : Qb;
+      Cx<T>* dst = pass == 0 ? Qb : Yb;
+      LSOP_HIP(prof("orth_gram", 2.0 * kb * n * e, 8.0 * kb * kb * (double)n, kb, s, [&] {
+        return launch_gemm_ah_b_seg<T>(src, kb, src, nullptr, kb, n, seg, G, part, ksub, s, 1.0);
+      }));
+      LSOP_HIP(launch_gram_orth(G, X, kb, pass == 0 ? tol : 1e-6, kept + (c0 / B) * nseg, s, nseg));
+      LSOP_HIP(prof("orth_update", 2.0 * kb * n * e, 8.0 * kb * kb * (double)n, kb, s, [&] {
+        return launch_gemm_update_seg<T>(src, kb, X, (size_t)kb * kb, kb, nullptr, nullptr, 0.0, dst, nullptr, n, seg,
+                                         s);
+      }));
+    }
+    LSOP_HIP(hipMemcpyAsync(Qb, Yb, sizeof(Cx<T>) * (size_t)kb * n, hipMemcpyDeviceToDevice, s));
+  }
+  return LSOP_OK;
+}
+
+// Q = orth(Y) over the whole grid (Alg. 2 step 3); Y is overwritten.
 template <typename T>
 int orth_impl(lsop_precond* pc, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s) {
-  // Cholesky-QR twice in the Gram metric: Q1 = Y X1, Q = Q1 X2.
   const int r = pc->rank;
   const size_t n = pc->op->n();
   Cx<double>* G = pc->small;
   Cx<double>* X = G + (size_t)r * r;
-  const double tol = std::is_same<T, float>::value ? 1e-9 : 1e-24;
-  for (int pass = 0; pass < 2; ++pass) {
-    const Cx<T>* src = pass == 0 ? Yin : Qout;
-    Cx<T>* dst = pass == 0 ? Qout : Yin;
-    LSOP_HIP(p_gemm_ah_b<T>(src, r, src, nullptr, r, n, G, pc->part, pc->ksplit, s));
-    LSOP_HIP(launch_gram_orth(G, X, r, pass == 0 ? tol : 1e-6, pc->dflag, s));
-    LSOP_HIP(p_gemm_update<T>(src, r, X, r, nullptr, nullptr, 0.0, dst, nullptr, n, s));
-  }
-  // result of pass 2 is in Yin; move it to Qout
-  LSOP_HIP(hipMemcpyAsync(Qout, Yin, sizeof(Cx<T>) * (size_t)r * n, hipMemcpyDeviceToDevice, s));
-  return LSOP_OK;
+  return orth_blocks<T>(Yin, Qout, r, n, n, 1, pc->ksplit, G, X, pc->part, pc->dflag, s);
 }
 
 template <typename T>
@@ -266,13 +299,14 @@ int build_impl(lsop_precond* pc, const double* omega, hipStream_t s) {
   Cx<double>* M = pc->small;
   Cx<double>* work = M + (size_t)r * r;
   LSOP_HIP(p_gemm_ah_b<T>(W, r, U, nullptr, r, n, M, pc->part, pc->ksplit, s));
-  LSOP_HIP(hipMemsetAsync(pc->dflag + 1, 0, sizeof(int), s));
-  LSOP_HIP(launch_lu_inverse_i_minus(M, pc->Z, work, r, pc->dflag + 1, s));
-  int flags[2] = {0, 0};
+  LSOP_HIP(hipMemsetAsync(pc->dflag + 32, 0, sizeof(int), s));
+  LSOP_HIP(launch_lu_inverse_i_minus(M, pc->Z, work, r, pc->dflag + 32, s));
+  int flags[33] = {0};
   LSOP_HIP(hipMemcpyAsync(flags, pc->dflag, sizeof(flags), hipMemcpyDeviceToHost, s));
   LSOP_HIP(hipStreamSynchronize(s));
-  pc->kept = flags[0];
-  if (flags[1]) return fail(LSOP_ESINGULAR, "I - W^H U is numerically singular");
+  pc->kept = 0;
+  for (int b = 0; b < (r + 63) / 64; ++b) pc->kept += flags[b];
+  if (flags[32]) return fail(LSOP_ESINGULAR, "I - W^H U is numerically singular");
   pc->built = true;
   return LSOP_OK;
 }
@@ -398,64 +432,47 @@ int hodlr_subconv(lsop_precond* pc, int lv, bool adj, const Cx<T>* x, Cx<T>* y, 
   return LSOP_OK;
 }
 
-// Cholesky-QR twice, separately on every half-node segment of level lv.
+// Orthonormal bases, separately on every half-node segment of level lv.
 template <typename T>
 int hodlr_orth(lsop_precond* pc, int lv, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s) {
-  const int r = pc->rank;
-  const size_t n = pc->op->n();
   const int W = pc->lev[lv].width, nseg = 2 * (pc->op->nx / W);
   const size_t seg = (size_t)(W / 2) * pc->op->nz;
-  const int ksub = hodlr_ksub(pc, seg, nseg);
-  Cx<double>* G = pc->hG;
-  Cx<double>* X = pc->hX;
-  const double tol = std::is_same<T, float>::value ? 1e-9 : 1e-24;
-  const double e = sizeof(Cx<T>);
-  for (int pass = 0; pass < 2; ++pass) {
-    const Cx<T>* src = pass == 0 ? Yin : Qout;
-    Cx<T>* dst = pass == 0 ? Qout : Yin;
-    LSOP_HIP(prof("hodlr_gemm_ah_b", 2.0 * r * n * e, 8.0 * r * r * (double)n, r, s, [&] {
-      return launch_gemm_ah_b_seg<T>(src, r, src, nullptr, r, n, seg, G, pc->part, ksub, s);
-    }));
-    LSOP_HIP(launch_gram_orth(G, X, r, pass == 0 ? tol : 1e-6, pc->hflag, s, nseg));
-    LSOP_HIP(prof("hodlr_gemm_update", 2.0 * r * n * e, 8.0 * r * r * (double)n, r, s, [&] {
-      return launch_gemm_update_seg<T>(src, r, X, (size_t)r * r, r, nullptr, nullptr, 0.0, dst, nullptr, n, seg, s);
-    }));
-  }
-  LSOP_HIP(hipMemcpyAsync(Qout, Yin, sizeof(Cx<T>) * (size_t)r * n, hipMemcpyDeviceToDevice, s));
-  return LSOP_OK;
+  return orth_blocks<T>(Yin, Qout, pc->rank, pc->op->n(), seg, nseg, hodlr_ksub(pc, seg, nseg), pc->hG, pc->hX,
+                        pc->part, pc->hflag, s);
 }
 
-// In-place inverse of the m x m diagonal block at offset o of each of cnt
-// FP64 leaf matrices (leading dimension and batch stride nl, nl^2) by the
-// 2 x 2 block formula of Section 2.4: with X = A^{-1} and S = D - C X B,
+// In-place inverse of the m x m block at offset o of each of cnt FP64
+// matrices (leading dimension ld, batch stride st) by the 2 x 2 block formula
+// of Section 2.4: with X = A^{-1} and S = D - C X B,
 //   [[A, B], [C, D]]^{-1} = [[X + X B S^{-1} C X, -X B S^{-1}], [-S^{-1} C X, S^{-1}]],
-// recursing on A and S down to 64 x 64 blocks (Gauss-Jordan with pivoting).
-int hodlr_block_inverse(lsop_precond* pc, Cx<double>* M, int nl, int cnt, size_t o, int m, int depth,
-                        const std::vector<size_t>& toff, hipStream_t s) {
-  const size_t ld = nl, st = (size_t)nl * nl;
+// recursing on A and S down to 64 x 64 blocks (Gauss-Jordan with partial
+// pivoting; flags[b] set on a vanishing pivot).  Temporaries of recursion
+// depth d at tbase + toff[d] (block_inverse_temps).
+int block_inverse(Cx<double>* M, size_t ld, size_t st, int cnt, size_t o, int m, int depth, Cx<double>* tbase,
+                  const std::vector<size_t>& toff, int* flags, hipStream_t s) {
   if (m <= 64) {
-    LSOP_HIP(prof("hodlr_leaf_base_inv", 0.0, 8.0 * m * m * (double)m * cnt, cnt, s, [&] {
-      return launch_lu_inverse(M + o, ld, st, M + o, ld, st, nullptr, m, true, pc->hflag, cnt, s);
+    LSOP_HIP(prof("block_inv_base", 0.0, 8.0 * m * m * (double)m * cnt, cnt, s, [&] {
+      return launch_lu_inverse(M + o, ld, st, M + o, ld, st, nullptr, m, true, flags, cnt, s);
     }));
     return LSOP_OK;
   }
   const int h = m / 2, h2 = m - h;
   const size_t A = o, B = o + h, C = o + (size_t)h * ld, D = C + h;
-  Cx<double>* T1 = pc->lwork + toff[depth];                       // h x h2
-  Cx<double>* T2 = T1 + (size_t)cnt * h * h2;                      // h2 x h
+  Cx<double>* T1 = tbase + toff[depth];   // h x h2
+  Cx<double>* T2 = T1 + (size_t)cnt * h * h2;  // h2 x h
   const size_t s1 = (size_t)h * h2;
-  int rc = hodlr_block_inverse(pc, M, nl, cnt, A, h, depth + 1, toff, s);
+  int rc = block_inverse(M, ld, st, cnt, A, h, depth + 1, tbase, toff, flags, s);
   if (rc) return rc;
   auto gemm = [&](const Cx<double>* a, size_t lda, size_t sa, const Cx<double>* b, size_t ldb, size_t sb,
                   Cx<double>* c, size_t ldc, size_t sc, int mm, int nn, int kk, double alpha, double beta) {
-    return prof("hodlr_leaf_gemm", 0.0, 8.0 * mm * nn * (double)kk * cnt, cnt, s, [&] {
+    return prof("block_inv_gemm", 0.0, 8.0 * mm * nn * (double)kk * cnt, cnt, s, [&] {
       return launch_bgemm<double>(a, lda, sa, b, ldb, sb, c, ldc, sc, nullptr, nullptr, mm, nn, kk, alpha, beta, cnt,
                                   s);
     });
   };
   LSOP_HIP(gemm(M + A, ld, st, M + B, ld, st, T1, h2, s1, h, h2, h, 1.0, 0.0));      // T1 = X B
   LSOP_HIP(gemm(M + C, ld, st, T1, h2, s1, M + D, ld, st, h2, h2, h, -1.0, 1.0));    // D <- S = D - C X B
-  rc = hodlr_block_inverse(pc, M, nl, cnt, D, h2, depth + 1, toff, s);              // D <- S^{-1}
+  rc = block_inverse(M, ld, st, cnt, D, h2, depth + 1, tbase, toff, flags, s);      // D <- S^{-1}
   if (rc) return rc;
   LSOP_HIP(gemm(M + C, ld, st, M + A, ld, st, T2, h, s1, h2, h, h, 1.0, 0.0));      // T2 = C X
   LSOP_HIP(gemm(T1, h2, s1, M + D, ld, st, M + B, ld, st, h, h2, h2, -1.0, 0.0));   // B <- -X B S^{-1}
@@ -464,11 +481,11 @@ int hodlr_block_inverse(lsop_precond* pc, Cx<double>* M, int nl, int cnt, size_t
   return LSOP_OK;
 }
 
-// temporaries of each recursion depth after the cnt leaf matrices
-std::vector<size_t> hodlr_temp_offsets(int nl, int cnt, size_t* total) {
+// offsets (from the temporaries' base) of each recursion depth of block_inverse on m0 x m0 blocks
+std::vector<size_t> block_inverse_temps(int m0, int cnt, size_t* total) {
   std::vector<size_t> off;
-  size_t at = (size_t)cnt * nl * nl;
-  for (int m = nl; m > 64; m = (m + 1) / 2) {
+  size_t at = 0;
+  for (int m = m0; m > 64; m = (m + 1) / 2) {
     off.push_back(at);
     const size_t h2 = (size_t)(m - m / 2);
     at += 2 * (size_t)cnt * h2 * h2;
@@ -486,10 +503,11 @@ int hodlr_leaves(lsop_precond* pc, hipStream_t s) {
   for (int l0 = 0; l0 < pc->nleaf; l0 += pc->leaf_chunk) {
     const int cnt = std::min(pc->leaf_chunk, pc->nleaf - l0);
     size_t total = 0;
-    const std::vector<size_t> toff = hodlr_temp_offsets(nl, cnt, &total);
+    const std::vector<size_t> toff = block_inverse_temps(nl, cnt, &total);
     LSOP_HIP(hipMemsetAsync(pc->hflag, 0, sizeof(int) * cnt, s));
     LSOP_HIP(launch_leaf_form(op->ktab, op->chi64, pc->lwork, op->nz, nl, l0, cnt, s));
-    int rc = hodlr_block_inverse(pc, pc->lwork, nl, cnt, 0, nl, 0, toff, s);
+    int rc = block_inverse(pc->lwork, nl, (size_t)nl * nl, cnt, 0, nl, 0, pc->lwork + (size_t)cnt * nl * nl, toff,
+                           pc->hflag, s);
     if (rc) return rc;
     std::vector<int> flags(cnt, 0);
     LSOP_HIP(hipMemcpyAsync(flags.data(), pc->hflag, sizeof(int) * cnt, hipMemcpyDeviceToHost, s));
@@ -544,6 +562,69 @@ int hodlr_apply(lsop_precond* pc, const Cx<T>* x, const int* xidx, Cx<T>* y, con
   return LSOP_OK;
 }
 
+// kinv = K^{-1} P for every node of level lv, from G[sg] = V_sg^H Wp_sg
+// (FP64, G0 = G[2k] on the first half, G1 = G[2k+1] on the second):
+// K = [[I, -G1], [-G0, I]], S = I - G0 G1,
+// K^{-1} = [[I + G1 S^{-1} G0, G1 S^{-1}], [S^{-1} G0, S^{-1}]],
+// and P swaps the two column halves (the segment order of the products).
+// S^{-1} by the recursive block formula, checked by max |S S^{-1} - I|; a
+// node that fails the check is redone by Gauss-Jordan with pivoting.
+int hodlr_core_inverse(lsop_precond* pc, int lv, hipStream_t s) {
+  hodlr_level& L = pc->lev[lv];
+  const int r = pc->rank, nodes = pc->op->nx / L.width;
+  const size_t r2 = (size_t)r * r, ld = 2 * (size_t)r, st = 4 * r2;
+  Cx<double>* K = L.kinv;
+  Cx<double>* B00 = K;
+  Cx<double>* B01 = K + r;
+  Cx<double>* B10 = K + (size_t)r * ld;
+  Cx<double>* B11 = B10 + r;
+  const Cx<double>* G0 = pc->hG;
+  const Cx<double>* G1 = pc->hG + r2;
+  Cx<double>* Sc = pc->hX;  // copy of S, r x r per node
+  size_t ttot = 0;
+  const std::vector<size_t> toff = block_inverse_temps(r, nodes, &ttot);
+  Cx<double>* tbase = pc->hK;
+  Cx<double>* P = pc->hK + ttot;
+  Cx<double>* gjw = P + (size_t)nodes * r2;
+  double* dev = reinterpret_cast<double*>(pc->part);
+  auto gemm = [&](const Cx<double>* a, size_t lda, size_t sa, const Cx<double>* b, size_t ldb, size_t sb,
+                  Cx<double>* c, size_t ldc, size_t sc, double alpha, double beta) {
+    return prof("hodlr_core_gemm", 0.0, 8.0 * r2 * (double)r * nodes, nodes, s, [&] {
+      return launch_bgemm<double>(a, lda, sa, b, ldb, sb, c, ldc, sc, nullptr, nullptr, r, r, r, alpha, beta, nodes,
+                                  s);
+    });
+  };
+  LSOP_HIP(launch_set_identity(B10, ld, st, r, nodes, s));
+  LSOP_HIP(gemm(G0, r, 2 * r2, G1, r, 2 * r2, B10, ld, st, -1.0, 1.0));   // S = I - G0 G1
+  LSOP_HIP(launch_set_identity(Sc, r, r2, r, nodes, s));
+  LSOP_HIP(gemm(G0, r, 2 * r2, G1, r, 2 * r2, Sc, r, r2, -1.0, 1.0));
+  LSOP_HIP(hipMemsetAsync(pc->hflag, 0, sizeof(int) * nodes, s));
+  int rc = block_inverse(K, ld, st, nodes, (size_t)r * ld, r, 0, tbase, toff, pc->hflag, s);
+  if (rc) return rc;
+  LSOP_HIP(gemm(Sc, r, r2, B10, ld, st, P, r, r2, 1.0, 0.0));
+  LSOP_HIP(launch_identity_deviation(P, r, r2, r, nodes, dev, s));
+  std::vector<int> flags(nodes, 0);
+  std::vector<double> devh(nodes, 0.0);
+  LSOP_HIP(hipMemcpyAsync(flags.data(), pc->hflag, sizeof(int) * nodes, hipMemcpyDeviceToHost, s));
+  LSOP_HIP(hipMemcpyAsync(devh.data(), dev, sizeof(double) * nodes, hipMemcpyDeviceToHost, s));
+  LSOP_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < nodes; ++k) {
+    if (!flags[k] && devh[k] <= 1e-8) continue;
+    // pivoted Gauss-Jordan for this node
+    LSOP_HIP(hipMemsetAsync(pc->hflag, 0, sizeof(int), s));
+    LSOP_HIP(launch_lu_inverse(Sc + (size_t)k * r2, r, r2, B10 + (size_t)k * st, ld, st, gjw, r, true, pc->hflag, 1, s));
+    int f = 0;
+    LSOP_HIP(hipMemcpyAsync(&f, pc->hflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    LSOP_HIP(hipStreamSynchronize(s));
+    if (f) return fail(LSOP_ESINGULAR, "a HODLR Woodbury core is numerically singular");
+  }
+  LSOP_HIP(gemm(G1, r, 2 * r2, B10, ld, st, B00, ld, st, 1.0, 0.0));       // G1 S^{-1}
+  LSOP_HIP(launch_set_identity(B01, ld, st, r, nodes, s));
+  LSOP_HIP(gemm(B00, ld, st, G0, r, 2 * r2, B01, ld, st, 1.0, 1.0));       // I + G1 S^{-1} G0
+  LSOP_HIP(gemm(B10, ld, st, G0, r, 2 * r2, B11, ld, st, 1.0, 0.0));       // S^{-1} G0
+  return LSOP_OK;
+}
+
 template <typename T>
 int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
   lsop_op* op = pc->op;
@@ -577,26 +658,24 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
     if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 0, 1, s))) return st;
     // step 3: orthonormal bases per half-node (result in Y)
     if ((st = hodlr_orth<T>(pc, lv, Q, Y, s))) return st;
+    // optional power iterations (Alg. 1 step 4) on both blocks of every node
+    for (int j = 0; j < pc->q; ++j) {
+      if ((st = hodlr_subconv<T>(pc, lv, true, Y, Q, r, 0, 1, s))) return st;
+      if ((st = hodlr_subconv<T>(pc, lv, true, Y, Q, r, 1, 0, s))) return st;
+      if ((st = hodlr_orth<T>(pc, lv, Q, Y, s))) return st;
+      if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 1, 0, s))) return st;
+      if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 0, 1, s))) return st;
+      if ((st = hodlr_orth<T>(pc, lv, Q, Y, s))) return st;
+    }
     // right factors v12 = (G0 V[I1, I2])^H Q12 on I2, v21 on I1
     if ((st = hodlr_subconv<T>(pc, lv, true, Y, V, r, 0, 1, s))) return st;
     if ((st = hodlr_subconv<T>(pc, lv, true, Y, V, r, 1, 0, s))) return st;
     // Wp = A_{lv+1}^{-1} Ut
     if ((st = hodlr_apply<T>(pc, Y, nullptr, Wp, nullptr, r, lv + 1, s))) return st;
-    // K per node from the per-half products V^H Wp; kinv = (P K)^{-1}
+    // K per node from the per-half products V^H Wp, then kinv = K^{-1} P
     const int ksub = hodlr_ksub(pc, seg, nseg);
     LSOP_HIP(launch_gemm_ah_b_seg<T>(V, r, Wp, nullptr, r, n, seg, pc->hG, pc->part, ksub, s));
-    LSOP_HIP(launch_pk_assemble(pc->hG, pc->hK, r, nodes, s));
-    LSOP_HIP(hipMemsetAsync(pc->hflag, 0, sizeof(int) * nodes, s));
-    const size_t m2 = (size_t)4 * r * r;
-    LSOP_HIP(prof("hodlr_core_inv", 0.0, 64.0 * r * r * (double)r * nodes, nodes, s, [&] {
-      return launch_lu_inverse(pc->hK, 2 * r, m2, L.kinv, 2 * r, m2, pc->hK + m2 * nodes, 2 * r, true, pc->hflag,
-                               nodes, s);
-    }));
-    std::vector<int> flags(nodes, 0);
-    LSOP_HIP(hipMemcpyAsync(flags.data(), pc->hflag, sizeof(int) * nodes, hipMemcpyDeviceToHost, s));
-    LSOP_HIP(hipStreamSynchronize(s));
-    for (int f : flags)
-      if (f) return fail(LSOP_ESINGULAR, "a HODLR Woodbury core is numerically singular");
+    if ((st = hodlr_core_inverse(pc, lv, s))) return st;
   }
   pc->kept = r;
   pc->built = true;
@@ -980,7 +1059,8 @@ int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out
     if (const char* lc = getenv("LSOP_HODLR_LEAF_CHUNK"))  // smaller chunks (exercises the chunked leaf build)
       pc->leaf_chunk = std::max(1, std::min(pc->leaf_chunk, atoi(lc)));
     size_t lw = 0;
-    (void)hodlr_temp_offsets(nl, pc->leaf_chunk, &lw);
+    (void)block_inverse_temps(nl, pc->leaf_chunk, &lw);
+    lw += (size_t)pc->leaf_chunk * nl * nl;
     pc->lwork_elems = lw;
     st |= dev_alloc(o, b, &pc->lwork, sizeof(Cx<double>) * lw);
     st |= dev_alloc(o, b, &pc->dinv, esz * (size_t)pc->nleaf * nl * nl);
@@ -990,10 +1070,10 @@ int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out
     const size_t small = (size_t)pc->maxseg * r * pc->tcap;
     st |= dev_alloc(o, b, &pc->hG, sizeof(Cx<double>) * small);
     st |= dev_alloc(o, b, &pc->hX, sizeof(Cx<double>) * small);
-    // node cores (2r x 2r) and, for 2r > 64, the Gauss-Jordan work (2 (2r)^2 each)
-    st |= dev_alloc(o, b, &pc->hK, sizeof(Cx<double>) * (size_t)(pc->maxseg / 2) * 4 * r * r * 3);
+    // node cores: recursion temporaries (< r^2 per node), S S^{-1} (r^2 per node), pivoted fallback work (2 r^2)
+    st |= dev_alloc(o, b, &pc->hK, sizeof(Cx<double>) * ((size_t)(pc->maxseg / 2) * 3 * r * r + 2 * (size_t)r * r));
     st |= dev_alloc(o, b, &pc->part, sizeof(Cx<double>) * (size_t)pc->ksub_cap * r * pc->tcap);
-    st |= dev_alloc(o, b, &pc->hflag, sizeof(int) * std::max(pc->maxseg, pc->leaf_chunk));
+    st |= dev_alloc(o, b, &pc->hflag, sizeof(int) * (4 * (size_t)pc->maxseg + pc->leaf_chunk + 64));
     pc->lev.resize(p->levels);
     for (int lv = 0; lv < p->levels && !st; ++lv) {
       hodlr_level& L = pc->lev[lv];

@@ -90,7 +90,7 @@ hipError_t launch_gemm_ah_b(const Cx<T>* A, int na, const Cx<T>* B, const int* v
 // nseg * ksub * na * nb complex doubles).
 template <typename T>
 hipError_t launch_gemm_ah_b_seg(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n, size_t seg,
-                                Cx<double>* C, Cx<double>* part, int ksub, hipStream_t s);
+                                Cx<double>* C, Cx<double>* part, int ksub, hipStream_t s, double alpha = 1.0);
 // Y[vy(b)][k] = X1[vy(b)][k] + beta * X2[vy(b)][k] + sum_a A[a][k] M[a][b]   (M FP64, na x nb)
 // X1 / X2 may be NULL (treated as 0).
 template <typename T>
@@ -120,13 +120,16 @@ hipError_t launch_leaf_form(const Cx<double>* ktab, const double* chi, Cx<double
 // out_b = transpose(in_b) converted to T (m x m each)
 template <typename T>
 hipError_t launch_transpose_convert(const Cx<double>* in, Cx<T>* out, int m, int batch, hipStream_t s);
-// node couplings [[-G_2k, I], [I, -G_2k+1]] from per-half inner products G (r x r each)
-hipError_t launch_pk_assemble(const Cx<double>* G, Cx<double>* out, int r, int nodes, hipStream_t s);
 // batched complex GEMM C_b = alpha A_b B_b + beta C_b (rows of A / C through mapa / mapc when given)
 template <typename T>
 hipError_t launch_bgemm(const Cx<T>* A, size_t lda, size_t sA, const Cx<T>* B, size_t ldb, size_t sB, Cx<T>* C,
                         size_t ldc, size_t sC, const int* mapa, const int* mapc, int M, int N, int K, double alpha,
                         double beta, int batch, hipStream_t s);
+// r x r identity blocks (leading dimension ld, batch stride st)
+hipError_t launch_set_identity(Cx<double>* out, size_t ld, size_t st, int r, int batch, hipStream_t s);
+// dev[b] = max |P_b - I| entrywise
+hipError_t launch_identity_deviation(const Cx<double>* P, size_t ld, size_t st, int r, int batch, double* dev,
+                                     hipStream_t s);
 // y[yidx[v]] += a * x[v] for v < nvec (x compact)
 template <typename T>
 hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, int nvec, size_t n, hipStream_t s);
@@ -187,7 +190,7 @@ struct lsop_precond {
   size_t lwork_elems = 0;
   void* hy = nullptr;                     // [tcap][n] apply / series temporary
   Cx<double>*hG = nullptr, *hX = nullptr;  // per-segment products [maxseg][rank][tcap]
-  Cx<double>* hK = nullptr;               // node cores and their Gauss-Jordan work
+  Cx<double>* hK = nullptr;               // node-core recursion temporaries and Gauss-Jordan work
   int* hflag = nullptr;                   // per-node / per-segment flags
   int maxseg = 0, ksub_cap = 0;
   uint64_t seed = 0;

@@ -122,9 +122,9 @@ __global__ void k_philox_normal(Cx<T>* __restrict__ out, size_t n, uint64_t seed
 }
 
 // ---------------------------------------------------------- C = A^H B (split over n)
-// C[sg][k] = sum over the ksub partials of segment sg (part[sg * ksub + p][k]).
+// C[sg][k] = alpha * sum over the ksub partials of segment sg (part[sg * ksub + p][k]).
 __global__ void k_reduce_parts(const Cx<double>* __restrict__ part, int ksub, int nseg, size_t count,
-                               Cx<double>* __restrict__ C) {
+                               Cx<double>* __restrict__ C, double alpha) {
   const size_t total = count * nseg;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
@@ -132,7 +132,7 @@ __global__ void k_reduce_parts(const Cx<double>* __restrict__ part, int ksub, in
     const Cx<double>* p0 = part + sg * ksub * count + k;
     Cx<double> s = czero<double>();
     for (int p = 0; p < ksub; ++p) s = s + p0[(size_t)p * count];
-    C[idx] = s;
+    C[idx] = alpha * s;
   }
 }
 
@@ -582,28 +582,33 @@ __global__ __launch_bounds__(256) void k_transpose_convert(const Cx<double>* __r
     if (j0 + r < m && i0 + tx < m) dst[(size_t)(j0 + r) * m + i0 + tx] = ccast<T>(tile[tx][r]);
 }
 
-// Row-permuted coupling matrix of one node: with G[sg] = V_sg^H W_sg (r x r)
-// for the node's halves sg = 2k (first) and 2k + 1 (second), the Woodbury
-// core K = [[I, -G[2k+1]], [-G[2k], I]] with its two row blocks swapped:
-// out[k] = [[-G[2k], I], [I, -G[2k+1]]] (2r x 2r).  Its inverse is K^{-1} P
-// (P the half swap), which applies K^{-1} to the segment-ordered products.
-__global__ void k_pk_assemble(const Cx<double>* __restrict__ G, Cx<double>* __restrict__ out, int r, int nodes) {
-  const int m = 2 * r;
-  const size_t per = (size_t)m * m, total = per * nodes;
+// out_b[i][j] = delta_ij for an r x r block (leading dimension ld, batch stride st)
+__global__ void k_set_identity(Cx<double>* __restrict__ out, size_t ld, size_t st, int r, int batch) {
+  const size_t per = (size_t)r * r, total = per * batch;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
-    const size_t k = idx / per;
-    const int i = (int)(idx % per) / m, j = (int)(idx % per) % m;
-    const int hi = i >= r, hj = j >= r, ii = i % r, jj = j % r;
-    Cx<double> v;
-    if (hi == hj) {
-      const Cx<double> g = G[((2 * k + hi) * r + ii) * r + jj];
-      v = Cx<double>{-g.re, -g.im};
-    } else {
-      v = Cx<double>{ii == jj ? 1.0 : 0.0, 0.0};
-    }
-    out[idx] = v;
+    const size_t b = idx / per;
+    const int i = (int)(idx % per) / r, j = (int)(idx % per) % r;
+    out[b * st + (size_t)i * ld + j] = Cx<double>{i == j ? 1.0 : 0.0, 0.0};
   }
+}
+
+// dev[b] = max_ij |P_b[i][j] - delta_ij| (one workgroup per batch entry)
+__global__ __launch_bounds__(256) void k_identity_deviation(const Cx<double>* __restrict__ P, size_t ld, size_t st,
+                                                             int r, double* __restrict__ dev) {
+  const Cx<double>* pb = P + (size_t)blockIdx.x * st;
+  double m = 0.0;
+  for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) {
+    const int i = idx / r, j = idx % r;
+    const Cx<double> v = pb[(size_t)i * ld + j];
+    const double re = v.re - (i == j ? 1.0 : 0.0);
+    m = fmax(m, sqrt(re * re + v.im * v.im));
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) dev[blockIdx.x] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 // Batched complex GEMM on MFMA: C_b = alpha A_b B_b + beta C_b, row-major,
@@ -752,7 +757,7 @@ hipError_t launch_philox_normal(Cx<T>* out, int nvec, size_t n, uint64_t seed, h
 
 template <typename T>
 hipError_t launch_gemm_ah_b_seg(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n, size_t seg,
-                                Cx<double>* C, Cx<double>* part, int ksub, hipStream_t s) {
+                                Cx<double>* C, Cx<double>* part, int ksub, hipStream_t s, double alpha) {
   if (na <= 0 || nb <= 0) return hipSuccess;
   if (seg == 0 || seg > n) seg = n;
   const int nseg = (int)((n + seg - 1) / seg);
@@ -765,14 +770,14 @@ hipError_t launch_gemm_ah_b_seg(const Cx<T>* A, int na, const Cx<T>* B, const in
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((size_t)na * nb * nseg, 2048)), dim3(256), 0, s, part, ksub, nseg,
-                     (size_t)na * nb, C);
+                     (size_t)na * nb, C, alpha);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gemm_ah_b(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n,
                             Cx<double>* C, Cx<double>* part, int ksplit, hipStream_t s) {
-  return launch_gemm_ah_b_seg<T>(A, na, B, vidx, nb, n, n, C, part, ksplit, s);
+  return launch_gemm_ah_b_seg<T>(A, na, B, vidx, nb, n, n, C, part, ksplit, s, 1.0);
 }
 
 template <typename T>
@@ -853,13 +858,6 @@ hipError_t launch_transpose_convert(const Cx<double>* in, Cx<T>* out, int m, int
   return hipGetLastError();
 }
 
-hipError_t launch_pk_assemble(const Cx<double>* G, Cx<double>* out, int r, int nodes, hipStream_t s) {
-  const size_t total = (size_t)4 * r * r * nodes;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pk_assemble, dim3(grid1(total, 8192)), dim3(256), 0, s, G, out, r, nodes);
-  return hipGetLastError();
-}
-
 template <typename T>
 hipError_t launch_bgemm(const Cx<T>* A, size_t lda, size_t sA, const Cx<T>* B, size_t ldb, size_t sB, Cx<T>* C,
                         size_t ldc, size_t sC, const int* mapa, const int* mapc, int M, int N, int K, double alpha,
@@ -868,6 +866,20 @@ hipError_t launch_bgemm(const Cx<T>* A, size_t lda, size_t sA, const Cx<T>* B, s
   const dim3 grid((N + GM_T - 1) / GM_T, (M + GM_T - 1) / GM_T, batch);
   hipLaunchKernelGGL((k_bgemm_mfma<T>), grid, dim3(256), 0, s, A, lda, sA, B, ldb, sB, C, ldc, sC, mapa, mapc, M, N,
                      K, (T)alpha, (T)beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_identity(Cx<double>* out, size_t ld, size_t st, int r, int batch, hipStream_t s) {
+  const size_t total = (size_t)r * r * batch;
+  if (total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_set_identity, dim3(grid1(total, 8192)), dim3(256), 0, s, out, ld, st, r, batch);
+  return hipGetLastError();
+}
+
+hipError_t launch_identity_deviation(const Cx<double>* P, size_t ld, size_t st, int r, int batch, double* dev,
+                                     hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_identity_deviation, dim3(batch), dim3(256), 0, s, P, ld, st, r, dev);
   return hipGetLastError();
 }
 
@@ -888,7 +900,7 @@ hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, 
   template hipError_t launch_gemm_ah_b<T>(const Cx<T>*, int, const Cx<T>*, const int*, int, size_t, Cx<double>*,    \
                                           Cx<double>*, int, hipStream_t);                                           \
   template hipError_t launch_gemm_ah_b_seg<T>(const Cx<T>*, int, const Cx<T>*, const int*, int, size_t, size_t,     \
-                                              Cx<double>*, Cx<double>*, int, hipStream_t);                          \
+                                              Cx<double>*, Cx<double>*, int, hipStream_t, double);                  \
   template hipError_t launch_gemm_update<T>(const Cx<T>*, int, const Cx<double>*, int, const Cx<T>*, const Cx<T>*, \
                                             double, Cx<T>*, const int*, size_t, hipStream_t);                       \
   template hipError_t launch_gemm_update_seg<T>(const Cx<T>*, int, const Cx<double>*, size_t, int, const Cx<T>*,   \

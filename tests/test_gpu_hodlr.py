@@ -33,16 +33,17 @@ def probe_rows(levels, r, n, seed):
     return synth.random_vectors((levels * r, n), seed).real.copy()
 
 
-@pytest.mark.parametrize("dtype,levels,r,tol", [(lsop.C128, 2, 12, 1e-10), (lsop.C128, 5, 8, 1e-10),
-                                                (lsop.C128, 6, 6, 1e-10), (lsop.C64, 3, 12, 1e-4)])
-def test_hodlr_apply_matches_oracle(dtype, levels, r, tol):
-    announce(f"hodlr apply dtype={dtype} levels={levels} r={r}")
+@pytest.mark.parametrize("dtype,levels,r,q,tol", [(lsop.C128, 2, 12, 0, 1e-10), (lsop.C128, 5, 8, 0, 1e-10),
+                                                  (lsop.C128, 6, 6, 0, 1e-10), (lsop.C128, 3, 10, 1, 1e-10),
+                                                  (lsop.C64, 3, 12, 0, 1e-4)])
+def test_hodlr_apply_matches_oracle(dtype, levels, r, q, tol):
+    announce(f"hodlr apply dtype={dtype} levels={levels} r={r} q={q}")
     w = layered(64)
     prob = O.Problem(w.vel, w.h, w.freq, w.c0)
     om = probe_rows(levels, r, prob.n, 21)
-    hs = HD.HodlrSolve(prob, r, levels, probes=lambda d: om[d * r:(d + 1) * r])
+    hs = HD.HodlrSolve(prob, r, levels, probes=lambda d: om[d * r:(d + 1) * r], q=q)
     op = make_op(w, dtype, 8)
-    pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=r, levels=levels)
+    pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=r, levels=levels, power_iters=q)
     pc.build(torch.as_tensor(om).cuda())
     x = synth.random_vectors((5, 64, 64), 9)
     tdt = torch.complex128 if dtype == lsop.C128 else torch.complex64

@@ -100,3 +100,17 @@ def test_explicit_probes_match_seeded_draws():
     P = root.u12 @ root.u12.conj().T
     assert np.linalg.norm(P @ Y - Y) <= 1e-12 * np.linalg.norm(Y)
     assert rel(root.u12 @ root.v12.conj().T, P @ A[i1, i2]) < 1e-13
+
+
+def test_power_iteration_improves_block_and_keeps_fixed_point():
+    """q = 1 (Alg. 1 step 4) tightens each off-diagonal block; the series still reaches the LU solution."""
+    w, prob = small(32)
+    A = O.operator_matrix(prob.K, prob.chi)
+    hs0 = HD.HodlrSolve(prob, 6, 2, seed=3)
+    hs1 = HD.HodlrSolve(prob, 6, 2, seed=3, q=1)
+    e0 = np.linalg.norm(hs0.approx.to_dense() - A, 2)
+    e1 = np.linalg.norm(hs1.approx.to_dense() - A, 2)
+    assert e1 < e0
+    psi0 = prob.incident(w.src_i, w.src_j)[0]
+    psi, it, r, st = O.series_solve(prob, hs1.apply, psi0, 1e-12, 80)
+    assert st == O.OK and rel(psi, O.solve_direct(prob, psi0)) < 1e-10
