@@ -222,12 +222,13 @@ int check_op(const lsop_op* op) {
 // written to Q; Y is overwritten.  Columns are taken in blocks of 64: each
 // block is first projected out of the previous blocks' basis twice (block
 // classical Gram-Schmidt), then orthonormalised by Cholesky-QR run twice in the
-// metric of its FP64 Gram matrix, numerically dependent columns dropped.
-// G, X: FP64 scratch of nseg * r * 64 entries each; kept[(block) * nseg + sg]
-// receives the kept column counts of the final pass.
+// metric of its FP64 Gram matrix.  A column is dropped (numerically
+// dependent) when its remaining norm falls below a fixed fraction of its norm
+// before any projection.  G, X, R: FP64 scratch of nseg * r * 64 entries each;
+// kept[(block) * nseg + sg] receives the kept column counts of the final pass.
 template <typename T>
 int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int ksub, Cx<double>* G, Cx<double>* X,
-                Cx<double>* part, int* kept, hipStream_t s) {
+                Cx<double>* R, Cx<double>* part, int* kept, hipStream_t s) {
   constexpr int B = 64;
   const double tol = std::is_same<T, float>::value ? 1e-9 : 1e-24;
   const double e = sizeof(Cx<T>);
@@ -235,6 +236,11 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
     const int kb = std::min(B, r - c0);
     Cx<T>* Yb = Y + (size_t)c0 * n;
     Cx<T>* Qb = Q + (size_t)c0 * n;
+    if (c0 > 0) {  // reference Gram of the block before projection
+      LSOP_HIP(prof("orth_gram", 2.0 * kb * n * e, 8.0 * kb * kb * (double)n, kb, s, [&] {
+        return launch_gemm_ah_b_seg<T>(Yb, kb, Yb, nullptr, kb, n, seg, R, part, ksub, s, 1.0);
+      }));
+    }
     for (int pass = 0; pass < 2 && c0 > 0; ++pass) {
       LSOP_HIP(prof("orth_project_ah_b", (double)(c0 + kb) * n * e, 8.0 * c0 * kb * (double)n, kb, s, [&] {
         return launch_gemm_ah_b_seg<T>(Q, c0, Yb, nullptr, kb, n, seg, G, part, ksub, s, -1.0);
@@ -249,7 +255,8 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
       LSOP_HIP(prof("orth_gram", 2.0 * kb * n * e, 8.0 * kb * kb * (double)n, kb, s, [&] {
         return launch_gemm_ah_b_seg<T>(src, kb, src, nullptr, kb, n, seg, G, part, ksub, s, 1.0);
       }));
-      LSOP_HIP(launch_gram_orth(G, X, kb, pass == 0 ? tol : 1e-6, kept + (c0 / B) * nseg, s, nseg));
+      LSOP_HIP(launch_gram_orth(G, X, kb, pass == 0 ? tol : 1e-6, kept + (c0 / B) * nseg, s, nseg,
+                                (pass == 0 && c0 > 0) ? R : nullptr));
       LSOP_HIP(prof("orth_update", 2.0 * kb * n * e, 8.0 * kb * kb * (double)n, kb, s, [&] {
         return launch_gemm_update_seg<T>(src, kb, X, (size_t)kb * kb, kb, nullptr, nullptr, 0.0, dst, nullptr, n, seg,
                                          s);
@@ -267,7 +274,8 @@ int orth_impl(lsop_precond* pc, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s) {
   const size_t n = pc->op->n();
   Cx<double>* G = pc->small;
   Cx<double>* X = G + (size_t)r * r;
-  return orth_blocks<T>(Yin, Qout, r, n, n, 1, pc->ksplit, G, X, pc->part, pc->dflag, s);
+  Cx<double>* R = X + (size_t)r * r;
+  return orth_blocks<T>(Yin, Qout, r, n, n, 1, pc->ksplit, G, X, R, pc->part, pc->dflag, s);
 }
 
 template <typename T>
@@ -438,7 +446,7 @@ int hodlr_orth(lsop_precond* pc, int lv, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s)
   const int W = pc->lev[lv].width, nseg = 2 * (pc->op->nx / W);
   const size_t seg = (size_t)(W / 2) * pc->op->nz;
   return orth_blocks<T>(Yin, Qout, pc->rank, pc->op->n(), seg, nseg, hodlr_ksub(pc, seg, nseg), pc->hG, pc->hX,
-                        pc->part, pc->hflag, s);
+                        pc->hK, pc->part, pc->hflag, s);
 }
 
 // In-place inverse of the m x m block at offset o of each of cnt FP64
@@ -551,7 +559,10 @@ int hodlr_apply(lsop_precond* pc, const Cx<T>* x, const int* xidx, Cx<T>* y, con
       LSOP_HIP(prof("hodlr_gemm_ah_b", (double)(r + m) * n * e, 8.0 * r * m * (double)n, m, s, [&] {
         return launch_gemm_ah_b_seg<T>(V, r, yb, yc, m, n, seg, pc->hG, pc->part, ksub, s);
       }));
-      LSOP_HIP(launch_small_gemm(L.kinv, pc->hG, pc->hX, 2 * r, m, 1.0, s, nodes));
+      LSOP_HIP(prof("hodlr_core_apply", 0.0, 32.0 * r * r * (double)m * nodes, m, s, [&] {
+        return launch_bgemm<double>(L.kinv, 2 * r, (size_t)4 * r * r, pc->hG, m, (size_t)2 * r * m, pc->hX, m,
+                                    (size_t)2 * r * m, nullptr, nullptr, 2 * r, m, 2 * r, 1.0, 0.0, nodes, s);
+      }));
       LSOP_HIP(prof("hodlr_gemm_update", (double)r * n * e + 2.0 * m * (double)n * e, 8.0 * r * m * (double)n, m, s,
                     [&] {
                       return launch_gemm_update_seg<T>(Wp, r, pc->hX, (size_t)r * m, m, yb, nullptr, 0.0, yb, yc, n,

@@ -101,9 +101,10 @@ template <typename T>
 hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<double>* M, size_t mstride, int nb,
                                   const Cx<T>* X1, const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n,
                                   size_t seg, hipStream_t s);
-// small FP64 dense kernels (one workgroup per batch entry, entries na * na apart)
+// small FP64 dense kernels (one workgroup per batch entry, entries na * na apart); gram_orth: na <= 64
+// gref (optional): Gram matrices whose diagonals are the drop references (default: G's own)
 hipError_t launch_gram_orth(const Cx<double>* G, Cx<double>* X, int na, double drop_tol, int* kept, hipStream_t s,
-                            int batch = 1);
+                            int batch = 1, const Cx<double>* gref = nullptr);
 // Z_b = (I - M_b)^{-1} (plain = false) or M_b^{-1} (plain = true); M_b = M + b * sm (leading dimension ldm),
 // Z_b likewise (may alias M_b); work: batch * 2 na^2 complex doubles when na > 64; singular[b] set to 1 on
 // failure (the caller clears it).

@@ -327,101 +327,114 @@ __global__ __launch_bounds__(256) void k_gemm_update_mfma(const Cx<T>* __restric
 }
 
 // ------------------------------------------------------- small FP64 kernels
-// Orthonormalising coefficients X (na x na) for Q = Y X from the Gram matrix
-// G = Y^H Y: column k of X is e_k projected twice (classical Gram-Schmidt in
-// the G inner product) against the kept columns, then normalised; columns
-// whose remaining G-norm^2 is <= drop_tol * G_kk are zeroed (dropped).
-// G and X point to LDS copies (na <= SMALL_NA) or to global memory.
+// Orthonormalising coefficients X (na x na, na <= 64) for Q = Y X from the
+// Gram matrix G = Y^H Y: column k of X is e_k projected twice (classical
+// Gram-Schmidt in the G inner product) against the kept columns, then
+// normalised; columns whose remaining G-norm^2 is <= drop_tol * R_kk are
+// zeroed (dropped), R = gref (the Gram matrix of the columns before an earlier
+// projection) or G itself.  One workgroup of four waves per batch entry b
+// (G_b, X_b, R_b at b * na * na, kept[b]).  LDS layouts are chosen so that lane i always reads
+// consecutive addresses: G x uses the Hermitian symmetry (G[i][l] = conj G[l][i]),
+// X is held column-major, and the projections X^H w are wavefront reductions.
 constexpr int SMALL_NA = 64;
 
-__device__ __forceinline__ void gram_orth_body(const Cx<double>* G, Cx<double>* X, int na, double drop_tol,
-                                               Cx<double>* x, Cx<double>* w, Cx<double>* cf, double* red,
-                                               int* nkept_out) {
-  const int t = threadIdx.x;
-  for (int i = t; i < na * na; i += blockDim.x) X[i] = czero<double>();
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_gram_orth_lds(const Cx<double>* __restrict__ Gg, Cx<double>* __restrict__ Xg,
+                                                        int na, double drop_tol, int* kept,
+                                                        const Cx<double>* __restrict__ gref) {
+  __shared__ Cx<double> G[SMALL_NA * SMALL_NA], Xc[SMALL_NA * SMALL_NA];
+  __shared__ Cx<double> x[SMALL_NA], w[SMALL_NA], cf[SMALL_NA];
+  __shared__ double nrm_s;
+  const size_t off = (size_t)blockIdx.x * na * na;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  for (int i = t; i < na * na; i += blockDim.x) G[i] = Gg[off + i];
   __syncthreads();
   int nkept = 0;
   for (int k = 0; k < na; ++k) {
-    for (int i = t; i < na; i += blockDim.x) x[i] = Cx<double>{i == k ? 1.0 : 0.0, 0.0};
+    if (t < na) x[t] = Cx<double>{t == k ? 1.0 : 0.0, 0.0};
     __syncthreads();
     for (int pass = 0; pass < 3; ++pass) {
-      // w = G x
-      for (int i = t; i < na; i += blockDim.x) {
-        Cx<double> s = czero<double>();
-        for (int l = 0; l < na; ++l) s = s + G[(size_t)i * na + l] * x[l];
-        w[i] = s;
+      if (t < na) {  // w = G x
+        Cx<double> acc = czero<double>();
+        for (int l = 0; l < na; ++l) acc = acc + cmul_conj(G[l * na + t], x[l]);
+        w[t] = acc;
       }
       __syncthreads();
       if (pass == 2) break;
-      // cf_j = X[:, j]^H w for j < k
-      for (int j = t; j < k; j += blockDim.x) {
-        Cx<double> s = czero<double>();
-        for (int i = 0; i < na; ++i) s = s + cmul_conj(X[(size_t)i * na + j], w[i]);
-        cf[j] = s;
+      for (int j = wv; j < k; j += 4) {  // cf_j = X[:, j]^H w
+        Cx<double> v = lane < na ? cmul_conj(Xc[j * SMALL_NA + lane], w[lane]) : czero<double>();
+        const double re = wave_sum(v.re), im = wave_sum(v.im);
+        if (lane == 0) cf[j] = Cx<double>{re, im};
       }
       __syncthreads();
-      // x -= X[:, :k] cf
-      for (int i = t; i < na; i += blockDim.x) {
-        Cx<double> s = czero<double>();
-        for (int j = 0; j < k; ++j) s = s + X[(size_t)i * na + j] * cf[j];
-        x[i] = x[i] - s;
+      if (t < na) {  // x -= X[:, :k] cf
+        Cx<double> acc = czero<double>();
+        for (int j = 0; j < k; ++j) acc = acc + Xc[j * SMALL_NA + t] * cf[j];
+        x[t] = x[t] - acc;
       }
       __syncthreads();
     }
-    // nrm2 = x^H G x = x^H w
-    double part = 0.0;
-    for (int i = t; i < na; i += blockDim.x) part += x[i].re * w[i].re + x[i].im * w[i].im;
-    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-    if ((t & 63) == 0) red[t >> 6] = part;
+    if (wv == 0) {  // nrm2 = x^H G x = x^H w
+      const double v = lane < na ? x[lane].re * w[lane].re + x[lane].im * w[lane].im : 0.0;
+      const double sum = wave_sum(v);
+      if (lane == 0) nrm_s = sum;
+    }
     __syncthreads();
-    double nrm2 = 0.0;
-    for (int i = 0; i < (int)(blockDim.x / 64); ++i) nrm2 += red[i];
-    const double gkk = G[(size_t)k * na + k].re;
+    const double nrm2 = nrm_s, gkk = gref ? gref[off + (size_t)k * na + k].re : G[k * na + k].re;
     const bool keep = gkk > 1e-300 && nrm2 > drop_tol * gkk;
     const double sc = keep ? 1.0 / sqrt(nrm2) : 0.0;
-    for (int i = t; i < na; i += blockDim.x) X[(size_t)i * na + k] = sc * x[i];
+    if (t < na) Xc[k * SMALL_NA + t] = sc * x[t];
     nkept += keep ? 1 : 0;
     __syncthreads();
   }
-  *nkept_out = nkept;
+  for (int idx = t; idx < na * na; idx += blockDim.x) {
+    const int i = idx / na, j = idx % na;
+    Xg[off + idx] = Xc[j * SMALL_NA + i];
+  }
+  if (t == 0) kept[blockIdx.x] = nkept;
 }
 
-// One workgroup per batch entry b: G_b, X_b at b * na * na, kept[b].
-__global__ __launch_bounds__(256) void k_gram_orth_lds(const Cx<double>* __restrict__ Gg, Cx<double>* __restrict__ Xg,
-                                                        int na, double drop_tol, int* kept) {
-  __shared__ Cx<double> G[SMALL_NA * SMALL_NA], X[SMALL_NA * SMALL_NA];
-  __shared__ Cx<double> x[SMALL_NA], w[SMALL_NA], cf[SMALL_NA];
-  __shared__ double red[4];
-  const size_t off = (size_t)blockIdx.x * na * na;
-  for (int i = threadIdx.x; i < na * na; i += blockDim.x) G[i] = Gg[off + i];
+// max over the workgroup of (value, index), lowest index on ties; red / redi
+// hold one entry per wavefront; the result is returned to every thread.
+__device__ __forceinline__ void block_argmax(double v, int i, double* red, int* redi, double* vo, int* io) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(v, o);
+    const int oi = __shfl_xor(i, o);
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+  const int nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = v;
+    redi[threadIdx.x >> 6] = i;
+  }
   __syncthreads();
-  int nk = 0;
-  gram_orth_body(G, X, na, drop_tol, x, w, cf, red, &nk);
-  for (int i = threadIdx.x; i < na * na; i += blockDim.x) Xg[off + i] = X[i];
-  if (threadIdx.x == 0) kept[blockIdx.x] = nk;
+  v = red[0];
+  i = redi[0];
+  for (int q = 1; q < nw; ++q)
+    if (red[q] > v || (red[q] == v && redi[q] < i)) {
+      v = red[q];
+      i = redi[q];
+    }
+  *vo = v;
+  *io = i;
+  __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_gram_orth(const Cx<double>* __restrict__ G, Cx<double>* __restrict__ X,
-                                                    int na, double drop_tol, int* kept) {
-  extern __shared__ unsigned char smem_raw[];
-  Cx<double>* x = reinterpret_cast<Cx<double>*>(smem_raw);  // [na]
-  Cx<double>* w = x + na;                                    // [na] = G x
-  Cx<double>* cf = w + na;                                   // [na] projections
-  __shared__ double red[4];
-  const size_t off = (size_t)blockIdx.x * na * na;
-  int nk = 0;
-  gram_orth_body(G + off, X + off, na, drop_tol, x, w, cf, red, &nk);
-  if (threadIdx.x == 0) kept[blockIdx.x] = nk;
-}
-
-// Inverse by Gauss-Jordan with partial pivoting on work = [B | I], where
-// B = I - M (plain = 0, eq. 12) or B = M (plain = 1).  M has leading dimension
-// ldm, Z ldz (Z may alias M).  work is in LDS for na <= SMALL_NA, else in
-// global memory.  *singular is set to 1 on a vanishing pivot (never cleared
-// here, so one flag can collect several calls).
+// Inverse by Gauss-Jordan with partial pivoting on work = [B | I] (row stride
+// wld >= 2 na), where B = I - M (plain = 0, eq. 12) or B = M (plain = 1).  M
+// has leading dimension ldm, Z ldz (Z may alias M).  *singular is set to 1 on
+// a vanishing pivot (never cleared here, so one flag can collect several
+// calls).
 __device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, size_t ldm, Cx<double>* Z, size_t ldz,
-                                                Cx<double>* work, int na, int plain, int* singular, Cx<double>* fcol,
-                                                double* best, int* bidx, double* scale_s) {
+                                                Cx<double>* work, int wld, int na, int plain, int* singular,
+                                                Cx<double>* fcol, double* red, int* redi) {
   const int t = threadIdx.x, w2 = 2 * na;
   double amax = 0.0;
   for (int idx = t; idx < na * w2; idx += blockDim.x) {
@@ -433,87 +446,69 @@ __device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, size_t ldm,
     } else {
       v = Cx<double>{(i == j - na) ? 1.0 : 0.0, 0.0};
     }
-    work[idx] = v;
+    work[(size_t)i * wld + j] = v;
     if (j < na) amax = fmax(amax, sqrt(norm2(v)));
   }
-  best[t] = amax;
-  __syncthreads();
-  if (t == 0) {
-    double m = 0.0;
-    for (int i = 0; i < (int)blockDim.x; ++i) m = fmax(m, best[i]);
-    *scale_s = m;
-  }
-  __syncthreads();
-  const double scale = *scale_s;
+  double scale;
+  int dummy;
+  block_argmax(amax, 0, red, redi, &scale, &dummy);
   for (int k = 0; k < na; ++k) {
     double bv = -1.0;
     int bi = k;
     for (int i = k + t; i < na; i += blockDim.x) {
-      const double v = norm2(work[(size_t)i * w2 + k]);
+      const double v = norm2(work[(size_t)i * wld + k]);
       if (v > bv) {
         bv = v;
         bi = i;
       }
     }
-    best[t] = bv;
-    bidx[t] = bi;
-    __syncthreads();
-    if (t == 0) {
-      double m = -1.0;
-      int mi = k;
-      for (int i = 0; i < (int)blockDim.x; ++i)
-        if (best[i] > m) {
-          m = best[i];
-          mi = bidx[i];
-        }
-      bidx[0] = mi;
-      best[0] = m;
-    }
-    __syncthreads();
-    const int p = bidx[0];
-    const double piv2 = best[0];
+    double piv2;
+    int p;
+    block_argmax(bv, bi, red, redi, &piv2, &p);
     if (!(sqrt(piv2) > 1e-14 * scale)) {
       if (t == 0) *singular = 1;
       return;  // uniform across the workgroup
     }
     if (p != k) {
       for (int j = t; j < w2; j += blockDim.x) {
-        const Cx<double> a = work[(size_t)k * w2 + j];
-        work[(size_t)k * w2 + j] = work[(size_t)p * w2 + j];
-        work[(size_t)p * w2 + j] = a;
+        const Cx<double> a = work[(size_t)k * wld + j];
+        work[(size_t)k * wld + j] = work[(size_t)p * wld + j];
+        work[(size_t)p * wld + j] = a;
       }
     }
     __syncthreads();
-    const Cx<double> pv = work[(size_t)k * w2 + k];
+    const Cx<double> pv = work[(size_t)k * wld + k];
     const double d = 1.0 / norm2(pv);
     const Cx<double> inv = Cx<double>{pv.re * d, -pv.im * d};
     __syncthreads();
-    for (int j = t; j < w2; j += blockDim.x) work[(size_t)k * w2 + j] = work[(size_t)k * w2 + j] * inv;
-    for (int i = t; i < na; i += blockDim.x) fcol[i] = work[(size_t)i * w2 + k];
+    for (int j = t; j < w2; j += blockDim.x) work[(size_t)k * wld + j] = work[(size_t)k * wld + j] * inv;
+    for (int i = t; i < na; i += blockDim.x) fcol[i] = work[(size_t)i * wld + k];
     __syncthreads();
     for (int idx = t; idx < na * w2; idx += blockDim.x) {
       const int i = idx / w2, j = idx % w2;
-      if (i != k) work[idx] = work[idx] - fcol[i] * work[(size_t)k * w2 + j];
+      if (i != k) work[(size_t)i * wld + j] = work[(size_t)i * wld + j] - fcol[i] * work[(size_t)k * wld + j];
     }
     __syncthreads();
   }
   for (int idx = t; idx < na * na; idx += blockDim.x) {
     const int i = idx / na, j = idx % na;
-    Z[(size_t)i * ldz + j] = work[(size_t)i * w2 + na + j];
+    Z[(size_t)i * ldz + j] = work[(size_t)i * wld + na + j];
   }
 }
 
-// Batch entry b = blockIdx.x: M + b * sm, Z + b * sz, singular[b].
+// Batch entry b = blockIdx.x: M + b * sm, Z + b * sz, singular[b].  The LDS
+// work rows have an odd stride (conflict-free column reads).
+constexpr int LU_WLD = 2 * SMALL_NA + 1;
+
 __global__ __launch_bounds__(256) void k_lu_inverse_lds(const Cx<double>* __restrict__ M, size_t ldm, size_t sm,
                                                          Cx<double>* Z, size_t ldz, size_t sz, int na, int plain,
                                                          int* singular) {
-  __shared__ Cx<double> work[SMALL_NA * 2 * SMALL_NA];
+  __shared__ Cx<double> work[SMALL_NA * LU_WLD];
   __shared__ Cx<double> fcol[SMALL_NA];
-  __shared__ double best[256];
-  __shared__ int bidx[256];
-  __shared__ double scale;
+  __shared__ double red[4];
+  __shared__ int redi[4];
   const size_t b = blockIdx.x;
-  lu_inverse_body(M + b * sm, ldm, Z + b * sz, ldz, work, na, plain, singular + b, fcol, best, bidx, &scale);
+  lu_inverse_body(M + b * sm, ldm, Z + b * sz, ldz, work, LU_WLD, na, plain, singular + b, fcol, red, redi);
 }
 
 __global__ __launch_bounds__(256) void k_lu_inverse_i_minus(const Cx<double>* __restrict__ M, size_t ldm, size_t sm,
@@ -522,12 +517,11 @@ __global__ __launch_bounds__(256) void k_lu_inverse_i_minus(const Cx<double>* __
                                                              int* singular) {
   extern __shared__ unsigned char smem_raw[];
   Cx<double>* fcol = reinterpret_cast<Cx<double>*>(smem_raw);  // [na]
-  __shared__ double best[256];
-  __shared__ int bidx[256];
-  __shared__ double scale;
+  __shared__ double red[4];
+  __shared__ int redi[4];
   const size_t b = blockIdx.x;
-  lu_inverse_body(M + b * sm, ldm, Z + b * sz, ldz, work + b * 2 * (size_t)na * na, na, plain, singular + b, fcol,
-                  best, bidx, &scale);
+  lu_inverse_body(M + b * sm, ldm, Z + b * sz, ldz, work + b * 2 * (size_t)na * na, 2 * na, na, plain, singular + b,
+                  fcol, red, redi);
 }
 
 // C_b = alpha * A_b (na x na) B_b (na x nb); batch entry b = blockIdx.y.
@@ -808,13 +802,10 @@ hipError_t launch_gemm_update(const Cx<T>* A, int na, const Cx<double>* M, int n
 }
 
 hipError_t launch_gram_orth(const Cx<double>* G, Cx<double>* X, int na, double drop_tol, int* kept, hipStream_t s,
-                            int batch) {
+                            int batch, const Cx<double>* gref) {
   if (batch <= 0) return hipSuccess;
-  if (na <= SMALL_NA)
-    hipLaunchKernelGGL(k_gram_orth_lds, dim3(batch), dim3(256), 0, s, G, X, na, drop_tol, kept);
-  else
-    hipLaunchKernelGGL(k_gram_orth, dim3(batch), dim3(256), sizeof(Cx<double>) * 3 * na, s, G, X, na, drop_tol,
-                       kept);
+  if (na < 1 || na > SMALL_NA) return hipErrorInvalidValue;  // callers orthonormalise in blocks of <= 64 columns
+  hipLaunchKernelGGL(k_gram_orth_lds, dim3(batch), dim3(256), 0, s, G, X, na, drop_tol, kept, gref);
   return hipGetLastError();
 }
 
