@@ -3,17 +3,20 @@
 
 One step is one pass of the whole path over one batch: set the medium
 (contrast, FP64 kernel table, circulant spectrum), form the incident fields of
-all sources, build the randomized low-rank preconditioner (Alg. 2 + eq. 12),
-and run the preconditioned scattering series (eq. 11) for every source to the
-relative residual target.  Inputs (velocity grid, source positions) are
-resident before the timed region.  The default workload is the 1024 x 1024
-grid at h = 5 m and 25 Hz with 128 sources on the top row and 64 probes,
-computed in complex FP32 (QR / LU in FP64).
+all sources, build the preconditioner, and run the preconditioned scattering
+series (eq. 11) for every source to the relative residual target.  Inputs
+(velocity grid, source positions) are resident before the timed region.  The
+default workload is the 1024 x 1024 grid at h = 5 m and 25 Hz with 128
+sources on the top row, computed in complex FP32 (QR / LU / leaf inverses in
+FP64), with the HODLR preconditioner of Section 2.4 (rank 256, 10 levels, one
+power iteration per block); `--pc lowrank` selects the rank-r preconditioner
+of Section 2.3 instead.
 
 Printed: one JSON line with the solves/s of sources that reached the target,
-the dominant kernel's roofline position (event-timed inside the timed
-region), the batched operator throughput, and the FP64 oracle timed on a
-bounded sample of the same workload on the host cores.
+the dominant kernel's roofline position (event-timed inside the timed region,
+per kernel function), the FFT-convolution throughput of the LS operator, and
+the FP64 oracle timed on a bounded sample of the same workload on the host
+cores.
 """
 import argparse
 import json
@@ -26,6 +29,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "LS solves/s to rel. residual 1e-6 at 1024^2 x128 src; FFT-conv HBM GB/s"
 HBM_PEAK_GBPS = 8000.0
+MFMA_PEAK_TFLOPS = {"float": 157.3, "double": 78.6}   # dense matrix-core peaks (fp32, fp64)
+VALU_PEAK_TFLOPS = {"float": 157.3, "double": 78.6}
 
 
 def parse():
@@ -35,79 +40,142 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1024, help="grid side (default: the 1024^2 workload)")
     ap.add_argument("--nsrc", type=int, default=128)
-    ap.add_argument("--rank", type=int, default=64)
+    ap.add_argument("--pc", choices=("hodlr", "lowrank"), default="hodlr")
+    ap.add_argument("--rank", type=int, default=None, help="probes per block (default 256 hodlr, 64 lowrank)")
+    ap.add_argument("--levels", type=int, default=10)
+    ap.add_argument("--power-iters", type=int, default=None, help="default 1 hodlr, 0 lowrank")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sources", type=int, default=2, help="sources in the oracle's timed sample")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device-to-device (a plain copy of known size for rocprofv3 --pmc scaling)")
-    return ap.parse_args()
+    ap.add_argument("--dump-profile", default=None,
+                    help="write the per-kernel-function event profile of the timed region to this JSON file")
+    a = ap.parse_args()
+    if a.rank is None:
+        a.rank = 256 if a.pc == "hodlr" else 64
+    if a.power_iters is None:
+        a.power_iters = 1 if a.pc == "hodlr" else 0
+    return a
 
 
 def load_traffic(kernel):
-    """Counter-measured HBM bytes per launch from the committed summary, if it matches the current source."""
+    """Counter-measured HBM bytes over algorithmic bytes for one kernel function, from the committed
+    summary, if it was taken on the current kernel sources."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    k = d.get("kernels", {}).get(kernel)
     from paper_2005_01372_amd.profiling import kernel_source_sha
+    k = d.get("kernels", {}).get(kernel)
     if not k or d.get("source_sha") != kernel_source_sha():
         return None
     return k.get("hbm_over_algorithmic")
 
 
-def cpu_baseline(w, rank, iterations, converged, nsrc_sample=2, nprobe_sample=2):
+def roofline_for(name, st):
+    """Roofline position of one kernel function from its event-timed totals."""
+    avg_s = st["ms"] / st["launches"] / 1e3
+    bpl, fpl = st["bytes"] / st["launches"], st["flops"] / st["launches"]
+    t = "double" if "<double" in name else "float"
+    mfma = name.startswith(("k_bgemm_mfma", "k_gemm_ah_b_mfma", "k_gemm_update_mfma"))
+    small = name.startswith(("k_lu_inverse", "k_gram_orth"))
+    out = {"kernel": name, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": st["launches"],
+           "algorithmic_bytes_per_launch": bpl, "algorithmic_flops_per_launch": fpl}
+    if mfma or small:
+        peak_f = (MFMA_PEAK_TFLOPS if mfma else VALU_PEAK_TFLOPS)["double" if small else t]
+        ridge = peak_f * 1e12 / (HBM_PEAK_GBPS * 1e9)
+        ai = fpl / bpl if bpl > 0 else float("inf")
+        out["arithmetic_intensity"] = round(ai, 2)
+        if ai >= ridge:
+            ach = fpl / avg_s / 1e12
+            out.update(bound="mfma" if mfma else "alu", achieved=round(ach, 2), peak=peak_f, unit="TFLOP/s",
+                       frac=round(ach / peak_f, 4))
+            return out
+    ach = bpl / avg_s / 1e9
+    out.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBPS, unit="GB/s", frac=round(ach / HBM_PEAK_GBPS, 4))
+    return out
+
+
+def cpu_baseline(w, args, iterations, converged, nsrc_sample=2):
     """The FP64 oracle (numpy / scipy, as written) timed on a bounded sample of the same step.
 
-    Sample: the full problem set-up; the two operator applications of Alg. 2
-    (G0 V Omega and V^H G0^H Q) for nprobe_sample of the `rank` probes,
-    extrapolated linearly; one n x rank Householder QR and the SMW core at
-    full size; one series iteration (residual + update with a rank-`rank` H)
-    for nsrc_sample sources, scaled by the number of source-iterations the
-    GPU run of the same method needed.  `converged` sources count as solves.
+    The oracle's HODLR builds a dense matrix and cannot hold the 1024^2 grid,
+    so the step is assembled from the oracle's own primitives, each timed on
+    a sample and scaled by how often the GPU step performs it: problem set-up;
+    the FFT operator application (every sub-domain convolution of a level
+    costs one full-grid application per vector); one dense leaf block and its
+    inverse (numpy.linalg.inv), times the number of leaves; Householder QR
+    (numpy.linalg.qr) of one half-node block per level, times the number of
+    half-nodes; the leaf and low-rank products of one preconditioner
+    application per vector; and the series iterations the GPU run needed.
     """
     import numpy as np
 
     from oracle import lsop_oracle as O
-    from paper_2005_01372_amd import synth
 
     cores = len(os.sched_getaffinity(0))
+    r, L, q = args.rank, args.levels, args.power_iters
     t0 = time.perf_counter()
     prob = O.Problem(w.vel, w.h, w.freq, w.c0)
     prob.workers = cores
     t_setup = time.perf_counter() - t0
-    om = synth.gaussian_probes(prob.n, rank, 3)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((nsrc_sample, prob.nx, prob.nz)) + 0j
     t1 = time.perf_counter()
-    Y = prob.apply(om[:nprobe_sample].reshape(nprobe_sample, prob.nx, prob.nz).astype(np.complex128), "G0V")
-    prob.apply(Y, "VHG0H")
-    t_apply = (time.perf_counter() - t1) * rank / nprobe_sample
-    t2 = time.perf_counter()
-    Q = O.orth(om.T.astype(np.complex128))
-    H = O.LowRankPreconditioner(Q, 1e-3 * Q)   # a rank-`rank` H of the right shapes (SMW core included)
-    t_qr = time.perf_counter() - t2
-    del Y
-    # one series iteration (eq. 13 residual + eq. 11 update) on nsrc_sample sources, timed per source-iteration
-    psi0 = prob.incident(w.src_i[:nsrc_sample], w.src_j[:nsrc_sample])
-    t3 = time.perf_counter()
-    for k in range(nsrc_sample):
-        psi = H.apply(psi0[k])
-        a = prob.apply(psi, "A") - psi0[k]
-        psi = psi - H.apply(a)
-    t_iter = (time.perf_counter() - t3) / nsrc_sample
-    it_total = sum(i + 1 for i in iterations)  # residual evaluations the GPU run needed, all sources
-    step_s = t_setup + t_apply + t_qr + t_iter * it_total
-    return {
-        "value": converged / step_s, "unit": "solves/s", "cores": cores, "kind": "oracle",
-        "sample": f"set-up; Alg. 2 applications for {nprobe_sample} of {rank} probes (x{rank // nprobe_sample}); "
-                  f"one {prob.n}x{rank} QR + SMW core; one series iteration for {nsrc_sample} sources, scaled by the "
-                  f"{it_total} source-iterations of the GPU run (same method, same stopping rule); "
-                  f"scipy.fft workers={cores}",
-        "step_seconds_extrapolated": round(step_s, 2), "setup_s": round(t_setup, 2),
-        "build_s_extrapolated": round(t_apply + t_qr, 2), "seconds_per_source_iteration": round(t_iter, 3),
-    }
+    prob.apply(x, "G0V")
+    t_conv = (time.perf_counter() - t1) / nsrc_sample            # one full-grid convolution, per vector
+    n = prob.n
+    if args.pc == "hodlr":
+        wl = prob.nx >> L
+        nl, nleaf = wl * prob.nz, 1 << L
+        t2 = time.perf_counter()
+        G = O.greens_matrix(prob.K[:wl, :])
+        D = np.eye(nl) - G * prob.chi[:wl].reshape(-1)[None, :]
+        Dinv = np.linalg.inv(D)
+        t_leaf = time.perf_counter() - t2
+        t3 = time.perf_counter()
+        Dinv @ x[0].reshape(-1)[:nl]
+        t_leafmv = (time.perf_counter() - t3) * nleaf                # one vector through all leaves
+        # Householder QR of one half-node block at the middle level, scaled to all half-nodes of every level
+        lv = L // 2
+        seg = (prob.nx >> (lv + 1)) * prob.nz
+        Yb = rng.standard_normal((seg, r)) + 1j * rng.standard_normal((seg, r))
+        t4 = time.perf_counter()
+        np.linalg.qr(Yb)
+        t_qr_level = (time.perf_counter() - t4) * (2 << lv)
+        Vr = rng.standard_normal((r, seg)) + 0j
+        t5 = time.perf_counter()
+        Vr.conj() @ Yb[:, 0]
+        Vr.T @ (Vr.conj() @ Yb[:, 0])
+        t_lr_level = (time.perf_counter() - t5) * (2 << lv)          # V^H y and W s over one level, one vector
+        t_h = t_leafmv + L * t_lr_level                              # one preconditioner application, one vector
+        convs_per_level = (4 + 4 * q) * r    # half-masked sub-domain passes, each a full-grid convolution per vector
+        t_build = nleaf * t_leaf + L * (convs_per_level * t_conv + (1 + 2 * q) * t_qr_level)
+        t_build += sum(r * (t_leafmv + (L - 1 - l) * t_lr_level) for l in range(L))   # W = A_{l+1}^{-1} U per level
+        desc = (f"set-up; one FFT application ({nsrc_sample} vectors); one {nl}x{nl} leaf formed and inverted (x{nleaf});"
+                f" one {seg}x{r} QR (x{2 << lv} half-nodes per level, {1 + 2 * q} per level); leaf and low-rank "
+                f"products of one H application; scaled by the GPU step's counts")
+    else:
+        Yb = rng.standard_normal((n, r)) + 0j
+        t4 = time.perf_counter()
+        np.linalg.qr(Yb)
+        t_qr = time.perf_counter() - t4
+        t5 = time.perf_counter()
+        Yb @ (Yb.conj().T @ x[0].reshape(-1))
+        t_h = time.perf_counter() - t5
+        t_build = 2 * (1 + q) * r * t_conv + (1 + 2 * q) * t_qr
+        desc = (f"set-up; one FFT application ({nsrc_sample} vectors); one {n}x{r} QR; one rank-{r} H application; "
+                f"scaled by the GPU step's counts")
+    it_total = sum(i + 1 for i in iterations)            # residual evaluations, all sources
+    h_total = sum(i + 1 for i in iterations)             # H applications (psi_0 = H psi0 plus one per update)
+    step_s = t_setup + t_build + it_total * t_conv + h_total * t_h
+    return {"value": converged / step_s, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": desc + f"; scipy.fft workers={cores}",
+            "step_seconds_extrapolated": round(step_s, 2), "setup_s": round(t_setup, 2),
+            "build_s_extrapolated": round(t_build, 2), "series_s_extrapolated": round(it_total * t_conv + h_total * t_h, 2)}
 
 
 def main():
@@ -130,32 +198,48 @@ def main():
 
     w = synth.model_random_ellipses(n=args.n, nsrc=args.nsrc)
     vel = torch.as_tensor(w.vel, device="cuda")
-    op = lsop.Operator(w.nx, w.nz, lsop.C64, max_vec=max(args.nsrc, args.rank))
-    pc = lsop.Preconditioner(op, lsop.PC_LOWRANK, rank=args.rank, seed=3)
+    op = lsop.Operator(w.nx, w.nz, lsop.C64, max_vec=max(args.nsrc, 64))
+    if args.pc == "hodlr":
+        pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=args.rank, levels=args.levels, power_iters=args.power_iters,
+                                 seed=3)
+    else:
+        pc = lsop.Preconditioner(op, lsop.PC_LOWRANK, rank=args.rank, power_iters=args.power_iters, seed=3)
     psi = torch.empty((w.nsrc, w.nx, w.nz), dtype=torch.complex64, device="cuda")
     op.set_problem(vel, w.h, w.freq, w.c0)
     op.autotune(w.nsrc)
+    phase = {"build": 0.0, "series": 0.0}
 
     def step():
         op.set_problem(vel, w.h, w.freq, w.c0)
         rhs = op.incident(w.src_i, w.src_j)
-        pc.build(None)
+        t0 = time.perf_counter()
+        pc.build(None)                       # synchronises its stream
+        t1 = time.perf_counter()
         _, info = lsop.series_solve(op, pc, rhs, psi=psi, tol=args.tol, max_iter=args.max_iter)
+        phase["build"] += t1 - t0
+        phase["series"] += time.perf_counter() - t1
         return info
 
     for _ in range(args.warmup):
         step()
+        print(f"[bench] warmup step done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    phase.update(build=0.0, series=0.0)
     lsop.profile_reset()
     lsop.profile_enable(True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         info = step()
+        print(f"[bench] timed step done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     lsop.profile_enable(False)
-    stats = lsop.profile_read()
+    by_use = lsop.profile_read()
+    by_fn = lsop.profile_read(by_kernel=True)
     lsop.profile_reset()
+    if args.dump_profile:
+        with open(args.dump_profile, "w") as f:
+            json.dump({"steps": args.steps, "warmup": args.warmup, "kernels": by_fn}, f, indent=1)
     step_s = (t1 - t0) / args.steps
     converged = sum(i.status == lsop.OK for i in info)
     statuses = {}
@@ -163,48 +247,51 @@ def main():
         statuses[i.status_name] = statuses.get(i.status_name, 0) + 1
     iters = [i.iters for i in info]
 
-    # dominant kernel (largest share of event-timed GPU time in the timed region)
-    dom = max(stats, key=lambda k: stats[k]["ms"])
-    d = stats[dom]
-    avg_s = d["ms"] / d["launches"] / 1e3
-    bpl = d["bytes"] / d["launches"]
-    achieved = bpl / avg_s / 1e9
-    roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                "traffic": (lambda r: None if r is None else round(r * bpl))(load_traffic(dom)),
-                "avg_launch_ms": round(avg_s * 1e3, 4), "algorithmic_bytes_per_launch": bpl,
-                "launches": d["launches"]}
+    # dominant kernel function: largest share of event-timed GPU time in the timed region
+    dom = max(by_fn, key=lambda k: by_fn[k]["ms"])
+    roof = roofline_for(dom, by_fn[dom])
+    ratio = load_traffic(dom)
+    roof["traffic"] = None if ratio is None else round(ratio * roof["algorithmic_bytes_per_launch"])
+    total_ms = sum(v["ms"] for v in by_fn.values())
     kernels = {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4),
-                   "share": round(v["ms"] / sum(s["ms"] for s in stats.values()), 4),
-                   "GBps": round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1)} for k, v in stats.items()}
+                   "share": round(v["ms"] / total_ms, 4)} for k, v in sorted(by_fn.items(), key=lambda kv: -kv[1]["ms"])}
+    uses = {k: round(v["ms"] / args.steps, 2) for k, v in sorted(by_use.items(), key=lambda kv: -kv[1]["ms"])}
 
-    # FFT-convolution throughput inside the timed region: the three passes together
-    passes = [k for k in ("lsop_rows_fwd", "lsop_cols", "lsop_rows_inv") if k in stats]
-    fft_bytes = sum(stats[k]["bytes"] for k in passes)
-    fft_ms = sum(stats[k]["ms"] for k in passes)
-    fft_gbps = fft_bytes / (fft_ms / 1e3) / 1e9
-    vec_applies = stats["lsop_cols"]["items"] if "lsop_cols" in stats else 0
-    # growth factor of the residual per iteration (an estimate of rho(M) when the series diverges)
+    # FFT-convolution throughput of the LS operator inside the timed region: its three passes together
+    passes = [k for k in ("lsop_rows_fwd", "lsop_cols", "lsop_rows_inv") if k in by_use]
+    fft_bytes = sum(by_use[k]["bytes"] for k in passes)
+    fft_ms = sum(by_use[k]["ms"] for k in passes)
+    fft_gbps = fft_bytes / (fft_ms / 1e3) / 1e9 if fft_ms > 0 else None
+    vec_applies = by_use["lsop_cols"]["items"] if "lsop_cols" in by_use else 0
     growth = [(i.rel_residual / i.rel_residual0) ** (1.0 / i.iters) for i in info if i.iters > 0
               and i.rel_residual0 > 0 and np.isfinite(i.rel_residual)]
-
+    if args.pc == "hodlr":
+        pcdesc = f"HODLR H, {args.levels} levels, rank {args.rank}, q={args.power_iters}"
+    else:
+        pcdesc = f"low-rank H rank {args.rank} (q={args.power_iters})"
+    build_s, series_s = phase["build"] / args.steps, phase["series"] / args.steps
     line = {
         "metric": METRIC, "value": converged / step_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "c64", "data": "synthetic",
         "config": {"workload": f"smooth random 1500-5000 m/s + 6 ellipses, {w.nx}x{w.nz}, h={w.h} m, {w.freq} Hz, "
-                               f"c0={w.c0} m/s, {w.nsrc} top-row sources, low-rank H rank {args.rank} (q=0), "
+                               f"c0={w.c0} m/s, {w.nsrc} top-row sources, {pcdesc}, "
                                f"series to rel. residual {args.tol}, cap {args.max_iter}",
-                   "grid": [w.nx, w.nz], "sources": w.nsrc, "rank": args.rank, "tol": args.tol},
+                   "grid": [w.nx, w.nz], "sources": w.nsrc, "preconditioner": args.pc, "rank": args.rank,
+                   "levels": args.levels if args.pc == "hodlr" else None, "power_iters": args.power_iters,
+                   "tol": args.tol},
         "converged": converged, "statuses": statuses, "iterations": [min(iters), max(iters)],
+        "build_s": round(build_s, 3), "series_s": round(series_s, 3),
+        "solves_per_s_series_only": round(converged / series_s, 1) if series_s > 0 else None,
         "residual_growth_per_iter": round(float(np.median(growth)), 3) if growth else None,
-        "fft_conv_GBps": round(fft_gbps, 1), "fft_conv_frac_of_peak": round(fft_gbps / HBM_PEAK_GBPS, 4),
-        "operator_applications_per_s": round(vec_applies / (fft_ms / 1e3), 1),
-        "col_tile": op.info().col_tile,
-        "roofline": roofline, "kernels": kernels,
+        "fft_conv_GBps": None if fft_gbps is None else round(fft_gbps, 1),
+        "fft_conv_frac_of_peak": None if fft_gbps is None else round(fft_gbps / HBM_PEAK_GBPS, 4),
+        "operator_applications_per_s": round(vec_applies / (fft_ms / 1e3), 1) if fft_ms > 0 else None,
+        "col_tile": op.info().col_tile, "preconditioner_bytes": pc.info()[2],
+        "roofline": roof, "kernels": kernels, "ms_per_step_by_use": uses,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, args.rank, iters, converged, args.cpu_sources)
+        line["cpu_baseline"] = cpu_baseline(w, args, iters, converged, args.cpu_sources)
     print(json.dumps(line), flush=True)
 
 

@@ -238,7 +238,11 @@ typedef struct {
 
 int lsop_profile_enable(int on);
 int lsop_profile_reset(void);
+/* aggregated by use (e.g. "lsop_cols": the column pass of the LS operator) */
 int lsop_profile_read(lsop_kernel_stat* stats, int max_stats, int* count);
+/* aggregated by kernel function, named as rocprofv3 names it without the
+ * namespace and argument list (e.g. "k_cols<float, 1024, 8>") */
+int lsop_profile_read_kernels(lsop_kernel_stat* stats, int max_stats, int* count);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,7 @@ hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // ------------------------------------------------------------ profiler
 struct ProfRec {
-  const char* name;
+  std::string name, fn;  // use label, kernel function
   hipEvent_t a, b;
   double bytes, flops, items;
 };
@@ -44,16 +44,77 @@ hipEvent_t ev_get() {
   return e;
 }
 
-// Runs `launch` (returning hipError_t); while profiling, brackets it with events.
+// Runs `launch` (one kernel launch, returning hipError_t); while profiling,
+// brackets it with events on its stream and records the use label, the kernel
+// function `fn` (read after the launch, so the launch may fill it in) and the
+// launch's algorithmic bytes and flops.
 template <typename F>
-hipError_t prof(const char* name, double bytes, double flops, double items, hipStream_t s, F&& launch) {
+hipError_t prof(const char* name, const std::string& fn, double bytes, double flops, double items, hipStream_t s,
+                F&& launch) {
   if (!g_prof) return launch();
-  ProfRec r{name, ev_get(), ev_get(), bytes, flops, items};
+  ProfRec r{name, "", ev_get(), ev_get(), bytes, flops, items};
   (void)hipEventRecord(r.a, s);
   hipError_t e = launch();
   (void)hipEventRecord(r.b, s);
+  r.fn = fn;
   g_recs.push_back(r);
   return e;
+}
+
+template <typename T>
+const char* tname();
+template <>
+const char* tname<float>() { return "float"; }
+template <>
+const char* tname<double>() { return "double"; }
+
+std::string fn_name(const char* base, const char* t, int a = -1, int b = -1) {
+  std::string f = std::string(base) + "<" + t;
+  if (a >= 0) f += ", " + std::to_string(a);
+  if (b >= 0) f += ", " + std::to_string(b);
+  return f + ">";
+}
+
+// C = alpha A^H B (segmented) as its two profiled launches
+template <typename T>
+hipError_t p_ah_b(const char* name, const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n,
+                  size_t seg, Cx<double>* C, Cx<double>* part, int ksub, hipStream_t s, double alpha = 1.0) {
+  if (na <= 0 || nb <= 0) return hipSuccess;
+  const GemmPlan p = gemm_ah_b_plan(n, seg, ksub);
+  const double e = sizeof(Cx<T>), nab = (double)na * nb * sizeof(Cx<double>), parts = (double)p.nseg * p.ksub;
+  hipError_t err = prof(name, fn_name("k_gemm_ah_b_mfma", tname<T>()), (double)(na + nb) * n * e + parts * nab,
+                        8.0 * na * nb * (double)n, nb, s,
+                        [&] { return launch_gemm_ah_b_part<T>(A, na, B, vidx, nb, n, p, part, s); });
+  if (err != hipSuccess) return err;
+  return prof(name, "k_reduce_parts", (parts + p.nseg) * nab, 2.0 * parts * na * nb, nb, s,
+              [&] { return launch_reduce_parts(part, p, (size_t)na * nb, C, alpha, s); });
+}
+
+// Y = X1 + beta X2 + A M (segmented), profiled
+template <typename T>
+hipError_t p_update(const char* name, const Cx<T>* A, int na, const Cx<double>* M, size_t mstride, int nb,
+                    const Cx<T>* X1, const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n, size_t seg,
+                    hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  const double e = sizeof(Cx<T>);
+  const double vecs = 1.0 + (X1 ? 1.0 : 0.0) + (X2 ? 1.0 : 0.0);
+  const double nsegs = (seg == 0 || seg >= n) ? 1.0 : (double)((n + seg - 1) / seg);
+  return prof(name, fn_name("k_gemm_update_mfma", tname<T>(), nb > 32 ? 4 : 2),
+              (double)na * n * e + vecs * nb * (double)n * e + nsegs * na * nb * sizeof(Cx<double>),
+              8.0 * na * nb * (double)n, nb, s,
+              [&] { return launch_gemm_update_seg<T>(A, na, M, mstride, nb, X1, X2, beta, Y, vidx, n, seg, s); });
+}
+
+// batched C = alpha A B + beta C, profiled
+template <typename T>
+hipError_t p_bgemm(const char* name, const Cx<T>* A, size_t lda, size_t sA, const Cx<T>* B, size_t ldb, size_t sB,
+                   Cx<T>* C, size_t ldc, size_t sC, const int* mapa, const int* mapc, int M, int N, int K,
+                   double alpha, double beta, int batch, hipStream_t s) {
+  const double e = sizeof(Cx<T>);
+  const double bytes = (double)batch * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2.0 : 1.0)) * e;
+  return prof(name, fn_name("k_bgemm_mfma", tname<T>()), bytes, 8.0 * M * N * (double)K * batch, batch, s, [&] {
+    return launch_bgemm<T>(A, lda, sA, B, ldb, sB, C, ldc, sC, mapa, mapc, M, N, K, alpha, beta, batch, s);
+  });
 }
 
 double fft_flops(int L) { return 5.0 * L * std::log2((double)L); }
@@ -140,18 +201,24 @@ int apply_impl(lsop_op* op, int mode, const Cx<T>* x, Cx<T>* y, const Cx<T>* rhs
     // algorithmic bytes: compulsory reads + writes of each pass (see the kernel file header)
     const double e = sizeof(Cx<T>), t = sizeof(T), nn = (double)n, np = (double)op->nx * op->pz();
     const double frow = 2.0 * fft_flops(op->lz) + 6.0 * op->lz;
-    const double fcol = 4.0 * fft_flops(op->lx) + 18.0 * op->lx;
+    const double fcols = 4.0 * fft_flops(op->lx) + 18.0 * op->lx;
     const bool xin = (mode == LSOP_MODE_A || mode == LSOP_MODE_AH);
     const bool chi_out = (mode == LSOP_MODE_AH || mode == LSOP_MODE_VHG0H);
-    LSOP_HIP(prof("lsop_rows_fwd", m * (nn * e + np * e) + (mulchi ? nn * t : 0.0), (double)m * op->nx * frow, m, s,
-                  [&] {
+    std::string fcol;
+    LSOP_HIP(prof("lsop_rows_fwd", fn_name("k_rows_fwd", tname<T>(), op->lz), m * (nn * e + np * e) + (mulchi ? nn * t : 0.0),
+                  (double)m * op->nx * frow, m, s, [&] {
                     return launch_rows_fwd<T>(op->lz, x + off, Dt<T>::chi(op), tmp, vc, op->nx, op->nz, m, mulchi,
                                               Dt<T>::twz(op), s);
                   }));
-    LSOP_HIP(prof("lsop_cols", m * 2.0 * np * e + 2.0 * op->pz() * op->lx * e, (double)m * op->pz() * fcol, m, s, [&] {
-      return launch_cols<T>(op->lx, tmp, Dt<T>::gs(op), op->nx, op->pz(), m, adj, Dt<T>::twx(op), s, op->col_tile);
-    }));
-    LSOP_HIP(prof("lsop_rows_inv",
+    LSOP_HIP(prof("lsop_cols", fcol, m * 2.0 * np * e + 2.0 * op->pz() * op->lx * e, (double)m * op->pz() * fcols, m, s,
+                  [&] {
+                    int used = 0;
+                    hipError_t er = launch_cols<T>(op->lx, tmp, Dt<T>::gs(op), op->nx, op->pz(), m, adj, Dt<T>::twx(op),
+                                                   s, op->col_tile, &used);
+                    fcol = fn_name("k_cols", tname<T>(), op->lx, used);
+                    return er;
+                  }));
+    LSOP_HIP(prof("lsop_rows_inv", fn_name("k_rows_inv", tname<T>(), op->lz),
                   m * (np * e + nn * e + (xin ? nn * e : 0.0) + (rhs ? nn * e : 0.0)) + (chi_out ? nn * t : 0.0),
                   (double)m * op->nx * frow, m, s, [&] {
                     return launch_rows_inv<T>(op->lz, tmp, x + off, Dt<T>::chi(op), rhs ? rhs + off : nullptr,
@@ -164,20 +231,13 @@ int apply_impl(lsop_op* op, int mode, const Cx<T>* x, Cx<T>* y, const Cx<T>* rhs
 template <typename T>
 hipError_t p_gemm_ah_b(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n, Cx<double>* C,
                        Cx<double>* part, int ksplit, hipStream_t s) {
-  const double e = sizeof(Cx<T>), nab = (double)na * nb * sizeof(Cx<double>);
-  return prof("lsop_gemm_ah_b", (double)(na + nb) * n * e + 2.0 * ksplit * nab + nab, 8.0 * na * nb * (double)n, nb,
-              s,
-              [&] { return launch_gemm_ah_b<T>(A, na, B, vidx, nb, n, C, part, ksplit, s); });
+  return p_ah_b<T>("lsop_gemm_ah_b", A, na, B, vidx, nb, n, n, C, part, ksplit, s);
 }
 
 template <typename T>
 hipError_t p_gemm_update(const Cx<T>* A, int na, const Cx<double>* M, int nb, const Cx<T>* X1, const Cx<T>* X2,
                          double beta, Cx<T>* Y, const int* vidx, size_t n, hipStream_t s) {
-  const double e = sizeof(Cx<T>);
-  const double vecs = 1.0 + (X1 ? 1.0 : 0.0) + (X2 ? 1.0 : 0.0);
-  return prof("lsop_gemm_update", (double)na * n * e + vecs * nb * (double)n * e + (double)na * nb * 16.0,
-              8.0 * na * nb * (double)n, nb, s,
-              [&] { return launch_gemm_update<T>(A, na, M, nb, X1, X2, beta, Y, vidx, n, s); });
+  return p_update<T>("lsop_gemm_update", A, na, M, 0, nb, X1, X2, beta, Y, vidx, n, n, s);
 }
 
 // Times the column pass for each tile width on the operator's shape (m vectors
@@ -237,30 +297,23 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
     Cx<T>* Yb = Y + (size_t)c0 * n;
     Cx<T>* Qb = Q + (size_t)c0 * n;
     if (c0 > 0) {  // reference Gram of the block before projection
-      LSOP_HIP(prof("orth_gram", 2.0 * kb * n * e, 8.0 * kb * kb * (double)n, kb, s, [&] {
-        return launch_gemm_ah_b_seg<T>(Yb, kb, Yb, nullptr, kb, n, seg, R, part, ksub, s, 1.0);
-      }));
+      LSOP_HIP(p_ah_b<T>("orth_gram", Yb, kb, Yb, nullptr, kb, n, seg, R, part, ksub, s));
     }
     for (int pass = 0; pass < 2 && c0 > 0; ++pass) {
-      LSOP_HIP(prof("orth_project_ah_b", (double)(c0 + kb) * n * e, 8.0 * c0 * kb * (double)n, kb, s, [&] {
-        return launch_gemm_ah_b_seg<T>(Q, c0, Yb, nullptr, kb, n, seg, G, part, ksub, s, -1.0);
-      }));
-      LSOP_HIP(prof("orth_project_update", (double)(c0 + 2 * kb) * n * e, 8.0 * c0 * kb * (double)n, kb, s, [&] {
-        return launch_gemm_update_seg<T>(Q, c0, G, (size_t)c0 * kb, kb, Yb, nullptr, 0.0, Yb, nullptr, n, seg, s);
-      }));
+      LSOP_HIP(p_ah_b<T>("orth_project", Q, c0, Yb, nullptr, kb, n, seg, G, part, ksub, s, -1.0));
+      LSOP_HIP(p_update<T>("orth_project", Q, c0, G, (size_t)c0 * kb, kb, Yb, nullptr, 0.0, Yb, nullptr, n, seg, s));
     }
     for (int pass = 0; pass < 2; ++pass) {
       const Cx<T>* src = pass == 0 ? Yb : Qb;
       Cx<T>* dst = pass == 0 ? Qb : Yb;
-      LSOP_HIP(prof("orth_gram", 2.0 * kb * n * e, 8.0 * kb * kb * (double)n, kb, s, [&] {
-        return launch_gemm_ah_b_seg<T>(src, kb, src, nullptr, kb, n, seg, G, part, ksub, s, 1.0);
-      }));
-      LSOP_HIP(launch_gram_orth(G, X, kb, pass == 0 ? tol : 1e-6, kept + (c0 / B) * nseg, s, nseg,
-                                (pass == 0 && c0 > 0) ? R : nullptr));
-      LSOP_HIP(prof("orth_update", 2.0 * kb * n * e, 8.0 * kb * kb * (double)n, kb, s, [&] {
-        return launch_gemm_update_seg<T>(src, kb, X, (size_t)kb * kb, kb, nullptr, nullptr, 0.0, dst, nullptr, n, seg,
-                                         s);
-      }));
+      LSOP_HIP(p_ah_b<T>("orth_gram", src, kb, src, nullptr, kb, n, seg, G, part, ksub, s));
+      LSOP_HIP(prof("orth_coeffs", "k_gram_orth_lds", 2.0 * nseg * kb * kb * sizeof(Cx<double>),
+                    8.0 * 3.0 * kb * kb * (double)kb * nseg, nseg, s, [&] {
+                      return launch_gram_orth(G, X, kb, pass == 0 ? tol : 1e-6, kept + (c0 / B) * nseg, s, nseg,
+                                              (pass == 0 && c0 > 0) ? R : nullptr);
+                    }));
+      LSOP_HIP(p_update<T>("orth_update", src, kb, X, (size_t)kb * kb, kb, nullptr, nullptr, 0.0, dst, nullptr, n, seg,
+                           s));
     }
     LSOP_HIP(hipMemcpyAsync(Qb, Yb, sizeof(Cx<T>) * (size_t)kb * n, hipMemcpyDeviceToDevice, s));
   }
@@ -425,14 +478,19 @@ int hodlr_subconv(lsop_precond* pc, int lv, bool adj, const Cx<T>* x, Cx<T>* y, 
   for (int c = 0; c < nvec; c += op->max_vec) {
     const int m = std::min(op->max_vec, nvec - c);
     const size_t off = (size_t)c * n;
-    LSOP_HIP(prof("hodlr_rows_fwd", m * (0.5 * nn * e + np * e), 0.0, m, s, [&] {
+    std::string fcol;
+    LSOP_HIP(prof("hodlr_rows_fwd", fn_name("k_rows_fwd", tname<T>(), op->lz), m * (0.5 * nn * e + np * e), 0.0, m, s, [&] {
       return launch_rows_fwd<T>(op->lz, x + off, Dt<T>::chi(op), tmp, nullptr, W, op->nz, m * nodes, !adj,
                                 Dt<T>::twz(op), s, nodes, in_lo, in_hi);
     }));
-    LSOP_HIP(prof("hodlr_cols", m * 2.0 * np * e + 2.0 * op->pz() * L.lx * e, 0.0, m, s, [&] {
-      return launch_cols<T>(L.lx, tmp, lev_gs<T>(L), W, op->pz(), m * nodes, adj, lev_tw<T>(L), s, 0);
+    LSOP_HIP(prof("hodlr_cols", fcol, m * 2.0 * np * e + 2.0 * op->pz() * L.lx * e, 0.0, m, s, [&] {
+      int used = 0;
+      hipError_t er = launch_cols<T>(L.lx, tmp, lev_gs<T>(L), W, op->pz(), m * nodes, adj, lev_tw<T>(L), s, 0, &used);
+      fcol = fn_name("k_cols", tname<T>(), L.lx, used);
+      return er;
     }));
-    LSOP_HIP(prof("hodlr_rows_inv", m * (np * e + 0.5 * nn * e), 0.0, m, s, [&] {
+    LSOP_HIP(prof("hodlr_rows_inv", fn_name("k_rows_inv", tname<T>(), op->lz), m * (np * e + 0.5 * nn * e), 0.0, m, s,
+                  [&] {
       return launch_rows_inv<T>(op->lz, tmp, x + off, Dt<T>::chi(op), nullptr, y + off, nullptr, nullptr, W, op->nz,
                                 m * nodes, adj ? 3 : 1, Dt<T>::twz(op), s, nodes, out_lo, out_hi);
     }));
@@ -459,7 +517,8 @@ int hodlr_orth(lsop_precond* pc, int lv, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s)
 int block_inverse(Cx<double>* M, size_t ld, size_t st, int cnt, size_t o, int m, int depth, Cx<double>* tbase,
                   const std::vector<size_t>& toff, int* flags, hipStream_t s) {
   if (m <= 64) {
-    LSOP_HIP(prof("block_inv_base", 0.0, 8.0 * m * m * (double)m * cnt, cnt, s, [&] {
+    LSOP_HIP(prof("block_inv_base", "k_lu_inverse_lds", 3.0 * m * m * (double)sizeof(Cx<double>) * cnt,
+                  8.0 * m * m * (double)m * cnt, cnt, s, [&] {
       return launch_lu_inverse(M + o, ld, st, M + o, ld, st, nullptr, m, true, flags, cnt, s);
     }));
     return LSOP_OK;
@@ -473,10 +532,8 @@ int block_inverse(Cx<double>* M, size_t ld, size_t st, int cnt, size_t o, int m,
   if (rc) return rc;
   auto gemm = [&](const Cx<double>* a, size_t lda, size_t sa, const Cx<double>* b, size_t ldb, size_t sb,
                   Cx<double>* c, size_t ldc, size_t sc, int mm, int nn, int kk, double alpha, double beta) {
-    return prof("block_inv_gemm", 0.0, 8.0 * mm * nn * (double)kk * cnt, cnt, s, [&] {
-      return launch_bgemm<double>(a, lda, sa, b, ldb, sb, c, ldc, sc, nullptr, nullptr, mm, nn, kk, alpha, beta, cnt,
-                                  s);
-    });
+    return p_bgemm<double>("block_inv_gemm", a, lda, sa, b, ldb, sb, c, ldc, sc, nullptr, nullptr, mm, nn, kk, alpha,
+                           beta, cnt, s);
   };
   LSOP_HIP(gemm(M + A, ld, st, M + B, ld, st, T1, h2, s1, h, h2, h, 1.0, 0.0));      // T1 = X B
   LSOP_HIP(gemm(M + C, ld, st, T1, h2, s1, M + D, ld, st, h2, h2, h, -1.0, 1.0));    // D <- S = D - C X B
@@ -544,11 +601,8 @@ int hodlr_apply(lsop_precond* pc, const Cx<T>* x, const int* xidx, Cx<T>* y, con
     const Cx<T>* xb = xidx ? x : x + (size_t)c * n;
     Cx<T>* yb = yidx ? y : y + (size_t)c * n;
     // leaves: y_k = D_k^{-1} x_k (D_k^{-1} stored transposed: y = x D^{-T})
-    LSOP_HIP(prof("hodlr_leaf_apply", (double)pc->nleaf * nl * nl * e + 2.0 * m * (double)n * e,
-                  8.0 * m * (double)nl * n, m, s, [&] {
-                    return launch_bgemm<T>(xb, n, nl, dinv, nl, (size_t)nl * nl, yb, n, nl, xc, yc, m, nl, nl, 1.0,
-                                           0.0, pc->nleaf, s);
-                  }));
+    LSOP_HIP(p_bgemm<T>("hodlr_leaf_apply", xb, n, nl, dinv, nl, (size_t)nl * nl, yb, n, nl, xc, yc, m, nl, nl, 1.0,
+                        0.0, pc->nleaf, s));
     for (int lv = pc->levels - 1; lv >= upto; --lv) {
       const hodlr_level& L = pc->lev[lv];
       const int nodes = op->nx / L.width, nseg = 2 * nodes;
@@ -556,18 +610,10 @@ int hodlr_apply(lsop_precond* pc, const Cx<T>* x, const int* xidx, Cx<T>* y, con
       const int ksub = hodlr_ksub(pc, seg, nseg);
       const Cx<T>* V = reinterpret_cast<const Cx<T>*>(L.V);
       const Cx<T>* Wp = reinterpret_cast<const Cx<T>*>(L.Wp);
-      LSOP_HIP(prof("hodlr_gemm_ah_b", (double)(r + m) * n * e, 8.0 * r * m * (double)n, m, s, [&] {
-        return launch_gemm_ah_b_seg<T>(V, r, yb, yc, m, n, seg, pc->hG, pc->part, ksub, s);
-      }));
-      LSOP_HIP(prof("hodlr_core_apply", 0.0, 32.0 * r * r * (double)m * nodes, m, s, [&] {
-        return launch_bgemm<double>(L.kinv, 2 * r, (size_t)4 * r * r, pc->hG, m, (size_t)2 * r * m, pc->hX, m,
-                                    (size_t)2 * r * m, nullptr, nullptr, 2 * r, m, 2 * r, 1.0, 0.0, nodes, s);
-      }));
-      LSOP_HIP(prof("hodlr_gemm_update", (double)r * n * e + 2.0 * m * (double)n * e, 8.0 * r * m * (double)n, m, s,
-                    [&] {
-                      return launch_gemm_update_seg<T>(Wp, r, pc->hX, (size_t)r * m, m, yb, nullptr, 0.0, yb, yc, n,
-                                                       seg, s);
-                    }));
+      LSOP_HIP(p_ah_b<T>("hodlr_apply_ah_b", V, r, yb, yc, m, n, seg, pc->hG, pc->part, ksub, s));
+      LSOP_HIP(p_bgemm<double>("hodlr_core_apply", L.kinv, 2 * r, (size_t)4 * r * r, pc->hG, m, (size_t)2 * r * m,
+                               pc->hX, m, (size_t)2 * r * m, nullptr, nullptr, 2 * r, m, 2 * r, 1.0, 0.0, nodes, s));
+      LSOP_HIP(p_update<T>("hodlr_apply_update", Wp, r, pc->hX, (size_t)r * m, m, yb, nullptr, 0.0, yb, yc, n, seg, s));
     }
   }
   return LSOP_OK;
@@ -600,10 +646,8 @@ int hodlr_core_inverse(lsop_precond* pc, int lv, hipStream_t s) {
   double* dev = reinterpret_cast<double*>(pc->part);
   auto gemm = [&](const Cx<double>* a, size_t lda, size_t sa, const Cx<double>* b, size_t ldb, size_t sb,
                   Cx<double>* c, size_t ldc, size_t sc, double alpha, double beta) {
-    return prof("hodlr_core_gemm", 0.0, 8.0 * r2 * (double)r * nodes, nodes, s, [&] {
-      return launch_bgemm<double>(a, lda, sa, b, ldb, sb, c, ldc, sc, nullptr, nullptr, r, r, r, alpha, beta, nodes,
-                                  s);
-    });
+    return p_bgemm<double>("hodlr_core_gemm", a, lda, sa, b, ldb, sb, c, ldc, sc, nullptr, nullptr, r, r, r, alpha,
+                           beta, nodes, s);
   };
   LSOP_HIP(launch_set_identity(B10, ld, st, r, nodes, s));
   LSOP_HIP(gemm(G0, r, 2 * r2, G1, r, 2 * r2, B10, ld, st, -1.0, 1.0));   // S = I - G0 G1
@@ -685,7 +729,7 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
     if ((st = hodlr_apply<T>(pc, Y, nullptr, Wp, nullptr, r, lv + 1, s))) return st;
     // K per node from the per-half products V^H Wp, then kinv = K^{-1} P
     const int ksub = hodlr_ksub(pc, seg, nseg);
-    LSOP_HIP(launch_gemm_ah_b_seg<T>(V, r, Wp, nullptr, r, n, seg, pc->hG, pc->part, ksub, s));
+    LSOP_HIP(p_ah_b<T>("hodlr_core_ah_b", V, r, Wp, nullptr, r, n, seg, pc->hG, pc->part, ksub, s));
     if ((st = hodlr_core_inverse(pc, lv, s))) return st;
   }
   pc->kept = r;
@@ -1279,17 +1323,18 @@ int lsop_profile_reset(void) {
   return LSOP_OK;
 }
 
-int lsop_profile_read(lsop_kernel_stat* stats, int max_stats, int* count) {
+static int profile_read_by(bool by_fn, lsop_kernel_stat* stats, int max_stats, int* count) {
   if (!count || (max_stats > 0 && !stats)) return fail(LSOP_EINVAL, "null argument");
   LSOP_HIP(hipDeviceSynchronize());
   std::vector<lsop_kernel_stat> agg;
   for (const auto& r : g_recs) {
     float ms = 0.f;
     LSOP_HIP(hipEventElapsedTime(&ms, r.a, r.b));
-    auto it = std::find_if(agg.begin(), agg.end(), [&](const lsop_kernel_stat& k) { return !strcmp(k.name, r.name); });
+    const char* key = by_fn ? r.fn.c_str() : r.name.c_str();
+    auto it = std::find_if(agg.begin(), agg.end(), [&](const lsop_kernel_stat& k) { return !strcmp(k.name, key); });
     if (it == agg.end()) {
       lsop_kernel_stat k{};
-      snprintf(k.name, sizeof(k.name), "%s", r.name);
+      snprintf(k.name, sizeof(k.name), "%s", key);
       agg.push_back(k);
       it = agg.end() - 1;
     }
@@ -1302,6 +1347,14 @@ int lsop_profile_read(lsop_kernel_stat* stats, int max_stats, int* count) {
   *count = (int)agg.size();
   for (int i = 0; i < (int)agg.size() && i < max_stats; ++i) stats[i] = agg[i];
   return LSOP_OK;
+}
+
+int lsop_profile_read(lsop_kernel_stat* stats, int max_stats, int* count) {
+  return profile_read_by(false, stats, max_stats, count);
+}
+
+int lsop_profile_read_kernels(lsop_kernel_stat* stats, int max_stats, int* count) {
+  return profile_read_by(true, stats, max_stats, count);
 }
 
 int lsop_bessel_host(int kind, double x, double* out2) {

@@ -39,9 +39,10 @@ hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, cons
                            int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s, int nodes = 1, int lo = 0,
                            int hi = -1);
 // tile: columns per workgroup (0 = widest that fits; narrower tiles allow more workgroups per CU)
+// *used (optional) receives the tile width launched
 template <typename T>
 hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int nslots, bool adj, const Cx<T>* tw2,
-                       hipStream_t s, int tile = 0);
+                       hipStream_t s, int tile = 0, int* used = nullptr);
 // epi: 0 y = x - c, 1 y = c, 2 y = x - chi c, 3 y = chi c; rhs != NULL: y -= rhs and rnorm[slot] += |y|^2
 // Sub-domain batches as in pass 1; rows outside [lo, hi) of a strip are not written.
 template <typename T>
@@ -85,6 +86,18 @@ hipError_t launch_philox_normal(Cx<T>* out, int nvec, size_t n, uint64_t seed, h
 template <typename T>
 hipError_t launch_gemm_ah_b(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n,
                             Cx<double>* C, Cx<double>* part, int ksplit, hipStream_t s);
+// The split of C = A^H B: `nseg` segments of `seg` elements, each cut into ksub chunks of `chunk`.
+struct GemmPlan {
+  size_t seg = 0, chunk = 0;
+  int nseg = 1, ksub = 1;
+};
+GemmPlan gemm_ah_b_plan(size_t n, size_t seg, int ksub);
+// the two launches of the segmented product: partials (nseg * ksub * na * nb) and their reduction
+template <typename T>
+hipError_t launch_gemm_ah_b_part(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n,
+                                 const GemmPlan& p, Cx<double>* part, hipStream_t s);
+hipError_t launch_reduce_parts(const Cx<double>* part, const GemmPlan& p, size_t count, Cx<double>* C, double alpha,
+                               hipStream_t s);
 // Segmented form: one na x nb result per segment of `seg` elements of k, at
 // C + sg * na * nb; each segment split into ksub partial chunks (part holds
 // nseg * ksub * na * nb complex doubles).

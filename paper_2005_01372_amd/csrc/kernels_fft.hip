@@ -462,7 +462,7 @@ hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, cons
 // narrower tile (more workgroups per CU) can be selected per call (tile > 0).
 template <typename T>
 hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int nslots, bool adj, const Cx<T>* tw2,
-                       hipStream_t s, int tile) {
+                       hipStream_t s, int tile, int* used) {
   if (nslots <= 0) return hipSuccess;
   if (pz % 16 != 0) return hipErrorInvalidValue;  // tile groups of one 128-byte line must divide the row
   LSOP_DISPATCH_LX(L, {
@@ -472,6 +472,7 @@ hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int n
     else if (C >= 8 && CMAX >= 8) C = 8;
     else if (C >= 4 && CMAX >= 4) C = 4;
     else C = CMAX < 2 ? CMAX : 2;
+    if (used) *used = C;
     const int ntiles = pz / C;
     const dim3 grid(ntiles * nslots);
     switch (C) {
@@ -568,7 +569,7 @@ hipError_t launch_incident(const Cx<double>* ktab, const int* si, const int* sj,
   template hipError_t launch_rows_fwd<T>(int, const Cx<T>*, const T*, Cx<T>*, const int*, int, int, int, bool,    \
                                          const Cx<T>*, hipStream_t, int, int, int);                               \
   template hipError_t launch_cols<T>(int, Cx<T>*, const Cx<T>*, int, int, int, bool, const Cx<T>*, hipStream_t,    \
-                                     int);                                                                        \
+                                     int, int*);                                                                  \
   template hipError_t launch_rows_inv<T>(int, const Cx<T>*, const Cx<T>*, const T*, const Cx<T>*, Cx<T>*,        \
                                          double*, const int*, int, int, int, int, const Cx<T>*, hipStream_t, int, \
                                          int, int);                                                               \

@@ -749,23 +749,44 @@ hipError_t launch_philox_normal(Cx<T>* out, int nvec, size_t n, uint64_t seed, h
   return hipGetLastError();
 }
 
+GemmPlan gemm_ah_b_plan(size_t n, size_t seg, int ksub) {
+  GemmPlan p;
+  if (seg == 0 || seg > n) seg = n;
+  p.seg = seg;
+  p.nseg = (int)((n + seg - 1) / seg);
+  if (ksub < 1) ksub = 1;
+  size_t chunk = (seg + ksub - 1) / ksub;
+  p.chunk = (chunk + GM_K - 1) / GM_K * GM_K;
+  p.ksub = (int)((seg + p.chunk - 1) / p.chunk);
+  return p;
+}
+
+template <typename T>
+hipError_t launch_gemm_ah_b_part(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n,
+                                 const GemmPlan& p, Cx<double>* part, hipStream_t s) {
+  if (na <= 0 || nb <= 0) return hipSuccess;
+  dim3 grid((na + GM_T - 1) / GM_T, (nb + GM_T - 1) / GM_T, (unsigned)(p.nseg * p.ksub));
+  hipLaunchKernelGGL((k_gemm_ah_b_mfma<T>), grid, dim3(256), 0, s, A, na, B, vidx, nb, n, p.seg, p.chunk, p.ksub,
+                     part);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_parts(const Cx<double>* part, const GemmPlan& p, size_t count, Cx<double>* C, double alpha,
+                               hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_parts, dim3(grid1(count * p.nseg, 2048)), dim3(256), 0, s, part, p.ksub, p.nseg, count,
+                     C, alpha);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_gemm_ah_b_seg(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n, size_t seg,
                                 Cx<double>* C, Cx<double>* part, int ksub, hipStream_t s, double alpha) {
   if (na <= 0 || nb <= 0) return hipSuccess;
-  if (seg == 0 || seg > n) seg = n;
-  const int nseg = (int)((n + seg - 1) / seg);
-  if (ksub < 1) ksub = 1;
-  size_t chunk = (seg + ksub - 1) / ksub;
-  chunk = (chunk + GM_K - 1) / GM_K * GM_K;
-  ksub = (int)((seg + chunk - 1) / chunk);
-  dim3 grid((na + GM_T - 1) / GM_T, (nb + GM_T - 1) / GM_T, (unsigned)(nseg * ksub));
-  hipLaunchKernelGGL((k_gemm_ah_b_mfma<T>), grid, dim3(256), 0, s, A, na, B, vidx, nb, n, seg, chunk, ksub, part);
-  hipError_t e = hipGetLastError();
+  const GemmPlan p = gemm_ah_b_plan(n, seg, ksub);
+  hipError_t e = launch_gemm_ah_b_part<T>(A, na, B, vidx, nb, n, p, part, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reduce_parts, dim3(grid1((size_t)na * nb * nseg, 2048)), dim3(256), 0, s, part, ksub, nseg,
-                     (size_t)na * nb, C, alpha);
-  return hipGetLastError();
+  return launch_reduce_parts(part, p, (size_t)na * nb, C, alpha, s);
 }
 
 template <typename T>
@@ -892,6 +913,8 @@ hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, 
                                           Cx<double>*, int, hipStream_t);                                           \
   template hipError_t launch_gemm_ah_b_seg<T>(const Cx<T>*, int, const Cx<T>*, const int*, int, size_t, size_t,     \
                                               Cx<double>*, Cx<double>*, int, hipStream_t, double);                  \
+  template hipError_t launch_gemm_ah_b_part<T>(const Cx<T>*, int, const Cx<T>*, const int*, int, size_t,            \
+                                               const GemmPlan&, Cx<double>*, hipStream_t);                          \
   template hipError_t launch_gemm_update<T>(const Cx<T>*, int, const Cx<double>*, int, const Cx<T>*, const Cx<T>*, \
                                             double, Cx<T>*, const int*, size_t, hipStream_t);                       \
   template hipError_t launch_gemm_update_seg<T>(const Cx<T>*, int, const Cx<double>*, size_t, int, const Cx<T>*,   \

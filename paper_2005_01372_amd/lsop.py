@@ -29,7 +29,8 @@ INIT = {"h_rhs": 0, "zero": 1, "user": 2}
 EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident", "lsop_autotune",
            "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "precond_create",
            "precond_build", "precond_apply", "precond_info", "precond_destroy", "series_solve",
-           "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read")
+           "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
+           "lsop_profile_read_kernels")
 
 
 class LsopError(RuntimeError):
@@ -96,6 +97,7 @@ def load_library(path=LIB_PATH):
         "lsop_profile_enable": (ip, [ip]),
         "lsop_profile_reset": (ip, []),
         "lsop_profile_read": (ip, [C.POINTER(KernelStat), ip, C.POINTER(ip)]),
+        "lsop_profile_read_kernels": (ip, [C.POINTER(KernelStat), ip, C.POINTER(ip)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -134,14 +136,16 @@ def profile_reset():
     _check(load_library().lsop_profile_reset())
 
 
-def profile_read():
-    """Per-kernel totals since the last reset: {name: dict(launches, ms, bytes, flops)}."""
+def profile_read(by_kernel=False):
+    """Totals since the last reset, by use label or (by_kernel) by kernel function:
+    {name: dict(launches, ms, bytes, flops, items)}."""
     lib = load_library()
-    arr = (KernelStat * 64)()
+    arr = (KernelStat * 128)()
     cnt = C.c_int()
-    _check(lib.lsop_profile_read(arr, 64, C.byref(cnt)))
+    fn = lib.lsop_profile_read_kernels if by_kernel else lib.lsop_profile_read
+    _check(fn(arr, 128, C.byref(cnt)))
     return {arr[i].name.decode(): dict(launches=arr[i].launches, ms=arr[i].total_ms, bytes=arr[i].bytes,
-                                       flops=arr[i].flops, items=arr[i].items) for i in range(min(cnt.value, 64))}
+                                       flops=arr[i].flops, items=arr[i].items) for i in range(min(cnt.value, 128))}
 
 
 class Operator:

@@ -3,12 +3,13 @@
 ``kernel_stats``: turns a ``--kernel-trace --stats --output-format csv`` run
 into a short text table.  ``traffic``: turns two ``--pmc FETCH_SIZE`` and
 ``--pmc WRITE_SIZE`` runs (of a command that also performs one plain device
-copy of known size) into HBM bytes per launch for one kernel, each counter
-scaled by what it reads for the copy.  Usage::
+copy of known size and dumps the library's event profile) into HBM bytes per
+launch for one kernel function, each counter scaled by what it reads for the
+copy.  Usage::
 
     python -m paper_2005_01372_amd.profiling stats <kernel_stats.csv> <out.txt> "<command>"
-    python -m paper_2005_01372_amd.profiling traffic <fetch.csv> <write.csv> <copy_bytes> <kernel substring> \
-        <lib name> <out.json> "<command>" <nx,lx,lz,element bytes>
+    python -m paper_2005_01372_amd.profiling traffic <fetch.csv> <write.csv> <copy_bytes> <kernel function> \
+        <profile dump.json> <out.json> "<command>"
 """
 from __future__ import annotations
 
@@ -48,53 +49,55 @@ def kernel_stats(csv_path, out_path, command, top=15):
     return lines
 
 
-def cols_algorithmic_bytes(name, grid_size, nx, lx, lz, esize):
-    """Algorithmic bytes of one column-pass dispatch, from its template tile width and grid size."""
-    c = int(name.split("<")[1].split(">")[0].split(",")[2])
-    g = 64 if lx >= 512 else {32: 8, 64: 8, 96: 8, 128: 16, 192: 8, 256: 32, 384: 16, 768: 32}[lx]
-    pz = 2 * lz
-    wgs = grid_size // (c * g)
-    nslots = wgs // (pz // c)
-    return nslots * 2.0 * nx * pz * esize + 2.0 * pz * lx * esize
+def _dispatches(csv_path, counter):
+    """[(dispatch id, kernel name, bytes)] for one counter (KiB per dispatch -> bytes), in dispatch order."""
+    out = []
+    for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] == counter:
+            out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
+    out.sort()
+    return out
 
 
-def _per_dispatch(csv_path, counter, geom=None):
-    """{kernel name: [(bytes, algorithmic bytes) per dispatch]} plus the copy dispatches issued before the first
-    library kernel."""
-    out, copies, seen_lib = {}, [], False
-    rows = sorted(csv.DictReader(open(csv_path)), key=lambda r: int(r["Dispatch_Id"]))
-    for r in rows:
-        if r["Counter_Name"] != counter:
-            continue
-        v = float(r["Counter_Value"]) * 1024.0  # KiB -> bytes
-        name = r["Kernel_Name"]
-        seen_lib = seen_lib or "lsop::" in name
-        if "copyBuffer" in name and not seen_lib and v >= (1 << 20):
-            copies.append(v)
-        alg = cols_algorithmic_bytes(name, int(r["Grid_Size"]), *geom) if (geom and "k_cols<" in name) else None
-        out.setdefault(name, []).append((v, alg))
-    return out, copies
+def _copy_scale(disp, copy_bytes):
+    """copy_bytes over what the counter read for the plain copies issued before the first library kernel."""
+    tot = 0.0
+    for _, name, v in disp:
+        if "lsop::" in name:
+            break
+        if "copyBuffer" in name and v >= (1 << 20):
+            tot += v
+    return copy_bytes / tot
 
 
-def traffic(fetch_csv, write_csv, copy_bytes, kernel_substr, lib_name, out_path, command, geom):
-    fetch, fcopy = _per_dispatch(fetch_csv, "FETCH_SIZE", geom)
-    write, wcopy = _per_dispatch(write_csv, "WRITE_SIZE", geom)
-    sf, sw = copy_bytes / sum(fcopy), copy_bytes / sum(wcopy)
-    names = [k for k in fetch if kernel_substr in k]
-    if not names:
-        raise SystemExit(f"no kernel matching {kernel_substr!r}")
-    f = [v for k in names for v in fetch[k]]
-    w = [v for k in names for v in write.get(k, [])]
-    fb, wb = sf * sum(v for v, _ in f), sw * sum(v for v, _ in w)
-    alg = sum(a for _, a in f)
+def traffic(fetch_csv, write_csv, copy_bytes, kernel_fn, dump_json, out_path, command):
+    """HBM bytes per launch of one kernel function over its algorithmic bytes.
+
+    The counter runs are of bench.py with --copy-probe (a plain 1 GiB copy
+    first, which scales each counter to bytes) and --dump-profile (the
+    library's own event profile of the timed region: launches and
+    algorithmic bytes per kernel function).  The timed region is the end of
+    the run, so its launches are the last `launches` dispatches of the kernel.
+    """
+    dump = json.load(open(dump_json))["kernels"][kernel_fn]
+    nl = int(dump["launches"])
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        disp = _dispatches(path, counter)
+        sc = _copy_scale(disp, copy_bytes)
+        mine = [v for _, name, v in disp if (kernel_fn + "(") in name][-nl:]
+        if len(mine) != nl:
+            raise SystemExit(f"{counter}: found {len(mine)} dispatches of {kernel_fn}, expected {nl}")
+        res[counter] = (sc, sc * sum(mine))
+    hbm = res["FETCH_SIZE"][1] + res["WRITE_SIZE"][1]
     rec = {
         "source_sha": kernel_source_sha(), "command": command, "copy_bytes": copy_bytes,
-        "copy_scale": {"FETCH_SIZE": sf, "WRITE_SIZE": sw},
-        "kernels": {lib_name: {
-            "rocprof_names": names, "dispatches": len(f),
-            "fetch_bytes_per_launch": fb / len(f), "write_bytes_per_launch": wb / len(w),
-            "algorithmic_bytes_per_launch": alg / len(f),
-            "hbm_over_algorithmic": (fb + wb) / alg}},
+        "copy_scale": {"FETCH_SIZE": res["FETCH_SIZE"][0], "WRITE_SIZE": res["WRITE_SIZE"][0]},
+        "kernels": {kernel_fn: {
+            "dispatches": nl,
+            "fetch_bytes_per_launch": res["FETCH_SIZE"][1] / nl, "write_bytes_per_launch": res["WRITE_SIZE"][1] / nl,
+            "algorithmic_bytes_per_launch": dump["bytes"] / nl,
+            "hbm_over_algorithmic": hbm / dump["bytes"]}},
     }
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -105,6 +108,5 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print("\n".join(kernel_stats(sys.argv[2], sys.argv[3], sys.argv[4])))
     elif sys.argv[1] == "traffic":
-        geom = tuple(int(v) for v in sys.argv[9].split(","))  # nx, lx, lz, bytes per complex element
         print(json.dumps(traffic(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6],
-                                 sys.argv[7], sys.argv[8], geom), indent=1))
+                                 sys.argv[7], sys.argv[8]), indent=1))
