@@ -217,6 +217,49 @@ typedef struct {
 int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_dev, int nvec,
                  const lsop_solve_params* params, lsop_solve_info* info_host, void* stream);
 
+/* ----------------------------------------------------------------------
+ * Batches of problems of uneven size (many instances of Section 2's problem,
+ * each with its own grid, medium, frequency and sources).  A batch wraps
+ * existing operator handles (created and set up by the caller, all complex
+ * float or all complex double; they must outlive the batch) and groups the
+ * instances by grid shape.  Every FFT pass of the LS operator (Section 2.2)
+ * is then one launch per shape group over all vectors of all its members,
+ * each vector carrying its own instance's contrast and spectrum.
+ * ---------------------------------------------------------------------- */
+typedef struct lsop_batch lsop_batch;
+
+/* Errors: EINVAL (null / unset operators, mixed dtypes), EUNSUPPORTED (LSOP_MIXED). */
+int lsop_batch_create(int count, lsop_op* const* ops, lsop_batch** out);
+
+/* y_i = op_i(x_i) (mode as lsop_apply) for nvec[i] vectors of instance i;
+ * x_dev[i], y_dev[i]: [nvec[i]][nx_i][nz_i] device buffers (no aliasing).
+ * Synchronises `stream` once to stage the per-vector operand tables. */
+int lsop_batch_apply(lsop_batch* b, int mode, const void* const* x_dev, void* const* y_dev, const int* nvec,
+                     void* stream);
+
+/* Column-pass tile width per shape group, timed once per (dtype, shape,
+ * vector-count class) in the process and reused by later batches. */
+int lsop_batch_autotune(lsop_batch* b, void* stream);
+
+/* The series of eq. (11) for every vector of every instance, advanced in
+ * lockstep: each iteration is one preconditioner update per instance
+ * (pcs[i], NULL or identity: Born) and one grouped residual evaluation.
+ * Vectors that finish (stopping rule of series_solve) are frozen: their
+ * residual is zeroed before the update, so their psi keeps the iterate whose
+ * residual was evaluated.  use_graph != 0: after the first iteration the
+ * launch sequence of one iteration is captured once as a HIP graph (on a
+ * stream of the library's own; no memset nodes) and replayed.  info: one
+ * entry per vector, instance by instance.  Synchronous.  Returns OK if every
+ * vector converged, else the first failing status; init as in series_solve
+ * (LSOP_INIT_USER: psi holds the start). */
+int lsop_batch_solve(lsop_batch* b, lsop_precond* const* pcs, const void* const* rhs_dev, void* const* psi_dev,
+                     const int* nvec, const lsop_solve_params* params, int use_graph, lsop_solve_info* info,
+                     void* stream);
+
+/* number of shape groups and device bytes held by the batch (tables, intermediates, work) */
+int lsop_batch_info(const lsop_batch* b, int* groups, size_t* bytes);
+void lsop_batch_destroy(lsop_batch* b);
+
 /* Diagnostics: FP64 Bessel evaluations used for the kernel table, on the host
  * (kind 0: (J0, Y0) at x > 0; kind 1: (J1, Y1) at 0 < x <= 2). */
 int lsop_bessel_host(int kind, double x, double* out2);

@@ -1,5 +1,6 @@
 // C ABI of liblsop.so: operator, preconditioner and series solver handles.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -738,12 +739,6 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
 }
 
 // --------------------------------------------------------------- series
-struct SeriesState {
-  std::vector<int> active;  // vector indices still iterating
-  std::vector<double> prev;
-  std::vector<int> rising;
-};
-
 // Runs eq. (11) on the vectors listed in `start` (all if empty).  rhs, psi, r
 // are [nvec][n] buffers of T.  Per-vector results go to info[vi].
 template <typename T>
@@ -834,6 +829,284 @@ int series_impl(lsop_op* op, lsop_precond* pc, const Cx<T>* rhs, Cx<T>* psi, int
 int overall_status(const lsop_solve_info* info, int nvec) {
   for (int v = 0; v < nvec; ++v)
     if (info[v].status != LSOP_OK) return info[v].status;
+  return LSOP_OK;
+}
+
+
+// ------------------------------------------------------------------ batches
+// Several operators (instances of possibly different sizes, each with its own
+// contrast and spectrum) advanced together: instances of the same grid shape
+// form a group, and every FFT pass is one launch per group whose slots (one
+// per vector) carry their own operands.
+
+int grow_buf(void** p, size_t* cap, size_t need, size_t* bytes) {
+  if (need <= *cap) return LSOP_OK;
+  if (*p) {
+    LSOP_HIP(hipDeviceSynchronize());
+    (void)hipFree(*p);
+    *bytes -= *cap;
+    *p = nullptr;
+    *cap = 0;
+  }
+  if (hipMalloc(p, need) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LSOP_ENOMEM, "batch allocation of " + std::to_string(need) + " bytes failed");
+  }
+  *cap = need;
+  *bytes += need;
+  return LSOP_OK;
+}
+
+// Host slot tables of all groups (group by group, member by member, vector by
+// vector); goff[g] = first slot of group g.  slot_of[i] = first slot of instance i.
+template <typename T>
+void batch_slots(lsop_batch* b, const Cx<T>* const* x, Cx<T>* const* y, const Cx<T>* const* rhs, double* rnorm,
+                 const int* nvec, std::vector<int>& goff, std::vector<int>& slot_of) {
+  goff.assign(b->groups.size() + 1, 0);
+  slot_of.assign(b->count, 0);
+  std::vector<Slot<T>> all;
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    goff[g] = (int)all.size();
+    for (int i : b->groups[g].members) {
+      lsop_op* op = b->ops[i];
+      const size_t n = op->n();
+      slot_of[i] = (int)all.size();
+      for (int v = 0; v < nvec[i]; ++v) {
+        Slot<T> sl;
+        sl.x = x[i] + (size_t)v * n;
+        sl.y = y[i] + (size_t)v * n;
+        sl.rhs = rhs ? rhs[i] + (size_t)v * n : nullptr;
+        sl.chi = Dt<T>::chi(op);
+        sl.gs = Dt<T>::gs(op);
+        sl.rnorm = rnorm ? rnorm + all.size() : nullptr;
+        all.push_back(sl);
+      }
+    }
+  }
+  goff[b->groups.size()] = (int)all.size();
+  b->host_tab.resize(all.size() * sizeof(Slot<T>));
+  if (!all.empty()) memcpy(b->host_tab.data(), all.data(), b->host_tab.size());
+}
+
+// upload the host tables and size the grouped intermediate
+template <typename T>
+int batch_prepare(lsop_batch* b, const std::vector<int>& goff, hipStream_t s) {
+  int st = grow_buf(&b->tab, &b->tab_cap, std::max<size_t>(b->host_tab.size(), 16), &b->bytes);
+  if (st) return st;
+  size_t tneed = 16;
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    const auto& G = b->groups[g];
+    tneed = std::max(tneed, sizeof(Cx<T>) * (size_t)(goff[g + 1] - goff[g]) * G.nx * 2 * G.lz);
+  }
+  if ((st = grow_buf(&b->tmp, &b->tmp_cap, tneed, &b->bytes))) return st;
+  if (!b->host_tab.empty()) {
+    LSOP_HIP(hipMemcpyAsync(b->tab, b->host_tab.data(), b->host_tab.size(), hipMemcpyHostToDevice, s));
+    LSOP_HIP(hipStreamSynchronize(s));  // the staging buffer is reused by the next call
+  }
+  return LSOP_OK;
+}
+
+// The three passes of `mode` for every group, one launch per pass per group.
+template <typename T>
+int batch_passes(lsop_batch* b, int mode, const std::vector<int>& goff, bool residual, hipStream_t s) {
+  const Slot<T>* tab = reinterpret_cast<const Slot<T>*>(b->tab);
+  Cx<T>* tmp = reinterpret_cast<Cx<T>*>(b->tmp);
+  const bool mulchi = (mode == LSOP_MODE_A || mode == LSOP_MODE_G0V), adj = !mulchi;
+  const bool xin = (mode == LSOP_MODE_A || mode == LSOP_MODE_AH);
+  const bool chi_out = (mode == LSOP_MODE_AH || mode == LSOP_MODE_VHG0H);
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    const auto& G = b->groups[g];
+    const int ns = goff[g + 1] - goff[g];
+    if (ns == 0) continue;
+    lsop_op* op0 = b->ops[G.members[0]];
+    const Slot<T>* tg = tab + goff[g];
+    const double e = sizeof(Cx<T>), t = sizeof(T), nn = (double)op0->n(), np = (double)op0->nx * op0->pz();
+    std::string fcol;
+    LSOP_HIP(prof("batch_rows_fwd", fn_name("k_rows_fwd", tname<T>(), G.lz), ns * (nn * e + np * e + (mulchi ? nn * t : 0.0)),
+                  0.0, ns, s, [&] {
+                    return launch_rows_fwd<T>(G.lz, nullptr, nullptr, tmp, nullptr, G.nx, G.nz, ns, mulchi,
+                                              Dt<T>::twz(op0), s, 1, 0, -1, tg);
+                  }));
+    LSOP_HIP(prof("batch_cols", fcol, ns * (2.0 * np * e + 2.0 * op0->pz() * G.lx * e), 0.0, ns, s, [&] {
+      int used = 0;
+      hipError_t er = launch_cols<T>(G.lx, tmp, nullptr, G.nx, op0->pz(), ns, adj, Dt<T>::twx(op0), s, G.col_tile,
+                                     &used, tg);
+      fcol = fn_name("k_cols", tname<T>(), G.lx, used);
+      return er;
+    }));
+    LSOP_HIP(prof("batch_rows_inv", fn_name("k_rows_inv", tname<T>(), G.lz),
+                  ns * (np * e + nn * e + (xin ? nn * e : 0.0) + (residual ? nn * e : 0.0) + (chi_out ? nn * t : 0.0)),
+                  0.0, ns, s, [&] {
+                    return launch_rows_inv<T>(G.lz, tmp, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, G.nx,
+                                              G.nz, ns, mode, Dt<T>::twz(op0), s, 1, 0, -1, tg);
+                  }));
+  }
+  return LSOP_OK;
+}
+
+template <typename T>
+int batch_apply_impl(lsop_batch* b, int mode, const Cx<T>* const* x, Cx<T>* const* y, const int* nvec, hipStream_t s) {
+  std::vector<int> goff, slot_of;
+  batch_slots<T>(b, x, y, nullptr, nullptr, nvec, goff, slot_of);
+  int st = batch_prepare<T>(b, goff, s);
+  if (st) return st;
+  return batch_passes<T>(b, mode, goff, false, s);
+}
+
+// One iteration of the grouped series (after the residuals of the previous
+// one): freeze finished vectors (zero their residual), psi <- psi - H r for
+// every instance, then r = A psi - rhs with |r|^2 per slot.
+template <typename T>
+int batch_iteration(lsop_batch* b, lsop_precond* const* pcs, Cx<T>* const* psi, Cx<T>* const* r, const int* nvec,
+                    const std::vector<int>& goff, double* rn, const int* live, int nslots, hipStream_t s) {
+  const Slot<T>* tab = reinterpret_cast<const Slot<T>*>(b->tab);
+  for (size_t g = 0; g < b->groups.size(); ++g) {
+    const int ns = goff[g + 1] - goff[g];
+    const auto& G = b->groups[g];
+    LSOP_HIP(launch_mask_slots<T>(tab + goff[g], live + goff[g], ns, (size_t)G.nx * G.nz, s));
+  }
+  for (int i = 0; i < b->count; ++i) {
+    if (nvec[i] == 0) continue;
+    if (pcs && pcs[i] && pcs[i]->kind != LSOP_PC_IDENTITY) {
+      int st = pc_apply_impl<T>(pcs[i], r[i], psi[i], nullptr, nvec[i], true, s);
+      if (st) return st;
+    } else {
+      LSOP_HIP(launch_axpby<T>(r[i], psi[i], -1.0, 1.0, nullptr, nvec[i], b->ops[i]->n(), s));
+    }
+  }
+  LSOP_HIP(launch_zero_f64(rn, nslots, s));
+  return batch_passes<T>(b, LSOP_MODE_A, goff, true, s);
+}
+
+template <typename T>
+int batch_series(lsop_batch* b, lsop_precond* const* pcs, const Cx<T>* const* rhs, Cx<T>* const* psi, const int* nvec,
+                 const lsop_solve_params* p, bool use_graph, lsop_solve_info* info, hipStream_t user_s) {
+  const int cnt = b->count;
+  // work: residual vectors, norms, live flags
+  std::vector<size_t> roff(cnt);
+  size_t rtot = 0;
+  int nslots = 0;
+  for (int i = 0; i < cnt; ++i) {
+    roff[i] = rtot;
+    rtot += (size_t)nvec[i] * b->ops[i]->n();
+    nslots += nvec[i];
+  }
+  if (nslots == 0) return LSOP_OK;
+  const size_t rb = align_up(sizeof(Cx<T>) * rtot), nb = align_up(sizeof(double) * nslots);
+  int st = grow_buf(&b->work, &b->work_cap, rb + nb + align_up(sizeof(int) * nslots), &b->bytes);
+  if (st) return st;
+  Cx<T>* rbase = reinterpret_cast<Cx<T>*>(b->work);
+  double* rn = reinterpret_cast<double*>((char*)b->work + rb);
+  int* live = reinterpret_cast<int*>((char*)b->work + rb + nb);
+  std::vector<Cx<T>*> r(cnt);
+  for (int i = 0; i < cnt; ++i) r[i] = rbase + roff[i];
+  // captured work runs on a stream of its own (the legacy default stream cannot be captured)
+  hipStream_t s = user_s;
+  hipStream_t own = nullptr;
+  if (use_graph) {
+    LSOP_HIP(hipStreamSynchronize(user_s));
+    LSOP_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+    s = own;
+  }
+  struct Cleanup {
+    hipStream_t st = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~Cleanup() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (st) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+      }
+    }
+  } cl;
+  cl.st = own;
+  std::vector<int> goff, slot_of;
+  batch_slots<T>(b, reinterpret_cast<const Cx<T>* const*>(psi), r.data(), rhs, rn, nvec, goff, slot_of);
+  if ((st = batch_prepare<T>(b, goff, s))) return st;
+  // |rhs|^2 per slot and psi_0
+  std::vector<double> b2(nslots), rh(nslots);
+  std::vector<int> liveh(nslots, 1), rising(nslots, 0), done(nslots, 0);
+  std::vector<double> prev(nslots, INFINITY);
+  for (int i = 0; i < cnt; ++i) {
+    if (nvec[i] == 0) continue;
+    const size_t n = b->ops[i]->n();
+    LSOP_HIP(launch_norm2<T>(rhs[i], rn + slot_of[i], nullptr, nvec[i], n, s));
+    if (p->init == LSOP_INIT_H_RHS) {
+      if (pcs && pcs[i] && pcs[i]->kind != LSOP_PC_IDENTITY) {
+        if ((st = pc_apply_impl<T>(pcs[i], rhs[i], psi[i], nullptr, nvec[i], false, s))) return st;
+      } else {
+        LSOP_HIP(launch_axpby<T>(rhs[i], psi[i], 1.0, 0.0, nullptr, nvec[i], n, s));
+      }
+    } else if (p->init == LSOP_INIT_ZERO) {
+      LSOP_HIP(launch_axpby<T>(rhs[i], psi[i], 0.0, 0.0, nullptr, nvec[i], n, s));
+    }
+  }
+  LSOP_HIP(hipMemcpyAsync(b2.data(), rn, sizeof(double) * nslots, hipMemcpyDeviceToHost, s));
+  LSOP_HIP(hipStreamSynchronize(s));
+  // slot -> (instance, vector) for the per-vector report (info is in instance order)
+  std::vector<int> info_of(nslots);
+  {
+    std::vector<int> ibase(cnt, 0);
+    int acc = 0;
+    for (int i = 0; i < cnt; ++i) {
+      ibase[i] = acc;
+      acc += nvec[i];
+    }
+    for (int i = 0; i < cnt; ++i)
+      for (int v = 0; v < nvec[i]; ++v) info_of[slot_of[i] + v] = ibase[i] + v;
+  }
+  LSOP_HIP(launch_zero_f64(rn, nslots, s));
+  if ((st = batch_passes<T>(b, LSOP_MODE_A, goff, true, s))) return st;
+  const bool prof_was = g_prof;
+  for (int it = 0;; ++it) {
+    LSOP_HIP(hipMemcpyAsync(rh.data(), rn, sizeof(double) * nslots, hipMemcpyDeviceToHost, s));
+    LSOP_HIP(hipStreamSynchronize(s));
+    int nlive = 0;
+    for (int k = 0; k < nslots; ++k) {
+      if (done[k]) continue;
+      lsop_solve_info& in = info[info_of[k]];
+      const double rel = b2[k] > 0 ? std::sqrt(rh[k] / b2[k]) : std::sqrt(rh[k]);
+      in.iters = it;
+      in.rel_residual = rel;
+      if (it == 0) in.rel_residual0 = rel;
+      int stt = -1;
+      if (!std::isfinite(rel)) stt = LSOP_DIVERGED;
+      else if (rel <= p->tol) stt = LSOP_OK;
+      else {
+        rising[k] = rel > prev[k] ? rising[k] + 1 : 0;
+        prev[k] = rel;
+        if (rising[k] >= 5) stt = LSOP_DIVERGED;
+        else if (it == p->max_iter) stt = LSOP_NOT_CONVERGED;
+      }
+      if (stt >= 0) {
+        in.status = stt;
+        done[k] = 1;
+        liveh[k] = 0;
+      } else {
+        ++nlive;
+      }
+    }
+    if (nlive == 0) break;
+    LSOP_HIP(hipMemcpyAsync(live, liveh.data(), sizeof(int) * nslots, hipMemcpyHostToDevice, s));
+    if (!use_graph) {
+      if ((st = batch_iteration<T>(b, pcs, psi, r.data(), nvec, goff, rn, live, nslots, s))) return st;
+      continue;
+    }
+    if (!cl.exec) {
+      LSOP_HIP(hipStreamSynchronize(s));  // the live flags are in place before capture starts
+      g_prof = false;
+      LSOP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+      st = batch_iteration<T>(b, pcs, psi, r.data(), nvec, goff, rn, live, nslots, s);
+      const hipError_t ec = hipStreamEndCapture(s, &cl.graph);
+      g_prof = prof_was;
+      if (st) return st;
+      LSOP_HIP(ec);
+      LSOP_HIP(hipGraphInstantiate(&cl.exec, cl.graph, nullptr, nullptr, 0));
+    }
+    LSOP_HIP(hipGraphLaunch(cl.exec, s));
+  }
   return LSOP_OK;
 }
 
@@ -1306,6 +1579,134 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
     for (int v : active) total_iters[v] += inner[v].iters;
   }
   return overall_status(info, nvec);
+}
+
+// ------------------------------------------------------------------ batches
+int lsop_batch_create(int count, lsop_op* const* ops, lsop_batch** out) {
+  if (!out) return fail(LSOP_EINVAL, "null output handle");
+  *out = nullptr;
+  if (count < 1 || !ops) return fail(LSOP_EINVAL, "count must be >= 1 with an operator array");
+  int dt = -1;
+  for (int i = 0; i < count; ++i) {
+    int st = check_op(ops[i]);
+    if (st) return st;
+    if (ops[i]->dtype == LSOP_MIXED) return fail(LSOP_EUNSUPPORTED, "batches take complex float or double operators");
+    if (dt >= 0 && ops[i]->dtype != dt) return fail(LSOP_EINVAL, "all operators of a batch must share one dtype");
+    dt = ops[i]->dtype;
+  }
+  lsop_batch* b = new lsop_batch();
+  b->count = count;
+  b->dtype = dt;
+  b->ops.assign(ops, ops + count);
+  b->group_of.assign(count, -1);
+  for (int i = 0; i < count; ++i) {
+    const lsop_op* op = ops[i];
+    int g = -1;
+    for (size_t k = 0; k < b->groups.size(); ++k) {
+      const auto& G = b->groups[k];
+      if (G.nx == op->nx && G.nz == op->nz && G.lx == op->lx && G.lz == op->lz) g = (int)k;
+    }
+    if (g < 0) {
+      lsop_batch::Group G;
+      G.nx = op->nx;
+      G.nz = op->nz;
+      G.lx = op->lx;
+      G.lz = op->lz;
+      G.col_tile = op->col_tile;
+      b->groups.push_back(G);
+      g = (int)b->groups.size() - 1;
+    }
+    b->groups[g].members.push_back(i);
+    b->group_of[i] = g;
+  }
+  *out = b;
+  return LSOP_OK;
+}
+
+static int check_batch_vectors(const lsop_batch* b, const void* const* x, void* const* y, const int* nvec) {
+  if (!b) return fail(LSOP_EINVAL, "null batch");
+  if (!nvec || !x || !y) return fail(LSOP_EINVAL, "null vector arrays");
+  for (int i = 0; i < b->count; ++i) {
+    if (nvec[i] < 0) return fail(LSOP_EINVAL, "nvec must be >= 0");
+    if (nvec[i] > 0 && (!x[i] || !y[i])) return fail(LSOP_EINVAL, "null vectors for an instance");
+    if (!b->ops[i]->ready) return fail(LSOP_EINVAL, "an operator of the batch has no problem set");
+  }
+  return LSOP_OK;
+}
+
+int lsop_batch_apply(lsop_batch* b, int mode, const void* const* x_dev, void* const* y_dev, const int* nvec,
+                     void* stream) {
+  int st = check_batch_vectors(b, x_dev, y_dev, nvec);
+  if (st) return st;
+  if (mode < 0 || mode > 3) return fail(LSOP_EINVAL, "bad mode");
+  if (b->dtype == LSOP_C64)
+    return batch_apply_impl<float>(b, mode, reinterpret_cast<const Cx<float>* const*>(x_dev),
+                                   reinterpret_cast<Cx<float>* const*>(y_dev), nvec, S(stream));
+  return batch_apply_impl<double>(b, mode, reinterpret_cast<const Cx<double>* const*>(x_dev),
+                                  reinterpret_cast<Cx<double>* const*>(y_dev), nvec, S(stream));
+}
+
+int lsop_batch_autotune(lsop_batch* b, void* stream) {
+  if (!b) return fail(LSOP_EINVAL, "null batch");
+  // one tuning per shape group (the tile depends on the column length and the slot count), cached by shape
+  static std::vector<std::array<int, 5>> cache;  // dtype, lx, lz, slots bucket, tile
+  for (auto& G : b->groups) {
+    lsop_op* op0 = b->ops[G.members[0]];
+    const int m = std::min(op0->max_vec, 64);
+    const int bucket = 31 - __builtin_clz((unsigned)std::max(1, m));
+    int tile = -1;
+    for (const auto& c : cache)
+      if (c[0] == b->dtype && c[1] == G.lx && c[2] == G.lz && c[3] == bucket) tile = c[4];
+    if (tile < 0) {
+      int st = lsop_autotune(op0, m, stream);
+      if (st) return st;
+      tile = op0->col_tile;
+      cache.push_back({b->dtype, G.lx, G.lz, bucket, tile});
+    }
+    G.col_tile = tile;
+  }
+  return LSOP_OK;
+}
+
+int lsop_batch_solve(lsop_batch* b, lsop_precond* const* pcs, const void* const* rhs_dev, void* const* psi_dev,
+                     const int* nvec, const lsop_solve_params* p, int use_graph, lsop_solve_info* info, void* stream) {
+  int st = check_batch_vectors(b, rhs_dev, psi_dev, nvec);
+  if (st) return st;
+  if (!p || !info) return fail(LSOP_EINVAL, "null params or info");
+  if (!(p->tol > 0) || p->max_iter < 0) return fail(LSOP_EINVAL, "tol must be > 0 and max_iter >= 0");
+  if (p->init < 0 || p->init > 2) return fail(LSOP_EINVAL, "bad init");
+  int total = 0;
+  for (int i = 0; i < b->count; ++i) {
+    if (pcs && pcs[i] && (pcs[i]->op != b->ops[i] || !pcs[i]->built))
+      return fail(LSOP_EINVAL, "preconditioner i must be built for operator i");
+    total += nvec[i];
+  }
+  for (int k = 0; k < total; ++k) info[k] = lsop_solve_info{0, 0, INFINITY, LSOP_NOT_CONVERGED, INFINITY};
+  if (b->dtype == LSOP_C64)
+    st = batch_series<float>(b, pcs, reinterpret_cast<const Cx<float>* const*>(rhs_dev),
+                             reinterpret_cast<Cx<float>* const*>(psi_dev), nvec, p, use_graph != 0, info, S(stream));
+  else
+    st = batch_series<double>(b, pcs, reinterpret_cast<const Cx<double>* const*>(rhs_dev),
+                              reinterpret_cast<Cx<double>* const*>(psi_dev), nvec, p, use_graph != 0, info,
+                              S(stream));
+  if (st) return st;
+  return overall_status(info, total);
+}
+
+int lsop_batch_info(const lsop_batch* b, int* groups, size_t* bytes) {
+  if (!b) return fail(LSOP_EINVAL, "null batch");
+  if (groups) *groups = (int)b->groups.size();
+  if (bytes) *bytes = b->bytes;
+  return LSOP_OK;
+}
+
+void lsop_batch_destroy(lsop_batch* b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  if (b->tab) (void)hipFree(b->tab);
+  if (b->tmp) (void)hipFree(b->tmp);
+  if (b->work) (void)hipFree(b->work);
+  delete b;
 }
 
 int lsop_profile_enable(int on) {

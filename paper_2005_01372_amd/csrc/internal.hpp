@@ -31,24 +31,36 @@ int fail(int status, const std::string& msg);
 // ----------------------------------------------------------------- FFT path
 // All launchers take the stream and return hipError_t of the launch.
 // T = float or double.
+
+// One vector of a grouped launch over several operators of the same shape.
+template <typename T>
+struct Slot {
+  const Cx<T>* x;    // input vector (nx * nz)
+  Cx<T>* y;          // output vector
+  const Cx<T>* rhs;  // right-hand side of the residual epilogue, or NULL
+  const T* chi;      // the operator's contrast
+  const Cx<T>* gs;   // the operator's spectrum
+  double* rnorm;     // |y|^2 accumulator (residual epilogue), or NULL
+};
 // Sub-domain batches (nodes > 1): each stored vector holds `nodes` strips of nx
 // rows, transformed independently (slot = vector * nodes + node, chi sliced per
 // strip); rows outside [lo, hi) of a strip are read as zero (hi < 0: nx).
+// Grouped batches (tab != NULL, nodes = 1, no vidx): slot s takes its operands from tab[s].
 template <typename T>
 hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, const int* vidx, int nx, int nz,
                            int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s, int nodes = 1, int lo = 0,
-                           int hi = -1);
+                           int hi = -1, const Slot<T>* tab = nullptr);
 // tile: columns per workgroup (0 = widest that fits; narrower tiles allow more workgroups per CU)
 // *used (optional) receives the tile width launched
 template <typename T>
 hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int nslots, bool adj, const Cx<T>* tw2,
-                       hipStream_t s, int tile = 0, int* used = nullptr);
+                       hipStream_t s, int tile = 0, int* used = nullptr, const Slot<T>* tab = nullptr);
 // epi: 0 y = x - c, 1 y = c, 2 y = x - chi c, 3 y = chi c; rhs != NULL: y -= rhs and rnorm[slot] += |y|^2
 // Sub-domain batches as in pass 1; rows outside [lo, hi) of a strip are not written.
 template <typename T>
 hipError_t launch_rows_inv(int L, const Cx<T>* tmp, const Cx<T>* x, const T* chi, const Cx<T>* rhs, Cx<T>* y,
                            double* rnorm, const int* vidx, int nx, int nz, int nslots, int epi, const Cx<T>* tw2,
-                           hipStream_t s, int nodes = 1, int lo = 0, int hi = -1);
+                           hipStream_t s, int nodes = 1, int lo = 0, int hi = -1, const Slot<T>* tab = nullptr);
 // spectrum of the circulant-extended kernel table (FP64), written as gs[2][pz][lx] in T
 hipError_t launch_spectrum(int lx, int lz, const Cx<double>* ktab, int nx, int nz, Cx<double>* s1t,
                            Cx<double>* gs64, Cx<float>* gs32, const Cx<double>* tw2x, const Cx<double>* tw2z,
@@ -66,7 +78,8 @@ template <typename T>
 hipError_t launch_norm2(const Cx<T>* x, double* out, const int* vidx, int nvec, size_t n, hipStream_t s);
 template <typename To, typename Ti>
 hipError_t launch_convert(const Cx<Ti>* x, Cx<To>* y, size_t count, hipStream_t s);
-// y[vi] = a*x[vi] + b*y[vi] (real a, b) over nvec vectors of length n, indexed through vidx
+// y[vi] = a*x[vi] + b*y[vi] (real a, b) over nvec vectors of length n, indexed through vidx; a term whose
+// coefficient is 0 is not read
 template <typename T>
 hipError_t launch_axpby(const Cx<T>* x, Cx<T>* y, double a, double b, const int* vidx, int nvec, size_t n,
                         hipStream_t s);
@@ -144,6 +157,11 @@ hipError_t launch_set_identity(Cx<double>* out, size_t ld, size_t st, int r, int
 // dev[b] = max |P_b - I| entrywise
 hipError_t launch_identity_deviation(const Cx<double>* P, size_t ld, size_t st, int r, int batch, double* dev,
                                      hipStream_t s);
+// p[0 .. count) = 0 (fill kernel, graph-capturable)
+hipError_t launch_zero_f64(double* p, size_t count, hipStream_t s);
+// zero the output vectors (tab[s].y, n elements) of the slots with live[s] == 0
+template <typename T>
+hipError_t launch_mask_slots(const Slot<T>* tab, const int* live, int nslots, size_t n, hipStream_t s);
 // y[yidx[v]] += a * x[v] for v < nvec (x compact)
 template <typename T>
 hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, int nvec, size_t n, hipStream_t s);
@@ -221,4 +239,25 @@ struct lsop_precond {
   bool built = false;
   size_t bytes = 0;
   std::vector<void*> owned;
+};
+
+// A batch of operators of possibly different sizes, grouped by shape: every
+// FFT pass is launched once per group over all vectors of its members.
+struct lsop_batch {
+  int count = 0, dtype = 0;
+  std::vector<lsop_op*> ops;
+  struct Group {
+    int nx = 0, nz = 0, lx = 0, lz = 0, col_tile = 0;
+    std::vector<int> members;
+  };
+  std::vector<Group> groups;
+  std::vector<int> group_of;      // instance -> group
+  void* tab = nullptr;            // slot tables of all groups (device)
+  size_t tab_cap = 0;             // bytes
+  void* tmp = nullptr;            // grouped intermediate (largest group)
+  size_t tmp_cap = 0;
+  void* work = nullptr;           // series: residual vectors, norms, live flags
+  size_t work_cap = 0;
+  std::vector<unsigned char> host_tab;
+  size_t bytes = 0;
 };

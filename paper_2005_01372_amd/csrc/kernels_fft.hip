@@ -58,6 +58,10 @@ constexpr int rows_threads() {
 // treated as `nodes` independent nx-row strips (slot = vector * nodes + node),
 // each with its own slice of chi; rows i outside [lo, hi) of a strip read as
 // zero (pass 1) or are not written (pass 3).
+//
+// Grouped batches (tab != NULL): slot s is one vector of one of several
+// operators of the same shape; tab[s] holds its operands (vector, contrast,
+// spectrum, right-hand side, norm accumulator).
 template <typename T, int L>
 __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>* __restrict__ x,
                                                                      const T* __restrict__ chi,
@@ -65,7 +69,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
                                                                      const int* __restrict__ vidx, int nx, int nz,
                                                                      int nitems, int mulchi,
                                                                      const Cx<T>* __restrict__ tw2, int nodes, int lo,
-                                                                     int hi) {
+                                                                     int hi, const Slot<T>* __restrict__ tab) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
   __shared__ Cx<T> sbuf[GPW][2][lds_len<L>()];
@@ -84,8 +88,8 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
     const int node = slot % nodes, vs = slot / nodes;
     const int vi = vidx ? vidx[vs] : vs;
     const size_t row = (size_t)node * nx + i;
-    const Cx<T>* xr = x + (size_t)vi * vstride + row * nz;
-    const T* cr = chi + row * nz;
+    const Cx<T>* xr = tab ? tab[slot].x + row * nz : x + (size_t)vi * vstride + row * nz;
+    const T* cr = (tab ? tab[slot].chi : chi) + row * nz;
     const bool in = i >= lo && i < hi;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -152,7 +156,8 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nb) {
 template <typename T, int L, int C>
 __global__ __launch_bounds__(C * FftPlan<L>::G) void k_cols(Cx<T>* __restrict__ tmp, const Cx<T>* __restrict__ gs,
                                                             int nx, int pz, int nslots, int adj,
-                                                            const Cx<T>* __restrict__ tw2) {
+                                                            const Cx<T>* __restrict__ tw2,
+                                                            const Slot<T>* __restrict__ tab) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, NT = C * G, ST = ColTile<T, L>::stride;
   __shared__ Cx<T> tile[C * ST];
@@ -184,8 +189,9 @@ __global__ __launch_bounds__(C * FftPlan<L>::G) void k_cols(Cx<T>* __restrict__ 
     ve[e] = col[lds_pad(p)];
     vo[e] = ve[e] * tw_lo<T, L>(stw, p);
   }
-  const Cx<T>* g0 = gs + (size_t)(c0 + c) * L;
-  const Cx<T>* g1 = gs + ((size_t)pz + c0 + c) * L;
+  const Cx<T>* gsl = tab ? tab[slot].gs : gs;
+  const Cx<T>* g0 = gsl + (size_t)(c0 + c) * L;
+  const Cx<T>* g1 = gsl + ((size_t)pz + c0 + c) * L;
   fft2_regs<T, L, false>(ve, vo, g, col, xbuf[c], stw);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -216,7 +222,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
                                                                      const int* __restrict__ vidx, int nx, int nz,
                                                                      int nitems, int epi,
                                                                      const Cx<T>* __restrict__ tw2, int nodes, int lo,
-                                                                     int hi) {
+                                                                     int hi, const Slot<T>* __restrict__ tab) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
   __shared__ Cx<T> sbuf[GPW][2][lds_len<L>()];
@@ -242,7 +248,12 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
       v[e] = tr[L + p];
     }
     fft2_regs<T, L, true>(acc, v, g, sbuf[grp][0], sbuf[grp][1], stw);
-    const size_t off = (size_t)vi * vstride + row * nz;
+    const size_t off = tab ? row * nz : (size_t)vi * vstride + row * nz;
+    const Cx<T>* xs = tab ? tab[slot].x : x;
+    Cx<T>* ys = tab ? tab[slot].y : y;
+    const Cx<T>* rs = tab ? tab[slot].rhs : rhs;
+    const T* cs = (tab ? tab[slot].chi : chi) + row * nz;
+    double* rn = tab ? tab[slot].rnorm : (rnorm ? rnorm + slot : nullptr);
     double nrm = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -251,22 +262,22 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
         const Cx<T> conv = acc[e] + cmul_conj(tw_lo<T, L>(stw, p), v[e]);
         Cx<T> out;
         switch (epi) {
-          case 0: out = x[off + p] - conv; break;
+          case 0: out = xs[off + p] - conv; break;
           case 1: out = conv; break;
-          case 2: out = x[off + p] - chi[row * nz + p] * conv; break;
-          default: out = chi[row * nz + p] * conv; break;
+          case 2: out = xs[off + p] - cs[p] * conv; break;
+          default: out = cs[p] * conv; break;
         }
-        if (rhs) {
-          out = out - rhs[off + p];
+        if (rs) {
+          out = out - rs[off + p];
           nrm += (double)out.re * (double)out.re + (double)out.im * (double)out.im;
         }
-        if (valid) y[off + p] = out;
+        if (valid) ys[off + p] = out;
       }
     }
-    if (rnorm) {
+    if (rn) {
 #pragma unroll
       for (int o = G / 2; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o);
-      if (valid && g == 0) atomicAdd(&rnorm[slot], nrm);
+      if (valid && g == 0) atomicAdd(rn, nrm);
     }
     wave_sync();
   }
@@ -445,15 +456,16 @@ int grid_for_rows(int nitems, int gpw) {
 
 template <typename T>
 hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, const int* vidx, int nx, int nz,
-                           int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s, int nodes, int lo, int hi) {
+                           int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s, int nodes, int lo, int hi,
+                           const Slot<T>* tab) {
   const int nitems = nslots * nx;
   if (nitems <= 0) return hipSuccess;
-  if (nodes < 1 || nslots % nodes != 0) return hipErrorInvalidValue;
+  if (nodes < 1 || nslots % nodes != 0 || (tab && (nodes != 1 || vidx))) return hipErrorInvalidValue;
   if (hi < 0) hi = nx;
   LSOP_DISPATCH_L(L, {
     constexpr int NT = rows_threads<T, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_rows_fwd<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(NT), 0, s, x, chi, tmp, vidx,
-                       nx, nz, nitems, (int)mulchi, tw2, nodes, lo, hi);
+                       nx, nz, nitems, (int)mulchi, tw2, nodes, lo, hi, tab);
   });
   return hipGetLastError();
 }
@@ -462,7 +474,7 @@ hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, cons
 // narrower tile (more workgroups per CU) can be selected per call (tile > 0).
 template <typename T>
 hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int nslots, bool adj, const Cx<T>* tw2,
-                       hipStream_t s, int tile, int* used) {
+                       hipStream_t s, int tile, int* used, const Slot<T>* tab) {
   if (nslots <= 0) return hipSuccess;
   if (pz % 16 != 0) return hipErrorInvalidValue;  // tile groups of one 128-byte line must divide the row
   LSOP_DISPATCH_LX(L, {
@@ -479,21 +491,21 @@ hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int n
       case 16:
         if constexpr (CMAX >= 16)
           hipLaunchKernelGGL((k_cols<T, LL, 16>), grid, dim3(16 * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz, nslots,
-                             (int)adj, tw2);
+                             (int)adj, tw2, tab);
         break;
       case 8:
         if constexpr (CMAX >= 8)
           hipLaunchKernelGGL((k_cols<T, LL, 8>), grid, dim3(8 * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz, nslots,
-                             (int)adj, tw2);
+                             (int)adj, tw2, tab);
         break;
       case 4:
         if constexpr (CMAX >= 4)
           hipLaunchKernelGGL((k_cols<T, LL, 4>), grid, dim3(4 * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz, nslots,
-                             (int)adj, tw2);
+                             (int)adj, tw2, tab);
         break;
       default:
         hipLaunchKernelGGL((k_cols<T, LL, (CMAX < 2 ? CMAX : 2)>), grid, dim3((CMAX < 2 ? CMAX : 2) * FftPlan<LL>::G),
-                           0, s, tmp, gs, nx, pz, nslots, (int)adj, tw2);
+                           0, s, tmp, gs, nx, pz, nslots, (int)adj, tw2, tab);
         break;
     }
   });
@@ -503,15 +515,16 @@ hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int n
 template <typename T>
 hipError_t launch_rows_inv(int L, const Cx<T>* tmp, const Cx<T>* x, const T* chi, const Cx<T>* rhs, Cx<T>* y,
                            double* rnorm, const int* vidx, int nx, int nz, int nslots, int epi, const Cx<T>* tw2,
-                           hipStream_t s, int nodes, int lo, int hi) {
+                           hipStream_t s, int nodes, int lo, int hi, const Slot<T>* tab) {
   const int nitems = nslots * nx;
   if (nitems <= 0) return hipSuccess;
-  if (nodes < 1 || nslots % nodes != 0 || (nodes > 1 && rnorm)) return hipErrorInvalidValue;
+  if (nodes < 1 || nslots % nodes != 0 || (nodes > 1 && rnorm) || (tab && (nodes != 1 || vidx)))
+    return hipErrorInvalidValue;
   if (hi < 0) hi = nx;
   LSOP_DISPATCH_L(L, {
     constexpr int NT = rows_threads<T, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_rows_inv<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(NT), 0, s, tmp, x, chi, rhs, y,
-                       rnorm, vidx, nx, nz, nitems, epi, tw2, nodes, lo, hi);
+                       rnorm, vidx, nx, nz, nitems, epi, tw2, nodes, lo, hi, tab);
   });
   return hipGetLastError();
 }
@@ -567,12 +580,12 @@ hipError_t launch_incident(const Cx<double>* ktab, const int* si, const int* sj,
 
 #define LSOP_INST(T)                                                                                               \
   template hipError_t launch_rows_fwd<T>(int, const Cx<T>*, const T*, Cx<T>*, const int*, int, int, int, bool,    \
-                                         const Cx<T>*, hipStream_t, int, int, int);                               \
+                                         const Cx<T>*, hipStream_t, int, int, int, const Slot<T>*);               \
   template hipError_t launch_cols<T>(int, Cx<T>*, const Cx<T>*, int, int, int, bool, const Cx<T>*, hipStream_t,    \
-                                     int, int*);                                                                  \
+                                     int, int*, const Slot<T>*);                                                  \
   template hipError_t launch_rows_inv<T>(int, const Cx<T>*, const Cx<T>*, const T*, const Cx<T>*, Cx<T>*,        \
                                          double*, const int*, int, int, int, int, const Cx<T>*, hipStream_t, int, \
-                                         int, int);                                                               \
+                                         int, int, const Slot<T>*);                                               \
   template hipError_t launch_incident<T>(const Cx<double>*, const int*, const int*, const Cx<double>*, Cx<T>*,    \
                                          int, int, int, double, hipStream_t);
 LSOP_INST(float)

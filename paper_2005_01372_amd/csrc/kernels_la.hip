@@ -39,16 +39,33 @@ __global__ void k_convert(const Cx<Ti>* __restrict__ x, Cx<To>* __restrict__ y, 
     y[k] = ccast<To>(x[k]);
 }
 
+// y = a x + b y; with b = 0 the old y is not read (it may hold uninitialised values)
 template <typename T>
 __global__ void k_axpby(const Cx<T>* __restrict__ x, Cx<T>* __restrict__ y, T a, T b, const int* __restrict__ vidx,
                         size_t n) {
   const int slot = blockIdx.y;
   const size_t off = (size_t)(vidx ? vidx[slot] : slot) * n;
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
-    const Cx<T> xv = x[off + k];
-    const Cx<T> yv = y[off + k];
+    const Cx<T> xv = a != T(0) ? x[off + k] : czero<T>();
+    const Cx<T> yv = b != T(0) ? y[off + k] : czero<T>();
     y[off + k] = Cx<T>{a * xv.re + b * yv.re, a * xv.im + b * yv.im};
   }
+}
+
+// p[k] = 0 for k < count (a fill kernel: usable inside captured graphs)
+__global__ void k_zero_f64(double* __restrict__ p, size_t count) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < count; k += (size_t)gridDim.x * blockDim.x)
+    p[k] = 0.0;
+}
+
+// tab[s].y[0 .. n) = 0 for the slots whose live[s] == 0 (frozen vectors of a grouped series)
+template <typename T>
+__global__ void k_mask_slots(const Slot<T>* __restrict__ tab, const int* __restrict__ live, size_t n) {
+  const int sl = blockIdx.y;
+  if (live[sl]) return;
+  Cx<T>* y = tab[sl].y;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    y[k] = czero<T>();
 }
 
 // y[yidx[v]] += a * x[v] (x compact, y through the index list)
@@ -895,6 +912,19 @@ hipError_t launch_identity_deviation(const Cx<double>* P, size_t ld, size_t st, 
   return hipGetLastError();
 }
 
+hipError_t launch_zero_f64(double* p, size_t count, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_f64, dim3(grid1(count, 1024)), dim3(256), 0, s, p, count);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mask_slots(const Slot<T>* tab, const int* live, int nslots, size_t n, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_mask_slots<T>), dim3(grid1(n, 256), nslots), dim3(256), 0, s, tab, live, n);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, int nvec, size_t n, hipStream_t s) {
   if (nvec <= 0) return hipSuccess;
@@ -924,7 +954,8 @@ hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, 
   template hipError_t launch_bgemm<T>(const Cx<T>*, size_t, size_t, const Cx<T>*, size_t, size_t, Cx<T>*, size_t,  \
                                       size_t, const int*, const int*, int, int, int, double, double, int,          \
                                       hipStream_t);                                                                 \
-  template hipError_t launch_axpy_map<T>(const Cx<T>*, Cx<T>*, const int*, double, int, size_t, hipStream_t);
+  template hipError_t launch_axpy_map<T>(const Cx<T>*, Cx<T>*, const int*, double, int, size_t, hipStream_t);       \
+  template hipError_t launch_mask_slots<T>(const Slot<T>*, const int*, int, size_t, hipStream_t);
 LSOP_INST_LA(float)
 LSOP_INST_LA(double)
 template hipError_t launch_convert<float, double>(const Cx<double>*, Cx<float>*, size_t, hipStream_t);

@@ -30,7 +30,8 @@ EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "ls
            "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "precond_create",
            "precond_build", "precond_apply", "precond_info", "precond_destroy", "series_solve",
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
-           "lsop_profile_read_kernels")
+           "lsop_profile_read_kernels", "lsop_batch_create", "lsop_batch_apply", "lsop_batch_autotune",
+           "lsop_batch_solve", "lsop_batch_info", "lsop_batch_destroy")
 
 
 class LsopError(RuntimeError):
@@ -98,6 +99,13 @@ def load_library(path=LIB_PATH):
         "lsop_profile_reset": (ip, []),
         "lsop_profile_read": (ip, [C.POINTER(KernelStat), ip, C.POINTER(ip)]),
         "lsop_profile_read_kernels": (ip, [C.POINTER(KernelStat), ip, C.POINTER(ip)]),
+        "lsop_batch_create": (ip, [ip, C.POINTER(vp), C.POINTER(vp)]),
+        "lsop_batch_apply": (ip, [vp, ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(ip), vp]),
+        "lsop_batch_autotune": (ip, [vp, vp]),
+        "lsop_batch_solve": (ip, [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), C.POINTER(ip),
+                                  C.POINTER(SolveParams), ip, C.POINTER(SolveInfo), vp]),
+        "lsop_batch_info": (ip, [vp, C.POINTER(ip), C.POINTER(C.c_size_t)]),
+        "lsop_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -306,3 +314,67 @@ def series_solve(op, pc, rhs, psi=None, tol=1e-10, max_iter=30, init="h_rhs", re
                              C.byref(p), info, _stream())
     _check(st, allow=() if raise_on_failure else (NOT_CONVERGED, DIVERGED))
     return psi, [SolveResult(i.iters, i.refine_steps, i.rel_residual, i.status, i.rel_residual0) for i in info]
+
+
+class Batch:
+    """Instances of uneven size advanced together: one launch per FFT pass per grid-shape group."""
+
+    def __init__(self, ops):
+        self.ops = list(ops)
+        self.lib = self.ops[0].lib
+        arr = (C.c_void_p * len(self.ops))(*[op.handle.value for op in self.ops])
+        h = C.c_void_p()
+        _check(self.lib.lsop_batch_create(len(self.ops), arr, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.lsop_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _arrays(self, xs, dtype=None):
+        if len(xs) != len(self.ops):
+            raise ValueError("one tensor per instance")
+        nv = [op._vecs(x, dtype) for op, x in zip(self.ops, xs)]
+        ptrs = (C.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        return ptrs, (C.c_int * len(xs))(*nv)
+
+    def apply(self, xs, mode="A", outs=None):
+        outs = [torch.empty_like(x) for x in xs] if outs is None else outs
+        px, nv = self._arrays(xs)
+        py, _ = self._arrays(outs)
+        _check(self.lib.lsop_batch_apply(self.handle, MODES[mode], px, py, nv, _stream()))
+        return outs
+
+    def autotune(self):
+        _check(self.lib.lsop_batch_autotune(self.handle, _stream()))
+
+    def info(self):
+        g, nb = C.c_int(), C.c_size_t()
+        _check(self.lib.lsop_batch_info(self.handle, C.byref(g), C.byref(nb)))
+        return g.value, nb.value
+
+    def solve(self, pcs, rhss, psis=None, tol=1e-10, max_iter=30, init="h_rhs", use_graph=True):
+        """Lockstep series for all instances; returns (psis, [[SolveResult per vector] per instance])."""
+        psis = [torch.empty_like(r) for r in rhss] if psis is None else psis
+        pr, nv = self._arrays(rhss)
+        pp, _ = self._arrays(psis)
+        pch = (C.c_void_p * len(self.ops))(*[(pc.handle.value if pc is not None else None) for pc in pcs])
+        total = sum(nv)
+        info = (SolveInfo * max(total, 1))()
+        p = SolveParams(float(tol), int(max_iter), INIT[init], 0, 0.0)
+        st = self.lib.lsop_batch_solve(self.handle, pch, pr, pp, nv, C.byref(p), int(bool(use_graph)), info,
+                                       _stream())
+        _check(st, allow=(NOT_CONVERGED, DIVERGED))
+        out, k = [], 0
+        for n in nv:
+            out.append([SolveResult(i.iters, i.refine_steps, i.rel_residual, i.status, i.rel_residual0)
+                        for i in info[k:k + n]])
+            k += n
+        return psis, out

@@ -1,0 +1,160 @@
+"""GPU parity of batches of uneven instances: grouped FFT passes and the lockstep series.
+
+The grouped launch runs the same per-vector arithmetic as one operator, so a
+batch apply must equal the per-instance applies bit for bit; both are also
+compared with the oracle.  The lockstep series freezes finished vectors, so it
+must reproduce each instance's own series (same statuses and iteration
+counts; solutions to 1e-12 in FP64, the residual norms being atomically
+accumulated in another order) and the dense-LU solution (<= 1e-10 in FP64).
+The captured-graph path is checked against the eager path over whole solves
+(one replay per iteration, with host synchronisation and flag uploads between
+replays), twice in a row.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import announce, dev, host, make_op, rel, require_gpu
+from oracle import lsop_oracle as O
+from paper_2005_01372_amd import lsop, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def instances(sizes=(32, 48, 32, 40, 48), freqs=(8.0, 12.0, 5.0, 10.0, 15.0)):
+    out = []
+    for t, (n, f) in enumerate(zip(sizes, freqs)):
+        rng = np.random.default_rng(100 + t)
+        s = synth.smoothed_field((n, n), n / 16.0, rng)
+        vel = 1800.0 + (s - s.min()) / (s.max() - s.min()) * 800.0
+        ns = 1 + t % 3
+        si = ((np.arange(ns) + 0.5) * n / ns).astype(np.int32)
+        out.append(synth.Workload(f"inst{t}", vel, 10.0, f, 2000.0, si, np.zeros(ns, np.int32)))
+    return out
+
+
+@pytest.mark.parametrize("dtype", [lsop.C128, lsop.C64])
+@pytest.mark.parametrize("mode", ["A", "G0V", "AH", "VHG0H"])
+def test_batch_apply_equals_single_operators(dtype, mode):
+    announce(f"batch apply dtype={dtype} mode={mode}")
+    ws = instances()
+    ops = [make_op(w, dtype, 4) for w in ws]
+    tdt = torch.complex128 if dtype == lsop.C128 else torch.complex64
+    xs = [dev(synth.random_vectors((1 + t % 3, w.nx, w.nz), 10 + t), tdt) for t, w in enumerate(ws)]
+    b = lsop.Batch(ops)
+    assert b.info()[0] == 3          # shapes 32, 48, 40
+    ys = b.apply(xs, mode)
+    tol = 1e-12 if dtype == lsop.C128 else 2e-5
+    for t, (w, op) in enumerate(zip(ws, ops)):
+        single = host(op.apply(xs[t], mode))
+        assert np.array_equal(host(ys[t]), single)
+        prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+        assert rel(host(ys[t]), O.apply_direct(prob.K, prob.chi, host(xs[t]), mode)) <= tol
+
+
+def preconditioners(ops, kinds):
+    pcs = []
+    for op, kind in zip(ops, kinds):
+        if kind is None:
+            pcs.append(None)
+        elif kind == "lowrank":
+            pc = lsop.Preconditioner(op, lsop.PC_LOWRANK, rank=24, seed=5)
+            pc.build()
+            pcs.append(pc)
+        else:
+            pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=16, levels=2, seed=6)
+            pc.build()
+            pcs.append(pc)
+    return pcs
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_series_matches_each_instance_and_lu(use_graph):
+    announce(f"batch series graph={use_graph}")
+    ws = instances()
+    kinds = ["hodlr", "lowrank", None, "lowrank", "hodlr"]
+    ops = [make_op(w, lsop.C128, 4) for w in ws]
+    pcs = preconditioners(ops, kinds)
+    rhss = [op.incident(w.src_i, w.src_j) for op, w in zip(ops, ws)]
+    b = lsop.Batch(ops)
+    psis, res = b.solve(pcs, rhss, tol=1e-13, max_iter=80, use_graph=use_graph)
+    for t, (w, op, pc) in enumerate(zip(ws, ops, pcs)):
+        psi1, res1 = lsop.series_solve(op, pc, rhss[t], tol=1e-13, max_iter=80)
+        prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+        ref = O.solve_direct(prob, prob.incident(w.src_i, w.src_j))
+        got = host(psis[t])
+        for v in range(len(w.src_i)):
+            assert res[t][v].status == res1[v].status == lsop.OK, (t, v, res[t][v], res1[v])
+            assert res[t][v].iters == res1[v].iters
+            assert rel(got[v], host(psi1)[v]) <= 1e-12
+            assert rel(got[v], ref[v]) <= 1e-10
+
+
+def test_batch_graph_equals_eager_twice_fp32():
+    announce("batch graph vs eager fp32")
+    ws = instances()
+    ops = [make_op(w, lsop.C64, 4) for w in ws]
+    pcs = preconditioners(ops, ["hodlr", "lowrank", None, "lowrank", "hodlr"])
+    rhss = [op.incident(w.src_i, w.src_j) for op, w in zip(ops, ws)]
+    b = lsop.Batch(ops)
+    b.autotune()
+    pe, re_ = b.solve(pcs, rhss, tol=1e-5, max_iter=60, use_graph=False)
+    for rep in range(2):
+        pg, rg = b.solve(pcs, rhss, tol=1e-5, max_iter=60, use_graph=True)
+        for t in range(len(ws)):
+            assert [r.status for r in rg[t]] == [r.status for r in re_[t]]
+            assert [r.iters for r in rg[t]] == [r.iters for r in re_[t]]
+            assert rel(host(pg[t]), host(pe[t])) <= 1e-6
+
+
+def test_batch_freezes_finished_vectors_and_reports_failures():
+    """A diverging instance (Born on strong contrast) does not disturb the others; its status is DIVERGED."""
+    announce("batch failures")
+    ws = instances()
+    strong = synth.model_layered_salt(n=32, h=10.0, freq=15.0, seed=2, nsrc=2)
+    ws = [ws[0], strong, ws[2]]
+    ops = [make_op(w, lsop.C128, 4) for w in ws]
+    pcs = preconditioners(ops, ["hodlr", None, None])
+    rhss = [op.incident(w.src_i, w.src_j) for op, w in zip(ops, ws)]
+    b = lsop.Batch(ops)
+    psis, res = b.solve(pcs, rhss, tol=1e-12, max_iter=60, use_graph=True)
+    assert all(r.status == lsop.DIVERGED for r in res[1])
+    for t in (0, 2):
+        prob = O.Problem(ws[t].vel, ws[t].h, ws[t].freq, ws[t].c0)
+        ref = O.solve_direct(prob, prob.incident(ws[t].src_i, ws[t].src_j))
+        assert all(r.status == lsop.OK for r in res[t])
+        assert rel(host(psis[t]), ref) <= 1e-9
+
+
+def test_batch_invalid_arguments():
+    announce("batch invalid")
+    ws = instances()[:2]
+    a = make_op(ws[0], lsop.C128, 4)
+    bop = make_op(ws[1], lsop.C64, 4)
+    with pytest.raises(lsop.LsopError):
+        lsop.Batch([a, bop])                     # mixed dtypes
+    m = make_op(ws[1], lsop.MIXED, 4)
+    with pytest.raises(lsop.LsopError):
+        lsop.Batch([m])
+    b = lsop.Batch([a])
+    with pytest.raises(ValueError):
+        b.apply([])
+
+
+def test_batch_output_buffers_contents_are_ignored():
+    announce("batch garbage psi")
+    ws = instances()[:3]
+    ops = [make_op(w, lsop.C128, 4) for w in ws]
+    rhss = [op.incident(w.src_i, w.src_j) for op, w in zip(ops, ws)]
+    psis = [torch.full_like(r, float("nan")) for r in rhss]
+    b = lsop.Batch(ops)
+    pcs = preconditioners(ops, ["hodlr", "lowrank", None])
+    psis, res = b.solve(pcs, rhss, psis=psis, tol=1e-12, max_iter=80, use_graph=True)
+    for t in range(3):
+        assert all(r.status == lsop.OK for r in res[t])
+        assert not torch.isnan(psis[t]).any()

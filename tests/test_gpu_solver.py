@@ -218,3 +218,16 @@ def test_warm_start_reaches_same_fixed_point():
                                   max_iter=80)
     assert info[0].status == lsop.OK
     assert rel(host(psi), ref) <= 1e-10
+
+
+@pytest.mark.parametrize("init", ["h_rhs", "zero"])
+def test_series_output_buffer_contents_are_ignored(init):
+    """psi is an output for these starts: NaN left in it by earlier use must not leak into the result."""
+    announce(f"garbage psi init={init}")
+    w = synth.weak_contrast(32)
+    op = make_op(w, lsop.C128, 4)
+    rhs = op.incident(w.src_i, w.src_j)
+    psi = torch.full_like(rhs, float("nan"))
+    psi, res = lsop.series_solve(op, None, rhs, psi=psi, tol=1e-12, max_iter=60, init=init)
+    assert res[0].status == lsop.OK
+    assert not torch.isnan(psi).any()
