@@ -686,6 +686,23 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
   lsop_op* op = pc->op;
   const int r = pc->rank;
   const size_t n = op->n();
+  // build-only workspace: sampling buffers and the FP64 leaf workspace, released on return
+  struct Transient {
+    lsop_precond* pc;
+    ~Transient() {
+      (void)hipDeviceSynchronize();
+      for (void** p : {&pc->U, &pc->Y, reinterpret_cast<void**>(&pc->lwork)})
+        if (*p) {
+          (void)hipFree(*p);
+          *p = nullptr;
+        }
+    }
+  } transient{pc};
+  if (hipMalloc(&pc->U, sizeof(Cx<T>) * r * n) != hipSuccess || hipMalloc(&pc->Y, sizeof(Cx<T>) * r * n) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&pc->lwork), sizeof(Cx<double>) * pc->lwork_elems) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LSOP_ENOMEM, "HODLR build workspace allocation failed");
+  }
   Cx<T>* Y = reinterpret_cast<Cx<T>*>(pc->Y);
   Cx<T>* Q = reinterpret_cast<Cx<T>*>(pc->U);
   // sub-domain spectra (depend on k0 and h)
@@ -1390,10 +1407,8 @@ int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out
     (void)block_inverse_temps(nl, pc->leaf_chunk, &lw);
     lw += (size_t)pc->leaf_chunk * nl * nl;
     pc->lwork_elems = lw;
-    st |= dev_alloc(o, b, &pc->lwork, sizeof(Cx<double>) * lw);
+    // the FP64 leaf workspace and the sampling buffers U, Y live only during precond_build
     st |= dev_alloc(o, b, &pc->dinv, esz * (size_t)pc->nleaf * nl * nl);
-    st |= dev_alloc(o, b, &pc->U, esz * r * n);
-    st |= dev_alloc(o, b, &pc->Y, esz * r * n);
     st |= dev_alloc(o, b, &pc->hy, esz * (size_t)pc->tcap * n);
     const size_t small = (size_t)pc->maxseg * r * pc->tcap;
     st |= dev_alloc(o, b, &pc->hG, sizeof(Cx<double>) * small);
