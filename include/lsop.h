@@ -183,7 +183,10 @@ void precond_destroy(lsop_precond* pc);
 /* ----------------------------------------------------------------------
  * The preconditioned scattering series (eqs. 10-11, 13-14).
  *   psi_0 = H psi0 (init = LSOP_INIT_H_RHS, the paper's phi_0), or psi_dev
- *   as given (LSOP_INIT_USER), or 0 (LSOP_INIT_ZERO);
+ *   as given (LSOP_INIT_USER), or 0 (LSOP_INIT_ZERO), or, per right-hand
+ *   side, whichever of psi_dev (a candidate such as a learned warm start) and
+ *   H psi0 has the smaller residual (LSOP_INIT_BEST; the candidate is also
+ *   replaced when its residual is not finite; LSOP_MIXED treats it as USER);
  *   repeat: a = A psi - psi0 (eq. 13); stop when ||a|| / ||psi0|| <= tol;
  *           psi <- psi - H a (eq. 11; eq. 14 read as psi - (a + U Z W^H a)).
  * Each right-hand side stops on its own; the returned iterate is the one whose
@@ -196,7 +199,7 @@ void precond_destroy(lsop_precond* pc);
  * per iteration (convergence test on the host).
  * rhs_dev, psi_dev: [nvec][nx][nz]; info_host: nvec entries.  Returns OK if
  * every right-hand side converged, else the first failing status. */
-typedef enum { LSOP_INIT_H_RHS = 0, LSOP_INIT_ZERO = 1, LSOP_INIT_USER = 2 } lsop_init;
+typedef enum { LSOP_INIT_H_RHS = 0, LSOP_INIT_ZERO = 1, LSOP_INIT_USER = 2, LSOP_INIT_BEST = 3 } lsop_init;
 
 typedef struct {
   double tol;        /* relative residual target */
@@ -259,6 +262,56 @@ int lsop_batch_solve(lsop_batch* b, lsop_precond* const* pcs, const void* const*
 /* number of shape groups and device bytes held by the batch (tables, intermediates, work) */
 int lsop_batch_info(const lsop_batch* b, int* groups, size_t* bytes);
 void lsop_batch_destroy(lsop_batch* b);
+
+/* ----------------------------------------------------------------------
+ * Learned warm start (a convolutional network giving phi_0 of the series;
+ * Section 2.2: the fixed point of eq. 11 does not depend on phi_0).
+ * U-Net with `levels` resolutions (channels base * 2^l), two 3x3 convolutions
+ * + ReLU per level, 2x2 average pooling, nearest 2x upsampling with
+ * concatenation [upsampled, skip], and a 1x1 head.  Activations FP32
+ * [B][H][W][C] (channels fastest); convolutions run on bf16 matrix cores with
+ * FP32 accumulation; FP32 master weights, trained with Adam on the mean
+ * squared error.  Parameters are flat FP32, layer by layer (e0a, e0b, ...,
+ * e(L-1)b, d(L-2)a, d(L-2)b, ..., d0b, head), each as weights
+ * [kh][kw][Ci][Co] followed by Co biases.  H and W must be multiples of
+ * 2^(levels-1) and within the sizes given at creation.  Not thread-safe;
+ * all calls are asynchronous on `stream` unless noted.
+ * ---------------------------------------------------------------------- */
+typedef struct unet unet;
+
+int unet_create(int levels, int base, int cin, int cout, int max_batch, int max_h, int max_w, unet** out);
+int unet_param_count(const unet* u, size_t* n);
+/* Loads FP32 parameters (device) and resets the optimizer state. */
+int unet_set_params(unet* u, const float* params_dev, void* stream);
+int unet_get_params(const unet* u, float* params_dev, void* stream);
+/* y = net(x): x [B][H][W][cin], y [B][H][W][cout] (device FP32).  x must stay
+ * valid until a following unet_backward. */
+int unet_forward(unet* u, const float* x_dev, int B, int H, int W, float* y_dev, void* stream);
+/* Parameter gradients for the output gradient dy of the last forward pass. */
+int unet_backward(unet* u, const float* dy_dev, void* stream);
+int unet_get_grads(const unet* u, float* grads_dev, void* stream);
+/* Forward, mean squared error against target, backward, one Adam step
+ * (beta 0.9 / 0.999, eps 1e-8) at rate lr.  loss_host (optional) receives the
+ * loss; the call then synchronises `stream`. */
+int unet_train_step(unet* u, const float* x_dev, const float* target_dev, int B, int H, int W, float lr,
+                    double* loss_host, void* stream);
+/* Network inputs for nvec incident fields of `op` (complex float for
+ * LSOP_C64 operators, complex double otherwise):
+ * per cell [c/c0 - 1, Re psi0 / s_v, Im psi0 / s_v, k0 h], s_v the RMS of
+ * field v; x_dev [nvec][nx][nz][4], scale_dev [nvec] receives s_v. */
+int unet_pack_inputs(unet* u, const lsop_op* op, const void* psi0_dev, int nvec, float* x_dev, float* scale_dev,
+                     void* stream);
+/* Training target of solution psi for incident field psi0: the scaled
+ * scattered field ((psi - psi0) / s_v) as (re, im), t_dev [nvec][nx][nz][2];
+ * scale_dev as returned by unet_pack_inputs. */
+int unet_pack_target(const lsop_op* op, const void* psi_dev, const void* psi0_dev, const float* scale_dev, int nvec,
+                     float* t_dev, void* stream);
+/* phi_0 = psi0 + s_v net(inputs) for nvec incident fields (the network is
+ * trained on the scaled scattered field (psi - psi0) / s_v); psi_dev
+ * [nvec][nx][nz] in the dtype of psi0. */
+int unet_warm_start(unet* u, const lsop_op* op, const void* psi0_dev, void* psi_dev, int nvec, void* stream);
+int unet_info(const unet* u, size_t* params, size_t* bytes);
+void unet_destroy(unet* u);
 
 /* Diagnostics: FP64 Bessel evaluations used for the kernel table, on the host
  * (kind 0: (J0, Y0) at x > 0; kind 1: (J1, Y1) at 0 < x <= 2). */

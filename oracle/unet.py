@@ -108,8 +108,9 @@ def param_count(levels=4, base=32, cin=4, cout=2):
 
 
 class UNet:
-    """FP64 reference network.  With bf16=True every conv operand (input activation and weights) is rounded to
-    bfloat16 before the product, as the device's matrix cores take them; sums stay in FP64."""
+    """FP64 reference network.  With bf16=True every operand of a convolution product (input activation and
+    weights forward; output gradient, weights and input activation backward) is rounded to bfloat16 first, as
+    the device's matrix cores take them; sums stay in FP64."""
 
     def __init__(self, params, levels=4, base=32, cin=4, cout=2, bf16=False):
         self.levels, self.base, self.cin, self.cout, self.bf16 = levels, base, cin, cout, bf16
@@ -158,11 +159,13 @@ class UNet:
         return self._conv("head", h)
 
     def _conv_back(self, name, dy):
+        # both products of the backward pass take bf16 operands (the output gradient too); the bias
+        # gradient sums the unrounded output gradient
         x = self._r(self.cache[name + ":in"])
         w = self._r(self.w[name])
-        if w.ndim == 4:
-            return conv3x3_backward(x, w, dy)
-        return conv1x1_backward(x, w, dy)
+        dyr = self._r(dy)
+        dx, dw, _ = conv3x3_backward(x, w, dyr) if w.ndim == 4 else conv1x1_backward(x, w, dyr)
+        return dx, dw, dy.sum(axis=(0, 1, 2))
 
     def backward(self, dout):
         """Gradients of every parameter (flat, parameter order) for the output gradient dout."""

@@ -761,7 +761,7 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
 template <typename T>
 int series_impl(lsop_op* op, lsop_precond* pc, const Cx<T>* rhs, Cx<T>* psi, int nvec, double tol, int max_iter,
                 int init, const std::vector<int>& start, lsop_solve_info* info, Cx<T>* r, double* dnorm,
-                int* dvidx, hipStream_t s) {
+                int* dvidx, hipStream_t s, Cx<T>* alt = nullptr) {
   const size_t n = op->n();
   std::vector<int> active = start;
   if (active.empty())
@@ -784,6 +784,30 @@ int series_impl(lsop_op* op, lsop_precond* pc, const Cx<T>* rhs, Cx<T>* psi, int
     }
   } else if (init == LSOP_INIT_ZERO) {
     LSOP_HIP(launch_axpby<T>(rhs, psi, 0.0, 0.0, dvidx, na0, n, s));
+  } else if (init == LSOP_INIT_BEST) {
+    // psi holds a candidate start: per vector, keep the better of it and H rhs (smaller residual)
+    std::vector<double> nu(na0), nh(na0);
+    LSOP_HIP(hipMemsetAsync(dnorm, 0, sizeof(double) * na0, s));
+    int st = apply_impl<T>(op, LSOP_MODE_A, psi, r, rhs, dnorm, dvidx, na0, s);
+    if (st) return st;
+    LSOP_HIP(hipMemcpyAsync(nu.data(), dnorm, sizeof(double) * na0, hipMemcpyDeviceToHost, s));
+    if (pc) {
+      if ((st = pc_apply_impl<T>(pc, rhs, alt, dvidx, na0, false, s))) return st;
+    } else {
+      LSOP_HIP(launch_axpby<T>(rhs, alt, 1.0, 0.0, dvidx, na0, n, s));
+    }
+    LSOP_HIP(hipMemsetAsync(dnorm, 0, sizeof(double) * na0, s));
+    if ((st = apply_impl<T>(op, LSOP_MODE_A, alt, r, rhs, dnorm, dvidx, na0, s))) return st;
+    LSOP_HIP(hipMemcpyAsync(nh.data(), dnorm, sizeof(double) * na0, hipMemcpyDeviceToHost, s));
+    LSOP_HIP(hipStreamSynchronize(s));
+    std::vector<int> take;
+    for (int k = 0; k < na0; ++k)
+      if (!(nu[k] <= nh[k])) take.push_back(active[k]);  // also replaces a non-finite candidate
+    if (!take.empty()) {
+      LSOP_HIP(hipMemcpyAsync(dvidx, take.data(), sizeof(int) * take.size(), hipMemcpyHostToDevice, s));
+      LSOP_HIP(launch_axpby<T>(alt, psi, 1.0, 0.0, dvidx, (int)take.size(), n, s));
+      LSOP_HIP(hipStreamSynchronize(s));
+    }
   }
   std::vector<double> prev(nvec, INFINITY);
   std::vector<int> rising(nvec, 0);
@@ -1510,7 +1534,7 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
   if (!p || !info) return fail(LSOP_EINVAL, "null params or info");
   if (nvec < 1 || !rhs_dev || !psi_dev) return fail(LSOP_EINVAL, "bad vectors");
   if (!(p->tol > 0) || p->max_iter < 0) return fail(LSOP_EINVAL, "tol must be > 0 and max_iter >= 0");
-  if (p->init < 0 || p->init > 2) return fail(LSOP_EINVAL, "bad init");
+  if (p->init < 0 || p->init > 3) return fail(LSOP_EINVAL, "bad init");
   if (pc && pc->op != op) return fail(LSOP_EINVAL, "preconditioner belongs to another operator");
   if (pc && !pc->built) return fail(LSOP_EINVAL, "preconditioner not built");
   lsop_precond* pcu = (pc && pc->kind != LSOP_PC_IDENTITY) ? pc : nullptr;
@@ -1519,18 +1543,21 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
   for (int v = 0; v < nvec; ++v) info[v] = lsop_solve_info{0, 0, INFINITY, LSOP_NOT_CONVERGED, INFINITY};
   if (op->dtype != LSOP_MIXED) {
     const size_t esz = op->dtype == LSOP_C64 ? sizeof(Cx<float>) : sizeof(Cx<double>);
-    const size_t need = align_up(esz * n * nvec) + align_up(sizeof(double) * nvec) + align_up(sizeof(int) * nvec);
+    const size_t vb = align_up(esz * n * nvec);
+    const size_t need = vb * (p->init == LSOP_INIT_BEST ? 2 : 1) + align_up(sizeof(double) * nvec) +
+                        align_up(sizeof(int) * nvec);
     if ((st = grow_scratch(op, need))) return st;
     char* base = (char*)op->scratch;
     void* r = base;
-    double* dn = (double*)(base + align_up(esz * n * nvec));
+    double* dn = (double*)(base + vb);
     int* dv = (int*)((char*)dn + align_up(sizeof(double) * nvec));
+    void* alt = p->init == LSOP_INIT_BEST ? (char*)dv + align_up(sizeof(int) * nvec) : nullptr;
     if (op->dtype == LSOP_C64)
       st = series_impl<float>(op, pcu, (const Cx<float>*)rhs_dev, (Cx<float>*)psi_dev, nvec, p->tol, p->max_iter,
-                              p->init, {}, info, (Cx<float>*)r, dn, dv, s);
+                              p->init, {}, info, (Cx<float>*)r, dn, dv, s, (Cx<float>*)alt);
     else
       st = series_impl<double>(op, pcu, (const Cx<double>*)rhs_dev, (Cx<double>*)psi_dev, nvec, p->tol, p->max_iter,
-                               p->init, {}, info, (Cx<double>*)r, dn, dv, s);
+                               p->init, {}, info, (Cx<double>*)r, dn, dv, s, (Cx<double>*)alt);
     if (st) return st;
     return overall_status(info, nvec);
   }
@@ -1556,7 +1583,8 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
   LSOP_HIP(launch_norm2<double>(rhs, dn, dv, nvec, n, s));
   LSOP_HIP(hipMemcpyAsync(b2.data(), dn, sizeof(double) * nvec, hipMemcpyDeviceToHost, s));
   LSOP_HIP(hipStreamSynchronize(s));
-  if (p->init != LSOP_INIT_USER) LSOP_HIP(hipMemsetAsync(psi, 0, sizeof(Cx<double>) * n * nvec, s));
+  if (p->init != LSOP_INIT_USER && p->init != LSOP_INIT_BEST)
+    LSOP_HIP(hipMemsetAsync(psi, 0, sizeof(Cx<double>) * n * nvec, s));
   std::vector<lsop_solve_info> inner(nvec);
   std::vector<int> total_iters(nvec, 0);
   for (int k = 0;; ++k) {

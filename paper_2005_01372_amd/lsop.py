@@ -24,14 +24,16 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", NOT_
 C64, C128, MIXED = 0, 1, 2
 MODES = {"A": 0, "G0V": 1, "AH": 2, "VHG0H": 3}
 PC_IDENTITY, PC_LOWRANK, PC_HODLR = 0, 1, 2
-INIT = {"h_rhs": 0, "zero": 1, "user": 2}
+INIT = {"h_rhs": 0, "zero": 1, "user": 2, "best": 3}
 
 EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident", "lsop_autotune",
            "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "precond_create",
            "precond_build", "precond_apply", "precond_info", "precond_destroy", "series_solve",
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
            "lsop_profile_read_kernels", "lsop_batch_create", "lsop_batch_apply", "lsop_batch_autotune",
-           "lsop_batch_solve", "lsop_batch_info", "lsop_batch_destroy")
+           "lsop_batch_solve", "lsop_batch_info", "lsop_batch_destroy", "unet_create", "unet_param_count",
+           "unet_set_params", "unet_get_params", "unet_forward", "unet_backward", "unet_get_grads", "unet_train_step",
+           "unet_pack_inputs", "unet_pack_target", "unet_warm_start", "unet_info", "unet_destroy")
 
 
 class LsopError(RuntimeError):
@@ -106,6 +108,19 @@ def load_library(path=LIB_PATH):
                                   C.POINTER(SolveParams), ip, C.POINTER(SolveInfo), vp]),
         "lsop_batch_info": (ip, [vp, C.POINTER(ip), C.POINTER(C.c_size_t)]),
         "lsop_batch_destroy": (None, [vp]),
+        "unet_create": (ip, [ip, ip, ip, ip, ip, ip, ip, C.POINTER(vp)]),
+        "unet_param_count": (ip, [vp, C.POINTER(C.c_size_t)]),
+        "unet_set_params": (ip, [vp, vp, vp]),
+        "unet_get_params": (ip, [vp, vp, vp]),
+        "unet_forward": (ip, [vp, vp, ip, ip, ip, vp, vp]),
+        "unet_backward": (ip, [vp, vp, vp]),
+        "unet_get_grads": (ip, [vp, vp, vp]),
+        "unet_train_step": (ip, [vp, vp, vp, ip, ip, ip, C.c_float, C.POINTER(dp), vp]),
+        "unet_pack_inputs": (ip, [vp, vp, vp, ip, vp, vp, vp]),
+        "unet_pack_target": (ip, [vp, vp, vp, vp, ip, vp, vp]),
+        "unet_warm_start": (ip, [vp, vp, vp, vp, ip, vp]),
+        "unet_info": (ip, [vp, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+        "unet_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -378,3 +393,96 @@ class Batch:
                         for i in info[k:k + n]])
             k += n
         return psis, out
+
+
+class UNet:
+    """Convolutional warm start of the series (bf16 matrix-core convolutions, FP32 master weights, Adam)."""
+
+    def __init__(self, levels=4, base=32, cin=4, cout=2, max_batch=16, max_h=128, max_w=128):
+        self.lib = load_library()
+        h = C.c_void_p()
+        _check(self.lib.unet_create(levels, base, cin, cout, max_batch, max_h, max_w, C.byref(h)))
+        self.handle = h
+        self.levels, self.base, self.cin, self.cout = levels, base, cin, cout
+        n = C.c_size_t()
+        _check(self.lib.unet_param_count(h, C.byref(n)))
+        self.nparams = n.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.unet_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _f32(t, shape=None):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+            raise TypeError("expected a contiguous CUDA float32 tensor")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
+
+    def set_params(self, params):
+        p = torch.as_tensor(params, dtype=torch.float32)
+        p = (p if p.is_cuda else p.cuda()).contiguous()
+        if p.numel() != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters")
+        self._p = p
+        _check(self.lib.unet_set_params(self.handle, _ptr(p), _stream()))
+
+    def params(self):
+        out = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        _check(self.lib.unet_get_params(self.handle, _ptr(out), _stream()))
+        return out
+
+    def forward(self, x):
+        self._f32(x)
+        B, H, W, c = x.shape
+        if c != self.cin:
+            raise ValueError("input channels")
+        y = torch.empty((B, H, W, self.cout), dtype=torch.float32, device="cuda")
+        self._x = x
+        _check(self.lib.unet_forward(self.handle, _ptr(x), B, H, W, _ptr(y), _stream()))
+        return y
+
+    def backward(self, dy):
+        self._f32(dy)
+        _check(self.lib.unet_backward(self.handle, _ptr(dy), _stream()))
+        g = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
+        _check(self.lib.unet_get_grads(self.handle, _ptr(g), _stream()))
+        return g
+
+    def train_step(self, x, target, lr):
+        self._f32(x)
+        B, H, W, _ = x.shape
+        self._f32(target, (B, H, W, self.cout))
+        loss = C.c_double()
+        _check(self.lib.unet_train_step(self.handle, _ptr(x), _ptr(target), B, H, W, float(lr), C.byref(loss),
+                                        _stream()))
+        return loss.value
+
+    def pack_inputs(self, op, psi0):
+        nv = op._vecs(psi0)
+        x = torch.empty((nv, op.nx, op.nz, 4), dtype=torch.float32, device="cuda")
+        sc = torch.empty(nv, dtype=torch.float32, device="cuda")
+        _check(self.lib.unet_pack_inputs(self.handle, op.handle, _ptr(psi0), nv, _ptr(x), _ptr(sc), _stream()))
+        return x, sc
+
+    def pack_target(self, op, psi, psi0, scale):
+        nv = op._vecs(psi0)
+        op._vecs(psi)
+        t = torch.empty((nv, op.nx, op.nz, 2), dtype=torch.float32, device="cuda")
+        _check(self.lib.unet_pack_target(op.handle, _ptr(psi), _ptr(psi0), _ptr(self._f32(scale)), nv, _ptr(t),
+                                         _stream()))
+        return t
+
+    def warm_start(self, op, psi0, out=None):
+        nv = op._vecs(psi0)
+        out = torch.empty_like(psi0) if out is None else out
+        _check(self.lib.unet_warm_start(self.handle, op.handle, _ptr(psi0), _ptr(out), nv, _stream()))
+        return out

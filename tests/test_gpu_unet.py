@@ -1,0 +1,134 @@
+"""GPU parity of the warm-start network and of the warm-started series.
+
+The device network rounds every convolution operand to bf16 and accumulates
+in FP32; the oracle (oracle/unet.py, bf16=True) rounds the same operands and
+sums in FP64.  The two sums differ by the FP32 summation error (~1e-6
+relative), which now and then rounds an activation to the neighbouring bf16
+value (a change of up to 2^-7 of one element) before the next layer; how much
+that moves the output depends on the data.  The tolerance is therefore
+measured, not guessed: a second oracle run perturbs every activation by
+1e-6 (relative, random) before its bf16 rounding, and the device must stay
+within 4x the spread between the two oracle runs, plus a floor of 1e-4
+(forward) / 1e-3 (per-layer gradient) for a flip that the perturbed run does
+not happen to reproduce.  A wrong index, weight or layer gives errors of order
+1e-1 and above.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import announce, dev, host, make_op, rel, require_gpu
+from oracle import lsop_oracle as O
+from oracle import unet as U
+from paper_2005_01372_amd import lsop, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def f32(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).cuda()
+
+
+class NoisyRounding(U.UNet):
+    """The oracle with every activation perturbed by a relative 1e-6 before its bf16 rounding (weights exact)."""
+
+    def __init__(self, *a, seed=11, **k):
+        super().__init__(*a, **k)
+        self._rng = np.random.default_rng(seed)
+
+    def _conv(self, name, x):
+        x = x * (1.0 + 1e-6 * self._rng.standard_normal(np.shape(x)))
+        return super()._conv(name, x)
+
+    def _conv_back(self, name, dy):
+        dy = dy * (1.0 + 1e-6 * self._rng.standard_normal(np.shape(dy)))
+        return super()._conv_back(name, dy)
+
+
+@pytest.mark.parametrize("levels,base,B,H,W", [(1, 8, 2, 8, 12), (2, 4, 1, 16, 8), (2, 8, 2, 16, 16), (1, 32, 1, 16, 8),
+                                              (4, 8, 2, 32, 32), (3, 32, 1, 24, 16)])
+def test_forward_and_gradients_match_oracle(levels, base, B, H, W):
+    announce(f"unet parity L={levels} base={base} {B}x{H}x{W}")
+    r = np.random.default_rng(levels * 100 + base)
+    theta = U.he_init(levels, base, 4, 2, seed=3) + 0.01 * r.standard_normal(U.param_count(levels, base))
+    theta = theta.astype(np.float32).astype(np.float64)
+    x = r.standard_normal((B, H, W, 4)).astype(np.float32)
+    dy = r.standard_normal((B, H, W, 2)).astype(np.float32)
+    ref = U.UNet(theta, levels, base, bf16=True)
+    y_ref = ref.forward(x.astype(np.float64))
+    g_ref = ref.backward(dy.astype(np.float64))
+    alt = NoisyRounding(theta, levels, base, bf16=True)
+    y_alt = alt.forward(x.astype(np.float64))
+    g_alt = alt.backward(dy.astype(np.float64))
+    net = lsop.UNet(levels, base, 4, 2, max_batch=4, max_h=32, max_w=32)
+    assert net.nparams == theta.size
+    net.set_params(theta)
+    y = net.forward(f32(x))
+    assert rel(y.cpu().numpy(), y_ref) <= 4 * rel(y_alt, y_ref) + 1e-4
+    g = net.backward(f32(dy)).cpu().numpy().astype(np.float64)
+    at = 0
+    for name, k, ci, co in U.layer_shapes(levels, base):
+        n = k * k * ci * co + co
+        spread = rel(g_alt[at:at + n], g_ref[at:at + n])
+        assert rel(g[at:at + n], g_ref[at:at + n]) <= 4 * spread + 1e-3, (name, spread)
+        at += n
+
+
+def test_training_reduces_loss_and_loss_matches_oracle():
+    announce("unet training")
+    r = np.random.default_rng(7)
+    L, base = 3, 8
+    theta = U.he_init(L, base, 4, 2, seed=1).astype(np.float32)
+    x = r.standard_normal((4, 16, 16, 4)).astype(np.float32)
+    t = (0.5 * x[..., 1:3] + 0.2 * np.roll(x[..., 1:3], 1, axis=1)).astype(np.float32)
+    net = lsop.UNet(L, base, 4, 2, max_batch=4, max_h=16, max_w=16)
+    net.set_params(theta)
+    ref = U.UNet(theta.astype(np.float64), L, base, bf16=True)
+    loss_ref, _ = U.mse(ref.forward(x.astype(np.float64)), t)
+    losses = [net.train_step(f32(x), f32(t), 3e-3) for _ in range(60)]
+    assert abs(losses[0] - loss_ref) <= 1e-3 * loss_ref
+    assert losses[-1] < 0.25 * losses[0]
+
+
+def test_pack_inputs_and_zero_network_warm_start():
+    announce("unet pack / zero warm start")
+    w = synth.model_layered_salt(n=32, h=10.0, freq=15.0, seed=2, nsrc=3)
+    op = make_op(w, lsop.C128, 4)
+    rhs = op.incident(w.src_i, w.src_j)
+    net = lsop.UNet(2, 4, 4, 2, max_batch=4, max_h=32, max_w=32)
+    net.set_params(np.zeros(net.nparams))
+    x, sc = net.pack_inputs(op, rhs)
+    xh, r0 = x.cpu().numpy(), host(rhs)
+    s = np.sqrt(np.mean(np.abs(r0) ** 2, axis=(1, 2)))
+    assert np.allclose(sc.cpu().numpy(), s, rtol=1e-6)
+    assert np.allclose(xh[..., 0], w.vel / w.c0 - 1.0, atol=1e-6)
+    assert np.allclose(xh[..., 1], r0.real / s[:, None, None], atol=1e-5)
+    assert np.allclose(xh[..., 2], r0.imag / s[:, None, None], atol=1e-5)
+    k0h = 2 * np.pi * w.freq / w.c0 * w.h
+    assert np.allclose(xh[..., 3], k0h, rtol=1e-6)
+    psi = net.warm_start(op, rhs)
+    assert np.array_equal(host(psi), r0)
+
+
+def test_best_start_takes_the_better_candidate():
+    """LSOP_INIT_BEST: an exact candidate finishes at iteration 0; a useless one falls back to H psi0."""
+    announce("series best start")
+    w = synth.model_layered_salt(n=32, h=10.0, freq=15.0, seed=2, nsrc=2)
+    prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+    ref = O.solve_direct(prob, prob.incident(w.src_i, w.src_j))
+    op = make_op(w, lsop.C128, 4)
+    pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=16, levels=2, seed=4)
+    pc.build()
+    rhs = op.incident(w.src_i, w.src_j)
+    _, base = lsop.series_solve(op, pc, rhs, tol=1e-12, max_iter=60)
+    cand = dev(ref)
+    cand[1] = float("nan")                       # second candidate unusable
+    psi, res = lsop.series_solve(op, pc, rhs, psi=cand, tol=1e-12, max_iter=60, init="best")
+    assert res[0].iters == 0 and res[0].status == lsop.OK
+    assert res[1].iters == base[1].iters and res[1].status == lsop.OK
+    assert rel(host(psi), ref) <= 1e-10
