@@ -1152,6 +1152,11 @@ int batch_series(lsop_batch* b, lsop_precond* const* pcs, const Cx<T>* const* rh
 }
 
 }  // namespace
+
+hipError_t prof_launch(const char* name, const char* fn, double bytes, double flops, double items, hipStream_t s,
+                       const std::function<hipError_t()>& launch) {
+  return prof(name, fn, bytes, flops, items, s, launch);
+}
 }  // namespace lsop
 
 using namespace lsop;

@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -165,6 +166,12 @@ hipError_t launch_mask_slots(const Slot<T>* tab, const int* live, int nslots, si
 // y[yidx[v]] += a * x[v] for v < nvec (x compact)
 template <typename T>
 hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, int nvec, size_t n, hipStream_t s);
+
+// Runs one kernel launch; while the library's profiler is on, brackets it with
+// events on stream s and records the use label, the kernel function name and
+// the launch's algorithmic bytes and flops.
+hipError_t prof_launch(const char* name, const char* fn, double bytes, double flops, double items, hipStream_t s,
+                       const std::function<hipError_t()>& launch);
 
 }  // namespace lsop
 

@@ -164,7 +164,29 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ X,
       }
 }
 
-// db[n] += sum over a pixel chunk of dY[p][n]
+// db[n] += sum over the pixels [blockIdx.x pchunk, ...) of dY[p][n], N <= 256: the block's first
+// T = (256 / N) N threads sweep the chunk as one flat array with stride T, so thread t always meets column
+// t % N; the per-thread sums are then reduced per column in LDS (one atomic per column and block).
+__global__ __launch_bounds__(256) void k_colsum_flat(const float* __restrict__ dY, int P, int N, int pchunk,
+                                                     float* __restrict__ db) {
+  __shared__ float red[256];
+  const int T = (256 / N) * N, t = threadIdx.x;
+  const int pbeg = blockIdx.x * pchunk, pend = min(P, pbeg + pchunk);
+  float s = 0.f;
+  if (t < T && pbeg < pend) {
+    const size_t end = (size_t)pend * N;
+    for (size_t i = (size_t)pbeg * N + t; i < end; i += T) s += dY[i];
+  }
+  red[t] = s;
+  __syncthreads();
+  if (t < N) {
+    float v = 0.f;
+    for (int m = t; m < T; m += N) v += red[m];
+    atomicAdd(&db[t], v);
+  }
+}
+
+// db[n] += sum over a pixel chunk of dY[p][n] (any N; one thread per column)
 __global__ void k_colsum(const float* __restrict__ dY, int P, int N, int pchunk, float* __restrict__ db) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
@@ -367,8 +389,8 @@ hipError_t launch_conv_fwd(int ks, const float* X, int C, const unsigned short* 
   return hipGetLastError();
 }
 
-hipError_t launch_conv_wgrad(int ks, const float* X, int C, const float* dY, int N, float* dW, float* db, int B, int H,
-                             int W, hipStream_t s) {
+hipError_t launch_conv_wgrad(int ks, const float* X, int C, const float* dY, int N, float* dW, int B, int H, int W,
+                             hipStream_t s) {
   const int P = B * H * W, K = ks * ks * C;
   if (P <= 0) return hipSuccess;
   // pixel chunks: enough workgroups to fill the chip, chunks a multiple of the 32-pixel stage
@@ -384,8 +406,16 @@ hipError_t launch_conv_wgrad(int ks, const float* X, int C, const float* dY, int
     hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, s, X, C, dY, N, dW, B, H, W, pchunk);
   else
     return hipErrorInvalidValue;
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !db) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum(const float* dY, int P, int N, float* db, hipStream_t s) {
+  if (P <= 0 || N <= 0) return hipSuccess;
+  if (N <= 256) {
+    const int pchunk = std::max(64, (P + 2047) / 2048);
+    hipLaunchKernelGGL(k_colsum_flat, dim3((P + pchunk - 1) / pchunk), dim3(256), 0, s, dY, P, N, pchunk, db);
+    return hipGetLastError();
+  }
   const int bchunk = 1024;
   hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64, (P + bchunk - 1) / bchunk), dim3(64), 0, s, dY, P, N, bchunk, db);
   return hipGetLastError();

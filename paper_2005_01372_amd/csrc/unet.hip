@@ -12,8 +12,9 @@ namespace lsop {
 // kernels_nn.hip
 hipError_t launch_conv_fwd(int ks, const float* X, int C, const unsigned short* Wb, int N, const float* bias, float* Y,
                            int B, int H, int W, bool relu, hipStream_t s);
-hipError_t launch_conv_wgrad(int ks, const float* X, int C, const float* dY, int N, float* dW, float* db, int B, int H,
-                             int W, hipStream_t s);
+hipError_t launch_conv_wgrad(int ks, const float* X, int C, const float* dY, int N, float* dW, int B, int H, int W,
+                             hipStream_t s);
+hipError_t launch_colsum(const float* dY, int P, int N, float* db, hipStream_t s);
 hipError_t launch_relu_bwd(float* g, const float* y, size_t n, hipStream_t s);
 hipError_t launch_avgpool2(const float* x, float* y, int B, int h, int w, int C, hipStream_t s);
 hipError_t launch_avgpool2_bwd(const float* dy, const float* add, float* dx, int B, int h, int w, int C,
@@ -85,14 +86,27 @@ int nn_alloc(unet* u, P** out, size_t bytes) {
 }
 
 int refresh_weights(unet* u, hipStream_t s) {
-  for (auto& L : u->layers) LSOP_HIP(launch_weights_bf16(u->P + L.poff, L.ks, L.ci, L.co, L.wb, L.wt, s));
+  for (auto& L : u->layers) {
+    const double kn = (double)L.ks * L.ks * L.ci * L.co;
+    LSOP_HIP(prof_launch("unet weights bf16", "k_weights_bf16", kn * 8.0, 0.0, 1, s,
+                         [&] { return launch_weights_bf16(u->P + L.poff, L.ks, L.ci, L.co, L.wb, L.wt, s); }));
+  }
+  return LSOP_OK;
+}
+
+// Y = act(conv(X) + bias) with the weights Wb (forward) or WT (data gradient); algorithmic traffic is the input,
+// the bf16 weights and the output once each; 2 P K N flops
+int conv_launch(const char* use, int ks, const float* X, int ci, const unsigned short* w, int co, const float* bias,
+                float* Y, int B, int H, int W, bool relu, hipStream_t s) {
+  const double P = (double)B * H * W, K = (double)ks * ks * ci;
+  LSOP_HIP(prof_launch(use, ks == 3 ? "k_conv_fwd<3>" : "k_conv_fwd<1>", P * ci * 4.0 + K * co * 2.0 + P * co * 4.0, 2.0 * P * K * co, P, s,
+                       [&] { return launch_conv_fwd(ks, X, ci, w, co, bias, Y, B, H, W, relu, s); }));
   return LSOP_OK;
 }
 
 int conv(unet* u, const unet::Layer& L, const float* X, float* Y, bool relu, int B, int H, int W, hipStream_t s) {
-  LSOP_HIP(launch_conv_fwd(L.ks, X, L.ci, L.wb, L.co, u->P + L.poff + (size_t)L.ks * L.ks * L.ci * L.co, Y, B, H, W,
-                           relu, s));
-  return LSOP_OK;
+  return conv_launch("unet conv forward", L.ks, X, L.ci, L.wb, L.co,
+                     u->P + L.poff + (size_t)L.ks * L.ks * L.ci * L.co, Y, B, H, W, relu, s);
 }
 
 int forward(unet* u, const float* x, int B, int H, int W, float* y, hipStream_t s) {
@@ -104,14 +118,19 @@ int forward(unet* u, const float* x, int B, int H, int W, float* y, hipStream_t 
     if (!st) st = conv(u, u->enc(l, 1), u->ea[l], u->eb[l], true, B, h, w, s);
     if (st) return st;
     if (l < Lv - 1) {
-      LSOP_HIP(launch_avgpool2(u->eb[l], u->pool[l], B, h / 2, w / 2, u->ch(l), s));
+      const double e = (double)B * h * w * u->ch(l);
+      LSOP_HIP(prof_launch("unet pool", "k_avgpool2", e * 5.0, e, e, s,
+                           [&] { return launch_avgpool2(u->eb[l], u->pool[l], B, h / 2, w / 2, u->ch(l), s); }));
       in = u->pool[l];
     }
   }
   const float* prev = u->eb[Lv - 1];
   for (int l = Lv - 2; l >= 0; --l) {
     const int h = H >> l, w = W >> l;
-    LSOP_HIP(launch_upcat(prev, u->eb[l], u->cat[l], B, h / 2, w / 2, u->ch(l + 1), u->ch(l), s));
+    const double e = (double)B * h * w * (u->ch(l + 1) + u->ch(l));
+    LSOP_HIP(prof_launch("unet upsample+concat", "k_upcat", e * 4.0 + (double)B * h * w * (u->ch(l + 1) / 4.0 + u->ch(l)) * 4.0,
+                         0.0, e, s,
+                         [&] { return launch_upcat(prev, u->eb[l], u->cat[l], B, h / 2, w / 2, u->ch(l + 1), u->ch(l), s); }));
     int st = conv(u, u->dec(l, 0), u->cat[l], u->da[l], true, B, h, w, s);
     if (!st) st = conv(u, u->dec(l, 1), u->da[l], u->db[l], true, B, h, w, s);
     if (st) return st;
@@ -131,10 +150,17 @@ int forward(unet* u, const float* x, int B, int H, int W, float* y, hipStream_t 
 // writes the weight / bias gradients and, when dX != NULL, the input gradient.
 int layer_back(unet* u, const unet::Layer& L, float* dY, const float* X, const float* Yout, float* dX, int B, int H,
                int W, hipStream_t s) {
-  if (Yout) LSOP_HIP(launch_relu_bwd(dY, Yout, (size_t)B * H * W * L.co, s));
+  const double P = (double)B * H * W, K = (double)L.ks * L.ks * L.ci;
+  if (Yout)
+    LSOP_HIP(prof_launch("unet relu backward", "k_relu_bwd", P * L.co * 12.0, P * L.co, P * L.co, s,
+                         [&] { return launch_relu_bwd(dY, Yout, (size_t)B * H * W * L.co, s); }));
   float* gw = u->G + L.poff;
-  LSOP_HIP(launch_conv_wgrad(L.ks, X, L.ci, dY, L.co, gw, gw + (size_t)L.ks * L.ks * L.ci * L.co, B, H, W, s));
-  if (dX) LSOP_HIP(launch_conv_fwd(L.ks, dY, L.co, L.wt, L.ci, nullptr, dX, B, H, W, false, s));
+  LSOP_HIP(prof_launch("unet weight gradient", L.ks == 3 ? "k_conv_wgrad<3>" : "k_conv_wgrad<1>",
+                       P * L.ci * 4.0 + P * L.co * 4.0 + K * L.co * 4.0, 2.0 * P * K * L.co, P, s,
+                       [&] { return launch_conv_wgrad(L.ks, X, L.ci, dY, L.co, gw, B, H, W, s); }));
+  LSOP_HIP(prof_launch("unet bias gradient", L.co <= 256 ? "k_colsum_flat" : "k_colsum", P * L.co * 4.0, P * L.co, P, s,
+                       [&] { return launch_colsum(dY, B * H * W, L.co, gw + (size_t)K * L.co, s); }));
+  if (dX) return conv_launch("unet data gradient", L.ks, dY, L.co, L.wt, L.ci, nullptr, dX, B, H, W, false, s);
   return LSOP_OK;
 }
 
@@ -149,13 +175,18 @@ int backward(unet* u, const float* dy, hipStream_t s) {
     const int h = H >> l, w = W >> l;
     if ((st = layer_back(u, u->dec(l, 1), ga, u->da[l], u->db[l], gb, B, h, w, s))) return st;
     if ((st = layer_back(u, u->dec(l, 0), gb, u->cat[l], u->da[l], ga, B, h, w, s))) return st;
-    LSOP_HIP(launch_upcat_bwd(ga, gb, u->skipg[l], B, h / 2, w / 2, u->ch(l + 1), u->ch(l), s));
+    const double e = (double)B * h * w * (u->ch(l + 1) + u->ch(l));
+    LSOP_HIP(prof_launch("unet upsample+concat backward", "k_upcat_bwd",
+                         e * 4.0 + (double)B * h * w * (u->ch(l + 1) / 4.0 + u->ch(l)) * 4.0, e, e, s,
+                         [&] { return launch_upcat_bwd(ga, gb, u->skipg[l], B, h / 2, w / 2, u->ch(l + 1), u->ch(l), s); }));
     std::swap(ga, gb);
   }
   for (int l = Lv - 1; l >= 0; --l) {
     const int h = H >> l, w = W >> l;
     if (l < Lv - 1) {
-      LSOP_HIP(launch_avgpool2_bwd(ga, u->skipg[l], gb, B, h / 2, w / 2, u->ch(l), s));
+      const double e = (double)B * h * w * u->ch(l);
+      LSOP_HIP(prof_launch("unet pool backward", "k_avgpool2_bwd", e * 4.0 * 2.25, e, e, s,
+                           [&] { return launch_avgpool2_bwd(ga, u->skipg[l], gb, B, h / 2, w / 2, u->ch(l), s); }));
       std::swap(ga, gb);
     }
     if ((st = layer_back(u, u->enc(l, 1), ga, u->ea[l], u->eb[l], gb, B, h, w, s))) return st;
@@ -310,10 +341,12 @@ int unet_train_step(unet* u, const float* x_dev, const float* target_dev, int B,
   if ((st = forward(u, x_dev, B, H, W, u->yout, s))) return st;
   LSOP_HIP(hipMemsetAsync(u->dloss, 0, sizeof(double), s));
   const size_t n = (size_t)B * H * W * u->cout;
-  LSOP_HIP(launch_mse(u->yout, target_dev, u->dout, n, u->dloss, s));
+  LSOP_HIP(prof_launch("unet loss", "k_mse", (double)n * 12.0, 3.0 * n, (double)n, s,
+                       [&] { return launch_mse(u->yout, target_dev, u->dout, n, u->dloss, s); }));
   if ((st = backward(u, u->dout, s))) return st;
   ++u->step;
-  LSOP_HIP(launch_adam(u->P, u->G, u->M, u->V, u->nparams, lr, 0.9f, 0.999f, 1e-8f, u->step, s));
+  LSOP_HIP(prof_launch("unet adam", "k_adam", (double)u->nparams * 28.0, 12.0 * u->nparams, (double)u->nparams, s,
+                       [&] { return launch_adam(u->P, u->G, u->M, u->V, u->nparams, lr, 0.9f, 0.999f, 1e-8f, u->step, s); }));
   if ((st = refresh_weights(u, s))) return st;
   if (loss_host) {
     LSOP_HIP(hipMemcpyAsync(loss_host, u->dloss, sizeof(double), hipMemcpyDeviceToHost, s));

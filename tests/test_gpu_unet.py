@@ -132,3 +132,75 @@ def test_best_start_takes_the_better_candidate():
     assert res[0].iters == 0 and res[0].status == lsop.OK
     assert res[1].iters == base[1].iters and res[1].status == lsop.OK
     assert rel(host(psi), ref) <= 1e-10
+
+
+def _solver_data(net, n, models, nsrc, seed0):
+    """(inputs, targets) from the solver itself: layered + salt models, 10-20 Hz, HODLR-preconditioned series
+    converged to 1e-6 (rank 32, 3 levels, one power iteration)."""
+    X, T = [], []
+    rng = np.random.default_rng(seed0)
+    for m in range(models):
+        w = synth.model_layered_salt(n=n, h=10.0, freq=float(rng.uniform(10.0, 20.0)), seed=seed0 + m, nsrc=nsrc)
+        op = lsop.Operator(n, n, lsop.C64, max_vec=nsrc)
+        op.set_problem(torch.as_tensor(w.vel).cuda(), w.h, w.freq, w.c0)
+        pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=32, levels=3, power_iters=1, seed=m)
+        pc.build()
+        rhs = op.incident(w.src_i, w.src_j)
+        psi, res = lsop.series_solve(op, pc, rhs, tol=1e-6, max_iter=30)
+        assert all(r.status == 0 for r in res)
+        x, sc = net.pack_inputs(op, rhs)
+        X.append(x)
+        T.append(net.pack_target(op, psi, rhs, sc))
+    return torch.cat(X), torch.cat(T)
+
+
+def test_trained_network_gains_over_the_series_without_it():
+    """What the learned start gains, on held-out models (seeds never trained on), at the training size.
+
+    A 3-level, 16-channel network is trained on the device for 1200 Adam steps
+    on 1536 solver-generated 64^2 solutions.  Against the true solution psi it
+    then gives a field closer than both starts the series has without it (0, and
+    the incident field psi0); its true LS residual is lower than theirs; and the
+    series (eq. 11, a weak rank-16 HODLR preconditioner) started from it needs
+    fewer iterations than the same series started from 0.  With the safeguard
+    (best of the candidate and H psi0 by true residual) the series never needs
+    more iterations than the paper's start H psi0.  The gain is a head start,
+    not a faster rate: a fraction of an iteration per solve here, nothing with
+    a strong preconditioner (the safeguard then keeps H psi0)."""
+    n, nsrc, levels, base = 64, 16, 3, 16
+    announce(f"warm-start gain: {levels} levels, {base} channels, {n}^2")
+    net = lsop.UNet(levels, base, 4, 2, max_batch=nsrc, max_h=n, max_w=n)
+    X, T = _solver_data(net, n, 96, nsrc, 2000)
+    net.set_params(U.he_init(levels, base, 4, 2, seed=0))
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    steps, losses = 1200, []
+    for s in range(steps):
+        idx = torch.randint(0, X.shape[0], (16,), device="cuda", generator=g)
+        losses.append(net.train_step(X[idx].contiguous(), T[idx].contiguous(), 2e-3 if s < 900 else 5e-4))
+    assert np.mean(losses[-50:]) < 0.3 * losses[0]
+    iters = {k: 0 for k in ("zero", "user", "h_rhs", "best")}
+    for seed in (9001, 9002):
+        w = synth.model_layered_salt(n=n, h=10.0, freq=15.0, seed=seed, nsrc=nsrc)
+        op = lsop.Operator(n, n, lsop.C64, max_vec=nsrc)
+        op.set_problem(torch.as_tensor(w.vel).cuda(), w.h, w.freq, w.c0)
+        rhs = op.incident(w.src_i, w.src_j)
+        strong = lsop.Preconditioner(op, lsop.PC_HODLR, rank=32, levels=3, power_iters=1, seed=9)
+        strong.build()
+        psi, res = lsop.series_solve(op, strong, rhs, tol=1e-6, max_iter=40)
+        assert all(r.status == 0 for r in res)
+        phi0 = net.warm_start(op, rhs)
+        err = lambda start: float(torch.linalg.vector_norm(start - psi) / torch.linalg.vector_norm(psi))
+        assert err(phi0) < 0.85 and err(rhs) > 1.1, (err(phi0), err(rhs))
+        resid = lambda start: np.median([r.rel_residual for r in lsop.series_solve(
+            op, None, rhs, psi=start.clone(), tol=1e-30, max_iter=0, init="user")[1]])
+        assert resid(phi0) < 1.0 and resid(phi0) < 0.5 * resid(rhs), (resid(phi0), resid(rhs))
+        weak = lsop.Preconditioner(op, lsop.PC_HODLR, rank=16, levels=3, power_iters=0, seed=5)
+        weak.build()
+        for init in iters:
+            _, rr = lsop.series_solve(op, weak, rhs, psi=phi0.clone(), tol=1e-6, max_iter=60, init=init)
+            assert all(r.status == 0 for r in rr), init
+            iters[init] += sum(r.iters for r in rr)
+    print("iterations over 32 held-out solves:", iters)
+    assert iters["user"] < iters["zero"]
+    assert iters["best"] <= iters["h_rhs"]
