@@ -29,15 +29,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "LS solves/s to rel. residual 1e-6 at 1024^2 x128 src; FFT-conv HBM GB/s"
 HBM_PEAK_GBPS = 8000.0
-MFMA_PEAK_TFLOPS = {"float": 157.3, "double": 78.6}   # dense matrix-core peaks (fp32, fp64)
+MFMA_PEAK_TFLOPS = {"float": 157.3, "double": 78.6, "bf16": 2500.0}   # dense matrix-core peaks
 VALU_PEAK_TFLOPS = {"float": 157.3, "double": 78.6}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("ls1024", "uneven"), default="ls1024",
-                    help="ls1024: the 1024^2 x 128-source headline; uneven: 64 instances of uneven size in one batch")
+    ap.add_argument("--workload", choices=("ls1024", "uneven", "unet"), default="ls1024",
+                    help="ls1024: the 1024^2 x 128-source headline; uneven: 64 instances of uneven size in one batch; "
+                         "unet: training steps of the warm-start network on solver-generated 128^2 solutions, then "
+                         "the warm-started series at 256^2 and 512^2")
+    ap.add_argument("--unet-models", type=int, default=32,
+                    help="layered + salt models (32 sources each) solved for the network's training data")
+    ap.add_argument("--unet-batch", type=int, default=16)
     ap.add_argument("--count", type=int, default=64, help="instances of the uneven batch")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -83,7 +88,9 @@ def roofline_for(name, st):
     avg_s = st["ms"] / st["launches"] / 1e3
     bpl, fpl = st["bytes"] / st["launches"], st["flops"] / st["launches"]
     t = "double" if "<double" in name else "float"
-    mfma = name.startswith(("k_bgemm_mfma", "k_gemm_ah_b_mfma", "k_gemm_update_mfma"))
+    if name.startswith(("k_conv_fwd", "k_conv_wgrad")):
+        t = "bf16"   # bf16 operands on the matrix cores, FP32 accumulation
+    mfma = name.startswith(("k_bgemm_mfma", "k_gemm_ah_b_mfma", "k_gemm_update_mfma", "k_conv_fwd", "k_conv_wgrad"))
     small = name.startswith(("k_lu_inverse", "k_gram_orth"))
     out = {"kernel": name, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": st["launches"],
            "algorithmic_bytes_per_launch": bpl, "algorithmic_flops_per_launch": fpl}
@@ -276,6 +283,146 @@ def main_uneven(args):
     print(json.dumps(line), flush=True)
 
 
+def unet_cpu_baseline(samples=1):
+    """The FP64 oracle network (numpy, as written) timed on forward + backward + loss of `samples` 128^2 samples
+    (bf16 operand rounding on, as on the device)."""
+    import numpy as np
+
+    from oracle import unet as U
+    net = U.UNet(U.he_init(4, 32, 4, 2, seed=0), 4, 32, 4, 2, bf16=True)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((samples, 128, 128, 4))
+    t = rng.standard_normal((samples, 128, 128, 2))
+    t0 = time.perf_counter()
+    y = net.forward(x)
+    _, dy = U.mse(y, t)
+    net.backward(dy)
+    dt = time.perf_counter() - t0
+    return {"value": round(samples / dt, 4), "unit": "samples/s", "cores": _threads(), "kind": "oracle",
+            "sample": f"{samples} training sample(s) at 128^2 (forward, loss, backward; the Adam update is "
+                      f"negligible), oracle network in FP64 numpy with bf16 operand rounding"}
+
+
+def _threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count()
+
+
+def main_unet(args):
+    """Warm-start network (4 levels, 32 base channels, bf16 MFMA, FP32 accumulation and master weights):
+    solver-generated training data at 128^2, timed training steps, then the warm start inside the series at
+    256^2 and 512^2 (init "best": the candidate or H psi0, whichever has the smaller true residual)."""
+    import numpy as np
+    import torch
+
+    from paper_2005_01372_amd import lsop, synth
+
+    torch.cuda.init()
+    n, nsrc, bs = 128, 32, args.unet_batch
+    net = lsop.UNet(4, 32, 4, 2, max_batch=max(bs, nsrc, 16), max_h=512, max_w=512)
+    net.init_params(seed=0)
+    # training data: config-2-style layered + salt models at 128^2, 10-20 Hz, solved by the series
+    rng = np.random.default_rng(1000)
+    X, T, gen_solves = [], [], 0
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for m in range(args.unet_models):
+        w = synth.model_layered_salt(n=n, h=10.0, freq=float(rng.uniform(10.0, 20.0)), seed=1000 + m, nsrc=nsrc)
+        op = lsop.Operator(n, n, lsop.C64, max_vec=nsrc)
+        op.set_problem(torch.as_tensor(w.vel, device="cuda"), w.h, w.freq, w.c0)
+        pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=64, levels=4, power_iters=1, seed=m)
+        pc.build()
+        rhs = op.incident(w.src_i, w.src_j)
+        psi, res = lsop.series_solve(op, pc, rhs, tol=1e-6, max_iter=30)
+        gen_solves += sum(r.status == lsop.OK for r in res)
+        x, sc = net.pack_inputs(op, rhs)
+        X.append(x)
+        T.append(net.pack_target(op, psi, rhs, sc))
+        del pc, op
+    X, T = torch.cat(X), torch.cat(T)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - g0
+    print(f"[bench] {X.shape[0]} training samples generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    batches = [torch.randint(0, X.shape[0], (bs,), device="cuda", generator=gen)
+               for _ in range(args.warmup + args.steps)]
+    xb = [X[i].contiguous() for i in batches]
+    tb = [T[i].contiguous() for i in batches]
+    losses = []
+    for s in range(args.warmup):
+        losses.append(net.train_step(xb[s], tb[s], 1e-3))
+    torch.cuda.synchronize()
+    lsop.profile_reset()
+    lsop.profile_enable(True)
+    t0 = time.perf_counter()
+    for s in range(args.warmup, args.warmup + args.steps):
+        losses.append(net.train_step(xb[s], tb[s], 1e-3))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lsop.profile_enable(False)
+    by_fn = lsop.profile_read(by_kernel=True)
+    lsop.profile_reset()
+    step_s = (t1 - t0) / args.steps
+    print(f"[bench] {args.steps} timed training steps done", file=sys.stderr, flush=True)
+    dom = max(by_fn, key=lambda k: by_fn[k]["ms"])
+    roof = roofline_for(dom, by_fn[dom])
+    ratio = load_traffic(dom)
+    roof["traffic"] = None if ratio is None else round(ratio * roof["algorithmic_bytes_per_launch"])
+    conv_flops = sum(v["flops"] for k, v in by_fn.items() if k.startswith("k_conv"))
+    # warm start inside the series at 256^2 and 512^2 (16 sources each)
+    evals = []
+    for m, (side, rank, lv) in enumerate(((256, 96, 6), (512, 160, 7))):
+        w = synth.model_layered_salt(n=side, h=10.0, freq=15.0, seed=77 + m, nsrc=16)
+        op = lsop.Operator(side, side, lsop.C64, max_vec=16)
+        op.set_problem(torch.as_tensor(w.vel, device="cuda"), w.h, w.freq, w.c0)
+        rhs = op.incident(w.src_i, w.src_j)
+        pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=rank, levels=lv, power_iters=1, seed=5)
+        pc.build()
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        _, rb = lsop.series_solve(op, pc, rhs, tol=1e-6, max_iter=40)
+        torch.cuda.synchronize()
+        a1 = time.perf_counter()
+        phi0 = net.warm_start(op, rhs)
+        torch.cuda.synchronize()
+        a2 = time.perf_counter()
+        _, rw = lsop.series_solve(op, pc, rhs, psi=phi0, tol=1e-6, max_iter=40, init="best")
+        torch.cuda.synchronize()
+        a3 = time.perf_counter()
+        evals.append({"side": side, "rank": rank, "levels": lv,
+                      "series_ms": round((a1 - a0) * 1e3, 2), "warm_start_ms": round((a2 - a1) * 1e3, 2),
+                      "warm_series_ms": round((a3 - a2) * 1e3, 2),
+                      "iterations": sum(r.iters for r in rb), "warm_iterations": sum(r.iters for r in rw),
+                      "converged": sum(r.status == lsop.OK for r in rb),
+                      "warm_converged": sum(r.status == lsop.OK for r in rw)})
+        del pc, op
+    line = {
+        "metric": "warm-start network training samples/s (128^2, batch %d)" % bs, "value": bs / step_s,
+        "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": f"4-level U-Net, 32 base channels, bf16 matrix-core operands with FP32 accumulation "
+                               f"and FP32 master weights (Adam); inputs (c/c0 - 1, psi0 / rms, k0 h) at 128^2; "
+                               f"training data solved by the library's own series on {args.unet_models} "
+                               f"layered + salt models x {nsrc} sources; warm start applied inside the series at "
+                               f"256^2 and 512^2", "batch": bs, "side": n},
+        "conv_tflops": round(conv_flops / (step_s * args.steps) / 1e12, 2),
+        "data_generation": {"solves": gen_solves, "seconds": round(gen_s, 2),
+                            "solves_per_s": round(gen_solves / gen_s, 1)},
+        "loss_first_last": [round(losses[0], 4), round(losses[-1], 4)], "warm_start_eval": evals,
+        "roofline": roof,
+        "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4)}
+                    for k, v in sorted(by_fn.items(), key=lambda kv: -kv[1]["ms"])[:12]},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = unet_cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -284,6 +431,8 @@ def main():
         sys.exit(2)
     if args.workload == "uneven":
         return main_uneven(args)
+    if args.workload == "unet":
+        return main_unet(args)
     import numpy as np
     import torch
 

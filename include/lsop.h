@@ -283,6 +283,11 @@ int unet_create(int levels, int base, int cin, int cout, int max_batch, int max_
 int unet_param_count(const unet* u, size_t* n);
 /* Loads FP32 parameters (device) and resets the optimizer state. */
 int unet_set_params(unet* u, const float* params_dev, void* stream);
+/* He-normal initialisation (weights N(0, 2 / fan_in) with fan_in = k^2 Ci,
+ * biases 0; the normal draws come from the device Philox4x32-10 stream with
+ * key `seed`), and resets the optimizer state.  The paper leaves the start
+ * free; this is the usual start for ReLU networks. */
+int unet_init_params(unet* u, unsigned long long seed, void* stream);
 int unet_get_params(const unet* u, float* params_dev, void* stream);
 /* y = net(x): x [B][H][W][cin], y [B][H][W][cout] (device FP32).  x must stay
  * valid until a following unet_backward. */

@@ -196,6 +196,13 @@ __global__ void k_colsum(const float* __restrict__ dY, int P, int N, int pchunk,
   atomicAdd(&db[n], s);
 }
 
+// out[i] = scale * z[stride i] (z: standard normal draws)
+__global__ void k_scale_copy(float* __restrict__ out, const float* __restrict__ z, size_t n, int stride,
+                             float scale) {
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
+    out[k] = scale * z[k * stride];
+}
+
 // g = g * (y > 0)
 __global__ void k_relu_bwd(float* __restrict__ g, const float* __restrict__ y, size_t n) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x)
@@ -418,6 +425,12 @@ hipError_t launch_colsum(const float* dY, int P, int N, float* db, hipStream_t s
   }
   const int bchunk = 1024;
   hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64, (P + bchunk - 1) / bchunk), dim3(64), 0, s, dY, P, N, bchunk, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(float* out, const float* z, size_t n, int stride, float scale, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_copy, dim3(nn_grid(n, 4096)), dim3(256), 0, s, out, z, n, stride, scale);
   return hipGetLastError();
 }
 

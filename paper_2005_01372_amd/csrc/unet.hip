@@ -16,6 +16,7 @@ hipError_t launch_conv_wgrad(int ks, const float* X, int C, const float* dY, int
                              hipStream_t s);
 hipError_t launch_colsum(const float* dY, int P, int N, float* db, hipStream_t s);
 hipError_t launch_relu_bwd(float* g, const float* y, size_t n, hipStream_t s);
+hipError_t launch_scale_copy(float* out, const float* z, size_t n, int stride, float scale, hipStream_t s);
 hipError_t launch_avgpool2(const float* x, float* y, int B, int h, int w, int C, hipStream_t s);
 hipError_t launch_avgpool2_bwd(const float* dy, const float* add, float* dx, int B, int h, int w, int C,
                                hipStream_t s);
@@ -300,6 +301,35 @@ int unet_set_params(unet* u, const float* params_dev, void* stream) {
   if (!u || !params_dev) return fail(LSOP_EINVAL, "null argument");
   hipStream_t s = SS(stream);
   LSOP_HIP(hipMemcpyAsync(u->P, params_dev, sizeof(float) * u->nparams, hipMemcpyDeviceToDevice, s));
+  LSOP_HIP(hipMemsetAsync(u->M, 0, sizeof(float) * u->nparams, s));
+  LSOP_HIP(hipMemsetAsync(u->V, 0, sizeof(float) * u->nparams, s));
+  u->step = 0;
+  return refresh_weights(u, s);
+}
+
+int unet_init_params(unet* u, unsigned long long seed, void* stream) {
+  if (!u) return fail(LSOP_EINVAL, "null argument");
+  hipStream_t s = SS(stream);
+  // one standard normal draw per parameter: the range finder's Philox4x32-10 generator, which writes real
+  // draws as complex numbers with zero imaginary part (read with stride 2) into a temporary buffer
+  Cx<float>* z = nullptr;
+  if (hipMalloc(&z, sizeof(Cx<float>) * u->nparams) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LSOP_ENOMEM, "unet_init_params: temporary of " + std::to_string(u->nparams) + " draws");
+  }
+  int st = LSOP_OK;
+  if (launch_philox_normal<float>(z, 1, u->nparams, seed, s) != hipSuccess) st = fail(LSOP_EHIP, "philox launch");
+  for (const auto& L : u->layers) {
+    if (st) break;
+    const size_t nw = (size_t)L.ks * L.ks * L.ci * L.co;
+    if (launch_scale_copy(u->P + L.poff, reinterpret_cast<const float*>(z + L.poff), nw, 2,
+                          std::sqrt(2.0f / (float)(L.ks * L.ks * L.ci)), s) != hipSuccess ||
+        hipMemsetAsync(u->P + L.poff + nw, 0, sizeof(float) * L.co, s) != hipSuccess)
+      st = fail(LSOP_EHIP, "unet_init_params launch");
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(z);
+  if (st) return st;
   LSOP_HIP(hipMemsetAsync(u->M, 0, sizeof(float) * u->nparams, s));
   LSOP_HIP(hipMemsetAsync(u->V, 0, sizeof(float) * u->nparams, s));
   u->step = 0;

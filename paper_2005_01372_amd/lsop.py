@@ -32,7 +32,7 @@ EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "ls
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
            "lsop_profile_read_kernels", "lsop_batch_create", "lsop_batch_apply", "lsop_batch_autotune",
            "lsop_batch_solve", "lsop_batch_info", "lsop_batch_destroy", "unet_create", "unet_param_count",
-           "unet_set_params", "unet_get_params", "unet_forward", "unet_backward", "unet_get_grads", "unet_train_step",
+           "unet_set_params", "unet_init_params", "unet_get_params", "unet_forward", "unet_backward", "unet_get_grads", "unet_train_step",
            "unet_pack_inputs", "unet_pack_target", "unet_warm_start", "unet_info", "unet_destroy")
 
 
@@ -112,6 +112,7 @@ def load_library(path=LIB_PATH):
         "unet_param_count": (ip, [vp, C.POINTER(C.c_size_t)]),
         "unet_set_params": (ip, [vp, vp, vp]),
         "unet_get_params": (ip, [vp, vp, vp]),
+        "unet_init_params": (ip, [vp, C.c_ulonglong, vp]),
         "unet_forward": (ip, [vp, vp, ip, ip, ip, vp, vp]),
         "unet_backward": (ip, [vp, vp, vp]),
         "unet_get_grads": (ip, [vp, vp, vp]),
@@ -434,6 +435,10 @@ class UNet:
             raise ValueError(f"expected {self.nparams} parameters")
         self._p = p
         _check(self.lib.unet_set_params(self.handle, _ptr(p), _stream()))
+
+    def init_params(self, seed=0):
+        """He-normal weights, zero biases (device Philox stream keyed by seed); resets the optimizer."""
+        _check(self.lib.unet_init_params(self.handle, int(seed), _stream()))
 
     def params(self):
         out = torch.empty(self.nparams, dtype=torch.float32, device="cuda")

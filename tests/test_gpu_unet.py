@@ -204,3 +204,26 @@ def test_trained_network_gains_over_the_series_without_it():
     print("iterations over 32 held-out solves:", iters)
     assert iters["user"] < iters["zero"]
     assert iters["best"] <= iters["h_rhs"]
+
+
+def test_init_params_is_he_normal():
+    """Per layer: weight mean ~0 and std ~sqrt(2 / fan_in) (fan_in = k^2 Ci), biases exactly 0; a new seed
+    gives new weights and the same seed the same ones."""
+    levels, base = 3, 16
+    net = lsop.UNet(levels, base, 4, 2, max_batch=1, max_h=16, max_w=16)
+    net.init_params(seed=7)
+    p = net.params().cpu().numpy().astype(np.float64)
+    net.init_params(seed=7)
+    assert np.array_equal(p, net.params().cpu().numpy())
+    net.init_params(seed=8)
+    assert not np.array_equal(p, net.params().cpu().numpy())
+    at = 0
+    for name, k, ci, co in U.layer_shapes(levels, base):
+        nw = k * k * ci * co
+        w, b = p[at:at + nw], p[at + nw:at + nw + co]
+        std = np.sqrt(2.0 / (k * k * ci))
+        tol = 6.0 / np.sqrt(nw)   # six standard errors of the sample moments
+        assert abs(w.mean()) < tol * std and abs(w.std() / std - 1.0) < tol, name
+        assert np.all(b == 0.0), name
+        at += nw + co
+    assert at == p.size
