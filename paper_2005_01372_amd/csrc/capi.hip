@@ -77,10 +77,25 @@ std::string fn_name(const char* base, const char* t, int a = -1, int b = -1) {
 }
 
 // C = alpha A^H B (segmented) as its two profiled launches
+// Chunks per segment for C = A^H B: the caller's ksub, raised for launches with few 64 x 64 output tiles until
+// there are about 2048 workgroups (8 per CU), while chunks keep at least 1024 elements and the partials fit the
+// part_cap entries of the workspace.
+int ksub_fill(size_t seg, int nseg, int na, int nb, int ksub, size_t part_cap) {
+  const size_t tiles = (size_t)((na + 63) / 64) * ((nb + 63) / 64) * nseg;
+  const size_t want = (2048 + tiles - 1) / tiles;
+  const size_t most = std::min<size_t>(std::max<size_t>(1, seg / 1024), part_cap / ((size_t)nseg * na * nb));
+  return (int)std::max<size_t>(ksub, std::min(want, most));
+}
+
 template <typename T>
 hipError_t p_ah_b(const char* name, const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n,
-                  size_t seg, Cx<double>* C, Cx<double>* part, int ksub, hipStream_t s, double alpha = 1.0) {
+                  size_t seg, Cx<double>* C, Cx<double>* part, int ksub, hipStream_t s, double alpha = 1.0,
+                  size_t part_cap = 0) {
   if (na <= 0 || nb <= 0) return hipSuccess;
+  {
+    const size_t sg = (seg == 0 || seg > n) ? n : seg;
+    ksub = ksub_fill(sg, (int)((n + sg - 1) / sg), na, nb, ksub, part_cap);
+  }
   const GemmPlan p = gemm_ah_b_plan(n, seg, ksub);
   const double e = sizeof(Cx<T>), nab = (double)na * nb * sizeof(Cx<double>), parts = (double)p.nseg * p.ksub;
   hipError_t err = prof(name, fn_name("k_gemm_ah_b_mfma", tname<T>()), (double)(na + nb) * n * e + parts * nab,
@@ -231,8 +246,8 @@ int apply_impl(lsop_op* op, int mode, const Cx<T>* x, Cx<T>* y, const Cx<T>* rhs
 
 template <typename T>
 hipError_t p_gemm_ah_b(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n, Cx<double>* C,
-                       Cx<double>* part, int ksplit, hipStream_t s) {
-  return p_ah_b<T>("lsop_gemm_ah_b", A, na, B, vidx, nb, n, n, C, part, ksplit, s);
+                       Cx<double>* part, int ksplit, hipStream_t s, size_t part_cap = 0) {
+  return p_ah_b<T>("lsop_gemm_ah_b", A, na, B, vidx, nb, n, n, C, part, ksplit, s, 1.0, part_cap);
 }
 
 template <typename T>
@@ -289,7 +304,7 @@ int check_op(const lsop_op* op) {
 // kept[(block) * nseg + sg] receives the kept column counts of the final pass.
 template <typename T>
 int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int ksub, Cx<double>* G, Cx<double>* X,
-                Cx<double>* R, Cx<double>* part, int* kept, hipStream_t s) {
+                Cx<double>* R, Cx<double>* part, size_t part_cap, int* kept, hipStream_t s) {
   constexpr int B = 64;
   const double tol = std::is_same<T, float>::value ? 1e-9 : 1e-24;
   const double e = sizeof(Cx<T>);
@@ -298,16 +313,16 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
     Cx<T>* Yb = Y + (size_t)c0 * n;
     Cx<T>* Qb = Q + (size_t)c0 * n;
     if (c0 > 0) {  // reference Gram of the block before projection
-      LSOP_HIP(p_ah_b<T>("orth_gram", Yb, kb, Yb, nullptr, kb, n, seg, R, part, ksub, s));
+      LSOP_HIP(p_ah_b<T>("orth_gram", Yb, kb, Yb, nullptr, kb, n, seg, R, part, ksub, s, 1.0, part_cap));
     }
     for (int pass = 0; pass < 2 && c0 > 0; ++pass) {
-      LSOP_HIP(p_ah_b<T>("orth_project", Q, c0, Yb, nullptr, kb, n, seg, G, part, ksub, s, -1.0));
+      LSOP_HIP(p_ah_b<T>("orth_project", Q, c0, Yb, nullptr, kb, n, seg, G, part, ksub, s, -1.0, part_cap));
       LSOP_HIP(p_update<T>("orth_project", Q, c0, G, (size_t)c0 * kb, kb, Yb, nullptr, 0.0, Yb, nullptr, n, seg, s));
     }
     for (int pass = 0; pass < 2; ++pass) {
       const Cx<T>* src = pass == 0 ? Yb : Qb;
       Cx<T>* dst = pass == 0 ? Qb : Yb;
-      LSOP_HIP(p_ah_b<T>("orth_gram", src, kb, src, nullptr, kb, n, seg, G, part, ksub, s));
+      LSOP_HIP(p_ah_b<T>("orth_gram", src, kb, src, nullptr, kb, n, seg, G, part, ksub, s, 1.0, part_cap));
       LSOP_HIP(prof("orth_coeffs", "k_gram_orth_lds", 2.0 * nseg * kb * kb * sizeof(Cx<double>),
                     8.0 * 3.0 * kb * kb * (double)kb * nseg, nseg, s, [&] {
                       return launch_gram_orth(G, X, kb, pass == 0 ? tol : 1e-6, kept + (c0 / B) * nseg, s, nseg,
@@ -329,7 +344,7 @@ int orth_impl(lsop_precond* pc, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s) {
   Cx<double>* G = pc->small;
   Cx<double>* X = G + (size_t)r * r;
   Cx<double>* R = X + (size_t)r * r;
-  return orth_blocks<T>(Yin, Qout, r, n, n, 1, pc->ksplit, G, X, R, pc->part, pc->dflag, s);
+  return orth_blocks<T>(Yin, Qout, r, n, n, 1, pc->ksplit, G, X, R, pc->part, pc->part_cap, pc->dflag, s);
 }
 
 template <typename T>
@@ -360,7 +375,7 @@ int build_impl(lsop_precond* pc, const double* omega, hipStream_t s) {
   // eq. (12): Z = (I_r - W^H U)^{-1}
   Cx<double>* M = pc->small;
   Cx<double>* work = M + (size_t)r * r;
-  LSOP_HIP(p_gemm_ah_b<T>(W, r, U, nullptr, r, n, M, pc->part, pc->ksplit, s));
+  LSOP_HIP(p_gemm_ah_b<T>(W, r, U, nullptr, r, n, M, pc->part, pc->ksplit, s, pc->part_cap));
   LSOP_HIP(hipMemsetAsync(pc->dflag + 32, 0, sizeof(int), s));
   LSOP_HIP(launch_lu_inverse_i_minus(M, pc->Z, work, r, pc->dflag + 32, s));
   int flags[33] = {0};
@@ -420,7 +435,7 @@ int pc_apply_impl(lsop_precond* pc, const Cx<T>* x, Cx<T>* y, const int* vidx, i
     const int m = std::min(pc->tcap, nvec - c);
     const int* vc = vidx ? vidx + c : nullptr;
     const size_t off = vidx ? 0 : (size_t)c * n;
-    LSOP_HIP(p_gemm_ah_b<T>(W, r, x + off, vc, m, n, T1, pc->part, pc->ksplit, s));
+    LSOP_HIP(p_gemm_ah_b<T>(W, r, x + off, vc, m, n, T1, pc->part, pc->ksplit, s, pc->part_cap));
     LSOP_HIP(launch_small_gemm(pc->Z, T1, T2, r, m, series_update ? -1.0 : 1.0, s));
     if (series_update)
       LSOP_HIP(p_gemm_update<T>(U, r, T2, m, y + off, x + off, -1.0, y + off, vc, n, s));
@@ -505,7 +520,7 @@ int hodlr_orth(lsop_precond* pc, int lv, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s)
   const int W = pc->lev[lv].width, nseg = 2 * (pc->op->nx / W);
   const size_t seg = (size_t)(W / 2) * pc->op->nz;
   return orth_blocks<T>(Yin, Qout, pc->rank, pc->op->n(), seg, nseg, hodlr_ksub(pc, seg, nseg), pc->hG, pc->hX,
-                        pc->hK, pc->part, pc->hflag, s);
+                        pc->hK, pc->part, pc->part_cap, pc->hflag, s);
 }
 
 // In-place inverse of the m x m block at offset o of each of cnt FP64
@@ -611,7 +626,7 @@ int hodlr_apply(lsop_precond* pc, const Cx<T>* x, const int* xidx, Cx<T>* y, con
       const int ksub = hodlr_ksub(pc, seg, nseg);
       const Cx<T>* V = reinterpret_cast<const Cx<T>*>(L.V);
       const Cx<T>* Wp = reinterpret_cast<const Cx<T>*>(L.Wp);
-      LSOP_HIP(p_ah_b<T>("hodlr_apply_ah_b", V, r, yb, yc, m, n, seg, pc->hG, pc->part, ksub, s));
+      LSOP_HIP(p_ah_b<T>("hodlr_apply_ah_b", V, r, yb, yc, m, n, seg, pc->hG, pc->part, ksub, s, 1.0, pc->part_cap));
       LSOP_HIP(p_bgemm<double>("hodlr_core_apply", L.kinv, 2 * r, (size_t)4 * r * r, pc->hG, m, (size_t)2 * r * m,
                                pc->hX, m, (size_t)2 * r * m, nullptr, nullptr, 2 * r, m, 2 * r, 1.0, 0.0, nodes, s));
       LSOP_HIP(p_update<T>("hodlr_apply_update", Wp, r, pc->hX, (size_t)r * m, m, yb, nullptr, 0.0, yb, yc, n, seg, s));
@@ -747,7 +762,7 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
     if ((st = hodlr_apply<T>(pc, Y, nullptr, Wp, nullptr, r, lv + 1, s))) return st;
     // K per node from the per-half products V^H Wp, then kinv = K^{-1} P
     const int ksub = hodlr_ksub(pc, seg, nseg);
-    LSOP_HIP(p_ah_b<T>("hodlr_core_ah_b", V, r, Wp, nullptr, r, n, seg, pc->hG, pc->part, ksub, s));
+    LSOP_HIP(p_ah_b<T>("hodlr_core_ah_b", V, r, Wp, nullptr, r, n, seg, pc->hG, pc->part, ksub, s, 1.0, pc->part_cap));
     if ((st = hodlr_core_inverse(pc, lv, s))) return st;
   }
   pc->kept = r;
@@ -1417,7 +1432,8 @@ int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out
     st |= dev_alloc(o, b, &pc->Z, sizeof(Cx<double>) * r * r);
     // small: G / M (r*r), X / LU work (2 r*r), T1, T2 (r * tcap each)
     st |= dev_alloc(o, b, &pc->small, sizeof(Cx<double>) * ((size_t)3 * r * r + (size_t)2 * r * pc->tcap));
-    st |= dev_alloc(o, b, &pc->part, sizeof(Cx<double>) * (size_t)pc->ksplit * r * pc->tcap);
+    pc->part_cap = (size_t)pc->ksplit * r * pc->tcap;
+    st |= dev_alloc(o, b, &pc->part, sizeof(Cx<double>) * pc->part_cap);
     st |= dev_alloc(o, b, &pc->dflag, 256);
   } else {
     // HODLR
@@ -1444,7 +1460,8 @@ int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out
     st |= dev_alloc(o, b, &pc->hX, sizeof(Cx<double>) * small);
     // node cores: recursion temporaries (< r^2 per node), S S^{-1} (r^2 per node), pivoted fallback work (2 r^2)
     st |= dev_alloc(o, b, &pc->hK, sizeof(Cx<double>) * ((size_t)(pc->maxseg / 2) * 3 * r * r + 2 * (size_t)r * r));
-    st |= dev_alloc(o, b, &pc->part, sizeof(Cx<double>) * (size_t)pc->ksub_cap * r * pc->tcap);
+    pc->part_cap = (size_t)pc->ksub_cap * r * pc->tcap;
+    st |= dev_alloc(o, b, &pc->part, sizeof(Cx<double>) * pc->part_cap);
     st |= dev_alloc(o, b, &pc->hflag, sizeof(int) * (4 * (size_t)pc->maxseg + pc->leaf_chunk + 64));
     pc->lev.resize(p->levels);
     for (int lv = 0; lv < p->levels && !st; ++lv) {

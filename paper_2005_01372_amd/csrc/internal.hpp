@@ -240,6 +240,7 @@ struct lsop_precond {
   Cx<double>* Z = nullptr;     // [rank][rank]
   Cx<double>* small = nullptr; // gram / X / LU work / T buffers
   Cx<double>* part = nullptr;  // split-K partials
+  size_t part_cap = 0;         // entries of part
   int* dflag = nullptr;
   int ksplit = 0;
   int tcap = 0;            // columns of the T buffers

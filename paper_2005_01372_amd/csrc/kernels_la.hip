@@ -191,6 +191,16 @@ struct Mfma<double> {
 // chunk ks % ksub of segment ks / ksub.
 constexpr int GM_T = 64, GM_K = 16;
 
+// Logical index of workgroup `id` of `total` such that consecutive logical
+// indices run on the same XCD: workgroups are handed out round-robin over the
+// 8 XCDs, each with its own L2, so XCD x takes the contiguous logical range
+// [x total / 8, (x + 1) total / 8) (a bijection when total % 8 == 0; identity
+// otherwise).  Workgroups that share operands (one segment's tiles) then
+// share an L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned id, unsigned total) {
+  return (total % 8u) ? id : (id % 8u) * (total / 8u) + id / 8u;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict__ A, int na,
                                                         const Cx<T>* __restrict__ B, const int* __restrict__ vidx,
@@ -200,7 +210,10 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
   constexpr int SROW = 2 * GM_K + 1;  // reals per LDS row (odd stride)
   __shared__ T sa[GM_T * SROW];
   __shared__ T sb[GM_T * SROW];
-  const int a0 = blockIdx.x * GM_T, b0 = blockIdx.y * GM_T, ks = blockIdx.z;
+  const unsigned lid = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+  const int a0 = (int)(lid % gridDim.x) * GM_T, b0 = (int)((lid / gridDim.x) % gridDim.y) * GM_T;
+  const int ks = (int)(lid / (gridDim.x * gridDim.y));
   const size_t seg_b = (size_t)(ks / ksub) * seg;
   const size_t seg_e = seg_b + seg < n ? seg_b + seg : n;
   const size_t k_begin = seg_b + (size_t)(ks % ksub) * chunk;
@@ -221,19 +234,28 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
   const int vb = b0 + lr;
   const Cx<T>* brow = (vb < nb) ? B + (size_t)(vidx ? vidx[vb] : vb) * n : nullptr;
   const int kk = l >> 4, c16 = l & 15;
-  for (size_t kb = k_begin; kb < k_end; kb += GM_K) {
+  // the next stage's operands are loaded into registers while the current stage's MFMAs run
+  Cx<T> va[4], vb2[4];
+  auto load = [&](size_t kb) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const size_t k = kb + lk + q;
       const bool kin = k < k_end;
-      const Cx<T> va = (arow && kin) ? arow[k] : czero<T>();
-      const Cx<T> vb2 = (brow && kin) ? brow[k] : czero<T>();
-      sa[lr * SROW + 2 * (lk + q)] = va.re;
-      sa[lr * SROW + 2 * (lk + q) + 1] = va.im;
-      sb[lr * SROW + 2 * (lk + q)] = vb2.re;
-      sb[lr * SROW + 2 * (lk + q) + 1] = vb2.im;
+      va[q] = (arow && kin) ? arow[k] : czero<T>();
+      vb2[q] = (brow && kin) ? brow[k] : czero<T>();
+    }
+  };
+  load(k_begin);
+  for (size_t kb = k_begin; kb < k_end; kb += GM_K) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sa[lr * SROW + 2 * (lk + q)] = va[q].re;
+      sa[lr * SROW + 2 * (lk + q) + 1] = va[q].im;
+      sb[lr * SROW + 2 * (lk + q)] = vb2[q].re;
+      sb[lr * SROW + 2 * (lk + q) + 1] = vb2[q].im;
     }
     __syncthreads();
+    if (kb + GM_K < k_end) load(kb + GM_K);
 #pragma unroll
     for (int st = 0; st < GM_K / 2; ++st) {
       const int col = 4 * st + kk;
@@ -273,9 +295,11 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
 // (segmented form: M for element k is M + (k / seg) * mstride):
 // each wave owns 16 consecutive k (coalesced B-operand loads and stores) and
 // up to NBT * 16 b (MFMA row tiles, real and imaginary chains); M is staged in
-// LDS GU2_A rows (a) at a time; the next A element is loaded while the current
-// step's MFMAs run.
-constexpr int GU2_A = 16;
+// LDS GU2_A rows (a) at a time, and the A elements of the next block are
+// loaded into registers while the current block's MFMAs run (a whole block
+// in flight per lane covers the HBM latency; short blocks keep the register
+// count, and so the occupancy, up).
+constexpr int GU2_A = 8;
 
 template <typename T, int NBT>
 __global__ __launch_bounds__(256) void k_gemm_update_mfma(const Cx<T>* __restrict__ A, int na,
@@ -287,9 +311,10 @@ __global__ __launch_bounds__(256) void k_gemm_update_mfma(const Cx<T>* __restric
   constexpr int BW = NBT * 16;
   __shared__ Cx<T> sm[GU2_A * BW];
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const size_t k0 = ((size_t)blockIdx.x * 4 + w) * 16;
+  const size_t bx = xcd_block(blockIdx.x, gridDim.x);
+  const size_t k0 = (bx * 4 + w) * 16;
   // segmented form: the workgroup's 64 elements lie in one segment (seg % 64 == 0)
-  Mm += ((size_t)blockIdx.x * 64 / seg) * mstride;
+  Mm += (bx * 64 / seg) * mstride;
   const int kk = l >> 4, c16 = l & 15, pp = kk & 1;
   const size_t kcol = k0 + c16;
   const bool kin = kcol < n;
@@ -300,8 +325,14 @@ __global__ __launch_bounds__(256) void k_gemm_update_mfma(const Cx<T>* __restric
       cre[j] = typename MF::acc{0, 0, 0, 0};
       cim[j] = typename MF::acc{0, 0, 0, 0};
     }
-    int a_next = kk >> 1;
-    Cx<T> av = (kin && a_next < na) ? A[(size_t)a_next * n + kcol] : czero<T>();
+    // lane's A elements of one block: a = a0 + 2 st + kk / 2, st < GU2_A / 2
+    const int ab = kk >> 1;
+    Cx<T> av[GU2_A / 2];
+#pragma unroll
+    for (int st = 0; st < GU2_A / 2; ++st) {
+      const int a = ab + 2 * st;
+      av[st] = (kin && a < na) ? A[(size_t)a * n + kcol] : czero<T>();
+    }
     for (int a0 = 0; a0 < na; a0 += GU2_A) {
       __syncthreads();
       for (int idx = threadIdx.x; idx < GU2_A * BW; idx += blockDim.x) {
@@ -309,11 +340,17 @@ __global__ __launch_bounds__(256) void k_gemm_update_mfma(const Cx<T>* __restric
         sm[idx] = (a < na && b < nb) ? ccast<T>(Mm[(size_t)a * nb + b]) : czero<T>();
       }
       __syncthreads();
+      Cx<T> cur[GU2_A / 2];
+#pragma unroll
+      for (int st = 0; st < GU2_A / 2; ++st) cur[st] = av[st];
 #pragma unroll
       for (int st = 0; st < GU2_A / 2; ++st) {
-        const T bop = pp ? av.im : av.re;
-        a_next += 2;
-        av = (kin && a_next < na) ? A[(size_t)a_next * n + kcol] : czero<T>();
+        const int a = a0 + GU2_A + ab + 2 * st;
+        av[st] = (kin && a < na) ? A[(size_t)a * n + kcol] : czero<T>();
+      }
+#pragma unroll
+      for (int st = 0; st < GU2_A / 2; ++st) {
+        const T bop = pp ? cur[st].im : cur[st].re;
         const int al = 2 * st + (kk >> 1);
 #pragma unroll
         for (int j = 0; j < NBT; ++j) {
@@ -350,9 +387,11 @@ __global__ __launch_bounds__(256) void k_gemm_update_mfma(const Cx<T>* __restric
 // normalised; columns whose remaining G-norm^2 is <= drop_tol * R_kk are
 // zeroed (dropped), R = gref (the Gram matrix of the columns before an earlier
 // projection) or G itself.  One workgroup of four waves per batch entry b
-// (G_b, X_b, R_b at b * na * na, kept[b]).  LDS layouts are chosen so that lane i always reads
-// consecutive addresses: G x uses the Hermitian symmetry (G[i][l] = conj G[l][i]),
-// X is held column-major, and the projections X^H w are wavefront reductions.
+// (G_b, X_b, R_b at b * na * na, kept[b]); each product is split four ways
+// over the waves.  LDS layouts are chosen so that lanes read consecutive (or
+// odd-strided) addresses: G x uses the Hermitian symmetry (G[i][l] =
+// conj G[l][i]), and X is held column-major with an odd row stride, so X cf
+// (down the columns) and X^H w (along them) are both conflict-free.
 constexpr int SMALL_NA = 64;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -363,11 +402,15 @@ __device__ __forceinline__ double wave_sum(double v) {
 __global__ __launch_bounds__(256) void k_gram_orth_lds(const Cx<double>* __restrict__ Gg, Cx<double>* __restrict__ Xg,
                                                         int na, double drop_tol, int* kept,
                                                         const Cx<double>* __restrict__ gref) {
-  __shared__ Cx<double> G[SMALL_NA * SMALL_NA], Xc[SMALL_NA * SMALL_NA];
-  __shared__ Cx<double> x[SMALL_NA], w[SMALL_NA], cf[SMALL_NA];
+  constexpr int XS = SMALL_NA + 1;  // row stride of X (odd: row and column walks are both conflict-free)
+  __shared__ Cx<double> G[SMALL_NA * SMALL_NA], Xc[SMALL_NA * XS];
+  __shared__ Cx<double> x[SMALL_NA], w[SMALL_NA], cf[SMALL_NA], red[4][SMALL_NA];
   __shared__ double nrm_s;
   const size_t off = (size_t)blockIdx.x * na * na;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  // every product below splits its sum four ways: wave wv takes the terms [l0, l1) (or j = wv mod 4) and the
+  // partial sums are added through red
+  const int l0 = wv * (SMALL_NA / 4), l1 = min(na, l0 + SMALL_NA / 4);
   for (int i = t; i < na * na; i += blockDim.x) G[i] = Gg[off + i];
   __syncthreads();
   int nkept = 0;
@@ -375,24 +418,30 @@ __global__ __launch_bounds__(256) void k_gram_orth_lds(const Cx<double>* __restr
     if (t < na) x[t] = Cx<double>{t == k ? 1.0 : 0.0, 0.0};
     __syncthreads();
     for (int pass = 0; pass < 3; ++pass) {
-      if (t < na) {  // w = G x
+      if (lane < na) {  // w = G x (G[l][i] = conj G[i][l])
         Cx<double> acc = czero<double>();
-        for (int l = 0; l < na; ++l) acc = acc + cmul_conj(G[l * na + t], x[l]);
-        w[t] = acc;
+        for (int l = l0; l < l1; ++l) acc = acc + cmul_conj(G[l * na + lane], x[l]);
+        red[wv][lane] = acc;
       }
+      __syncthreads();
+      if (t < na) w[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
       __syncthreads();
       if (pass == 2) break;
-      for (int j = wv; j < k; j += 4) {  // cf_j = X[:, j]^H w
-        Cx<double> v = lane < na ? cmul_conj(Xc[j * SMALL_NA + lane], w[lane]) : czero<double>();
-        const double re = wave_sum(v.re), im = wave_sum(v.im);
-        if (lane == 0) cf[j] = Cx<double>{re, im};
+      if (lane < k) {  // cf_j = X[:, j]^H w
+        Cx<double> acc = czero<double>();
+        for (int l = l0; l < l1; ++l) acc = acc + cmul_conj(Xc[lane * XS + l], w[l]);
+        red[wv][lane] = acc;
       }
       __syncthreads();
-      if (t < na) {  // x -= X[:, :k] cf
+      if (t < k) cf[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
+      __syncthreads();
+      if (lane < na) {  // x -= X[:, :k] cf
         Cx<double> acc = czero<double>();
-        for (int j = 0; j < k; ++j) acc = acc + Xc[j * SMALL_NA + t] * cf[j];
-        x[t] = x[t] - acc;
+        for (int j = wv; j < k; j += 4) acc = acc + Xc[j * XS + lane] * cf[j];
+        red[wv][lane] = acc;
       }
+      __syncthreads();
+      if (t < na) x[t] = x[t] - (red[0][t] + red[1][t] + red[2][t] + red[3][t]);
       __syncthreads();
     }
     if (wv == 0) {  // nrm2 = x^H G x = x^H w
@@ -404,13 +453,13 @@ __global__ __launch_bounds__(256) void k_gram_orth_lds(const Cx<double>* __restr
     const double nrm2 = nrm_s, gkk = gref ? gref[off + (size_t)k * na + k].re : G[k * na + k].re;
     const bool keep = gkk > 1e-300 && nrm2 > drop_tol * gkk;
     const double sc = keep ? 1.0 / sqrt(nrm2) : 0.0;
-    if (t < na) Xc[k * SMALL_NA + t] = sc * x[t];
+    if (t < na) Xc[k * XS + t] = sc * x[t];
     nkept += keep ? 1 : 0;
     __syncthreads();
   }
   for (int idx = t; idx < na * na; idx += blockDim.x) {
     const int i = idx / na, j = idx % na;
-    Xg[off + idx] = Xc[j * SMALL_NA + i];
+    Xg[off + idx] = Xc[j * XS + i];
   }
   if (t == 0) kept[blockIdx.x] = nkept;
 }
