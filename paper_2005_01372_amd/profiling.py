@@ -70,8 +70,8 @@ def _copy_scale(disp, copy_bytes):
     return copy_bytes / tot
 
 
-def traffic(fetch_csv, write_csv, copy_bytes, kernel_fn, dump_json, out_path, command):
-    """HBM bytes per launch of one kernel function over its algorithmic bytes.
+def traffic(fetch_csv, write_csv, copy_bytes, kernel_fns, dump_json, out_path, command):
+    """HBM bytes per launch of each kernel function (``;``-separated names) over its algorithmic bytes.
 
     The counter runs are of bench.py with --copy-probe (a plain 1 GiB copy
     first, which scales each counter to bytes) and --dump-profile (the
@@ -79,26 +79,26 @@ def traffic(fetch_csv, write_csv, copy_bytes, kernel_fn, dump_json, out_path, co
     algorithmic bytes per kernel function).  The timed region is the end of
     the run, so its launches are the last `launches` dispatches of the kernel.
     """
-    dump = json.load(open(dump_json))["kernels"][kernel_fn]
-    nl = int(dump["launches"])
-    res = {}
-    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        disp = _dispatches(path, counter)
-        sc = _copy_scale(disp, copy_bytes)
-        mine = [v for _, name, v in disp if (kernel_fn + "(") in name][-nl:]
-        if len(mine) != nl:
-            raise SystemExit(f"{counter}: found {len(mine)} dispatches of {kernel_fn}, expected {nl}")
-        res[counter] = (sc, sc * sum(mine))
-    hbm = res["FETCH_SIZE"][1] + res["WRITE_SIZE"][1]
-    rec = {
-        "source_sha": kernel_source_sha(), "command": command, "copy_bytes": copy_bytes,
-        "copy_scale": {"FETCH_SIZE": res["FETCH_SIZE"][0], "WRITE_SIZE": res["WRITE_SIZE"][0]},
-        "kernels": {kernel_fn: {
+    dumps = json.load(open(dump_json))["kernels"]
+    disp = {c: _dispatches(p, c) for c, p in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv))}
+    scale = {c: _copy_scale(d, copy_bytes) for c, d in disp.items()}
+    kernels = {}
+    for kernel_fn in [k for k in kernel_fns.split(";") if k]:
+        dump = dumps[kernel_fn]
+        nl = int(dump["launches"])
+        tot = {}
+        for counter, d in disp.items():
+            mine = [v for _, name, v in d if (kernel_fn + "(") in name][-nl:]
+            if len(mine) != nl:
+                raise SystemExit(f"{counter}: found {len(mine)} dispatches of {kernel_fn}, expected {nl}")
+            tot[counter] = scale[counter] * sum(mine)
+        kernels[kernel_fn] = {
             "dispatches": nl,
-            "fetch_bytes_per_launch": res["FETCH_SIZE"][1] / nl, "write_bytes_per_launch": res["WRITE_SIZE"][1] / nl,
+            "fetch_bytes_per_launch": tot["FETCH_SIZE"] / nl, "write_bytes_per_launch": tot["WRITE_SIZE"] / nl,
             "algorithmic_bytes_per_launch": dump["bytes"] / nl,
-            "hbm_over_algorithmic": hbm / dump["bytes"]}},
-    }
+            "hbm_over_algorithmic": (tot["FETCH_SIZE"] + tot["WRITE_SIZE"]) / dump["bytes"]}
+    rec = {"source_sha": kernel_source_sha(), "command": command, "copy_bytes": copy_bytes,
+           "copy_scale": scale, "kernels": kernels}
     with open(out_path, "w") as fh:
         json.dump(rec, fh, indent=1)
     return rec
