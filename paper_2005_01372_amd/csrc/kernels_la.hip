@@ -705,19 +705,28 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
   if (m0 + ar < M) arow = A + bt * sA + (size_t)(mapa ? mapa[m0 + ar] : m0 + ar) * lda;
   const Cx<T>* bbase = B + bt * sB;
   const int kk = l >> 4, c16 = l & 15;
-  for (int kb = 0; kb < K; kb += GM_K) {
+  // the next stage's operands are loaded into registers while the current stage's MFMAs run
+  Cx<T> va[4], vb[4];
+  auto load = [&](int kb) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k = kb + ak + q;
-      const Cx<T> va = (arow && k < K) ? arow[k] : czero<T>();
-      sa[ar * SROW + 2 * (ak + q)] = va.re;
-      sa[ar * SROW + 2 * (ak + q) + 1] = va.im;
+      va[q] = (arow && k < K) ? arow[k] : czero<T>();
       const int kb2 = kb + bk, nn = n0 + bn + q;
-      const Cx<T> vb = (kb2 < K && nn < N) ? bbase[(size_t)kb2 * ldb + nn] : czero<T>();
-      sb[(bn + q) * SROW + 2 * bk] = vb.re;
-      sb[(bn + q) * SROW + 2 * bk + 1] = vb.im;
+      vb[q] = (kb2 < K && nn < N) ? bbase[(size_t)kb2 * ldb + nn] : czero<T>();
+    }
+  };
+  load(0);
+  for (int kb = 0; kb < K; kb += GM_K) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sa[ar * SROW + 2 * (ak + q)] = va[q].re;
+      sa[ar * SROW + 2 * (ak + q) + 1] = va[q].im;
+      sb[(bn + q) * SROW + 2 * bk] = vb[q].re;
+      sb[(bn + q) * SROW + 2 * bk + 1] = vb[q].im;
     }
     __syncthreads();
+    if (kb + GM_K < K) load(kb + GM_K);
 #pragma unroll
     for (int st = 0; st < GM_K / 2; ++st) {
       const int col = 4 * st + kk;
