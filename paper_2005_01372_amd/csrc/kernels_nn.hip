@@ -7,10 +7,11 @@
 // Activations are FP32 in memory, [B][H][W][C] (channels fastest); a
 // convolution rounds its operands to bf16 (nearest, ties to even) as it stages
 // them in LDS.  Weights of a layer with kernel size KS are kept as bf16
-// copies Wb[k][co] with k = tap * Ci + ci, tap = di * KS + dj, and, for the
-// data gradient, WT[k'][ci] with k' = (KS^2 - 1 - tap) * Co + co (taps
+// copies Wb[co][k] with k = tap * Ci + ci, tap = di * KS + dj, and, for the
+// data gradient, WT[ci][k'] with k' = (KS^2 - 1 - tap) * Co + co (taps
 // flipped, channels swapped): the data gradient of a stride-1 zero-padded
-// correlation is the correlation of the output gradient with WT.
+// correlation is the correlation of the output gradient with WT.  Both are
+// output-channel major (k contiguous), so a weight tile row is one run.
 #include "internal.hpp"
 
 namespace lsop {
@@ -32,6 +33,7 @@ __device__ __forceinline__ unsigned short to_bf16(float x) {
 // column l % 16.
 constexpr int NN_T = 64, NN_K = 32, NN_SK = NN_K + 4;
 
+template <int SK = NN_SK>
 __device__ __forceinline__ void nn_mma_stage(const unsigned short* sA, const unsigned short* sB, int wm, int wn, int l,
                                              nn_f4 (&acc)[2][2]) {
 #pragma unroll
@@ -39,10 +41,10 @@ __device__ __forceinline__ void nn_mma_stage(const unsigned short* sA, const uns
     nn_s4 a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
-      a[i] = *reinterpret_cast<const nn_s4*>(&sA[(wm + i * 16 + (l & 15)) * NN_SK + ks + 4 * (l >> 4)]);
+      a[i] = *reinterpret_cast<const nn_s4*>(&sA[(wm + i * 16 + (l & 15)) * SK + ks + 4 * (l >> 4)]);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-      b[j] = *reinterpret_cast<const nn_s4*>(&sB[(wn + j * 16 + (l & 15)) * NN_SK + ks + 4 * (l >> 4)]);
+      b[j] = *reinterpret_cast<const nn_s4*>(&sB[(wn + j * 16 + (l & 15)) * SK + ks + 4 * (l >> 4)]);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -90,10 +92,86 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const float* __restrict__ X, i
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int k = k0 + bk, n = n0 + bn + q;
-      sB[(bn + q) * NN_SK + bk] = (k < K && n < N) ? Wb[(size_t)k * N + n] : (unsigned short)0;
+      sB[(bn + q) * NN_SK + bk] = (k < K && n < N) ? Wb[(size_t)n * K + k] : (unsigned short)0;
     }
     __syncthreads();
     nn_mma_stage(sA, sB, wm, wn, l, acc);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int p = p0 + wm + i * 16 + 4 * (l >> 4) + r;
+        const int n = n0 + wn + j * 16 + (l & 15);
+        if (p < P && n < N) {
+          float v = acc[i][j][r] + (bias ? bias[n] : 0.f);
+          if (relu) v = fmaxf(v, 0.f);
+          Y[(size_t)p * N + n] = v;
+        }
+      }
+}
+
+// k_conv_fwd for C % 8 == 0 (so K % 8 == 0, and 8 consecutive k share one
+// tap): each thread moves 8 consecutive k of one pixel (two float4 loads, one
+// 16-byte bf16 LDS write; one index division per stage) and 8 consecutive k
+// of one output channel's weights; the next stage is loaded into registers
+// while the current one is multiplied.  X and Wb 16-byte aligned.
+constexpr int NN_SKV = NN_K + 8;  // bf16 per LDS row: 16-byte aligned rows, conflict-free MFMA operand reads
+
+__device__ __forceinline__ unsigned nn_pack2(float lo, float hi) {
+  return (unsigned)to_bf16(lo) | ((unsigned)to_bf16(hi) << 16);
+}
+
+template <int KS>
+__global__ __launch_bounds__(256) void k_conv_fwd_v(const float* __restrict__ X, int C,
+                                                    const unsigned short* __restrict__ Wb, int N,
+                                                    const float* __restrict__ bias, float* __restrict__ Y, int B,
+                                                    int H, int W, int relu) {
+  __shared__ __align__(16) unsigned short sA[NN_T * NN_SKV];
+  __shared__ __align__(16) unsigned short sB[NN_T * NN_SKV];
+  const int P = B * H * W, K = KS * KS * C;
+  const int p0 = blockIdx.x * NN_T, n0 = blockIdx.y * NN_T;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  nn_f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = nn_f4{0.f, 0.f, 0.f, 0.f};
+  const int row = threadIdx.x >> 2, ak = (threadIdx.x & 3) * 8;  // pixel (A) / output channel (B), 8 k
+  const int pix = p0 + row;
+  const bool pin = pix < P;
+  const int pb = pin ? pix / (H * W) : 0, prem = pin ? pix % (H * W) : 0;
+  const int py = prem / W, px = prem % W;
+  const unsigned short* wrow = (n0 + row < N) ? Wb + (size_t)(n0 + row) * K : nullptr;
+  float4 xa, xb;
+  uint4 wv;
+  auto load = [&](int k0) {
+    const int k = k0 + ak;
+    xa = make_float4(0.f, 0.f, 0.f, 0.f);
+    xb = xa;
+    if (pin && k < K) {
+      const int tap = k / C, c = k - tap * C;
+      const int yy = py + tap / KS - KS / 2, xx = px + tap % KS - KS / 2;
+      if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+        const float4* src = reinterpret_cast<const float4*>(X + (((size_t)pb * H + yy) * W + xx) * C + c);
+        xa = src[0];
+        xb = src[1];
+      }
+    }
+    wv = (wrow && k < K) ? *reinterpret_cast<const uint4*>(wrow + k) : make_uint4(0u, 0u, 0u, 0u);
+  };
+  load(0);
+  for (int k0 = 0; k0 < K; k0 += NN_K) {
+    *reinterpret_cast<uint4*>(&sA[row * NN_SKV + ak]) =
+        make_uint4(nn_pack2(xa.x, xa.y), nn_pack2(xa.z, xa.w), nn_pack2(xb.x, xb.y), nn_pack2(xb.z, xb.w));
+    *reinterpret_cast<uint4*>(&sB[row * NN_SKV + ak]) = wv;
+    __syncthreads();
+    if (k0 + NN_K < K) load(k0 + NN_K);
+    nn_mma_stage<NN_SKV>(sA, sB, wm, wn, l, acc);
     __syncthreads();
   }
 #pragma unroll
@@ -149,6 +227,79 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const float* __restrict__ X,
       sB[lr * NN_SK + lp + q] = to_bf16(vb);
     }
     __syncthreads();
+    nn_mma_stage(sA, sB, wm, wn, l, acc);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = k0 + wm + i * 16 + 4 * (l >> 4) + r;
+        const int n = n0 + wn + j * 16 + (l & 15);
+        if (k < K && n < N) atomicAdd(&dW[(size_t)k * N + n], acc[i][j][r]);
+      }
+}
+
+// k_conv_wgrad for C % 8 == 0 and N % 8 == 0: each thread loads, per
+// 32-pixel stage, 8 consecutive k (one tap, 8 channels) and 8 consecutive n of
+// one pixel as float4 pairs (one index division per stage) and scatters them
+// into the pixel-contiguous LDS rows; the next stage is loaded into registers
+// while the current one is multiplied.  X and dY 16-byte aligned.
+template <int KS>
+__global__ __launch_bounds__(256) void k_conv_wgrad_v(const float* __restrict__ X, int C,
+                                                      const float* __restrict__ dY, int N, float* __restrict__ dW,
+                                                      int B, int H, int W, int pchunk) {
+  __shared__ unsigned short sA[NN_T * NN_SK];  // [k row][pixel]
+  __shared__ unsigned short sB[NN_T * NN_SK];  // [n][pixel]
+  const int P = B * H * W, K = KS * KS * C;
+  const int k0 = blockIdx.x * NN_T, n0 = blockIdx.y * NN_T;
+  const int pbeg = blockIdx.z * pchunk, pend = min(P, pbeg + pchunk);
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  nn_f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = nn_f4{0.f, 0.f, 0.f, 0.f};
+  const int q = threadIdx.x >> 3, c8 = (threadIdx.x & 7) * 8;  // pixel of the stage, 8 consecutive k / n
+  const int kr = k0 + c8, nr = n0 + c8;
+  const bool kin = kr < K, nin = nr < N;
+  const int tap = kin ? kr / C : 0, cc = kin ? kr - tap * C : 0;
+  const int dy = tap / KS - KS / 2, dx = tap % KS - KS / 2;
+  float4 xa, xb, ga, gb;
+  auto load = [&](int q0) {
+    const int p = q0 + q;
+    xa = make_float4(0.f, 0.f, 0.f, 0.f);
+    xb = xa;
+    ga = xa;
+    gb = xa;
+    if (p < pend) {
+      const int b = p / (H * W), rem = p % (H * W), y = rem / W + dy, x = rem % W + dx;
+      if (kin && y >= 0 && y < H && x >= 0 && x < W) {
+        const float4* src = reinterpret_cast<const float4*>(X + (((size_t)b * H + y) * W + x) * C + cc);
+        xa = src[0];
+        xb = src[1];
+      }
+      if (nin) {
+        const float4* g = reinterpret_cast<const float4*>(dY + (size_t)p * N + nr);
+        ga = g[0];
+        gb = g[1];
+      }
+    }
+  };
+  load(pbeg);
+  for (int q0 = pbeg; q0 < pend; q0 += NN_K) {
+    const float xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+    const float gv[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      sA[(c8 + j) * NN_SK + q] = to_bf16(xv[j]);
+      sB[(c8 + j) * NN_SK + q] = to_bf16(gv[j]);
+    }
+    __syncthreads();
+    if (q0 + NN_K < pend) load(q0 + NN_K);
     nn_mma_stage(sA, sB, wm, wn, l, acc);
     __syncthreads();
   }
@@ -318,8 +469,8 @@ __global__ void k_weights_bf16(const float* __restrict__ Wf, int KS, int Ci, int
     const size_t row = k / Co;
     const int ci = (int)(row % Ci), tap = (int)(row / Ci);
     const unsigned short h = to_bf16(Wf[k]);
-    Wb[k] = h;
-    WT[((size_t)(taps - 1 - tap) * Co + co) * Ci + ci] = h;
+    Wb[(size_t)co * taps * Ci + row] = h;                                          // [co][tap Ci + ci]
+    WT[(size_t)ci * taps * Co + (size_t)(taps - 1 - tap) * Co + co] = h;          // [ci][flipped tap Co + co]
   }
 }
 
@@ -387,7 +538,12 @@ hipError_t launch_conv_fwd(int ks, const float* X, int C, const unsigned short* 
   const int P = B * H * W;
   if (P <= 0 || N <= 0) return hipSuccess;
   const dim3 grid((P + NN_T - 1) / NN_T, (N + NN_T - 1) / NN_T);
-  if (ks == 3)
+  const bool vec = C % 8 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)Wb % 16) == 0;
+  if (vec && ks == 3)
+    hipLaunchKernelGGL(k_conv_fwd_v<3>, grid, dim3(256), 0, s, X, C, Wb, N, bias, Y, B, H, W, (int)relu);
+  else if (vec && ks == 1)
+    hipLaunchKernelGGL(k_conv_fwd_v<1>, grid, dim3(256), 0, s, X, C, Wb, N, bias, Y, B, H, W, (int)relu);
+  else if (ks == 3)
     hipLaunchKernelGGL(k_conv_fwd<3>, grid, dim3(256), 0, s, X, C, Wb, N, bias, Y, B, H, W, (int)relu);
   else if (ks == 1)
     hipLaunchKernelGGL(k_conv_fwd<1>, grid, dim3(256), 0, s, X, C, Wb, N, bias, Y, B, H, W, (int)relu);
@@ -407,7 +563,12 @@ hipError_t launch_conv_wgrad(int ks, const float* X, int C, const float* dY, int
   pchunk = (pchunk + NN_K - 1) / NN_K * NN_K;
   nz = (P + pchunk - 1) / pchunk;
   const dim3 grid((K + NN_T - 1) / NN_T, (N + NN_T - 1) / NN_T, nz);
-  if (ks == 3)
+  const bool vec = C % 8 == 0 && N % 8 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)dY % 16) == 0;
+  if (vec && ks == 3)
+    hipLaunchKernelGGL(k_conv_wgrad_v<3>, grid, dim3(256), 0, s, X, C, dY, N, dW, B, H, W, pchunk);
+  else if (vec && ks == 1)
+    hipLaunchKernelGGL(k_conv_wgrad_v<1>, grid, dim3(256), 0, s, X, C, dY, N, dW, B, H, W, pchunk);
+  else if (ks == 3)
     hipLaunchKernelGGL(k_conv_wgrad<3>, grid, dim3(256), 0, s, X, C, dY, N, dW, B, H, W, pchunk);
   else if (ks == 1)
     hipLaunchKernelGGL(k_conv_wgrad<1>, grid, dim3(256), 0, s, X, C, dY, N, dW, B, H, W, pchunk);

@@ -100,7 +100,10 @@ int refresh_weights(unet* u, hipStream_t s) {
 int conv_launch(const char* use, int ks, const float* X, int ci, const unsigned short* w, int co, const float* bias,
                 float* Y, int B, int H, int W, bool relu, hipStream_t s) {
   const double P = (double)B * H * W, K = (double)ks * ks * ci;
-  LSOP_HIP(prof_launch(use, ks == 3 ? "k_conv_fwd<3>" : "k_conv_fwd<1>", P * ci * 4.0 + K * co * 2.0 + P * co * 4.0, 2.0 * P * K * co, P, s,
+  // the launcher takes the vector kernel when channels come in eights and both operands are 16-byte aligned
+  const bool vec = ci % 8 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)w % 16) == 0;
+  const char* fn = vec ? (ks == 3 ? "k_conv_fwd_v<3>" : "k_conv_fwd_v<1>") : (ks == 3 ? "k_conv_fwd<3>" : "k_conv_fwd<1>");
+  LSOP_HIP(prof_launch(use, fn, P * ci * 4.0 + K * co * 2.0 + P * co * 4.0, 2.0 * P * K * co, P, s,
                        [&] { return launch_conv_fwd(ks, X, ci, w, co, bias, Y, B, H, W, relu, s); }));
   return LSOP_OK;
 }
@@ -156,7 +159,10 @@ int layer_back(unet* u, const unet::Layer& L, float* dY, const float* X, const f
     LSOP_HIP(prof_launch("unet relu backward", "k_relu_bwd", P * L.co * 12.0, P * L.co, P * L.co, s,
                          [&] { return launch_relu_bwd(dY, Yout, (size_t)B * H * W * L.co, s); }));
   float* gw = u->G + L.poff;
-  LSOP_HIP(prof_launch("unet weight gradient", L.ks == 3 ? "k_conv_wgrad<3>" : "k_conv_wgrad<1>",
+  const bool vec = L.ci % 8 == 0 && L.co % 8 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)dY % 16) == 0;
+  const char* wfn = vec ? (L.ks == 3 ? "k_conv_wgrad_v<3>" : "k_conv_wgrad_v<1>")
+                        : (L.ks == 3 ? "k_conv_wgrad<3>" : "k_conv_wgrad<1>");
+  LSOP_HIP(prof_launch("unet weight gradient", wfn,
                        P * L.ci * 4.0 + P * L.co * 4.0 + K * L.co * 4.0, 2.0 * P * K * L.co, P, s,
                        [&] { return launch_conv_wgrad(L.ks, X, L.ci, dY, L.co, gw, B, H, W, s); }));
   LSOP_HIP(prof_launch("unet bias gradient", L.co <= 256 ? "k_colsum_flat" : "k_colsum", P * L.co * 4.0, P * L.co, P, s,
