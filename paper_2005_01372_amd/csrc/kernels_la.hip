@@ -518,6 +518,8 @@ __device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, size_t ldm,
   double scale;
   int dummy;
   block_argmax(amax, 0, red, redi, &scale, &dummy);
+  // elimination layout: thread t owns column uj = t % w2 of rows ui0, ui0 + urs, ... (no division in the loop)
+  const int urs = (int)blockDim.x / w2, uj = t % w2, ui0 = t / w2;
   for (int k = 0; k < na; ++k) {
     double bv = -1.0;
     int bi = k;
@@ -550,9 +552,11 @@ __device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, size_t ldm,
     for (int j = t; j < w2; j += blockDim.x) work[(size_t)k * wld + j] = work[(size_t)k * wld + j] * inv;
     for (int i = t; i < na; i += blockDim.x) fcol[i] = work[(size_t)i * wld + k];
     __syncthreads();
-    for (int idx = t; idx < na * w2; idx += blockDim.x) {
-      const int i = idx / w2, j = idx % w2;
-      if (i != k) work[(size_t)i * wld + j] = work[(size_t)i * wld + j] - fcol[i] * work[(size_t)k * wld + j];
+    // rank-1 elimination; left-block columns before k are zero in the pivot row and are skipped
+    if (ui0 < urs && (uj >= na || uj >= k)) {
+      const Cx<double> pr = work[(size_t)k * wld + uj];
+      for (int i = ui0; i < na; i += urs)
+        if (i != k) work[(size_t)i * wld + uj] = work[(size_t)i * wld + uj] - fcol[i] * pr;
     }
     __syncthreads();
   }
