@@ -172,6 +172,17 @@ int precond_create(lsop_op* op, const lsop_precond_params* params, lsop_precond*
  * leaf block or a node's Woodbury core is singular. */
 int precond_build(lsop_precond* pc, const void* omega_dev, void* stream);
 
+/* Builds `count` preconditioners (Philox probes, as precond_build with
+ * omega_dev = NULL) concurrently: `streams` (1..16) host threads, each with a
+ * non-blocking stream of its own, take the preconditioners one at a time,
+ * largest grid first.  Independent builds of small grids leave most of the
+ * device idle alone (the instances of an uneven batch, Section 3.1.2's many
+ * media); running several at once fills it.  The preconditioners must belong
+ * to distinct operators (EINVAL otherwise: an operator's scratch is shared by
+ * its builds).  Synchronises the device before and all its streams after;
+ * returns the first failure of any build (the others still complete). */
+int precond_build_batch(lsop_precond* const* pcs, int count, int streams);
+
 /* y = H x for nvec vectors (x, y in the inner dtype of the op). */
 int precond_apply(lsop_precond* pc, const void* x_dev, void* y_dev, int nvec, void* stream);
 

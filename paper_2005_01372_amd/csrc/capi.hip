@@ -1,10 +1,13 @@
 // C ABI of liblsop.so: operator, preconditioner and series solver handles.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "bessel.hpp"
@@ -33,6 +36,7 @@ struct ProfRec {
 bool g_prof = false;
 std::vector<ProfRec> g_recs;
 std::vector<hipEvent_t> g_pool;
+std::mutex g_prof_mu;  // guards g_recs and g_pool: builds may run on several host threads
 
 hipEvent_t ev_get() {
   if (!g_pool.empty()) {
@@ -53,11 +57,17 @@ template <typename F>
 hipError_t prof(const char* name, const std::string& fn, double bytes, double flops, double items, hipStream_t s,
                 F&& launch) {
   if (!g_prof) return launch();
-  ProfRec r{name, "", ev_get(), ev_get(), bytes, flops, items};
+  ProfRec r{name, "", nullptr, nullptr, bytes, flops, items};
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    r.a = ev_get();
+    r.b = ev_get();
+  }
   (void)hipEventRecord(r.a, s);
   hipError_t e = launch();
   (void)hipEventRecord(r.b, s);
   r.fn = fn;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   g_recs.push_back(r);
   return e;
 }
@@ -701,20 +711,23 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
   lsop_op* op = pc->op;
   const int r = pc->rank;
   const size_t n = op->n();
-  // build-only workspace: sampling buffers and the FP64 leaf workspace, released on return
+  // build-only workspace: sampling buffers and the FP64 leaf workspace, taken from and returned to the
+  // stream-ordered pool of stream s (no device-wide synchronisation, so builds on other streams keep running)
   struct Transient {
     lsop_precond* pc;
+    hipStream_t s;
     ~Transient() {
-      (void)hipDeviceSynchronize();
       for (void** p : {&pc->U, &pc->Y, reinterpret_cast<void**>(&pc->lwork)})
         if (*p) {
-          (void)hipFree(*p);
+          (void)hipFreeAsync(*p, s);
           *p = nullptr;
         }
+      (void)hipStreamSynchronize(s);
     }
-  } transient{pc};
-  if (hipMalloc(&pc->U, sizeof(Cx<T>) * r * n) != hipSuccess || hipMalloc(&pc->Y, sizeof(Cx<T>) * r * n) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&pc->lwork), sizeof(Cx<double>) * pc->lwork_elems) != hipSuccess) {
+  } transient{pc, s};
+  if (hipMallocAsync(&pc->U, sizeof(Cx<T>) * r * n, s) != hipSuccess ||
+      hipMallocAsync(&pc->Y, sizeof(Cx<T>) * r * n, s) != hipSuccess ||
+      hipMallocAsync(reinterpret_cast<void**>(&pc->lwork), sizeof(Cx<double>) * pc->lwork_elems, s) != hipSuccess) {
     (void)hipGetLastError();
     return fail(LSOP_ENOMEM, "HODLR build workspace allocation failed");
   }
@@ -1515,6 +1528,49 @@ int precond_build(lsop_precond* pc, const void* omega_dev, void* stream) {
   return build_impl<float>(pc, (const double*)omega_dev, S(stream));
 }
 
+int precond_build_batch(lsop_precond* const* pcs, int count, int streams) {
+  if (count < 0 || (count > 0 && !pcs)) return fail(LSOP_EINVAL, "bad preconditioner list");
+  if (streams < 1 || streams > 16) return fail(LSOP_EINVAL, "streams must be in 1..16");
+  std::vector<int> order;
+  for (int i = 0; i < count; ++i) {
+    if (!pcs[i]) return fail(LSOP_EINVAL, "null preconditioner in the list");
+    for (int j = 0; j < i; ++j)
+      if (pcs[j]->op == pcs[i]->op) return fail(LSOP_EINVAL, "two preconditioners of one operator in one batch build");
+    order.push_back(i);
+  }
+  // largest grids first, handed out one at a time to the workers (longest-processing-time order)
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pcs[a]->op->n() > pcs[b]->op->n(); });
+  LSOP_HIP(hipDeviceSynchronize());
+  const int nw = std::max(1, std::min(streams, count));
+  std::atomic<int> next{0};
+  std::vector<int> status(nw, LSOP_OK);
+  std::vector<std::string> msg(nw);
+  auto worker = [&](int w) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      status[w] = LSOP_EHIP;
+      msg[w] = "stream creation failed";
+      return;
+    }
+    for (int k; (k = next.fetch_add(1)) < count;) {
+      const int r = precond_build(pcs[order[k]], nullptr, st);
+      if (r != LSOP_OK && status[w] == LSOP_OK) {
+        status[w] = r;
+        msg[w] = lsop_last_error();
+      }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nw; ++w) pool.emplace_back(worker, w);
+  worker(0);
+  for (auto& t : pool) t.join();
+  for (int w = 0; w < nw; ++w)
+    if (status[w] != LSOP_OK) return fail(status[w], msg[w]);
+  return LSOP_OK;
+}
+
 int precond_apply(lsop_precond* pc, const void* x_dev, void* y_dev, int nvec, void* stream) {
   if (!pc) return fail(LSOP_EINVAL, "null preconditioner");
   if (!pc->built) return fail(LSOP_EINVAL, "preconditioner not built");
@@ -1781,6 +1837,7 @@ int lsop_profile_enable(int on) {
 
 int lsop_profile_reset(void) {
   (void)hipDeviceSynchronize();
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   for (auto& r : g_recs) {
     g_pool.push_back(r.a);
     g_pool.push_back(r.b);
@@ -1792,6 +1849,7 @@ int lsop_profile_reset(void) {
 static int profile_read_by(bool by_fn, lsop_kernel_stat* stats, int max_stats, int* count) {
   if (!count || (max_stats > 0 && !stats)) return fail(LSOP_EINVAL, "null argument");
   LSOP_HIP(hipDeviceSynchronize());
+  std::lock_guard<std::mutex> lk(g_prof_mu);
   std::vector<lsop_kernel_stat> agg;
   for (const auto& r : g_recs) {
     float ms = 0.f;

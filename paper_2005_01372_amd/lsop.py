@@ -28,7 +28,7 @@ INIT = {"h_rhs": 0, "zero": 1, "user": 2, "best": 3}
 
 EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident", "lsop_autotune",
            "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "precond_create",
-           "precond_build", "precond_apply", "precond_info", "precond_destroy", "series_solve",
+           "precond_build", "precond_build_batch", "precond_apply", "precond_info", "precond_destroy", "series_solve",
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
            "lsop_profile_read_kernels", "lsop_batch_create", "lsop_batch_apply", "lsop_batch_autotune",
            "lsop_batch_solve", "lsop_batch_info", "lsop_batch_destroy", "unet_create", "unet_param_count",
@@ -92,6 +92,7 @@ def load_library(path=LIB_PATH):
         "lsop_last_error": (C.c_char_p, []),
         "precond_create": (ip, [vp, C.POINTER(PrecondParams), C.POINTER(vp)]),
         "precond_build": (ip, [vp, vp, vp]),
+        "precond_build_batch": (ip, [vp, C.c_int, C.c_int]),
         "precond_apply": (ip, [vp, vp, vp, ip, vp]),
         "precond_info": (ip, [vp, C.POINTER(ip), C.POINTER(dp), C.POINTER(C.c_size_t)]),
         "precond_destroy": (None, [vp]),
@@ -330,6 +331,13 @@ def series_solve(op, pc, rhs, psi=None, tol=1e-10, max_iter=30, init="h_rhs", re
                              C.byref(p), info, _stream())
     _check(st, allow=() if raise_on_failure else (NOT_CONVERGED, DIVERGED))
     return psi, [SolveResult(i.iters, i.refine_steps, i.rel_residual, i.status, i.rel_residual0) for i in info]
+
+
+def build_batch(pcs, streams=4):
+    """Builds several preconditioners (distinct operators) concurrently on `streams` device streams."""
+    pcs = list(pcs)
+    arr = (C.c_void_p * max(1, len(pcs)))(*[pc.handle for pc in pcs])
+    return _check(load_library().precond_build_batch(arr, len(pcs), int(streams)))
 
 
 class Batch:

@@ -158,3 +158,28 @@ def test_batch_output_buffers_contents_are_ignored():
     for t in range(3):
         assert all(r.status == lsop.OK for r in res[t])
         assert not torch.isnan(psis[t]).any()
+
+
+def test_concurrent_builds_match_one_by_one_builds():
+    """precond_build_batch on three streams builds the same preconditioners as one-by-one builds with the same
+    probe seeds: H x agrees to FP32 rounding for instances of several sizes; a list holding two preconditioners
+    of one operator is rejected."""
+    announce("concurrent HODLR builds, 5 instances, 3 streams")
+    cases = [(64, 8.0), (96, 10.0), (128, 12.0), (64, 15.0), (128, 6.0)]
+    seq, conc, xs = [], [], []
+    for i, (n, f) in enumerate(cases):
+        w = synth.model_smooth_inclusion(n=n, freq=f, seed=30 + i)
+        op = make_op(w, lsop.C64, max_vec=4)
+        kw = dict(rank=32, levels=2, power_iters=1, seed=7 + i)
+        seq.append(lsop.Preconditioner(op, lsop.PC_HODLR, **kw))
+        op2 = make_op(w, lsop.C64, max_vec=4)
+        conc.append(lsop.Preconditioner(op2, lsop.PC_HODLR, **kw))
+        xs.append(dev(synth.random_vectors((3, n, n), seed=50 + i), torch.complex64))
+    for pc in seq:
+        pc.build()
+    lsop.build_batch(conc, streams=3)
+    for a, b, x in zip(seq, conc, xs):
+        ya, yb = host(a.apply(x)), host(b.apply(x))
+        assert rel(yb, ya) <= 1e-5
+    with pytest.raises(lsop.LsopError):
+        lsop.build_batch([seq[0], seq[0]], streams=2)
