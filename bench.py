@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--unet-models", type=int, default=32,
                     help="layered + salt models (32 sources each) solved for the network's training data")
     ap.add_argument("--unet-batch", type=int, default=16)
+    ap.add_argument("--unet-no-eval", action="store_true",
+                    help="skip the warm-started series after the timed training steps (counter runs: the timed "
+                         "launches are then each kernel's last dispatches)")
     ap.add_argument("--count", type=int, default=64, help="instances of the uneven batch")
     ap.add_argument("--build-streams", type=int, default=8,
                     help="uneven batch: preconditioner builds run concurrently on this many device streams")
@@ -70,10 +73,10 @@ def parse():
     return a
 
 
-def load_traffic(kernel):
+def load_traffic(kernel, summary="pmc_traffic.json"):
     """Counter-measured HBM bytes over algorithmic bytes for one kernel function, from the committed
     summary, if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -324,6 +327,11 @@ def main_unet(args):
     from paper_2005_01372_amd import lsop, synth
 
     torch.cuda.init()
+    if args.copy_probe:
+        a = torch.ones(1 << 27, dtype=torch.complex64, device="cuda")   # 1 GiB
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+        del a
     n, nsrc, bs = 128, 32, args.unet_batch
     net = lsop.UNet(4, 32, 4, 2, max_batch=max(bs, nsrc, 16), max_h=512, max_w=512)
     net.init_params(seed=0)
@@ -371,14 +379,17 @@ def main_unet(args):
     lsop.profile_reset()
     step_s = (t1 - t0) / args.steps
     print(f"[bench] {args.steps} timed training steps done", file=sys.stderr, flush=True)
+    if args.dump_profile:
+        with open(args.dump_profile, "w") as f:
+            json.dump({"steps": args.steps, "warmup": args.warmup, "kernels": by_fn}, f, indent=1)
     dom = max(by_fn, key=lambda k: by_fn[k]["ms"])
     roof = roofline_for(dom, by_fn[dom])
-    ratio = load_traffic(dom)
+    ratio = load_traffic(dom, "pmc_traffic_unet.json")
     roof["traffic"] = None if ratio is None else round(ratio * roof["algorithmic_bytes_per_launch"])
     conv_flops = sum(v["flops"] for k, v in by_fn.items() if k.startswith("k_conv"))
     # warm start inside the series at 256^2 and 512^2 (16 sources each)
     evals = []
-    for m, (side, rank, lv) in enumerate(((256, 96, 6), (512, 160, 7))):
+    for m, (side, rank, lv) in enumerate(() if args.unet_no_eval else ((256, 96, 6), (512, 160, 7))):
         w = synth.model_layered_salt(n=side, h=10.0, freq=15.0, seed=77 + m, nsrc=16)
         op = lsop.Operator(side, side, lsop.C64, max_vec=16)
         op.set_problem(torch.as_tensor(w.vel, device="cuda"), w.h, w.freq, w.c0)

@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("kernels_fft.hip", "kernels_la.hip", "fft_engine.hpp"):
+    for f in ("kernels_fft.hip", "kernels_la.hip", "fft_engine.hpp", "kernels_nn.hip"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
