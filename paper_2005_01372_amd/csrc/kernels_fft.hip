@@ -135,15 +135,21 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
 // that group's interleaved even/odd FFT pair, xbuf as the other.
 template <typename T, int L>
 struct ColTile {
-  // widest tile that keeps 128-byte row segments and fits the LDS and thread budgets
+  // widest tile that keeps 128-byte row segments and fits the LDS and thread budgets; transforms done by a
+  // single lane (lengths 2-8: the x-transforms of narrow sub-domains) take 256-column tiles, so that
+  // workgroups are not mostly empty and their number does not swamp the dispatcher (measured: wider tiles for
+  // the multi-lane lengths 16-64 were slightly slower)
   static constexpr int stride = lds_len<L>() + 1;
   static constexpr int lds_cap =
       (156 * 1024 - lds_len<L>() * (int)sizeof(Cx<T>)) / ((stride + lds_len<L>()) * (int)sizeof(Cx<T>));
-  static constexpr int want = 128 / (int)sizeof(Cx<T>);
+  static constexpr int line = 128 / (int)sizeof(Cx<T>);
+  static constexpr int wide = FftPlan<L>::G == 1 ? 256 : 1;
+  static constexpr int want = line > wide ? line : wide;
   static constexpr int c0 = want < lds_cap ? want : lds_cap;
   static constexpr int thr_cap = 1024 / FftPlan<L>::G;
   static constexpr int c1 = c0 < thr_cap ? c0 : thr_cap;
-  static constexpr int C = c1 >= 16 ? 16 : c1 >= 8 ? 8 : c1 >= 4 ? 4 : c1 >= 2 ? 2 : 1;
+  static constexpr int C = c1 >= 256 ? 256 : c1 >= 128 ? 128 : c1 >= 64 ? 64 : c1 >= 32 ? 32 : c1 >= 16 ? 16
+                         : c1 >= 8   ? 8   : c1 >= 4   ? 4   : c1 >= 2  ? 2  : 1;
 };
 
 // blockIdx -> logical id so that consecutive logical ids run on the same XCD
@@ -480,14 +486,33 @@ hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int n
   LSOP_DISPATCH_LX(L, {
     constexpr int CMAX = ColTile<T, LL>::C;
     int C = (tile > 0 && tile < CMAX) ? tile : CMAX;
-    if (C >= 16 && CMAX >= 16) C = 16;
-    else if (C >= 8 && CMAX >= 8) C = 8;
-    else if (C >= 4 && CMAX >= 4) C = 4;
-    else C = CMAX < 2 ? CMAX : 2;
+    C = C >= 256 ? 256 : C >= 128 ? 128 : C >= 64 ? 64 : C >= 32 ? 32 : C >= 16 ? 16 : C >= 8 ? 8 : C >= 4 ? 4
+      : (CMAX < 2 ? CMAX : 2);
+    while (C > 16 && pz % C != 0) C /= 2;  // tiles must divide the row (pz % 16 == 0)
     if (used) *used = C;
     const int ntiles = pz / C;
     const dim3 grid(ntiles * nslots);
     switch (C) {
+      case 256:
+        if constexpr (CMAX >= 256)
+          hipLaunchKernelGGL((k_cols<T, LL, 256>), grid, dim3(256 * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz, nslots,
+                             (int)adj, tw2, tab);
+        break;
+      case 128:
+        if constexpr (CMAX >= 128)
+          hipLaunchKernelGGL((k_cols<T, LL, 128>), grid, dim3(128 * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz, nslots,
+                             (int)adj, tw2, tab);
+        break;
+      case 64:
+        if constexpr (CMAX >= 64)
+          hipLaunchKernelGGL((k_cols<T, LL, 64>), grid, dim3(64 * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz, nslots,
+                             (int)adj, tw2, tab);
+        break;
+      case 32:
+        if constexpr (CMAX >= 32)
+          hipLaunchKernelGGL((k_cols<T, LL, 32>), grid, dim3(32 * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz, nslots,
+                             (int)adj, tw2, tab);
+        break;
       case 16:
         if constexpr (CMAX >= 16)
           hipLaunchKernelGGL((k_cols<T, LL, 16>), grid, dim3(16 * FftPlan<LL>::G), 0, s, tmp, gs, nx, pz, nslots,
