@@ -312,10 +312,14 @@ int check_op(const lsop_op* op) {
 // dependent) when its remaining norm falls below a fixed fraction of its norm
 // before any projection.  G, X, R: FP64 scratch of nseg * r * 64 entries each;
 // kept[(block) * nseg + sg] receives the kept column counts of the final pass.
+// full = false (an intermediate basis of the power iteration, whose only use is
+// the next sample: its span matters, not how orthonormal it is) projects once
+// and runs Cholesky-QR once.
 template <typename T>
 int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int ksub, Cx<double>* G, Cx<double>* X,
-                Cx<double>* R, Cx<double>* part, size_t part_cap, int* kept, hipStream_t s) {
+                Cx<double>* R, Cx<double>* part, size_t part_cap, int* kept, hipStream_t s, bool full = true) {
   constexpr int B = 64;
+  const int passes = full ? 2 : 1;
   const double tol = std::is_same<T, float>::value ? 1e-9 : 1e-24;
   const double e = sizeof(Cx<T>);
   for (int c0 = 0; c0 < r; c0 += B) {
@@ -325,11 +329,11 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
     if (c0 > 0) {  // reference Gram of the block before projection
       LSOP_HIP(p_ah_b<T>("orth_gram", Yb, kb, Yb, nullptr, kb, n, seg, R, part, ksub, s, 1.0, part_cap));
     }
-    for (int pass = 0; pass < 2 && c0 > 0; ++pass) {
+    for (int pass = 0; pass < passes && c0 > 0; ++pass) {
       LSOP_HIP(p_ah_b<T>("orth_project", Q, c0, Yb, nullptr, kb, n, seg, G, part, ksub, s, -1.0, part_cap));
       LSOP_HIP(p_update<T>("orth_project", Q, c0, G, (size_t)c0 * kb, kb, Yb, nullptr, 0.0, Yb, nullptr, n, seg, s));
     }
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < passes; ++pass) {
       const Cx<T>* src = pass == 0 ? Yb : Qb;
       Cx<T>* dst = pass == 0 ? Qb : Yb;
       LSOP_HIP(p_ah_b<T>("orth_gram", src, kb, src, nullptr, kb, n, seg, G, part, ksub, s, 1.0, part_cap));
@@ -341,7 +345,7 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
       LSOP_HIP(p_update<T>("orth_update", src, kb, X, (size_t)kb * kb, kb, nullptr, nullptr, 0.0, dst, nullptr, n, seg,
                            s));
     }
-    LSOP_HIP(hipMemcpyAsync(Qb, Yb, sizeof(Cx<T>) * (size_t)kb * n, hipMemcpyDeviceToDevice, s));
+    if (passes == 2) LSOP_HIP(hipMemcpyAsync(Qb, Yb, sizeof(Cx<T>) * (size_t)kb * n, hipMemcpyDeviceToDevice, s));
   }
   return LSOP_OK;
 }
@@ -526,11 +530,11 @@ int hodlr_subconv(lsop_precond* pc, int lv, bool adj, const Cx<T>* x, Cx<T>* y, 
 
 // Orthonormal bases, separately on every half-node segment of level lv.
 template <typename T>
-int hodlr_orth(lsop_precond* pc, int lv, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s) {
+int hodlr_orth(lsop_precond* pc, int lv, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s, bool full) {
   const int W = pc->lev[lv].width, nseg = 2 * (pc->op->nx / W);
   const size_t seg = (size_t)(W / 2) * pc->op->nz;
   return orth_blocks<T>(Yin, Qout, pc->rank, pc->op->n(), seg, nseg, hodlr_ksub(pc, seg, nseg), pc->hG, pc->hX,
-                        pc->hK, pc->part, pc->part_cap, pc->hflag, s);
+                        pc->hK, pc->part, pc->part_cap, pc->hflag, s, full);
 }
 
 // In-place inverse of the m x m block at offset o of each of cnt FP64
@@ -757,16 +761,17 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
     // on the I1 cells and G0 V[I2, I1] Om on the I2 cells
     if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 1, 0, s))) return st;
     if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 0, 1, s))) return st;
-    // step 3: orthonormal bases per half-node (result in Y)
-    if ((st = hodlr_orth<T>(pc, lv, Q, Y, s))) return st;
+    // step 3: orthonormal bases per half-node (result in Y); with power iterations this basis is an
+    // intermediate one (one projection and one Cholesky-QR pass), the last one is orthonormalised in full
+    if ((st = hodlr_orth<T>(pc, lv, Q, Y, s, pc->q == 0))) return st;
     // optional power iterations (Alg. 1 step 4) on both blocks of every node
     for (int j = 0; j < pc->q; ++j) {
       if ((st = hodlr_subconv<T>(pc, lv, true, Y, Q, r, 0, 1, s))) return st;
       if ((st = hodlr_subconv<T>(pc, lv, true, Y, Q, r, 1, 0, s))) return st;
-      if ((st = hodlr_orth<T>(pc, lv, Q, Y, s))) return st;
+      if ((st = hodlr_orth<T>(pc, lv, Q, Y, s, false))) return st;
       if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 1, 0, s))) return st;
       if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 0, 1, s))) return st;
-      if ((st = hodlr_orth<T>(pc, lv, Q, Y, s))) return st;
+      if ((st = hodlr_orth<T>(pc, lv, Q, Y, s, j == pc->q - 1))) return st;
     }
     // right factors v12 = (G0 V[I1, I2])^H Q12 on I2, v21 on I1
     if ((st = hodlr_subconv<T>(pc, lv, true, Y, V, r, 0, 1, s))) return st;
