@@ -528,13 +528,55 @@ int hodlr_subconv(lsop_precond* pc, int lv, bool adj, const Cx<T>* x, Cx<T>* y, 
   return LSOP_OK;
 }
 
+// FP64 workspace of one orthonormalisation (orth_blocks): G, X, R, the split-K partials and the kept counts.
+struct OrthScratch {
+  Cx<double>*G, *X, *R, *part;
+  size_t part_cap;
+  int* kept;
+};
+
 // Orthonormal bases, separately on every half-node segment of level lv.
 template <typename T>
-int hodlr_orth(lsop_precond* pc, int lv, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s, bool full) {
+int hodlr_orth(lsop_precond* pc, int lv, Cx<T>* Yin, Cx<T>* Qout, const OrthScratch& sc, hipStream_t s, bool full) {
   const int W = pc->lev[lv].width, nseg = 2 * (pc->op->nx / W);
   const size_t seg = (size_t)(W / 2) * pc->op->nz;
-  return orth_blocks<T>(Yin, Qout, pc->rank, pc->op->n(), seg, nseg, hodlr_ksub(pc, seg, nseg), pc->hG, pc->hX,
-                        pc->hK, pc->part, pc->part_cap, pc->hflag, s, full);
+  return orth_blocks<T>(Yin, Qout, pc->rank, pc->op->n(), seg, nseg, hodlr_ksub(pc, seg, nseg), sc.G, sc.X, sc.R,
+                        sc.part, sc.part_cap, sc.kept, s, full);
+}
+
+// Sampling of level lv (Alg. 1 on both off-diagonal blocks of every node, q power iterations): the
+// orthonormal bases U, returned in Y, and the right factors V (lev[lv].V).  Q and sc are workspace; the FFT
+// passes use the operator's intermediate.
+template <typename T>
+int hodlr_sample(lsop_precond* pc, int lv, const double* omega, Cx<T>* Y, Cx<T>* Q, const OrthScratch& sc,
+                 hipStream_t s) {
+  const int r = pc->rank;
+  const size_t n = pc->op->n();
+  Cx<T>* V = reinterpret_cast<Cx<T>*>(pc->lev[lv].V);
+  int st;
+  // Alg. 1 step 1: Gaussian probes of this level
+  if (omega) LSOP_HIP(launch_real_to_complex<T>(omega + (size_t)lv * r * n, Y, (size_t)r * n, s));
+  else LSOP_HIP(launch_philox_normal<T>(Y, r, n, pc->seed, s, lv * r));
+  // step 2: samples of both off-diagonal blocks of every node, G0 V[I1, I2] Om
+  // on the I1 cells and G0 V[I2, I1] Om on the I2 cells
+  if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 1, 0, s))) return st;
+  if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 0, 1, s))) return st;
+  // step 3: orthonormal bases per half-node (result in Y); with power iterations this basis is an
+  // intermediate one (one projection and one Cholesky-QR pass), the last one is orthonormalised in full
+  if ((st = hodlr_orth<T>(pc, lv, Q, Y, sc, s, pc->q == 0))) return st;
+  // optional power iterations (Alg. 1 step 4) on both blocks of every node
+  for (int j = 0; j < pc->q; ++j) {
+    if ((st = hodlr_subconv<T>(pc, lv, true, Y, Q, r, 0, 1, s))) return st;
+    if ((st = hodlr_subconv<T>(pc, lv, true, Y, Q, r, 1, 0, s))) return st;
+    if ((st = hodlr_orth<T>(pc, lv, Q, Y, sc, s, false))) return st;
+    if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 1, 0, s))) return st;
+    if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 0, 1, s))) return st;
+    if ((st = hodlr_orth<T>(pc, lv, Q, Y, sc, s, j == pc->q - 1))) return st;
+  }
+  // right factors v12 = (G0 V[I1, I2])^H Q12 on I2, v21 on I1
+  if ((st = hodlr_subconv<T>(pc, lv, true, Y, V, r, 0, 1, s))) return st;
+  if ((st = hodlr_subconv<T>(pc, lv, true, Y, V, r, 1, 0, s))) return st;
+  return LSOP_OK;
 }
 
 // In-place inverse of the m x m block at offset o of each of cnt FP64
@@ -710,6 +752,10 @@ int hodlr_core_inverse(lsop_precond* pc, int lv, hipStream_t s) {
   return LSOP_OK;
 }
 
+// The levels are built deepest first: level lv's sampling needs only the operator, its solve (Wp =
+// A_{lv+1}^{-1} U, then its node cores) the deeper levels.  (Sampling the next level on a second stream
+// beside the current solve was measured: the FFT passes and the level GEMMs slowed each other down and the
+// build gained 1.5%, so the build stays on one stream.)
 template <typename T>
 int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
   lsop_op* op = pc->op;
@@ -737,6 +783,7 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
   }
   Cx<T>* Y = reinterpret_cast<Cx<T>*>(pc->Y);
   Cx<T>* Q = reinterpret_cast<Cx<T>*>(pc->U);
+  const OrthScratch sc{pc->hG, pc->hX, pc->hK, pc->part, pc->part_cap, pc->hflag};
   // sub-domain spectra (depend on k0 and h)
   for (int lv = 0; lv < pc->levels; ++lv) {
     hodlr_level& L = pc->lev[lv];
@@ -754,28 +801,7 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
     const size_t seg = (size_t)(L.width / 2) * op->nz;
     Cx<T>* V = reinterpret_cast<Cx<T>*>(L.V);
     Cx<T>* Wp = reinterpret_cast<Cx<T>*>(L.Wp);
-    // Alg. 1 step 1: Gaussian probes of this level
-    if (omega) LSOP_HIP(launch_real_to_complex<T>(omega + (size_t)lv * r * n, Y, (size_t)r * n, s));
-    else LSOP_HIP(launch_philox_normal<T>(Y, r, n, pc->seed, s, lv * r));
-    // step 2: samples of both off-diagonal blocks of every node, G0 V[I1, I2] Om
-    // on the I1 cells and G0 V[I2, I1] Om on the I2 cells
-    if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 1, 0, s))) return st;
-    if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 0, 1, s))) return st;
-    // step 3: orthonormal bases per half-node (result in Y); with power iterations this basis is an
-    // intermediate one (one projection and one Cholesky-QR pass), the last one is orthonormalised in full
-    if ((st = hodlr_orth<T>(pc, lv, Q, Y, s, pc->q == 0))) return st;
-    // optional power iterations (Alg. 1 step 4) on both blocks of every node
-    for (int j = 0; j < pc->q; ++j) {
-      if ((st = hodlr_subconv<T>(pc, lv, true, Y, Q, r, 0, 1, s))) return st;
-      if ((st = hodlr_subconv<T>(pc, lv, true, Y, Q, r, 1, 0, s))) return st;
-      if ((st = hodlr_orth<T>(pc, lv, Q, Y, s, false))) return st;
-      if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 1, 0, s))) return st;
-      if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 0, 1, s))) return st;
-      if ((st = hodlr_orth<T>(pc, lv, Q, Y, s, j == pc->q - 1))) return st;
-    }
-    // right factors v12 = (G0 V[I1, I2])^H Q12 on I2, v21 on I1
-    if ((st = hodlr_subconv<T>(pc, lv, true, Y, V, r, 0, 1, s))) return st;
-    if ((st = hodlr_subconv<T>(pc, lv, true, Y, V, r, 1, 0, s))) return st;
+    if ((st = hodlr_sample<T>(pc, lv, omega, Y, Q, sc, s))) return st;
     // Wp = A_{lv+1}^{-1} Ut
     if ((st = hodlr_apply<T>(pc, Y, nullptr, Wp, nullptr, r, lv + 1, s))) return st;
     // K per node from the per-half products V^H Wp, then kinv = K^{-1} P
