@@ -53,6 +53,16 @@ class NoisyRounding(U.UNet):
 @pytest.mark.parametrize("levels,base,B,H,W", [(1, 8, 2, 8, 12), (2, 4, 1, 16, 8), (2, 8, 2, 16, 16), (1, 32, 1, 16, 8),
                                               (4, 8, 2, 32, 32), (3, 32, 1, 24, 16)])
 def test_forward_and_gradients_match_oracle(levels, base, B, H, W):
+    _parity(levels, base, B, H, W)
+
+
+def test_full_size_network_matches_oracle():
+    """The benchmark's network itself: 4 levels, 32 base channels, one 128 x 128 sample (vector convolution
+    kernels on every layer with channels in eights, the scalar ones on the input layer and the head)."""
+    _parity(4, 32, 1, 128, 128)
+
+
+def _parity(levels, base, B, H, W):
     announce(f"unet parity L={levels} base={base} {B}x{H}x{W}")
     r = np.random.default_rng(levels * 100 + base)
     theta = U.he_init(levels, base, 4, 2, seed=3) + 0.01 * r.standard_normal(U.param_count(levels, base))
@@ -65,7 +75,7 @@ def test_forward_and_gradients_match_oracle(levels, base, B, H, W):
     alt = NoisyRounding(theta, levels, base, bf16=True)
     y_alt = alt.forward(x.astype(np.float64))
     g_alt = alt.backward(dy.astype(np.float64))
-    net = lsop.UNet(levels, base, 4, 2, max_batch=4, max_h=32, max_w=32)
+    net = lsop.UNet(levels, base, 4, 2, max_batch=max(B, 4), max_h=max(H, 32), max_w=max(W, 32))
     assert net.nparams == theta.size
     net.set_params(theta)
     y = net.forward(f32(x))
