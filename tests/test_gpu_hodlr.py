@@ -203,3 +203,41 @@ def test_full_size_benchmark_solve():
         den_0 += abs(ref_0) ** 2
     assert np.sqrt(num_a / den_a) <= 1e-5
     assert np.sqrt(num_0 / den_0) <= 1e-5
+
+
+def test_layered_salt_256_fp64_and_refined_fp32():
+    """The 256^2 layered + salt workload (h = 10 m, 15 Hz, 1500-4500 m/s with two salt blocks, 32 top-row
+    sources).  FP64, and FP32 with FP64 refinement, each HODLR-preconditioned (rank 80, 5 levels, q = 1): both
+    converge to 1e-10 and agree to 1e-9; the FP64 solution reproduces the oracle's direct sums at sampled
+    cells, i.e. it solves the oracle's equation.  The simple preconditioner of Section 2.3 with 40 (+10)
+    probes does not converge here (the paper finds it limited to low frequency and small models)."""
+    announce("layered+salt 256^2 x 32: fp64 vs fp32 + refinement")
+    w = synth.model_layered_salt(n=256, h=10.0, freq=15.0, seed=2, nsrc=32)
+    out = {}
+    for dt in (lsop.C128, lsop.MIXED):
+        op = make_op(w, dt, 32)
+        pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=80, levels=5, power_iters=1, seed=4)
+        pc.build()
+        rhs = op.incident(w.src_i, w.src_j)
+        psi, res = lsop.series_solve(op, pc, rhs, tol=1e-10, max_iter=60, inner_tol=1e-5)
+        assert all(r.status == lsop.OK and r.rel_residual <= 1e-10 for r in res), dt
+        out[dt] = host(psi)
+    assert rel(out[lsop.MIXED], out[lsop.C128]) <= 1e-9
+    psi = out[lsop.C128]
+    chi = O.contrast(w.vel, w.freq, w.c0)
+    K = O.cell_kernel(256, 256, w.h, O.wavenumber(w.freq, w.c0))
+    rhs_ref = O.Problem(w.vel, w.h, w.freq, w.c0).incident(w.src_i, w.src_j)
+    ii = np.arange(256)
+    rng = np.random.default_rng(3)
+    num = den = 0.0
+    for _ in range(16):
+        v, i, j = rng.integers(0, 32), rng.integers(0, 256), rng.integers(0, 256)
+        a = psi[v, i, j] - np.sum(K[np.abs(ii - i)[:, None], np.abs(ii - j)[None, :]] * chi * psi[v])
+        num += abs(a - rhs_ref[v, i, j]) ** 2
+        den += abs(rhs_ref[v, i, j]) ** 2
+    assert np.sqrt(num / den) <= 1e-8
+    op = make_op(w, lsop.C128, 32)
+    pl = lsop.Preconditioner(op, lsop.PC_LOWRANK, rank=50, seed=4)
+    pl.build()
+    _, res = lsop.series_solve(op, pl, op.incident(w.src_i, w.src_j), tol=1e-10, max_iter=30)
+    assert all(r.status != lsop.OK for r in res)
