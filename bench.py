@@ -47,6 +47,10 @@ def parse():
                     help="skip the warm-started series after the timed training steps (counter runs: the timed "
                          "launches are then each kernel's last dispatches)")
     ap.add_argument("--count", type=int, default=64, help="instances of the uneven batch")
+    ap.add_argument("--leaf-cols", type=int, default=1,
+                    help="uneven batch: HODLR trees as deep as leaves of at least this many grid columns allow "
+                         "(measured: 1 column 114.8 solves/s, 2 columns 112.8, 3 columns 85.5; the FP64 leaf "
+                         "inverses grow with the cube of the leaf size)")
     ap.add_argument("--build-streams", type=int, default=8,
                     help="uneven batch: preconditioner builds run concurrently on this many device streams")
     ap.add_argument("--steps", type=int, default=3)
@@ -193,14 +197,14 @@ def cpu_baseline(w, args, iterations, converged, nsrc_sample=2):
             "build_s_extrapolated": round(t_build, 2), "series_s_extrapolated": round(it_total * t_conv + h_total * t_h, 2)}
 
 
-def hodlr_policy(n, h, freq, cmin):
+def hodlr_policy(n, h, freq, cmin, leaf_cols=1):
     """HODLR parameters for one instance: rank ~3 per wavelength across the grid (16-aligned, 32..256), one
-    power iteration, and leaves 3-4 grid columns wide."""
+    power iteration, and the deepest tree whose leaves keep at least `leaf_cols` grid columns."""
     import math
     nlam = n * h * freq / cmin
     r = int(min(256, max(32, 16 * math.ceil(3.0 * nlam / 16))))
     levels = 1
-    while n % (1 << (levels + 1)) == 0 and (n >> (levels + 1)) >= 3:
+    while n % (1 << (levels + 1)) == 0 and (n >> (levels + 1)) >= leaf_cols:
         levels += 1
     return r, levels
 
@@ -219,7 +223,7 @@ def main_uneven(args):
     pcs = []
     for w, op, v in zip(ws, ops, vels):
         op.set_problem(v, w.h, w.freq, w.c0)
-        r, lv = hodlr_policy(w.nx, w.h, w.freq, float(w.vel.min()))
+        r, lv = hodlr_policy(w.nx, w.h, w.freq, float(w.vel.min()), args.leaf_cols)
         pcs.append(lsop.Preconditioner(op, lsop.PC_HODLR, rank=r, levels=lv, power_iters=1, seed=3))
     batch = lsop.Batch(ops)
     batch.autotune()
@@ -278,7 +282,8 @@ def main_uneven(args):
                                f"(rank ~3 per wavelength, q=1) built {args.build_streams} at a time on separate streams, "
                                f"lockstep series in one batch with a captured "
                                f"graph per iteration, autotuned column tiles per shape group",
-                   "instances": len(ws), "sources": len(flat), "shape_groups": batch.info()[0]},
+                   "instances": len(ws), "sources": len(flat), "shape_groups": batch.info()[0],
+                   "leaf_cols": args.leaf_cols, "build_streams": args.build_streams},
         "converged": converged, "statuses": statuses,
         "iterations": [min(x.iters for x in flat), max(x.iters for x in flat)],
         "build_s": round(phase["build"] / args.steps, 3), "series_s": round(phase["series"] / args.steps, 3),
