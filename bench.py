@@ -42,7 +42,7 @@ def parse():
                          "the warm-started series at 256^2 and 512^2")
     ap.add_argument("--unet-models", type=int, default=32,
                     help="layered + salt models (32 sources each) solved for the network's training data")
-    ap.add_argument("--unet-batch", type=int, default=16)
+    ap.add_argument("--unet-batch", type=int, default=64, help="training batch (the workload leaves it free)")
     ap.add_argument("--unet-no-eval", action="store_true",
                     help="skip the warm-started series after the timed training steps (counter runs: the timed "
                          "launches are then each kernel's last dispatches)")
