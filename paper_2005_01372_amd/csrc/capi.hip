@@ -586,30 +586,35 @@ int hodlr_sample(lsop_precond* pc, int lv, const double* omega, Cx<T>* Y, Cx<T>*
 // recursing on A and S down to 64 x 64 blocks (Gauss-Jordan with partial
 // pivoting; flags[b] set on a vanishing pivot).  Temporaries of recursion
 // depth d at tbase + toff[d] (block_inverse_temps).
-int block_inverse(Cx<double>* M, size_t ld, size_t st, int cnt, size_t o, int m, int depth, Cx<double>* tbase,
+// W: the working precision (double, or float for the leaves of a complex-FP32 preconditioner).
+template <typename W>
+int block_inverse(Cx<W>* M, size_t ld, size_t st, int cnt, size_t o, int m, int depth, Cx<W>* tbase,
                   const std::vector<size_t>& toff, int* flags, hipStream_t s) {
   if (m <= 64) {
-    LSOP_HIP(prof("block_inv_base", "k_lu_inverse_lds", 3.0 * m * m * (double)sizeof(Cx<double>) * cnt,
+    LSOP_HIP(prof("block_inv_base", fn_name("k_lu_inverse_lds", tname<W>()), 3.0 * m * m * (double)sizeof(Cx<W>) * cnt,
                   8.0 * m * m * (double)m * cnt, cnt, s, [&] {
-      return launch_lu_inverse(M + o, ld, st, M + o, ld, st, nullptr, m, true, flags, cnt, s);
+      if constexpr (std::is_same<W, double>::value)
+        return launch_lu_inverse(M + o, ld, st, M + o, ld, st, nullptr, m, true, flags, cnt, s);
+      else
+        return launch_lu_inverse_small_f32(M + o, ld, st, M + o, ld, st, m, true, flags, cnt, s);
     }));
     return LSOP_OK;
   }
   const int h = m / 2, h2 = m - h;
   const size_t A = o, B = o + h, C = o + (size_t)h * ld, D = C + h;
-  Cx<double>* T1 = tbase + toff[depth];   // h x h2
-  Cx<double>* T2 = T1 + (size_t)cnt * h * h2;  // h2 x h
+  Cx<W>* T1 = tbase + toff[depth];         // h x h2
+  Cx<W>* T2 = T1 + (size_t)cnt * h * h2;   // h2 x h
   const size_t s1 = (size_t)h * h2;
-  int rc = block_inverse(M, ld, st, cnt, A, h, depth + 1, tbase, toff, flags, s);
+  int rc = block_inverse<W>(M, ld, st, cnt, A, h, depth + 1, tbase, toff, flags, s);
   if (rc) return rc;
-  auto gemm = [&](const Cx<double>* a, size_t lda, size_t sa, const Cx<double>* b, size_t ldb, size_t sb,
-                  Cx<double>* c, size_t ldc, size_t sc, int mm, int nn, int kk, double alpha, double beta) {
-    return p_bgemm<double>("block_inv_gemm", a, lda, sa, b, ldb, sb, c, ldc, sc, nullptr, nullptr, mm, nn, kk, alpha,
-                           beta, cnt, s);
+  auto gemm = [&](const Cx<W>* a, size_t lda, size_t sa, const Cx<W>* b, size_t ldb, size_t sb, Cx<W>* c, size_t ldc,
+                  size_t sc, int mm, int nn, int kk, double alpha, double beta) {
+    return p_bgemm<W>("block_inv_gemm", a, lda, sa, b, ldb, sb, c, ldc, sc, nullptr, nullptr, mm, nn, kk, alpha, beta,
+                      cnt, s);
   };
   LSOP_HIP(gemm(M + A, ld, st, M + B, ld, st, T1, h2, s1, h, h2, h, 1.0, 0.0));      // T1 = X B
   LSOP_HIP(gemm(M + C, ld, st, T1, h2, s1, M + D, ld, st, h2, h2, h, -1.0, 1.0));    // D <- S = D - C X B
-  rc = block_inverse(M, ld, st, cnt, D, h2, depth + 1, tbase, toff, flags, s);      // D <- S^{-1}
+  rc = block_inverse<W>(M, ld, st, cnt, D, h2, depth + 1, tbase, toff, flags, s);   // D <- S^{-1}
   if (rc) return rc;
   LSOP_HIP(gemm(M + C, ld, st, M + A, ld, st, T2, h, s1, h2, h, h, 1.0, 0.0));      // T2 = C X
   LSOP_HIP(gemm(T1, h2, s1, M + D, ld, st, M + B, ld, st, h, h2, h2, -1.0, 0.0));   // B <- -X B S^{-1}
@@ -642,16 +647,29 @@ int hodlr_leaves(lsop_precond* pc, hipStream_t s) {
     size_t total = 0;
     const std::vector<size_t> toff = block_inverse_temps(nl, cnt, &total);
     LSOP_HIP(hipMemsetAsync(pc->hflag, 0, sizeof(int) * cnt, s));
-    LSOP_HIP(launch_leaf_form(op->ktab, op->chi64, pc->lwork, op->nz, nl, l0, cnt, s));
-    int rc = block_inverse(pc->lwork, nl, (size_t)nl * nl, cnt, 0, nl, 0, pc->lwork + (size_t)cnt * nl * nl, toff,
-                           pc->hflag, s);
+    // complex-FP32 preconditioners invert their leaves in FP32 (error ~ cond * 1e-7, far below the low-rank
+    // truncation of the off-diagonal blocks); complex-FP64 ones in FP64
+    int rc;
+    if constexpr (std::is_same<T, float>::value) {
+      Cx<float>* lw = reinterpret_cast<Cx<float>*>(pc->lwork);
+      LSOP_HIP(launch_leaf_form<float>(op->ktab, op->chi64, lw, op->nz, nl, l0, cnt, s));
+      rc = block_inverse<float>(lw, nl, (size_t)nl * nl, cnt, 0, nl, 0, lw + (size_t)cnt * nl * nl, toff, pc->hflag, s);
+    } else {
+      LSOP_HIP(launch_leaf_form<double>(op->ktab, op->chi64, pc->lwork, op->nz, nl, l0, cnt, s));
+      rc = block_inverse<double>(pc->lwork, nl, (size_t)nl * nl, cnt, 0, nl, 0, pc->lwork + (size_t)cnt * nl * nl,
+                                 toff, pc->hflag, s);
+    }
     if (rc) return rc;
     std::vector<int> flags(cnt, 0);
     LSOP_HIP(hipMemcpyAsync(flags.data(), pc->hflag, sizeof(int) * cnt, hipMemcpyDeviceToHost, s));
     LSOP_HIP(hipStreamSynchronize(s));
     for (int f : flags)
       if (f) return fail(LSOP_ESINGULAR, "a HODLR leaf block is numerically singular");
-    LSOP_HIP(launch_transpose_convert<T>(pc->lwork, dinv + (size_t)l0 * nl * nl, nl, cnt, s));
+    if constexpr (std::is_same<T, float>::value)
+      LSOP_HIP(launch_transpose_f32(reinterpret_cast<const Cx<float>*>(pc->lwork), dinv + (size_t)l0 * nl * nl, nl,
+                                    cnt, s));
+    else
+      LSOP_HIP(launch_transpose_convert<T>(pc->lwork, dinv + (size_t)l0 * nl * nl, nl, cnt, s));
   }
   return LSOP_OK;
 }

@@ -142,9 +142,15 @@ hipError_t launch_lu_inverse_i_minus(const Cx<double>* M, Cx<double>* Z, Cx<doub
 // C_b = alpha * A_b (na x na) * B_b (na x nb)
 hipError_t launch_small_gemm(const Cx<double>* A, const Cx<double>* B, Cx<double>* C, int na, int nb, double alpha,
                              hipStream_t s, int batch = 1);
-// HODLR: dense leaf blocks of I - G0 V (FP64), leaves leaf0 .. leaf0 + nleaf - 1 of nl cells
-hipError_t launch_leaf_form(const Cx<double>* ktab, const double* chi, Cx<double>* out, int nz, int nl, int leaf0,
+// FP32 Gauss-Jordan inverses of batch blocks of na <= 64 (as launch_lu_inverse, plain form)
+hipError_t launch_lu_inverse_small_f32(const Cx<float>* M, size_t ldm, size_t sm, Cx<float>* Z, size_t ldz, size_t sz,
+                                      int na, bool plain, int* singular, int batch, hipStream_t s);
+// HODLR: dense leaf blocks of I - G0 V (formed in FP64, stored as To), leaves leaf0 .. leaf0 + nleaf - 1 of nl cells
+template <typename To>
+hipError_t launch_leaf_form(const Cx<double>* ktab, const double* chi, Cx<To>* out, int nz, int nl, int leaf0,
                             int nleaf, hipStream_t s);
+// out_b = transpose(in_b), FP32 (m x m each)
+hipError_t launch_transpose_f32(const Cx<float>* in, Cx<float>* out, int m, int batch, hipStream_t s);
 // out_b = transpose(in_b) converted to T (m x m each)
 template <typename T>
 hipError_t launch_transpose_convert(const Cx<double>* in, Cx<T>* out, int m, int batch, hipStream_t s);

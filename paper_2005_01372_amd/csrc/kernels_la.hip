@@ -497,23 +497,25 @@ __device__ __forceinline__ void block_argmax(double v, int i, double* red, int* 
 // wld >= 2 na), where B = I - M (plain = 0, eq. 12) or B = M (plain = 1).  M
 // has leading dimension ldm, Z ldz (Z may alias M).  *singular is set to 1 on
 // a vanishing pivot (never cleared here, so one flag can collect several
-// calls).
-__device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, size_t ldm, Cx<double>* Z, size_t ldz,
-                                                Cx<double>* work, int wld, int na, int plain, int* singular,
-                                                Cx<double>* fcol, double* red, int* redi) {
+// calls).  T = double (pivot threshold 1e-14 of the largest entry) or float (1e-6).
+template <typename T>
+__device__ __forceinline__ void lu_inverse_body(const Cx<T>* M, size_t ldm, Cx<T>* Z, size_t ldz, Cx<T>* work,
+                                                int wld, int na, int plain, int* singular, Cx<T>* fcol, double* red,
+                                                int* redi) {
+  const double tiny = sizeof(T) == sizeof(double) ? 1e-14 : 1e-6;
   const int t = threadIdx.x, w2 = 2 * na;
   double amax = 0.0;
   for (int idx = t; idx < na * w2; idx += blockDim.x) {
     const int i = idx / w2, j = idx % w2;
-    Cx<double> v;
+    Cx<T> v;
     if (j < na) {
-      const Cx<double> m = M[(size_t)i * ldm + j];
-      v = plain ? m : Cx<double>{(i == j ? 1.0 : 0.0) - m.re, -m.im};
+      const Cx<T> m = M[(size_t)i * ldm + j];
+      v = plain ? m : Cx<T>{(i == j ? T(1) : T(0)) - m.re, -m.im};
     } else {
-      v = Cx<double>{(i == j - na) ? 1.0 : 0.0, 0.0};
+      v = Cx<T>{(i == j - na) ? T(1) : T(0), T(0)};
     }
     work[(size_t)i * wld + j] = v;
-    if (j < na) amax = fmax(amax, sqrt(norm2(v)));
+    if (j < na) amax = fmax(amax, sqrt((double)norm2(v)));
   }
   double scale;
   int dummy;
@@ -524,7 +526,7 @@ __device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, size_t ldm,
     double bv = -1.0;
     int bi = k;
     for (int i = k + t; i < na; i += blockDim.x) {
-      const double v = norm2(work[(size_t)i * wld + k]);
+      const double v = (double)norm2(work[(size_t)i * wld + k]);
       if (v > bv) {
         bv = v;
         bi = i;
@@ -533,28 +535,28 @@ __device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, size_t ldm,
     double piv2;
     int p;
     block_argmax(bv, bi, red, redi, &piv2, &p);
-    if (!(sqrt(piv2) > 1e-14 * scale)) {
+    if (!(sqrt(piv2) > tiny * scale)) {
       if (t == 0) *singular = 1;
       return;  // uniform across the workgroup
     }
     if (p != k) {
       for (int j = t; j < w2; j += blockDim.x) {
-        const Cx<double> a = work[(size_t)k * wld + j];
+        const Cx<T> a = work[(size_t)k * wld + j];
         work[(size_t)k * wld + j] = work[(size_t)p * wld + j];
         work[(size_t)p * wld + j] = a;
       }
     }
     __syncthreads();
-    const Cx<double> pv = work[(size_t)k * wld + k];
-    const double d = 1.0 / norm2(pv);
-    const Cx<double> inv = Cx<double>{pv.re * d, -pv.im * d};
+    const Cx<T> pv = work[(size_t)k * wld + k];
+    const T d = T(1) / norm2(pv);
+    const Cx<T> inv = Cx<T>{pv.re * d, -pv.im * d};
     __syncthreads();
     for (int j = t; j < w2; j += blockDim.x) work[(size_t)k * wld + j] = work[(size_t)k * wld + j] * inv;
     for (int i = t; i < na; i += blockDim.x) fcol[i] = work[(size_t)i * wld + k];
     __syncthreads();
     // rank-1 elimination; left-block columns before k are zero in the pivot row and are skipped
     if (ui0 < urs && (uj >= na || uj >= k)) {
-      const Cx<double> pr = work[(size_t)k * wld + uj];
+      const Cx<T> pr = work[(size_t)k * wld + uj];
       for (int i = ui0; i < na; i += urs)
         if (i != k) work[(size_t)i * wld + uj] = work[(size_t)i * wld + uj] - fcol[i] * pr;
     }
@@ -570,15 +572,15 @@ __device__ __forceinline__ void lu_inverse_body(const Cx<double>* M, size_t ldm,
 // work rows have an odd stride (conflict-free column reads).
 constexpr int LU_WLD = 2 * SMALL_NA + 1;
 
-__global__ __launch_bounds__(256) void k_lu_inverse_lds(const Cx<double>* __restrict__ M, size_t ldm, size_t sm,
-                                                         Cx<double>* Z, size_t ldz, size_t sz, int na, int plain,
-                                                         int* singular) {
-  __shared__ Cx<double> work[SMALL_NA * LU_WLD];
-  __shared__ Cx<double> fcol[SMALL_NA];
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_inverse_lds(const Cx<T>* __restrict__ M, size_t ldm, size_t sm, Cx<T>* Z,
+                                                         size_t ldz, size_t sz, int na, int plain, int* singular) {
+  __shared__ Cx<T> work[SMALL_NA * LU_WLD];
+  __shared__ Cx<T> fcol[SMALL_NA];
   __shared__ double red[4];
   __shared__ int redi[4];
   const size_t b = blockIdx.x;
-  lu_inverse_body(M + b * sm, ldm, Z + b * sz, ldz, work, LU_WLD, na, plain, singular + b, fcol, red, redi);
+  lu_inverse_body<T>(M + b * sm, ldm, Z + b * sz, ldz, work, LU_WLD, na, plain, singular + b, fcol, red, redi);
 }
 
 __global__ __launch_bounds__(256) void k_lu_inverse_i_minus(const Cx<double>* __restrict__ M, size_t ldm, size_t sm,
@@ -590,7 +592,8 @@ __global__ __launch_bounds__(256) void k_lu_inverse_i_minus(const Cx<double>* __
   __shared__ double red[4];
   __shared__ int redi[4];
   const size_t b = blockIdx.x;
-  lu_inverse_body(M + b * sm, ldm, Z + b * sz, ldz, work + b * 2 * (size_t)na * na, 2 * na, na, plain, singular + b,
+  lu_inverse_body<double>(M + b * sm, ldm, Z + b * sz, ldz, work + b * 2 * (size_t)na * na, 2 * na, na, plain,
+                          singular + b,
                   fcol, red, redi);
 }
 
@@ -613,8 +616,9 @@ __global__ void k_small_gemm(const Cx<double>* __restrict__ A, const Cx<double>*
 // Dense diagonal leaf blocks of A = I - G0 V (eq. 5) for leaves of w grid
 // columns (nl = w nz cells, column-wise order): out[b][a][c] =
 // delta_ac - K(|ia - ic|, |ja - jc|) chi[c] for leaf leaf0 + b.
+template <typename To>
 __global__ void k_leaf_form(const Cx<double>* __restrict__ ktab, const double* __restrict__ chi,
-                            Cx<double>* __restrict__ out, int nz, int nl, int leaf0, int nleaf) {
+                            Cx<To>* __restrict__ out, int nz, int nl, int leaf0, int nleaf) {
   const size_t per = (size_t)nl * nl, total = per * nleaf;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
@@ -625,17 +629,17 @@ __global__ void k_leaf_form(const Cx<double>* __restrict__ ktab, const double* _
     const int di = ia > ic ? ia - ic : ic - ia, dj = ja > jc ? ja - jc : jc - ja;
     const double x = chi[(size_t)(leaf0 + b) * nl + c];
     const Cx<double> k = ktab[(size_t)di * nz + dj];
-    out[idx] = Cx<double>{(a == c ? 1.0 : 0.0) - x * k.re, -x * k.im};
+    out[idx] = Cx<To>{(To)((a == c ? 1.0 : 0.0) - x * k.re), (To)(-x * k.im)};
   }
 }
 
-// out[b][j][i] = in[b][i][j] (FP64 -> T), 32 x 32 tiles through LDS.
-template <typename T>
-__global__ __launch_bounds__(256) void k_transpose_convert(const Cx<double>* __restrict__ in, Cx<T>* __restrict__ out,
+// out[b][j][i] = in[b][i][j] (Ti -> T), 32 x 32 tiles through LDS.
+template <typename T, typename Ti = double>
+__global__ __launch_bounds__(256) void k_transpose_convert(const Cx<Ti>* __restrict__ in, Cx<T>* __restrict__ out,
                                                             int m) {
-  __shared__ Cx<double> tile[32][33];
+  __shared__ Cx<Ti> tile[32][33];
   const size_t b = blockIdx.z;
-  const Cx<double>* src = in + b * m * m;
+  const Cx<Ti>* src = in + b * m * m;
   Cx<T>* dst = out + b * m * m;
   const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
   const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
@@ -913,11 +917,20 @@ hipError_t launch_lu_inverse(const Cx<double>* M, size_t ldm, size_t sm, Cx<doub
                              Cx<double>* work, int na, bool plain, int* singular, int batch, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   if (na <= SMALL_NA)
-    hipLaunchKernelGGL(k_lu_inverse_lds, dim3(batch), dim3(256), 0, s, M, ldm, sm, Z, ldz, sz, na, (int)plain,
-                       singular);
+    hipLaunchKernelGGL(k_lu_inverse_lds<double>, dim3(batch), dim3(256), 0, s, M, ldm, sm, Z, ldz, sz, na,
+                       (int)plain, singular);
   else
     hipLaunchKernelGGL(k_lu_inverse_i_minus, dim3(batch), dim3(256), sizeof(Cx<double>) * na, s, M, ldm, sm, Z, ldz,
                        sz, work, na, (int)plain, singular);
+  return hipGetLastError();
+}
+
+hipError_t launch_lu_inverse_small_f32(const Cx<float>* M, size_t ldm, size_t sm, Cx<float>* Z, size_t ldz, size_t sz,
+                                      int na, bool plain, int* singular, int batch, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  if (na < 1 || na > SMALL_NA) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_lu_inverse_lds<float>, dim3(batch), dim3(256), 0, s, M, ldm, sm, Z, ldz, sz, na, (int)plain,
+                     singular);
   return hipGetLastError();
 }
 
@@ -933,11 +946,24 @@ hipError_t launch_small_gemm(const Cx<double>* A, const Cx<double>* B, Cx<double
   return hipGetLastError();
 }
 
-hipError_t launch_leaf_form(const Cx<double>* ktab, const double* chi, Cx<double>* out, int nz, int nl, int leaf0,
+template <typename To>
+hipError_t launch_leaf_form(const Cx<double>* ktab, const double* chi, Cx<To>* out, int nz, int nl, int leaf0,
                             int nleaf, hipStream_t s) {
   const size_t total = (size_t)nl * nl * nleaf;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_leaf_form, dim3(grid1(total, 16384)), dim3(256), 0, s, ktab, chi, out, nz, nl, leaf0, nleaf);
+  hipLaunchKernelGGL((k_leaf_form<To>), dim3(grid1(total, 16384)), dim3(256), 0, s, ktab, chi, out, nz, nl, leaf0,
+                     nleaf);
+  return hipGetLastError();
+}
+template hipError_t launch_leaf_form<double>(const Cx<double>*, const double*, Cx<double>*, int, int, int, int,
+                                             hipStream_t);
+template hipError_t launch_leaf_form<float>(const Cx<double>*, const double*, Cx<float>*, int, int, int, int,
+                                            hipStream_t);
+
+hipError_t launch_transpose_f32(const Cx<float>* in, Cx<float>* out, int m, int batch, hipStream_t s) {
+  if (batch <= 0 || m <= 0) return hipSuccess;
+  const dim3 grid((m + 31) / 32, (m + 31) / 32, batch);
+  hipLaunchKernelGGL((k_transpose_convert<float, float>), grid, dim3(256), 0, s, in, out, m);
   return hipGetLastError();
 }
 
@@ -945,7 +971,7 @@ template <typename T>
 hipError_t launch_transpose_convert(const Cx<double>* in, Cx<T>* out, int m, int batch, hipStream_t s) {
   if (batch <= 0 || m <= 0) return hipSuccess;
   const dim3 grid((m + 31) / 32, (m + 31) / 32, batch);
-  hipLaunchKernelGGL((k_transpose_convert<T>), grid, dim3(256), 0, s, in, out, m);
+  hipLaunchKernelGGL((k_transpose_convert<T, double>), grid, dim3(256), 0, s, in, out, m);
   return hipGetLastError();
 }
 
