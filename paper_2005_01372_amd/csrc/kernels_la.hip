@@ -694,8 +694,12 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
   constexpr int SROW = 2 * GM_K + 1;
   __shared__ T sa[GM_T * SROW];
   __shared__ T sb[GM_T * SROW];
-  const size_t bt = blockIdx.z;
-  const int n0 = blockIdx.x * GM_T, m0 = blockIdx.y * GM_T;
+  // all tiles of one batch entry (which share its A rows and B columns) at consecutive logical indices on
+  // one XCD, so their re-reads of the operands are L2 hits
+  const unsigned lid = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
+                                 gridDim.x * gridDim.y * gridDim.z);
+  const size_t bt = lid / (gridDim.x * gridDim.y);
+  const int n0 = (int)(lid % gridDim.x) * GM_T, m0 = (int)((lid / gridDim.x) % gridDim.y) * GM_T;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
   typename MF::acc cre[2][2], cim[2][2];
