@@ -295,10 +295,10 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
 // (segmented form: M for element k is M + (k / seg) * mstride):
 // each wave owns 16 consecutive k (coalesced B-operand loads and stores) and
 // up to NBT * 16 b (MFMA row tiles, real and imaginary chains); M is staged in
-// LDS GU2_A rows (a) at a time, and the A elements of the next block are
-// loaded into registers while the current block's MFMAs run (a whole block
-// in flight per lane covers the HBM latency; short blocks keep the register
-// count, and so the occupancy, up).
+// LDS GU2_A rows (a) at a time; the A elements and the M rows of the next
+// block are loaded into registers while the current block's MFMAs run (a
+// whole block in flight per lane covers the memory latency; short blocks keep
+// the register count, and so the occupancy, up).
 constexpr int GU2_A = 8;
 
 template <typename T, int NBT>
@@ -325,21 +325,33 @@ __global__ __launch_bounds__(256) void k_gemm_update_mfma(const Cx<T>* __restric
       cre[j] = typename MF::acc{0, 0, 0, 0};
       cim[j] = typename MF::acc{0, 0, 0, 0};
     }
-    // lane's A elements of one block: a = a0 + 2 st + kk / 2, st < GU2_A / 2
+    // lane's A elements of one block: a = a0 + 2 st + kk / 2, st < GU2_A / 2; the thread's share of the
+    // M block (PER elements, idx = threadIdx.x + 256 q); both loaded one block ahead of their use
+    constexpr int PER = (GU2_A * BW + 255) / 256;
     const int ab = kk >> 1;
     Cx<T> av[GU2_A / 2];
+    Cx<double> mv[PER];
 #pragma unroll
     for (int st = 0; st < GU2_A / 2; ++st) {
       const int a = ab + 2 * st;
       av[st] = (kin && a < na) ? A[(size_t)a * n + kcol] : czero<T>();
     }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = threadIdx.x + 256 * q, a = idx / BW, b = b0 + idx % BW;
+      mv[q] = (idx < GU2_A * BW && a < na && b < nb) ? Mm[(size_t)a * nb + b] : czero<double>();
+    }
     for (int a0 = 0; a0 < na; a0 += GU2_A) {
       __syncthreads();
-      for (int idx = threadIdx.x; idx < GU2_A * BW; idx += blockDim.x) {
-        const int a = a0 + idx / BW, b = b0 + idx % BW;
-        sm[idx] = (a < na && b < nb) ? ccast<T>(Mm[(size_t)a * nb + b]) : czero<T>();
-      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q)
+        if (threadIdx.x + 256 * q < GU2_A * BW) sm[threadIdx.x + 256 * q] = ccast<T>(mv[q]);
       __syncthreads();
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int idx = threadIdx.x + 256 * q, a = a0 + GU2_A + idx / BW, b = b0 + idx % BW;
+        mv[q] = (idx < GU2_A * BW && a < na && b < nb) ? Mm[(size_t)a * nb + b] : czero<double>();
+      }
       Cx<T> cur[GU2_A / 2];
 #pragma unroll
       for (int st = 0; st < GU2_A / 2; ++st) cur[st] = av[st];
