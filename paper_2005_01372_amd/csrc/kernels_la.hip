@@ -207,9 +207,11 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
                                                         int nb, size_t n, size_t seg, size_t chunk, int ksub,
                                                         Cx<double>* __restrict__ part) {
   using M = Mfma<T>;
-  constexpr int SROW = 2 * GM_K + 1;  // reals per LDS row (odd stride)
-  __shared__ T sa[GM_T * SROW];
-  __shared__ T sb[GM_T * SROW];
+  // reals per LDS row: an even stride, so that (re, im) pairs are stored and read as one aligned pair (the 16
+  // row offsets 34 c mod 64 banks are still distinct)
+  constexpr int SROW = 2 * GM_K + 2;
+  __shared__ __align__(16) T sa[GM_T * SROW];
+  __shared__ __align__(16) T sb[GM_T * SROW];
   const unsigned lid = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
                                  gridDim.x * gridDim.y * gridDim.z);
   const int a0 = (int)(lid % gridDim.x) * GM_T, b0 = (int)((lid / gridDim.x) % gridDim.y) * GM_T;
@@ -249,10 +251,8 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
   for (size_t kb = k_begin; kb < k_end; kb += GM_K) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      sa[lr * SROW + 2 * (lk + q)] = va[q].re;
-      sa[lr * SROW + 2 * (lk + q) + 1] = va[q].im;
-      sb[lr * SROW + 2 * (lk + q)] = vb2[q].re;
-      sb[lr * SROW + 2 * (lk + q) + 1] = vb2[q].im;
+      *reinterpret_cast<Cx<T>*>(&sa[lr * SROW + 2 * (lk + q)]) = va[q];
+      *reinterpret_cast<Cx<T>*>(&sb[lr * SROW + 2 * (lk + q)]) = vb2[q];
     }
     __syncthreads();
     if (kb + GM_K < k_end) load(kb + GM_K);
@@ -264,9 +264,9 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
       for (int i = 0; i < 2; ++i) av[i] = sa[(wa + i * 16 + c16) * SROW + col];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const int rb = (wb + j * 16 + c16) * SROW;
-        bre[j] = sb[rb + col];
-        bim[j] = (kk & 1) ? -sb[rb + col - 1] : sb[rb + col + 1];
+        const Cx<T> v = *reinterpret_cast<const Cx<T>*>(&sb[(wb + j * 16 + c16) * SROW + (col & ~1)]);
+        bre[j] = (kk & 1) ? v.im : v.re;
+        bim[j] = (kk & 1) ? -v.re : v.im;
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
