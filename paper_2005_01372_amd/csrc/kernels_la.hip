@@ -703,9 +703,9 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
                                                     const int* __restrict__ mapa, const int* __restrict__ mapc, int M,
                                                     int N, int K, T alpha, T beta) {
   using MF = Mfma<T>;
-  constexpr int SROW = 2 * GM_K + 1;
-  __shared__ T sa[GM_T * SROW];
-  __shared__ T sb[GM_T * SROW];
+  constexpr int SROW = 2 * GM_K + 2;  // even: (re, im) pairs stored and read as one aligned pair
+  __shared__ __align__(16) T sa[GM_T * SROW];
+  __shared__ __align__(16) T sb[GM_T * SROW];
   // all tiles of one batch entry (which share its A rows and B columns) at consecutive logical indices on
   // one XCD, so their re-reads of the operands are L2 hits
   const unsigned lid = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
@@ -744,10 +744,8 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
   for (int kb = 0; kb < K; kb += GM_K) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      sa[ar * SROW + 2 * (ak + q)] = va[q].re;
-      sa[ar * SROW + 2 * (ak + q) + 1] = va[q].im;
-      sb[(bn + q) * SROW + 2 * bk] = vb[q].re;
-      sb[(bn + q) * SROW + 2 * bk + 1] = vb[q].im;
+      *reinterpret_cast<Cx<T>*>(&sa[ar * SROW + 2 * (ak + q)]) = va[q];
+      *reinterpret_cast<Cx<T>*>(&sb[(bn + q) * SROW + 2 * bk]) = vb[q];
     }
     __syncthreads();
     if (kb + GM_K < K) load(kb + GM_K);
@@ -759,9 +757,9 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
       for (int i = 0; i < 2; ++i) av[i] = sa[(wm + i * 16 + c16) * SROW + col];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const int rb = (wn + j * 16 + c16) * SROW;
-        bre[j] = (kk & 1) ? -sb[rb + col] : sb[rb + col];
-        bim[j] = (kk & 1) ? sb[rb + col - 1] : sb[rb + col + 1];
+        const Cx<T> v = *reinterpret_cast<const Cx<T>*>(&sb[(wn + j * 16 + c16) * SROW + (col & ~1)]);
+        bre[j] = (kk & 1) ? -v.im : v.re;
+        bim[j] = (kk & 1) ? v.re : v.im;
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
