@@ -338,7 +338,7 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
       Cx<T>* dst = pass == 0 ? Qb : Yb;
       LSOP_HIP(p_ah_b<T>("orth_gram", src, kb, src, nullptr, kb, n, seg, G, part, ksub, s, 1.0, part_cap));
       LSOP_HIP(prof("orth_coeffs", "k_gram_orth_lds", 2.0 * nseg * kb * kb * sizeof(Cx<double>),
-                    8.0 * 3.0 * kb * kb * (double)kb * nseg, nseg, s, [&] {
+                    8.0 / 3.0 * kb * kb * (double)kb * nseg, nseg, s, [&] {
                       return launch_gram_orth(G, X, kb, pass == 0 ? tol : 1e-6, kept + (c0 / B) * nseg, s, nseg,
                                               (pass == 0 && c0 > 0) ? R : nullptr);
                     }));

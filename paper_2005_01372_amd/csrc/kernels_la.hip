@@ -394,84 +394,63 @@ __global__ __launch_bounds__(256) void k_gemm_update_mfma(const Cx<T>* __restric
 
 // ------------------------------------------------------- small FP64 kernels
 // Orthonormalising coefficients X (na x na, na <= 64) for Q = Y X from the
-// Gram matrix G = Y^H Y: column k of X is e_k projected twice (classical
-// Gram-Schmidt in the G inner product) against the kept columns, then
-// normalised; columns whose remaining G-norm^2 is <= drop_tol * R_kk are
-// zeroed (dropped), R = gref (the Gram matrix of the columns before an earlier
-// projection) or G itself.  One workgroup of four waves per batch entry b
-// (G_b, X_b, R_b at b * na * na, kept[b]); each product is split four ways
-// over the waves.  LDS layouts are chosen so that lanes read consecutive (or
-// odd-strided) addresses: G x uses the Hermitian symmetry (G[i][l] =
-// conj G[l][i]), and X is held column-major with an odd row stride, so X cf
-// (down the columns) and X^H w (along them) are both conflict-free.
+// Gram matrix G = Y^H Y: X = R^{-1} with G = R^H R (Cholesky), so that
+// X^H G X = I.  A column whose Schur-complement diagonal (its G-norm^2 after
+// projection on the kept earlier columns) is <= drop_tol * R_kk is dropped: its
+// row of R and its column of X are zero and it takes no part in later
+// eliminations; R = gref (the Gram matrix of the columns before an earlier
+// projection) or G itself.  One workgroup of four waves per batch entry b (G_b,
+// X_b, R_b at b * na * na, kept[b]).  The right-looking factorisation is run
+// as row operations on [G | I] in LDS: step k scales row k by 1 / sqrt(d_k)
+// (wave 0), then every later row i subtracts conj(R_ki) times it (rows split
+// over the waves, lane = column); the upper triangle of the left block becomes
+// R and the right block R^{-H} = X^H.  Two barriers per column.
 constexpr int SMALL_NA = 64;
-
-__device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
 
 __global__ __launch_bounds__(256) void k_gram_orth_lds(const Cx<double>* __restrict__ Gg, Cx<double>* __restrict__ Xg,
                                                         int na, double drop_tol, int* kept,
                                                         const Cx<double>* __restrict__ gref) {
-  constexpr int XS = SMALL_NA + 1;  // row stride of X (odd: row and column walks are both conflict-free)
-  __shared__ Cx<double> G[SMALL_NA * SMALL_NA], Xc[SMALL_NA * XS];
-  __shared__ Cx<double> x[SMALL_NA], w[SMALL_NA], cf[SMALL_NA], red[4][SMALL_NA];
-  __shared__ double nrm_s;
+  constexpr int ES = SMALL_NA + 1;  // row stride of E (odd: the transposed read at the end is conflict-free)
+  __shared__ Cx<double> S[SMALL_NA * SMALL_NA];  // G, reduced in place (upper triangle: R)
+  __shared__ Cx<double> E[SMALL_NA * ES];        // I, taken to R^{-H} by the same row operations
+  __shared__ double g0[SMALL_NA];                // reference diagonal of the drop test
   const size_t off = (size_t)blockIdx.x * na * na;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  // every product below splits its sum four ways: wave wv takes the terms [l0, l1) (or j = wv mod 4) and the
-  // partial sums are added through red
-  const int l0 = wv * (SMALL_NA / 4), l1 = min(na, l0 + SMALL_NA / 4);
-  for (int i = t; i < na * na; i += blockDim.x) G[i] = Gg[off + i];
+  const int t = threadIdx.x, j = t & 63, wv = t >> 6;
+  for (int idx = t; idx < na * na; idx += blockDim.x) {
+    const int i = idx / na, c = idx - i * na;
+    S[i * SMALL_NA + c] = Gg[off + idx];
+    E[i * ES + c] = Cx<double>{i == c ? 1.0 : 0.0, 0.0};
+  }
+  if (t < na) g0[t] = (gref ? gref : Gg)[off + (size_t)t * na + t].re;
   __syncthreads();
   int nkept = 0;
   for (int k = 0; k < na; ++k) {
-    if (t < na) x[t] = Cx<double>{t == k ? 1.0 : 0.0, 0.0};
-    __syncthreads();
-    for (int pass = 0; pass < 3; ++pass) {
-      if (lane < na) {  // w = G x (G[l][i] = conj G[i][l])
-        Cx<double> acc = czero<double>();
-        for (int l = l0; l < l1; ++l) acc = acc + cmul_conj(G[l * na + lane], x[l]);
-        red[wv][lane] = acc;
-      }
-      __syncthreads();
-      if (t < na) w[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-      __syncthreads();
-      if (pass == 2) break;
-      if (lane < k) {  // cf_j = X[:, j]^H w
-        Cx<double> acc = czero<double>();
-        for (int l = l0; l < l1; ++l) acc = acc + cmul_conj(Xc[lane * XS + l], w[l]);
-        red[wv][lane] = acc;
-      }
-      __syncthreads();
-      if (t < k) cf[t] = red[0][t] + red[1][t] + red[2][t] + red[3][t];
-      __syncthreads();
-      if (lane < na) {  // x -= X[:, :k] cf
-        Cx<double> acc = czero<double>();
-        for (int j = wv; j < k; j += 4) acc = acc + Xc[j * XS + lane] * cf[j];
-        red[wv][lane] = acc;
-      }
-      __syncthreads();
-      if (t < na) x[t] = x[t] - (red[0][t] + red[1][t] + red[2][t] + red[3][t]);
-      __syncthreads();
-    }
-    if (wv == 0) {  // nrm2 = x^H G x = x^H w
-      const double v = lane < na ? x[lane].re * w[lane].re + x[lane].im * w[lane].im : 0.0;
-      const double sum = wave_sum(v);
-      if (lane == 0) nrm_s = sum;
-    }
-    __syncthreads();
-    const double nrm2 = nrm_s, gkk = gref ? gref[off + (size_t)k * na + k].re : G[k * na + k].re;
-    const bool keep = gkk > 1e-300 && nrm2 > drop_tol * gkk;
-    const double sc = keep ? 1.0 / sqrt(nrm2) : 0.0;
-    if (t < na) Xc[k * XS + t] = sc * x[t];
+    // pivot: d = remaining G-norm^2 of column k (every thread takes the same decision)
+    const double d = S[k * SMALL_NA + k].re, g = g0[k];
+    const bool keep = g > 1e-300 && d > drop_tol * g;
     nkept += keep ? 1 : 0;
+    if (wv == 0 && j < na) {
+      const double sc = keep ? 1.0 / sqrt(d) : 0.0;
+      if (j > k) S[k * SMALL_NA + j] = sc * S[k * SMALL_NA + j];
+      else E[k * ES + j] = sc * E[k * ES + j];
+    }
+    __syncthreads();
+    if (keep && j < na) {
+      // lane j's entry of row k: R_kj in the left block (j > k), E_kj in the right one (j <= k)
+      const Cx<double> rk = j > k ? S[k * SMALL_NA + j] : E[k * ES + j];
+      for (int i = k + 1 + wv; i < na; i += 4) {
+        const Cx<double> c = S[k * SMALL_NA + i];
+        const Cx<double> cc{c.re, -c.im};
+        if (j >= i) S[i * SMALL_NA + j] = S[i * SMALL_NA + j] - cc * rk;
+        else if (j <= k) E[i * ES + j] = E[i * ES + j] - cc * rk;
+      }
+    }
     __syncthreads();
   }
   for (int idx = t; idx < na * na; idx += blockDim.x) {
-    const int i = idx / na, j = idx % na;
-    Xg[off + idx] = Xc[j * XS + i];
+    const int i = idx / na, c = idx - i * na;
+    const Cx<double> e = E[c * ES + i];
+    Xg[off + idx] = Cx<double>{e.re, -e.im};
   }
   if (t == 0) kept[blockIdx.x] = nkept;
 }
