@@ -591,7 +591,7 @@ template <typename W>
 int block_inverse(Cx<W>* M, size_t ld, size_t st, int cnt, size_t o, int m, int depth, Cx<W>* tbase,
                   const std::vector<size_t>& toff, int* flags, hipStream_t s) {
   if (m <= 64) {
-    LSOP_HIP(prof("block_inv_base", fn_name("k_lu_inverse_lds", tname<W>()), 3.0 * m * m * (double)sizeof(Cx<W>) * cnt,
+    LSOP_HIP(prof("block_inv_base", fn_name("k_lu_inverse_lds", tname<W>()), 2.0 * m * m * (double)sizeof(Cx<W>) * cnt,
                   8.0 * m * m * (double)m * cnt, cnt, s, [&] {
       if constexpr (std::is_same<W, double>::value)
         return launch_lu_inverse(M + o, ld, st, M + o, ld, st, nullptr, m, true, flags, cnt, s);

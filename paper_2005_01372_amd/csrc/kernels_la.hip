@@ -484,39 +484,41 @@ __device__ __forceinline__ void block_argmax(double v, int i, double* red, int* 
   __syncthreads();
 }
 
-// Inverse by Gauss-Jordan with partial pivoting on work = [B | I] (row stride
-// wld >= 2 na), where B = I - M (plain = 0, eq. 12) or B = M (plain = 1).  M
-// has leading dimension ldm, Z ldz (Z may alias M).  *singular is set to 1 on
-// a vanishing pivot (never cleared here, so one flag can collect several
-// calls).  T = double (pivot threshold 1e-14 of the largest entry) or float (1e-6).
+// Inverse by in-place Gauss-Jordan with partial pivoting of B = I - M (plain =
+// 0, eq. 12) or B = M (plain = 1), held in work (row stride wld >= na).  Step k
+// swaps the pivot row into place, scales it by 1 / pivot with the pivot slot
+// set to 1 / pivot, and eliminates column k from every other row with the
+// slot set to -(its entry) / pivot: column k of the array then holds column k
+// of the inverse of the row-permuted matrix.  The row swaps are undone at the
+// end as column swaps in reverse order (inv(P B) P = inv(B)).  M has leading
+// dimension ldm, Z ldz (Z may alias M).  *singular is set to 1 on a vanishing
+// pivot (never cleared here, so one flag can collect several calls).  fcol:
+// na entries, perm: 2 na entries of shared memory.  T = double (pivot
+// threshold 1e-14 of the largest entry) or float (1e-6).
 template <typename T>
 __device__ __forceinline__ void lu_inverse_body(const Cx<T>* M, size_t ldm, Cx<T>* Z, size_t ldz, Cx<T>* work,
-                                                int wld, int na, int plain, int* singular, Cx<T>* fcol, double* red,
-                                                int* redi) {
+                                                int wld, int na, int plain, int* singular, Cx<T>* fcol, int* perm,
+                                                double* red, int* redi) {
   const double tiny = sizeof(T) == sizeof(double) ? 1e-14 : 1e-6;
-  const int t = threadIdx.x, w2 = 2 * na;
+  const int t = threadIdx.x, nt = blockDim.x;
   double amax = 0.0;
-  for (int idx = t; idx < na * w2; idx += blockDim.x) {
-    const int i = idx / w2, j = idx % w2;
-    Cx<T> v;
-    if (j < na) {
-      const Cx<T> m = M[(size_t)i * ldm + j];
-      v = plain ? m : Cx<T>{(i == j ? T(1) : T(0)) - m.re, -m.im};
-    } else {
-      v = Cx<T>{(i == j - na) ? T(1) : T(0), T(0)};
-    }
+  for (int idx = t; idx < na * na; idx += nt) {
+    const int i = idx / na, j = idx - i * na;
+    const Cx<T> m = M[(size_t)i * ldm + j];
+    const Cx<T> v = plain ? m : Cx<T>{(i == j ? T(1) : T(0)) - m.re, -m.im};
     work[(size_t)i * wld + j] = v;
-    if (j < na) amax = fmax(amax, sqrt((double)norm2(v)));
+    amax = fmax(amax, sqrt((double)norm2(v)));
   }
   double scale;
   int dummy;
   block_argmax(amax, 0, red, redi, &scale, &dummy);
-  // elimination layout: thread t owns column uj = t % w2 of rows ui0, ui0 + urs, ... (no division in the loop)
-  const int urs = (int)blockDim.x / w2, uj = t % w2, ui0 = t / w2;
+  // elimination layout: thread t owns column uj = t % na of rows ui0, ui0 + urs, ... (no division in the loop);
+  // urs = 0 (na > nt) falls back to a loop over columns
+  const int urs = nt / na, uj = t % na, ui0 = t / na;
   for (int k = 0; k < na; ++k) {
     double bv = -1.0;
     int bi = k;
-    for (int i = k + t; i < na; i += blockDim.x) {
+    for (int i = k + t; i < na; i += nt) {
       const double v = (double)norm2(work[(size_t)i * wld + k]);
       if (v > bv) {
         bv = v;
@@ -530,8 +532,9 @@ __device__ __forceinline__ void lu_inverse_body(const Cx<T>* M, size_t ldm, Cx<T
       if (t == 0) *singular = 1;
       return;  // uniform across the workgroup
     }
+    if (t == 0) perm[k] = p;
     if (p != k) {
-      for (int j = t; j < w2; j += blockDim.x) {
+      for (int j = t; j < na; j += nt) {
         const Cx<T> a = work[(size_t)k * wld + j];
         work[(size_t)k * wld + j] = work[(size_t)p * wld + j];
         work[(size_t)p * wld + j] = a;
@@ -542,50 +545,73 @@ __device__ __forceinline__ void lu_inverse_body(const Cx<T>* M, size_t ldm, Cx<T
     const T d = T(1) / norm2(pv);
     const Cx<T> inv = Cx<T>{pv.re * d, -pv.im * d};
     __syncthreads();
-    for (int j = t; j < w2; j += blockDim.x) work[(size_t)k * wld + j] = work[(size_t)k * wld + j] * inv;
-    for (int i = t; i < na; i += blockDim.x) fcol[i] = work[(size_t)i * wld + k];
+    for (int j = t; j < na; j += nt)
+      work[(size_t)k * wld + j] = (j == k ? Cx<T>{T(1), T(0)} : work[(size_t)k * wld + j]) * inv;
+    for (int i = t; i < na; i += nt) fcol[i] = work[(size_t)i * wld + k];
     __syncthreads();
-    // rank-1 elimination; left-block columns before k are zero in the pivot row and are skipped
-    if (ui0 < urs && (uj >= na || uj >= k)) {
-      const Cx<T> pr = work[(size_t)k * wld + uj];
-      for (int i = ui0; i < na; i += urs)
-        if (i != k) work[(size_t)i * wld + uj] = work[(size_t)i * wld + uj] - fcol[i] * pr;
+    if (urs > 0) {
+      if (ui0 < urs) {
+        const Cx<T> pr = work[(size_t)k * wld + uj];
+        for (int i = ui0; i < na; i += urs)
+          if (i != k)
+            work[(size_t)i * wld + uj] = (uj == k ? czero<T>() : work[(size_t)i * wld + uj]) - fcol[i] * pr;
+      }
+    } else {
+      for (int j = t; j < na; j += nt) {
+        const Cx<T> pr = work[(size_t)k * wld + j];
+        for (int i = 0; i < na; ++i)
+          if (i != k) work[(size_t)i * wld + j] = (j == k ? czero<T>() : work[(size_t)i * wld + j]) - fcol[i] * pr;
+      }
     }
     __syncthreads();
   }
-  for (int idx = t; idx < na * na; idx += blockDim.x) {
-    const int i = idx / na, j = idx % na;
-    Z[(size_t)i * ldz + j] = work[(size_t)i * wld + na + j];
+  // column of the array that lands at column j of the inverse: the row swaps replayed backwards as column swaps
+  int* pos = perm + na;
+  if (t == 0) {
+    for (int j = 0; j < na; ++j) pos[j] = j;
+    for (int k = na - 1; k >= 0; --k) {
+      const int q = perm[k], a = pos[k];
+      pos[k] = pos[q];
+      pos[q] = a;
+    }
+  }
+  __syncthreads();
+  for (int idx = t; idx < na * na; idx += nt) {
+    const int i = idx / na, j = idx - i * na;
+    Z[(size_t)i * ldz + j] = work[(size_t)i * wld + pos[j]];
   }
 }
 
 // Batch entry b = blockIdx.x: M + b * sm, Z + b * sz, singular[b].  The LDS
 // work rows have an odd stride (conflict-free column reads).
-constexpr int LU_WLD = 2 * SMALL_NA + 1;
+constexpr int LU_WLD = SMALL_NA + 1;
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_inverse_lds(const Cx<T>* __restrict__ M, size_t ldm, size_t sm, Cx<T>* Z,
                                                          size_t ldz, size_t sz, int na, int plain, int* singular) {
   __shared__ Cx<T> work[SMALL_NA * LU_WLD];
   __shared__ Cx<T> fcol[SMALL_NA];
+  __shared__ int perm[2 * SMALL_NA];
   __shared__ double red[4];
   __shared__ int redi[4];
   const size_t b = blockIdx.x;
-  lu_inverse_body<T>(M + b * sm, ldm, Z + b * sz, ldz, work, LU_WLD, na, plain, singular + b, fcol, red, redi);
+  lu_inverse_body<T>(M + b * sm, ldm, Z + b * sz, ldz, work, LU_WLD, na, plain, singular + b, fcol, perm, red, redi);
 }
 
+// larger na: the work array in global memory (2 na^2 entries per batch entry, row stride 2 na); fcol and the
+// permutation in dynamic shared memory (na complex + 2 na ints)
 __global__ __launch_bounds__(256) void k_lu_inverse_i_minus(const Cx<double>* __restrict__ M, size_t ldm, size_t sm,
                                                              Cx<double>* Z, size_t ldz, size_t sz,
                                                              Cx<double>* __restrict__ work, int na, int plain,
                                                              int* singular) {
   extern __shared__ unsigned char smem_raw[];
-  Cx<double>* fcol = reinterpret_cast<Cx<double>*>(smem_raw);  // [na]
+  Cx<double>* fcol = reinterpret_cast<Cx<double>*>(smem_raw);   // [na]
+  int* perm = reinterpret_cast<int*>(fcol + na);                 // [2 na]
   __shared__ double red[4];
   __shared__ int redi[4];
   const size_t b = blockIdx.x;
   lu_inverse_body<double>(M + b * sm, ldm, Z + b * sz, ldz, work + b * 2 * (size_t)na * na, 2 * na, na, plain,
-                          singular + b,
-                  fcol, red, redi);
+                          singular + b, fcol, perm, red, redi);
 }
 
 // C_b = alpha * A_b (na x na) B_b (na x nb); batch entry b = blockIdx.y.
@@ -913,8 +939,8 @@ hipError_t launch_lu_inverse(const Cx<double>* M, size_t ldm, size_t sm, Cx<doub
     hipLaunchKernelGGL(k_lu_inverse_lds<double>, dim3(batch), dim3(256), 0, s, M, ldm, sm, Z, ldz, sz, na,
                        (int)plain, singular);
   else
-    hipLaunchKernelGGL(k_lu_inverse_i_minus, dim3(batch), dim3(256), sizeof(Cx<double>) * na, s, M, ldm, sm, Z, ldz,
-                       sz, work, na, (int)plain, singular);
+    hipLaunchKernelGGL(k_lu_inverse_i_minus, dim3(batch), dim3(256), (sizeof(Cx<double>) + 2 * sizeof(int)) * na, s,
+                       M, ldm, sm, Z, ldz, sz, work, na, (int)plain, singular);
   return hipGetLastError();
 }
 

@@ -45,6 +45,23 @@ def test_precond_apply_matches_oracle(dtype, q, tol):
     assert rel(host(pc.apply(dev(x, tdt))), H.apply(x)) <= tol
 
 
+def test_precond_rank_above_128_matches_oracle():
+    """Z = (I - W^H U)^{-1} of more than 128 probes takes the pivoted Gauss-Jordan in global memory, whose
+    thread layout (one column per thread, fewer threads than 2 * rank) differs from the small-block kernel."""
+    announce("precond apply rank 160")
+    w = cfg1(48)
+    prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+    r = 160
+    om = synth.gaussian_probes(prob.n, r, 7)
+    H = O.LowRankPreconditioner.build(prob, om.reshape(r, 48, 48))
+    op = make_op(w, lsop.C128, 4)
+    pc = lsop.Preconditioner(op, lsop.PC_LOWRANK, rank=r)
+    pc.build(torch.as_tensor(om).cuda())
+    assert pc.info()[0] == r
+    x = synth.random_vectors((3, 48, 48), 4)
+    assert rel(host(pc.apply(dev(x))), H.apply(x)) <= 1e-10
+
+
 def test_device_philox_probes_match_oracle():
     """A preconditioner drawn on the device (Philox4x32-10 + Box-Muller) equals one built from the oracle's draw."""
     announce("philox")
