@@ -701,8 +701,21 @@ int hodlr_apply(lsop_precond* pc, const Cx<T>* x, const int* xidx, Cx<T>* y, con
       const Cx<T>* V = reinterpret_cast<const Cx<T>*>(L.V);
       const Cx<T>* Wp = reinterpret_cast<const Cx<T>*>(L.Wp);
       LSOP_HIP(p_ah_b<T>("hodlr_apply_ah_b", V, r, yb, yc, m, n, seg, pc->hG, pc->part, ksub, s, 1.0, pc->part_cap));
-      LSOP_HIP(p_bgemm<double>("hodlr_core_apply", L.kinv, 2 * r, (size_t)4 * r * r, pc->hG, m, (size_t)2 * r * m,
-                               pc->hX, m, (size_t)2 * r * m, nullptr, nullptr, 2 * r, m, 2 * r, 1.0, 0.0, nodes, s));
+      if constexpr (std::is_same<T, float>::value) {
+        // the update rounds the core's output to FP32 anyway: the core product runs on the fp32 matrix cores
+        // (K^{-1} inverted in FP64, applied from its FP32 copy)
+        const size_t cnt = (size_t)nseg * r * m;
+        LSOP_HIP(prof("hodlr_core_apply", "k_convert<float, double>", cnt * 24.0, 0.0, (double)cnt, s,
+                      [&] { return launch_convert<float, double>(pc->hG, pc->hG32, cnt, s); }));
+        LSOP_HIP(p_bgemm<float>("hodlr_core_apply", L.kinv32, 2 * r, (size_t)4 * r * r, pc->hG32, m,
+                                (size_t)2 * r * m, pc->hX32, m, (size_t)2 * r * m, nullptr, nullptr, 2 * r, m, 2 * r,
+                                1.0, 0.0, nodes, s));
+        LSOP_HIP(prof("hodlr_core_apply", "k_convert<double, float>", cnt * 24.0, 0.0, (double)cnt, s,
+                      [&] { return launch_convert<double, float>(pc->hX32, pc->hX, cnt, s); }));
+      } else {
+        LSOP_HIP(p_bgemm<double>("hodlr_core_apply", L.kinv, 2 * r, (size_t)4 * r * r, pc->hG, m, (size_t)2 * r * m,
+                                 pc->hX, m, (size_t)2 * r * m, nullptr, nullptr, 2 * r, m, 2 * r, 1.0, 0.0, nodes, s));
+      }
       LSOP_HIP(p_update<T>("hodlr_apply_update", Wp, r, pc->hX, (size_t)r * m, m, yb, nullptr, 0.0, yb, yc, n, seg, s));
     }
   }
@@ -767,6 +780,7 @@ int hodlr_core_inverse(lsop_precond* pc, int lv, hipStream_t s) {
   LSOP_HIP(launch_set_identity(B01, ld, st, r, nodes, s));
   LSOP_HIP(gemm(B00, ld, st, G0, r, 2 * r2, B01, ld, st, 1.0, 1.0));       // I + G1 S^{-1} G0
   LSOP_HIP(gemm(B10, ld, st, G0, r, 2 * r2, B11, ld, st, 1.0, 0.0));       // S^{-1} G0
+  if (L.kinv32) LSOP_HIP(launch_convert<float, double>(K, L.kinv32, (size_t)nodes * st, s));
   return LSOP_OK;
 }
 
@@ -1520,6 +1534,10 @@ int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out
     const size_t small = (size_t)pc->maxseg * r * pc->tcap;
     st |= dev_alloc(o, b, &pc->hG, sizeof(Cx<double>) * small);
     st |= dev_alloc(o, b, &pc->hX, sizeof(Cx<double>) * small);
+    if (pc->dt == LSOP_C64) {
+      st |= dev_alloc(o, b, &pc->hG32, sizeof(Cx<float>) * small);
+      st |= dev_alloc(o, b, &pc->hX32, sizeof(Cx<float>) * small);
+    }
     // node cores: recursion temporaries (< r^2 per node), S S^{-1} (r^2 per node), pivoted fallback work (2 r^2)
     st |= dev_alloc(o, b, &pc->hK, sizeof(Cx<double>) * ((size_t)(pc->maxseg / 2) * 3 * r * r + 2 * (size_t)r * r));
     pc->part_cap = (size_t)pc->ksub_cap * r * pc->tcap;
@@ -1538,6 +1556,7 @@ int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out
       st |= dev_alloc(o, b, &L.V, esz * r * n);
       st |= dev_alloc(o, b, &L.Wp, esz * r * n);
       st |= dev_alloc(o, b, &L.kinv, sizeof(Cx<double>) * (size_t)nodes * 4 * r * r);
+      if (pc->dt == LSOP_C64) st |= dev_alloc(o, b, &L.kinv32, sizeof(Cx<float>) * (size_t)nodes * 4 * r * r);
       const size_t gsz = (size_t)2 * op->pz() * L.lx;
       if (pc->dt == LSOP_C128) st |= dev_alloc(o, b, &L.gs64, sizeof(Cx<double>) * gsz);
       else st |= dev_alloc(o, b, &L.gs32, sizeof(Cx<float>) * gsz);

@@ -218,6 +218,7 @@ struct hodlr_level {
   void* V = nullptr;                      // [rank][n] packed right factors (per half-node)
   void* Wp = nullptr;                     // [rank][n] A_{l+1}^{-1} U, packed
   Cx<double>* kinv = nullptr;             // [nodes][2 rank][2 rank] (P K)^{-1}
+  Cx<float>* kinv32 = nullptr;            // its FP32 copy (complex-FP32 preconditioners apply the cores in FP32)
   Cx<double>* gs64 = nullptr;             // sub-domain spectrum [2][pz][lx]
   Cx<float>* gs32 = nullptr;
   Cx<double>* tw64 = nullptr;             // x twiddles w_{2 lx}
@@ -235,6 +236,7 @@ struct lsop_precond {
   size_t lwork_elems = 0;
   void* hy = nullptr;                     // [tcap][n] apply / series temporary
   Cx<double>*hG = nullptr, *hX = nullptr;  // per-segment products [maxseg][rank][tcap]
+  Cx<float>*hG32 = nullptr, *hX32 = nullptr;  // their FP32 copies around the FP32 core apply
   Cx<double>* hK = nullptr;               // node-core recursion temporaries and Gauss-Jordan work
   int* hflag = nullptr;                   // per-node / per-segment flags
   int maxseg = 0, ksub_cap = 0;
