@@ -143,7 +143,8 @@ const char* lsop_last_error(void);
  *                    recompression); the leaves by the recursive 2 x 2 block
  *                    formula, in FP32 for complex-FP32 operators (including
  *                    the mixed mode) and FP64 for complex-FP64 ones; the node
- *                    cores always in FP64.  Requires nx divisible by 2^levels,
+ *                    cores always inverted in FP64 and applied in the
+ *                    operator's precision.  Requires nx divisible by 2^levels,
  *                    (nx / 2^levels) * nz a multiple of 64 and at most 8192.
  * ---------------------------------------------------------------------- */
 typedef enum { LSOP_PC_IDENTITY = 0, LSOP_PC_LOWRANK = 1, LSOP_PC_HODLR = 2 } lsop_pc_kind;
