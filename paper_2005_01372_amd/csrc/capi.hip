@@ -1097,17 +1097,61 @@ int batch_iteration(lsop_batch* b, lsop_precond* const* pcs, Cx<T>* const* psi, 
     const auto& G = b->groups[g];
     LSOP_HIP(launch_mask_slots<T>(tab + goff[g], live + goff[g], ns, (size_t)G.nx * G.nz, s));
   }
+  // psi_i <- psi_i - H_i r_i: independent per instance (each preconditioner has its own scratch), so the
+  // instances are spread over the side streams, which fork from and join back into s (also under capture,
+  // where they become parallel branches of the graph)
+  const int K = b->active_side;
+  if (K > 0) {
+    LSOP_HIP(hipEventRecord(b->ev[0], s));
+    for (int k = 0; k < K; ++k) LSOP_HIP(hipStreamWaitEvent(b->side[k], b->ev[0], 0));
+  }
+  int j = 0;
   for (int i = 0; i < b->count; ++i) {
     if (nvec[i] == 0) continue;
+    hipStream_t si = K > 0 ? b->side[j++ % K] : s;
     if (pcs && pcs[i] && pcs[i]->kind != LSOP_PC_IDENTITY) {
-      int st = pc_apply_impl<T>(pcs[i], r[i], psi[i], nullptr, nvec[i], true, s);
+      int st = pc_apply_impl<T>(pcs[i], r[i], psi[i], nullptr, nvec[i], true, si);
       if (st) return st;
     } else {
-      LSOP_HIP(launch_axpby<T>(r[i], psi[i], -1.0, 1.0, nullptr, nvec[i], b->ops[i]->n(), s));
+      LSOP_HIP(launch_axpby<T>(r[i], psi[i], -1.0, 1.0, nullptr, nvec[i], b->ops[i]->n(), si));
     }
+  }
+  for (int k = 0; k < K; ++k) {
+    LSOP_HIP(hipEventRecord(b->ev[1 + k], b->side[k]));
+    LSOP_HIP(hipStreamWaitEvent(s, b->ev[1 + k], 0));
   }
   LSOP_HIP(launch_zero_f64(rn, nslots, s));
   return batch_passes<T>(b, LSOP_MODE_A, goff, true, s);
+}
+
+// Side streams for the per-instance applies of the series: up to kSeriesStreams, none when fewer than two
+// instances apply a preconditioner or when one preconditioner serves two instances (their applies would
+// share its scratch).
+constexpr int kSeriesStreams = 8;
+int batch_side_streams(lsop_batch* b, lsop_precond* const* pcs, const int* nvec) {
+  int busy = 0;
+  std::vector<const lsop_precond*> seen;
+  for (int i = 0; i < b->count; ++i) {
+    if (nvec[i] == 0) continue;
+    ++busy;
+    if (pcs && pcs[i] && pcs[i]->kind != LSOP_PC_IDENTITY) {
+      if (std::find(seen.begin(), seen.end(), pcs[i]) != seen.end()) busy = -b->count;
+      seen.push_back(pcs[i]);
+    }
+  }
+  const int want = busy >= 2 ? std::min(busy, kSeriesStreams) : 0;
+  while ((int)b->side.size() < want) {
+    hipStream_t st = nullptr;
+    LSOP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    b->side.push_back(st);
+  }
+  while ((int)b->ev.size() < 1 + (int)b->side.size()) {
+    hipEvent_t e = nullptr;
+    LSOP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    b->ev.push_back(e);
+  }
+  b->active_side = want;  // streams created for an earlier, larger series stay for later calls
+  return LSOP_OK;
 }
 
 template <typename T>
@@ -1157,6 +1201,7 @@ int batch_series(lsop_batch* b, lsop_precond* const* pcs, const Cx<T>* const* rh
   std::vector<int> goff, slot_of;
   batch_slots<T>(b, reinterpret_cast<const Cx<T>* const*>(psi), r.data(), rhs, rn, nvec, goff, slot_of);
   if ((st = batch_prepare<T>(b, goff, s))) return st;
+  if ((st = batch_side_streams(b, pcs, nvec))) return st;
   // |rhs|^2 per slot and psi_0
   std::vector<double> b2(nslots), rh(nslots);
   std::vector<int> liveh(nslots, 1), rising(nslots, 0), done(nslots, 0);
@@ -1895,6 +1940,8 @@ void lsop_batch_destroy(lsop_batch* b) {
   if (b->tab) (void)hipFree(b->tab);
   if (b->tmp) (void)hipFree(b->tmp);
   if (b->work) (void)hipFree(b->work);
+  for (hipStream_t st : b->side) (void)hipStreamDestroy(st);
+  for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
   delete b;
 }
 

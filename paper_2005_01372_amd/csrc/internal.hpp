@@ -276,4 +276,9 @@ struct lsop_batch {
   size_t work_cap = 0;
   std::vector<unsigned char> host_tab;
   size_t bytes = 0;
+  // series: the per-instance preconditioner applies of an iteration run on these streams (forked from and
+  // joined back into the series stream with ev: ev[0] the fork, ev[1 + k] the join of side[k])
+  std::vector<hipStream_t> side;
+  std::vector<hipEvent_t> ev;
+  int active_side = 0;            // side streams used by the current series
 };
