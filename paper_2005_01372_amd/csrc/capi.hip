@@ -1206,19 +1206,30 @@ int batch_series(lsop_batch* b, lsop_precond* const* pcs, const Cx<T>* const* rh
   std::vector<double> b2(nslots), rh(nslots);
   std::vector<int> liveh(nslots, 1), rising(nslots, 0), done(nslots, 0);
   std::vector<double> prev(nslots, INFINITY);
-  for (int i = 0; i < cnt; ++i) {
+  // psi_0 = H rhs per instance, spread over the side streams as in the iterations
+  const int K = b->active_side;
+  if (K > 0) {
+    LSOP_HIP(hipEventRecord(b->ev[0], s));
+    for (int k = 0; k < K; ++k) LSOP_HIP(hipStreamWaitEvent(b->side[k], b->ev[0], 0));
+  }
+  for (int i = 0, j = 0; i < cnt; ++i) {
     if (nvec[i] == 0) continue;
     const size_t n = b->ops[i]->n();
-    LSOP_HIP(launch_norm2<T>(rhs[i], rn + slot_of[i], nullptr, nvec[i], n, s));
+    hipStream_t si = K > 0 ? b->side[j++ % K] : s;
+    LSOP_HIP(launch_norm2<T>(rhs[i], rn + slot_of[i], nullptr, nvec[i], n, si));
     if (p->init == LSOP_INIT_H_RHS) {
       if (pcs && pcs[i] && pcs[i]->kind != LSOP_PC_IDENTITY) {
-        if ((st = pc_apply_impl<T>(pcs[i], rhs[i], psi[i], nullptr, nvec[i], false, s))) return st;
+        if ((st = pc_apply_impl<T>(pcs[i], rhs[i], psi[i], nullptr, nvec[i], false, si))) return st;
       } else {
-        LSOP_HIP(launch_axpby<T>(rhs[i], psi[i], 1.0, 0.0, nullptr, nvec[i], n, s));
+        LSOP_HIP(launch_axpby<T>(rhs[i], psi[i], 1.0, 0.0, nullptr, nvec[i], n, si));
       }
     } else if (p->init == LSOP_INIT_ZERO) {
-      LSOP_HIP(launch_axpby<T>(rhs[i], psi[i], 0.0, 0.0, nullptr, nvec[i], n, s));
+      LSOP_HIP(launch_axpby<T>(rhs[i], psi[i], 0.0, 0.0, nullptr, nvec[i], n, si));
     }
+  }
+  for (int k = 0; k < K; ++k) {
+    LSOP_HIP(hipEventRecord(b->ev[1 + k], b->side[k]));
+    LSOP_HIP(hipStreamWaitEvent(s, b->ev[1 + k], 0));
   }
   LSOP_HIP(hipMemcpyAsync(b2.data(), rn, sizeof(double) * nslots, hipMemcpyDeviceToHost, s));
   LSOP_HIP(hipStreamSynchronize(s));
