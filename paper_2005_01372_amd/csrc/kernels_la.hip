@@ -197,6 +197,18 @@ constexpr int GM_T = 64, GM_K = 16;
 // [x total / 8, (x + 1) total / 8) (a bijection when total % 8 == 0; identity
 // otherwise).  Workgroups that share operands (one segment's tiles) then
 // share an L2.
+// four reals as one vector (16 bytes for float; the FP64 instantiations never take the vector path)
+template <typename T>
+struct Vec4 {
+  using type = float4;
+};
+template <>
+struct Vec4<double> {
+  struct type {
+    double x, y, z, w;
+  };
+};
+
 __device__ __forceinline__ unsigned xcd_block(unsigned id, unsigned total) {
   return (total % 8u) ? id : (id % 8u) * (total / 8u) + id / 8u;
 }
@@ -236,15 +248,33 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
   const int vb = b0 + lr;
   const Cx<T>* brow = (vb < nb) ? B + (size_t)(vidx ? vidx[vb] : vb) * n : nullptr;
   const int kk = l >> 4, c16 = l & 15;
-  // the next stage's operands are loaded into registers while the current stage's MFMAs run
+  // the next stage's operands are loaded into registers while the current stage's MFMAs run; complex FP32
+  // runs of 4 in range are loaded 16 bytes at a time (aligned when A and B are 16-byte aligned and n and
+  // k_begin are even, since then row * n + k is even for every row and stage)
   Cx<T> va[4], vb2[4];
+  const bool vec = sizeof(T) == 4 && ((n | k_begin) & 1) == 0 &&
+                   ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15) == 0;
   auto load = [&](size_t kb) {
+    const size_t k0 = kb + lk;
+    if (vec && k0 + 4 <= k_end) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const size_t k = kb + lk + q;
-      const bool kin = k < k_end;
-      va[q] = (arow && kin) ? arow[k] : czero<T>();
-      vb2[q] = (brow && kin) ? brow[k] : czero<T>();
+      for (int h = 0; h < 2; ++h) {
+        using V = typename Vec4<T>::type;
+        const V x = arow ? *reinterpret_cast<const V*>(arow + k0 + 2 * h) : V{0, 0, 0, 0};
+        const V y = brow ? *reinterpret_cast<const V*>(brow + k0 + 2 * h) : V{0, 0, 0, 0};
+        va[2 * h] = Cx<T>{x.x, x.y};
+        va[2 * h + 1] = Cx<T>{x.z, x.w};
+        vb2[2 * h] = Cx<T>{y.x, y.y};
+        vb2[2 * h + 1] = Cx<T>{y.z, y.w};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const size_t k = k0 + q;
+        const bool kin = k < k_end;
+        va[q] = (arow && kin) ? arow[k] : czero<T>();
+        vb2[q] = (brow && kin) ? brow[k] : czero<T>();
+      }
     }
   };
   load(k_begin);
@@ -734,15 +764,38 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
   if (m0 + ar < M) arow = A + bt * sA + (size_t)(mapa ? mapa[m0 + ar] : m0 + ar) * lda;
   const Cx<T>* bbase = B + bt * sB;
   const int kk = l >> 4, c16 = l & 15;
-  // the next stage's operands are loaded into registers while the current stage's MFMAs run
+  // the next stage's operands are loaded into registers while the current stage's MFMAs run; complex FP32
+  // runs of 4 (k of an A row, n of a B row) are loaded 16 bytes at a time when the entry's base is 16-byte
+  // aligned and its row stride even (every run then starts at an even element)
   Cx<T> va[4], vb[4];
+  using V = typename Vec4<T>::type;
+  const bool veca = sizeof(T) == 4 && (lda & 1) == 0 && (reinterpret_cast<uintptr_t>(A + bt * sA) & 15) == 0;
+  const bool vecb = sizeof(T) == 4 && (ldb & 1) == 0 && (reinterpret_cast<uintptr_t>(bbase) & 15) == 0;
   auto load = [&](int kb) {
+    const int k0 = kb + ak, kb2 = kb + bk, nn0 = n0 + bn;
+    if (veca && k0 + 4 <= K) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = kb + ak + q;
-      va[q] = (arow && k < K) ? arow[k] : czero<T>();
-      const int kb2 = kb + bk, nn = n0 + bn + q;
-      vb[q] = (kb2 < K && nn < N) ? bbase[(size_t)kb2 * ldb + nn] : czero<T>();
+      for (int h = 0; h < 2; ++h) {
+        const V x = arow ? *reinterpret_cast<const V*>(arow + k0 + 2 * h) : V{0, 0, 0, 0};
+        va[2 * h] = Cx<T>{x.x, x.y};
+        va[2 * h + 1] = Cx<T>{x.z, x.w};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) va[q] = (arow && k0 + q < K) ? arow[k0 + q] : czero<T>();
+    }
+    if (vecb && kb2 < K && nn0 + 4 <= N) {
+      const Cx<T>* bp = bbase + (size_t)kb2 * ldb + nn0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const V y = *reinterpret_cast<const V*>(bp + 2 * h);
+        vb[2 * h] = Cx<T>{y.x, y.y};
+        vb[2 * h + 1] = Cx<T>{y.z, y.w};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        vb[q] = (kb2 < K && nn0 + q < N) ? bbase[(size_t)kb2 * ldb + nn0 + q] : czero<T>();
     }
   };
   load(0);
