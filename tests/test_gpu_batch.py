@@ -112,6 +112,37 @@ def test_batch_graph_equals_eager_twice_fp32():
             assert rel(host(pg[t]), host(pe[t])) <= 1e-6
 
 
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_repeated_operator_shares_its_preconditioner(use_graph):
+    """One operator and its preconditioner serve two instances (other sources): their applies share the
+    preconditioner's scratch, so the series keeps them on one stream; every instance still equals its own
+    series and the dense-LU solution."""
+    announce(f"batch repeated operator graph={use_graph}")
+    ws = instances()[:2]
+    ops2 = [make_op(w, lsop.C128, 4) for w in ws]
+    pc2 = preconditioners(ops2, ["hodlr", "lowrank"])
+    w0 = ws[0]
+    other_i = np.array([3, w0.nx - 4], np.int32)
+    other_j = np.array([w0.nz // 2, 1], np.int32)
+    ops = [ops2[0], ops2[1], ops2[0]]
+    pcs = [pc2[0], pc2[1], pc2[0]]
+    srcs = [(w0.src_i, w0.src_j), (ws[1].src_i, ws[1].src_j), (other_i, other_j)]
+    rhss = [op.incident(si, sj) for op, (si, sj) in zip(ops, srcs)]
+    b = lsop.Batch(ops)
+    psis, res = b.solve(pcs, rhss, tol=1e-13, max_iter=80, use_graph=use_graph)
+    for t, (op, pc) in enumerate(zip(ops, pcs)):
+        psi1, res1 = lsop.series_solve(op, pc, rhss[t], tol=1e-13, max_iter=80)
+        w = ws[0] if t != 1 else ws[1]
+        prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+        ref = O.solve_direct(prob, prob.incident(*srcs[t]))
+        got = host(psis[t])
+        for v in range(len(srcs[t][0])):
+            assert res[t][v].status == res1[v].status == lsop.OK, (t, v, res[t][v], res1[v])
+            assert res[t][v].iters == res1[v].iters
+            assert rel(got[v], host(psi1)[v]) <= 1e-12
+            assert rel(got[v], ref[v]) <= 1e-10
+
+
 def test_batch_freezes_finished_vectors_and_reports_failures():
     """A diverging instance (Born on strong contrast) does not disturb the others; its status is DIVERGED."""
     announce("batch failures")
