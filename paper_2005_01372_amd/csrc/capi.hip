@@ -1130,16 +1130,17 @@ int batch_iteration(lsop_batch* b, lsop_precond* const* pcs, Cx<T>* const* psi, 
 constexpr int kSeriesStreams = 8;
 int batch_side_streams(lsop_batch* b, lsop_precond* const* pcs, const int* nvec) {
   int busy = 0;
+  bool shared = false;
   std::vector<const lsop_precond*> seen;
   for (int i = 0; i < b->count; ++i) {
     if (nvec[i] == 0) continue;
     ++busy;
     if (pcs && pcs[i] && pcs[i]->kind != LSOP_PC_IDENTITY) {
-      if (std::find(seen.begin(), seen.end(), pcs[i]) != seen.end()) busy = -b->count;
+      shared = shared || std::find(seen.begin(), seen.end(), pcs[i]) != seen.end();
       seen.push_back(pcs[i]);
     }
   }
-  const int want = busy >= 2 ? std::min(busy, kSeriesStreams) : 0;
+  const int want = (!shared && busy >= 2) ? std::min(busy, kSeriesStreams) : 0;
   while ((int)b->side.size() < want) {
     hipStream_t st = nullptr;
     LSOP_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
