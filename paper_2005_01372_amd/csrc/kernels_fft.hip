@@ -180,12 +180,29 @@ __global__ __launch_bounds__(C * FftPlan<L>::G) void k_cols(Cx<T>* __restrict__ 
   const int slot = rem / PAIR;
   const int c0 = (grp_id * PAIR + rem % PAIR) * C;
   Cx<T>* tb = tmp + (size_t)slot * nx * pz + c0;
+  const int c = threadIdx.x / G, g = threadIdx.x % G;
+  const Cx<T>* gsl = tab ? tab[slot].gs : gs;
+  const Cx<T>* g0 = gsl + (size_t)(c0 + c) * L;
+  const Cx<T>* g1 = gsl + ((size_t)pz + c0 + c) * L;
+  // this group's spectrum values: loaded before the tile where that was measured faster (lengths up to 128,
+  // and 4-column tiles), so that their latency hides behind the tile load and the forward transform; the wider
+  // tiles of the long lengths load them between the transforms
+  constexpr bool early = L <= 128 || C <= 4;
+  Cx<T> s0[E], s1[E];
+  auto load_spectrum = [&] {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int p = fft_elem<L>(g, e);
+      s0[e] = g0[p];
+      s1[e] = g1[p];
+    }
+  };
+  if constexpr (early) load_spectrum();
   for (int idx = threadIdx.x; idx < L * C; idx += NT) {
-    const int i = idx / C, c = idx % C;
-    tile[c * ST + lds_pad(i)] = (i < nx) ? tb[(size_t)i * pz + c] : czero<T>();
+    const int i = idx / C, cc = idx % C;
+    tile[cc * ST + lds_pad(i)] = (i < nx) ? tb[(size_t)i * pz + cc] : czero<T>();
   }
   __syncthreads();
-  const int c = threadIdx.x / G, g = threadIdx.x % G;
   Cx<T>* col = tile + c * ST;
   // even (h = 0) and odd (h = 1) frequency halves along x
   Cx<T> ve[E], vo[E];
@@ -195,16 +212,12 @@ __global__ __launch_bounds__(C * FftPlan<L>::G) void k_cols(Cx<T>* __restrict__ 
     ve[e] = col[lds_pad(p)];
     vo[e] = ve[e] * tw_lo<T, L>(stw, p);
   }
-  const Cx<T>* gsl = tab ? tab[slot].gs : gs;
-  const Cx<T>* g0 = gsl + (size_t)(c0 + c) * L;
-  const Cx<T>* g1 = gsl + ((size_t)pz + c0 + c) * L;
   fft2_regs<T, L, false>(ve, vo, g, col, xbuf[c], stw);
+  if constexpr (!early) load_spectrum();
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int p = fft_elem<L>(g, e);
-    const Cx<T> s0 = g0[p], s1 = g1[p];
-    ve[e] = adj ? cmul_conj(s0, ve[e]) : s0 * ve[e];
-    vo[e] = adj ? cmul_conj(s1, vo[e]) : s1 * vo[e];
+    ve[e] = adj ? cmul_conj(s0[e], ve[e]) : s0[e] * ve[e];
+    vo[e] = adj ? cmul_conj(s1[e], vo[e]) : s1[e] * vo[e];
   }
   fft2_regs<T, L, true>(ve, vo, g, col, xbuf[c], stw);
   wave_sync();
