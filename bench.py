@@ -459,8 +459,8 @@ def main_unet(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in the design "
-                                   "notes but not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "lsop runs on one GPU: sharding the sources or the grid over several GPUs is "
+                                   "designed but not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
     if args.workload == "uneven":
         return main_uneven(args)
