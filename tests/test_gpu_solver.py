@@ -45,6 +45,23 @@ def test_precond_apply_matches_oracle(dtype, q, tol):
     assert rel(host(pc.apply(dev(x, tdt))), H.apply(x)) <= tol
 
 
+def test_precond_fp32_odd_cell_count_matches_oracle():
+    """45 x 45 = 2025 cells: the complex-FP32 products cannot take their 16-byte operand loads (odd row
+    length), so this covers their element-wise path; rank 72 spans two orthonormalisation blocks."""
+    announce("precond apply fp32 odd n")
+    w = cfg1(45)
+    prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+    r = 72
+    om = synth.gaussian_probes(prob.n, r, 11)
+    H = O.LowRankPreconditioner.build(prob, om.reshape(r, 45, 45))
+    op = make_op(w, lsop.C64, 4)
+    pc = lsop.Preconditioner(op, lsop.PC_LOWRANK, rank=r)
+    pc.build(torch.as_tensor(om).cuda())
+    assert pc.info()[0] == r
+    x = synth.random_vectors((3, 45, 45), 2)
+    assert rel(host(pc.apply(dev(x, torch.complex64))), H.apply(x)) <= 2e-5
+
+
 def test_precond_rank_above_128_matches_oracle():
     """Z = (I - W^H U)^{-1} of more than 128 probes takes the pivoted Gauss-Jordan in global memory, whose
     thread layout (one column per thread, fewer threads than 2 * rank) differs from the small-block kernel."""
