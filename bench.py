@@ -58,6 +58,17 @@ def parse():
     ap.add_argument("--n", type=int, default=1024, help="grid side (default: the 1024^2 workload)")
     ap.add_argument("--nsrc", type=int, default=128)
     ap.add_argument("--pc", choices=("hodlr", "lowrank"), default="hodlr")
+    ap.add_argument("--dtype", choices=("c64", "c128", "mixed"), default="c64",
+                    help="ls1024: complex FP32 series (c64), plain complex FP64 series (c128), or complex FP32 inner "
+                         "series with FP64 residuals and refinement (mixed)")
+    ap.add_argument("--no-fp64-compare", action="store_true",
+                    help="ls1024: skip the untimed plain FP64 series after the timed steps (the relative error of "
+                         "every timed solution against it, and its own solves/s on the same GPU)")
+    ap.add_argument("--init", choices=("h_rhs", "learned"), default="h_rhs",
+                    help="ls1024: series start H psi0 (the paper's), or the warm-start network's field, kept per "
+                         "source only where its true residual is smaller (the network is first trained, untimed, "
+                         "on --unet-models solver-generated layered + salt models at 128^2)")
+    ap.add_argument("--unet-train-steps", type=int, default=300, help="ls1024 --init learned: training steps")
     ap.add_argument("--rank", type=int, default=None, help="probes per block (default 256 hodlr, 64 lowrank)")
     ap.add_argument("--levels", type=int, default=10)
     ap.add_argument("--power-iters", type=int, default=None, help="default 1 hodlr, 0 lowrank")
@@ -75,6 +86,38 @@ def parse():
     if a.power_iters is None:
         a.power_iters = 1 if a.pc == "hodlr" else 0
     return a
+
+
+def measure_copy_gbps(nbytes=4 << 30, reps=5):
+    """Achievable HBM bandwidth on this GPU: a plain device-to-device copy of nbytes (read + write counted),
+    best of `reps`, timed with events on the current stream."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.complex64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / best / 1e9
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def load_traffic(kernel, summary="pmc_traffic.json"):
@@ -191,8 +234,8 @@ def cpu_baseline(w, args, iterations, converged, nsrc_sample=2):
     it_total = sum(i + 1 for i in iterations)            # residual evaluations, all sources
     h_total = sum(i + 1 for i in iterations)             # H applications (psi_0 = H psi0 plus one per update)
     step_s = t_setup + t_build + it_total * t_conv + h_total * t_h
-    return {"value": converged / step_s, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": desc + f"; scipy.fft workers={cores}",
+    return {"value": converged / step_s, "unit": "solves/s", "cores": cores, "cpu_model": cpu_model(),
+            "kind": "oracle", "sample": desc + f"; scipy.fft workers={cores}",
             "step_seconds_extrapolated": round(step_s, 2), "setup_s": round(t_setup, 2),
             "build_s_extrapolated": round(t_build, 2), "series_s_extrapolated": round(it_total * t_conv + h_total * t_h, 2)}
 
@@ -323,7 +366,8 @@ def unet_cpu_baseline(samples=1):
     _, dy = U.mse(y, t)
     net.backward(dy)
     dt = time.perf_counter() - t0
-    return {"value": round(samples / dt, 4), "unit": "samples/s", "cores": _threads(), "kind": "oracle",
+    return {"value": round(samples / dt, 4), "unit": "samples/s", "cores": _threads(), "cpu_model": cpu_model(),
+            "kind": "oracle",
             "sample": f"{samples} training sample(s) at 128^2 (forward, loss, backward; the Adam update is "
                       f"negligible), oracle network in FP64 numpy with bf16 operand rounding"}
 
@@ -334,6 +378,47 @@ def _threads():
         return max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
     except Exception:
         return os.cpu_count()
+
+
+def train_warm_start(args, batch=16):
+    """Warm-start network for ls1024 --init learned (untimed): 4 levels, 32 base channels, trained for
+    --unet-train-steps Adam steps on solutions of --unet-models layered + salt models at 128^2 (10-20 Hz,
+    32 top-row sources each) that the library's own HODLR series computed; sized for inference on the
+    benchmark grid in chunks of `batch` sources."""
+    import numpy as np
+    import torch
+
+    from paper_2005_01372_amd import lsop, synth
+
+    n, nsrc = 128, 32
+    net = lsop.UNet(4, 32, 4, 2, max_batch=batch, max_h=max(args.n, n), max_w=max(args.n, n))
+    net.init_params(seed=0)
+    rng = np.random.default_rng(1000)
+    X, T = [], []
+    for m in range(args.unet_models):
+        w = synth.model_layered_salt(n=n, h=10.0, freq=float(rng.uniform(10.0, 20.0)), seed=1000 + m, nsrc=nsrc)
+        op = lsop.Operator(n, n, lsop.C64, max_vec=nsrc)
+        op.set_problem(torch.as_tensor(w.vel, device="cuda"), w.h, w.freq, w.c0)
+        pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=64, levels=4, power_iters=1, seed=m)
+        pc.build()
+        rhs = op.incident(w.src_i, w.src_j)
+        psi, _ = lsop.series_solve(op, pc, rhs, tol=1e-6, max_iter=30)
+        for c in range(0, nsrc, batch):
+            x, sc = net.pack_inputs(op, rhs[c:c + batch])
+            X.append(x)
+            T.append(net.pack_target(op, psi[c:c + batch], rhs[c:c + batch], sc))
+        del pc, op
+    X, T = torch.cat(X), torch.cat(T)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    for _ in range(args.unet_train_steps):
+        i = torch.randint(0, X.shape[0], (batch,), device="cuda", generator=gen)
+        loss = net.train_step(X[i].contiguous(), T[i].contiguous(), 1e-3)
+    print(f"[bench] warm-start network trained on {X.shape[0]} samples, last loss {loss:.4f}", file=sys.stderr,
+          flush=True)
+    del X, T
+    torch.cuda.empty_cache()
+    return net
 
 
 def main_unet(args):
@@ -478,26 +563,39 @@ def main():
         torch.cuda.synchronize()
         del a
 
+    copy_gbps = measure_copy_gbps()
     w = synth.model_random_ellipses(n=args.n, nsrc=args.nsrc)
     vel = torch.as_tensor(w.vel, device="cuda")
-    op = lsop.Operator(w.nx, w.nz, lsop.C64, max_vec=max(args.nsrc, 64))
-    if args.pc == "hodlr":
-        pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=args.rank, levels=args.levels, power_iters=args.power_iters,
-                                 seed=3)
-    else:
-        pc = lsop.Preconditioner(op, lsop.PC_LOWRANK, rank=args.rank, power_iters=args.power_iters, seed=3)
-    psi = torch.empty((w.nsrc, w.nx, w.nz), dtype=torch.complex64, device="cuda")
-    op.set_problem(vel, w.h, w.freq, w.c0)
-    op.autotune(w.nsrc)
+    dt = {"c64": lsop.C64, "c128": lsop.C128, "mixed": lsop.MIXED}[args.dtype]
+    net = train_warm_start(args) if args.init == "learned" else None
+
+    def make(dtype):
+        o = lsop.Operator(w.nx, w.nz, dtype, max_vec=max(args.nsrc, 64))
+        if args.pc == "hodlr":
+            p = lsop.Preconditioner(o, lsop.PC_HODLR, rank=args.rank, levels=args.levels,
+                                    power_iters=args.power_iters, seed=3)
+        else:
+            p = lsop.Preconditioner(o, lsop.PC_LOWRANK, rank=args.rank, power_iters=args.power_iters, seed=3)
+        o.set_problem(vel, w.h, w.freq, w.c0)
+        o.autotune(w.nsrc)
+        return o, p
+
+    op, pc = make(dt)
+    psi = torch.empty((w.nsrc, w.nx, w.nz), dtype=op.vec_dtype, device="cuda")
     phase = {"build": 0.0, "series": 0.0}
 
-    def step():
-        op.set_problem(vel, w.h, w.freq, w.c0)
-        rhs = op.incident(w.src_i, w.src_j)
+    def step(o=op, p=pc, out=psi, learned=net):
+        o.set_problem(vel, w.h, w.freq, w.c0)
+        rhs = o.incident(w.src_i, w.src_j)
         t0 = time.perf_counter()
-        pc.build(None)                       # synchronises its stream
+        p.build(None)                       # synchronises its stream
         t1 = time.perf_counter()
-        _, info = lsop.series_solve(op, pc, rhs, psi=psi, tol=args.tol, max_iter=args.max_iter)
+        init = "h_rhs"
+        if learned is not None:             # the network's field as candidate start, chunk by chunk
+            for c in range(0, w.nsrc, 16):
+                learned.warm_start(o, rhs[c:c + 16], out=out[c:c + 16])
+            init = "best"
+        _, info = lsop.series_solve(o, p, rhs, psi=out, tol=args.tol, max_iter=args.max_iter, init=init)
         phase["build"] += t1 - t0
         phase["series"] += time.perf_counter() - t1
         return info
@@ -528,6 +626,37 @@ def main():
     for i in info:
         statuses[i.status_name] = statuses.get(i.status_name, 0) + 1
     iters = [i.iters for i in info]
+    col_tile, pc_bytes = op.info().col_tile, pc.info()[2]
+
+    # the plain FP64 series on the same GPU (untimed): its own solves/s, and every timed solution's relative
+    # error against it
+    fp64 = None
+    if args.dtype != "c128" and not args.no_fp64_compare:
+        del pc
+        torch.cuda.empty_cache()
+        op64, pc64 = make(lsop.C128)
+        psi64 = torch.empty((w.nsrc, w.nx, w.nz), dtype=torch.complex128, device="cuda")
+        phase64 = dict(phase)
+        phase.update(build=0.0, series=0.0)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        info64 = step(op64, pc64, psi64, None)
+        torch.cuda.synchronize()
+        f1 = time.perf_counter()
+        ok64 = sum(i.status == lsop.OK for i in info64)
+        err = (torch.linalg.vector_norm((psi.to(torch.complex128) - psi64).reshape(w.nsrc, -1), dim=1)
+               / torch.linalg.vector_norm(psi64.reshape(w.nsrc, -1), dim=1)).cpu().numpy()
+        fp64 = {"solves_per_s": round(ok64 / (f1 - f0), 2), "converged": ok64,
+                "iterations": [min(i.iters for i in info64), max(i.iters for i in info64)],
+                "build_s": round(phase["build"], 3), "series_s": round(phase["series"], 3),
+                "rel_err_vs_fp64": {"max": float(err.max()), "median": float(np.median(err)),
+                                    "min": float(err.min())},
+                "timing": "one untimed complex-FP64 step after the timed region (same workload, preconditioner "
+                          "parameters and stopping rule)"}
+        phase.update(phase64)
+        del pc64, op64, psi64
+        torch.cuda.empty_cache()
+        print("[bench] fp64 comparison done", file=sys.stderr, flush=True)
 
     # dominant kernel function: largest share of event-timed GPU time in the timed region
     dom = max(by_fn, key=lambda k: by_fn[k]["ms"])
@@ -555,13 +684,13 @@ def main():
     line = {
         "metric": METRIC, "value": converged / step_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(step_s * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": f"smooth random 1500-5000 m/s + 6 ellipses, {w.nx}x{w.nz}, h={w.h} m, {w.freq} Hz, "
                                f"c0={w.c0} m/s, {w.nsrc} top-row sources, {pcdesc}, "
                                f"series to rel. residual {args.tol}, cap {args.max_iter}",
                    "grid": [w.nx, w.nz], "sources": w.nsrc, "preconditioner": args.pc, "rank": args.rank,
                    "levels": args.levels if args.pc == "hodlr" else None, "power_iters": args.power_iters,
-                   "tol": args.tol},
+                   "tol": args.tol, "init": args.init},
         "converged": converged, "statuses": statuses, "iterations": [min(iters), max(iters)],
         "build_s": round(build_s, 3), "series_s": round(series_s, 3),
         "solves_per_s_series_only": round(converged / series_s, 1) if series_s > 0 else None,
@@ -569,9 +698,13 @@ def main():
         "fft_conv_GBps": None if fft_gbps is None else round(fft_gbps, 1),
         "fft_conv_frac_of_peak": None if fft_gbps is None else round(fft_gbps / HBM_PEAK_GBPS, 4),
         "operator_applications_per_s": round(vec_applies / (fft_ms / 1e3), 1) if fft_ms > 0 else None,
-        "col_tile": op.info().col_tile, "preconditioner_bytes": pc.info()[2],
+        "col_tile": col_tile, "preconditioner_bytes": pc_bytes,
+        "hbm_copy_GBps_measured": round(copy_gbps, 1),
+        "fft_conv_frac_of_measured_copy": None if fft_gbps is None else round(fft_gbps / copy_gbps, 4),
+        "fp64_series": fp64,
         "roofline": roof, "kernels": kernels, "ms_per_step_by_use": uses,
     }
+    roof["peak_measured_copy"] = round(copy_gbps, 1) if roof.get("unit") == "GB/s" else None
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args, iters, converged, args.cpu_sources)
     print(json.dumps(line), flush=True)

@@ -209,3 +209,18 @@ def he_init(levels=4, base=32, cin=4, cout=2, seed=0):
         out.append(rng.standard_normal(k * k * ci * co) * np.sqrt(2.0 / (k * k * ci)))
         out.append(np.zeros(co))
     return np.concatenate(out)
+
+
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, ICLR 2015, Algorithm 1) in FP64.
+
+    Moments m <- b1 m + (1 - b1) g and v <- b2 v + (1 - b2) g^2, bias-corrected
+    by 1 - b1^t and 1 - b2^t (t = 1 at the first step), then
+    p <- p - lr m_hat / (sqrt(v_hat) + eps).  Returns (p, m, v) as new arrays.
+    """
+    p, g = np.asarray(p, np.float64), np.asarray(g, np.float64)
+    m = b1 * np.asarray(m, np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, np.float64) + (1.0 - b2) * g * g
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    return p - lr * m_hat / (np.sqrt(v_hat) + eps), m, v

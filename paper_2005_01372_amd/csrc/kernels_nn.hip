@@ -12,6 +12,8 @@
 // flipped, channels swapped): the data gradient of a stride-1 zero-padded
 // correlation is the correlation of the output gradient with WT.  Both are
 // output-channel major (k contiguous), so a weight tile row is one run.
+#include <cmath>
+
 #include "internal.hpp"
 
 namespace lsop {
@@ -446,13 +448,15 @@ __global__ void k_mse(const float* __restrict__ out, const float* __restrict__ t
   if (threadIdx.x == 0) atomicAdd(loss, (red[0] + red[1] + red[2] + red[3]) / (double)n);
 }
 
-// Adam (Kingma & Ba) on FP32 master weights: m, v moments, bias-corrected step.
+// Adam (Kingma & Ba, Algorithm 1) on FP32 master weights: m, v moments, bias-corrected step.  The decay
+// complements 1 - beta and the bias corrections 1 - beta^t arrive precomputed in FP64 and rounded once:
+// 1 - beta2^t formed in FP32 from beta2 = 0.999 loses about 5e-5 of its value to cancellation.
 __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ M, float* __restrict__ V,
-                       size_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+                       size_t n, float lr, float b1, float omb1, float b2, float omb2, float eps, float c1, float c2) {
   for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (size_t)gridDim.x * blockDim.x) {
     const float g = G[k];
-    const float m = b1 * M[k] + (1.f - b1) * g;
-    const float v = b2 * V[k] + (1.f - b2) * g * g;
+    const float m = b1 * M[k] + omb1 * g;
+    const float v = b2 * V[k] + omb2 * g * g;
     M[k] = m;
     V[k] = v;
     P[k] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
@@ -632,10 +636,11 @@ hipError_t launch_mse(const float* out, const float* t, float* dout, size_t n, d
   return hipGetLastError();
 }
 
-hipError_t launch_adam(float* P, const float* G, float* M, float* V, size_t n, float lr, float b1, float b2,
-                       float eps, int step, hipStream_t s) {
-  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-  hipLaunchKernelGGL(k_adam, dim3(nn_grid(n)), dim3(256), 0, s, P, G, M, V, n, lr, b1, b2, eps, c1, c2);
+hipError_t launch_adam(float* P, const float* G, float* M, float* V, size_t n, float lr, double b1, double b2,
+                       double eps, int step, hipStream_t s) {
+  const float c1 = (float)(1.0 - std::pow(b1, step)), c2 = (float)(1.0 - std::pow(b2, step));
+  hipLaunchKernelGGL(k_adam, dim3(nn_grid(n)), dim3(256), 0, s, P, G, M, V, n, lr, (float)b1, (float)(1.0 - b1),
+                     (float)b2, (float)(1.0 - b2), (float)eps, c1, c2);
   return hipGetLastError();
 }
 

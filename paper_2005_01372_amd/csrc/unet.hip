@@ -25,8 +25,8 @@ hipError_t launch_upcat(const float* lo, const float* skip, float* out, int B, i
 hipError_t launch_upcat_bwd(const float* dcat, float* dlo, float* dskip, int B, int h, int w, int Cu, int Cs,
                             hipStream_t s);
 hipError_t launch_mse(const float* out, const float* t, float* dout, size_t n, double* loss, hipStream_t s);
-hipError_t launch_adam(float* P, const float* G, float* M, float* V, size_t n, float lr, float b1, float b2,
-                       float eps, int step, hipStream_t s);
+hipError_t launch_adam(float* P, const float* G, float* M, float* V, size_t n, float lr, double b1, double b2,
+                       double eps, int step, hipStream_t s);
 hipError_t launch_weights_bf16(const float* Wf, int ks, int Ci, int Co, unsigned short* Wb, unsigned short* WT,
                                hipStream_t s);
 template <typename T>
@@ -382,7 +382,7 @@ int unet_train_step(unet* u, const float* x_dev, const float* target_dev, int B,
   if ((st = backward(u, u->dout, s))) return st;
   ++u->step;
   LSOP_HIP(prof_launch("unet adam", "k_adam", (double)u->nparams * 28.0, 12.0 * u->nparams, (double)u->nparams, s,
-                       [&] { return launch_adam(u->P, u->G, u->M, u->V, u->nparams, lr, 0.9f, 0.999f, 1e-8f, u->step, s); }));
+                       [&] { return launch_adam(u->P, u->G, u->M, u->V, u->nparams, lr, 0.9, 0.999, 1e-8, u->step, s); }));
   if ((st = refresh_weights(u, s))) return st;
   if (loss_host) {
     LSOP_HIP(hipMemcpyAsync(loss_host, u->dloss, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -146,6 +146,13 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _gpu(*tensors):
+    """Raise unless every tensor lives on the GPU (called after the shape and dtype checks of a call)."""
+    for t in tensors:
+        if not t.is_cuda:
+            raise TypeError("tensors passed to the library must be on the GPU")
+
+
 def bessel_host(kind, x):
     lib = load_library()
     out = (C.c_double * 2)()
@@ -213,25 +220,37 @@ class Operator:
         self.h, self.freq, self.c0 = float(h), float(freq), float(c0)
         return self
 
-    def _vecs(self, x, dtype=None):
+    def _vecs(self, x, dtype=None, nvec=None):
+        """Number of [nx][nz] vectors in x, after checking its shape, dtype, layout and device (and, when
+        nvec is given, that it holds exactly that many vectors)."""
         dtype = dtype or self.vec_dtype
-        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dtype and x.is_contiguous()):
-            raise TypeError(f"expected a contiguous CUDA tensor of {dtype}")
-        if x.shape[-2:] != (self.nx, self.nz):
-            raise ValueError(f"vectors must end in {(self.nx, self.nz)}")
-        return x.numel() // (self.nx * self.nz)
+        if not isinstance(x, torch.Tensor):
+            raise TypeError("expected a torch tensor")
+        if x.dim() < 2 or tuple(x.shape[-2:]) != (self.nx, self.nz):
+            raise ValueError(f"vectors must end in {(self.nx, self.nz)}, got {tuple(x.shape)}")
+        nv = x.numel() // (self.nx * self.nz)
+        if nvec is not None and nv != nvec:
+            raise ValueError(f"expected {nvec} vectors, got {nv}")
+        if x.dtype != dtype:
+            raise TypeError(f"expected {dtype}, got {x.dtype}")
+        if not x.is_contiguous():
+            raise ValueError("vectors must be contiguous")
+        return nv
 
     def apply(self, x, mode="A", out=None):
         nv = self._vecs(x)
         out = torch.empty_like(x) if out is None else out
-        self._vecs(out)
+        self._vecs(out, nvec=nv)
+        _gpu(x, out)
         _check(self.lib.lsop_apply(self.handle, MODES[mode], _ptr(x), _ptr(out), nv, _stream()))
         return out
 
     def residual(self, psi, rhs, out=None):
         nv = self._vecs(psi)
-        self._vecs(rhs)
+        self._vecs(rhs, nvec=nv)
         out = torch.empty_like(psi) if out is None else out
+        self._vecs(out, nvec=nv)
+        _gpu(psi, rhs, out)
         nrm = torch.empty(nv, dtype=torch.float64, device=psi.device)
         _check(self.lib.lsop_residual(self.handle, _ptr(psi), _ptr(rhs), _ptr(out), _ptr(nrm), nv, _stream()))
         return out, nrm
@@ -297,6 +316,8 @@ class Preconditioner:
     def apply(self, x, out=None):
         nv = self.op._vecs(x, self.op.inner_dtype)
         out = torch.empty_like(x) if out is None else out
+        self.op._vecs(out, self.op.inner_dtype, nvec=nv)
+        _gpu(x, out)
         _check(self.lib.precond_apply(self.handle, _ptr(x), _ptr(out), nv, _stream()))
         return out
 
@@ -324,7 +345,8 @@ def series_solve(op, pc, rhs, psi=None, tol=1e-10, max_iter=30, init="h_rhs", re
     """Preconditioned scattering series (eq. 11); returns (psi, [SolveResult per right-hand side])."""
     nv = op._vecs(rhs)
     psi = torch.empty_like(rhs) if psi is None else psi
-    op._vecs(psi)
+    op._vecs(psi, nvec=nv)
+    _gpu(rhs, psi)
     p = SolveParams(float(tol), int(max_iter), INIT[init], int(refine_max), float(inner_tol))
     info = (SolveInfo * nv)()
     st = op.lib.series_solve(op.handle, pc.handle if pc is not None else None, _ptr(rhs), _ptr(psi), nv,
@@ -362,17 +384,19 @@ class Batch:
         except Exception:
             pass
 
-    def _arrays(self, xs, dtype=None):
+    def _arrays(self, xs, dtype=None, nvec=None):
         if len(xs) != len(self.ops):
             raise ValueError("one tensor per instance")
-        nv = [op._vecs(x, dtype) for op, x in zip(self.ops, xs)]
+        nvec = nvec or [None] * len(xs)
+        nv = [op._vecs(x, dtype, k) for op, x, k in zip(self.ops, xs, nvec)]
         ptrs = (C.c_void_p * len(xs))(*[x.data_ptr() for x in xs])
         return ptrs, (C.c_int * len(xs))(*nv)
 
     def apply(self, xs, mode="A", outs=None):
         outs = [torch.empty_like(x) for x in xs] if outs is None else outs
         px, nv = self._arrays(xs)
-        py, _ = self._arrays(outs)
+        py, _ = self._arrays(outs, nvec=list(nv))
+        _gpu(*xs, *outs)
         _check(self.lib.lsop_batch_apply(self.handle, MODES[mode], px, py, nv, _stream()))
         return outs
 
@@ -388,7 +412,10 @@ class Batch:
         """Lockstep series for all instances; returns (psis, [[SolveResult per vector] per instance])."""
         psis = [torch.empty_like(r) for r in rhss] if psis is None else psis
         pr, nv = self._arrays(rhss)
-        pp, _ = self._arrays(psis)
+        pp, _ = self._arrays(psis, nvec=list(nv))
+        if len(pcs) != len(self.ops):
+            raise ValueError("one preconditioner (or None) per instance")
+        _gpu(*rhss, *psis)
         pch = (C.c_void_p * len(self.ops))(*[(pc.handle.value if pc is not None else None) for pc in pcs])
         total = sum(nv)
         info = (SolveInfo * max(total, 1))()
@@ -430,10 +457,14 @@ class UNet:
 
     @staticmethod
     def _f32(t, shape=None):
-        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
-            raise TypeError("expected a contiguous CUDA float32 tensor")
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("expected a torch tensor")
         if shape is not None and tuple(t.shape) != tuple(shape):
             raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise TypeError("expected a contiguous float32 tensor")
+        if not t.is_cuda:
+            raise TypeError("expected a tensor on the GPU")
         return t
 
     def set_params(self, params):
@@ -454,23 +485,29 @@ class UNet:
         return out
 
     def forward(self, x):
+        if not isinstance(x, torch.Tensor) or x.dim() != 4 or x.shape[3] != self.cin:
+            raise ValueError(f"input must be [B][H][W][{self.cin}]")
         self._f32(x)
         B, H, W, c = x.shape
-        if c != self.cin:
-            raise ValueError("input channels")
         y = torch.empty((B, H, W, self.cout), dtype=torch.float32, device="cuda")
         self._x = x
+        self._out_shape = (B, H, W, self.cout)
         _check(self.lib.unet_forward(self.handle, _ptr(x), B, H, W, _ptr(y), _stream()))
         return y
 
     def backward(self, dy):
-        self._f32(dy)
+        shape = getattr(self, "_out_shape", None)
+        if shape is None:
+            raise RuntimeError("backward needs a preceding forward")
+        self._f32(dy, shape)
         _check(self.lib.unet_backward(self.handle, _ptr(dy), _stream()))
         g = torch.empty(self.nparams, dtype=torch.float32, device="cuda")
         _check(self.lib.unet_get_grads(self.handle, _ptr(g), _stream()))
         return g
 
     def train_step(self, x, target, lr):
+        if not isinstance(x, torch.Tensor) or x.dim() != 4 or x.shape[3] != self.cin:
+            raise ValueError(f"input must be [B][H][W][{self.cin}]")
         self._f32(x)
         B, H, W, _ = x.shape
         self._f32(target, (B, H, W, self.cout))
@@ -481,6 +518,7 @@ class UNet:
 
     def pack_inputs(self, op, psi0):
         nv = op._vecs(psi0)
+        _gpu(psi0)
         x = torch.empty((nv, op.nx, op.nz, 4), dtype=torch.float32, device="cuda")
         sc = torch.empty(nv, dtype=torch.float32, device="cuda")
         _check(self.lib.unet_pack_inputs(self.handle, op.handle, _ptr(psi0), nv, _ptr(x), _ptr(sc), _stream()))
@@ -488,7 +526,9 @@ class UNet:
 
     def pack_target(self, op, psi, psi0, scale):
         nv = op._vecs(psi0)
-        op._vecs(psi)
+        op._vecs(psi, nvec=nv)
+        self._f32(scale, (nv,))
+        _gpu(psi, psi0)
         t = torch.empty((nv, op.nx, op.nz, 2), dtype=torch.float32, device="cuda")
         _check(self.lib.unet_pack_target(op.handle, _ptr(psi), _ptr(psi0), _ptr(self._f32(scale)), nv, _ptr(t),
                                          _stream()))
@@ -497,5 +537,7 @@ class UNet:
     def warm_start(self, op, psi0, out=None):
         nv = op._vecs(psi0)
         out = torch.empty_like(psi0) if out is None else out
+        op._vecs(out, psi0.dtype, nvec=nv)
+        _gpu(psi0, out)
         _check(self.lib.unet_warm_start(self.handle, op.handle, _ptr(psi0), _ptr(out), nv, _stream()))
         return out

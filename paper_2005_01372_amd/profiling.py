@@ -23,10 +23,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def kernel_source_sha():
+    """Hash of every source file of the library (kernels, launch settings, host plans): a change to any of them
+    marks counter records taken before it as stale."""
     h = hashlib.sha256()
-    for f in ("kernels_fft.hip", "kernels_la.hip", "fft_engine.hpp", "kernels_nn.hip"):
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(HERE, "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    with open(os.path.join(HERE, "..", "include", "lsop.h"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -7,6 +7,8 @@ unitary factor, which the approximation does not see): complex double
 inverses and cores).  Series solutions are compared with the dense-LU
 solution: double <= 1e-10 (residual 1e-13), FP32 + FP64 refinement <= 1e-10.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -166,43 +168,52 @@ def test_hodlr_invalid_parameters():
         lsop.Preconditioner(op2, lsop.PC_HODLR, rank=8, levels=4)
 
 
+@pytest.mark.timeout(900)
 def test_full_size_benchmark_solve():
     """The benchmark configuration itself: 1024 x 1024 (h = 5 m, 25 Hz, 1500-5000 m/s with ellipses), 128 top-row
-    sources, HODLR rank 256, 10 levels, one power iteration, complex FP32, series to 1e-6.  Every source
-    converges; the residual recomputed through the separate operator entry point agrees with the one fused into
-    the series and is <= 1e-6 (plus FP32 rounding); at sampled cells the oracle's direct sums reproduce both the
-    incident field and A psi of the returned solution."""
+    sources, HODLR rank 256, 10 levels, one power iteration, complex FP32 with the autotuned column tile, series
+    to 1e-6.  Every source converges.  The oracle recomputes the relative residual ||A psi - psi0|| / ||psi0|| of
+    every returned solution in FP64 (its own incident fields and FFT product on the CPU): <= 1.5e-6 for all 128,
+    and within a few per cent of the residual the series reported.  At sampled cells the oracle's direct sums
+    (its definition of G0 V) reproduce A psi of the device's operator entry point."""
     announce("benchmark configuration 1024^2 x 128, HODLR r256 L10 q1")
     w = synth.model_random_ellipses(n=1024, nsrc=128)
     op = make_op(w, lsop.C64, 128)
     rhs = op.incident(w.src_i, w.src_j)
+    tile = op.autotune(128)
+    announce(f"autotuned column tile {tile}")
     pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=256, levels=10, power_iters=1, seed=3)
     pc.build()
     psi, res = lsop.series_solve(op, pc, rhs, tol=1e-6, max_iter=30)
     assert all(r.status == lsop.OK for r in res)
-    a = op.apply(psi, "A") - rhs
-    rr = (torch.linalg.vector_norm(a.reshape(128, -1), dim=1) /
-          torch.linalg.vector_norm(rhs.reshape(128, -1), dim=1)).cpu().numpy()
+    ap_h = host(op.apply(psi, "A"))
+    psi_h = host(psi)
+    del pc
+    torch.cuda.empty_cache()
+    # FP64 residual of every source by the oracle (incident field and operator of its own)
+    prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+    prob.workers = os.cpu_count()
+    rr = np.empty(128)
+    for c in range(0, 128, 8):
+        psi0 = prob.incident(w.src_i[c:c + 8], w.src_j[c:c + 8])
+        rr[c:c + 8] = O.relative_residual(prob, psi_h[c:c + 8], psi0)
+        if c % 32 == 24:
+            announce(f"oracle residuals of sources {c - 24}..{c + 7}: max {rr[c - 24:c + 8].max():.3e}")
+    announce(f"oracle residuals: max {rr.max():.3e}, min {rr.min():.3e}")
     assert np.all(rr <= 1.5e-6), rr.max()
     assert np.allclose(rr, [r.rel_residual for r in res], rtol=0.05, atol=5e-8)
-    # sampled cells against the oracle's definitions (direct sums over all 1024^2 cells)
-    chi = O.contrast(w.vel, w.freq, w.c0)
-    K = O.cell_kernel(1024, 1024, w.h, O.wavenumber(w.freq, w.c0))
-    psi_h, rhs_h, ap_h = host(psi), host(rhs), host(a + rhs)
+    # sampled cells of A psi against the oracle's direct sums over all 1024^2 cells
+    chi, K = prob.chi, prob.K
     ii = np.arange(1024)
     rng = np.random.default_rng(1)
-    num_a = den_a = num_0 = den_0 = 0.0
+    num_a = den_a = 0.0
     for _ in range(12):
         v, i, j = rng.integers(0, 128), rng.integers(0, 1024), rng.integers(0, 1024)
         Kij = K[np.abs(ii - i)[:, None], np.abs(ii - j)[None, :]]
         ref_a = psi_h[v, i, j] - np.sum(Kij * chi * psi_h[v])
         num_a += abs(ap_h[v, i, j] - ref_a) ** 2
         den_a += abs(ref_a) ** 2
-        ref_0 = K[abs(i - w.src_i[v]), abs(j - w.src_j[v])] / w.h ** 2
-        num_0 += abs(rhs_h[v, i, j] - ref_0) ** 2
-        den_0 += abs(ref_0) ** 2
     assert np.sqrt(num_a / den_a) <= 1e-5
-    assert np.sqrt(num_0 / den_0) <= 1e-5
 
 
 def test_layered_salt_256_fp64_and_refined_fp32():

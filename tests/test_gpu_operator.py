@@ -4,6 +4,8 @@ Tolerances (relative L2 over all cells and vectors): complex double <= 1e-12
 (the FFT product and the direct sum differ by rounding only); complex float
 <= 1e-5 (the bound stated for FP32 results).
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -194,3 +196,52 @@ def test_invalid_arguments():
         op.incident([25], [0])
     with pytest.raises(lsop.LsopError):
         lsop.Preconditioner(op, lsop.PC_LOWRANK, rank=0)
+
+
+# The column pass runs with the tile width the autotuner (or LSOP_COL_TILE) picks.  Every width a length can
+# take is compared on the full grid with the oracle's FFT product, in all four modes: 1024^2 (the benchmark's
+# length, whose autotuned complex-float tile is 4 columns: the line-paired branch with the early spectrum
+# loads) and 2048^2 in complex float, 1024^2 in complex double.  The widths a length cannot take are clamped
+# by the library to its widest, so only the distinct kernels are listed.
+_ORACLE_CACHE = {}
+
+
+def _oracle_apply(n, mode):
+    key = (n, mode)
+    if key not in _ORACLE_CACHE:
+        w = synth.model_random_ellipses(n=n, nsrc=1)
+        prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+        prob.workers = os.cpu_count()
+        x = synth.random_vectors((3, n, n), 17)
+        _ORACLE_CACHE[key] = (w, x, prob.apply(x, mode))
+        if len(_ORACLE_CACHE) > 4:  # keep the host memory of the 2048^2 cases bounded
+            _ORACLE_CACHE.pop(next(iter(_ORACLE_CACHE)))
+    return _ORACLE_CACHE[key]
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("n,dtype,tile,tol", [(1024, lsop.C64, 8, 1e-5), (1024, lsop.C64, 4, 1e-5),
+                                              (1024, lsop.C64, 2, 1e-5), (2048, lsop.C64, 4, 1e-5),
+                                              (2048, lsop.C64, 2, 1e-5), (1024, lsop.C128, 4, 1e-12),
+                                              (1024, lsop.C128, 2, 1e-12)])
+@pytest.mark.parametrize("mode", ["A", "G0V", "AH", "VHG0H"])
+def test_column_tiles_full_grid(n, dtype, tile, tol, mode, monkeypatch):
+    announce(f"column tile {tile} at {n}^2 dtype={dtype} mode={mode}")
+    w, x, ref = _oracle_apply(n, mode)
+    monkeypatch.setenv("LSOP_COL_TILE", str(tile))
+    op = make_op(w, dtype, 3)
+    assert op.info().col_tile == tile
+    tdt = torch.complex64 if dtype == lsop.C64 else torch.complex128
+    xd = dev(x, tdt)
+    lsop.profile_reset()
+    lsop.profile_enable(True)
+    try:
+        y = host(op.apply(xd, mode))
+        ran = [k for k in lsop.profile_read(by_kernel=True) if k.startswith("k_cols")]
+    finally:
+        lsop.profile_enable(False)
+    tname = "float" if dtype == lsop.C64 else "double"
+    assert ran == [f"k_cols<{tname}, {n}, {tile}>"], ran
+    assert rel(y, ref) <= tol
+    del op, xd
+    torch.cuda.empty_cache()

@@ -237,3 +237,30 @@ def test_init_params_is_he_normal():
         assert np.all(b == 0.0), name
         at += nw + co
     assert at == p.size
+
+
+def test_adam_update_matches_oracle():
+    """Two unet_train_step calls: the parameters after each equal the oracle's Adam (Kingma & Ba, Algorithm 1,
+    FP64) applied to the start parameters with the gradients the device computed for those steps (read back
+    with unet_get_grads; the gradients themselves are checked against the oracle network above).  FP32
+    master weights: per element within 2e-6 of |p| plus 1e-6 of the learning rate."""
+    announce("adam update vs oracle")
+    levels, base, B, H, W, lr = 2, 8, 2, 16, 16, 1e-3
+    r = np.random.default_rng(5)
+    theta = (U.he_init(levels, base, 4, 2, seed=9)
+             + 0.01 * r.standard_normal(U.param_count(levels, base))).astype(np.float32)
+    net = lsop.UNet(levels, base, 4, 2, max_batch=4, max_h=32, max_w=32)
+    net.set_params(theta)  # also zeroes the Adam moments and the step count
+    x = f32(r.standard_normal((B, H, W, 4)))
+    t = f32(r.standard_normal((B, H, W, 2)))
+    p, m, v = theta.astype(np.float64), np.zeros(theta.size), np.zeros(theta.size)
+    for step in (1, 2):
+        net.train_step(x, t, lr)
+        g = torch.empty(net.nparams, dtype=torch.float32, device="cuda")
+        lsop._check(net.lib.unet_get_grads(net.handle, lsop._ptr(g), lsop._stream()))
+        g_h = g.cpu().numpy().astype(np.float64)
+        assert np.all(np.isfinite(g_h)) and np.any(g_h != 0)
+        p, m, v = U.adam_step(p, g_h, m, v, step, lr)
+        got = net.params().cpu().numpy().astype(np.float64)
+        err = np.abs(got - p)
+        assert np.all(err <= 2e-6 * np.abs(p) + 1e-6 * lr), (step, float(err.max()))

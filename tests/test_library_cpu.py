@@ -73,3 +73,94 @@ def test_hankel_against_mpmath_high_precision(lib):
         ref = complex(mp.hankel1(0, x))
         j0, y0 = lsop.bessel_host(0, float(x))
         assert abs(complex(j0, y0) - ref) <= 3e-15 * abs(ref), x
+
+
+# ---------------------------------------------------------------- binding argument checks
+# Every tensor reaches the C ABI as a raw pointer, so the binding checks shapes, vector counts and dtypes
+# before any call: a short or mistyped buffer would become out-of-bounds device accesses.  These run without a
+# GPU on handles whose library calls are never reached (the checks raise first); CPU tensors of the right shape
+# are refused for their device.
+import torch  # noqa: E402
+
+
+class _NoLib:
+    def __getattr__(self, name):
+        raise AssertionError(f"library call {name} reached despite a bad argument")
+
+
+def _fake_op(nx=6, nz=5, dtype=lsop.C64):
+    op = object.__new__(lsop.Operator)
+    op.lib, op.handle = _NoLib(), None
+    op.nx, op.nz, op.dtype, op.max_vec = nx, nz, dtype, 4
+    op.vec_dtype = torch.complex64 if dtype == lsop.C64 else torch.complex128
+    op.inner_dtype = torch.complex64 if dtype in (lsop.C64, lsop.MIXED) else torch.complex128
+    return op
+
+
+def test_operator_checks_outputs_and_counts():
+    op = _fake_op()
+    x = torch.zeros((3, 6, 5), dtype=torch.complex64)
+    with pytest.raises(ValueError):          # output holds fewer vectors than the input
+        op.apply(x, out=torch.zeros((2, 6, 5), dtype=torch.complex64))
+    with pytest.raises(TypeError):           # wrong element type for a complex-float operator
+        op.apply(x, out=torch.zeros((3, 6, 5), dtype=torch.complex128))
+    with pytest.raises(ValueError):          # wrong grid
+        op.apply(torch.zeros((3, 5, 6), dtype=torch.complex64))
+    with pytest.raises(ValueError):          # rhs vector count differs from psi
+        op.residual(x, torch.zeros((4, 6, 5), dtype=torch.complex64))
+    with pytest.raises(ValueError):
+        op.apply(torch.zeros((3, 6, 10), dtype=torch.complex64)[:, :, ::2])  # right shape, not contiguous
+    with pytest.raises(TypeError):           # right shape and dtype, but host memory
+        op.apply(x)
+
+
+def test_series_and_preconditioner_check_outputs():
+    op = _fake_op(dtype=lsop.MIXED)
+    rhs = torch.zeros((2, 6, 5), dtype=torch.complex128)
+    with pytest.raises(ValueError):
+        lsop.series_solve(op, None, rhs, psi=torch.zeros((1, 6, 5), dtype=torch.complex128))
+    with pytest.raises(TypeError):
+        lsop.series_solve(op, None, rhs, psi=torch.zeros((2, 6, 5), dtype=torch.complex64))
+    pc = object.__new__(lsop.Preconditioner)
+    pc.op, pc.lib = op, _NoLib()
+    x = torch.zeros((2, 6, 5), dtype=torch.complex64)   # the inner dtype of a mixed operator
+    with pytest.raises(ValueError):
+        pc.apply(x, out=torch.zeros((1, 6, 5), dtype=torch.complex64))
+    with pytest.raises(TypeError):
+        pc.apply(x, out=torch.zeros((2, 6, 5), dtype=torch.complex128))
+
+
+def test_batch_checks_outputs():
+    b = object.__new__(lsop.Batch)
+    b.ops, b.lib = [_fake_op(6, 5), _fake_op(4, 4)], _NoLib()
+    xs = [torch.zeros((2, 6, 5), dtype=torch.complex64), torch.zeros((1, 4, 4), dtype=torch.complex64)]
+    with pytest.raises(ValueError):
+        b.apply(xs, outs=[torch.zeros((2, 6, 5), dtype=torch.complex64), torch.zeros((2, 4, 4), dtype=torch.complex64)])
+    with pytest.raises(ValueError):
+        b.solve([None, None], xs, psis=[torch.zeros((1, 6, 5), dtype=torch.complex64), xs[1]])
+    with pytest.raises(ValueError):
+        b.solve([None], xs)
+
+
+def test_unet_checks_shapes():
+    net = object.__new__(lsop.UNet)
+    net.lib, net.handle, net.cin, net.cout = _NoLib(), None, 4, 2
+    with pytest.raises(RuntimeError):        # backward before any forward
+        net.backward(torch.zeros((1, 8, 8, 2)))
+    net._out_shape = (2, 8, 8, 2)
+    with pytest.raises(ValueError):          # dy not shaped like the last forward's output
+        net.backward(torch.zeros((1, 8, 8, 2)))
+    with pytest.raises(TypeError):
+        net.backward(torch.zeros((2, 8, 8, 2), dtype=torch.float64))
+    with pytest.raises(ValueError):          # input channels
+        net.forward(torch.zeros((1, 8, 8, 3)))
+    op = _fake_op()
+    psi0 = torch.zeros((2, 6, 5), dtype=torch.complex64)
+    with pytest.raises(ValueError):          # one scale per vector
+        net.pack_target(op, psi0, psi0, torch.zeros(3))
+    with pytest.raises(ValueError):
+        net.pack_target(op, torch.zeros((1, 6, 5), dtype=torch.complex64), psi0, torch.zeros(2))
+    with pytest.raises(ValueError):
+        net.warm_start(op, psi0, out=torch.zeros((1, 6, 5), dtype=torch.complex64))
+    with pytest.raises(TypeError):
+        net.warm_start(op, psi0, out=torch.zeros((2, 6, 5), dtype=torch.complex128))

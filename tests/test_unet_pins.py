@@ -82,3 +82,38 @@ def test_bf16_rounding():
     assert U.bf16_round(-2.5) == -2.5
     x = rng(6).standard_normal(1000)
     assert np.all(np.abs(U.bf16_round(x) - x) <= (2.0 ** -8 + 2.0 ** -24) * np.abs(x))   # unit roundoff 2^-8
+
+
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    vals = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()[:2]
+            vals[k] = float(v)
+    return vals
+
+
+def test_adam_two_steps_hand_worked():
+    """Two steps on one parameter against the hand-worked values (moments, bias correction, update)."""
+    g = _golden("adam_two_steps.txt")
+    p, m, v = U.adam_step(np.array([1.0]), np.array([0.5]), np.zeros(1), np.zeros(1), 1, 0.1)
+    for k, x in (("m1", m[0]), ("v1", v[0]), ("p1", p[0])):
+        assert abs(x - g[k]) <= 1e-14 * abs(g[k]), k
+    p, m, v = U.adam_step(p, np.array([-0.25]), m, v, 2, 0.1)
+    for k, x in (("m2", m[0]), ("v2", v[0]), ("p2", p[0])):
+        assert abs(x - g[k]) <= 1e-14 * abs(g[k]), k
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias-corrected moments are exactly g and g^2 at every step, so each
+    step moves p by lr g / (|g| + eps): after t steps p = p0 - t lr g / (|g| + eps).  A missing or wrong bias
+    correction breaks this at the first steps."""
+    r = rng(7)
+    g = r.standard_normal(50) * 10.0 ** r.uniform(-3, 2, 50)
+    p0 = r.standard_normal(50)
+    p, m, v = p0.copy(), np.zeros(50), np.zeros(50)
+    for t in range(1, 8):
+        p, m, v = U.adam_step(p, g, m, v, t, 0.01)
+        assert np.allclose(p, p0 - t * 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-13)
