@@ -22,8 +22,15 @@
  *    before any launch; on LSOP_EINVAL / LSOP_EUNSUPPORTED outputs are left
  *    untouched.  lsop_last_error() describes the last failure of the calling
  *    thread.  No C++ exception crosses this boundary.
- *  - Handles own their device state (allocated at *_create, freed at
- *    *_destroy).  A handle must not be used from two streams at once.
+ *  - Device memory: by default handles own their device state (allocated at
+ *    *_create, freed at *_destroy) and grow a workspace as calls need it.
+ *    Callers that own all device memory instead query the sizes
+ *    (lsop_state_bytes, precond_state_bytes, lsop_workspace_bytes), create
+ *    handles in their own buffers (lsop_create_in, precond_create_in) and
+ *    attach a workspace (lsop_attach_workspace): the operator, preconditioner
+ *    and series calls then allocate no device memory.  Batches and the
+ *    network keep library-owned memory.  A handle must not be used from two
+ *    streams at once.
  */
 #ifndef LSOP_H
 #define LSOP_H
@@ -118,15 +125,53 @@ int lsop_kernel_table(const lsop_op* op, void* table_dev, void* stream);
 
 int lsop_info(const lsop_op* op, lsop_op_info* info);
 void lsop_destroy(lsop_op* op);
+
+/* Caller-owned memory.  lsop_state_bytes: device bytes of an operator's state
+ * (contrast, FP64 kernel table, circulant spectrum, twiddles, the FFT
+ * intermediate of max_vec vectors, source staging) for lsop_create's
+ * arguments; host only, no device call.  Errors as lsop_create. */
+int lsop_state_bytes(int nx, int nz, int dtype, int max_vec, size_t* bytes);
+
+/* lsop_create with the state carved from the caller's device buffer state_dev
+ * of state_bytes bytes (256-byte aligned, at least lsop_state_bytes; it must
+ * outlive the handle, and lsop_destroy does not free it).  Errors: as
+ * lsop_create; ENOMEM if state_bytes is too small; EINVAL if state_dev is
+ * NULL or not 256-byte aligned. */
+int lsop_create_in(int nx, int nz, int dtype, int max_vec, void* state_dev, size_t state_bytes, lsop_op** out);
+
+/* Device workspace that lsop_set_problem and series_solve on nvec right-hand
+ * sides with start `init` (lsop_init) need; host only. */
+int lsop_workspace_bytes(const lsop_op* op, int nvec, int init, size_t* bytes);
+
+/* Hand the operator a caller-owned workspace (ws_dev, ws_bytes; 256-byte
+ * aligned; it must outlive the handle or a later attach).  From then on
+ * lsop_set_problem, series_solve and the builds of this operator's
+ * preconditioners take their temporaries from it and never allocate; a call
+ * that needs more fails with ENOMEM before any launch.  Replaces any
+ * library-owned workspace (freed after a device synchronisation).  ws_dev =
+ * NULL returns the operator to library-owned growth. */
+int lsop_attach_workspace(lsop_op* op, void* ws_dev, size_t ws_bytes);
+
+/* Diagnostic: device allocations (hipMalloc / hipMallocAsync calls) the
+ * library has made in this process. */
+int lsop_alloc_count(size_t* calls);
 const char* lsop_last_error(void);
 
 /* ----------------------------------------------------------------------
  * Preconditioners H for the series of eq. (11).
  *  LSOP_PC_IDENTITY  H = I (the Born series, Section 2.2).
+ *  LSOP_PC_SCALAR    H = alpha I (Section 2.2: the scalar choice of the
+ *                    homotopy series, alpha < 1).
  *  LSOP_PC_LOWRANK   H = I + U Z W^H with G0 V ~= U W^H from the randomized
  *                    range finder of Alg. 2 (power_iters = q) and
  *                    Z = (I_r - W^H U)^{-1} by Sherman-Morrison-Woodbury
- *                    (eq. 12).  `rank` probe vectors.
+ *                    (eq. 12).  `rank` + `oversample` probe vectors; with
+ *                    oversample p > 0 the (rank + p)-column factorisation is
+ *                    truncated to `rank` columns through an FP64 SVD of its
+ *                    (rank + p) x (rank + p) core (W~ = Q2 R2, R2^H =
+ *                    U_b S V_b^H, U = Q U_b S restricted to the leading
+ *                    `rank` singular values, W = Q2 V_b likewise; Halko et
+ *                    al. 2011, Section 5; the paper uses p = 0).
  *  LSOP_PC_HODLR     H = A_h^{-1}, A_h the hierarchically off-diagonal
  *                    low-rank approximation of A = I - G0 V (Section 2.4,
  *                    Fig. 1): cells in column-wise order, a binary tree of
@@ -147,22 +192,37 @@ const char* lsop_last_error(void);
  *                    operator's precision.  Requires nx divisible by 2^levels,
  *                    (nx / 2^levels) * nz a multiple of 64 and at most 8192.
  * ---------------------------------------------------------------------- */
-typedef enum { LSOP_PC_IDENTITY = 0, LSOP_PC_LOWRANK = 1, LSOP_PC_HODLR = 2 } lsop_pc_kind;
+typedef enum { LSOP_PC_IDENTITY = 0, LSOP_PC_LOWRANK = 1, LSOP_PC_HODLR = 2, LSOP_PC_SCALAR = 3 } lsop_pc_kind;
 
 typedef struct {
   int kind;         /* lsop_pc_kind */
-  int rank;         /* number of Gaussian probes r (LOWRANK, HODLR), 1 <= rank <= 256 */
+  int rank;         /* LOWRANK: kept rank r; HODLR: probes per block; 1 <= rank <= 256 */
   int power_iters;  /* q >= 0 (Alg. 1 power iterations; the paper's HODLR uses q = 0) */
   uint64_t seed;    /* Philox4x32-10 key when no probe block is supplied */
   int levels;       /* HODLR tree depth, >= 1 (ignored otherwise) */
+  int oversample;   /* LOWRANK: extra probes p >= 0, rank + p <= 256 (0 elsewhere) */
+  double alpha;     /* SCALAR: H = alpha I, alpha finite and non-zero */
 } lsop_precond_params;
 
 /* Allocate a preconditioner for `op` (U, W: rank x n complex in the inner
  * dtype of op; Z: rank x rank).  Errors: EINVAL, ENOMEM. */
 int precond_create(lsop_op* op, const lsop_precond_params* params, lsop_precond** out);
 
-/* Build H (Alg. 2 then eq. 12).  omega_dev: rank x nx*nz real doubles, probe
- * k contiguous, or NULL to draw standard normals on the device with
+/* Caller-owned memory: device bytes of the preconditioner's state (*state)
+ * and of the transient workspace its build needs (*build_ws; it comes from
+ * the operator's attached workspace, so attach at least the larger of this
+ * and lsop_workspace_bytes).  Host only. */
+int precond_state_bytes(const lsop_op* op, const lsop_precond_params* params, size_t* state, size_t* build_ws);
+
+/* precond_create with the state carved from the caller's buffer (256-byte
+ * aligned, at least precond_state_bytes' *state; it must outlive the handle,
+ * precond_destroy does not free it).  Errors: as precond_create; ENOMEM if
+ * state_bytes is too small. */
+int precond_create_in(lsop_op* op, const lsop_precond_params* params, void* state_dev, size_t state_bytes,
+                      lsop_precond** out);
+
+/* Build H (Alg. 2 then eq. 12).  omega_dev: (rank + oversample) x nx*nz real
+ * doubles, probe k contiguous, or NULL to draw standard normals on the device with
  * Philox4x32-10 (counter = (pair index lo, hi, k, 0), key = seed) and
  * Box-Muller.  Columns of the range basis that are numerically dependent are
  * dropped (zero columns of U), so chi = 0 gives H = I exactly.  Synchronises

@@ -23,6 +23,19 @@ int fail(int status, const std::string& msg) {
   return status;
 }
 
+// Device allocations the library makes (diagnostic: caller-owned handles must not add any).
+std::atomic<size_t> g_allocs{0};
+
+hipError_t lib_malloc(void** p, size_t nbytes) {
+  ++g_allocs;
+  return hipMalloc(p, nbytes);
+}
+
+hipError_t lib_malloc_async(void** p, size_t nbytes, hipStream_t s) {
+  ++g_allocs;
+  return hipMallocAsync(p, nbytes, s);
+}
+
 namespace {
 
 hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -145,16 +158,41 @@ hipError_t p_bgemm(const char* name, const Cx<T>* A, size_t lda, size_t sA, cons
 
 double fft_flops(int L) { return 5.0 * L * std::log2((double)L); }
 
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Where a handle's device state comes from: the library (one hipMalloc per buffer, recorded in `owned`), the
+// caller's buffer (base / cap: buffers carved at 256-byte aligned offsets), or nowhere (count_only: the size
+// query walks the same plan and only adds up the aligned sizes).  `bytes` is the running total.
+struct Alloc {
+  std::vector<void*>* owned = nullptr;
+  size_t* bytes = nullptr;
+  char* base = nullptr;
+  size_t cap = 0;
+  bool count_only = false;
+};
+
 template <typename P>
-int dev_alloc(std::vector<void*>& owned, size_t& bytes, P** out, size_t nbytes) {
+int dev_alloc(Alloc& a, P** out, size_t nbytes) {
+  *out = nullptr;
+  nbytes = align_up(nbytes == 0 ? 16 : nbytes);
+  if (a.count_only) {
+    *a.bytes += nbytes;
+    return LSOP_OK;
+  }
+  if (a.base) {
+    if (*a.bytes + nbytes > a.cap)
+      return fail(LSOP_ENOMEM, "caller's state buffer of " + std::to_string(a.cap) + " bytes is too small");
+    *out = reinterpret_cast<P*>(a.base + *a.bytes);
+    *a.bytes += nbytes;
+    return LSOP_OK;
+  }
   void* p = nullptr;
-  if (nbytes == 0) nbytes = 16;
-  if (hipMalloc(&p, nbytes) != hipSuccess) {
+  if (lib_malloc(&p, nbytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(LSOP_ENOMEM, "hipMalloc of " + std::to_string(nbytes) + " bytes failed");
   }
-  owned.push_back(p);
-  bytes += nbytes;
+  a.owned->push_back(p);
+  *a.bytes += nbytes;
   *out = reinterpret_cast<P*>(p);
   return LSOP_OK;
 }
@@ -175,23 +213,26 @@ std::vector<Cx<double>> twiddles(int L) {
   return w;
 }
 
+// The operator's workspace of at least `need` bytes: the caller's attached workspace (never grown: too small is
+// ENOMEM, reported before the call launches anything that depends on it) or a library buffer grown on demand.
 int grow_scratch(lsop_op* op, size_t need) {
   if (need <= op->scratch_bytes) return LSOP_OK;
+  if (op->ws_external)
+    return fail(LSOP_ENOMEM, "the attached workspace of " + std::to_string(op->scratch_bytes) +
+                                 " bytes is smaller than the " + std::to_string(need) + " bytes this call needs");
   if (op->scratch) {
     LSOP_HIP(hipDeviceSynchronize());
     (void)hipFree(op->scratch);
     op->scratch = nullptr;
     op->scratch_bytes = 0;
   }
-  if (hipMalloc(&op->scratch, need) != hipSuccess) {
+  if (lib_malloc(&op->scratch, need) != hipSuccess) {
     (void)hipGetLastError();
     return fail(LSOP_ENOMEM, "scratch allocation of " + std::to_string(need) + " bytes failed");
   }
   op->scratch_bytes = need;
   return LSOP_OK;
 }
-
-size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 template <typename T>
 struct Dt;
@@ -353,7 +394,7 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
 // Q = orth(Y) over the whole grid (Alg. 2 step 3); Y is overwritten.
 template <typename T>
 int orth_impl(lsop_precond* pc, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s) {
-  const int r = pc->rank;
+  const int r = pc->probes;
   const size_t n = pc->op->n();
   Cx<double>* G = pc->small;
   Cx<double>* X = G + (size_t)r * r;
@@ -364,39 +405,62 @@ int orth_impl(lsop_precond* pc, Cx<T>* Yin, Cx<T>* Qout, hipStream_t s) {
 template <typename T>
 int build_impl(lsop_precond* pc, const double* omega, hipStream_t s) {
   lsop_op* op = pc->op;
-  const int r = pc->rank;
+  const int l = pc->probes, r = pc->rank;
   const size_t n = op->n();
   Cx<T>* U = reinterpret_cast<Cx<T>*>(pc->U);
   Cx<T>* W = reinterpret_cast<Cx<T>*>(pc->W);
   Cx<T>* Y = reinterpret_cast<Cx<T>*>(pc->Y);
   // Alg. 2 step 1: Gaussian probes
-  if (omega) LSOP_HIP(launch_real_to_complex<T>(omega, Y, (size_t)r * n, s));
-  else LSOP_HIP(launch_philox_normal<T>(Y, r, n, pc->seed, s));
+  if (omega) LSOP_HIP(launch_real_to_complex<T>(omega, Y, (size_t)l * n, s));
+  else LSOP_HIP(launch_philox_normal<T>(Y, l, n, pc->seed, s));
   // step 2: Y0 = G0 (V Omega)
-  int st = apply_impl<T>(op, LSOP_MODE_G0V, Y, Y, nullptr, nullptr, nullptr, r, s);
+  int st = apply_impl<T>(op, LSOP_MODE_G0V, Y, Y, nullptr, nullptr, nullptr, l, s);
   if (st) return st;
   // step 3: Q0 = orth(Y0)
   if ((st = orth_impl<T>(pc, Y, U, s))) return st;
   // step 4: power iterations with the adjoint
   for (int j = 0; j < pc->q; ++j) {
-    if ((st = apply_impl<T>(op, LSOP_MODE_VHG0H, U, Y, nullptr, nullptr, nullptr, r, s))) return st;
+    if ((st = apply_impl<T>(op, LSOP_MODE_VHG0H, U, Y, nullptr, nullptr, nullptr, l, s))) return st;
     if ((st = orth_impl<T>(pc, Y, W, s))) return st;  // W holds Q~_j
-    if ((st = apply_impl<T>(op, LSOP_MODE_G0V, W, Y, nullptr, nullptr, nullptr, r, s))) return st;
+    if ((st = apply_impl<T>(op, LSOP_MODE_G0V, W, Y, nullptr, nullptr, nullptr, l, s))) return st;
     if ((st = orth_impl<T>(pc, Y, U, s))) return st;
   }
   // step 5: W = V^H G0^H Q_q, U = Q_q
-  if ((st = apply_impl<T>(op, LSOP_MODE_VHG0H, U, W, nullptr, nullptr, nullptr, r, s))) return st;
+  if ((st = apply_impl<T>(op, LSOP_MODE_VHG0H, U, W, nullptr, nullptr, nullptr, l, s))) return st;
+  int flags[34] = {0};
+  if (l > r) {
+    // oversampled: G0 V ~= Q W~^H with l columns; W~ = Q2 R2, R2^H = U_b S V_b^H (FP64 SVD),
+    // U = Q (U_b S)(:, :r), W = Q2 V_b(:, :r)
+    Cx<T>* Q2 = reinterpret_cast<Cx<T>*>(pc->Q2);
+    LSOP_HIP(hipMemcpyAsync(Y, W, sizeof(Cx<T>) * (size_t)l * n, hipMemcpyDeviceToDevice, s));
+    if ((st = orth_impl<T>(pc, Y, Q2, s))) return st;
+    Cx<double>* R2 = pc->svdw;
+    Cx<double>* Bc = R2 + (size_t)l * l;
+    Cx<double>* Vc = Bc + (size_t)l * l;
+    Cx<double>* Mu = Vc + (size_t)l * l;
+    Cx<double>* Mw = Mu + (size_t)l * r;
+    LSOP_HIP(p_gemm_ah_b<T>(Q2, l, W, nullptr, l, n, R2, pc->part, pc->ksplit, s, pc->part_cap));
+    LSOP_HIP(hipMemsetAsync(pc->dflag + 33, 0, sizeof(int), s));
+    LSOP_HIP(prof("lowrank_truncate", "k_svd_jacobi", 5.0 * l * l * sizeof(Cx<double>), 0.0, l, s,
+                  [&] { return launch_svd_trunc(R2, l, r, Bc, Vc, Mu, Mw, pc->dflag + 33, s); }));
+    LSOP_HIP(p_gemm_update<T>(U, l, Mu, r, nullptr, nullptr, 0.0, Y, nullptr, n, s));
+    LSOP_HIP(p_gemm_update<T>(Q2, l, Mw, r, nullptr, nullptr, 0.0, W, nullptr, n, s));
+    LSOP_HIP(hipMemcpyAsync(U, Y, sizeof(Cx<T>) * (size_t)r * n, hipMemcpyDeviceToDevice, s));
+  }
   // eq. (12): Z = (I_r - W^H U)^{-1}
   Cx<double>* M = pc->small;
   Cx<double>* work = M + (size_t)r * r;
   LSOP_HIP(p_gemm_ah_b<T>(W, r, U, nullptr, r, n, M, pc->part, pc->ksplit, s, pc->part_cap));
   LSOP_HIP(hipMemsetAsync(pc->dflag + 32, 0, sizeof(int), s));
   LSOP_HIP(launch_lu_inverse_i_minus(M, pc->Z, work, r, pc->dflag + 32, s));
-  int flags[33] = {0};
   LSOP_HIP(hipMemcpyAsync(flags, pc->dflag, sizeof(flags), hipMemcpyDeviceToHost, s));
   LSOP_HIP(hipStreamSynchronize(s));
   pc->kept = 0;
-  for (int b = 0; b < (r + 63) / 64; ++b) pc->kept += flags[b];
+  if (l > r) {
+    pc->kept = flags[33];
+  } else {
+    for (int b = 0; b < (l + 63) / 64; ++b) pc->kept += flags[b];
+  }
   if (flags[32]) return fail(LSOP_ESINGULAR, "I - W^H U is numerically singular");
   pc->built = true;
   return LSOP_OK;
@@ -424,6 +488,11 @@ int pc_apply_impl(lsop_precond* pc, const Cx<T>* x, Cx<T>* y, const int* vidx, i
       }
     }
     return LSOP_OK;
+  }
+  if (pc->kind == LSOP_PC_SCALAR) {  // H = alpha I: y = alpha x, or psi <- psi - alpha r
+    const hipError_t e = series_update ? launch_axpby<T>(x, y, -pc->alpha, 1.0, vidx, nvec, n, s)
+                                       : launch_axpby<T>(x, y, pc->alpha, 0.0, vidx, nvec, n, s);
+    return e == hipSuccess ? LSOP_OK : fail(LSOP_EHIP, "axpby launch failed");
   }
   if (pc->kind == LSOP_PC_HODLR) {
     if (!series_update) return hodlr_apply<T>(pc, x, vidx, y, vidx, nvec, 0, s);
@@ -794,11 +863,20 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
   const int r = pc->rank;
   const size_t n = op->n();
   // build-only workspace: sampling buffers and the FP64 leaf workspace, taken from and returned to the
-  // stream-ordered pool of stream s (no device-wide synchronisation, so builds on other streams keep running)
+  // stream-ordered pool of stream s (no device-wide synchronisation, so builds on other streams keep running),
+  // or carved from the operator's attached workspace (after the sub-domain spectra, which use its start as
+  // their intermediate earlier on the same stream)
+  const size_t bU = align_up(sizeof(Cx<T>) * r * n), bL = align_up(sizeof(Cx<double>) * pc->lwork_elems);
   struct Transient {
     lsop_precond* pc;
     hipStream_t s;
+    bool pooled;
     ~Transient() {
+      if (!pooled) {
+        pc->U = pc->Y = nullptr;
+        pc->lwork = nullptr;
+        return;
+      }
       for (void** p : {&pc->U, &pc->Y, reinterpret_cast<void**>(&pc->lwork)})
         if (*p) {
           (void)hipFreeAsync(*p, s);
@@ -806,10 +884,19 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
         }
       (void)hipStreamSynchronize(s);
     }
-  } transient{pc, s};
-  if (hipMallocAsync(&pc->U, sizeof(Cx<T>) * r * n, s) != hipSuccess ||
-      hipMallocAsync(&pc->Y, sizeof(Cx<T>) * r * n, s) != hipSuccess ||
-      hipMallocAsync(reinterpret_cast<void**>(&pc->lwork), sizeof(Cx<double>) * pc->lwork_elems, s) != hipSuccess) {
+  } transient{pc, s, !op->ws_external};
+  if (op->ws_external) {
+    if (op->scratch_bytes < 2 * bU + bL)
+      return fail(LSOP_ENOMEM, "the attached workspace is smaller than the " + std::to_string(2 * bU + bL) +
+                                   " bytes this HODLR build needs");
+    char* w = reinterpret_cast<char*>(op->scratch);
+    pc->U = w;
+    pc->Y = w + bU;
+    pc->lwork = reinterpret_cast<Cx<double>*>(w + 2 * bU);
+  } else if (lib_malloc_async(&pc->U, sizeof(Cx<T>) * r * n, s) != hipSuccess ||
+             lib_malloc_async(&pc->Y, sizeof(Cx<T>) * r * n, s) != hipSuccess ||
+             lib_malloc_async(reinterpret_cast<void**>(&pc->lwork), sizeof(Cx<double>) * pc->lwork_elems, s) !=
+                 hipSuccess) {
     (void)hipGetLastError();
     return fail(LSOP_ENOMEM, "HODLR build workspace allocation failed");
   }
@@ -844,6 +931,20 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
   pc->kept = r;
   pc->built = true;
   return LSOP_OK;
+}
+
+// Workspace of lsop_set_problem (the transposed FP64 intermediate of the spectrum) and of series_solve on nvec
+// right-hand sides (the layouts carved in series_solve).
+size_t spectrum_ws_bytes(const lsop_op* op) { return sizeof(Cx<double>) * (size_t)op->px() * op->pz(); }
+
+size_t series_ws_bytes(const lsop_op* op, int nvec, int init) {
+  const size_t n = op->n();
+  const size_t tail = align_up(sizeof(double) * nvec) + align_up(sizeof(int) * nvec);
+  if (op->dtype != LSOP_MIXED) {
+    const size_t esz = op->dtype == LSOP_C64 ? sizeof(Cx<float>) : sizeof(Cx<double>);
+    return align_up(esz * n * nvec) * (init == LSOP_INIT_BEST ? 2 : 1) + tail;
+  }
+  return align_up(sizeof(Cx<double>) * n * nvec) + 3 * align_up(sizeof(Cx<float>) * n * nvec) + tail;
 }
 
 // --------------------------------------------------------------- series
@@ -980,7 +1081,7 @@ int grow_buf(void** p, size_t* cap, size_t need, size_t* bytes) {
     *p = nullptr;
     *cap = 0;
   }
-  if (hipMalloc(p, need) != hipSuccess) {
+  if (lib_malloc(p, need) != hipSuccess) {
     (void)hipGetLastError();
     return fail(LSOP_ENOMEM, "batch allocation of " + std::to_string(need) + " bytes failed");
   }
@@ -1313,71 +1414,125 @@ extern "C" {
 
 const char* lsop_last_error(void) { return g_err.c_str(); }
 
-int lsop_create(int nx, int nz, int dtype, int max_vec, lsop_op** out) {
-  if (!out) return fail(LSOP_EINVAL, "null output handle");
-  *out = nullptr;
+}  // extern "C"
+
+namespace lsop {
+namespace {
+
+// Validates lsop_create's arguments and fills the plan fields of a fresh handle.
+int op_plan(int nx, int nz, int dtype, int max_vec, lsop_op* op) {
   if (nx < 1 || nz < 1 || max_vec < 1) return fail(LSOP_EINVAL, "nx, nz and max_vec must be >= 1");
   if (dtype != LSOP_C64 && dtype != LSOP_C128 && dtype != LSOP_MIXED) return fail(LSOP_EUNSUPPORTED, "bad dtype");
   const int lx = fft_length_for(nx), lz = fft_length_for(nz);
   if (lx < 0 || lz < 0) return fail(LSOP_EUNSUPPORTED, "grid side exceeds the largest FFT length (2048)");
   if ((size_t)nx * nz > (size_t)INT32_MAX / 2) return fail(LSOP_EUNSUPPORTED, "grid too large");
-  lsop_op* op = new lsop_op();
   op->nx = nx;
   op->nz = nz;
   op->lx = lx;
   op->lz = lz;
   op->dtype = dtype;
   op->max_vec = max_vec;
+  op->src_cap = 4096;
   if (const char* ct = getenv("LSOP_COL_TILE")) op->col_tile = atoi(ct);
+  return LSOP_OK;
+}
+
+// Every device buffer of an operator's state, in one fixed order (the size query walks the same list).
+int op_buffers(lsop_op* op, Alloc& a) {
   const size_t n = op->n();
   const size_t px = op->px(), pz = op->pz();
+  const int lx = op->lx, lz = op->lz;
   int st = 0;
-  auto& o = op->owned;
-  auto& b = op->bytes;
-  st |= dev_alloc(o, b, &op->chi64, sizeof(double) * n);
-  if (op->has32()) st |= dev_alloc(o, b, &op->chi32, sizeof(float) * n);
-  st |= dev_alloc(o, b, &op->ktab, sizeof(Cx<double>) * n);
-  if (op->has64()) st |= dev_alloc(o, b, &op->gs64, sizeof(Cx<double>) * px * pz);
-  if (op->has32()) st |= dev_alloc(o, b, &op->gs32, sizeof(Cx<float>) * px * pz);
-  st |= dev_alloc(o, b, &op->tw2x64, sizeof(Cx<double>) * 2 * lx);
-  st |= dev_alloc(o, b, &op->tw2z64, sizeof(Cx<double>) * 2 * lz);
+  st |= dev_alloc(a, &op->chi64, sizeof(double) * n);
+  if (op->has32()) st |= dev_alloc(a, &op->chi32, sizeof(float) * n);
+  st |= dev_alloc(a, &op->ktab, sizeof(Cx<double>) * n);
+  if (op->has64()) st |= dev_alloc(a, &op->gs64, sizeof(Cx<double>) * px * pz);
+  if (op->has32()) st |= dev_alloc(a, &op->gs32, sizeof(Cx<float>) * px * pz);
+  st |= dev_alloc(a, &op->tw2x64, sizeof(Cx<double>) * 2 * lx);
+  st |= dev_alloc(a, &op->tw2z64, sizeof(Cx<double>) * 2 * lz);
   if (op->has32()) {
-    st |= dev_alloc(o, b, &op->tw2x32, sizeof(Cx<float>) * 2 * lx);
-    st |= dev_alloc(o, b, &op->tw2z32, sizeof(Cx<float>) * 2 * lz);
+    st |= dev_alloc(a, &op->tw2x32, sizeof(Cx<float>) * 2 * lx);
+    st |= dev_alloc(a, &op->tw2z32, sizeof(Cx<float>) * 2 * lz);
   }
   const size_t esz = op->has64() ? sizeof(Cx<double>) : sizeof(Cx<float>);
-  st |= dev_alloc(o, b, &op->tmp, esz * (size_t)max_vec * nx * pz);
-  st |= dev_alloc(o, b, &op->flag, 256);
-  op->src_cap = 4096;
-  st |= dev_alloc(o, b, &op->dsrc, sizeof(int) * 2 * op->src_cap);
-  st |= dev_alloc(o, b, &op->damp, sizeof(Cx<double>) * op->src_cap);
-  if (st) {
-    free_all(op->owned);
-    delete op;
-    return LSOP_ENOMEM;
-  }
-  // twiddle tables
+  st |= dev_alloc(a, &op->tmp, esz * (size_t)op->max_vec * op->nx * pz);
+  st |= dev_alloc(a, &op->flag, 256);
+  st |= dev_alloc(a, &op->dsrc, sizeof(int) * 2 * op->src_cap);
+  st |= dev_alloc(a, &op->damp, sizeof(Cx<double>) * op->src_cap);
+  return st ? LSOP_ENOMEM : LSOP_OK;
+}
+
+// Twiddle tables of both axes (host-computed, uploaded synchronously).
+int op_twiddles(lsop_op* op) {
   for (int axis = 0; axis < 2; ++axis) {
-    const int L = axis == 0 ? lx : lz;
+    const int L = axis == 0 ? op->lx : op->lz;
     std::vector<Cx<double>> w = twiddles(L);
     Cx<double>* d64 = axis == 0 ? op->tw2x64 : op->tw2z64;
-    if (hipMemcpy(d64, w.data(), sizeof(Cx<double>) * w.size(), hipMemcpyHostToDevice) != hipSuccess) {
-      free_all(op->owned);
-      delete op;
+    if (hipMemcpy(d64, w.data(), sizeof(Cx<double>) * w.size(), hipMemcpyHostToDevice) != hipSuccess)
       return fail(LSOP_EHIP, "twiddle upload failed");
-    }
     if (op->has32()) {
       std::vector<Cx<float>> w32(w.size());
       for (size_t t = 0; t < w.size(); ++t) w32[t] = ccast<float>(w[t]);
       Cx<float>* d32 = axis == 0 ? op->tw2x32 : op->tw2z32;
-      if (hipMemcpy(d32, w32.data(), sizeof(Cx<float>) * w32.size(), hipMemcpyHostToDevice) != hipSuccess) {
-        free_all(op->owned);
-        delete op;
+      if (hipMemcpy(d32, w32.data(), sizeof(Cx<float>) * w32.size(), hipMemcpyHostToDevice) != hipSuccess)
         return fail(LSOP_EHIP, "twiddle upload failed");
-      }
     }
   }
+  return LSOP_OK;
+}
+
+int op_create(int nx, int nz, int dtype, int max_vec, void* state, size_t state_bytes, lsop_op** out) {
+  if (!out) return fail(LSOP_EINVAL, "null output handle");
+  *out = nullptr;
+  lsop_op* op = new lsop_op();
+  int st = op_plan(nx, nz, dtype, max_vec, op);
+  if (st) {
+    delete op;
+    return st;
+  }
+  Alloc a;
+  a.owned = &op->owned;
+  a.bytes = &op->bytes;
+  if (state) {
+    a.base = reinterpret_cast<char*>(state);
+    a.cap = state_bytes;
+    op->state_external = true;
+  }
+  if ((st = op_buffers(op, a)) || (st = op_twiddles(op))) {
+    free_all(op->owned);
+    delete op;
+    return st;
+  }
   *out = op;
+  return LSOP_OK;
+}
+
+}  // namespace
+}  // namespace lsop
+
+extern "C" {
+
+int lsop_create(int nx, int nz, int dtype, int max_vec, lsop_op** out) {
+  return op_create(nx, nz, dtype, max_vec, nullptr, 0, out);
+}
+
+int lsop_create_in(int nx, int nz, int dtype, int max_vec, void* state_dev, size_t state_bytes, lsop_op** out) {
+  if (!state_dev || (reinterpret_cast<uintptr_t>(state_dev) & 255) != 0)
+    return fail(LSOP_EINVAL, "state buffer must be non-null and 256-byte aligned");
+  return op_create(nx, nz, dtype, max_vec, state_dev, state_bytes, out);
+}
+
+int lsop_state_bytes(int nx, int nz, int dtype, int max_vec, size_t* bytes) {
+  if (!bytes) return fail(LSOP_EINVAL, "null output");
+  lsop_op op;
+  int st = op_plan(nx, nz, dtype, max_vec, &op);
+  if (st) return st;
+  size_t total = 0;
+  Alloc a;
+  a.bytes = &total;
+  a.count_only = true;
+  (void)op_buffers(&op, a);
+  *bytes = total;
   return LSOP_OK;
 }
 
@@ -1411,8 +1566,7 @@ int lsop_set_problem(lsop_op* op, const double* vel_dev, double h, double freq_h
   const Cx<double> self = c * Cx<double>{j1, y1} - Cx<double>{1.0 / (k0 * k0), 0.0};
   LSOP_HIP(launch_table(op->ktab, op->nx, op->nz, k0 * h, cj1, self, s));
   // spectrum: the row pass writes a transposed px x pz FP64 intermediate
-  const size_t s1 = sizeof(Cx<double>) * (size_t)op->px() * op->pz();
-  int st = grow_scratch(op, s1);
+  int st = grow_scratch(op, spectrum_ws_bytes(op));
   if (st) return st;
   LSOP_HIP(launch_spectrum(op->lx, op->lz, op->ktab, op->nx, op->nz, reinterpret_cast<Cx<double>*>(op->scratch),
                            op->gs64, op->gs32, op->tw2x64, op->tw2z64, s));
@@ -1508,7 +1662,7 @@ int lsop_info(const lsop_op* op, lsop_op_info* info) {
   info->lz = op->lz;
   info->dtype = op->dtype;
   info->max_vec = op->max_vec;
-  info->state_bytes = op->bytes + op->scratch_bytes;
+  info->state_bytes = op->bytes + (op->ws_external ? 0 : op->scratch_bytes);
   info->col_tile = op->col_tile;
   return LSOP_OK;
 }
@@ -1517,59 +1671,81 @@ void lsop_destroy(lsop_op* op) {
   if (!op) return;
   (void)hipDeviceSynchronize();
   free_all(op->owned);
-  if (op->scratch) (void)hipFree(op->scratch);
+  if (op->scratch && !op->ws_external) (void)hipFree(op->scratch);
   delete op;
 }
 
+int lsop_workspace_bytes(const lsop_op* op, int nvec, int init, size_t* bytes) {
+  if (!op || !bytes) return fail(LSOP_EINVAL, "null argument");
+  if (nvec < 0 || init < 0 || init > 3) return fail(LSOP_EINVAL, "bad nvec or init");
+  *bytes = std::max(spectrum_ws_bytes(op), series_ws_bytes(op, nvec, init));
+  return LSOP_OK;
+}
+
+int lsop_attach_workspace(lsop_op* op, void* ws_dev, size_t ws_bytes) {
+  if (!op) return fail(LSOP_EINVAL, "null operator handle");
+  if (ws_dev && (reinterpret_cast<uintptr_t>(ws_dev) & 255) != 0)
+    return fail(LSOP_EINVAL, "workspace must be 256-byte aligned");
+  if (op->scratch && !op->ws_external) {
+    LSOP_HIP(hipDeviceSynchronize());
+    (void)hipFree(op->scratch);
+  }
+  op->scratch = ws_dev;
+  op->scratch_bytes = ws_dev ? ws_bytes : 0;
+  op->ws_external = ws_dev != nullptr;
+  return LSOP_OK;
+}
+
+int lsop_alloc_count(size_t* calls) {
+  if (!calls) return fail(LSOP_EINVAL, "null output");
+  *calls = g_allocs.load();
+  return LSOP_OK;
+}
+
 // ------------------------------------------------------------ preconditioner
-int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out) {
-  if (!out) return fail(LSOP_EINVAL, "null output handle");
-  *out = nullptr;
+}  // extern "C"
+
+namespace lsop {
+namespace {
+
+// Validates precond_create's parameters and fills the plan fields (no device memory).
+int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
   if (!op || !p) return fail(LSOP_EINVAL, "null argument");
-  if (p->kind != LSOP_PC_IDENTITY && p->kind != LSOP_PC_LOWRANK && p->kind != LSOP_PC_HODLR)
+  if (p->kind != LSOP_PC_IDENTITY && p->kind != LSOP_PC_LOWRANK && p->kind != LSOP_PC_HODLR &&
+      p->kind != LSOP_PC_SCALAR)
     return fail(LSOP_EINVAL, "bad preconditioner kind");
-  if (p->kind != LSOP_PC_IDENTITY && (p->rank < 1 || p->rank > 256 || p->power_iters < 0))
+  if (p->kind == LSOP_PC_SCALAR && (!std::isfinite(p->alpha) || p->alpha == 0.0))
+    return fail(LSOP_EINVAL, "alpha must be finite and non-zero");
+  if ((p->kind == LSOP_PC_LOWRANK || p->kind == LSOP_PC_HODLR) &&
+      (p->rank < 1 || p->rank > 256 || p->power_iters < 0))
     return fail(LSOP_EINVAL, "rank must be in [1, 256] and power_iters >= 0");
+  if (p->kind == LSOP_PC_LOWRANK && (p->oversample < 0 || p->rank + p->oversample > 256))
+    return fail(LSOP_EINVAL, "oversample must be >= 0 with rank + oversample <= 256");
+  if (p->kind != LSOP_PC_LOWRANK && p->oversample != 0)
+    return fail(LSOP_EINVAL, "oversampling applies to the low-rank preconditioner only");
   if (p->kind == LSOP_PC_HODLR) {
     if (p->levels < 1 || p->levels > 16 || op->nx % (1 << p->levels) != 0)
       return fail(LSOP_EINVAL, "HODLR levels must be >= 1 with nx divisible by 2^levels");
     const size_t nl = (size_t)(op->nx >> p->levels) * op->nz;
     if (nl % 64 != 0 || nl > 8192)
       return fail(LSOP_EINVAL, "HODLR leaf size (nx / 2^levels) * nz must be a multiple of 64 and at most 8192");
+    for (int lv = 0; lv < p->levels; ++lv)
+      if (fft_length_sub(op->nx >> lv) < 0) return fail(LSOP_EUNSUPPORTED, "unsupported HODLR level width");
   }
-  lsop_precond* pc = new lsop_precond();
   pc->op = op;
   pc->kind = p->kind;
   pc->seed = p->seed;
+  pc->alpha = p->alpha;
   pc->dt = op->dtype == LSOP_C128 ? LSOP_C128 : LSOP_C64;
-  if (p->kind == LSOP_PC_IDENTITY) {
-    pc->built = true;
-    *out = pc;
-    return LSOP_OK;
-  }
+  if (p->kind == LSOP_PC_IDENTITY || p->kind == LSOP_PC_SCALAR) return LSOP_OK;
   pc->rank = p->rank;
+  pc->probes = p->kind == LSOP_PC_LOWRANK ? p->rank + p->oversample : p->rank;
   pc->q = p->power_iters;
   const size_t n = op->n();
-  const size_t esz = pc->dt == LSOP_C128 ? sizeof(Cx<double>) : sizeof(Cx<float>);
-  const int r = pc->rank;
-  pc->tcap = std::max(op->max_vec, r);
+  pc->tcap = std::max(op->max_vec, pc->probes);
   size_t ks = n / 4096;
   pc->ksplit = (int)std::max<size_t>(1, std::min<size_t>(ks, 256));
-  int st = 0;
-  auto& o = pc->owned;
-  auto& b = pc->bytes;
-  if (p->kind == LSOP_PC_LOWRANK) {
-    st |= dev_alloc(o, b, &pc->U, esz * r * n);
-    st |= dev_alloc(o, b, &pc->W, esz * r * n);
-    st |= dev_alloc(o, b, &pc->Y, esz * r * n);
-    st |= dev_alloc(o, b, &pc->Z, sizeof(Cx<double>) * r * r);
-    // small: G / M (r*r), X / LU work (2 r*r), T1, T2 (r * tcap each)
-    st |= dev_alloc(o, b, &pc->small, sizeof(Cx<double>) * ((size_t)3 * r * r + (size_t)2 * r * pc->tcap));
-    pc->part_cap = (size_t)pc->ksplit * r * pc->tcap;
-    st |= dev_alloc(o, b, &pc->part, sizeof(Cx<double>) * pc->part_cap);
-    st |= dev_alloc(o, b, &pc->dflag, 256);
-  } else {
-    // HODLR
+  if (p->kind == LSOP_PC_HODLR) {
     pc->levels = p->levels;
     pc->leaf_w = op->nx >> p->levels;
     pc->nleaf = 1 << p->levels;
@@ -1585,57 +1761,147 @@ int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out
     (void)block_inverse_temps(nl, pc->leaf_chunk, &lw);
     lw += (size_t)pc->leaf_chunk * nl * nl;
     pc->lwork_elems = lw;
-    // the FP64 leaf workspace and the sampling buffers U, Y live only during precond_build
-    st |= dev_alloc(o, b, &pc->dinv, esz * (size_t)pc->nleaf * nl * nl);
-    st |= dev_alloc(o, b, &pc->hy, esz * (size_t)pc->tcap * n);
-    const size_t small = (size_t)pc->maxseg * r * pc->tcap;
-    st |= dev_alloc(o, b, &pc->hG, sizeof(Cx<double>) * small);
-    st |= dev_alloc(o, b, &pc->hX, sizeof(Cx<double>) * small);
-    if (pc->dt == LSOP_C64) {
-      st |= dev_alloc(o, b, &pc->hG32, sizeof(Cx<float>) * small);
-      st |= dev_alloc(o, b, &pc->hX32, sizeof(Cx<float>) * small);
-    }
-    // node cores: recursion temporaries (< r^2 per node), S S^{-1} (r^2 per node), pivoted fallback work (2 r^2)
-    st |= dev_alloc(o, b, &pc->hK, sizeof(Cx<double>) * ((size_t)(pc->maxseg / 2) * 3 * r * r + 2 * (size_t)r * r));
-    pc->part_cap = (size_t)pc->ksub_cap * r * pc->tcap;
-    st |= dev_alloc(o, b, &pc->part, sizeof(Cx<double>) * pc->part_cap);
-    st |= dev_alloc(o, b, &pc->hflag, sizeof(int) * (4 * (size_t)pc->maxseg + pc->leaf_chunk + 64));
     pc->lev.resize(p->levels);
-    for (int lv = 0; lv < p->levels && !st; ++lv) {
-      hodlr_level& L = pc->lev[lv];
-      L.width = op->nx >> lv;
-      L.lx = fft_length_sub(L.width);
-      if (L.lx < 0) {
-        st = LSOP_EUNSUPPORTED;
-        break;
-      }
-      const int nodes = 1 << lv;
-      st |= dev_alloc(o, b, &L.V, esz * r * n);
-      st |= dev_alloc(o, b, &L.Wp, esz * r * n);
-      st |= dev_alloc(o, b, &L.kinv, sizeof(Cx<double>) * (size_t)nodes * 4 * r * r);
-      if (pc->dt == LSOP_C64) st |= dev_alloc(o, b, &L.kinv32, sizeof(Cx<float>) * (size_t)nodes * 4 * r * r);
-      const size_t gsz = (size_t)2 * op->pz() * L.lx;
-      if (pc->dt == LSOP_C128) st |= dev_alloc(o, b, &L.gs64, sizeof(Cx<double>) * gsz);
-      else st |= dev_alloc(o, b, &L.gs32, sizeof(Cx<float>) * gsz);
-      st |= dev_alloc(o, b, &L.tw64, sizeof(Cx<double>) * 2 * L.lx);
-      st |= dev_alloc(o, b, &L.tw32, sizeof(Cx<float>) * 2 * L.lx);
-      if (!st) {
-        std::vector<Cx<double>> w = twiddles(L.lx);
-        std::vector<Cx<float>> w32(w.size());
-        for (size_t t = 0; t < w.size(); ++t) w32[t] = ccast<float>(w[t]);
-        if (hipMemcpy(L.tw64, w.data(), sizeof(Cx<double>) * w.size(), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(L.tw32, w32.data(), sizeof(Cx<float>) * w32.size(), hipMemcpyHostToDevice) != hipSuccess)
-          st = LSOP_EHIP;
-      }
+    for (int lv = 0; lv < p->levels; ++lv) {
+      pc->lev[lv].width = op->nx >> lv;
+      pc->lev[lv].lx = fft_length_sub(pc->lev[lv].width);
     }
+  }
+  return LSOP_OK;
+}
+
+// Every device buffer of a preconditioner's state, in one fixed order (the size query walks the same list).
+int pc_buffers(lsop_precond* pc, Alloc& a) {
+  if (pc->kind == LSOP_PC_IDENTITY || pc->kind == LSOP_PC_SCALAR) return LSOP_OK;
+  const lsop_op* op = pc->op;
+  const size_t n = op->n();
+  const size_t esz = pc->dt == LSOP_C128 ? sizeof(Cx<double>) : sizeof(Cx<float>);
+  const int r = pc->rank, l = pc->probes;
+  int st = 0;
+  if (pc->kind == LSOP_PC_LOWRANK) {
+    st |= dev_alloc(a, &pc->U, esz * l * n);
+    st |= dev_alloc(a, &pc->W, esz * l * n);
+    st |= dev_alloc(a, &pc->Y, esz * l * n);
+    st |= dev_alloc(a, &pc->Z, sizeof(Cx<double>) * r * r);
+    // small: G / M (l*l), X / LU work (2 l*l), T1, T2 (l * tcap each)
+    st |= dev_alloc(a, &pc->small, sizeof(Cx<double>) * ((size_t)3 * l * l + (size_t)2 * l * pc->tcap));
+    pc->part_cap = (size_t)pc->ksplit * l * pc->tcap;
+    st |= dev_alloc(a, &pc->part, sizeof(Cx<double>) * pc->part_cap);
+    st |= dev_alloc(a, &pc->dflag, 256);
+    if (l > r) {
+      st |= dev_alloc(a, &pc->Q2, esz * l * n);
+      st |= dev_alloc(a, &pc->svdw, sizeof(Cx<double>) * ((size_t)3 * l * l + (size_t)2 * l * r));
+    }
+    return st ? LSOP_ENOMEM : LSOP_OK;
+  }
+  // HODLR: the FP64 leaf workspace and the sampling buffers U, Y live only during precond_build
+  const int nl = pc->leaf_w * op->nz;
+  st |= dev_alloc(a, &pc->dinv, esz * (size_t)pc->nleaf * nl * nl);
+  st |= dev_alloc(a, &pc->hy, esz * (size_t)pc->tcap * n);
+  const size_t small = (size_t)pc->maxseg * r * pc->tcap;
+  st |= dev_alloc(a, &pc->hG, sizeof(Cx<double>) * small);
+  st |= dev_alloc(a, &pc->hX, sizeof(Cx<double>) * small);
+  if (pc->dt == LSOP_C64) {
+    st |= dev_alloc(a, &pc->hG32, sizeof(Cx<float>) * small);
+    st |= dev_alloc(a, &pc->hX32, sizeof(Cx<float>) * small);
+  }
+  // node cores: recursion temporaries (< r^2 per node), S S^{-1} (r^2 per node), pivoted fallback work (2 r^2)
+  st |= dev_alloc(a, &pc->hK, sizeof(Cx<double>) * ((size_t)(pc->maxseg / 2) * 3 * r * r + 2 * (size_t)r * r));
+  pc->part_cap = (size_t)pc->ksub_cap * r * pc->tcap;
+  st |= dev_alloc(a, &pc->part, sizeof(Cx<double>) * pc->part_cap);
+  st |= dev_alloc(a, &pc->hflag, sizeof(int) * (4 * (size_t)pc->maxseg + pc->leaf_chunk + 64));
+  for (int lv = 0; lv < pc->levels; ++lv) {
+    hodlr_level& L = pc->lev[lv];
+    const int nodes = 1 << lv;
+    st |= dev_alloc(a, &L.V, esz * r * n);
+    st |= dev_alloc(a, &L.Wp, esz * r * n);
+    st |= dev_alloc(a, &L.kinv, sizeof(Cx<double>) * (size_t)nodes * 4 * r * r);
+    if (pc->dt == LSOP_C64) st |= dev_alloc(a, &L.kinv32, sizeof(Cx<float>) * (size_t)nodes * 4 * r * r);
+    const size_t gsz = (size_t)2 * op->pz() * L.lx;
+    if (pc->dt == LSOP_C128) st |= dev_alloc(a, &L.gs64, sizeof(Cx<double>) * gsz);
+    else st |= dev_alloc(a, &L.gs32, sizeof(Cx<float>) * gsz);
+    st |= dev_alloc(a, &L.tw64, sizeof(Cx<double>) * 2 * L.lx);
+    st |= dev_alloc(a, &L.tw32, sizeof(Cx<float>) * 2 * L.lx);
+  }
+  return st ? LSOP_ENOMEM : LSOP_OK;
+}
+
+// Transient workspace of precond_build: HODLR sampling buffers and FP64 leaf workspace (or the sub-domain
+// spectrum intermediate, if larger); none for the other kinds.
+size_t pc_build_ws_bytes(const lsop_precond* pc) {
+  if (pc->kind != LSOP_PC_HODLR) return 0;
+  const size_t n = pc->op->n();
+  const size_t esz = pc->dt == LSOP_C128 ? sizeof(Cx<double>) : sizeof(Cx<float>);
+  size_t spec = 0;
+  for (const hodlr_level& L : pc->lev) spec = std::max(spec, sizeof(Cx<double>) * (size_t)(2 * L.lx) * pc->op->pz());
+  return std::max(spec, 2 * align_up(esz * pc->rank * n) + align_up(sizeof(Cx<double>) * pc->lwork_elems));
+}
+
+int pc_create(lsop_op* op, const lsop_precond_params* p, void* state, size_t state_bytes, lsop_precond** out) {
+  if (!out) return fail(LSOP_EINVAL, "null output handle");
+  *out = nullptr;
+  lsop_precond* pc = new lsop_precond();
+  int st = pc_plan(op, p, pc);
+  if (st) {
+    delete pc;
+    return st;
+  }
+  if (pc->kind == LSOP_PC_IDENTITY || pc->kind == LSOP_PC_SCALAR) pc->built = true;
+  Alloc a;
+  a.owned = &pc->owned;
+  a.bytes = &pc->bytes;
+  if (state) {
+    a.base = reinterpret_cast<char*>(state);
+    a.cap = state_bytes;
+    pc->state_external = true;
+  }
+  st = pc_buffers(pc, a);
+  for (int lv = 0; lv < pc->levels && !st; ++lv) {
+    hodlr_level& L = pc->lev[lv];
+    std::vector<Cx<double>> w = twiddles(L.lx);
+    std::vector<Cx<float>> w32(w.size());
+    for (size_t t = 0; t < w.size(); ++t) w32[t] = ccast<float>(w[t]);
+    if (hipMemcpy(L.tw64, w.data(), sizeof(Cx<double>) * w.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(L.tw32, w32.data(), sizeof(Cx<float>) * w32.size(), hipMemcpyHostToDevice) != hipSuccess)
+      st = fail(LSOP_EHIP, "twiddle upload failed");
   }
   if (st) {
     free_all(pc->owned);
     delete pc;
-    return st == LSOP_EUNSUPPORTED ? fail(st, "unsupported HODLR level width")
-                                   : (st == LSOP_EHIP ? fail(st, "twiddle upload failed") : LSOP_ENOMEM);
+    return st;
   }
   *out = pc;
+  return LSOP_OK;
+}
+
+}  // namespace
+}  // namespace lsop
+
+extern "C" {
+
+int precond_create(lsop_op* op, const lsop_precond_params* p, lsop_precond** out) {
+  return pc_create(op, p, nullptr, 0, out);
+}
+
+int precond_create_in(lsop_op* op, const lsop_precond_params* p, void* state_dev, size_t state_bytes,
+                      lsop_precond** out) {
+  if (!state_dev || (reinterpret_cast<uintptr_t>(state_dev) & 255) != 0)
+    return fail(LSOP_EINVAL, "state buffer must be non-null and 256-byte aligned");
+  return pc_create(op, p, state_dev, state_bytes, out);
+}
+
+int precond_state_bytes(const lsop_op* op, const lsop_precond_params* p, size_t* state, size_t* build_ws) {
+  if (!state || !build_ws) return fail(LSOP_EINVAL, "null output");
+  lsop_precond pc;
+  int st = pc_plan(const_cast<lsop_op*>(op), p, &pc);
+  if (st) return st;
+  size_t total = 0;
+  Alloc a;
+  a.bytes = &total;
+  a.count_only = true;
+  (void)pc_buffers(&pc, a);
+  *state = total;
+  *build_ws = pc_build_ws_bytes(&pc);
   return LSOP_OK;
 }
 
@@ -1643,7 +1909,7 @@ int precond_build(lsop_precond* pc, const void* omega_dev, void* stream) {
   if (!pc) return fail(LSOP_EINVAL, "null preconditioner");
   int st = check_op(pc->op);
   if (st) return st;
-  if (pc->kind == LSOP_PC_IDENTITY) return LSOP_OK;
+  if (pc->kind == LSOP_PC_IDENTITY || pc->kind == LSOP_PC_SCALAR) return LSOP_OK;
   pc->built = false;
   if (pc->kind == LSOP_PC_HODLR) {
     if (pc->dt == LSOP_C128) return hodlr_build<double>(pc, (const double*)omega_dev, S(stream));
@@ -1747,9 +2013,7 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
   if (op->dtype != LSOP_MIXED) {
     const size_t esz = op->dtype == LSOP_C64 ? sizeof(Cx<float>) : sizeof(Cx<double>);
     const size_t vb = align_up(esz * n * nvec);
-    const size_t need = vb * (p->init == LSOP_INIT_BEST ? 2 : 1) + align_up(sizeof(double) * nvec) +
-                        align_up(sizeof(int) * nvec);
-    if ((st = grow_scratch(op, need))) return st;
+    if ((st = grow_scratch(op, series_ws_bytes(op, nvec, p->init)))) return st;
     char* base = (char*)op->scratch;
     void* r = base;
     double* dn = (double*)(base + vb);
@@ -1768,8 +2032,7 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
   const int refine_max = p->refine_max > 0 ? p->refine_max : 8;
   const double inner_tol = p->inner_tol > 0 ? p->inner_tol : 1e-5;
   const size_t b64 = align_up(sizeof(Cx<double>) * n * nvec), b32 = align_up(sizeof(Cx<float>) * n * nvec);
-  const size_t need = b64 + 3 * b32 + align_up(sizeof(double) * nvec) + align_up(sizeof(int) * nvec);
-  if ((st = grow_scratch(op, need))) return st;
+  if ((st = grow_scratch(op, series_ws_bytes(op, nvec, p->init)))) return st;
   char* base = (char*)op->scratch;
   Cx<double>* r64 = (Cx<double>*)base;
   Cx<float>* rhs32 = (Cx<float>*)(base + b64);

@@ -21,6 +21,9 @@ int fft_length_sub(int n);
 // Error reporting (per thread).
 void set_error(const std::string& msg);
 int fail(int status, const std::string& msg);
+// Every device allocation of the library goes through these (counted for lsop_alloc_count).
+hipError_t lib_malloc(void** p, size_t nbytes);
+hipError_t lib_malloc_async(void** p, size_t nbytes, hipStream_t s);
 
 #define LSOP_HIP(...)                                                                       \
   do {                                                                                      \
@@ -145,6 +148,11 @@ hipError_t launch_small_gemm(const Cx<double>* A, const Cx<double>* B, Cx<double
 // FP32 Gauss-Jordan inverses of batch blocks of na <= 64 (as launch_lu_inverse, plain form)
 hipError_t launch_lu_inverse_small_f32(const Cx<float>* M, size_t ldm, size_t sm, Cx<float>* Z, size_t ldz, size_t sz,
                                       int na, bool plain, int* singular, int batch, hipStream_t s);
+// Truncation of an oversampled factorisation: one-sided Jacobi SVD of R2^H (R2 row-major l x l, FP64) in one
+// workgroup; M = (U_b S)(:, :k) and Mp = V_b(:, :k), both row-major l x k; Bc, Vc: l * l work each; *kept
+// (cleared by the caller) receives the number of non-zero singular values among the k kept.  l <= 256.
+hipError_t launch_svd_trunc(const Cx<double>* R2, int l, int k, Cx<double>* Bc, Cx<double>* Vc, Cx<double>* M,
+                            Cx<double>* Mp, int* kept, hipStream_t s);
 // HODLR: dense leaf blocks of I - G0 V (formed in FP64, stored as To), leaves leaf0 .. leaf0 + nleaf - 1 of nl cells
 template <typename To>
 hipError_t launch_leaf_form(const Cx<double>* ktab, const double* chi, Cx<To>* out, int nz, int nl, int leaf0,
@@ -206,9 +214,11 @@ struct lsop_op {
   Cx<double>* damp = nullptr;
   int src_cap = 0;
   size_t bytes = 0;
-  // growable scratch for solvers
+  // growable scratch for solvers (or the caller's workspace, see lsop_attach_workspace)
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
+  bool ws_external = false;     // scratch is the caller's: never grown, reallocated or freed
+  bool state_external = false;  // device state carved from the caller's buffer (lsop_create_in)
   std::vector<void*> owned;
 };
 
@@ -228,6 +238,11 @@ struct hodlr_level {
 struct lsop_precond {
   lsop_op* op = nullptr;
   int kind = 0, rank = 0, q = 0, kept = 0;
+  int probes = 0;          // probe vectors l = rank + oversample (LOWRANK)
+  double alpha = 0.0;      // SCALAR: H = alpha I
+  void* Q2 = nullptr;      // [probes][n] orthonormal basis of W~ (oversampled builds)
+  Cx<double>* svdw = nullptr;  // R2, Bc, Vc (probes^2 each), M, Mp (probes * rank each)
+  bool state_external = false;
   // HODLR (kind LSOP_PC_HODLR)
   int levels = 0, leaf_w = 0, nleaf = 0, leaf_chunk = 0;
   std::vector<hodlr_level> lev;

@@ -76,7 +76,7 @@ hipStream_t SS(void* s) { return reinterpret_cast<hipStream_t>(s); }
 template <typename P>
 int nn_alloc(unet* u, P** out, size_t bytes) {
   void* p = nullptr;
-  if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) {
+  if (lib_malloc(&p, bytes ? bytes : 16) != hipSuccess) {
     (void)hipGetLastError();
     return fail(LSOP_ENOMEM, "network allocation of " + std::to_string(bytes) + " bytes failed");
   }
@@ -319,7 +319,7 @@ int unet_init_params(unet* u, unsigned long long seed, void* stream) {
   // one standard normal draw per parameter: the range finder's Philox4x32-10 generator, which writes real
   // draws as complex numbers with zero imaginary part (read with stride 2) into a temporary buffer
   Cx<float>* z = nullptr;
-  if (hipMalloc(&z, sizeof(Cx<float>) * u->nparams) != hipSuccess) {
+  if (lib_malloc(reinterpret_cast<void**>(&z), sizeof(Cx<float>) * u->nparams) != hipSuccess) {
     (void)hipGetLastError();
     return fail(LSOP_ENOMEM, "unet_init_params: temporary of " + std::to_string(u->nparams) + " draws");
   }

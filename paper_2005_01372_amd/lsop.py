@@ -23,11 +23,13 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", NOT_
                 DIVERGED: "DIVERGED", ESINGULAR: "ESINGULAR", EUNSUPPORTED: "EUNSUPPORTED"}
 C64, C128, MIXED = 0, 1, 2
 MODES = {"A": 0, "G0V": 1, "AH": 2, "VHG0H": 3}
-PC_IDENTITY, PC_LOWRANK, PC_HODLR = 0, 1, 2
+PC_IDENTITY, PC_LOWRANK, PC_HODLR, PC_SCALAR = 0, 1, 2, 3
 INIT = {"h_rhs": 0, "zero": 1, "user": 2, "best": 3}
 
 EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident", "lsop_autotune",
-           "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "precond_create",
+           "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "lsop_state_bytes",
+           "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count",
+           "precond_state_bytes", "precond_create_in", "precond_create",
            "precond_build", "precond_build_batch", "precond_apply", "precond_info", "precond_destroy", "series_solve",
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
            "lsop_profile_read_kernels", "lsop_batch_create", "lsop_batch_apply", "lsop_batch_autotune",
@@ -49,7 +51,7 @@ class OpInfo(C.Structure):
 
 class PrecondParams(C.Structure):
     _fields_ = [("kind", C.c_int), ("rank", C.c_int), ("power_iters", C.c_int), ("seed", C.c_uint64),
-                ("levels", C.c_int)]
+                ("levels", C.c_int), ("oversample", C.c_int), ("alpha", C.c_double)]
 
 
 class SolveParams(C.Structure):
@@ -90,6 +92,13 @@ def load_library(path=LIB_PATH):
         "lsop_info": (ip, [vp, C.POINTER(OpInfo)]),
         "lsop_destroy": (None, [vp]),
         "lsop_last_error": (C.c_char_p, []),
+        "lsop_state_bytes": (ip, [ip, ip, ip, ip, C.POINTER(C.c_size_t)]),
+        "lsop_create_in": (ip, [ip, ip, ip, ip, vp, C.c_size_t, C.POINTER(vp)]),
+        "lsop_workspace_bytes": (ip, [vp, ip, ip, C.POINTER(C.c_size_t)]),
+        "lsop_attach_workspace": (ip, [vp, vp, C.c_size_t]),
+        "lsop_alloc_count": (ip, [C.POINTER(C.c_size_t)]),
+        "precond_state_bytes": (ip, [vp, C.POINTER(PrecondParams), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+        "precond_create_in": (ip, [vp, C.POINTER(PrecondParams), vp, C.c_size_t, C.POINTER(vp)]),
         "precond_create": (ip, [vp, C.POINTER(PrecondParams), C.POINTER(vp)]),
         "precond_build": (ip, [vp, vp, vp]),
         "precond_build_batch": (ip, [vp, C.c_int, C.c_int]),
@@ -160,6 +169,30 @@ def bessel_host(kind, x):
     return out[0], out[1]
 
 
+def state_bytes(nx, nz, dtype=C128, max_vec=64):
+    """Device bytes of an operator's state (lsop_state_bytes; host only)."""
+    b = C.c_size_t()
+    _check(load_library().lsop_state_bytes(int(nx), int(nz), int(dtype), int(max_vec), C.byref(b)))
+    return b.value
+
+
+def alloc_count():
+    """Device allocations the library has made in this process (lsop_alloc_count)."""
+    c = C.c_size_t()
+    _check(load_library().lsop_alloc_count(C.byref(c)))
+    return c.value
+
+
+def _byte_buffer(t, need, what):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise TypeError(f"{what} must be a contiguous CUDA tensor")
+    if t.numel() * t.element_size() < need:
+        raise ValueError(f"{what} holds {t.numel() * t.element_size()} bytes, {need} needed")
+    if t.data_ptr() % 256:
+        raise ValueError(f"{what} must be 256-byte aligned")
+    return t
+
+
 def profile_enable(on=True):
     _check(load_library().lsop_profile_enable(int(bool(on))))
 
@@ -181,13 +214,22 @@ def profile_read(by_kernel=False):
 
 
 class Operator:
-    """The LS operator of one grid and medium (lsop_create + lsop_set_problem)."""
+    """The LS operator of one grid and medium (lsop_create + lsop_set_problem).
 
-    def __init__(self, nx, nz, dtype=C128, max_vec=64):
+    state: optional caller-owned device buffer (a CUDA tensor of at least state_bytes(...) bytes) that holds the
+    operator's device state instead of library allocations (lsop_create_in); it is kept alive by the object."""
+
+    def __init__(self, nx, nz, dtype=C128, max_vec=64, state=None):
         self.lib = load_library()
         self.nx, self.nz, self.dtype, self.max_vec = int(nx), int(nz), int(dtype), int(max_vec)
         h = C.c_void_p()
-        _check(self.lib.lsop_create(self.nx, self.nz, self.dtype, self.max_vec, C.byref(h)))
+        if state is None:
+            _check(self.lib.lsop_create(self.nx, self.nz, self.dtype, self.max_vec, C.byref(h)))
+        else:
+            need = state_bytes(self.nx, self.nz, self.dtype, self.max_vec)
+            self._state = _byte_buffer(state, need, "state")
+            _check(self.lib.lsop_create_in(self.nx, self.nz, self.dtype, self.max_vec, _ptr(state),
+                                           state.numel() * state.element_size(), C.byref(h)))
         self.handle = h
         self.vec_dtype = torch.complex64 if self.dtype == C64 else torch.complex128
         self.inner_dtype = torch.complex64 if self.dtype in (C64, MIXED) else torch.complex128
@@ -269,6 +311,21 @@ class Operator:
         _check(self.lib.lsop_incident(self.handle, si, sj, ap, len(src_i), _ptr(out), _stream()))
         return out
 
+    def workspace_bytes(self, nvec, init="h_rhs"):
+        """Workspace that set_problem and a series on nvec right-hand sides need (lsop_workspace_bytes)."""
+        b = C.c_size_t()
+        _check(self.lib.lsop_workspace_bytes(self.handle, int(nvec), INIT[init], C.byref(b)))
+        return b.value
+
+    def attach_workspace(self, ws):
+        """Hand the operator a caller-owned workspace (a CUDA tensor; None returns to library-owned growth)."""
+        if ws is None:
+            _check(self.lib.lsop_attach_workspace(self.handle, None, 0))
+        else:
+            _byte_buffer(ws, 1, "workspace")
+            _check(self.lib.lsop_attach_workspace(self.handle, _ptr(ws), ws.numel() * ws.element_size()))
+        self._ws = ws
+
     def autotune(self, nvec):
         """Pick the fastest column-pass tile for batches of nvec vectors; returns the chosen width."""
         _check(self.lib.lsop_autotune(self.handle, int(nvec), _stream()))
@@ -284,13 +341,30 @@ class Preconditioner:
     """H for the series: identity (Born), the randomized low-rank SMW form (Alg. 2 + eq. 12), or the
     inverse of the HODLR approximation of I - G0 V (Section 2.4, ``levels`` tree levels)."""
 
-    def __init__(self, op, kind=PC_LOWRANK, rank=32, power_iters=0, seed=0, levels=0):
+    def __init__(self, op, kind=PC_LOWRANK, rank=32, power_iters=0, seed=0, levels=0, oversample=0, alpha=0.0,
+                 state=None):
         self.op, self.lib = op, op.lib
-        p = PrecondParams(int(kind), int(rank), int(power_iters), int(seed), int(levels))
+        p = PrecondParams(int(kind), int(rank), int(power_iters), int(seed), int(levels), int(oversample),
+                          float(alpha))
         h = C.c_void_p()
-        _check(self.lib.precond_create(op.handle, C.byref(p), C.byref(h)))
+        if state is None:
+            _check(self.lib.precond_create(op.handle, C.byref(p), C.byref(h)))
+        else:
+            need, _ = Preconditioner.state_bytes(op, kind, rank, power_iters, seed, levels, oversample, alpha)
+            self._state = _byte_buffer(state, need, "state")
+            _check(self.lib.precond_create_in(op.handle, C.byref(p), _ptr(state), state.numel() * state.element_size(),
+                                              C.byref(h)))
         self.handle = h
-        self.kind, self.rank, self.levels = kind, rank, levels
+        self.kind, self.rank, self.levels, self.oversample = kind, rank, levels, oversample
+
+    @staticmethod
+    def state_bytes(op, kind=PC_LOWRANK, rank=32, power_iters=0, seed=0, levels=0, oversample=0, alpha=0.0):
+        """(state bytes, build workspace bytes) of a preconditioner of `op` (precond_state_bytes; host only)."""
+        p = PrecondParams(int(kind), int(rank), int(power_iters), int(seed), int(levels), int(oversample),
+                          float(alpha))
+        st, ws = C.c_size_t(), C.c_size_t()
+        _check(op.lib.precond_state_bytes(op.handle, C.byref(p), C.byref(st), C.byref(ws)))
+        return st.value, ws.value
 
     def close(self):
         if getattr(self, "handle", None):
@@ -308,8 +382,8 @@ class Preconditioner:
             omega = torch.as_tensor(omega, dtype=torch.float64)
             omega = (omega if omega.is_cuda else omega.cuda()).contiguous()
             blocks = self.levels if self.kind == PC_HODLR else 1
-            if omega.numel() != blocks * self.rank * self.op.nx * self.op.nz:
-                raise ValueError("omega must hold (levels x) rank x nx*nz values")
+            if omega.numel() != blocks * (self.rank + self.oversample) * self.op.nx * self.op.nz:
+                raise ValueError("omega must hold (levels x) (rank + oversample) x nx*nz values")
             self._omega = omega
         return _check(self.lib.precond_build(self.handle, _ptr(omega) if omega is not None else None, _stream()))
 
