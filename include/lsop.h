@@ -155,6 +155,17 @@ int lsop_attach_workspace(lsop_op* op, void* ws_dev, size_t ws_bytes);
 /* Diagnostic: device allocations (hipMalloc / hipMallocAsync calls) the
  * library has made in this process. */
 int lsop_alloc_count(size_t* calls);
+
+/* lsop_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same passes, with the FFT intermediate in a fixed 64 MiB device array of the
+ * library (allocated with the library's code object on each GPU it runs on and
+ * held until the process ends) instead of the operator's buffer, processed in
+ * chunks of as many vectors as fit.  Makes no device allocation.  Errors: as
+ * lsop_apply; EINVAL if one vector's intermediate (nx * 2 lz complex values of
+ * the operator's widest dtype) exceeds 64 MiB.  All calls on one GPU share the
+ * array: calls that overlap on one GPU (several streams or threads) race. */
+int lsop_apply_noalloc(lsop_op* op, int mode, const void* x_dev, void* y_dev, int nvec, void* stream);
 const char* lsop_last_error(void);
 
 /* ----------------------------------------------------------------------

@@ -253,15 +253,18 @@ struct Dt<double> {
 
 // y = op(x) (mode), or r = A x - rhs with norms when rhs != NULL.  Vectors are
 // addressed through vidx (device, nvec entries) when given, else 0..nvec-1.
+// tmp_in / chunk: an intermediate other than the operator's own, holding `chunk` vectors (default: op->tmp,
+// max_vec vectors).
 template <typename T>
 int apply_impl(lsop_op* op, int mode, const Cx<T>* x, Cx<T>* y, const Cx<T>* rhs, double* rnorm, const int* vidx,
-               int nvec, hipStream_t s) {
+               int nvec, hipStream_t s, void* tmp_in = nullptr, int chunk = 0) {
   const size_t n = op->n();
-  Cx<T>* tmp = reinterpret_cast<Cx<T>*>(op->tmp);
+  Cx<T>* tmp = reinterpret_cast<Cx<T>*>(tmp_in ? tmp_in : op->tmp);
+  const int step = chunk > 0 ? chunk : op->max_vec;
   const bool mulchi = (mode == LSOP_MODE_A || mode == LSOP_MODE_G0V);
   const bool adj = !mulchi;
-  for (int c = 0; c < nvec; c += op->max_vec) {
-    const int m = std::min(op->max_vec, nvec - c);
+  for (int c = 0; c < nvec; c += step) {
+    const int m = std::min(step, nvec - c);
     const int* vc = vidx ? vidx + c : nullptr;
     const size_t off = vidx ? 0 : (size_t)c * n;
     double* rn = rnorm ? rnorm + c : nullptr;
@@ -1405,6 +1408,23 @@ int batch_series(lsop_batch* b, lsop_precond* const* pcs, const Cx<T>* const* rh
 hipError_t prof_launch(const char* name, const char* fn, double bytes, double flops, double items, hipStream_t s,
                        const std::function<hipError_t()>& launch) {
   return prof(name, fn, bytes, flops, items, s, launch);
+}
+
+size_t apply_tmp_bytes_per_vec(const lsop_op* op) {
+  return (op->has64() ? sizeof(Cx<double>) : sizeof(Cx<float>)) * (size_t)op->nx * op->pz();
+}
+
+int apply_into(lsop_op* op, int mode, const void* x, void* y, int nvec, void* tmp, int chunk, hipStream_t s) {
+  int st = check_op(op);
+  if (st) return st;
+  if (mode < 0 || mode > 3) return fail(LSOP_EINVAL, "bad mode");
+  if (nvec < 0 || (nvec > 0 && (!x || !y))) return fail(LSOP_EINVAL, "bad vectors");
+  if (nvec == 0) return LSOP_OK;
+  if (op->dtype == LSOP_C64)
+    return apply_impl<float>(op, mode, (const Cx<float>*)x, (Cx<float>*)y, nullptr, nullptr, nullptr, nvec, s, tmp,
+                             chunk);
+  return apply_impl<double>(op, mode, (const Cx<double>*)x, (Cx<double>*)y, nullptr, nullptr, nullptr, nvec, s, tmp,
+                            chunk);
 }
 }  // namespace lsop
 

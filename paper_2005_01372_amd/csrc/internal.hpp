@@ -187,6 +187,11 @@ hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, 
 hipError_t prof_launch(const char* name, const char* fn, double bytes, double flops, double items, hipStream_t s,
                        const std::function<hipError_t()>& launch);
 
+// The operator's FFT intermediate per vector, and y = op(x) with a caller-chosen intermediate of `chunk`
+// vectors (the passes of lsop_apply, chunk by chunk).
+size_t apply_tmp_bytes_per_vec(const lsop_op* op);
+int apply_into(lsop_op* op, int mode, const void* x, void* y, int nvec, void* tmp, int chunk, hipStream_t s);
+
 }  // namespace lsop
 
 // ------------------------------------------------------------------ handles

@@ -28,7 +28,7 @@ INIT = {"h_rhs": 0, "zero": 1, "user": 2, "best": 3}
 
 EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident", "lsop_autotune",
            "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "lsop_state_bytes",
-           "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count",
+           "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count", "lsop_apply_noalloc",
            "precond_state_bytes", "precond_create_in", "precond_create",
            "precond_build", "precond_build_batch", "precond_apply", "precond_info", "precond_destroy", "series_solve",
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
@@ -97,6 +97,7 @@ def load_library(path=LIB_PATH):
         "lsop_workspace_bytes": (ip, [vp, ip, ip, C.POINTER(C.c_size_t)]),
         "lsop_attach_workspace": (ip, [vp, vp, C.c_size_t]),
         "lsop_alloc_count": (ip, [C.POINTER(C.c_size_t)]),
+        "lsop_apply_noalloc": (ip, [vp, ip, vp, vp, ip, vp]),
         "precond_state_bytes": (ip, [vp, C.POINTER(PrecondParams), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "precond_create_in": (ip, [vp, C.POINTER(PrecondParams), vp, C.c_size_t, C.POINTER(vp)]),
         "precond_create": (ip, [vp, C.POINTER(PrecondParams), C.POINTER(vp)]),
@@ -285,6 +286,16 @@ class Operator:
         self._vecs(out, nvec=nv)
         _gpu(x, out)
         _check(self.lib.lsop_apply(self.handle, MODES[mode], _ptr(x), _ptr(out), nv, _stream()))
+        return out
+
+    def apply_noalloc(self, x, mode="A", out=None):
+        """lsop_apply_noalloc: as apply, with the FFT intermediate in the library's fixed device array (no
+        device allocation by the library; out must then be supplied to avoid torch's)."""
+        nv = self._vecs(x)
+        out = torch.empty_like(x) if out is None else out
+        self._vecs(out, nvec=nv)
+        _gpu(x, out)
+        _check(self.lib.lsop_apply_noalloc(self.handle, MODES[mode], _ptr(x), _ptr(out), nv, _stream()))
         return out
 
     def residual(self, psi, rhs, out=None):
