@@ -306,6 +306,38 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
                  const lsop_solve_params* params, lsop_solve_info* info_host, void* stream);
 
 /* ----------------------------------------------------------------------
+ * Restarted GMRES(m), the Krylov method the paper compares the preconditioned
+ * series with (Section 3.2.3), right-preconditioned by H: it solves
+ * A H y = psi0 - A psi_start and returns psi = psi_start + H y, so it
+ * converges whatever the spectral radius of M = I - H A (the series needs
+ * rho(M) < 1).  Every right-hand side runs its own Arnoldi process (classical
+ * Gram-Schmidt applied twice, FP64 sums), in lockstep with the others; the
+ * Hessenberg least-squares problems are solved on the host in FP64 (Givens
+ * rotations).  A cycle of a right-hand side ends when its residual estimate
+ * reaches tol, after `restart` iterations, at max_iter or on breakdown; the
+ * true residual ||A psi - psi0|| / ||psi0|| then decides convergence.
+ * info[v].iters counts inner iterations (one A and one H application each).
+ * pc NULL or identity: unpreconditioned.  LSOP_MIXED operators run FP64
+ * iterative refinement around complex-FP32 GMRES (inner_tol, refine_max as in
+ * series_solve).  Workspace: gmres_workspace_bytes ((restart + 3) vectors per
+ * right-hand side plus small terms); grown by the library or taken from the
+ * attached workspace.  Synchronises `stream` once per inner iteration.
+ * Returns OK if every right-hand side converged, else the first failing
+ * status (NOT_CONVERGED at max_iter). */
+typedef struct {
+  double tol;        /* relative residual target */
+  int restart;       /* Krylov dimension per cycle, 1..200 */
+  int max_iter;      /* inner iterations in total (per refinement step for MIXED) */
+  int init;          /* LSOP_INIT_H_RHS, LSOP_INIT_ZERO or LSOP_INIT_USER */
+  int refine_max;    /* MIXED only: outer refinement steps (default 8) */
+  double inner_tol;  /* MIXED only: inner relative tolerance (default 1e-5) */
+} lsop_gmres_params;
+
+int gmres_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_dev, int nvec,
+                const lsop_gmres_params* params, lsop_solve_info* info_host, void* stream);
+int gmres_workspace_bytes(const lsop_op* op, int nvec, int restart, size_t* bytes);
+
+/* ----------------------------------------------------------------------
  * Batches of problems of uneven size (many instances of Section 2's problem,
  * each with its own grid, medium, frequency and sources).  A batch wraps
  * existing operator handles (created and set up by the caller, all complex

@@ -947,6 +947,7 @@ size_t series_ws_bytes(const lsop_op* op, int nvec, int init) {
     const size_t esz = op->dtype == LSOP_C64 ? sizeof(Cx<float>) : sizeof(Cx<double>);
     return align_up(esz * n * nvec) * (init == LSOP_INIT_BEST ? 2 : 1) + tail;
   }
+  // refinement (FP64 residual, FP32 right-hand side and correction, norms, list) and the inner series' residual
   return align_up(sizeof(Cx<double>) * n * nvec) + 3 * align_up(sizeof(Cx<float>) * n * nvec) + tail;
 }
 
@@ -1060,6 +1061,304 @@ int series_impl(lsop_op* op, lsop_precond* pc, const Cx<T>* rhs, Cx<T>* psi, int
     }
   }
   return LSOP_OK;
+}
+
+// ------------------------------------------------------------------ GMRES
+// Restarted GMRES(m) with right preconditioning, the Krylov method the paper compares the series with
+// (Section 3.2.3): A H y = psi0 - A psi_start, psi = psi_start + H y.  Every right-hand side runs its own Arnoldi
+// process (classical Gram-Schmidt, applied twice, FP64 sums) in lockstep with the others; the small Hessenberg
+// least-squares problems are reduced by Givens rotations on the host in FP64.  A cycle ends for a right-hand side
+// when its residual estimate reaches tol, at m inner iterations, at max_iter or on breakdown; the true residual
+// A psi - psi0 then decides convergence (relative to ||psi0||, as the series).
+
+// Workspace of gmres_impl: Krylov basis (m + 1 blocks of nvec vectors), two vector temporaries, the partial dot
+// products, two coefficient columns, the solution coefficients, norms and the active list.
+size_t gmres_ws_bytes(size_t n, int nvec, int m, size_t esz) {
+  const size_t vb = align_up(esz * n * nvec);
+  return (size_t)(m + 1) * vb + 2 * vb + align_up(sizeof(Cx<double>) * (size_t)nvec * (m + 1) * mdot_chunks(n)) +
+         3 * align_up(sizeof(Cx<double>) * (size_t)nvec * (m + 2)) + align_up(sizeof(double) * nvec) +
+         align_up(sizeof(int) * nvec);
+}
+
+struct GmresHost {
+  std::vector<Cx<double>> R, cs, sn, g;  // R: (m + 1) x m upper part (column j at j * (m + 1)); rotations; rhs
+  int len = 0;                            // inner iterations of the current cycle
+  bool inner = false;                     // still iterating in this cycle
+};
+
+inline Cx<double> cconj(Cx<double> a) { return {a.re, -a.im}; }
+inline double cabs2(Cx<double> a) { return a.re * a.re + a.im * a.im; }
+
+template <typename T>
+int gmres_impl(lsop_op* op, lsop_precond* pc, const Cx<T>* rhs, Cx<T>* psi, int nvec, double tol, int m, int max_iter,
+               int init, const std::vector<int>& start, lsop_solve_info* info, char* ws, hipStream_t s) {
+  const size_t n = op->n();
+  const size_t vb = align_up(sizeof(Cx<T>) * n * nvec);
+  char* w = ws;
+  Cx<T>* V = reinterpret_cast<Cx<T>*>(w);
+  const size_t bstride = vb / sizeof(Cx<T>);
+  w += (size_t)(m + 1) * vb;
+  Cx<T>* Zb = reinterpret_cast<Cx<T>*>(w);
+  w += vb;
+  Cx<T>* Wb = reinterpret_cast<Cx<T>*>(w);
+  w += vb;
+  Cx<double>* part = reinterpret_cast<Cx<double>*>(w);
+  w += align_up(sizeof(Cx<double>) * (size_t)nvec * (m + 1) * mdot_chunks(n));
+  const size_t cb = align_up(sizeof(Cx<double>) * (size_t)nvec * (m + 2));
+  Cx<double>* h1 = reinterpret_cast<Cx<double>*>(w);
+  Cx<double>* h2 = reinterpret_cast<Cx<double>*>(w + cb);
+  Cx<double>* coef = reinterpret_cast<Cx<double>*>(w + 2 * cb);
+  w += 3 * cb;
+  double* dn = reinterpret_cast<double*>(w);
+  w += align_up(sizeof(double) * nvec);
+  int* dv = reinterpret_cast<int*>(w);
+  const int hs = m + 2;  // coefficient column stride
+
+  std::vector<int> act = start;
+  if (act.empty())
+    for (int v = 0; v < nvec; ++v) act.push_back(v);
+  const int na0 = (int)act.size();
+  std::vector<double> b2(nvec, 0.0), rn(nvec, 0.0);
+  LSOP_HIP(hipMemcpyAsync(dv, act.data(), sizeof(int) * na0, hipMemcpyHostToDevice, s));
+  LSOP_HIP(launch_norm2<T>(rhs, dn, dv, na0, n, s));
+  LSOP_HIP(hipMemcpyAsync(rn.data(), dn, sizeof(double) * na0, hipMemcpyDeviceToHost, s));
+  LSOP_HIP(hipStreamSynchronize(s));
+  for (int k = 0; k < na0; ++k) b2[act[k]] = rn[k];
+  // start
+  if (init == LSOP_INIT_H_RHS) {
+    if (pc) {
+      int st = pc_apply_impl<T>(pc, rhs, psi, dv, na0, false, s);
+      if (st) return st;
+    } else {
+      LSOP_HIP(launch_axpby<T>(rhs, psi, 1.0, 0.0, dv, na0, n, s));
+    }
+  } else if (init == LSOP_INIT_ZERO) {
+    LSOP_HIP(launch_axpby<T>(rhs, psi, 0.0, 0.0, dv, na0, n, s));
+  }
+  std::vector<GmresHost> hst(nvec);
+  std::vector<int> total(nvec, 0);
+  for (int v : act) {
+    info[v].iters = 0;
+    info[v].status = LSOP_NOT_CONVERGED;
+    info[v].rel_residual = INFINITY;
+    hst[v].R.assign((size_t)(m + 1) * m, Cx<double>{0, 0});
+    hst[v].cs.assign(m, Cx<double>{0, 0});
+    hst[v].sn.assign(m, Cx<double>{0, 0});
+    hst[v].g.assign(m + 1, Cx<double>{0, 0});
+  }
+  std::vector<Cx<double>> hc1((size_t)nvec * hs), hc2((size_t)nvec * hs), yc((size_t)nvec * hs);
+  for (int cycle = 0;; ++cycle) {
+    // true residual r = A psi - psi0 of every active right-hand side
+    int na = (int)act.size();
+    LSOP_HIP(hipMemcpyAsync(dv, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, s));
+    LSOP_HIP(hipMemsetAsync(dn, 0, sizeof(double) * na, s));
+    int st = apply_impl<T>(op, LSOP_MODE_A, psi, Wb, rhs, dn, dv, na, s);
+    if (st) return st;
+    LSOP_HIP(hipMemcpyAsync(rn.data(), dn, sizeof(double) * na, hipMemcpyDeviceToHost, s));
+    LSOP_HIP(hipStreamSynchronize(s));
+    std::vector<int> next;
+    std::vector<double> beta;
+    for (int k = 0; k < na; ++k) {
+      const int v = act[k];
+      const double rel = b2[v] > 0 ? std::sqrt(rn[k] / b2[v]) : std::sqrt(rn[k]);
+      info[v].iters = total[v];
+      info[v].rel_residual = rel;
+      if (cycle == 0) info[v].rel_residual0 = rel;
+      if (!std::isfinite(rel)) info[v].status = LSOP_DIVERGED;
+      else if (rel <= tol) info[v].status = LSOP_OK;
+      else if (total[v] >= max_iter) info[v].status = LSOP_NOT_CONVERGED;
+      else {
+        next.push_back(v);
+        beta.push_back(std::sqrt(rn[k]));
+      }
+    }
+    // v_0 = -r / beta for the right-hand sides that continue (r is still in Wb, slot order of act)
+    if (next.empty()) break;
+    LSOP_HIP(launch_scale_by_norm<T>(Wb, V, dn, -1.0, dv, na, n, s));  // all of act (finished ones are unused)
+    act.swap(next);
+    na = (int)act.size();
+    for (int k = 0; k < na; ++k) {
+      GmresHost& H = hst[act[k]];
+      std::fill(H.R.begin(), H.R.end(), Cx<double>{0, 0});
+      std::fill(H.g.begin(), H.g.end(), Cx<double>{0, 0});
+      H.g[0] = Cx<double>{beta[k], 0.0};
+      H.len = 0;
+      H.inner = true;
+    }
+    std::vector<int> in = act;  // right-hand sides still iterating in this cycle
+    for (int j = 0; j < m && !in.empty(); ++j) {
+      const int ni = (int)in.size();
+      LSOP_HIP(hipMemcpyAsync(dv, in.data(), sizeof(int) * ni, hipMemcpyHostToDevice, s));
+      Cx<T>* vj = V + (size_t)j * bstride;
+      const Cx<T>* src = vj;
+      if (pc) {
+        if ((st = pc_apply_impl<T>(pc, vj, Zb, dv, ni, false, s))) return st;
+        src = Zb;
+      }
+      if ((st = apply_impl<T>(op, LSOP_MODE_A, src, Wb, nullptr, nullptr, dv, ni, s))) return st;
+      // classical Gram-Schmidt against v_0 .. v_j, twice
+      LSOP_HIP(launch_mdot<T>(V, bstride, j + 1, Wb, dv, ni, n, part, h1, hs, false, s));
+      LSOP_HIP(launch_mcombine<T>(V, bstride, j + 1, h1, hs, -1.0, 1.0, Wb, dv, ni, n, s));
+      LSOP_HIP(launch_mdot<T>(V, bstride, j + 1, Wb, dv, ni, n, part, h2, hs, false, s));
+      LSOP_HIP(launch_mcombine<T>(V, bstride, j + 1, h2, hs, -1.0, 1.0, Wb, dv, ni, n, s));
+      LSOP_HIP(launch_norm2<T>(Wb, dn, dv, ni, n, s));
+      LSOP_HIP(launch_scale_by_norm<T>(Wb, V + (size_t)(j + 1) * bstride, dn, 1.0, dv, ni, n, s));
+      LSOP_HIP(hipMemcpyAsync(hc1.data(), h1, sizeof(Cx<double>) * (size_t)ni * hs, hipMemcpyDeviceToHost, s));
+      LSOP_HIP(hipMemcpyAsync(hc2.data(), h2, sizeof(Cx<double>) * (size_t)ni * hs, hipMemcpyDeviceToHost, s));
+      LSOP_HIP(hipMemcpyAsync(rn.data(), dn, sizeof(double) * ni, hipMemcpyDeviceToHost, s));
+      LSOP_HIP(hipStreamSynchronize(s));
+      std::vector<int> keep;
+      for (int k = 0; k < ni; ++k) {
+        const int v = in[k];
+        GmresHost& H = hst[v];
+        Cx<double>* col = H.R.data() + (size_t)j * (m + 1);
+        for (int i = 0; i <= j; ++i) {
+          const Cx<double> a = hc1[(size_t)k * hs + i], b = hc2[(size_t)k * hs + i];
+          col[i] = Cx<double>{a.re + b.re, a.im + b.im};
+        }
+        const double hn = std::sqrt(rn[k]);
+        col[j + 1] = Cx<double>{hn, 0.0};
+        // earlier rotations, then a new one that zeroes col[j + 1]
+        for (int i = 0; i < j; ++i) {
+          const Cx<double> x = col[i], y = col[i + 1];
+          const double c = H.cs[i].re;
+          const Cx<double> sv = H.sn[i];
+          col[i] = Cx<double>{c * x.re + sv.re * y.re - sv.im * y.im, c * x.im + sv.re * y.im + sv.im * y.re};
+          const Cx<double> sc = cconj(sv);
+          col[i + 1] = Cx<double>{-(sc.re * x.re - sc.im * x.im) + c * y.re, -(sc.re * x.im + sc.im * x.re) + c * y.im};
+        }
+        const Cx<double> a = col[j], b = col[j + 1];
+        const double na_ = std::sqrt(cabs2(a)), t = std::sqrt(cabs2(a) + cabs2(b));
+        double c = 1.0;
+        Cx<double> sv{0.0, 0.0};
+        if (t > 0.0) {
+          if (na_ == 0.0) {
+            c = 0.0;
+            sv = Cx<double>{cconj(b).re / t, cconj(b).im / t};
+            col[j] = Cx<double>{t, 0.0};
+          } else {
+            c = na_ / t;
+            const Cx<double> ph{a.re / na_, a.im / na_};
+            const Cx<double> cb = cconj(b);
+            sv = Cx<double>{(ph.re * cb.re - ph.im * cb.im) / t, (ph.re * cb.im + ph.im * cb.re) / t};
+            col[j] = Cx<double>{ph.re * t, ph.im * t};
+          }
+        }
+        col[j + 1] = Cx<double>{0.0, 0.0};
+        H.cs[j] = Cx<double>{c, 0.0};
+        H.sn[j] = sv;
+        const Cx<double> gj = H.g[j];
+        const Cx<double> sc = cconj(sv);
+        H.g[j + 1] = Cx<double>{-(sc.re * gj.re - sc.im * gj.im), -(sc.re * gj.im + sc.im * gj.re)};
+        H.g[j] = Cx<double>{c * gj.re, c * gj.im};
+        H.len = j + 1;
+        ++total[v];
+        const double est = std::sqrt(cabs2(H.g[j + 1]));
+        const double bnorm = b2[v] > 0 ? std::sqrt(b2[v]) : 1.0;
+        if (!(est / bnorm > tol) || hn == 0.0 || total[v] >= max_iter || !std::isfinite(est)) continue;
+        keep.push_back(v);
+      }
+      in.swap(keep);
+    }
+    // psi += H (V y) with R y = g for each right-hand side of the cycle
+    int maxlen = 0;
+    std::fill(yc.begin(), yc.end(), Cx<double>{0, 0});
+    for (int k = 0; k < na; ++k) {
+      GmresHost& H = hst[act[k]];
+      const int L = H.len;
+      maxlen = std::max(maxlen, L);
+      Cx<double>* y = yc.data() + (size_t)k * hs;
+      for (int i = L - 1; i >= 0; --i) {
+        Cx<double> acc = H.g[i];
+        for (int q = i + 1; q < L; ++q) {
+          const Cx<double> r = H.R[(size_t)q * (m + 1) + i];
+          acc = Cx<double>{acc.re - (r.re * y[q].re - r.im * y[q].im), acc.im - (r.re * y[q].im + r.im * y[q].re)};
+        }
+        const Cx<double> d = H.R[(size_t)i * (m + 1) + i];
+        const double dd = cabs2(d);
+        y[i] = dd > 0.0 ? Cx<double>{(acc.re * d.re + acc.im * d.im) / dd, (acc.im * d.re - acc.re * d.im) / dd}
+                        : Cx<double>{0.0, 0.0};
+      }
+    }
+    LSOP_HIP(hipMemcpyAsync(dv, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, s));
+    LSOP_HIP(hipMemcpyAsync(coef, yc.data(), sizeof(Cx<double>) * (size_t)na * hs, hipMemcpyHostToDevice, s));
+    LSOP_HIP(launch_mcombine<T>(V, bstride, maxlen, coef, hs, 1.0, 0.0, Zb, dv, na, n, s));
+    const Cx<T>* upd = Zb;
+    if (pc) {
+      if ((st = pc_apply_impl<T>(pc, Zb, Wb, dv, na, false, s))) return st;
+      upd = Wb;
+    }
+    LSOP_HIP(launch_axpby<T>(upd, psi, 1.0, 1.0, dv, na, n, s));
+  }
+  return LSOP_OK;
+}
+
+// Iterative refinement of a complex-FP64 solve (LSOP_MIXED): outer FP64 residuals r = A psi - psi0 and the
+// accumulated psi in FP64, inner solves of A d = r in complex FP32 (any inner method), psi <- psi - d, until
+// the FP64 relative residual <= tol.  Workspace at base: r (FP64), r and d (FP32), norms, active list
+// (refine_ws_bytes); the inner method's own workspace follows it.
+size_t refine_ws_bytes(size_t n, int nvec) {
+  return align_up(sizeof(Cx<double>) * n * nvec) + 2 * align_up(sizeof(Cx<float>) * n * nvec) +
+         align_up(sizeof(double) * nvec) + align_up(sizeof(int) * nvec);
+}
+
+int overall_status(const lsop_solve_info* info, int nvec);
+
+template <typename Inner>
+int refine_impl(lsop_op* op, const Cx<double>* rhs, Cx<double>* psi, int nvec, double tol, int refine_max, int init,
+                lsop_solve_info* info, char* base, hipStream_t s, Inner&& inner) {
+  const size_t n = op->n();
+  const size_t b64 = align_up(sizeof(Cx<double>) * n * nvec), b32 = align_up(sizeof(Cx<float>) * n * nvec);
+  Cx<double>* r64 = (Cx<double>*)base;
+  Cx<float>* rhs32 = (Cx<float>*)(base + b64);
+  Cx<float>* d32 = (Cx<float>*)(base + b64 + b32);
+  double* dn = (double*)(base + b64 + 2 * b32);
+  int* dv = (int*)((char*)dn + align_up(sizeof(double) * nvec));
+  std::vector<int> active(nvec);
+  for (int v = 0; v < nvec; ++v) active[v] = v;
+  std::vector<double> b2(nvec), rn(nvec);
+  LSOP_HIP(hipMemcpyAsync(dv, active.data(), sizeof(int) * nvec, hipMemcpyHostToDevice, s));
+  LSOP_HIP(launch_norm2<double>(rhs, dn, dv, nvec, n, s));
+  LSOP_HIP(hipMemcpyAsync(b2.data(), dn, sizeof(double) * nvec, hipMemcpyDeviceToHost, s));
+  LSOP_HIP(hipStreamSynchronize(s));
+  if (init != LSOP_INIT_USER && init != LSOP_INIT_BEST)
+    LSOP_HIP(hipMemsetAsync(psi, 0, sizeof(Cx<double>) * n * nvec, s));
+  std::vector<lsop_solve_info> inn(nvec);
+  std::vector<int> total_iters(nvec, 0);
+  int st = 0;
+  for (int k = 0;; ++k) {
+    const int na = (int)active.size();
+    LSOP_HIP(hipMemcpyAsync(dv, active.data(), sizeof(int) * na, hipMemcpyHostToDevice, s));
+    LSOP_HIP(hipMemsetAsync(dn, 0, sizeof(double) * na, s));
+    // FP64 residual r = A psi - psi0
+    if ((st = apply_impl<double>(op, LSOP_MODE_A, psi, r64, rhs, dn, dv, na, s))) return st;
+    LSOP_HIP(hipMemcpyAsync(rn.data(), dn, sizeof(double) * na, hipMemcpyDeviceToHost, s));
+    LSOP_HIP(hipStreamSynchronize(s));
+    std::vector<int> next;
+    for (int j = 0; j < na; ++j) {
+      const int v = active[j];
+      const double rel = b2[v] > 0 ? std::sqrt(rn[j] / b2[v]) : std::sqrt(rn[j]);
+      info[v].rel_residual = rel;
+      if (k == 0) info[v].rel_residual0 = rel;
+      info[v].refine_steps = k;
+      info[v].iters = total_iters[v];
+      if (!std::isfinite(rel)) info[v].status = LSOP_DIVERGED;
+      else if (rel <= tol) info[v].status = LSOP_OK;
+      else if (k == refine_max) info[v].status = LSOP_NOT_CONVERGED;
+      else if (k > 0 && inn[v].status == LSOP_DIVERGED) info[v].status = LSOP_DIVERGED;
+      else next.push_back(v);
+    }
+    active.swap(next);
+    if (active.empty()) break;
+    // inner FP32 solve of A d = r; psi <- psi - d
+    LSOP_HIP(launch_convert<float, double>(r64, rhs32, n * nvec, s));
+    if ((st = inner(rhs32, d32, active, inn.data(), dn, dv))) return st;
+    const int nn = (int)active.size();
+    LSOP_HIP(hipMemcpyAsync(dv, active.data(), sizeof(int) * nn, hipMemcpyHostToDevice, s));
+    LSOP_HIP(launch_accumulate<float>(d32, psi, -1.0, dv, nn, n, s));
+    for (int v : active) total_iters[v] += inn[v].iters;
+  }
+  return overall_status(info, nvec);
 }
 
 int overall_status(const lsop_solve_info* info, int nvec) {
@@ -2051,63 +2350,75 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
   // ---- mixed precision: iterative refinement (outer FP64, inner FP32 series)
   const int refine_max = p->refine_max > 0 ? p->refine_max : 8;
   const double inner_tol = p->inner_tol > 0 ? p->inner_tol : 1e-5;
-  const size_t b64 = align_up(sizeof(Cx<double>) * n * nvec), b32 = align_up(sizeof(Cx<float>) * n * nvec);
   if ((st = grow_scratch(op, series_ws_bytes(op, nvec, p->init)))) return st;
-  char* base = (char*)op->scratch;
-  Cx<double>* r64 = (Cx<double>*)base;
-  Cx<float>* rhs32 = (Cx<float>*)(base + b64);
-  Cx<float>* d32 = (Cx<float>*)(base + b64 + b32);
-  Cx<float>* w32 = (Cx<float>*)(base + b64 + 2 * b32);
-  double* dn = (double*)(base + b64 + 3 * b32);
-  int* dv = (int*)((char*)dn + align_up(sizeof(double) * nvec));
-  const Cx<double>* rhs = (const Cx<double>*)rhs_dev;
-  Cx<double>* psi = (Cx<double>*)psi_dev;
-  std::vector<int> active(nvec);
-  for (int v = 0; v < nvec; ++v) active[v] = v;
-  std::vector<double> b2(nvec), rn(nvec);
-  LSOP_HIP(hipMemcpyAsync(dv, active.data(), sizeof(int) * nvec, hipMemcpyHostToDevice, s));
-  LSOP_HIP(launch_norm2<double>(rhs, dn, dv, nvec, n, s));
-  LSOP_HIP(hipMemcpyAsync(b2.data(), dn, sizeof(double) * nvec, hipMemcpyDeviceToHost, s));
-  LSOP_HIP(hipStreamSynchronize(s));
-  if (p->init != LSOP_INIT_USER && p->init != LSOP_INIT_BEST)
-    LSOP_HIP(hipMemsetAsync(psi, 0, sizeof(Cx<double>) * n * nvec, s));
-  std::vector<lsop_solve_info> inner(nvec);
-  std::vector<int> total_iters(nvec, 0);
-  for (int k = 0;; ++k) {
-    const int na = (int)active.size();
-    LSOP_HIP(hipMemcpyAsync(dv, active.data(), sizeof(int) * na, hipMemcpyHostToDevice, s));
-    LSOP_HIP(hipMemsetAsync(dn, 0, sizeof(double) * na, s));
-    // FP64 residual r = A psi - psi0
-    if ((st = apply_impl<double>(op, LSOP_MODE_A, psi, r64, rhs, dn, dv, na, s))) return st;
-    LSOP_HIP(hipMemcpyAsync(rn.data(), dn, sizeof(double) * na, hipMemcpyDeviceToHost, s));
-    LSOP_HIP(hipStreamSynchronize(s));
-    std::vector<int> next;
-    for (int j = 0; j < na; ++j) {
-      const int v = active[j];
-      const double rel = b2[v] > 0 ? std::sqrt(rn[j] / b2[v]) : std::sqrt(rn[j]);
-      info[v].rel_residual = rel;
-      if (k == 0) info[v].rel_residual0 = rel;
-      info[v].refine_steps = k;
-      info[v].iters = total_iters[v];
-      if (!std::isfinite(rel)) info[v].status = LSOP_DIVERGED;
-      else if (rel <= p->tol) info[v].status = LSOP_OK;
-      else if (k == refine_max) info[v].status = LSOP_NOT_CONVERGED;
-      else if (k > 0 && inner[v].status == LSOP_DIVERGED) info[v].status = LSOP_DIVERGED;
-      else next.push_back(v);
-    }
-    active.swap(next);
-    if (active.empty()) break;
-    // inner FP32 series on A d = r; psi <- psi - d
-    LSOP_HIP(launch_convert<float, double>(r64, rhs32, n * nvec, s));
-    if ((st = series_impl<float>(op, pcu, rhs32, d32, nvec, inner_tol, p->max_iter, LSOP_INIT_H_RHS, active,
-                                 inner.data(), w32, dn, dv, s)))
+  char* w32 = (char*)op->scratch + refine_ws_bytes(n, nvec);
+  auto inner = [&](const Cx<float>* rhs32, Cx<float>* d32, const std::vector<int>& active, lsop_solve_info* inf,
+                   double* dn, int* dv) {
+    return series_impl<float>(op, pcu, rhs32, d32, nvec, inner_tol, p->max_iter, LSOP_INIT_H_RHS, active, inf,
+                              (Cx<float>*)w32, dn, dv, s);
+  };
+  return refine_impl(op, (const Cx<double>*)rhs_dev, (Cx<double>*)psi_dev, nvec, p->tol, refine_max, p->init, info,
+                     (char*)op->scratch, s, inner);
+}
+
+static int gmres_ws_query(const lsop_op* op, int nvec, int restart, size_t* bytes);
+
+int gmres_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_dev, int nvec,
+                const lsop_gmres_params* p, lsop_solve_info* info, void* stream) {
+  int st = check_op(op);
+  if (st) return st;
+  if (!p || !info) return fail(LSOP_EINVAL, "null params or info");
+  if (nvec < 1 || !rhs_dev || !psi_dev) return fail(LSOP_EINVAL, "bad vectors");
+  if (!(p->tol > 0) || p->max_iter < 0 || p->restart < 1 || p->restart > 200)
+    return fail(LSOP_EINVAL, "tol must be > 0, max_iter >= 0 and restart in [1, 200]");
+  if (p->init != LSOP_INIT_H_RHS && p->init != LSOP_INIT_ZERO && p->init != LSOP_INIT_USER)
+    return fail(LSOP_EINVAL, "GMRES starts from H psi0, zero or the caller's psi");
+  if (pc && pc->op != op) return fail(LSOP_EINVAL, "preconditioner belongs to another operator");
+  if (pc && !pc->built) return fail(LSOP_EINVAL, "preconditioner not built");
+  lsop_precond* pcu = (pc && pc->kind != LSOP_PC_IDENTITY) ? pc : nullptr;
+  hipStream_t s = S(stream);
+  const size_t n = op->n();
+  size_t need = 0;
+  if ((st = gmres_ws_query(op, nvec, p->restart, &need))) return st;
+  if ((st = grow_scratch(op, need))) return st;
+  for (int v = 0; v < nvec; ++v) info[v] = lsop_solve_info{0, 0, INFINITY, LSOP_NOT_CONVERGED, INFINITY};
+  if (op->dtype == LSOP_C64) {
+    if ((st = gmres_impl<float>(op, pcu, (const Cx<float>*)rhs_dev, (Cx<float>*)psi_dev, nvec, p->tol, p->restart,
+                                p->max_iter, p->init, {}, info, (char*)op->scratch, s)))
       return st;
-    const int nn = (int)active.size();
-    LSOP_HIP(hipMemcpyAsync(dv, active.data(), sizeof(int) * nn, hipMemcpyHostToDevice, s));
-    LSOP_HIP(launch_accumulate<float>(d32, psi, -1.0, dv, nn, n, s));
-    for (int v : active) total_iters[v] += inner[v].iters;
+    return overall_status(info, nvec);
   }
-  return overall_status(info, nvec);
+  if (op->dtype == LSOP_C128) {
+    if ((st = gmres_impl<double>(op, pcu, (const Cx<double>*)rhs_dev, (Cx<double>*)psi_dev, nvec, p->tol,
+                                 p->restart, p->max_iter, p->init, {}, info, (char*)op->scratch, s)))
+      return st;
+    return overall_status(info, nvec);
+  }
+  // mixed: FP64 refinement around complex-FP32 GMRES (inner tolerance inner_tol, default 1e-5)
+  const double inner_tol = p->inner_tol > 0 ? p->inner_tol : 1e-5;
+  const int refine_max = p->refine_max > 0 ? p->refine_max : 8;
+  char* gws = (char*)op->scratch + refine_ws_bytes(n, nvec);
+  auto inner = [&](const Cx<float>* rhs32, Cx<float>* d32, const std::vector<int>& active, lsop_solve_info* inf,
+                   double*, int*) {
+    return gmres_impl<float>(op, pcu, rhs32, d32, nvec, inner_tol, p->restart, p->max_iter, LSOP_INIT_ZERO, active,
+                             inf, gws, s);
+  };
+  return refine_impl(op, (const Cx<double>*)rhs_dev, (Cx<double>*)psi_dev, nvec, p->tol, refine_max,
+                     p->init == LSOP_INIT_USER ? LSOP_INIT_USER : LSOP_INIT_ZERO, info, (char*)op->scratch, s, inner);
+}
+
+static int gmres_ws_query(const lsop_op* op, int nvec, int restart, size_t* bytes) {
+  const size_t n = op->n();
+  if (op->dtype == LSOP_C64) *bytes = gmres_ws_bytes(n, nvec, restart, sizeof(Cx<float>));
+  else if (op->dtype == LSOP_C128) *bytes = gmres_ws_bytes(n, nvec, restart, sizeof(Cx<double>));
+  else *bytes = refine_ws_bytes(n, nvec) + gmres_ws_bytes(n, nvec, restart, sizeof(Cx<float>));
+  return LSOP_OK;
+}
+
+int gmres_workspace_bytes(const lsop_op* op, int nvec, int restart, size_t* bytes) {
+  if (!op || !bytes) return fail(LSOP_EINVAL, "null argument");
+  if (nvec < 0 || restart < 1 || restart > 200) return fail(LSOP_EINVAL, "bad nvec or restart");
+  return gmres_ws_query(op, nvec, restart, bytes);
 }
 
 // ------------------------------------------------------------------ batches

@@ -153,6 +153,20 @@ hipError_t launch_lu_inverse_small_f32(const Cx<float>* M, size_t ldm, size_t sm
 // (cleared by the caller) receives the number of non-zero singular values among the k kept.  l <= 256.
 hipError_t launch_svd_trunc(const Cx<double>* R2, int l, int k, Cx<double>* Bc, Cx<double>* Vc, Cx<double>* M,
                             Cx<double>* Mp, int* kept, hipStream_t s);
+// Krylov kernels (restarted GMRES), basis stored [i][vector][n] with block stride bstride, vectors through
+// vidx[a], a < na.  mdot: h[a * hstride + i] (+)= sum_k conj(V[i][vs][k]) w[vs][k] for i < nb, through the
+// partial sums part (na * nb * mdot_chunks(n) entries).  mcombine: out[vs] = beta out[vs] + alpha
+// sum_i coef[a * cstride + i] V[i][vs].  scale_by_norm: y[vs] = sign x[vs] / sqrt(nrm2[a]) (0 where nrm2 = 0).
+int mdot_chunks(size_t n);
+template <typename T>
+hipError_t launch_mdot(const Cx<T>* V, size_t bstride, int nb, const Cx<T>* w, const int* vidx, int na, size_t n,
+                       Cx<double>* part, Cx<double>* h, int hstride, bool accumulate, hipStream_t s);
+template <typename T>
+hipError_t launch_mcombine(const Cx<T>* V, size_t bstride, int nb, const Cx<double>* coef, int cstride, double alpha,
+                           double beta, Cx<T>* out, const int* vidx, int na, size_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_scale_by_norm(const Cx<T>* x, Cx<T>* y, const double* nrm2, double sign, const int* vidx, int na,
+                                size_t n, hipStream_t s);
 // HODLR: dense leaf blocks of I - G0 V (formed in FP64, stored as To), leaves leaf0 .. leaf0 + nleaf - 1 of nl cells
 template <typename To>
 hipError_t launch_leaf_form(const Cx<double>* ktab, const double* chi, Cx<To>* out, int nz, int nl, int leaf0,

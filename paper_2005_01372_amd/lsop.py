@@ -28,7 +28,7 @@ INIT = {"h_rhs": 0, "zero": 1, "user": 2, "best": 3}
 
 EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident", "lsop_autotune",
            "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "lsop_state_bytes",
-           "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count", "lsop_apply_noalloc",
+           "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count", "lsop_apply_noalloc", "gmres_solve", "gmres_workspace_bytes",
            "precond_state_bytes", "precond_create_in", "precond_create",
            "precond_build", "precond_build_batch", "precond_apply", "precond_info", "precond_destroy", "series_solve",
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
@@ -57,6 +57,11 @@ class PrecondParams(C.Structure):
 class SolveParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("init", C.c_int), ("refine_max", C.c_int),
                 ("inner_tol", C.c_double)]
+
+
+class GmresParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_iter", C.c_int), ("init", C.c_int),
+                ("refine_max", C.c_int), ("inner_tol", C.c_double)]
 
 
 class KernelStat(C.Structure):
@@ -98,6 +103,8 @@ def load_library(path=LIB_PATH):
         "lsop_attach_workspace": (ip, [vp, vp, C.c_size_t]),
         "lsop_alloc_count": (ip, [C.POINTER(C.c_size_t)]),
         "lsop_apply_noalloc": (ip, [vp, ip, vp, vp, ip, vp]),
+        "gmres_solve": (ip, [vp, vp, vp, vp, ip, C.POINTER(GmresParams), C.POINTER(SolveInfo), vp]),
+        "gmres_workspace_bytes": (ip, [vp, ip, ip, C.POINTER(C.c_size_t)]),
         "precond_state_bytes": (ip, [vp, C.POINTER(PrecondParams), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "precond_create_in": (ip, [vp, C.POINTER(PrecondParams), vp, C.c_size_t, C.POINTER(vp)]),
         "precond_create": (ip, [vp, C.POINTER(PrecondParams), C.POINTER(vp)]),
@@ -436,6 +443,22 @@ def series_solve(op, pc, rhs, psi=None, tol=1e-10, max_iter=30, init="h_rhs", re
     info = (SolveInfo * nv)()
     st = op.lib.series_solve(op.handle, pc.handle if pc is not None else None, _ptr(rhs), _ptr(psi), nv,
                              C.byref(p), info, _stream())
+    _check(st, allow=() if raise_on_failure else (NOT_CONVERGED, DIVERGED))
+    return psi, [SolveResult(i.iters, i.refine_steps, i.rel_residual, i.status, i.rel_residual0) for i in info]
+
+
+def gmres_solve(op, pc, rhs, psi=None, tol=1e-10, restart=30, max_iter=300, init="zero", refine_max=8,
+                inner_tol=1e-5, raise_on_failure=False):
+    """Restarted GMRES(restart), right-preconditioned by pc (Section 3.2.3's comparison method); returns
+    (psi, [SolveResult per right-hand side]) with iters = inner iterations."""
+    nv = op._vecs(rhs)
+    psi = torch.empty_like(rhs) if psi is None else psi
+    op._vecs(psi, nvec=nv)
+    _gpu(rhs, psi)
+    p = GmresParams(float(tol), int(restart), int(max_iter), INIT[init], int(refine_max), float(inner_tol))
+    info = (SolveInfo * nv)()
+    st = op.lib.gmres_solve(op.handle, pc.handle if pc is not None else None, _ptr(rhs), _ptr(psi), nv,
+                            C.byref(p), info, _stream())
     _check(st, allow=() if raise_on_failure else (NOT_CONVERGED, DIVERGED))
     return psi, [SolveResult(i.iters, i.refine_steps, i.rel_residual, i.status, i.rel_residual0) for i in info]
 
