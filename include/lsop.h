@@ -338,6 +338,49 @@ int gmres_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_de
 int gmres_workspace_bytes(const lsop_op* op, int nvec, int restart, size_t* bytes);
 
 /* ----------------------------------------------------------------------
+ * Frequency sweep (Section 3.1): the problem at each of nfreq increasing
+ * frequencies (the paper sweeps integer frequencies lowest first), the
+ * series of eq. (11) with a preconditioner of kind pc0->kind built per
+ * frequency, the rank managed as in Section 3.1: the series gets at most
+ * max_iter iterations (30 in the paper); if a frequency does not converge,
+ * its preconditioner is rebuilt with rank + rank_step and the series
+ * restarted from H psi0 (at most max_rebuilds times); if it converged but
+ * needed more than escalate_above iterations (10 in the paper), the next
+ * frequency starts at rank + rank_step (the paper's steps: +200 for the
+ * simple preconditioner, +5 for the hierarchical one).  Sources are point
+ * sources (as lsop_incident) with amplitude 1, or, with ricker_fc > 0, the
+ * spectrum of a Ricker wavelet of centre frequency ricker_fc delayed by
+ * 1 / ricker_fc: (2 / sqrt(pi)) f^2 / fc^3 exp(-f^2 / fc^2) exp(-2 pi i f / fc)
+ * (the paper's source; its normalisation is not stated).
+ * psi_dev: [nfreq][nsrc][nx][nz] in the operator's dtype (also scratch for the
+ * next frequency's incident fields).  info_host[k]: the frequency's final
+ * rank, rebuilds, largest iteration count and residual, status.  The
+ * operator's medium is left at the last frequency.  Synchronous.  Returns OK
+ * if every frequency converged, else the first failing status. */
+typedef struct {
+  double tol;          /* relative residual per source */
+  int max_iter;        /* series iterations per attempt (30) */
+  int escalate_above;  /* raise the rank for the next frequency above this many iterations (10) */
+  int rank_step;       /* rank increase (200 simple, 5 HODLR in the paper) */
+  int rank_max;        /* cap (<= 256; 0: 256) */
+  int max_rebuilds;    /* rebuilds per frequency */
+  double ricker_fc;    /* Hz; 0: unit amplitudes */
+} lsop_sweep_params;
+
+typedef struct {
+  double freq;
+  int rank;               /* rank of the preconditioner that produced the returned fields */
+  int rebuilds;           /* rebuilds at this frequency */
+  int iters_max;          /* largest iteration count over the sources */
+  int status;             /* lsop_status of the frequency */
+  double rel_residual_max;
+} lsop_sweep_info;
+
+int lsop_sweep(lsop_op* op, const double* vel_dev, double h, double c0, const double* freqs_host, int nfreq,
+               const lsop_precond_params* pc0, const lsop_sweep_params* params, const int* src_i_host,
+               const int* src_j_host, int nsrc, void* psi_dev, lsop_sweep_info* info_host, void* stream);
+
+/* ----------------------------------------------------------------------
  * Batches of problems of uneven size (many instances of Section 2's problem,
  * each with its own grid, medium, frequency and sources).  A batch wraps
  * existing operator handles (created and set up by the caller, all complex

@@ -2421,6 +2421,108 @@ int gmres_workspace_bytes(const lsop_op* op, int nvec, int restart, size_t* byte
   return gmres_ws_query(op, nvec, restart, bytes);
 }
 
+// ------------------------------------------------------------------ frequency sweep
+// Section 3.1: integer frequencies lowest first; a preconditioner per frequency; at most max_iter iterations of
+// the series; on failure the preconditioner is rebuilt with a larger rank and the series restarted from psi0;
+// when a frequency needed more than escalate_above iterations, the next one starts at a larger rank.
+static Cx<double> ricker_amp(double f, double fc) {
+  // Fourier transform of the Ricker wavelet (1 - 2 pi^2 fc^2 t'^2) exp(-pi^2 fc^2 t'^2), t' = t - 1/fc:
+  // (2 / sqrt(pi)) f^2 / fc^3 exp(-f^2 / fc^2) times the delay phase exp(-i 2 pi f / fc)
+  const double pi = lsop_bessel::kPi;
+  const double a = 2.0 / std::sqrt(pi) * f * f / (fc * fc * fc) * std::exp(-f * f / (fc * fc));
+  const double ph = -2.0 * pi * f / fc;
+  return Cx<double>{a * std::cos(ph), a * std::sin(ph)};
+}
+
+int lsop_sweep(lsop_op* op, const double* vel_dev, double h, double c0, const double* freqs, int nfreq,
+               const lsop_precond_params* pc0, const lsop_sweep_params* sp, const int* src_i, const int* src_j,
+               int nsrc, void* psi_dev, lsop_sweep_info* info, void* stream) {
+  if (!op || !vel_dev || !freqs || !pc0 || !sp || !src_i || !src_j || !psi_dev || !info)
+    return fail(LSOP_EINVAL, "null argument");
+  if (nfreq < 1 || nsrc < 1) return fail(LSOP_EINVAL, "nfreq and nsrc must be >= 1");
+  for (int k = 0; k < nfreq; ++k)
+    if (!(freqs[k] > 0) || (k > 0 && !(freqs[k] > freqs[k - 1])))
+      return fail(LSOP_EINVAL, "frequencies must be positive and increasing (lowest first)");
+  if (pc0->kind != LSOP_PC_LOWRANK && pc0->kind != LSOP_PC_HODLR)
+    return fail(LSOP_EINVAL, "the sweep escalates the rank of a low-rank or HODLR preconditioner");
+  if (!(sp->tol > 0) || sp->max_iter < 1 || sp->rank_step < 1 || sp->max_rebuilds < 0 || sp->escalate_above < 0 ||
+      sp->ricker_fc < 0 || !std::isfinite(sp->ricker_fc))
+    return fail(LSOP_EINVAL, "bad sweep parameters");
+  const int rank_cap = std::min(256 - (pc0->kind == LSOP_PC_LOWRANK ? pc0->oversample : 0),
+                                sp->rank_max > 0 ? sp->rank_max : 256);
+  if (pc0->rank < 1 || pc0->rank > rank_cap) return fail(LSOP_EINVAL, "initial rank outside [1, rank_max]");
+  for (int k = 0; k < nsrc; ++k)
+    if (src_i[k] < 0 || src_i[k] >= op->nx || src_j[k] < 0 || src_j[k] >= op->nz)
+      return fail(LSOP_EINVAL, "source outside the grid");
+  const size_t esz = op->dtype == LSOP_C64 ? sizeof(Cx<float>) : sizeof(Cx<double>);
+  const size_t vstride = esz * op->n() * nsrc;
+  lsop_precond_params pp = *pc0;
+  std::vector<double> amp(2 * (size_t)nsrc);
+  std::vector<lsop_solve_info> si(nsrc);
+  lsop_solve_params prm{sp->tol, sp->max_iter, LSOP_INIT_H_RHS, 0, 0.0};
+  int overall = LSOP_OK;
+  // the incident fields of the current frequency live in the caller's output slice of the *next* frequency
+  // until that one is solved; the last frequency uses a small library buffer
+  void* last_rhs = nullptr;
+  int st = 0;
+  for (int k = 0; k < nfreq; ++k) {
+    info[k] = lsop_sweep_info{freqs[k], pp.rank, 0, 0, LSOP_NOT_CONVERGED, INFINITY};
+    if ((st = lsop_set_problem(op, vel_dev, h, freqs[k], c0, stream))) return st;
+    const Cx<double> a = sp->ricker_fc > 0 ? ricker_amp(freqs[k], sp->ricker_fc) : Cx<double>{1.0, 0.0};
+    for (int q = 0; q < nsrc; ++q) {
+      amp[2 * q] = a.re;
+      amp[2 * q + 1] = a.im;
+    }
+    char* psi_k = (char*)psi_dev + (size_t)k * vstride;
+    void* rhs = nullptr;
+    if (k + 1 < nfreq) {
+      rhs = (char*)psi_dev + (size_t)(k + 1) * vstride;
+    } else {
+      if (!last_rhs && lib_malloc(&last_rhs, vstride) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LSOP_ENOMEM, "sweep: incident-field buffer");
+      }
+      rhs = last_rhs;
+    }
+    if ((st = lsop_incident(op, src_i, src_j, amp.data(), nsrc, rhs, stream))) break;
+    for (int rebuild = 0;; ++rebuild) {
+      for (lsop_solve_info& x : si) x = lsop_solve_info{0, 0, INFINITY, LSOP_NOT_CONVERGED, INFINITY};
+      lsop_precond* pc = nullptr;
+      if ((st = precond_create(op, &pp, &pc))) break;
+      st = precond_build(pc, nullptr, stream);
+      int ss = st;
+      if (!st) ss = series_solve(op, pc, rhs, psi_k, nsrc, &prm, si.data(), stream);
+      precond_destroy(pc);
+      if (st && st != LSOP_ESINGULAR) break;  // a singular core counts as a failed build: raise the rank
+      st = 0;
+      int itmax = 0;
+      double resmax = 0.0;
+      for (const lsop_solve_info& x : si) {
+        itmax = std::max(itmax, x.iters);
+        resmax = std::max(resmax, x.rel_residual);
+      }
+      info[k].rank = pp.rank;
+      info[k].rebuilds = rebuild;
+      info[k].iters_max = itmax;
+      info[k].rel_residual_max = resmax;
+      info[k].status = ss;
+      if (ss == LSOP_OK) {
+        if (itmax > sp->escalate_above) pp.rank = std::min(rank_cap, pp.rank + sp->rank_step);
+        break;
+      }
+      if (rebuild >= sp->max_rebuilds || pp.rank >= rank_cap) break;
+      pp.rank = std::min(rank_cap, pp.rank + sp->rank_step);  // rebuild with a larger rank, restart from psi0
+    }
+    if (st) break;
+    if (info[k].status != LSOP_OK && overall == LSOP_OK) overall = info[k].status;
+  }
+  if (last_rhs) {
+    (void)hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream));
+    (void)hipFree(last_rhs);
+  }
+  return st ? st : overall;
+}
+
 // ------------------------------------------------------------------ batches
 int lsop_batch_create(int count, lsop_op* const* ops, lsop_batch** out) {
   if (!out) return fail(LSOP_EINVAL, "null output handle");

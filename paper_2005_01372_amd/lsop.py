@@ -28,7 +28,7 @@ INIT = {"h_rhs": 0, "zero": 1, "user": 2, "best": 3}
 
 EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident", "lsop_autotune",
            "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "lsop_state_bytes",
-           "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count", "lsop_apply_noalloc", "gmres_solve", "gmres_workspace_bytes",
+           "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count", "lsop_apply_noalloc", "gmres_solve", "gmres_workspace_bytes", "lsop_sweep",
            "precond_state_bytes", "precond_create_in", "precond_create",
            "precond_build", "precond_build_batch", "precond_apply", "precond_info", "precond_destroy", "series_solve",
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
@@ -62,6 +62,16 @@ class SolveParams(C.Structure):
 class GmresParams(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int), ("max_iter", C.c_int), ("init", C.c_int),
                 ("refine_max", C.c_int), ("inner_tol", C.c_double)]
+
+
+class SweepParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("escalate_above", C.c_int), ("rank_step", C.c_int),
+                ("rank_max", C.c_int), ("max_rebuilds", C.c_int), ("ricker_fc", C.c_double)]
+
+
+class SweepInfo(C.Structure):
+    _fields_ = [("freq", C.c_double), ("rank", C.c_int), ("rebuilds", C.c_int), ("iters_max", C.c_int),
+                ("status", C.c_int), ("rel_residual_max", C.c_double)]
 
 
 class KernelStat(C.Structure):
@@ -105,6 +115,8 @@ def load_library(path=LIB_PATH):
         "lsop_apply_noalloc": (ip, [vp, ip, vp, vp, ip, vp]),
         "gmres_solve": (ip, [vp, vp, vp, vp, ip, C.POINTER(GmresParams), C.POINTER(SolveInfo), vp]),
         "gmres_workspace_bytes": (ip, [vp, ip, ip, C.POINTER(C.c_size_t)]),
+        "lsop_sweep": (ip, [vp, vp, dp, dp, C.POINTER(dp), ip, C.POINTER(PrecondParams), C.POINTER(SweepParams),
+                            vp, vp, ip, vp, C.POINTER(SweepInfo), vp]),
         "precond_state_bytes": (ip, [vp, C.POINTER(PrecondParams), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
         "precond_create_in": (ip, [vp, C.POINTER(PrecondParams), vp, C.c_size_t, C.POINTER(vp)]),
         "precond_create": (ip, [vp, C.POINTER(PrecondParams), C.POINTER(vp)]),
@@ -461,6 +473,34 @@ def gmres_solve(op, pc, rhs, psi=None, tol=1e-10, restart=30, max_iter=300, init
                             C.byref(p), info, _stream())
     _check(st, allow=() if raise_on_failure else (NOT_CONVERGED, DIVERGED))
     return psi, [SolveResult(i.iters, i.refine_steps, i.rel_residual, i.status, i.rel_residual0) for i in info]
+
+
+def sweep(op, vel, h, c0, freqs, src_i, src_j, kind=PC_LOWRANK, rank=8, levels=0, power_iters=0, oversample=0,
+          seed=0, tol=1e-6, max_iter=30, escalate_above=10, rank_step=8, rank_max=256, max_rebuilds=8,
+          ricker_fc=0.0):
+    """Frequency sweep of Section 3.1 (lowest first, rank escalation, restart from psi0); returns
+    (psi [nfreq][nsrc][nx][nz], [dict per frequency])."""
+    vel = torch.as_tensor(vel, dtype=torch.float64)
+    vel = (vel if vel.is_cuda else vel.cuda()).contiguous()
+    if tuple(vel.shape) != (op.nx, op.nz):
+        raise ValueError(f"velocity must be {(op.nx, op.nz)}")
+    nf, ns = len(freqs), len(src_i)
+    if len(src_j) != ns:
+        raise ValueError("src_i and src_j differ in length")
+    f = (C.c_double * nf)(*[float(v) for v in freqs])
+    si = (C.c_int * ns)(*[int(v) for v in src_i])
+    sj = (C.c_int * ns)(*[int(v) for v in src_j])
+    pp = PrecondParams(int(kind), int(rank), int(power_iters), int(seed), int(levels), int(oversample), 0.0)
+    sp = SweepParams(float(tol), int(max_iter), int(escalate_above), int(rank_step), int(rank_max),
+                     int(max_rebuilds), float(ricker_fc))
+    psi = torch.empty((nf, ns, op.nx, op.nz), dtype=op.vec_dtype, device="cuda")
+    info = (SweepInfo * nf)()
+    st = op.lib.lsop_sweep(op.handle, _ptr(vel), float(h), float(c0), f, nf, C.byref(pp), C.byref(sp), si, sj, ns,
+                           _ptr(psi), info, _stream())
+    _check(st, allow=(NOT_CONVERGED, DIVERGED, ESINGULAR))
+    op.h, op.c0, op.freq = float(h), float(c0), float(freqs[-1])
+    return psi, [dict(freq=i.freq, rank=i.rank, rebuilds=i.rebuilds, iters_max=i.iters_max, status=i.status,
+                      rel_residual_max=i.rel_residual_max) for i in info]
 
 
 def build_batch(pcs, streams=4):
