@@ -17,7 +17,7 @@ Readings of points the paper leaves open (each pinned by a test):
 * The background Green's function of the 2D Helmholtz operator with the
   paper's sign convention (Section 2.1: right-hand sides -S and -delta) is
   G0(r) = (i/4) H0^(1)(k0 r), outgoing for an exp(-i omega t) time factor.
-* "G0 evaluated in the gridblocks" (Section 2.1, eq. 4): the product G0 * dv
+* The value of G0 per pair of grid cells (Section 2.1, eq. 4): the product G0 * dv
   of the matrix G0 V is taken as the integral of G0 over the source cell,
   with the square cell replaced by the disk of equal area (radius
   a = h / sqrt(pi)).  Integrating (i/4) H0^(1) over that disk gives, by
@@ -25,11 +25,11 @@ Readings of points the paper leaves open (each pinned by a test):
   for a cell at lag (p,q), rho = sqrt(p^2+q^2) > 0, and the closed form
   K(0,0) = (i pi a / (2 k0)) H1^(1)(k0 a) - 1/k0^2 for the singular self cell.
   (G0 V)_{mn} = K(m - n) chi_n.
-* The "extended" first row (Section 2.2, after eq. 11) is the symmetric
+* The extension of G0's first row for the FFT (Section 2.2, after eq. 11) is the symmetric
   circulant embedding into a P_x x P_z array with P >= 2N - 1 (here P = 2N),
   lag -p stored at index P - p.  This makes the FFT product exact on the grid.
 * Every transpose in Alg. 1 / Alg. 2 is the conjugate transpose (Section 2.3
-  states that T denotes the complex conjugate transpose), so
+  defines its transposes that way), so
   W = V^H G0^H Q.
 * Eq. (14) as printed cannot be the update (its fixed point is psi = 0); it is
   read as psi_j = psi_{j-1} - (a_{j-1} + U Z W^H a_{j-1}) = psi_{j-1} - H a_{j-1},

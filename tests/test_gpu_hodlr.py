@@ -3,9 +3,14 @@
 H x is compared with the oracle's nested-SMW inverse of the same HODLR
 approximation built from the same probe rows (the range bases differ by a
 unitary factor, which the approximation does not see): complex double
-<= 1e-10; complex float <= 1e-4 (FP32 convolutions and bases; FP64 leaf
-inverses and cores).  Series solutions are compared with the dense-LU
-solution: double <= 1e-10 (residual 1e-13), FP32 + FP64 refinement <= 1e-10.
+<= 1e-10.  Complex-float preconditioners sample, orthonormalise, invert their
+leaves and apply their node cores in FP32 (the cores are inverted in FP64), so
+their H x carries FP32 rounding amplified by the conditioning of the leaves
+and cores; their bound is derived from the measured spread between the FP32
+and FP64 device builds of the same probes (the FP64 build matching the oracle
+to 1e-10), with a fixed ceiling.  Series solutions are compared with the
+dense-LU solution: double <= 1e-10 (residual 1e-13), FP32 + FP64 refinement
+<= 1e-10.
 """
 import os
 
@@ -36,8 +41,7 @@ def probe_rows(levels, r, n, seed):
 
 
 @pytest.mark.parametrize("dtype,levels,r,q,tol", [(lsop.C128, 2, 12, 0, 1e-10), (lsop.C128, 5, 8, 0, 1e-10),
-                                                  (lsop.C128, 6, 6, 0, 1e-10), (lsop.C128, 3, 10, 1, 1e-10),
-                                                  (lsop.C64, 3, 12, 0, 1e-4)])
+                                                  (lsop.C128, 6, 6, 0, 1e-10), (lsop.C128, 3, 10, 1, 1e-10)])
 def test_hodlr_apply_matches_oracle(dtype, levels, r, q, tol):
     announce(f"hodlr apply dtype={dtype} levels={levels} r={r} q={q}")
     w = layered(64)
@@ -50,6 +54,35 @@ def test_hodlr_apply_matches_oracle(dtype, levels, r, q, tol):
     x = synth.random_vectors((5, 64, 64), 9)
     tdt = torch.complex128 if dtype == lsop.C128 else torch.complex64
     assert rel(host(pc.apply(dev(x, tdt))), hs.apply(x)) <= tol
+
+
+@pytest.mark.parametrize("nx,nz,levels,r,q", [(64, 64, 3, 12, 0), (16, 1024, 4, 16, 1)])
+def test_hodlr_fp32_apply_matches_oracle(nx, nz, levels, r, q):
+    """Complex FP32 against the oracle, including leaves of one grid column of 1024 cells (a 4-level tree on a
+    16 x 1024 strip, q = 1).  Bound: 1.5 x the measured FP32-vs-FP64 spread of the same probes, at most 1e-4."""
+    announce(f"hodlr fp32 {nx}x{nz} levels={levels} r={r} q={q}")
+    w = synth.model_layered_salt(n=64, h=10.0, freq=15.0, seed=2, nsrc=1)
+    if (nx, nz) != (64, 64):
+        rng = np.random.default_rng(4)
+        vel = 2000.0 * (1.0 + 0.25 * synth.smoothed_field((nx, nz), 6.0, rng))
+        w = synth.Workload(f"strip {nx}x{nz}", vel, 10.0, 12.0, 2000.0, np.array([nx // 2]), np.array([0]))
+    prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+    om = probe_rows(levels, r, prob.n, 23)
+    hs = HD.HodlrSolve(prob, r, levels, probes=lambda d: om[d * r:(d + 1) * r], q=q)
+    x = synth.random_vectors((4, nx, nz), 9)
+    ref = hs.apply(x)
+    out = {}
+    for dtype, tdt in ((lsop.C128, torch.complex128), (lsop.C64, torch.complex64)):
+        op = make_op(w, dtype, 8)
+        pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=r, levels=levels, power_iters=q)
+        pc.build(torch.as_tensor(om).cuda())
+        out[dtype] = host(pc.apply(dev(x, tdt)))
+        del pc, op
+    assert rel(out[lsop.C128], ref) <= 1e-10
+    spread = rel(out[lsop.C64], out[lsop.C128])
+    err = rel(out[lsop.C64], ref)
+    announce(f"fp32 error {err:.2e}, fp32-vs-fp64 spread {spread:.2e}")
+    assert err <= min(1.5 * spread, 1e-4)
 
 
 def test_hodlr_device_probes_match_explicit():
