@@ -96,6 +96,28 @@ int lsop_create(int nx, int nz, int dtype, int max_vec, lsop_op** out);
 int lsop_set_problem(lsop_op* op, const double* vel_dev, double h, double freq_hz, double c0,
                      void* stream);
 
+/* The medium of the convergent Born series (Section 2.2, reviewing Osnabrugge
+ * et al.): the background made dissipative, k_eps^2 = k0^2 + i eps (Re, Im
+ * k_eps > 0; time factor exp(-i omega t)), and the gain put into the
+ * potential, V_eps = chi - i eps r, so that the equation inside the grid is
+ * unchanged: the operator becomes I - G_eps V_eps with G_eps the same
+ * disk-integrated kernel at complex wavenumber (Bessel functions of complex
+ * argument), and lsop_incident gives G_eps S.  Outside the grid the medium is
+ * the dissipative background (absorbing).  absorb > 0 cells at the grid edges
+ * form an absorbing layer: there the gain is scaled by
+ * r = 1 - (1 - d / absorb) / 2 (d = cells to the edge), i.e. the medium turns
+ * lossy gradually.  With eps >= max |chi| (and absorb = 0) the series with
+ * H = LSOP_PC_GAMMA converges; a layer needs a larger eps (2 max |chi| was
+ * measured to suffice).  vel_dev, h, freq_hz, c0 as lsop_set_problem.
+ * The dissipative state (V_eps, and a [max_vec][nx][nz] temporary of the
+ * widest dtype) is library-owned, allocated at the first call.  HODLR
+ * preconditioners and batches reject damped operators; lsop_set_problem
+ * returns the operator to the undissipated medium.  Errors: as
+ * lsop_set_problem; EINVAL for eps <= 0, absorb outside [0, min(nx, nz) / 2]
+ * or |k_eps h| / sqrt(pi) > 2. */
+int lsop_set_problem_damped(lsop_op* op, const double* vel_dev, double h, double freq_hz, double c0, double eps,
+                            int absorb, void* stream);
+
 /* y = op(x) for nvec vectors (mode: lsop_mode).  x and y may alias. */
 int lsop_apply(lsop_op* op, int mode, const void* x_dev, void* y_dev, int nvec, void* stream);
 
@@ -173,6 +195,11 @@ const char* lsop_last_error(void);
  *  LSOP_PC_IDENTITY  H = I (the Born series, Section 2.2).
  *  LSOP_PC_SCALAR    H = alpha I (Section 2.2: the scalar choice of the
  *                    homotopy series, alpha < 1).
+ *  LSOP_PC_GAMMA     H = gamma = i V_eps / eps pointwise, for an operator set
+ *                    by lsop_set_problem_damped: the series is then the
+ *                    convergent Born series (Section 2.2), started from
+ *                    gamma psi0 (LSOP_INIT_H_RHS).  Holds no state; reads the
+ *                    operator's current V_eps and eps at every apply.
  *  LSOP_PC_LOWRANK   H = I + U Z W^H with G0 V ~= U W^H from the randomized
  *                    range finder of Alg. 2 (power_iters = q) and
  *                    Z = (I_r - W^H U)^{-1} by Sherman-Morrison-Woodbury
@@ -203,7 +230,13 @@ const char* lsop_last_error(void);
  *                    operator's precision.  Requires nx divisible by 2^levels,
  *                    (nx / 2^levels) * nz a multiple of 64 and at most 8192.
  * ---------------------------------------------------------------------- */
-typedef enum { LSOP_PC_IDENTITY = 0, LSOP_PC_LOWRANK = 1, LSOP_PC_HODLR = 2, LSOP_PC_SCALAR = 3 } lsop_pc_kind;
+typedef enum {
+  LSOP_PC_IDENTITY = 0,
+  LSOP_PC_LOWRANK = 1,
+  LSOP_PC_HODLR = 2,
+  LSOP_PC_SCALAR = 3,
+  LSOP_PC_GAMMA = 4
+} lsop_pc_kind;
 
 typedef struct {
   int kind;         /* lsop_pc_kind */
@@ -481,6 +514,10 @@ void unet_destroy(unet* u);
 /* Diagnostics: FP64 Bessel evaluations used for the kernel table, on the host
  * (kind 0: (J0, Y0) at x > 0; kind 1: (J1, Y1) at 0 < x <= 2). */
 int lsop_bessel_host(int kind, double x, double* out2);
+/* The same at complex argument z = re + i im (Re z > 0, Im z >= 0), as used for
+ * the dissipative kernel table: kind 0: H0^(1)(z) as (re, im) in out4[0..1];
+ * kind 1: J1(z), Y1(z) for |z| <= 2 as out4[0..3]. */
+int lsop_bessel_host_c(int kind, double re, double im, double* out4);
 
 /* Per-kernel timing (diagnostics).  While enabled, every kernel launch of the
  * library is bracketed by HIP events recorded on its launch stream, and the

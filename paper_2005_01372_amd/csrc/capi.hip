@@ -8,9 +8,11 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "bessel.hpp"
+#include "bessel_complex.hpp"
 #include "internal.hpp"
 
 namespace lsop {
@@ -260,14 +262,49 @@ int apply_impl(lsop_op* op, int mode, const Cx<T>* x, Cx<T>* y, const Cx<T>* rhs
                int nvec, hipStream_t s, void* tmp_in = nullptr, int chunk = 0) {
   const size_t n = op->n();
   Cx<T>* tmp = reinterpret_cast<Cx<T>*>(tmp_in ? tmp_in : op->tmp);
-  const int step = chunk > 0 ? chunk : op->max_vec;
+  int step = chunk > 0 ? chunk : op->max_vec;
   const bool mulchi = (mode == LSOP_MODE_A || mode == LSOP_MODE_G0V);
   const bool adj = !mulchi;
+  // dissipative background (convergent Born series): the complex potential multiplies outside the FFT passes,
+  // through the operator's [max_vec][n] temporary
+  const bool damped = op->damped;
+  Cx<T>* vt = reinterpret_cast<Cx<T>*>(op->vtmp);
+  const Cx<T>* Vp = damped ? reinterpret_cast<const Cx<T>*>(std::is_same<T, float>::value ? (const void*)op->v32
+                                                                                            : (const void*)op->v64)
+                           : nullptr;
+  if (damped) step = std::min(step, op->max_vec);
   for (int c = 0; c < nvec; c += step) {
     const int m = std::min(step, nvec - c);
     const int* vc = vidx ? vidx + c : nullptr;
     const size_t off = vidx ? 0 : (size_t)c * n;
     double* rn = rnorm ? rnorm + c : nullptr;
+    if (damped) {
+      // u = V x (forward modes) into the temporary; the passes then convolve without the real contrast
+      const Cx<T>* xin1 = x + off;
+      const int* vin1 = vc;
+      if (mulchi) {
+        LSOP_HIP(prof("damped_vmul", "k_vmul", 3.0 * m * n * sizeof(Cx<T>), 6.0 * m * n, m, s, [&] {
+          return launch_vmul<T>(Vp, x + off, vc, nullptr, vt, nullptr, m, n, 0, 0.0, s);
+        }));
+        xin1 = vt;
+        vin1 = nullptr;
+      }
+      LSOP_HIP(launch_rows_fwd<T>(op->lz, xin1, Dt<T>::chi(op), tmp, vin1, op->nx, op->nz, m, false, Dt<T>::twz(op),
+                                  s));
+      LSOP_HIP(launch_cols<T>(op->lx, tmp, Dt<T>::gs(op), op->nx, op->pz(), m, adj, Dt<T>::twx(op), s, op->col_tile));
+      if (mulchi) {
+        LSOP_HIP(launch_rows_inv<T>(op->lz, tmp, x + off, Dt<T>::chi(op), rhs ? rhs + off : nullptr, y + off, rn, vc,
+                                    op->nx, op->nz, m, mode == LSOP_MODE_A ? 0 : 1, Dt<T>::twz(op), s));
+      } else {
+        // c = G^H x into the temporary, then y = x - conj(V) c (AH) or conj(V) c (VHG0H)
+        LSOP_HIP(launch_rows_inv<T>(op->lz, tmp, nullptr, Dt<T>::chi(op), nullptr, vt, nullptr, nullptr, op->nx,
+                                    op->nz, m, 1, Dt<T>::twz(op), s));
+        LSOP_HIP(prof("damped_vmul", "k_vmul", 3.0 * m * n * sizeof(Cx<T>), 6.0 * m * n, m, s, [&] {
+          return launch_vmul<T>(Vp, x + off, vc, vt, y + off, vc, m, n, mode == LSOP_MODE_AH ? 1 : 2, 0.0, s);
+        }));
+      }
+      continue;
+    }
     // algorithmic bytes: compulsory reads + writes of each pass (see the kernel file header)
     const double e = sizeof(Cx<T>), t = sizeof(T), nn = (double)n, np = (double)op->nx * op->pz();
     const double frow = 2.0 * fft_flops(op->lz) + 6.0 * op->lz;
@@ -491,6 +528,14 @@ int pc_apply_impl(lsop_precond* pc, const Cx<T>* x, Cx<T>* y, const int* vidx, i
       }
     }
     return LSOP_OK;
+  }
+  if (pc->kind == LSOP_PC_GAMMA) {  // H = gamma = i V_eps / eps pointwise (convergent Born series)
+    const lsop_op* op = pc->op;
+    if (!op->damped) return fail(LSOP_EINVAL, "H = gamma needs an operator set by lsop_set_problem_damped");
+    const Cx<T>* V = reinterpret_cast<const Cx<T>*>(std::is_same<T, float>::value ? (const void*)op->v32
+                                                                                    : (const void*)op->v64);
+    const hipError_t e = launch_vmul<T>(V, x, vidx, nullptr, y, vidx, nvec, n, series_update ? 4 : 3, 1.0 / op->eps, s);
+    return e == hipSuccess ? LSOP_OK : fail(LSOP_EHIP, "gamma launch failed");
   }
   if (pc->kind == LSOP_PC_SCALAR) {  // H = alpha I: y = alpha x, or psi <- psi - alpha r
     const hipError_t e = series_update ? launch_axpby<T>(x, y, -pc->alpha, 1.0, vidx, nvec, n, s)
@@ -1868,6 +1913,7 @@ int lsop_set_problem(lsop_op* op, const double* vel_dev, double h, double freq_h
   if (ka > 2.0) return fail(LSOP_EINVAL, "grid too coarse: k0 h / sqrt(pi) > 2");
   hipStream_t s = S(stream);
   const size_t n = op->n();
+  op->damped = false;
   LSOP_HIP(hipMemsetAsync(op->flag, 0, sizeof(unsigned), s));
   LSOP_HIP(launch_contrast(vel_dev, op->chi64, op->chi32, (int)n, w * w, 1.0 / (c0 * c0), op->flag, s));
   unsigned bad = 0;
@@ -1893,6 +1939,59 @@ int lsop_set_problem(lsop_op* op, const double* vel_dev, double h, double freq_h
   op->freq = freq_hz;
   op->c0 = c0;
   op->k0 = k0;
+  op->ready = true;
+  return LSOP_OK;
+}
+
+int lsop_set_problem_damped(lsop_op* op, const double* vel_dev, double h, double freq_hz, double c0, double eps,
+                            int absorb, void* stream) {
+  if (!op) return fail(LSOP_EINVAL, "null operator handle");
+  if (!(eps > 0) || !std::isfinite(eps)) return fail(LSOP_EINVAL, "eps must be positive and finite");
+  if (absorb < 0 || 2 * absorb > std::min(op->nx, op->nz)) return fail(LSOP_EINVAL, "absorb outside [0, min(nx, nz) / 2]");
+  // the undissipated set-up validates the medium and fills the contrast; the kernel table and spectrum are then
+  // replaced by those of the dissipative background
+  int st = lsop_set_problem(op, vel_dev, h, freq_hz, c0, stream);
+  if (st) return st;
+  op->ready = false;
+  hipStream_t s = S(stream);
+  const size_t n = op->n();
+  if (!op->v64) {
+    const size_t esz = op->has64() ? sizeof(Cx<double>) : sizeof(Cx<float>);
+    void *a = nullptr, *b = nullptr, *c = nullptr;
+    if (lib_malloc(&a, sizeof(Cx<double>) * n) != hipSuccess || lib_malloc(&b, sizeof(Cx<float>) * n) != hipSuccess ||
+        lib_malloc(&c, esz * (size_t)op->max_vec * n) != hipSuccess) {
+      (void)hipGetLastError();
+      for (void* p : {a, b, c})
+        if (p) (void)hipFree(p);
+      return fail(LSOP_ENOMEM, "dissipative operator buffers");
+    }
+    op->v64 = reinterpret_cast<Cx<double>*>(a);
+    op->v32 = reinterpret_cast<Cx<float>*>(b);
+    op->vtmp = c;
+    op->owned.push_back(a);
+    op->owned.push_back(b);
+    op->owned.push_back(c);
+  }
+  LSOP_HIP(launch_damped_potential(op->chi64, op->nx, op->nz, eps, absorb, op->v64, op->v32, s));
+  // k^2 = k0^2 + i eps, Re k > 0, Im k > 0; the same disk-integrated kernel with k in place of k0
+  using lsop_bessel::C;
+  const double pi = lsop_bessel::kPi;
+  const double k0 = op->k0;
+  const C k = lsop_bessel::c_sqrt(C{k0 * k0, eps});
+  const double a = h / std::sqrt(pi);
+  const C ka = a * k;
+  if (lsop_bessel::c_abs(ka) > 2.0) return fail(LSOP_EINVAL, "grid too coarse for the dissipative kernel: |k a| > 2");
+  C j1, y1;
+  lsop_bessel::bessel1_small_c(ka, &j1, &y1);
+  const C cc = lsop_bessel::c_div(C{0.0, pi * a}, 2.0 * k);
+  const C cj1 = cc * j1;
+  const C self = cc * C{j1.re - y1.im, j1.im + y1.re} - lsop_bessel::c_div(C{1.0, 0.0}, k * k);
+  LSOP_HIP(launch_table_c(op->ktab, op->nx, op->nz, h * k, cj1, self, s));
+  if ((st = grow_scratch(op, spectrum_ws_bytes(op)))) return st;
+  LSOP_HIP(launch_spectrum(op->lx, op->lz, op->ktab, op->nx, op->nz, reinterpret_cast<Cx<double>*>(op->scratch),
+                           op->gs64, op->gs32, op->tw2x64, op->tw2z64, s));
+  op->eps = eps;
+  op->damped = true;
   op->ready = true;
   return LSOP_OK;
 }
@@ -2031,7 +2130,7 @@ namespace {
 int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
   if (!op || !p) return fail(LSOP_EINVAL, "null argument");
   if (p->kind != LSOP_PC_IDENTITY && p->kind != LSOP_PC_LOWRANK && p->kind != LSOP_PC_HODLR &&
-      p->kind != LSOP_PC_SCALAR)
+      p->kind != LSOP_PC_SCALAR && p->kind != LSOP_PC_GAMMA)
     return fail(LSOP_EINVAL, "bad preconditioner kind");
   if (p->kind == LSOP_PC_SCALAR && (!std::isfinite(p->alpha) || p->alpha == 0.0))
     return fail(LSOP_EINVAL, "alpha must be finite and non-zero");
@@ -2056,7 +2155,7 @@ int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
   pc->seed = p->seed;
   pc->alpha = p->alpha;
   pc->dt = op->dtype == LSOP_C128 ? LSOP_C128 : LSOP_C64;
-  if (p->kind == LSOP_PC_IDENTITY || p->kind == LSOP_PC_SCALAR) return LSOP_OK;
+  if (p->kind == LSOP_PC_IDENTITY || p->kind == LSOP_PC_SCALAR || p->kind == LSOP_PC_GAMMA) return LSOP_OK;
   pc->rank = p->rank;
   pc->probes = p->kind == LSOP_PC_LOWRANK ? p->rank + p->oversample : p->rank;
   pc->q = p->power_iters;
@@ -2091,7 +2190,7 @@ int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
 
 // Every device buffer of a preconditioner's state, in one fixed order (the size query walks the same list).
 int pc_buffers(lsop_precond* pc, Alloc& a) {
-  if (pc->kind == LSOP_PC_IDENTITY || pc->kind == LSOP_PC_SCALAR) return LSOP_OK;
+  if (pc->kind == LSOP_PC_IDENTITY || pc->kind == LSOP_PC_SCALAR || pc->kind == LSOP_PC_GAMMA) return LSOP_OK;
   const lsop_op* op = pc->op;
   const size_t n = op->n();
   const size_t esz = pc->dt == LSOP_C128 ? sizeof(Cx<double>) : sizeof(Cx<float>);
@@ -2165,7 +2264,7 @@ int pc_create(lsop_op* op, const lsop_precond_params* p, void* state, size_t sta
     delete pc;
     return st;
   }
-  if (pc->kind == LSOP_PC_IDENTITY || pc->kind == LSOP_PC_SCALAR) pc->built = true;
+  if (pc->kind == LSOP_PC_IDENTITY || pc->kind == LSOP_PC_SCALAR || pc->kind == LSOP_PC_GAMMA) pc->built = true;
   Alloc a;
   a.owned = &pc->owned;
   a.bytes = &pc->bytes;
@@ -2229,6 +2328,10 @@ int precond_build(lsop_precond* pc, const void* omega_dev, void* stream) {
   int st = check_op(pc->op);
   if (st) return st;
   if (pc->kind == LSOP_PC_IDENTITY || pc->kind == LSOP_PC_SCALAR) return LSOP_OK;
+  if (pc->kind == LSOP_PC_GAMMA)
+    return pc->op->damped ? LSOP_OK : fail(LSOP_EINVAL, "H = gamma needs an operator set by lsop_set_problem_damped");
+  if (pc->kind == LSOP_PC_HODLR && pc->op->damped)
+    return fail(LSOP_EUNSUPPORTED, "the HODLR build samples the undissipated contrast; not for a damped operator");
   pc->built = false;
   if (pc->kind == LSOP_PC_HODLR) {
     if (pc->dt == LSOP_C128) return hodlr_build<double>(pc, (const double*)omega_dev, S(stream));
@@ -2533,6 +2636,7 @@ int lsop_batch_create(int count, lsop_op* const* ops, lsop_batch** out) {
     int st = check_op(ops[i]);
     if (st) return st;
     if (ops[i]->dtype == LSOP_MIXED) return fail(LSOP_EUNSUPPORTED, "batches take complex float or double operators");
+    if (ops[i]->damped) return fail(LSOP_EUNSUPPORTED, "batches take undissipated operators");
     if (dt >= 0 && ops[i]->dtype != dt) return fail(LSOP_EINVAL, "all operators of a batch must share one dtype");
     dt = ops[i]->dtype;
   }
@@ -2566,6 +2670,8 @@ int lsop_batch_create(int count, lsop_op* const* ops, lsop_batch** out) {
 }
 
 static int check_batch_vectors(const lsop_batch* b, const void* const* x, void* const* y, const int* nvec) {
+  for (const lsop_op* op : b->ops)
+    if (op->damped) return fail(LSOP_EUNSUPPORTED, "a batch member was set up as a dissipative operator");
   if (!b) return fail(LSOP_EINVAL, "null batch");
   if (!nvec || !x || !y) return fail(LSOP_EINVAL, "null vector arrays");
   for (int i = 0; i < b->count; ++i) {
@@ -2702,6 +2808,30 @@ int lsop_profile_read(lsop_kernel_stat* stats, int max_stats, int* count) {
 
 int lsop_profile_read_kernels(lsop_kernel_stat* stats, int max_stats, int* count) {
   return profile_read_by(true, stats, max_stats, count);
+}
+
+int lsop_bessel_host_c(int kind, double re, double im, double* out4) {
+  if (!out4) return fail(LSOP_EINVAL, "null output");
+  const lsop_bessel::C z{re, im};
+  if (!(re > 0) || !(im >= 0) || !std::isfinite(re) || !std::isfinite(im))
+    return fail(LSOP_EINVAL, "argument must have Re z > 0 and Im z >= 0");
+  if (kind == 0) {
+    const lsop_bessel::C hv = lsop_bessel::hankel0_c(z);
+    out4[0] = hv.re;
+    out4[1] = hv.im;
+    return LSOP_OK;
+  }
+  if (kind == 1) {
+    if (lsop_bessel::c_abs(z) > 2.0) return fail(LSOP_EINVAL, "|z| must be <= 2");
+    lsop_bessel::C j1, y1;
+    lsop_bessel::bessel1_small_c(z, &j1, &y1);
+    out4[0] = j1.re;
+    out4[1] = j1.im;
+    out4[2] = y1.re;
+    out4[3] = y1.im;
+    return LSOP_OK;
+  }
+  return fail(LSOP_EINVAL, "bad kind");
 }
 
 int lsop_bessel_host(int kind, double x, double* out2) {

@@ -167,6 +167,17 @@ hipError_t launch_mcombine(const Cx<T>* V, size_t bstride, int nb, const Cx<doub
 template <typename T>
 hipError_t launch_scale_by_norm(const Cx<T>* x, Cx<T>* y, const double* nrm2, double sign, const int* vidx, int na,
                                 size_t n, hipStream_t s);
+// Convergent Born series: kernel table at complex wavenumber (complex kh = k h), the potential
+// V_eps = chi - i eps r (absorbing-layer profile r, see lsop_set_problem_damped) in FP64 and FP32 (either may be
+// NULL), and pointwise products with it (x through xidx, y through yidx, c compact): op 0 y = V x,
+// 1 y = x - conj(V) c, 2 y = conj(V) c, 3 y = gamma x, 4 y = y - gamma x, gamma = i V scale (scale = 1 / eps).
+hipError_t launch_table_c(Cx<double>* ktab, int nx, int nz, Cx<double> kh, Cx<double> cj1, Cx<double> self,
+                          hipStream_t s);
+hipError_t launch_damped_potential(const double* chi, int nx, int nz, double eps, int absorb, Cx<double>* v64,
+                                   Cx<float>* v32, hipStream_t s);
+template <typename T>
+hipError_t launch_vmul(const Cx<T>* V, const Cx<T>* x, const int* xidx, const Cx<T>* c, Cx<T>* y, const int* yidx,
+                       int nvec, size_t n, int op, double scale, hipStream_t s);
 // HODLR: dense leaf blocks of I - G0 V (formed in FP64, stored as To), leaves leaf0 .. leaf0 + nleaf - 1 of nl cells
 template <typename To>
 hipError_t launch_leaf_form(const Cx<double>* ktab, const double* chi, Cx<To>* out, int nz, int nl, int leaf0,
@@ -237,6 +248,12 @@ struct lsop_op {
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
   bool ws_external = false;     // scratch is the caller's: never grown, reallocated or freed
+  // convergent Born series (lsop_set_problem_damped): dissipative background and complex potential
+  bool damped = false;
+  double eps = 0.0;
+  Cx<double>* v64 = nullptr;    // V_eps = chi - i eps r, [nx][nz]
+  Cx<float>* v32 = nullptr;
+  void* vtmp = nullptr;         // [max_vec][n] pointwise products around the convolution
   bool state_external = false;  // device state carved from the caller's buffer (lsop_create_in)
   std::vector<void*> owned;
 };

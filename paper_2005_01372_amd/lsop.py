@@ -23,12 +23,12 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", NOT_
                 DIVERGED: "DIVERGED", ESINGULAR: "ESINGULAR", EUNSUPPORTED: "EUNSUPPORTED"}
 C64, C128, MIXED = 0, 1, 2
 MODES = {"A": 0, "G0V": 1, "AH": 2, "VHG0H": 3}
-PC_IDENTITY, PC_LOWRANK, PC_HODLR, PC_SCALAR = 0, 1, 2, 3
+PC_IDENTITY, PC_LOWRANK, PC_HODLR, PC_SCALAR, PC_GAMMA = 0, 1, 2, 3, 4
 INIT = {"h_rhs": 0, "zero": 1, "user": 2, "best": 3}
 
 EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident", "lsop_autotune",
            "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "lsop_state_bytes",
-           "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count", "lsop_apply_noalloc", "gmres_solve", "gmres_workspace_bytes", "lsop_sweep",
+           "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count", "lsop_apply_noalloc", "gmres_solve", "gmres_workspace_bytes", "lsop_sweep", "lsop_set_problem_damped", "lsop_bessel_host_c",
            "precond_state_bytes", "precond_create_in", "precond_create",
            "precond_build", "precond_build_batch", "precond_apply", "precond_info", "precond_destroy", "series_solve",
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
@@ -100,6 +100,8 @@ def load_library(path=LIB_PATH):
         "lsop_create": (ip, [ip, ip, ip, ip, C.POINTER(vp)]),
         "lsop_set_problem": (ip, [vp, vp, dp, dp, dp, vp]),
         "lsop_apply": (ip, [vp, ip, vp, vp, ip, vp]),
+        "lsop_set_problem_damped": (ip, [vp, vp, dp, dp, dp, dp, ip, vp]),
+        "lsop_bessel_host_c": (ip, [ip, dp, dp, C.POINTER(dp)]),
         "lsop_residual": (ip, [vp, vp, vp, vp, vp, ip, vp]),
         "lsop_incident": (ip, [vp, vp, vp, vp, ip, vp, vp]),
         "lsop_kernel_table": (ip, [vp, vp, vp]),
@@ -213,6 +215,16 @@ def _byte_buffer(t, need, what):
     return t
 
 
+def bessel_host_c(kind, z):
+    """Host evaluation of the library's complex-argument Bessel routines: kind 0 -> H0^(1)(z); kind 1 -> (J1, Y1)."""
+    lib = load_library()
+    out = (C.c_double * 4)()
+    _check(lib.lsop_bessel_host_c(int(kind), float(complex(z).real), float(complex(z).imag), out))
+    if kind == 0:
+        return complex(out[0], out[1])
+    return complex(out[0], out[1]), complex(out[2], out[3])
+
+
 def profile_enable(on=True):
     _check(load_library().lsop_profile_enable(int(bool(on))))
 
@@ -280,6 +292,21 @@ class Operator:
         self._vel = vel
         _check(self.lib.lsop_set_problem(self.handle, _ptr(vel), float(h), float(freq), float(c0), _stream()))
         self.h, self.freq, self.c0 = float(h), float(freq), float(c0)
+        return self
+
+    def set_problem_damped(self, vel, h, freq, c0=2000.0, eps=None, absorb=0):
+        """The convergent Born series' medium (lsop_set_problem_damped): dissipative background k0^2 + i eps, gain
+        in the potential, optional absorbing layer of `absorb` cells."""
+        vel = torch.as_tensor(vel, dtype=torch.float64)
+        if not vel.is_cuda:
+            vel = vel.cuda()
+        vel = vel.contiguous()
+        if tuple(vel.shape) != (self.nx, self.nz):
+            raise ValueError(f"velocity must be {(self.nx, self.nz)}")
+        self._vel = vel
+        _check(self.lib.lsop_set_problem_damped(self.handle, _ptr(vel), float(h), float(freq), float(c0), float(eps),
+                                                int(absorb), _stream()))
+        self.h, self.freq, self.c0, self.eps = float(h), float(freq), float(c0), float(eps)
         return self
 
     def _vecs(self, x, dtype=None, nvec=None):

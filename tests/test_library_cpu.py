@@ -164,3 +164,31 @@ def test_unet_checks_shapes():
         net.warm_start(op, psi0, out=torch.zeros((1, 6, 5), dtype=torch.complex64))
     with pytest.raises(TypeError):
         net.warm_start(op, psi0, out=torch.zeros((2, 6, 5), dtype=torch.complex128))
+
+
+@pytest.mark.parametrize("z", [0.3 + 0.05j, 1.7 + 0.6j, 5.0 + 0.01j, 9.3 + 2.5j, 15.0 + 4.0j, 19.9 + 1.0j,
+                               20.1 + 1.0j, 37.0 + 9.0j, 150.0 + 20.0j, 800.0 + 0.5j])
+def test_host_hankel0_complex(lib, z):
+    """H0^(1) at complex argument (the dissipative kernel table), against scipy's AMOS routine.  For large Im z the
+    value itself is small (e^{-Im z}) and J0, Y0 cancel in the series branch, so the bound is relative to
+    |J0| + |Y0| there."""
+    h = lsop.bessel_host_c(0, z)
+    ref = sp.hankel1(0, z)
+    scale = max(abs(ref), abs(sp.jv(0, z)) + abs(sp.yv(0, z))) if abs(z) < 20 else abs(ref)
+    assert abs(h - ref) <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("z", [0.05 + 0.001j, 0.2 + 0.1j, 0.9 + 0.4j, 1.5 + 1.2j])
+def test_host_bessel1_complex(lib, z):
+    j1, y1 = lsop.bessel_host_c(1, z)
+    assert abs(j1 - sp.jv(1, z)) <= 1e-14 * abs(sp.jv(1, z))
+    assert abs(y1 - sp.yv(1, z)) <= 1e-14 * abs(sp.yv(1, z))
+
+
+@pytest.mark.parametrize("z", [12.0 + 8.0j, 14.0 + 6.5j, 10.5 + 9.6j])
+def test_host_hankel0_complex_large_imaginary_part(lib, z):
+    """Where Im z is large the library switches to Hankel's expansion before |z| = 20 (|z| + Im z >= 20): H0 is
+    then accurate relative to its own (small) size."""
+    h = lsop.bessel_host_c(0, z)
+    ref = sp.hankel1(0, z)
+    assert abs(h - ref) <= 1e-12 * abs(ref)
