@@ -76,6 +76,7 @@ typedef struct {
   int max_vec;     /* vectors per internal batch */
   size_t state_bytes;  /* device bytes held by the handle */
   int col_tile;    /* columns per workgroup in the column FFT pass (0 = widest that fits) */
+  int ny, ly;      /* 3D operators: cells and FFT length along y (1 and 0 in 2D) */
 } lsop_op_info;
 
 /* Plan an operator for an nx x nz grid and allocate its device state.
@@ -117,6 +118,29 @@ int lsop_set_problem(lsop_op* op, const double* vel_dev, double h, double freq_h
  * or |k_eps h| / sqrt(pi) > 2. */
 int lsop_set_problem_damped(lsop_op* op, const double* vel_dev, double h, double freq_hz, double c0, double eps,
                             int absorb, void* stream);
+
+/* ----------------------------------------------------------------------
+ * 3D operators (the extension to 3D the paper points to in Sections 1 and 4).
+ * Grid nx x ny x nz cells of size h, cell (i, j, l) with l fastest:
+ * n = (i ny + j) nz + l; vectors [nvec][nx][ny][nz].  G0(r) = e^{i k0 r} /
+ * (4 pi r) (outgoing, exp(-i omega t)); the kernel table is its integral over
+ * the ball of the cell's volume (radius a = h (3 / (4 pi))^(1/3)):
+ * K = (sin k0 a - k0 a cos k0 a) / k0^3 e^{i k0 r} / r at r = h |lag| > 0 and
+ * ((1 - i k0 a) e^{i k0 a} - 1) / k0^2 on the diagonal; (G0 V)_{mn} =
+ * K(m - n) chi_n.  The FFT convolution runs in five passes (z rows, y columns
+ * per x-plane, x columns with the spectrum, y columns back, z rows back with
+ * the epilogue) on an intermediate of nx * 2ly * 2lz values per vector.
+ * lsop_apply, lsop_residual, lsop_apply_noalloc, series_solve, gmres_solve and
+ * the LOWRANK / SCALAR preconditioners take 3D operators unchanged; HODLR,
+ * batches, the dissipative medium and the network are 2D only.  3D operators
+ * are library-owned (no lsop_create_in form). */
+int lsop_create3d(int nx, int ny, int nz, int dtype, int max_vec, lsop_op** out);
+/* Contrast (eq. 1), kernel table and spectrum; vel_dev nx*ny*nz doubles.  Errors as lsop_set_problem
+ * (k0 a > 2: grid too coarse). */
+int lsop_set_problem3d(lsop_op* op, const double* vel_dev, double h, double freq_hz, double c0, void* stream);
+/* psi0 of point sources: src_ijl_host[3 k + {0, 1, 2}] = (i, j, l), density amp / h^3. */
+int lsop_incident3d(lsop_op* op, const int* src_ijl_host, const double* amp_reim_host, int nsrc, void* psi0_dev,
+                    void* stream);
 
 /* y = op(x) for nvec vectors (mode: lsop_mode).  x and y may alias. */
 int lsop_apply(lsop_op* op, int mode, const void* x_dev, void* y_dev, int nvec, void* stream);

@@ -244,6 +244,7 @@ struct Dt<float> {
   static const Cx<float>* gs(const lsop_op* op) { return op->gs32; }
   static const Cx<float>* twx(const lsop_op* op) { return op->tw2x32; }
   static const Cx<float>* twz(const lsop_op* op) { return op->tw2z32; }
+  static const Cx<float>* twy(const lsop_op* op) { return op->tw2y32; }
 };
 template <>
 struct Dt<double> {
@@ -251,6 +252,7 @@ struct Dt<double> {
   static const Cx<double>* gs(const lsop_op* op) { return op->gs64; }
   static const Cx<double>* twx(const lsop_op* op) { return op->tw2x64; }
   static const Cx<double>* twz(const lsop_op* op) { return op->tw2z64; }
+  static const Cx<double>* twy(const lsop_op* op) { return op->tw2y64; }
 };
 
 // y = op(x) (mode), or r = A x - rhs with norms when rhs != NULL.  Vectors are
@@ -278,6 +280,46 @@ int apply_impl(lsop_op* op, int mode, const Cx<T>* x, Cx<T>* y, const Cx<T>* rhs
     const int* vc = vidx ? vidx + c : nullptr;
     const size_t off = vidx ? 0 : (size_t)c * n;
     double* rn = rnorm ? rnorm + c : nullptr;
+    // algorithmic bytes: compulsory reads + writes of each pass (see the kernel file header)
+    const double e = sizeof(Cx<T>), t = sizeof(T), nn = (double)n;
+    const double np = (double)op->nx * op->pz();
+    const double frow = 2.0 * fft_flops(op->lz) + 6.0 * op->lz;
+    const double fcols = 4.0 * fft_flops(op->lx) + 18.0 * op->lx;
+    const bool xin = (mode == LSOP_MODE_A || mode == LSOP_MODE_AH);
+    const bool chi_out = (mode == LSOP_MODE_AH || mode == LSOP_MODE_VHG0H);
+    if (op->dims == 3) {
+      // 3D: z rows (x-plane i's ny rows stored in a plane of py rows), y columns forward per x-plane, x columns
+      // with the spectrum (k_cols over the py pz columns), y columns inverse, z rows inverse with the epilogue
+      const int py = op->py(), pz = op->pz(), planes = m * op->nx;
+      const double np3 = (double)op->nx * py * pz;
+      LSOP_HIP(prof("lsop3_rows_fwd", fn_name("k_rows_fwd", tname<T>(), op->lz),
+                    m * (nn * e + np3 * e / 2) + (mulchi ? nn * t : 0.0), (double)planes * op->ny * frow, m, s, [&] {
+                      return launch_rows_fwd<T>(op->lz, x + off, Dt<T>::chi(op), tmp, vc, op->ny, op->nz, planes,
+                                                mulchi, Dt<T>::twz(op), s, op->nx, 0, op->ny, nullptr, py);
+                    }));
+      LSOP_HIP(prof("lsop3_cols_y", "k_cols_half", m * (np3 * e / 2 + np3 * e), (double)planes * pz *
+                    2.0 * fft_flops(op->ly), m, s, [&] {
+                      return launch_cols_half<T>(0, op->ly, tmp, py, op->ny, pz, planes, Dt<T>::twy(op), s);
+                    }));
+      LSOP_HIP(prof("lsop3_cols_x", fn_name("k_cols", tname<T>(), op->lx), m * 2.0 * np3 * e + np3 * e,
+                    (double)m * py * pz * fcols, m, s, [&] {
+                      return launch_cols<T>(op->lx, tmp, Dt<T>::gs(op), op->nx, py * pz, m, adj, Dt<T>::twx(op), s,
+                                            op->col_tile);
+                    }));
+      LSOP_HIP(prof("lsop3_cols_y", "k_cols_half", m * (np3 * e + np3 * e / 2), (double)planes * pz *
+                    2.0 * fft_flops(op->ly), m, s, [&] {
+                      return launch_cols_half<T>(1, op->ly, tmp, py, op->ny, pz, planes, Dt<T>::twy(op), s);
+                    }));
+      LSOP_HIP(prof("lsop3_rows_inv", fn_name("k_rows_inv", tname<T>(), op->lz),
+                    m * (np3 * e / 2 + nn * e + (xin ? nn * e : 0.0) + (rhs ? nn * e : 0.0)) +
+                        (chi_out ? nn * t : 0.0),
+                    (double)planes * op->ny * frow, m, s, [&] {
+                      return launch_rows_inv<T>(op->lz, tmp, x + off, Dt<T>::chi(op), rhs ? rhs + off : nullptr,
+                                                y + off, rn, vc, op->ny, op->nz, planes, mode, Dt<T>::twz(op), s,
+                                                op->nx, 0, op->ny, nullptr, py);
+                    }));
+      continue;
+    }
     if (damped) {
       // u = V x (forward modes) into the temporary; the passes then convolve without the real contrast
       const Cx<T>* xin1 = x + off;
@@ -305,12 +347,6 @@ int apply_impl(lsop_op* op, int mode, const Cx<T>* x, Cx<T>* y, const Cx<T>* rhs
       }
       continue;
     }
-    // algorithmic bytes: compulsory reads + writes of each pass (see the kernel file header)
-    const double e = sizeof(Cx<T>), t = sizeof(T), nn = (double)n, np = (double)op->nx * op->pz();
-    const double frow = 2.0 * fft_flops(op->lz) + 6.0 * op->lz;
-    const double fcols = 4.0 * fft_flops(op->lx) + 18.0 * op->lx;
-    const bool xin = (mode == LSOP_MODE_A || mode == LSOP_MODE_AH);
-    const bool chi_out = (mode == LSOP_MODE_AH || mode == LSOP_MODE_VHG0H);
     std::string fcol;
     LSOP_HIP(prof("lsop_rows_fwd", fn_name("k_rows_fwd", tname<T>(), op->lz), m * (nn * e + np * e) + (mulchi ? nn * t : 0.0),
                   (double)m * op->nx * frow, m, s, [&] {
@@ -983,7 +1019,9 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
 
 // Workspace of lsop_set_problem (the transposed FP64 intermediate of the spectrum) and of series_solve on nvec
 // right-hand sides (the layouts carved in series_solve).
-size_t spectrum_ws_bytes(const lsop_op* op) { return sizeof(Cx<double>) * (size_t)op->px() * op->pz(); }
+size_t spectrum_ws_bytes(const lsop_op* op) {
+  return sizeof(Cx<double>) * (size_t)op->px() * op->py() * op->pz();
+}
 
 size_t series_ws_bytes(const lsop_op* op, int nvec, int init) {
   const size_t n = op->n();
@@ -1755,7 +1793,7 @@ hipError_t prof_launch(const char* name, const char* fn, double bytes, double fl
 }
 
 size_t apply_tmp_bytes_per_vec(const lsop_op* op) {
-  return (op->has64() ? sizeof(Cx<double>) : sizeof(Cx<float>)) * (size_t)op->nx * op->pz();
+  return (op->has64() ? sizeof(Cx<double>) : sizeof(Cx<float>)) * (size_t)op->nx * op->py() * op->pz();
 }
 
 int apply_into(lsop_op* op, int mode, const void* x, void* y, int nvec, void* tmp, int chunk, hipStream_t s) {
@@ -1807,37 +1845,40 @@ int op_buffers(lsop_op* op, Alloc& a) {
   const size_t px = op->px(), pz = op->pz();
   const int lx = op->lx, lz = op->lz;
   int st = 0;
+  const size_t py = op->py();
   st |= dev_alloc(a, &op->chi64, sizeof(double) * n);
   if (op->has32()) st |= dev_alloc(a, &op->chi32, sizeof(float) * n);
   st |= dev_alloc(a, &op->ktab, sizeof(Cx<double>) * n);
-  if (op->has64()) st |= dev_alloc(a, &op->gs64, sizeof(Cx<double>) * px * pz);
-  if (op->has32()) st |= dev_alloc(a, &op->gs32, sizeof(Cx<float>) * px * pz);
+  if (op->has64()) st |= dev_alloc(a, &op->gs64, sizeof(Cx<double>) * px * py * pz);
+  if (op->has32()) st |= dev_alloc(a, &op->gs32, sizeof(Cx<float>) * px * py * pz);
   st |= dev_alloc(a, &op->tw2x64, sizeof(Cx<double>) * 2 * lx);
   st |= dev_alloc(a, &op->tw2z64, sizeof(Cx<double>) * 2 * lz);
+  if (op->dims == 3) st |= dev_alloc(a, &op->tw2y64, sizeof(Cx<double>) * 2 * op->ly);
   if (op->has32()) {
     st |= dev_alloc(a, &op->tw2x32, sizeof(Cx<float>) * 2 * lx);
     st |= dev_alloc(a, &op->tw2z32, sizeof(Cx<float>) * 2 * lz);
+    if (op->dims == 3) st |= dev_alloc(a, &op->tw2y32, sizeof(Cx<float>) * 2 * op->ly);
   }
   const size_t esz = op->has64() ? sizeof(Cx<double>) : sizeof(Cx<float>);
-  st |= dev_alloc(a, &op->tmp, esz * (size_t)op->max_vec * op->nx * pz);
+  st |= dev_alloc(a, &op->tmp, esz * (size_t)op->max_vec * op->nx * py * pz);
   st |= dev_alloc(a, &op->flag, 256);
-  st |= dev_alloc(a, &op->dsrc, sizeof(int) * 2 * op->src_cap);
+  st |= dev_alloc(a, &op->dsrc, sizeof(int) * 3 * op->src_cap);
   st |= dev_alloc(a, &op->damp, sizeof(Cx<double>) * op->src_cap);
   return st ? LSOP_ENOMEM : LSOP_OK;
 }
 
 // Twiddle tables of both axes (host-computed, uploaded synchronously).
 int op_twiddles(lsop_op* op) {
-  for (int axis = 0; axis < 2; ++axis) {
-    const int L = axis == 0 ? op->lx : op->lz;
+  for (int axis = 0; axis < op->dims; ++axis) {
+    const int L = axis == 0 ? op->lx : axis == 1 ? op->lz : op->ly;
     std::vector<Cx<double>> w = twiddles(L);
-    Cx<double>* d64 = axis == 0 ? op->tw2x64 : op->tw2z64;
+    Cx<double>* d64 = axis == 0 ? op->tw2x64 : axis == 1 ? op->tw2z64 : op->tw2y64;
     if (hipMemcpy(d64, w.data(), sizeof(Cx<double>) * w.size(), hipMemcpyHostToDevice) != hipSuccess)
       return fail(LSOP_EHIP, "twiddle upload failed");
     if (op->has32()) {
       std::vector<Cx<float>> w32(w.size());
       for (size_t t = 0; t < w.size(); ++t) w32[t] = ccast<float>(w[t]);
-      Cx<float>* d32 = axis == 0 ? op->tw2x32 : op->tw2z32;
+      Cx<float>* d32 = axis == 0 ? op->tw2x32 : axis == 1 ? op->tw2z32 : op->tw2y32;
       if (hipMemcpy(d32, w32.data(), sizeof(Cx<float>) * w32.size(), hipMemcpyHostToDevice) != hipSuccess)
         return fail(LSOP_EHIP, "twiddle upload failed");
     }
@@ -1845,11 +1886,26 @@ int op_twiddles(lsop_op* op) {
   return LSOP_OK;
 }
 
-int op_create(int nx, int nz, int dtype, int max_vec, void* state, size_t state_bytes, lsop_op** out) {
+// 3D plan on top of the 2D one: the y axis, its FFT length, and the size limit of the flattened index.
+int op_plan3(int nx, int ny, int nz, int dtype, int max_vec, lsop_op* op) {
+  int st = op_plan(nx, nz, dtype, max_vec, op);
+  if (st) return st;
+  if (ny < 1) return fail(LSOP_EINVAL, "ny must be >= 1");
+  const int ly = fft_length_for(ny);
+  if (ly < 0) return fail(LSOP_EUNSUPPORTED, "grid side exceeds the largest FFT length (2048)");
+  if ((size_t)nx * ny * nz > (size_t)INT32_MAX / 4 || (size_t)nx * 2 * ly * 2 * op->lz > (size_t)INT32_MAX)
+    return fail(LSOP_EUNSUPPORTED, "3D grid too large");
+  op->ny = ny;
+  op->ly = ly;
+  op->dims = 3;
+  return LSOP_OK;
+}
+
+int op_create(int nx, int nz, int dtype, int max_vec, void* state, size_t state_bytes, lsop_op** out, int ny = 0) {
   if (!out) return fail(LSOP_EINVAL, "null output handle");
   *out = nullptr;
   lsop_op* op = new lsop_op();
-  int st = op_plan(nx, nz, dtype, max_vec, op);
+  int st = ny > 0 ? op_plan3(nx, ny, nz, dtype, max_vec, op) : op_plan(nx, nz, dtype, max_vec, op);
   if (st) {
     delete op;
     return st;
@@ -1902,6 +1958,7 @@ int lsop_state_bytes(int nx, int nz, int dtype, int max_vec, size_t* bytes) {
 
 int lsop_set_problem(lsop_op* op, const double* vel_dev, double h, double freq_hz, double c0, void* stream) {
   if (!op) return fail(LSOP_EINVAL, "null operator handle");
+  if (op->dims == 3) return fail(LSOP_EINVAL, "3D operator: use lsop_set_problem3d");
   if (!vel_dev) return fail(LSOP_EINVAL, "null velocity");
   if (!(h > 0) || !(freq_hz > 0) || !(c0 > 0) || !std::isfinite(h) || !std::isfinite(freq_hz) || !std::isfinite(c0))
     return fail(LSOP_EINVAL, "h, freq_hz and c0 must be positive and finite");
@@ -1946,6 +2003,7 @@ int lsop_set_problem(lsop_op* op, const double* vel_dev, double h, double freq_h
 int lsop_set_problem_damped(lsop_op* op, const double* vel_dev, double h, double freq_hz, double c0, double eps,
                             int absorb, void* stream) {
   if (!op) return fail(LSOP_EINVAL, "null operator handle");
+  if (op->dims == 3) return fail(LSOP_EUNSUPPORTED, "the dissipative medium is built for 2D operators");
   if (!(eps > 0) || !std::isfinite(eps)) return fail(LSOP_EINVAL, "eps must be positive and finite");
   if (absorb < 0 || 2 * absorb > std::min(op->nx, op->nz)) return fail(LSOP_EINVAL, "absorb outside [0, min(nx, nz) / 2]");
   // the undissipated set-up validates the medium and fills the contrast; the kernel table and spectrum are then
@@ -1996,6 +2054,78 @@ int lsop_set_problem_damped(lsop_op* op, const double* vel_dev, double h, double
   return LSOP_OK;
 }
 
+int lsop_create3d(int nx, int ny, int nz, int dtype, int max_vec, lsop_op** out) {
+  return op_create(nx, nz, dtype, max_vec, nullptr, 0, out, ny);
+}
+
+int lsop_set_problem3d(lsop_op* op, const double* vel_dev, double h, double freq_hz, double c0, void* stream) {
+  if (!op) return fail(LSOP_EINVAL, "null operator handle");
+  if (op->dims != 3) return fail(LSOP_EINVAL, "2D operator: use lsop_set_problem");
+  if (!vel_dev) return fail(LSOP_EINVAL, "null velocity");
+  if (!(h > 0) || !(freq_hz > 0) || !(c0 > 0) || !std::isfinite(h) || !std::isfinite(freq_hz) || !std::isfinite(c0))
+    return fail(LSOP_EINVAL, "h, freq_hz and c0 must be positive and finite");
+  const double pi = lsop_bessel::kPi;
+  const double w = 2.0 * pi * freq_hz, k0 = w / c0;
+  const double a = h * std::cbrt(3.0 / (4.0 * pi));   // radius of the ball of the cell's volume
+  const double ka = k0 * a;
+  if (ka > 2.0) return fail(LSOP_EINVAL, "grid too coarse: k0 a > 2");
+  hipStream_t s = S(stream);
+  const size_t n = op->n();
+  op->ready = false;
+  LSOP_HIP(hipMemsetAsync(op->flag, 0, sizeof(unsigned), s));
+  LSOP_HIP(launch_contrast(vel_dev, op->chi64, op->chi32, (int)n, w * w, 1.0 / (c0 * c0), op->flag, s));
+  unsigned bad = 0;
+  LSOP_HIP(hipMemcpyAsync(&bad, op->flag, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+  LSOP_HIP(hipStreamSynchronize(s));
+  if (bad) return fail(LSOP_EINVAL, "velocity must be finite and positive");
+  // ball-integrated e^{ikr} / (4 pi r): c1 e^{ik0 r} / r off the diagonal, ((1 - i ka) e^{ika} - 1) / k0^2 on it
+  double sn, cs;
+  sincos(ka, &sn, &cs);
+  const double c1 = (sn - ka * cs) / (k0 * k0 * k0);
+  const Cx<double> self{(cs + ka * sn - 1.0) / (k0 * k0), (sn - ka * cs) / (k0 * k0)};
+  LSOP_HIP(launch_table3(op->ktab, op->nx, op->ny, op->nz, k0, h, c1, self, s));
+  int st = grow_scratch(op, spectrum_ws_bytes(op));
+  if (st) return st;
+  LSOP_HIP(launch_spectrum3(op->lx, op->ly, op->lz, op->ktab, op->nx, op->ny, op->nz,
+                            reinterpret_cast<Cx<double>*>(op->tmp), reinterpret_cast<Cx<double>*>(op->scratch),
+                            op->gs64, op->gs32, op->tw2x64, op->tw2y64, op->tw2z64, s));
+  op->h = h;
+  op->freq = freq_hz;
+  op->c0 = c0;
+  op->k0 = k0;
+  op->ready = true;
+  return LSOP_OK;
+}
+
+int lsop_incident3d(lsop_op* op, const int* src_ijl_host, const double* amp_reim_host, int nsrc, void* psi0_dev,
+                    void* stream) {
+  int st = check_op(op);
+  if (st) return st;
+  if (op->dims != 3) return fail(LSOP_EINVAL, "2D operator: use lsop_incident");
+  if (nsrc < 0 || (nsrc > 0 && (!src_ijl_host || !psi0_dev))) return fail(LSOP_EINVAL, "bad sources");
+  if (nsrc > op->src_cap) return fail(LSOP_EINVAL, "too many sources in one call (max 4096)");
+  for (int k = 0; k < nsrc; ++k)
+    if (src_ijl_host[3 * k] < 0 || src_ijl_host[3 * k] >= op->nx || src_ijl_host[3 * k + 1] < 0 ||
+        src_ijl_host[3 * k + 1] >= op->ny || src_ijl_host[3 * k + 2] < 0 || src_ijl_host[3 * k + 2] >= op->nz)
+      return fail(LSOP_EINVAL, "source outside the grid");
+  if (nsrc == 0) return LSOP_OK;
+  hipStream_t s = S(stream);
+  std::vector<Cx<double>> amp(nsrc);
+  for (int k = 0; k < nsrc; ++k)
+    amp[k] = amp_reim_host ? Cx<double>{amp_reim_host[2 * k], amp_reim_host[2 * k + 1]} : Cx<double>{1.0, 0.0};
+  LSOP_HIP(hipStreamSynchronize(s));
+  LSOP_HIP(hipMemcpy(op->dsrc, src_ijl_host, sizeof(int) * 3 * (size_t)nsrc, hipMemcpyHostToDevice));
+  LSOP_HIP(hipMemcpy(op->damp, amp.data(), sizeof(Cx<double>) * nsrc, hipMemcpyHostToDevice));
+  const double inv_dv = 1.0 / (op->h * op->h * op->h);
+  if (op->dtype == LSOP_C64)
+    LSOP_HIP(launch_incident3<float>(op->ktab, op->dsrc, op->damp, (Cx<float>*)psi0_dev, op->nx, op->ny, op->nz,
+                                     nsrc, inv_dv, s));
+  else
+    LSOP_HIP(launch_incident3<double>(op->ktab, op->dsrc, op->damp, (Cx<double>*)psi0_dev, op->nx, op->ny, op->nz,
+                                      nsrc, inv_dv, s));
+  return LSOP_OK;
+}
+
 int lsop_apply(lsop_op* op, int mode, const void* x_dev, void* y_dev, int nvec, void* stream) {
   int st = check_op(op);
   if (st) return st;
@@ -2026,6 +2156,7 @@ int lsop_incident(lsop_op* op, const int* src_i_host, const int* src_j_host, con
                   void* psi0_dev, void* stream) {
   int st = check_op(op);
   if (st) return st;
+  if (op->dims == 3) return fail(LSOP_EINVAL, "3D operator: use lsop_incident3d");
   if (nsrc < 0 || (nsrc > 0 && (!src_i_host || !src_j_host || !psi0_dev))) return fail(LSOP_EINVAL, "bad sources");
   if (nsrc > op->src_cap) return fail(LSOP_EINVAL, "too many sources in one call (max 4096)");
   for (int k = 0; k < nsrc; ++k)
@@ -2082,6 +2213,8 @@ int lsop_info(const lsop_op* op, lsop_op_info* info) {
   info->max_vec = op->max_vec;
   info->state_bytes = op->bytes + (op->ws_external ? 0 : op->scratch_bytes);
   info->col_tile = op->col_tile;
+  info->ny = op->ny;
+  info->ly = op->ly;
   return LSOP_OK;
 }
 
@@ -2142,6 +2275,7 @@ int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
   if (p->kind != LSOP_PC_LOWRANK && p->oversample != 0)
     return fail(LSOP_EINVAL, "oversampling applies to the low-rank preconditioner only");
   if (p->kind == LSOP_PC_HODLR) {
+    if (op->dims == 3) return fail(LSOP_EUNSUPPORTED, "the HODLR tree is built on 2D column strips");
     if (p->levels < 1 || p->levels > 16 || op->nx % (1 << p->levels) != 0)
       return fail(LSOP_EINVAL, "HODLR levels must be >= 1 with nx divisible by 2^levels");
     const size_t nl = (size_t)(op->nx >> p->levels) * op->nz;
@@ -2637,6 +2771,7 @@ int lsop_batch_create(int count, lsop_op* const* ops, lsop_batch** out) {
     if (st) return st;
     if (ops[i]->dtype == LSOP_MIXED) return fail(LSOP_EUNSUPPORTED, "batches take complex float or double operators");
     if (ops[i]->damped) return fail(LSOP_EUNSUPPORTED, "batches take undissipated operators");
+    if (ops[i]->dims == 3) return fail(LSOP_EUNSUPPORTED, "batches take 2D operators");
     if (dt >= 0 && ops[i]->dtype != dt) return fail(LSOP_EINVAL, "all operators of a batch must share one dtype");
     dt = ops[i]->dtype;
   }

@@ -50,25 +50,44 @@ struct Slot {
 // rows, transformed independently (slot = vector * nodes + node, chi sliced per
 // strip); rows outside [lo, hi) of a strip are read as zero (hi < 0: nx).
 // Grouped batches (tab != NULL, nodes = 1, no vidx): slot s takes its operands from tab[s].
+// trows: rows per slot of tmp (default nx): a slot's rows i < nx are written to tmp rows slot * trows + i (the
+// 3D operator stores each x-plane's ny rows in a plane of py rows).
 template <typename T>
 hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, const int* vidx, int nx, int nz,
                            int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s, int nodes = 1, int lo = 0,
-                           int hi = -1, const Slot<T>* tab = nullptr);
+                           int hi = -1, const Slot<T>* tab = nullptr, int trows = -1);
 // tile: columns per workgroup (0 = widest that fits; narrower tiles allow more workgroups per CU)
 // *used (optional) receives the tile width launched
 template <typename T>
 hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int nslots, bool adj, const Cx<T>* tw2,
                        hipStream_t s, int tile = 0, int* used = nullptr, const Slot<T>* tab = nullptr);
 // epi: 0 y = x - c, 1 y = c, 2 y = x - chi c, 3 y = chi c; rhs != NULL: y -= rhs and rnorm[slot] += |y|^2
-// Sub-domain batches as in pass 1; rows outside [lo, hi) of a strip are not written.
+// Sub-domain batches as in pass 1; rows outside [lo, hi) of a strip are not written.  The residual norm of
+// a slot accumulates into rnorm[slot / nodes] (one norm per stored vector).
 template <typename T>
 hipError_t launch_rows_inv(int L, const Cx<T>* tmp, const Cx<T>* x, const T* chi, const Cx<T>* rhs, Cx<T>* y,
                            double* rnorm, const int* vidx, int nx, int nz, int nslots, int epi, const Cx<T>* tw2,
-                           hipStream_t s, int nodes = 1, int lo = 0, int hi = -1, const Slot<T>* tab = nullptr);
+                           hipStream_t s, int nodes = 1, int lo = 0, int hi = -1, const Slot<T>* tab = nullptr,
+                           int trows = -1);
 // spectrum of the circulant-extended kernel table (FP64), written as gs[2][pz][lx] in T
 hipError_t launch_spectrum(int lx, int lz, const Cx<double>* ktab, int nx, int nz, Cx<double>* s1t,
                            Cx<double>* gs64, Cx<float>* gs32, const Cx<double>* tw2x, const Cx<double>* tw2z,
                            hipStream_t s);
+// 3D operator: forward-only (dir 0) / inverse-only (dir 1) column transforms over slots of [rows_slot][pz]
+// (dir 0: rows < nrow in, 2L rows out in split order; dir 1: 2L rows in, rows < nrow out); the 3D lag table
+// (K = c1 e^{i k0 r} / r, K(0) = self); its spectrum gs[2][py pz][lx] (u: nx ny nz, F: px py pz complex doubles
+// of workspace); incident fields of sources src[3 k + {0, 1, 2}] = (i, j, l).
+template <typename T>
+hipError_t launch_cols_half(int dir, int L, Cx<T>* tmp, int rows_slot, int nrow, int pz, int nslots,
+                            const Cx<T>* tw2, hipStream_t s);
+hipError_t launch_table3(Cx<double>* ktab, int nx, int ny, int nz, double k0, double h, double c1, Cx<double> self,
+                         hipStream_t s);
+hipError_t launch_spectrum3(int lx, int ly, int lz, const Cx<double>* ktab, int nx, int ny, int nz, Cx<double>* u,
+                            Cx<double>* F, Cx<double>* gs64, Cx<float>* gs32, const Cx<double>* tw2x,
+                            const Cx<double>* tw2y, const Cx<double>* tw2z, hipStream_t s);
+template <typename T>
+hipError_t launch_incident3(const Cx<double>* ktab, const int* src, const Cx<double>* amp, Cx<T>* out, int nx,
+                            int ny, int nz, int nsrc, double inv_dv, hipStream_t s);
 hipError_t launch_contrast(const double* vel, double* chi64, float* chi32, int n, double w2, double inv_c02,
                            unsigned* bad, hipStream_t s);
 hipError_t launch_table(Cx<double>* ktab, int nx, int nz, double k0h, Cx<double> cj1, Cx<double> self,
@@ -222,11 +241,13 @@ int apply_into(lsop_op* op, int mode, const void* x, void* y, int nvec, void* tm
 // ------------------------------------------------------------------ handles
 struct lsop_op {
   int nx = 0, nz = 0, lx = 0, lz = 0, dtype = 0, max_vec = 0;
+  int ny = 1, ly = 0, dims = 2;  // 3D operators (lsop_create3d): ny cells along y, y FFT length ly
   int col_tile = 0;  // column-pass tile width (0 = widest that fits)
   bool ready = false;
   double h = 0, freq = 0, c0 = 0, k0 = 0;
-  size_t n() const { return (size_t)nx * nz; }
+  size_t n() const { return (size_t)nx * ny * nz; }
   int px() const { return 2 * lx; }
+  int py() const { return dims == 3 ? 2 * ly : 1; }
   int pz() const { return 2 * lz; }
   bool has64() const { return dtype != LSOP_C64; }
   bool has32() const { return dtype != LSOP_C128; }
@@ -236,9 +257,9 @@ struct lsop_op {
   Cx<double>* ktab = nullptr;                   // [nx][nz]
   Cx<double>* gs64 = nullptr;                   // [2][pz][lx]
   Cx<float>* gs32 = nullptr;
-  Cx<double>*tw2x64 = nullptr, *tw2z64 = nullptr;  // w_{2L}^t, t < 2L
-  Cx<float>*tw2x32 = nullptr, *tw2z32 = nullptr;
-  void* tmp = nullptr;                          // [max_vec][nx][pz] in the widest dtype
+  Cx<double>*tw2x64 = nullptr, *tw2z64 = nullptr, *tw2y64 = nullptr;  // w_{2L}^t, t < 2L
+  Cx<float>*tw2x32 = nullptr, *tw2z32 = nullptr, *tw2y32 = nullptr;
+  void* tmp = nullptr;                          // [max_vec][nx][py][pz] in the widest dtype (py = 1 in 2D)
   unsigned* flag = nullptr;
   int* dsrc = nullptr;                          // sources (2 * cap) + vidx scratch
   Cx<double>* damp = nullptr;

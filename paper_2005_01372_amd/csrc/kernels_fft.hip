@@ -69,7 +69,8 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
                                                                      const int* __restrict__ vidx, int nx, int nz,
                                                                      int nitems, int mulchi,
                                                                      const Cx<T>* __restrict__ tw2, int nodes, int lo,
-                                                                     int hi, const Slot<T>* __restrict__ tab) {
+                                                                     int hi, const Slot<T>* __restrict__ tab,
+                                                                     int trows) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
   __shared__ Cx<T> sbuf[GPW][2][lds_len<L>()];
@@ -113,7 +114,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
       b[e] = a[e] * tw_lo<T, L>(stw, p);
     }
     if (base + step < nitems) fetch(base + step);
-    Cx<T>* tr = tmp + ((size_t)slot * nx + i) * (2 * L);
+    Cx<T>* tr = tmp + ((size_t)slot * trows + i) * (2 * L);
     fft2_regs<T, L, false>(a, b, g, sbuf[grp][0], sbuf[grp][1], stw);
     if (valid) {
 #pragma unroll
@@ -233,6 +234,166 @@ __global__ __launch_bounds__(C * FftPlan<L>::G) void k_cols(Cx<T>* __restrict__ 
   }
 }
 
+// Forward-only (DIR 0) and inverse-only (DIR 1) column transforms: the y passes of the 3D operator and the
+// spectrum set-up.  Slot s holds a [rows_slot][pz] array; a workgroup owns C adjacent columns as in k_cols.
+// DIR 0: rows i < nrow are the input (the rest of the padded axis is zero); the length-2L transform is written
+// back as rows m (wavenumber 2m) and L + m (wavenumber 2m + 1), m < L (rows_slot >= 2L).  DIR 1: rows m and
+// L + m hold the even and odd halves of a spectrum; the first nrow outputs of the unnormalised inverse length-2L
+// transform are written to rows i < nrow.
+template <typename T, int L, int C, int DIR>
+__global__ __launch_bounds__(C * FftPlan<L>::G) void k_cols_half(Cx<T>* __restrict__ tmp, int rows_slot, int nrow,
+                                                                 int pz, int nslots,
+                                                                 const Cx<T>* __restrict__ tw2) {
+  using P = FftPlan<L>;
+  constexpr int G = P::G, E = P::E, NT = C * G, ST = ColTile<T, L>::stride;
+  __shared__ Cx<T> tile[C * ST];
+  __shared__ Cx<T> xbuf[C][lds_len<L>()];
+  __shared__ Cx<T> stw[lds_len<L>()];
+  stage_twiddles<T, L>(stw, tw2);
+  constexpr int PAIR = (C * (int)sizeof(Cx<T>) >= 128) ? 1 : 128 / (C * (int)sizeof(Cx<T>));
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int grp_id = lb / (nslots * PAIR), rem = lb % (nslots * PAIR);
+  const int slot = rem / PAIR;
+  const int c0 = (grp_id * PAIR + rem % PAIR) * C;
+  Cx<T>* tb = tmp + (size_t)slot * rows_slot * pz + c0;
+  const int c = threadIdx.x / G, g = threadIdx.x % G;
+  for (int idx = threadIdx.x; idx < L * C; idx += NT) {
+    const int i = idx / C, cc = idx % C;
+    if constexpr (DIR == 0) {
+      tile[cc * ST + lds_pad(i)] = (i < nrow) ? tb[(size_t)i * pz + cc] : czero<T>();
+    } else {
+      tile[cc * ST + lds_pad(i)] = tb[(size_t)i * pz + cc];
+      xbuf[cc][lds_pad(i)] = tb[(size_t)(L + i) * pz + cc];
+    }
+  }
+  __syncthreads();
+  Cx<T>* col = tile + c * ST;
+  Cx<T> ve[E], vo[E];
+  if constexpr (DIR == 0) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int p = fft_elem<L>(g, e);
+      ve[e] = col[lds_pad(p)];
+      vo[e] = ve[e] * tw_lo<T, L>(stw, p);
+    }
+    fft2_regs<T, L, false>(ve, vo, g, col, xbuf[c], stw);
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int p = fft_elem<L>(g, e);
+      col[lds_pad(p)] = ve[e];
+      xbuf[c][lds_pad(p)] = vo[e];
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < L * C; idx += NT) {
+      const int i = idx / C, cc = idx % C;
+      tb[(size_t)i * pz + cc] = tile[cc * ST + lds_pad(i)];
+      tb[(size_t)(L + i) * pz + cc] = xbuf[cc][lds_pad(i)];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int p = fft_elem<L>(g, e);
+      ve[e] = col[lds_pad(p)];
+      vo[e] = xbuf[c][lds_pad(p)];
+    }
+    wave_sync();
+    fft2_regs<T, L, true>(ve, vo, g, col, xbuf[c], stw);
+    wave_sync();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int p = fft_elem<L>(g, e);
+      col[lds_pad(p)] = ve[e] + cmul_conj(tw_lo<T, L>(stw, p), vo[e]);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nrow * C; idx += NT) {
+      const int i = idx / C, cc = idx % C;
+      tb[(size_t)i * pz + cc] = tile[cc * ST + lds_pad(i)];
+    }
+  }
+}
+
+// 3D spectrum from the forward transforms F of the weighted lag table (lags l >= 0 with weight 1/2 at l = 0 on
+// each axis, so that the transform of the even circulant extension is the sum of F over the 8 sign flips of
+// the wavenumber): F is [px][py pz] in the split order of the passes (wavenumber 2m at position m, 2m + 1 at
+// L + m on every axis); gs[h][cy pz + cz][m] = scale * sum_{signs} F at (+-kx, +-ky, +-kz), kx = 2m + h.
+__device__ __forceinline__ int split_pos(int k, int L) { return (k & 1) ? L + (k >> 1) : (k >> 1); }
+__device__ __forceinline__ int split_k(int pos, int L) { return pos < L ? 2 * pos : 2 * (pos - L) + 1; }
+
+__global__ void k_spec3_sym(const Cx<double>* __restrict__ F, int lx, int ly, int lz, double scale,
+                            Cx<double>* __restrict__ gs64, Cx<float>* __restrict__ gs32) {
+  const int px = 2 * lx, py = 2 * ly, pz = 2 * lz;
+  const size_t cols = (size_t)py * pz, total = (size_t)px * cols;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    const int m = (int)(t % lx);
+    const size_t r = t / lx;
+    const size_t cc = r % cols;
+    const int h = (int)(r / cols);
+    const int cy = (int)(cc / pz), cz = (int)(cc % pz);
+    const int kx = 2 * m + h, ky = split_k(cy, ly), kz = split_k(cz, lz);
+    const int xs[2] = {split_pos(kx, lx), split_pos((px - kx) % px, lx)};
+    const int ys[2] = {split_pos(ky, ly), split_pos((py - ky) % py, ly)};
+    const int zs[2] = {split_pos(kz, lz), split_pos((pz - kz) % pz, lz)};
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const Cx<double> v = F[(size_t)xs[a] * cols + (size_t)ys[b] * pz + zs[c]];
+          re += v.re;
+          im += v.im;
+        }
+    const Cx<double> out{scale * re, scale * im};
+    if (gs64) gs64[t] = out;
+    if (gs32) gs32[t] = ccast<float>(out);
+  }
+}
+
+// Weighted lag table of the 3D spectrum: u[p][q][s] = K3[p][q][s] w(p) w(q) w(s), w(0) = 1/2, else 1.
+__global__ void k_lag_weight3(const Cx<double>* __restrict__ K, int nx, int ny, int nz, Cx<double>* __restrict__ u) {
+  const size_t n = (size_t)nx * ny * nz;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int s = (int)(t % nz), q = (int)((t / nz) % ny), p = (int)(t / ((size_t)ny * nz));
+    const double w = (p ? 1.0 : 0.5) * (q ? 1.0 : 0.5) * (s ? 1.0 : 0.5);
+    u[t] = Cx<double>{w * K[t].re, w * K[t].im};
+  }
+}
+
+// 3D lag table of the ball-integrated Green's function: K = c1 e^{i k0 r} / r (r = h |lag| > 0), K(0) = self.
+__global__ void k_table3(Cx<double>* __restrict__ ktab, int nx, int ny, int nz, double k0, double h, double c1,
+                         Cx<double> self) {
+  const size_t n = (size_t)nx * ny * nz;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int s = (int)(t % nz), q = (int)((t / nz) % ny), p = (int)(t / ((size_t)ny * nz));
+    if (t == 0) {
+      ktab[0] = self;
+      continue;
+    }
+    const double r = h * sqrt((double)p * p + (double)q * q + (double)s * s);
+    double sn, cs;
+    sincos(k0 * r, &sn, &cs);
+    ktab[t] = Cx<double>{c1 * cs / r, c1 * sn / r};
+  }
+}
+
+// Incident fields of 3D point sources: psi0 = amp K3(|i - si|, |j - sj|, |l - sl|) / h^3.
+template <typename T>
+__global__ void k_incident3(const Cx<double>* __restrict__ ktab, const int* __restrict__ src,
+                            const Cx<double>* __restrict__ amp, Cx<T>* __restrict__ out, int nx, int ny, int nz,
+                            int nsrc, double inv_dv) {
+  const size_t n = (size_t)nx * ny * nz, total = n * nsrc;
+  for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x) {
+    const int sidx = (int)(k / n);
+    const size_t r = k % n;
+    const int l = (int)(r % nz), j = (int)((r / nz) % ny), i = (int)(r / ((size_t)ny * nz));
+    const int di = abs(i - src[3 * sidx]), dj = abs(j - src[3 * sidx + 1]), dl = abs(l - src[3 * sidx + 2]);
+    const Cx<double> v = inv_dv * (amp[sidx] * ktab[((size_t)di * ny + dj) * nz + dl]);
+    out[k] = ccast<T>(v);
+  }
+}
+
 // ------------------------------------------------------------------ pass 3
 template <typename T, int L>
 __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>* __restrict__ tmp, const Cx<T>* x,
@@ -241,7 +402,8 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
                                                                      const int* __restrict__ vidx, int nx, int nz,
                                                                      int nitems, int epi,
                                                                      const Cx<T>* __restrict__ tw2, int nodes, int lo,
-                                                                     int hi, const Slot<T>* __restrict__ tab) {
+                                                                     int hi, const Slot<T>* __restrict__ tab,
+                                                                     int trows) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
   __shared__ Cx<T> sbuf[GPW][2][lds_len<L>()];
@@ -258,7 +420,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
     const int node = slot % nodes, vs = slot / nodes;
     const int vi = vidx ? vidx[vs] : vs;
     const size_t row = (size_t)node * nx + i;
-    const Cx<T>* tr = tmp + ((size_t)slot * nx + i) * (2 * L);
+    const Cx<T>* tr = tmp + ((size_t)slot * trows + i) * (2 * L);
     Cx<T> acc[E], v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -272,7 +434,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
     Cx<T>* ys = tab ? tab[slot].y : y;
     const Cx<T>* rs = tab ? tab[slot].rhs : rhs;
     const T* cs = (tab ? tab[slot].chi : chi) + row * nz;
-    double* rn = tab ? tab[slot].rnorm : (rnorm ? rnorm + slot : nullptr);
+    double* rn = tab ? tab[slot].rnorm : (rnorm ? rnorm + slot / nodes : nullptr);
     double nrm = 0.0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -476,15 +638,17 @@ int grid_for_rows(int nitems, int gpw) {
 template <typename T>
 hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, const int* vidx, int nx, int nz,
                            int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s, int nodes, int lo, int hi,
-                           const Slot<T>* tab) {
+                           const Slot<T>* tab, int trows) {
   const int nitems = nslots * nx;
   if (nitems <= 0) return hipSuccess;
   if (nodes < 1 || nslots % nodes != 0 || (tab && (nodes != 1 || vidx))) return hipErrorInvalidValue;
   if (hi < 0) hi = nx;
+  if (trows < 0) trows = nx;
+  if (trows < nx) return hipErrorInvalidValue;
   LSOP_DISPATCH_L(L, {
     constexpr int NT = rows_threads<T, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_rows_fwd<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(NT), 0, s, x, chi, tmp, vidx,
-                       nx, nz, nitems, (int)mulchi, tw2, nodes, lo, hi, tab);
+                       nx, nz, nitems, (int)mulchi, tw2, nodes, lo, hi, tab, trows);
   });
   return hipGetLastError();
 }
@@ -553,16 +717,17 @@ hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int n
 template <typename T>
 hipError_t launch_rows_inv(int L, const Cx<T>* tmp, const Cx<T>* x, const T* chi, const Cx<T>* rhs, Cx<T>* y,
                            double* rnorm, const int* vidx, int nx, int nz, int nslots, int epi, const Cx<T>* tw2,
-                           hipStream_t s, int nodes, int lo, int hi, const Slot<T>* tab) {
+                           hipStream_t s, int nodes, int lo, int hi, const Slot<T>* tab, int trows) {
   const int nitems = nslots * nx;
   if (nitems <= 0) return hipSuccess;
-  if (nodes < 1 || nslots % nodes != 0 || (nodes > 1 && rnorm) || (tab && (nodes != 1 || vidx)))
-    return hipErrorInvalidValue;
+  if (nodes < 1 || nslots % nodes != 0 || (tab && (nodes != 1 || vidx))) return hipErrorInvalidValue;
   if (hi < 0) hi = nx;
+  if (trows < 0) trows = nx;
+  if (trows < nx) return hipErrorInvalidValue;
   LSOP_DISPATCH_L(L, {
     constexpr int NT = rows_threads<T, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_rows_inv<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(NT), 0, s, tmp, x, chi, rhs, y,
-                       rnorm, vidx, nx, nz, nitems, epi, tw2, nodes, lo, hi, tab);
+                       rnorm, vidx, nx, nz, nitems, epi, tw2, nodes, lo, hi, tab, trows);
   });
   return hipGetLastError();
 }
@@ -616,14 +781,80 @@ hipError_t launch_incident(const Cx<double>* ktab, const int* si, const int* sj,
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_cols_half(int dir, int L, Cx<T>* tmp, int rows_slot, int nrow, int pz, int nslots,
+                            const Cx<T>* tw2, hipStream_t s) {
+  if (nslots <= 0) return hipSuccess;
+  if (pz % 16 != 0 || rows_slot < 2 * L || nrow < 1 || nrow > L) return hipErrorInvalidValue;
+  LSOP_DISPATCH_L(L, {
+    constexpr int C = ColTile<T, LL>::C;
+    const dim3 grid((pz / C) * nslots);
+    if (dir == 0)
+      hipLaunchKernelGGL((k_cols_half<T, LL, C, 0>), grid, dim3(C * FftPlan<LL>::G), 0, s, tmp, rows_slot, nrow, pz,
+                         nslots, tw2);
+    else
+      hipLaunchKernelGGL((k_cols_half<T, LL, C, 1>), grid, dim3(C * FftPlan<LL>::G), 0, s, tmp, rows_slot, nrow, pz,
+                         nslots, tw2);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_table3(Cx<double>* ktab, int nx, int ny, int nz, double k0, double h, double c1, Cx<double> self,
+                         hipStream_t s) {
+  const size_t n = (size_t)nx * ny * nz;
+  size_t grid = (n + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_table3, dim3((unsigned)grid), dim3(256), 0, s, ktab, nx, ny, nz, k0, h, c1, self);
+  return hipGetLastError();
+}
+
+// 3D spectrum: weighted lag table (into u: nx ny nz complex doubles), forward z rows into F ([px][py][pz]), y
+// columns per x-plane, x columns, then the sign-flip sum into gs.
+hipError_t launch_spectrum3(int lx, int ly, int lz, const Cx<double>* ktab, int nx, int ny, int nz, Cx<double>* u,
+                            Cx<double>* F, Cx<double>* gs64, Cx<float>* gs32, const Cx<double>* tw2x,
+                            const Cx<double>* tw2y, const Cx<double>* tw2z, hipStream_t s) {
+  const int px = 2 * lx, py = 2 * ly, pz = 2 * lz;
+  const size_t n = (size_t)nx * ny * nz;
+  size_t grid = (n + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  hipLaunchKernelGGL(k_lag_weight3, dim3((unsigned)grid), dim3(256), 0, s, ktab, nx, ny, nz, u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_rows_fwd<double>(lz, u, nullptr, F, nullptr, ny, nz, nx, false, tw2z, s, nx, 0, ny, nullptr, py)))
+    return e;
+  if ((e = launch_cols_half<double>(0, ly, F, py, ny, pz, nx, tw2y, s))) return e;
+  if ((e = launch_cols_half<double>(0, lx, F, px, nx, py * pz, 1, tw2x, s))) return e;
+  const size_t total = (size_t)px * py * pz;
+  grid = (total + 255) / 256;
+  if (grid > 16384) grid = 16384;
+  hipLaunchKernelGGL(k_spec3_sym, dim3((unsigned)grid), dim3(256), 0, s, F, lx, ly, lz,
+                     1.0 / ((double)px * (double)py * (double)pz), gs64, gs32);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_incident3(const Cx<double>* ktab, const int* src, const Cx<double>* amp, Cx<T>* out, int nx,
+                            int ny, int nz, int nsrc, double inv_dv, hipStream_t s) {
+  const size_t total = (size_t)nx * ny * nz * nsrc;
+  size_t grid = (total + 255) / 256;
+  if (grid > 16384) grid = 16384;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_incident3<T>), dim3((unsigned)grid), dim3(256), 0, s, ktab, src, amp, out, nx, ny, nz, nsrc,
+                     inv_dv);
+  return hipGetLastError();
+}
+
 #define LSOP_INST(T)                                                                                               \
   template hipError_t launch_rows_fwd<T>(int, const Cx<T>*, const T*, Cx<T>*, const int*, int, int, int, bool,    \
-                                         const Cx<T>*, hipStream_t, int, int, int, const Slot<T>*);               \
+                                         const Cx<T>*, hipStream_t, int, int, int, const Slot<T>*, int);          \
   template hipError_t launch_cols<T>(int, Cx<T>*, const Cx<T>*, int, int, int, bool, const Cx<T>*, hipStream_t,    \
                                      int, int*, const Slot<T>*);                                                  \
   template hipError_t launch_rows_inv<T>(int, const Cx<T>*, const Cx<T>*, const T*, const Cx<T>*, Cx<T>*,        \
                                          double*, const int*, int, int, int, int, const Cx<T>*, hipStream_t, int, \
-                                         int, int, const Slot<T>*);                                               \
+                                         int, int, const Slot<T>*, int);                                          \
+  template hipError_t launch_cols_half<T>(int, int, Cx<T>*, int, int, int, int, const Cx<T>*, hipStream_t);      \
+  template hipError_t launch_incident3<T>(const Cx<double>*, const int*, const Cx<double>*, Cx<T>*, int, int,    \
+                                          int, int, double, hipStream_t);                                         \
   template hipError_t launch_incident<T>(const Cx<double>*, const int*, const int*, const Cx<double>*, Cx<T>*,    \
                                          int, int, int, double, hipStream_t);
 LSOP_INST(float)

@@ -395,6 +395,7 @@ int unet_pack_inputs(unet* u, const lsop_op* op, const void* psi0_dev, int nvec,
                      void* stream) {
   if (!u || !op || !psi0_dev || !x_dev || !scale_dev) return fail(LSOP_EINVAL, "null argument");
   if (!op->ready) return fail(LSOP_EINVAL, "operator has no problem set");
+  if (op->dims != 2) return fail(LSOP_EUNSUPPORTED, "the warm-start network takes 2D operators");
   if (u->cin != 4) return fail(LSOP_EINVAL, "the warm start takes 4 input channels");
   if (nvec < 1 || nvec > u->maxB) return fail(LSOP_EINVAL, "nvec outside the network's batch limit");
   hipStream_t s = SS(stream);
@@ -417,6 +418,7 @@ int unet_pack_inputs(unet* u, const lsop_op* op, const void* psi0_dev, int nvec,
 int unet_pack_target(const lsop_op* op, const void* psi_dev, const void* psi0_dev, const float* scale_dev, int nvec,
                      float* t_dev, void* stream) {
   if (!op || !psi_dev || !psi0_dev || !scale_dev || !t_dev) return fail(LSOP_EINVAL, "null argument");
+  if (op->dims != 2) return fail(LSOP_EUNSUPPORTED, "the warm-start network takes 2D operators");
   if (nvec < 1) return fail(LSOP_EINVAL, "nvec must be >= 1");
   hipStream_t s = SS(stream);
   if (op->dtype == LSOP_C64)
@@ -430,6 +432,7 @@ int unet_pack_target(const lsop_op* op, const void* psi_dev, const void* psi0_de
 
 int unet_warm_start(unet* u, const lsop_op* op, const void* psi0_dev, void* psi_dev, int nvec, void* stream) {
   if (!u || !op || !psi0_dev || !psi_dev) return fail(LSOP_EINVAL, "null argument");
+  if (op->dims != 2) return fail(LSOP_EUNSUPPORTED, "the warm-start network takes 2D operators");
   if (u->cout != 2) return fail(LSOP_EINVAL, "the warm start takes 2 output channels");
   int st = check_shape(u, nvec, op->nx, op->nz);
   if (st) return st;

@@ -28,7 +28,8 @@ INIT = {"h_rhs": 0, "zero": 1, "user": 2, "best": 3}
 
 EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "lsop_incident", "lsop_autotune",
            "lsop_kernel_table", "lsop_info", "lsop_destroy", "lsop_last_error", "lsop_state_bytes",
-           "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count", "lsop_apply_noalloc", "gmres_solve", "gmres_workspace_bytes", "lsop_sweep", "lsop_set_problem_damped", "lsop_bessel_host_c",
+           "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count", "lsop_apply_noalloc", "gmres_solve", "gmres_workspace_bytes", "lsop_sweep", "lsop_set_problem_damped", "lsop_bessel_host_c", "lsop_create3d",
+           "lsop_set_problem3d", "lsop_incident3d",
            "precond_state_bytes", "precond_create_in", "precond_create",
            "precond_build", "precond_build_batch", "precond_apply", "precond_info", "precond_destroy", "series_solve",
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
@@ -46,7 +47,8 @@ class LsopError(RuntimeError):
 
 class OpInfo(C.Structure):
     _fields_ = [("nx", C.c_int), ("nz", C.c_int), ("lx", C.c_int), ("lz", C.c_int), ("dtype", C.c_int),
-                ("max_vec", C.c_int), ("state_bytes", C.c_size_t), ("col_tile", C.c_int)]
+                ("max_vec", C.c_int), ("state_bytes", C.c_size_t), ("col_tile", C.c_int), ("ny", C.c_int),
+                ("ly", C.c_int)]
 
 
 class PrecondParams(C.Structure):
@@ -102,6 +104,9 @@ def load_library(path=LIB_PATH):
         "lsop_apply": (ip, [vp, ip, vp, vp, ip, vp]),
         "lsop_set_problem_damped": (ip, [vp, vp, dp, dp, dp, dp, ip, vp]),
         "lsop_bessel_host_c": (ip, [ip, dp, dp, C.POINTER(dp)]),
+        "lsop_create3d": (ip, [ip, ip, ip, ip, ip, C.POINTER(vp)]),
+        "lsop_set_problem3d": (ip, [vp, vp, dp, dp, dp, vp]),
+        "lsop_incident3d": (ip, [vp, vp, vp, ip, vp, vp]),
         "lsop_residual": (ip, [vp, vp, vp, vp, vp, ip, vp]),
         "lsop_incident": (ip, [vp, vp, vp, vp, ip, vp, vp]),
         "lsop_kernel_table": (ip, [vp, vp, vp]),
@@ -390,6 +395,64 @@ class Operator:
 
     def kernel_table(self):
         out = torch.empty((self.nx, self.nz), dtype=torch.complex128, device="cuda")
+        _check(self.lib.lsop_kernel_table(self.handle, _ptr(out), _stream()))
+        return out
+
+
+class Operator3D(Operator):
+    """The 3D LS operator (lsop_create3d + lsop_set_problem3d); vectors [..][nx][ny][nz].  Series, GMRES and
+    the low-rank / scalar preconditioners take it like a 2D operator."""
+
+    def __init__(self, nx, ny, nz, dtype=C128, max_vec=16):
+        self.lib = load_library()
+        self.nx, self.ny, self.nz, self.dtype, self.max_vec = int(nx), int(ny), int(nz), int(dtype), int(max_vec)
+        h = C.c_void_p()
+        _check(self.lib.lsop_create3d(self.nx, self.ny, self.nz, self.dtype, self.max_vec, C.byref(h)))
+        self.handle = h
+        self.vec_dtype = torch.complex64 if self.dtype == C64 else torch.complex128
+        self.inner_dtype = torch.complex64 if self.dtype in (C64, MIXED) else torch.complex128
+
+    def set_problem(self, vel, h, freq, c0=2000.0):
+        vel = torch.as_tensor(vel, dtype=torch.float64)
+        vel = (vel if vel.is_cuda else vel.cuda()).contiguous()
+        if tuple(vel.shape) != (self.nx, self.ny, self.nz):
+            raise ValueError(f"velocity must be {(self.nx, self.ny, self.nz)}")
+        self._vel = vel
+        _check(self.lib.lsop_set_problem3d(self.handle, _ptr(vel), float(h), float(freq), float(c0), _stream()))
+        self.h, self.freq, self.c0 = float(h), float(freq), float(c0)
+        return self
+
+    def _vecs(self, x, dtype=None, nvec=None):
+        dtype = dtype or self.vec_dtype
+        if not isinstance(x, torch.Tensor):
+            raise TypeError("expected a torch tensor")
+        if x.dim() < 3 or tuple(x.shape[-3:]) != (self.nx, self.ny, self.nz):
+            raise ValueError(f"vectors must end in {(self.nx, self.ny, self.nz)}, got {tuple(x.shape)}")
+        nv = x.numel() // (self.nx * self.ny * self.nz)
+        if nvec is not None and nv != nvec:
+            raise ValueError(f"expected {nvec} vectors, got {nv}")
+        if x.dtype != dtype:
+            raise TypeError(f"expected {dtype}, got {x.dtype}")
+        if not x.is_contiguous():
+            raise ValueError("vectors must be contiguous")
+        return nv
+
+    def incident(self, src, amp=None):
+        src = [tuple(int(v) for v in s) for s in src]
+        flat = (C.c_int * (3 * len(src)))(*[v for s in src for v in s])
+        if amp is not None:
+            a = []
+            for v in amp:
+                a += [complex(v).real, complex(v).imag]
+            ap = (C.c_double * len(a))(*a)
+        else:
+            ap = None
+        out = torch.empty((len(src), self.nx, self.ny, self.nz), dtype=self.vec_dtype, device="cuda")
+        _check(self.lib.lsop_incident3d(self.handle, flat, ap, len(src), _ptr(out), _stream()))
+        return out
+
+    def kernel_table(self):
+        out = torch.empty((self.nx, self.ny, self.nz), dtype=torch.complex128, device="cuda")
         _check(self.lib.lsop_kernel_table(self.handle, _ptr(out), _stream()))
         return out
 
