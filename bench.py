@@ -352,6 +352,7 @@ def main_uneven(args):
         "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4)}
                     for k, v in sorted(by_fn.items(), key=lambda kv: -kv[1]["ms"])[:12]},
     }
+    line["command"] = " ".join(["python", "bench.py"] + sys.argv[1:])
     print(json.dumps(line), flush=True)
 
 
@@ -542,6 +543,7 @@ def main_unet(args):
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = unet_cpu_baseline()
+    line["command"] = " ".join(["python", "bench.py"] + sys.argv[1:])
     print(json.dumps(line), flush=True)
 
 
@@ -722,6 +724,7 @@ def main():
     roof["peak_measured_copy"] = round(copy_gbps, 1) if roof.get("unit") == "GB/s" else None
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args, iters, converged, args.cpu_sources)
+    line["command"] = " ".join(["python", "bench.py"] + sys.argv[1:])
     print(json.dumps(line), flush=True)
 
 

@@ -19,8 +19,13 @@ Readings (where Section 2.4 is not specific):
 * recompression of a rank-2r sum to rank r: deterministic truncated SVD of
   the factored form (QR of both factors, SVD of the small core); the paper
   allows either SVD or a randomized variant and uses the latter for speed.
-* the blocks are exact submatrices of A = I - G0 V formed from the dense
-  matrix (this oracle is for small grids only).
+* the blocks are exact submatrices of A = I - G0 V, either sliced from the
+  dense matrix (small grids) or, for grids whose dense matrix does not fit
+  in memory, given by `StripOperator`: a dense leaf block formed from the
+  kernel table of its own strip, an off-diagonal block applied as the FFT
+  convolution of the node's strip with the input and output restricted to
+  the two halves (the same Toeplitz block, since a strip of whole grid
+  columns is a grid of its own with the same lags).
 * two inverses are given: `HodlrPreconditioner` follows the paper (block
   formula in HODLR arithmetic with recompression to rank r); `HodlrSolve`
   applies the exact inverse of the same HODLR approximation by nested
@@ -29,13 +34,14 @@ Readings (where Section 2.4 is not specific):
 
 Pins: tests/test_hodlr_pins.py (full rank reproduces A and A^{-1}; the
 truncation is SVD-optimal; the nested solve inverts its own HODLR matrix;
-preconditioned series reaches the dense LU solution).
+preconditioned series reaches the dense LU solution; the strip operator's
+blocks equal those of the dense matrix).
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .lsop_oracle import operator_matrix, range_finder_generic
+from .lsop_oracle import apply_fft, operator_matrix, orth, range_finder_generic, spectrum
 
 
 class Node:
@@ -123,26 +129,88 @@ def truncate(U, V, r):
     return qu @ (w[:, :r] * s[:r]), qv @ zh.conj().T[:, :r]
 
 
-def build(A, tree, r, seed=0, probes=None, q=0):
-    """HODLR approximation of the dense matrix A on the given tree (off-diagonal blocks by Alg. 1, q = 0).
+class StripOperator:
+    """Blocks of A = I - G0 V on column strips without the dense matrix (grids too large for it).
 
+    A strip of whole grid columns [c0, c1) is a grid of its own: its diagonal
+    block of A is the operator matrix of the kernel table's first c1 - c0 rows
+    and the strip's contrast.  For disjoint index sets the off-diagonal block
+    is -(G0 V)[I_out, I_in], applied as the strip's FFT convolution (eq. 11's
+    product) with the input zero outside I_in and the output read on I_out.
+    """
+
+    def __init__(self, prob):
+        self.prob = prob
+        self._spec = {}
+
+    def _ghat(self, w):
+        if w not in self._spec:
+            self._spec[w] = spectrum(self.prob.K[:w, :])
+        return self._spec[w]
+
+    def diag(self, c0, c1):
+        return operator_matrix(self.prob.K[:c1 - c0, :], self.prob.chi[c0:c1])
+
+    def block(self, c0, c_in, c_out):
+        """(matvec, rmatvec) of A[I_out, I_in] within the strip starting at column c0; c_in, c_out are the
+        (first, last + 1) columns of the input and output index sets."""
+        nz = self.prob.nz
+        w = max(c_in[1], c_out[1]) - c0
+        chi = self.prob.chi[c0:c0 + w]
+        gh = self._ghat(w)
+        si = slice((c_in[0] - c0) * nz, (c_in[1] - c0) * nz)
+        so = slice((c_out[0] - c0) * nz, (c_out[1] - c0) * nz)
+
+        def run(x, src, dst, mode):
+            k = x.shape[1]
+            e = np.zeros((k, w * nz), np.complex128)
+            e[:, src] = x.T
+            y = apply_fft(gh, chi, e.reshape(k, w, nz), mode).reshape(k, w * nz)
+            return -y[:, dst].T
+        return (lambda x: run(x, si, so, "G0V")), (lambda y: run(y, so, si, "VHG0H"))
+
+
+def range_finder_ops(matvec, rmatvec, omega, q=0):
+    """Alg. 1 for a block given by its products with a block of vectors and with its adjoint."""
+    Q = orth(matvec(omega))
+    for _ in range(q):
+        Qt = orth(rmatvec(Q))
+        Q = orth(matvec(Qt))
+    return Q, rmatvec(Q)
+
+
+def build(A, tree, r, seed=0, probes=None, q=0):
+    """HODLR approximation of A on the given tree (off-diagonal blocks by Alg. 1, q = 0 in Section 2.4).
+
+    A: the dense matrix, or a `StripOperator`.
     probes: optional callable depth -> real [r, n] block; a node at that depth
     samples its upper block A[I1, I2] with the probe rows restricted to I2 and
     its lower block A[I2, I1] with them restricted to I1.  Without it, the
     probes are drawn from numpy's PCG64 with `seed`.
     """
     rng = np.random.default_rng(seed)
+    strips = A if isinstance(A, StripOperator) else None
 
     def fill(node, depth):
         if not hasattr(node, "children_cols"):
-            node.dense = A[node.lo:node.hi, node.lo:node.hi].copy()
+            if strips is not None:
+                node.dense = strips.diag(*node.leaf_cols)
+            else:
+                node.dense = A[node.lo:node.hi, node.lo:node.hi].copy()
             return node
         node.a11, node.a22 = fill(node.c1, depth + 1), fill(node.c2, depth + 1)
         i1 = slice(node.a11.lo, node.a11.hi)
         i2 = slice(node.a22.lo, node.a22.hi)
         om = probes(depth) if probes is not None else None
-        node.u12, node.v12 = lowrank_from_block(A[i1, i2], r, rng, None if om is None else om[:, i2].T, q)
-        node.u21, node.v21 = lowrank_from_block(A[i2, i1], r, rng, None if om is None else om[:, i1].T, q)
+        if strips is None:
+            node.u12, node.v12 = lowrank_from_block(A[i1, i2], r, rng, None if om is None else om[:, i2].T, q)
+            node.u21, node.v21 = lowrank_from_block(A[i2, i1], r, rng, None if om is None else om[:, i1].T, q)
+            return node
+        c0, cm, c1 = node.children_cols
+        o12 = rng.standard_normal((i2.stop - i2.start, r)) if om is None else om[:, i2].T
+        node.u12, node.v12 = range_finder_ops(*strips.block(c0, (cm, c1), (c0, cm)), o12, q)
+        o21 = rng.standard_normal((i1.stop - i1.start, r)) if om is None else om[:, i1].T
+        node.u21, node.v21 = range_finder_ops(*strips.block(c0, (c0, cm), (cm, c1)), o21, q)
         return node
     return fill(tree, 0)
 
@@ -213,8 +281,8 @@ class HodlrSolve:
     inverted without the rank truncation of the H-arithmetic inverse.
     """
 
-    def __init__(self, prob, rank, levels, min_width=1, seed=0, probes=None, q=0):
-        A = operator_matrix(prob.K, prob.chi)
+    def __init__(self, prob, rank, levels, min_width=1, seed=0, probes=None, q=0, matrix_free=False):
+        A = StripOperator(prob) if matrix_free else operator_matrix(prob.K, prob.chi)
         self.tree = split_tree(prob.nx, prob.nz, levels, min_width)
         self.approx = build(A, self.tree, rank, seed, probes, q)
         self.n = prob.n

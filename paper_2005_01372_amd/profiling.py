@@ -67,14 +67,14 @@ def _dispatches(csv_path, counter):
 
 
 def _copy_scale(disp, copy_bytes):
-    """copy_bytes over what the counter read for the plain copies issued before the first library kernel."""
-    tot = 0.0
+    """copy_bytes over what the counter read for the first plain copy of at least 1 MiB (the probe, issued
+    before anything else; later copies, such as a bandwidth measurement, are of other sizes)."""
     for _, name, v in disp:
         if "lsop::" in name:
             break
         if "copyBuffer" in name and v >= (1 << 20):
-            tot += v
-    return copy_bytes / tot
+            return copy_bytes / v
+    raise SystemExit("no copy probe found before the first library kernel")
 
 
 def traffic(fetch_csv, write_csv, copy_bytes, kernel_fns, dump_json, out_path, command):

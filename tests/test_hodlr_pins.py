@@ -114,3 +114,41 @@ def test_power_iteration_improves_block_and_keeps_fixed_point():
     psi0 = prob.incident(w.src_i, w.src_j)[0]
     psi, it, r, st = O.series_solve(prob, hs1.apply, psi0, 1e-12, 80)
     assert st == O.OK and rel(psi, O.solve_direct(prob, psi0)) < 1e-10
+
+
+def test_strip_operator_blocks_equal_dense_blocks():
+    """The matrix-free strip operator reproduces the dense matrix's diagonal strip blocks and its off-diagonal
+    blocks and their adjoints (FFT convolution on a strip against direct slices of I - G0 V), on a
+    non-square grid and strips that do not start at column 0."""
+    rng = np.random.default_rng(5)
+    vel = 2000.0 * (1.0 + 0.3 * synth.smoothed_field((14, 9), 2.0, rng))
+    prob = O.Problem(vel, 10.0, 15.0, 2000.0)
+    A = O.operator_matrix(prob.K, prob.chi)
+    S = HD.StripOperator(prob)
+    nz = prob.nz
+    assert np.allclose(S.diag(3, 7), A[3 * nz:7 * nz, 3 * nz:7 * nz], rtol=0, atol=1e-15)
+    for c0, cin, cout in ((2, (6, 11), (2, 6)), (2, (2, 6), (6, 11)), (0, (0, 7), (7, 14)), (5, (9, 10), (5, 9))):
+        B = A[cout[0] * nz:cout[1] * nz, cin[0] * nz:cin[1] * nz]
+        mv, rmv = S.block(c0, cin, cout)
+        x = rng.standard_normal((B.shape[1], 3)) + 1j * rng.standard_normal((B.shape[1], 3))
+        y = rng.standard_normal((B.shape[0], 2)) + 1j * rng.standard_normal((B.shape[0], 2))
+        assert rel(mv(x), B @ x) <= 1e-12
+        assert rel(rmv(y), B.conj().T @ y) <= 1e-12
+
+
+def test_matrix_free_build_equals_dense_build():
+    """With the same probes, the HODLR matrix sampled through the strip operator equals the one sampled
+    from the dense matrix (q = 0 and q = 1), and so do the nested solves."""
+    w, prob = small(16)
+    A = O.operator_matrix(prob.K, prob.chi)
+    rng = np.random.default_rng(8)
+    om = rng.standard_normal((3 * 5, prob.n))
+    probes = lambda d: om[d * 5:(d + 1) * 5]
+    for q in (0, 1):
+        hd = HD.build(A, HD.split_tree(prob.nx, prob.nz, 3), 5, probes=probes, q=q).to_dense()
+        hm = HD.build(HD.StripOperator(prob), HD.split_tree(prob.nx, prob.nz, 3), 5, probes=probes, q=q).to_dense()
+        assert rel(hm, hd) <= 1e-11
+    sd = HD.HodlrSolve(prob, 5, 3, probes=probes, q=1)
+    sm = HD.HodlrSolve(prob, 5, 3, probes=probes, q=1, matrix_free=True)
+    x = synth.random_vectors((2, prob.nx, prob.nz), 1)
+    assert rel(sm.apply(x), sd.apply(x)) <= 1e-11
