@@ -94,10 +94,11 @@ const char* tname<float>() { return "float"; }
 template <>
 const char* tname<double>() { return "double"; }
 
-std::string fn_name(const char* base, const char* t, int a = -1, int b = -1) {
+std::string fn_name(const char* base, const char* t, int a = -1, int b = -1, int c = -1) {
   std::string f = std::string(base) + "<" + t;
   if (a >= 0) f += ", " + std::to_string(a);
   if (b >= 0) f += ", " + std::to_string(b);
+  if (c >= 0) f += ", " + std::to_string(c);
   return f + ">";
 }
 
@@ -140,7 +141,9 @@ hipError_t p_update(const char* name, const Cx<T>* A, int na, const Cx<double>* 
   const double e = sizeof(Cx<T>);
   const double vecs = 1.0 + (X1 ? 1.0 : 0.0) + (X2 ? 1.0 : 0.0);
   const double nsegs = (seg == 0 || seg >= n) ? 1.0 : (double)((n + seg - 1) / seg);
-  return prof(name, fn_name("k_gemm_update_mfma", tname<T>(), nb > 32 ? 4 : 2),
+  // the instantiation launch_gemm_update_seg picks
+  const int nbt = nb > 32 ? 4 : 2, ga = nb > 32 ? 4 : 8, wpe = nb > 32 ? (sizeof(T) == 4 ? 6 : 3) : 0;
+  return prof(name, fn_name("k_gemm_update_mfma", tname<T>(), nbt, ga, wpe),
               (double)na * n * e + vecs * nb * (double)n * e + nsegs * na * nb * sizeof(Cx<double>),
               8.0 * na * nb * (double)n, nb, s,
               [&] { return launch_gemm_update_seg<T>(A, na, M, mstride, nb, X1, X2, beta, Y, vidx, n, seg, s); });
