@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--unet-models", type=int, default=32,
                     help="layered + salt models (32 sources each) solved for the network's training data")
     ap.add_argument("--unet-batch", type=int, default=64, help="training batch (the workload leaves it free)")
+    ap.add_argument("--unet-epochs", type=int, default=0,
+                    help="unet: untimed training epochs over all generated samples after the timed steps, then the "
+                         "error of the warm start on held-out 128^2 models (and the evaluation at 256^2 and 512^2 "
+                         "uses the trained network)")
     ap.add_argument("--unet-no-eval", action="store_true",
                     help="skip the warm-started series after the timed training steps (counter runs: the timed "
                          "launches are then each kernel's last dispatches)")
@@ -496,6 +500,45 @@ def main_unet(args):
     ratio = load_traffic(dom, "pmc_traffic_unet.json")
     roof["traffic"] = None if ratio is None else round(ratio * roof["algorithmic_bytes_per_launch"])
     conv_flops = sum(v["flops"] for k, v in by_fn.items() if k.startswith("k_conv"))
+    training = None
+    if args.unet_epochs > 0:
+        nsamp, last = X.shape[0], float("nan")
+        g2 = torch.Generator(device="cuda")
+        g2.manual_seed(1)
+        torch.cuda.synchronize()
+        e0 = time.perf_counter()
+        for _ in range(args.unet_epochs):
+            perm = torch.randperm(nsamp, device="cuda", generator=g2)
+            for s in range(nsamp // bs):
+                i = perm[s * bs:(s + 1) * bs]
+                last = net.train_step(X[i].contiguous(), T[i].contiguous(), 1e-3)
+        torch.cuda.synchronize()
+        e1 = time.perf_counter()
+        # held-out models (seeds never trained on): relative error of the warm start, of psi0 and of zero
+        errs, errs0 = [], []
+        for m in range(2):
+            w = synth.model_layered_salt(n=n, h=10.0, freq=15.0, seed=5001 + m, nsrc=nsrc)
+            op = lsop.Operator(n, n, lsop.C64, max_vec=nsrc)
+            op.set_problem(torch.as_tensor(w.vel, device="cuda"), w.h, w.freq, w.c0)
+            pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=64, levels=4, power_iters=1, seed=m)
+            pc.build()
+            rhs = op.incident(w.src_i, w.src_j)
+            psi, _ = lsop.series_solve(op, pc, rhs, tol=1e-6, max_iter=30)
+            phi0 = net.warm_start(op, rhs)
+            nrm = torch.linalg.vector_norm(psi.reshape(nsrc, -1), dim=1)
+            errs += (torch.linalg.vector_norm((phi0 - psi).reshape(nsrc, -1), dim=1) / nrm).tolist()
+            errs0 += (torch.linalg.vector_norm((rhs - psi).reshape(nsrc, -1), dim=1) / nrm).tolist()
+            del pc, op
+        training = {"epochs": args.unet_epochs, "samples": nsamp, "steps": args.unet_epochs * (nsamp // bs),
+                    "seconds": round(e1 - e0, 2), "last_loss": round(last, 4),
+                    "heldout_rel_err_warm_start": [round(min(errs), 3), round(float(np.median(errs)), 3),
+                                                   round(max(errs), 3)],
+                    "heldout_rel_err_psi0": [round(min(errs0), 3), round(float(np.median(errs0)), 3),
+                                             round(max(errs0), 3)],
+                    "heldout_rel_err_zero": 1.0,
+                    "note": "min / median / max over 64 held-out sources (2 models x 32) at 128^2, 15 Hz"}
+        print(f"[bench] {args.unet_epochs} epochs in {e1 - e0:.1f} s, held-out error {np.median(errs):.3f}",
+              file=sys.stderr, flush=True)
     # warm start inside the series at 256^2 and 512^2 (16 sources each)
     evals = []
     for m, (side, rank, lv) in enumerate(() if args.unet_no_eval else ((256, 96, 6), (512, 160, 7))):
@@ -536,7 +579,8 @@ def main_unet(args):
         "conv_tflops": round(conv_flops / (step_s * args.steps) / 1e12, 2),
         "data_generation": {"solves": gen_solves, "seconds": round(gen_s, 2),
                             "solves_per_s": round(gen_solves / gen_s, 1)},
-        "loss_first_last": [round(losses[0], 4), round(losses[-1], 4)], "warm_start_eval": evals,
+        "loss_first_last": [round(losses[0], 4), round(losses[-1], 4)], "training": training,
+        "warm_start_eval": evals,
         "roofline": roof,
         "kernels": {k: {"launches": v["launches"], "avg_ms": round(v["ms"] / v["launches"], 4)}
                     for k, v in sorted(by_fn.items(), key=lambda kv: -kv[1]["ms"])[:12]},

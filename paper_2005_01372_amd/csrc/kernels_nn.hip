@@ -1,5 +1,5 @@
 // Kernels of the convolutional warm-start network: 3x3 / 1x1 convolutions as
-// implicit GEMMs on bf16 matrix cores (v_mfma_f32_16x16x16bf16_1k) with FP32
+// implicit GEMMs on bf16 matrix cores (gfx950's v_mfma_f32_16x16x32_bf16) with FP32
 // accumulation, their weight gradients, and the element-wise layers (ReLU,
 // 2x2 average pooling, nearest 2x upsampling with channel concatenation, mean
 // squared loss, Adam on FP32 master weights).
@@ -29,29 +29,41 @@ __device__ __forceinline__ unsigned short to_bf16(float x) {
 
 // Tile 64 (rows) x 64 (columns) per workgroup of four waves (each 32 x 32 =
 // 2 x 2 MFMA 16x16 tiles); K staged 32 at a time, LDS rows of NN_SK bf16
-// (k contiguous, so each lane's four k values are one 8-byte read).
-// MFMA 16x16x16 bf16: lane l supplies A[l % 16][4 (l / 16) .. + 3] and
-// B[4 (l / 16) .. + 3][l % 16]; register r of the result is row 4 (l / 16) + r,
-// column l % 16.
+// (k contiguous, so each lane's eight k values are one or two reads).
+// MFMA 16x16x32 bf16: lane l supplies A[l % 16][8 (l / 16) .. + 7] and
+// B[8 (l / 16) .. + 7][l % 16] (both operands take the same k positions, so the
+// product does not depend on how the matrix core orders k); register r of the
+// result is row 4 (l / 16) + r, column l % 16.
 constexpr int NN_T = 64, NN_K = 32, NN_SK = NN_K + 4;
+
+typedef __bf16 nn_bf8 __attribute__((ext_vector_type(8)));
+
+// eight consecutive bf16 of an LDS row: one 16-byte read where rows are 16-byte aligned, else two 8-byte reads
+template <int SK>
+__device__ __forceinline__ nn_bf8 nn_ld8(const unsigned short* p) {
+  if constexpr (SK % 8 == 0) {
+    return *reinterpret_cast<const nn_bf8*>(p);
+  } else {
+    const nn_s4 lo = *reinterpret_cast<const nn_s4*>(p), hi = *reinterpret_cast<const nn_s4*>(p + 4);
+    typedef short nn_s8 __attribute__((ext_vector_type(8)));
+    const nn_s8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(nn_bf8, v);
+  }
+}
 
 template <int SK = NN_SK>
 __device__ __forceinline__ void nn_mma_stage(const unsigned short* sA, const unsigned short* sB, int wm, int wn, int l,
                                              nn_f4 (&acc)[2][2]) {
+  static_assert(NN_K == 32, "one 16x16x32 step per stage");
+  nn_bf8 a[2], b[2];
 #pragma unroll
-  for (int ks = 0; ks < NN_K; ks += 16) {
-    nn_s4 a[2], b[2];
+  for (int i = 0; i < 2; ++i) a[i] = nn_ld8<SK>(&sA[(wm + i * 16 + (l & 15)) * SK + 8 * (l >> 4)]);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-      a[i] = *reinterpret_cast<const nn_s4*>(&sA[(wm + i * 16 + (l & 15)) * SK + ks + 4 * (l >> 4)]);
+  for (int j = 0; j < 2; ++j) b[j] = nn_ld8<SK>(&sB[(wn + j * 16 + (l & 15)) * SK + 8 * (l >> 4)]);
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      b[j] = *reinterpret_cast<const nn_s4*>(&sB[(wn + j * 16 + (l & 15)) * SK + ks + 4 * (l >> 4)]);
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
-  }
+    for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
 }
 
 // Y[p][n] = act(bias[n] + sum_k A[p][k] Wb[k][n]) with A the implicit im2col of
