@@ -255,10 +255,10 @@ def invert(H, r):
 class HodlrPreconditioner:
     """H = (HODLR approximation of I - G0 V)^{-1}, used in eq. (11) (Section 2.4)."""
 
-    def __init__(self, prob, rank, levels, min_width=1, seed=0):
+    def __init__(self, prob, rank, levels, min_width=1, seed=0, probes=None):
         A = operator_matrix(prob.K, prob.chi)
         self.tree = split_tree(prob.nx, prob.nz, levels, min_width)
-        self.approx = build(A, self.tree, rank, seed)
+        self.approx = build(A, self.tree, rank, seed, probes)
         self.inv = invert(self.approx, rank)
         self.n = prob.n
 
