@@ -80,6 +80,13 @@ def parse():
     ap.add_argument("--rank", type=int, default=None, help="probes per block (default 256 hodlr, 64 lowrank)")
     ap.add_argument("--levels", type=int, default=10)
     ap.add_argument("--power-iters", type=int, default=None, help="default 1 hodlr, 0 lowrank")
+    ap.add_argument("--q-from-level", type=int, default=None,
+                    help="hodlr: power iterations on tree levels >= this one only (ls1024 default 5; measured: "
+                         "0 -> 63.9, 2 -> 67.0, 4 -> 68.9, 5 -> 70.1, 6 -> 69.7 (4-5 iterations), 7 -> 65.5 "
+                         "(7 iterations) solves/s, 8 does not converge)")
+    ap.add_argument("--q-from-frac", type=float, default=0.5,
+                    help="uneven: each instance's power iterations on its tree levels >= this fraction of its "
+                         "depth only (measured: 0 -> 151.0, 0.3 -> 171.2, 0.5 -> 174.7, 0.7 -> 157.5 solves/s)"),
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -93,6 +100,8 @@ def parse():
         a.rank = 256 if a.pc == "hodlr" else 64
     if a.power_iters is None:
         a.power_iters = 1 if a.pc == "hodlr" else 0
+    if a.q_from_level is None:
+        a.q_from_level = 5 if (a.pc == "hodlr" and a.workload == "ls1024") else 0
     return a
 
 
@@ -222,11 +231,13 @@ def cpu_baseline(w, args, iterations, converged, nsrc_sample=2):
         Vr.T @ (Vr.conj() @ Yb[:, 0])
         t_lr_level = (time.perf_counter() - t5) * (2 << lv)          # V^H y and W s over one level, one vector
         t_h = t_leafmv + L * t_lr_level                              # one preconditioner application, one vector
-        convs_per_level = (4 + 4 * q) * r    # half-masked sub-domain passes, each a full-grid convolution per vector
-        t_build = nleaf * t_leaf + L * (convs_per_level * t_conv + (1 + 2 * q) * t_qr_level)
+        # per level: half-masked sub-domain passes, each a full-grid convolution per vector, and the QR passes;
+        # the power iterations only on the levels >= q_from_level
+        qs = [q if l >= args.q_from_level else 0 for l in range(L)]
+        t_build = nleaf * t_leaf + sum((4 + 4 * ql) * r * t_conv + (1 + 2 * ql) * t_qr_level for ql in qs)
         t_build += sum(r * (t_leafmv + (L - 1 - l) * t_lr_level) for l in range(L))   # W = A_{l+1}^{-1} U per level
         desc = (f"set-up; one FFT application ({nsrc_sample} vectors); one {nl}x{nl} leaf formed and inverted (x{nleaf});"
-                f" one {seg}x{r} QR (x{2 << lv} half-nodes per level, {1 + 2 * q} per level); leaf and low-rank "
+                f" one {seg}x{r} QR (x{2 << lv} half-nodes per level, 1 + 2 q per level); leaf and low-rank "
                 f"products of one H application; scaled by the GPU step's counts")
     else:
         Yb = rng.standard_normal((n, r)) + 0j
@@ -275,7 +286,8 @@ def main_uneven(args):
     for w, op, v in zip(ws, ops, vels):
         op.set_problem(v, w.h, w.freq, w.c0)
         r, lv = hodlr_policy(w.nx, w.h, w.freq, float(w.vel.min()), args.leaf_cols)
-        pcs.append(lsop.Preconditioner(op, lsop.PC_HODLR, rank=r, levels=lv, power_iters=1, seed=3))
+        pcs.append(lsop.Preconditioner(op, lsop.PC_HODLR, rank=r, levels=lv, power_iters=1, seed=3,
+                                       q_from_level=int(round(args.q_from_frac * lv))))
     batch = lsop.Batch(ops)
     batch.autotune()
     psis = [torch.empty((w.nsrc, w.nx, w.nz), dtype=torch.complex64, device="cuda") for w in ws]
@@ -348,7 +360,7 @@ def main_uneven(args):
                                f"lockstep series in one batch with a captured "
                                f"graph per iteration, autotuned column tiles per shape group",
                    "instances": len(ws), "sources": len(flat), "shape_groups": batch.info()[0],
-                   "leaf_cols": args.leaf_cols, "build_streams": args.build_streams},
+                   "leaf_cols": args.leaf_cols, "build_streams": args.build_streams, "q_from_frac": args.q_from_frac},
         "converged": converged, "statuses": statuses,
         "iterations": [min(x.iters for x in flat), max(x.iters for x in flat)],
         "build_s": round(build_s, 3), "series_s": round(series_s, 3),
@@ -623,7 +635,7 @@ def main():
         o = lsop.Operator(w.nx, w.nz, dtype, max_vec=max(args.nsrc, 64))
         if args.pc == "hodlr":
             p = lsop.Preconditioner(o, lsop.PC_HODLR, rank=args.rank, levels=args.levels,
-                                    power_iters=args.power_iters, seed=3)
+                                    power_iters=args.power_iters, seed=3, q_from_level=args.q_from_level)
         else:
             p = lsop.Preconditioner(o, lsop.PC_LOWRANK, rank=args.rank, power_iters=args.power_iters, seed=3)
         o.set_problem(vel, w.h, w.freq, w.c0)
@@ -736,7 +748,8 @@ def main():
     growth = [(i.rel_residual / i.rel_residual0) ** (1.0 / i.iters) for i in info if i.iters > 0
               and i.rel_residual0 > 0 and np.isfinite(i.rel_residual)]
     if args.pc == "hodlr":
-        pcdesc = f"HODLR H, {args.levels} levels, rank {args.rank}, q={args.power_iters}"
+        pcdesc = f"HODLR H, {args.levels} levels, rank {args.rank}, q={args.power_iters}" + \
+                 (f" on levels >= {args.q_from_level}" if args.q_from_level else "")
     else:
         pcdesc = f"low-rank H rank {args.rank} (q={args.power_iters})"
     build_s, series_s = phase["build"] / args.steps, phase["series"] / args.steps
@@ -750,6 +763,7 @@ def main():
                                f"cap {args.max_iter}",
                    "grid": [w.nx, w.nz], "sources": w.nsrc, "preconditioner": args.pc, "rank": args.rank,
                    "levels": args.levels if args.pc == "hodlr" else None, "power_iters": args.power_iters,
+                   "q_from_level": args.q_from_level if args.pc == "hodlr" else None,
                    "tol": args.tol, "init": args.init, "solver": args.solver,
                    "restart": args.restart if args.solver == "gmres" else None},
         "converged": converged, "statuses": statuses, "iterations": [min(iters), max(iters)],

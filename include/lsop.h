@@ -270,6 +270,9 @@ typedef struct {
   int levels;       /* HODLR tree depth, >= 1 (ignored otherwise) */
   int oversample;   /* LOWRANK: extra probes p >= 0, rank + p <= 256 (0 elsewhere) */
   double alpha;     /* SCALAR: H = alpha I, alpha finite and non-zero */
+  int q_from_level; /* HODLR: the power iterations run on tree levels >= this one only (0: every level; the
+                       wide blocks of the top levels were measured to need none at 1024^2, the narrow deep
+                       ones do); >= 0, ignored elsewhere */
 } lsop_precond_params;
 
 /* Allocate a preconditioner for `op` (U, W: rank x n complex in the inner

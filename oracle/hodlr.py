@@ -179,10 +179,12 @@ def range_finder_ops(matvec, rmatvec, omega, q=0):
     return Q, rmatvec(Q)
 
 
-def build(A, tree, r, seed=0, probes=None, q=0):
+def build(A, tree, r, seed=0, probes=None, q=0, q_from_level=0):
     """HODLR approximation of A on the given tree (off-diagonal blocks by Alg. 1, q = 0 in Section 2.4).
 
     A: the dense matrix, or a `StripOperator`.
+    q_from_level: the q power iterations are taken on the blocks of tree depth >= q_from_level only (not in
+    the paper, which uses q = 0 throughout; 0 applies them everywhere).
     probes: optional callable depth -> real [r, n] block; a node at that depth
     samples its upper block A[I1, I2] with the probe rows restricted to I2 and
     its lower block A[I2, I1] with them restricted to I1.  Without it, the
@@ -202,15 +204,16 @@ def build(A, tree, r, seed=0, probes=None, q=0):
         i1 = slice(node.a11.lo, node.a11.hi)
         i2 = slice(node.a22.lo, node.a22.hi)
         om = probes(depth) if probes is not None else None
+        qd = q if depth >= q_from_level else 0
         if strips is None:
-            node.u12, node.v12 = lowrank_from_block(A[i1, i2], r, rng, None if om is None else om[:, i2].T, q)
-            node.u21, node.v21 = lowrank_from_block(A[i2, i1], r, rng, None if om is None else om[:, i1].T, q)
+            node.u12, node.v12 = lowrank_from_block(A[i1, i2], r, rng, None if om is None else om[:, i2].T, qd)
+            node.u21, node.v21 = lowrank_from_block(A[i2, i1], r, rng, None if om is None else om[:, i1].T, qd)
             return node
         c0, cm, c1 = node.children_cols
         o12 = rng.standard_normal((i2.stop - i2.start, r)) if om is None else om[:, i2].T
-        node.u12, node.v12 = range_finder_ops(*strips.block(c0, (cm, c1), (c0, cm)), o12, q)
+        node.u12, node.v12 = range_finder_ops(*strips.block(c0, (cm, c1), (c0, cm)), o12, qd)
         o21 = rng.standard_normal((i1.stop - i1.start, r)) if om is None else om[:, i1].T
-        node.u21, node.v21 = range_finder_ops(*strips.block(c0, (c0, cm), (cm, c1)), o21, q)
+        node.u21, node.v21 = range_finder_ops(*strips.block(c0, (c0, cm), (cm, c1)), o21, qd)
         return node
     return fill(tree, 0)
 
@@ -281,10 +284,11 @@ class HodlrSolve:
     inverted without the rank truncation of the H-arithmetic inverse.
     """
 
-    def __init__(self, prob, rank, levels, min_width=1, seed=0, probes=None, q=0, matrix_free=False):
+    def __init__(self, prob, rank, levels, min_width=1, seed=0, probes=None, q=0, matrix_free=False,
+                 q_from_level=0):
         A = StripOperator(prob) if matrix_free else operator_matrix(prob.K, prob.chi)
         self.tree = split_tree(prob.nx, prob.nz, levels, min_width)
-        self.approx = build(A, self.tree, rank, seed, probes, q)
+        self.approx = build(A, self.tree, rank, seed, probes, q, q_from_level)
         self.n = prob.n
         self._prepare(self.approx)
 

@@ -719,15 +719,16 @@ int hodlr_sample(lsop_precond* pc, int lv, const double* omega, Cx<T>* Y, Cx<T>*
   if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 0, 1, s))) return st;
   // step 3: orthonormal bases per half-node (result in Y); with power iterations this basis is an
   // intermediate one (one projection and one Cholesky-QR pass), the last one is orthonormalised in full
-  if ((st = hodlr_orth<T>(pc, lv, Q, Y, sc, s, pc->q == 0))) return st;
+  const int q = lv >= pc->q_from ? pc->q : 0;
+  if ((st = hodlr_orth<T>(pc, lv, Q, Y, sc, s, q == 0))) return st;
   // optional power iterations (Alg. 1 step 4) on both blocks of every node
-  for (int j = 0; j < pc->q; ++j) {
+  for (int j = 0; j < q; ++j) {
     if ((st = hodlr_subconv<T>(pc, lv, true, Y, Q, r, 0, 1, s))) return st;
     if ((st = hodlr_subconv<T>(pc, lv, true, Y, Q, r, 1, 0, s))) return st;
     if ((st = hodlr_orth<T>(pc, lv, Q, Y, sc, s, false))) return st;
     if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 1, 0, s))) return st;
     if ((st = hodlr_subconv<T>(pc, lv, false, Y, Q, r, 0, 1, s))) return st;
-    if ((st = hodlr_orth<T>(pc, lv, Q, Y, sc, s, j == pc->q - 1))) return st;
+    if ((st = hodlr_orth<T>(pc, lv, Q, Y, sc, s, j == q - 1))) return st;
   }
   // right factors v12 = (G0 V[I1, I2])^H Q12 on I2, v21 on I1
   if ((st = hodlr_subconv<T>(pc, lv, true, Y, V, r, 0, 1, s))) return st;
@@ -2277,6 +2278,7 @@ int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
     return fail(LSOP_EINVAL, "oversample must be >= 0 with rank + oversample <= 256");
   if (p->kind != LSOP_PC_LOWRANK && p->oversample != 0)
     return fail(LSOP_EINVAL, "oversampling applies to the low-rank preconditioner only");
+  if (p->q_from_level < 0) return fail(LSOP_EINVAL, "q_from_level must be >= 0");
   if (p->kind == LSOP_PC_HODLR) {
     if (op->dims == 3) return fail(LSOP_EUNSUPPORTED, "the HODLR tree is built on 2D column strips");
     if (p->levels < 1 || p->levels > 16 || op->nx % (1 << p->levels) != 0)
@@ -2296,6 +2298,7 @@ int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
   pc->rank = p->rank;
   pc->probes = p->kind == LSOP_PC_LOWRANK ? p->rank + p->oversample : p->rank;
   pc->q = p->power_iters;
+  pc->q_from = p->kind == LSOP_PC_HODLR ? p->q_from_level : 0;
   const size_t n = op->n();
   pc->tcap = std::max(op->max_vec, pc->probes);
   size_t ks = n / 4096;

@@ -295,6 +295,7 @@ struct hodlr_level {
 struct lsop_precond {
   lsop_op* op = nullptr;
   int kind = 0, rank = 0, q = 0, kept = 0;
+  int q_from = 0;  // HODLR: power iterations on levels >= q_from only
   int probes = 0;          // probe vectors l = rank + oversample (LOWRANK)
   double alpha = 0.0;      // SCALAR: H = alpha I
   void* Q2 = nullptr;      // [probes][n] orthonormal basis of W~ (oversampled builds)

@@ -53,7 +53,7 @@ class OpInfo(C.Structure):
 
 class PrecondParams(C.Structure):
     _fields_ = [("kind", C.c_int), ("rank", C.c_int), ("power_iters", C.c_int), ("seed", C.c_uint64),
-                ("levels", C.c_int), ("oversample", C.c_int), ("alpha", C.c_double)]
+                ("levels", C.c_int), ("oversample", C.c_int), ("alpha", C.c_double), ("q_from_level", C.c_int)]
 
 
 class SolveParams(C.Structure):
@@ -462,15 +462,16 @@ class Preconditioner:
     inverse of the HODLR approximation of I - G0 V (Section 2.4, ``levels`` tree levels)."""
 
     def __init__(self, op, kind=PC_LOWRANK, rank=32, power_iters=0, seed=0, levels=0, oversample=0, alpha=0.0,
-                 state=None):
+                 state=None, q_from_level=0):
         self.op, self.lib = op, op.lib
         p = PrecondParams(int(kind), int(rank), int(power_iters), int(seed), int(levels), int(oversample),
-                          float(alpha))
+                          float(alpha), int(q_from_level))
         h = C.c_void_p()
         if state is None:
             _check(self.lib.precond_create(op.handle, C.byref(p), C.byref(h)))
         else:
-            need, _ = Preconditioner.state_bytes(op, kind, rank, power_iters, seed, levels, oversample, alpha)
+            need, _ = Preconditioner.state_bytes(op, kind, rank, power_iters, seed, levels, oversample, alpha,
+                                                 q_from_level)
             self._state = _byte_buffer(state, need, "state")
             _check(self.lib.precond_create_in(op.handle, C.byref(p), _ptr(state), state.numel() * state.element_size(),
                                               C.byref(h)))
@@ -478,10 +479,11 @@ class Preconditioner:
         self.kind, self.rank, self.levels, self.oversample = kind, rank, levels, oversample
 
     @staticmethod
-    def state_bytes(op, kind=PC_LOWRANK, rank=32, power_iters=0, seed=0, levels=0, oversample=0, alpha=0.0):
+    def state_bytes(op, kind=PC_LOWRANK, rank=32, power_iters=0, seed=0, levels=0, oversample=0, alpha=0.0,
+                    q_from_level=0):
         """(state bytes, build workspace bytes) of a preconditioner of `op` (precond_state_bytes; host only)."""
         p = PrecondParams(int(kind), int(rank), int(power_iters), int(seed), int(levels), int(oversample),
-                          float(alpha))
+                          float(alpha), int(q_from_level))
         st, ws = C.c_size_t(), C.c_size_t()
         _check(op.lib.precond_state_bytes(op.handle, C.byref(p), C.byref(st), C.byref(ws)))
         return st.value, ws.value

@@ -56,6 +56,27 @@ def test_hodlr_apply_matches_oracle(dtype, levels, r, q, tol):
     assert rel(host(pc.apply(dev(x, tdt))), hs.apply(x)) <= tol
 
 
+@pytest.mark.parametrize("qfrom", [1, 3, 6])
+def test_hodlr_power_iterations_from_a_level_match_oracle(qfrom):
+    """Power iterations on the levels >= q_from_level only (the top levels' blocks by the plain range finder):
+    H x equals the oracle's nested solve of the same mixed construction, same probe rows, to 1e-10 (FP64);
+    q_from_level past the deepest level is the q = 0 construction."""
+    announce(f"hodlr q_from_level={qfrom}")
+    w = layered(64)
+    prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+    levels, r = 5, 8
+    om = probe_rows(levels, r, prob.n, 21)
+    hs = HD.HodlrSolve(prob, r, levels, probes=lambda d: om[d * r:(d + 1) * r], q=1, q_from_level=qfrom)
+    op = make_op(w, lsop.C128, 8)
+    pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=r, levels=levels, power_iters=1, q_from_level=qfrom)
+    pc.build(torch.as_tensor(om).cuda())
+    x = synth.random_vectors((3, 64, 64), 9)
+    assert rel(host(pc.apply(dev(x))), hs.apply(x)) <= 1e-10
+    if qfrom >= levels:
+        h0 = HD.HodlrSolve(prob, r, levels, probes=lambda d: om[d * r:(d + 1) * r], q=0)
+        assert rel(hs.apply(x), h0.apply(x)) <= 1e-13
+
+
 @pytest.mark.parametrize("nx,nz,levels,r,q", [(64, 64, 3, 12, 0), (16, 1024, 4, 16, 1)])
 def test_hodlr_fp32_apply_matches_oracle(nx, nz, levels, r, q):
     """Complex FP32 against the oracle, including leaves of one grid column of 1024 cells (a 4-level tree on a
@@ -220,7 +241,8 @@ def test_hodlr_invalid_parameters():
     announce("hodlr invalid")
     w = layered(32)
     op = make_op(w, lsop.C128, 4)
-    for kw in ({"levels": 0}, {"levels": 6}, {"levels": 2, "rank": 0}, {"levels": 2, "rank": 300}):
+    for kw in ({"levels": 0}, {"levels": 6}, {"levels": 2, "rank": 0}, {"levels": 2, "rank": 300},
+               {"levels": 2, "q_from_level": -1}):
         args = {"rank": 8, **kw}
         with pytest.raises(lsop.LsopError):
             lsop.Preconditioner(op, lsop.PC_HODLR, **args)

@@ -152,3 +152,22 @@ def test_matrix_free_build_equals_dense_build():
     sm = HD.HodlrSolve(prob, 5, 3, probes=probes, q=1, matrix_free=True)
     x = synth.random_vectors((2, prob.nx, prob.nz), 1)
     assert rel(sm.apply(x), sd.apply(x)) <= 1e-11
+
+
+def test_power_iterations_from_a_level():
+    """q_from_level selects per tree depth between the q = 0 block construction and the q-iteration one: from
+    level 0 it is the q-iteration HODLR matrix, from a level past the deepest it is the q = 0 one, and in
+    between the top blocks are those of q = 0 and the deep ones those of q = 1 (same probes)."""
+    w, prob = small(16)
+    A = O.operator_matrix(prob.K, prob.chi)
+    om = np.random.default_rng(3).standard_normal((3 * 4, prob.n))
+    probes = lambda d: om[d * 4:(d + 1) * 4]
+    tree = lambda: HD.split_tree(prob.nx, prob.nz, 3)
+    h0 = HD.build(A, tree(), 4, probes=probes, q=0)
+    h1 = HD.build(A, tree(), 4, probes=probes, q=1)
+    assert rel(HD.build(A, tree(), 4, probes=probes, q=1, q_from_level=0).to_dense(), h1.to_dense()) == 0
+    assert rel(HD.build(A, tree(), 4, probes=probes, q=1, q_from_level=3).to_dense(), h0.to_dense()) == 0
+    hm = HD.build(A, tree(), 4, probes=probes, q=1, q_from_level=1)
+    assert rel(hm.u12 @ hm.v12.conj().T, h0.u12 @ h0.v12.conj().T) == 0           # depth 0: q = 0
+    assert rel(hm.a11.u12 @ hm.a11.v12.conj().T, h1.a11.u12 @ h1.a11.v12.conj().T) == 0   # depth 1: q = 1
+    assert rel(hm.a11.u12 @ hm.a11.v12.conj().T, h0.a11.u12 @ h0.a11.v12.conj().T) > 0
