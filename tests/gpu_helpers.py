@@ -13,7 +13,7 @@ def require_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     if not os.path.exists(lsop.LIB_PATH):
-        pytest.fail("liblsop.so is not built: the HIP path must be present on a GPU box")
+        pytest.fail("liblsop.so is not built: GPU tests need the HIP library (run the build first)")
     lsop.load_library()
 
 
