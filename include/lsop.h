@@ -273,6 +273,10 @@ typedef struct {
   int q_from_level; /* HODLR: the power iterations run on tree levels >= this one only (0: every level; the
                        wide blocks of the top levels were measured to need none at 1024^2, the narrow deep
                        ones do); >= 0, ignored elsewhere */
+  int min_width;    /* HODLR: the other stopping rule of Section 2.4, a minimum size: no split leaves a node
+                       narrower than min_width grid columns, so the tree depth is the smaller of `levels` and
+                       the deepest level whose nodes are at least min_width wide (0 or 1: no limit; >= 0);
+                       precond_depth reports the depth taken */
 } lsop_precond_params;
 
 /* Allocate a preconditioner for `op` (U, W: rank x n complex in the inner
@@ -323,6 +327,9 @@ int precond_apply(lsop_precond* pc, const void* x_dev, void* y_dev, int nvec, vo
 /* rank kept, compression 2 r / n (Section 3.1.1), device bytes held.
  * HODLR: rank = r, compression = stored complex entries / n^2. */
 int precond_info(const lsop_precond* pc, int* rank, double* compression, size_t* bytes);
+/* Depth of a HODLR preconditioner's tree after the min_width rule (the number of probe blocks precond_build
+ * takes); 0 for the other kinds.  Host only. */
+int precond_depth(const lsop_precond* pc, int* levels);
 void precond_destroy(lsop_precond* pc);
 
 /* ----------------------------------------------------------------------

@@ -2279,14 +2279,19 @@ int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
   if (p->kind != LSOP_PC_LOWRANK && p->oversample != 0)
     return fail(LSOP_EINVAL, "oversampling applies to the low-rank preconditioner only");
   if (p->q_from_level < 0) return fail(LSOP_EINVAL, "q_from_level must be >= 0");
+  if (p->min_width < 0) return fail(LSOP_EINVAL, "min_width must be >= 0");
+  // Section 2.4's minimum-size rule: no level whose nodes would be narrower than min_width columns
+  int levels = p->levels;
+  if (p->kind == LSOP_PC_HODLR && p->min_width > 1)
+    while (levels > 1 && (op->nx >> levels) < p->min_width) --levels;
   if (p->kind == LSOP_PC_HODLR) {
     if (op->dims == 3) return fail(LSOP_EUNSUPPORTED, "the HODLR tree is built on 2D column strips");
-    if (p->levels < 1 || p->levels > 16 || op->nx % (1 << p->levels) != 0)
+    if (levels < 1 || levels > 16 || op->nx % (1 << levels) != 0)
       return fail(LSOP_EINVAL, "HODLR levels must be >= 1 with nx divisible by 2^levels");
-    const size_t nl = (size_t)(op->nx >> p->levels) * op->nz;
+    const size_t nl = (size_t)(op->nx >> levels) * op->nz;
     if (nl % 64 != 0 || nl > 8192)
       return fail(LSOP_EINVAL, "HODLR leaf size (nx / 2^levels) * nz must be a multiple of 64 and at most 8192");
-    for (int lv = 0; lv < p->levels; ++lv)
+    for (int lv = 0; lv < levels; ++lv)
       if (fft_length_sub(op->nx >> lv) < 0) return fail(LSOP_EUNSUPPORTED, "unsupported HODLR level width");
   }
   pc->op = op;
@@ -2304,9 +2309,9 @@ int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
   size_t ks = n / 4096;
   pc->ksplit = (int)std::max<size_t>(1, std::min<size_t>(ks, 256));
   if (p->kind == LSOP_PC_HODLR) {
-    pc->levels = p->levels;
-    pc->leaf_w = op->nx >> p->levels;
-    pc->nleaf = 1 << p->levels;
+    pc->levels = levels;
+    pc->leaf_w = op->nx >> levels;
+    pc->nleaf = 1 << levels;
     const int nl = pc->leaf_w * op->nz;
     pc->maxseg = pc->nleaf;
     pc->ksub_cap = std::max(512, pc->maxseg);
@@ -2319,8 +2324,8 @@ int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
     (void)block_inverse_temps(nl, pc->leaf_chunk, &lw);
     lw += (size_t)pc->leaf_chunk * nl * nl;
     pc->lwork_elems = lw;
-    pc->lev.resize(p->levels);
-    for (int lv = 0; lv < p->levels; ++lv) {
+    pc->lev.resize(levels);
+    for (int lv = 0; lv < levels; ++lv) {
       pc->lev[lv].width = op->nx >> lv;
       pc->lev[lv].lx = fft_length_sub(pc->lev[lv].width);
     }
@@ -2531,6 +2536,12 @@ int precond_apply(lsop_precond* pc, const void* x_dev, void* y_dev, int nvec, vo
   if (pc->dt == LSOP_C128)
     return pc_apply_impl<double>(pc, (const Cx<double>*)x_dev, (Cx<double>*)y_dev, nullptr, nvec, false, S(stream));
   return pc_apply_impl<float>(pc, (const Cx<float>*)x_dev, (Cx<float>*)y_dev, nullptr, nvec, false, S(stream));
+}
+
+int precond_depth(const lsop_precond* pc, int* levels) {
+  if (!pc || !levels) return fail(LSOP_EINVAL, "null argument");
+  *levels = pc->kind == LSOP_PC_HODLR ? pc->levels : 0;
+  return LSOP_OK;
 }
 
 int precond_info(const lsop_precond* pc, int* rank, double* compression, size_t* bytes) {

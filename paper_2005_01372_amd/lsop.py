@@ -31,7 +31,8 @@ EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "ls
            "lsop_create_in", "lsop_workspace_bytes", "lsop_attach_workspace", "lsop_alloc_count", "lsop_apply_noalloc", "gmres_solve", "gmres_workspace_bytes", "lsop_sweep", "lsop_set_problem_damped", "lsop_bessel_host_c", "lsop_create3d",
            "lsop_set_problem3d", "lsop_incident3d",
            "precond_state_bytes", "precond_create_in", "precond_create",
-           "precond_build", "precond_build_batch", "precond_apply", "precond_info", "precond_destroy", "series_solve",
+           "precond_build", "precond_build_batch", "precond_apply", "precond_info", "precond_depth", "precond_destroy",
+           "series_solve",
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
            "lsop_profile_read_kernels", "lsop_batch_create", "lsop_batch_apply", "lsop_batch_autotune",
            "lsop_batch_solve", "lsop_batch_info", "lsop_batch_destroy", "unet_create", "unet_param_count",
@@ -53,7 +54,8 @@ class OpInfo(C.Structure):
 
 class PrecondParams(C.Structure):
     _fields_ = [("kind", C.c_int), ("rank", C.c_int), ("power_iters", C.c_int), ("seed", C.c_uint64),
-                ("levels", C.c_int), ("oversample", C.c_int), ("alpha", C.c_double), ("q_from_level", C.c_int)]
+                ("levels", C.c_int), ("oversample", C.c_int), ("alpha", C.c_double), ("q_from_level", C.c_int),
+                ("min_width", C.c_int)]
 
 
 class SolveParams(C.Structure):
@@ -131,6 +133,7 @@ def load_library(path=LIB_PATH):
         "precond_build_batch": (ip, [vp, C.c_int, C.c_int]),
         "precond_apply": (ip, [vp, vp, vp, ip, vp]),
         "precond_info": (ip, [vp, C.POINTER(ip), C.POINTER(dp), C.POINTER(C.c_size_t)]),
+        "precond_depth": (ip, [vp, C.POINTER(ip)]),
         "precond_destroy": (None, [vp]),
         "series_solve": (ip, [vp, vp, vp, vp, ip, C.POINTER(SolveParams), C.POINTER(SolveInfo), vp]),
         "lsop_bessel_host": (ip, [ip, dp, C.POINTER(dp)]),
@@ -462,28 +465,31 @@ class Preconditioner:
     inverse of the HODLR approximation of I - G0 V (Section 2.4, ``levels`` tree levels)."""
 
     def __init__(self, op, kind=PC_LOWRANK, rank=32, power_iters=0, seed=0, levels=0, oversample=0, alpha=0.0,
-                 state=None, q_from_level=0):
+                 state=None, q_from_level=0, min_width=0):
         self.op, self.lib = op, op.lib
         p = PrecondParams(int(kind), int(rank), int(power_iters), int(seed), int(levels), int(oversample),
-                          float(alpha), int(q_from_level))
+                          float(alpha), int(q_from_level), int(min_width))
         h = C.c_void_p()
         if state is None:
             _check(self.lib.precond_create(op.handle, C.byref(p), C.byref(h)))
         else:
             need, _ = Preconditioner.state_bytes(op, kind, rank, power_iters, seed, levels, oversample, alpha,
-                                                 q_from_level)
+                                                 q_from_level, min_width)
             self._state = _byte_buffer(state, need, "state")
             _check(self.lib.precond_create_in(op.handle, C.byref(p), _ptr(state), state.numel() * state.element_size(),
                                               C.byref(h)))
         self.handle = h
-        self.kind, self.rank, self.levels, self.oversample = kind, rank, levels, oversample
+        depth = C.c_int()
+        _check(self.lib.precond_depth(h, C.byref(depth)))
+        # HODLR: the tree depth after the minimum-width rule (the number of probe blocks build() takes)
+        self.kind, self.rank, self.levels, self.oversample = kind, rank, depth.value or levels, oversample
 
     @staticmethod
     def state_bytes(op, kind=PC_LOWRANK, rank=32, power_iters=0, seed=0, levels=0, oversample=0, alpha=0.0,
-                    q_from_level=0):
+                    q_from_level=0, min_width=0):
         """(state bytes, build workspace bytes) of a preconditioner of `op` (precond_state_bytes; host only)."""
         p = PrecondParams(int(kind), int(rank), int(power_iters), int(seed), int(levels), int(oversample),
-                          float(alpha), int(q_from_level))
+                          float(alpha), int(q_from_level), int(min_width))
         st, ws = C.c_size_t(), C.c_size_t()
         _check(op.lib.precond_state_bytes(op.handle, C.byref(p), C.byref(st), C.byref(ws)))
         return st.value, ws.value

@@ -56,6 +56,25 @@ def test_hodlr_apply_matches_oracle(dtype, levels, r, q, tol):
     assert rel(host(pc.apply(dev(x, tdt))), hs.apply(x)) <= tol
 
 
+@pytest.mark.parametrize("levels,min_width,depth", [(6, 8, 3), (3, 4, 3), (5, 16, 2)])
+def test_hodlr_minimum_width_matches_oracle(levels, min_width, depth):
+    """Section 2.4's minimum-size stopping rule: with min_width the tree stops where a split would leave nodes
+    narrower than min_width columns; the device reports the depth it took, and H x equals the oracle's nested
+    solve on its own tree with the same rule and probe rows, to 1e-10 (FP64)."""
+    announce(f"hodlr levels={levels} min_width={min_width}")
+    w = layered(64)
+    prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+    r = 8
+    op = make_op(w, lsop.C128, 8)
+    pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=r, levels=levels, min_width=min_width)
+    assert pc.levels == depth
+    om = probe_rows(depth, r, prob.n, 21)
+    hs = HD.HodlrSolve(prob, r, levels, min_width=min_width, probes=lambda d: om[d * r:(d + 1) * r])
+    pc.build(torch.as_tensor(om).cuda())
+    x = synth.random_vectors((3, 64, 64), 9)
+    assert rel(host(pc.apply(dev(x))), hs.apply(x)) <= 1e-10
+
+
 @pytest.mark.parametrize("qfrom", [1, 3, 6])
 def test_hodlr_power_iterations_from_a_level_match_oracle(qfrom):
     """Power iterations on the levels >= q_from_level only (the top levels' blocks by the plain range finder):
@@ -242,7 +261,7 @@ def test_hodlr_invalid_parameters():
     w = layered(32)
     op = make_op(w, lsop.C128, 4)
     for kw in ({"levels": 0}, {"levels": 6}, {"levels": 2, "rank": 0}, {"levels": 2, "rank": 300},
-               {"levels": 2, "q_from_level": -1}):
+               {"levels": 2, "q_from_level": -1}, {"levels": 2, "min_width": -1}):
         args = {"rank": 8, **kw}
         with pytest.raises(lsop.LsopError):
             lsop.Preconditioner(op, lsop.PC_HODLR, **args)
