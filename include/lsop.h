@@ -372,6 +372,18 @@ typedef struct {
 int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_dev, int nvec,
                  const lsop_solve_params* params, lsop_solve_info* info_host, void* stream);
 
+/* series_solve from point sources (Section 2.1: the wavefield of given sources, the paper's problem
+ * statement): the incident fields of lsop_incident (src_i_host, src_j_host, amp_reim_host as there) are formed
+ * in the operator's workspace and solved for; psi_dev: [nsrc][nx][nz] output (input with LSOP_INIT_USER /
+ * LSOP_INIT_BEST); info_host: nsrc entries.  The same results as lsop_incident followed by series_solve.
+ * Workspace: series_sources_workspace_bytes (the nsrc incident fields ahead of series_solve's own); grown by
+ * the library or taken from the attached workspace.  2D operators.  Errors: as lsop_incident and
+ * series_solve. */
+int series_solve_sources(lsop_op* op, lsop_precond* pc, const int* src_i_host, const int* src_j_host,
+                         const double* amp_reim_host, int nsrc, void* psi_dev, const lsop_solve_params* params,
+                         lsop_solve_info* info_host, void* stream);
+int series_sources_workspace_bytes(const lsop_op* op, int nsrc, int init, size_t* bytes);
+
 /* ----------------------------------------------------------------------
  * Restarted GMRES(m), the Krylov method the paper compares the preconditioned
  * series with (Section 3.2.3), right-preconditioned by H: it solves

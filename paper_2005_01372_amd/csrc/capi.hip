@@ -2569,8 +2569,10 @@ void precond_destroy(lsop_precond* pc) {
 }
 
 // ------------------------------------------------------------------ series
-int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_dev, int nvec,
-                 const lsop_solve_params* p, lsop_solve_info* info, void* stream) {
+// series_solve with its workspace at byte offset `off` of the operator's scratch (the bytes before it hold the
+// right-hand sides of series_solve_sources)
+static int series_solve_at(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_dev, int nvec,
+                           const lsop_solve_params* p, lsop_solve_info* info, void* stream, size_t off) {
   int st = check_op(op);
   if (st) return st;
   if (!p || !info) return fail(LSOP_EINVAL, "null params or info");
@@ -2586,8 +2588,8 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
   if (op->dtype != LSOP_MIXED) {
     const size_t esz = op->dtype == LSOP_C64 ? sizeof(Cx<float>) : sizeof(Cx<double>);
     const size_t vb = align_up(esz * n * nvec);
-    if ((st = grow_scratch(op, series_ws_bytes(op, nvec, p->init)))) return st;
-    char* base = (char*)op->scratch;
+    if ((st = grow_scratch(op, off + series_ws_bytes(op, nvec, p->init)))) return st;
+    char* base = (char*)op->scratch + off;
     void* r = base;
     double* dn = (double*)(base + vb);
     int* dv = (int*)((char*)dn + align_up(sizeof(double) * nvec));
@@ -2604,15 +2606,49 @@ int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_d
   // ---- mixed precision: iterative refinement (outer FP64, inner FP32 series)
   const int refine_max = p->refine_max > 0 ? p->refine_max : 8;
   const double inner_tol = p->inner_tol > 0 ? p->inner_tol : 1e-5;
-  if ((st = grow_scratch(op, series_ws_bytes(op, nvec, p->init)))) return st;
-  char* w32 = (char*)op->scratch + refine_ws_bytes(n, nvec);
+  if ((st = grow_scratch(op, off + series_ws_bytes(op, nvec, p->init)))) return st;
+  char* w32 = (char*)op->scratch + off + refine_ws_bytes(n, nvec);
   auto inner = [&](const Cx<float>* rhs32, Cx<float>* d32, const std::vector<int>& active, lsop_solve_info* inf,
                    double* dn, int* dv) {
     return series_impl<float>(op, pcu, rhs32, d32, nvec, inner_tol, p->max_iter, LSOP_INIT_H_RHS, active, inf,
                               (Cx<float>*)w32, dn, dv, s);
   };
   return refine_impl(op, (const Cx<double>*)rhs_dev, (Cx<double>*)psi_dev, nvec, p->tol, refine_max, p->init, info,
-                     (char*)op->scratch, s, inner);
+                     (char*)op->scratch + off, s, inner);
+}
+
+int series_solve(lsop_op* op, lsop_precond* pc, const void* rhs_dev, void* psi_dev, int nvec,
+                 const lsop_solve_params* p, lsop_solve_info* info, void* stream) {
+  return series_solve_at(op, pc, rhs_dev, psi_dev, nvec, p, info, stream, 0);
+}
+
+// bytes of the incident fields series_solve_sources keeps in the workspace ahead of the series' own
+static size_t sources_rhs_bytes(const lsop_op* op, int nsrc) {
+  const size_t esz = op->dtype == LSOP_C64 ? sizeof(Cx<float>) : sizeof(Cx<double>);
+  return align_up(esz * op->n() * (size_t)nsrc);
+}
+
+int series_sources_workspace_bytes(const lsop_op* op, int nsrc, int init, size_t* bytes) {
+  if (!op || !bytes) return fail(LSOP_EINVAL, "null argument");
+  if (nsrc < 0 || init < 0 || init > 3) return fail(LSOP_EINVAL, "bad nsrc or init");
+  *bytes = sources_rhs_bytes(op, nsrc) + series_ws_bytes(op, nsrc, init);
+  return LSOP_OK;
+}
+
+int series_solve_sources(lsop_op* op, lsop_precond* pc, const int* src_i_host, const int* src_j_host,
+                         const double* amp_reim_host, int nsrc, void* psi_dev, const lsop_solve_params* p,
+                         lsop_solve_info* info, void* stream) {
+  int st = check_op(op);
+  if (st) return st;
+  if (op->dims == 3) return fail(LSOP_EINVAL, "3D operator: use lsop_incident3d and series_solve");
+  if (!p || !info) return fail(LSOP_EINVAL, "null params or info");
+  if (nsrc < 1 || !src_i_host || !src_j_host || !psi_dev) return fail(LSOP_EINVAL, "bad sources");
+  if (p->init < 0 || p->init > 3) return fail(LSOP_EINVAL, "bad init");
+  const size_t rb = sources_rhs_bytes(op, nsrc);
+  // the whole workspace first: a library-owned workspace that grew later would lose the incident fields
+  if ((st = grow_scratch(op, rb + series_ws_bytes(op, nsrc, p->init)))) return st;
+  if ((st = lsop_incident(op, src_i_host, src_j_host, amp_reim_host, nsrc, op->scratch, stream))) return st;
+  return series_solve_at(op, pc, op->scratch, psi_dev, nsrc, p, info, stream, rb);
 }
 
 static int gmres_ws_query(const lsop_op* op, int nvec, int restart, size_t* bytes);

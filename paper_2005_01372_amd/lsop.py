@@ -32,7 +32,7 @@ EXPORTS = ("lsop_create", "lsop_set_problem", "lsop_apply", "lsop_residual", "ls
            "lsop_set_problem3d", "lsop_incident3d",
            "precond_state_bytes", "precond_create_in", "precond_create",
            "precond_build", "precond_build_batch", "precond_apply", "precond_info", "precond_depth", "precond_destroy",
-           "series_solve",
+           "series_solve", "series_solve_sources", "series_sources_workspace_bytes",
            "lsop_bessel_host", "lsop_profile_enable", "lsop_profile_reset", "lsop_profile_read",
            "lsop_profile_read_kernels", "lsop_batch_create", "lsop_batch_apply", "lsop_batch_autotune",
            "lsop_batch_solve", "lsop_batch_info", "lsop_batch_destroy", "unet_create", "unet_param_count",
@@ -136,6 +136,8 @@ def load_library(path=LIB_PATH):
         "precond_depth": (ip, [vp, C.POINTER(ip)]),
         "precond_destroy": (None, [vp]),
         "series_solve": (ip, [vp, vp, vp, vp, ip, C.POINTER(SolveParams), C.POINTER(SolveInfo), vp]),
+        "series_solve_sources": (ip, [vp, vp, vp, vp, vp, ip, vp, C.POINTER(SolveParams), C.POINTER(SolveInfo), vp]),
+        "series_sources_workspace_bytes": (ip, [vp, ip, ip, C.POINTER(C.c_size_t)]),
         "lsop_bessel_host": (ip, [ip, dp, C.POINTER(dp)]),
         "lsop_profile_enable": (ip, [ip]),
         "lsop_profile_reset": (ip, []),
@@ -362,7 +364,10 @@ class Operator:
         _check(self.lib.lsop_residual(self.handle, _ptr(psi), _ptr(rhs), _ptr(out), _ptr(nrm), nv, _stream()))
         return out, nrm
 
-    def incident(self, src_i, src_j, amp=None):
+    @staticmethod
+    def _sources(src_i, src_j, amp):
+        if len(src_i) != len(src_j) or (amp is not None and len(amp) != len(src_i)):
+            raise ValueError("src_i, src_j (and amp) must have one entry per source")
         si = (C.c_int * len(src_i))(*[int(v) for v in src_i])
         sj = (C.c_int * len(src_j))(*[int(v) for v in src_j])
         if amp is not None:
@@ -372,6 +377,10 @@ class Operator:
             ap = (C.c_double * len(a))(*a)
         else:
             ap = None
+        return si, sj, ap
+
+    def incident(self, src_i, src_j, amp=None):
+        si, sj, ap = self._sources(src_i, src_j, amp)
         out = torch.empty((len(src_i), self.nx, self.nz), dtype=self.vec_dtype, device="cuda")
         _check(self.lib.lsop_incident(self.handle, si, sj, ap, len(src_i), _ptr(out), _stream()))
         return out
@@ -555,6 +564,32 @@ def series_solve(op, pc, rhs, psi=None, tol=1e-10, max_iter=30, init="h_rhs", re
                              C.byref(p), info, _stream())
     _check(st, allow=() if raise_on_failure else (NOT_CONVERGED, DIVERGED))
     return psi, [SolveResult(i.iters, i.refine_steps, i.rel_residual, i.status, i.rel_residual0) for i in info]
+
+
+def series_solve_sources(op, pc, src_i, src_j, amp=None, psi=None, tol=1e-10, max_iter=30, init="h_rhs",
+                         refine_max=8, inner_tol=1e-5, raise_on_failure=False):
+    """The series for point sources (series_solve_sources): the incident fields are formed in the operator's
+    workspace; returns (psi, [SolveResult per source])."""
+    si, sj, ap = op._sources(src_i, src_j, amp)
+    ns = len(src_i)
+    if ns < 1:
+        raise ValueError("at least one source")
+    psi = torch.empty((ns, op.nx, op.nz), dtype=op.vec_dtype, device="cuda") if psi is None else psi
+    op._vecs(psi, nvec=ns)
+    _gpu(psi)
+    p = SolveParams(float(tol), int(max_iter), INIT[init], int(refine_max), float(inner_tol))
+    info = (SolveInfo * ns)()
+    st = op.lib.series_solve_sources(op.handle, pc.handle if pc is not None else None, si, sj, ap, ns, _ptr(psi),
+                                     C.byref(p), info, _stream())
+    _check(st, allow=() if raise_on_failure else (NOT_CONVERGED, DIVERGED))
+    return psi, [SolveResult(i.iters, i.refine_steps, i.rel_residual, i.status, i.rel_residual0) for i in info]
+
+
+def series_sources_workspace_bytes(op, nsrc, init="h_rhs"):
+    """Workspace of series_solve_sources for nsrc sources (host only)."""
+    b = C.c_size_t()
+    _check(op.lib.series_sources_workspace_bytes(op.handle, int(nsrc), INIT[init], C.byref(b)))
+    return b.value
 
 
 def gmres_solve(op, pc, rhs, psi=None, tol=1e-10, restart=30, max_iter=300, init="zero", refine_max=8,

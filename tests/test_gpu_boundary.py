@@ -154,3 +154,40 @@ def test_caller_owned_memory_matches_library_owned(kind):
         lsop.series_solve(op2, pc2, rhs2, psi=psi2, tol=1e-12, max_iter=60)
     assert e.value.status == lsop.ENOMEM
     del pc2, op2, pc, op
+
+
+@pytest.mark.parametrize("dt", [lsop.C128, lsop.MIXED, lsop.C64])
+def test_series_from_sources_equals_incident_then_series(dt):
+    """series_solve_sources (the wavefield of given point sources) gives the iterates of lsop_incident followed
+    by series_solve, also in a caller-owned workspace of the size its query reports (no device allocation)."""
+    announce(f"series from sources dtype={dt}")
+    w = synth.model_layered_salt(n=64, h=10.0, freq=15.0, seed=2, nsrc=5)
+    amp = [1.0, 0.5 - 0.25j, 2.0, 1j, -1.0]
+    op = make_op(w, dt, 8)
+    pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=16, levels=3, power_iters=1, seed=5)
+    pc.build()
+    rhs = op.incident(w.src_i, w.src_j, amp)
+    stol = 1e-5 if dt == lsop.C64 else 1e-11
+    psi_a, res_a = lsop.series_solve(op, pc, rhs, tol=stol, max_iter=40)
+    psi_b, res_b = lsop.series_solve_sources(op, pc, w.src_i, w.src_j, amp, tol=stol, max_iter=40)
+    tol = 1e-6 if dt == lsop.C64 else 1e-13    # the residual norms are summed with atomics: the last bits may differ
+    assert rel(host(psi_b), host(psi_a)) <= tol
+    assert [r.iters for r in res_a] == [r.iters for r in res_b]
+    assert all(r.status == lsop.OK for r in res_b)
+    need = lsop.series_sources_workspace_bytes(op, 5)
+    ws = torch.empty(max(need, op.workspace_bytes(5)), dtype=torch.uint8, device="cuda")
+    op.attach_workspace(ws)
+    torch.cuda.synchronize()
+    before = lsop.alloc_count()
+    psi_c, _ = lsop.series_solve_sources(op, pc, w.src_i, w.src_j, amp, tol=stol, max_iter=40)
+    torch.cuda.synchronize()
+    assert lsop.alloc_count() == before
+    assert rel(host(psi_c), host(psi_a)) <= tol
+    op.attach_workspace(ws[:need // 2])
+    with pytest.raises(lsop.LsopError) as e:
+        lsop.series_solve_sources(op, pc, w.src_i, w.src_j, amp, tol=stol, max_iter=40)
+    assert e.value.status == lsop.ENOMEM
+    op.attach_workspace(None)
+    with pytest.raises(ValueError):
+        lsop.series_solve_sources(op, pc, w.src_i, w.src_j[:2], None)
+    del pc, op
