@@ -320,6 +320,37 @@ def test_full_size_benchmark_solve():
     assert np.sqrt(num_a / den_a) <= 1e-5
 
 
+@pytest.mark.timeout(900)
+def test_full_size_mixed_precision_solve():
+    """The benchmark workload solved by FP32 inner series inside FP64 refinement down to 1e-9: the oracle's FP64
+    residual ||A psi - psi0|| / ||psi0|| (its own incident fields and FFT product on the CPU) is <= 1.5e-9 for
+    every one of 32 sources (every fourth of the benchmark's 128), i.e. the complex-float preconditioner and
+    inner series deliver FP64 accuracy at full size."""
+    announce("benchmark workload 1024^2, mixed precision to 1e-9")
+    w = synth.model_random_ellipses(n=1024, nsrc=128)
+    sel = np.arange(0, 128, 4)
+    op = make_op(w, lsop.MIXED, 32)
+    op.autotune(32)
+    pc = lsop.Preconditioner(op, lsop.PC_HODLR, rank=256, levels=10, power_iters=1, seed=3, q_from_level=5)
+    pc.build()
+    rhs = op.incident(w.src_i[sel], w.src_j[sel])
+    psi, res = lsop.series_solve(op, pc, rhs, tol=1e-9, max_iter=30, inner_tol=1e-5)
+    announce(f"refinement steps {min(r.refine_steps for r in res)}-{max(r.refine_steps for r in res)}, "
+             f"inner iterations {min(r.iters for r in res)}-{max(r.iters for r in res)}")
+    assert all(r.status == lsop.OK for r in res)
+    psi_h = host(psi)
+    del pc
+    torch.cuda.empty_cache()
+    prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+    prob.workers = os.cpu_count()
+    rr = np.empty(len(sel))
+    for c in range(0, len(sel), 8):
+        psi0 = prob.incident(w.src_i[sel[c:c + 8]], w.src_j[sel[c:c + 8]])
+        rr[c:c + 8] = O.relative_residual(prob, psi_h[c:c + 8], psi0)
+    announce(f"oracle residuals: max {rr.max():.3e}, min {rr.min():.3e}")
+    assert np.all(rr <= 1.5e-9), rr.max()
+
+
 def _golden_layered_salt():
     """The oracle's solution of the 256^2 layered + salt workload at sampled cells (tests/golden/, written by
     make_layered_salt_256.py from oracle/ only)."""
