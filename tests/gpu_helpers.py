@@ -39,3 +39,19 @@ def make_op(w, dtype=lsop.C128, max_vec=16):
     op = lsop.Operator(w.nx, w.nz, dtype, max_vec)
     op.set_problem(torch.as_tensor(w.vel).cuda(), w.h, w.freq, w.c0)
     return op
+
+
+def golden_layered_salt():
+    """The oracle's solution of the 256^2 layered + salt workload at sampled cells (tests/golden/, written by
+    make_layered_salt_256.py from oracle/ only)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "layered_salt_256_solution.txt")
+    norms, cells = {}, {}
+    for line in open(path):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "R":
+            norms[int(f[1])] = float(f[4])
+        else:
+            cells.setdefault(int(f[1]), []).append((int(f[2]), int(f[3]), complex(float(f[4]), float(f[5]))))
+    return norms, cells

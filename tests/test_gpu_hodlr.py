@@ -18,7 +18,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import announce, dev, host, make_op, rel, require_gpu
+from gpu_helpers import announce, dev, golden_layered_salt, host, make_op, rel, require_gpu
 from oracle import hodlr as HD
 from oracle import lsop_oracle as O
 from oracle.philox import gaussian_probes as philox_probes
@@ -351,22 +351,6 @@ def test_full_size_mixed_precision_solve():
     assert np.all(rr <= 1.5e-9), rr.max()
 
 
-def _golden_layered_salt():
-    """The oracle's solution of the 256^2 layered + salt workload at sampled cells (tests/golden/, written by
-    make_layered_salt_256.py from oracle/ only)."""
-    path = os.path.join(os.path.dirname(__file__), "golden", "layered_salt_256_solution.txt")
-    norms, cells = {}, {}
-    for line in open(path):
-        f = line.split()
-        if not f or f[0].startswith("#"):
-            continue
-        if f[0] == "R":
-            norms[int(f[1])] = float(f[4])
-        else:
-            cells.setdefault(int(f[1]), []).append((int(f[2]), int(f[3]), complex(float(f[4]), float(f[5]))))
-    return norms, cells
-
-
 def test_layered_salt_256_fp64_and_refined_fp32():
     """The 256^2 layered + salt workload (h = 10 m, 15 Hz, 1500-4500 m/s with two salt blocks, 32 top-row
     sources).  FP64, and FP32 with FP64 refinement, each HODLR-preconditioned (rank 80, 5 levels, q = 1),
@@ -376,7 +360,7 @@ def test_layered_salt_256_fp64_and_refined_fp32():
     here (the paper finds it limited to low frequency and small models)."""
     announce("layered+salt 256^2 x 32: fp64 vs fp32 + refinement vs the oracle's solution")
     w = synth.model_layered_salt(n=256, h=10.0, freq=15.0, seed=2, nsrc=32)
-    norms, cells = _golden_layered_salt()
+    norms, cells = golden_layered_salt()
     out = {}
     for dt in (lsop.C128, lsop.MIXED):
         op = make_op(w, dt, 32)
