@@ -650,6 +650,19 @@ int hodlr_ksub(const lsop_precond* pc, size_t seg, int nseg) {
 // Sub-domain convolution at level lv: y = G0 V x (adj = false) or
 // V^H G0^H x (adj = true) on each node's strip alone, input restricted to the
 // half in_half of every node, only the half out_half of y written.
+//
+// Levels marked half move only the input half through the intermediate and convolve at period W (the node
+// width) in x: the input half's h = W / 2 rows go to the first half of the period and the output half is read
+// from the second, so the circular lag (period position of the output minus that of the input) runs over
+// 1 .. W - 1 and never wraps.  The forward table puts lag c at position c; the adjoint pass multiplies by the
+// conjugate spectrum, i.e. the table conj(K(W - c)).  The strip rows are mapped to period positions so that the
+// circular lag equals |x_out - x_in| (forward) or W - |x_out - x_in| (adjoint); for input position i and output
+// position h + j (0 <= i, j < h):
+//   forward, half 0 -> 1:  x_in = i,         x_out = h + j
+//   forward, half 1 -> 0:  x_in = W - 1 - i, x_out = h - 1 - j
+//   adjoint, half 0 -> 1:  x_in = h - 1 - i, x_out = W - 1 - j
+//   adjoint, half 1 -> 0:  x_in = h + i,     x_out = j
+// (G0 depends on |x_out - x_in| only, Section 2.2.)
 template <typename T>
 int hodlr_subconv(lsop_precond* pc, int lv, bool adj, const Cx<T>* x, Cx<T>* y, int nvec, int in_half, int out_half,
                   hipStream_t s) {
@@ -658,27 +671,42 @@ int hodlr_subconv(lsop_precond* pc, int lv, bool adj, const Cx<T>* x, Cx<T>* y, 
   const int W = L.width, nodes = op->nx / W, half = W / 2;
   const int in_lo = in_half ? half : 0, in_hi = in_half ? W : half;
   const int out_lo = out_half ? half : 0, out_hi = out_half ? W : half;
+  if (L.half && in_half == out_half) return fail(LSOP_EINVAL, "sub-domain convolution within one half");
+  RowMap rin, rout;
+  int rows = W;  // rows per node in the intermediate
+  if (L.half) {
+    rows = half;
+    rin.ns = rout.ns = half;
+    if (!adj) {
+      rin.xa = in_half ? W - 1 : 0, rin.xs = in_half ? -1 : 1;
+      rout.xa = in_half ? half - 1 : half, rout.xs = in_half ? -1 : 1;
+    } else {
+      rin.xa = in_half ? half : half - 1, rin.xs = in_half ? 1 : -1;
+      rout.xa = in_half ? 0 : W - 1, rout.xs = in_half ? 1 : -1;
+    }
+  }
   const size_t n = op->n();
   Cx<T>* tmp = reinterpret_cast<Cx<T>*>(op->tmp);
-  const double e = sizeof(Cx<T>), nn = (double)n, np = (double)op->nx * op->pz();
+  const double e = sizeof(Cx<T>), nn = (double)n, np = (double)nodes * rows * op->pz();
   for (int c = 0; c < nvec; c += op->max_vec) {
     const int m = std::min(op->max_vec, nvec - c);
     const size_t off = (size_t)c * n;
     std::string fcol;
     LSOP_HIP(prof("hodlr_rows_fwd", fn_name("k_rows_fwd", tname<T>(), op->lz), m * (0.5 * nn * e + np * e), 0.0, m, s, [&] {
       return launch_rows_fwd<T>(op->lz, x + off, Dt<T>::chi(op), tmp, nullptr, W, op->nz, m * nodes, !adj,
-                                Dt<T>::twz(op), s, nodes, in_lo, in_hi);
+                                Dt<T>::twz(op), s, nodes, in_lo, in_hi, nullptr, rows, rin);
     }));
     LSOP_HIP(prof("hodlr_cols", fcol, m * 2.0 * np * e + 2.0 * op->pz() * L.lx * e, 0.0, m, s, [&] {
       int used = 0;
-      hipError_t er = launch_cols<T>(L.lx, tmp, lev_gs<T>(L), W, op->pz(), m * nodes, adj, lev_tw<T>(L), s, 0, &used);
+      hipError_t er = launch_cols<T>(L.lx, tmp, lev_gs<T>(L), rows, op->pz(), m * nodes, adj, lev_tw<T>(L), s, 0,
+                                     &used);
       fcol = fn_name("k_cols", tname<T>(), L.lx, used);
       return er;
     }));
     LSOP_HIP(prof("hodlr_rows_inv", fn_name("k_rows_inv", tname<T>(), op->lz), m * (np * e + 0.5 * nn * e), 0.0, m, s,
                   [&] {
       return launch_rows_inv<T>(op->lz, tmp, x + off, Dt<T>::chi(op), nullptr, y + off, nullptr, nullptr, W, op->nz,
-                                m * nodes, adj ? 3 : 1, Dt<T>::twz(op), s, nodes, out_lo, out_hi);
+                                m * nodes, adj ? 3 : 1, Dt<T>::twz(op), s, nodes, out_lo, out_hi, nullptr, rows, rout);
     }));
   }
   return LSOP_OK;
@@ -998,7 +1026,7 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
     int st = grow_scratch(op, s1);
     if (st) return st;
     LSOP_HIP(launch_spectrum(L.lx, op->lz, op->ktab, L.width, op->nz, reinterpret_cast<Cx<double>*>(op->scratch),
-                             L.gs64, L.gs32, L.tw64, op->tw2z64, s));
+                             L.gs64, L.gs32, L.tw64, op->tw2z64, s, L.half));
   }
   int st = hodlr_leaves<T>(pc, s);
   if (st) return st;
@@ -2325,9 +2353,17 @@ int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
     lw += (size_t)pc->leaf_chunk * nl * nl;
     pc->lwork_elems = lw;
     pc->lev.resize(levels);
+    // the zero-padded sampling form on every level (both forms give the same samples; compared in tests)
+    const char* pad_env = getenv("LSOP_HODLR_PADDED_SAMPLING");
+    const bool padded_sampling = pad_env && atoi(pad_env) != 0;
     for (int lv = 0; lv < levels; ++lv) {
-      pc->lev[lv].width = op->nx >> lv;
-      pc->lev[lv].lx = fft_length_sub(pc->lev[lv].width);
+      hodlr_level& L = pc->lev[lv];
+      L.width = op->nx >> lv;
+      // between the two halves of a node only the x-lags 1 .. width - 1 occur, so a circular convolution of
+      // period width (x-transform pair of length width / 2) is exact where that length is one the FFT engine has
+      const int h = L.width / 2;
+      L.half = L.width % 2 == 0 && h >= 2 && fft_length_sub(h) == h && !padded_sampling;
+      L.lx = L.half ? h : fft_length_sub(L.width);
     }
   }
   return LSOP_OK;

@@ -52,10 +52,16 @@ struct Slot {
 // Grouped batches (tab != NULL, nodes = 1, no vidx): slot s takes its operands from tab[s].
 // trows: rows per slot of tmp (default nx): a slot's rows i < nx are written to tmp rows slot * trows + i (the
 // 3D operator stores each x-plane's ny rows in a plane of py rows).
+// rm: which strip rows the pass visits.  Item i of a slot (0 <= i < rm.ns, default nx) is strip row
+// rm.xa + rm.xs * i (xs = +1 or -1) and row i of the slot's part of tmp; the default visits every row in order.
+// Sub-domain convolutions between the two halves of a node use it to move one half only, reflected or not.
+struct RowMap {
+  int ns = -1, xa = 0, xs = 1;
+};
 template <typename T>
 hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, const int* vidx, int nx, int nz,
                            int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s, int nodes = 1, int lo = 0,
-                           int hi = -1, const Slot<T>* tab = nullptr, int trows = -1);
+                           int hi = -1, const Slot<T>* tab = nullptr, int trows = -1, RowMap rm = RowMap());
 // tile: columns per workgroup (0 = widest that fits; narrower tiles allow more workgroups per CU)
 // *used (optional) receives the tile width launched
 template <typename T>
@@ -63,16 +69,21 @@ hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int n
                        hipStream_t s, int tile = 0, int* used = nullptr, const Slot<T>* tab = nullptr);
 // epi: 0 y = x - c, 1 y = c, 2 y = x - chi c, 3 y = chi c; rhs != NULL: y -= rhs and rnorm[slot] += |y|^2
 // Sub-domain batches as in pass 1; rows outside [lo, hi) of a strip are not written.  The residual norm of
-// a slot accumulates into rnorm[slot / nodes] (one norm per stored vector).
+// a slot accumulates into rnorm[slot / nodes] (one norm per stored vector).  rm as in pass 1.
 template <typename T>
 hipError_t launch_rows_inv(int L, const Cx<T>* tmp, const Cx<T>* x, const T* chi, const Cx<T>* rhs, Cx<T>* y,
                            double* rnorm, const int* vidx, int nx, int nz, int nslots, int epi, const Cx<T>* tw2,
                            hipStream_t s, int nodes = 1, int lo = 0, int hi = -1, const Slot<T>* tab = nullptr,
-                           int trows = -1);
-// spectrum of the circulant-extended kernel table (FP64), written as gs[2][pz][lx] in T
+                           int trows = -1, RowMap rm = RowMap());
+// spectrum of the circulant-extended kernel table (FP64), written as gs[2][pz][lx] in T.
+// circ = false: the x-lags are embedded symmetrically in the period 2 lx (lag min(p, 2 lx - p)), the table of
+// a linear convolution.  circ = true: period 2 lx holds lag p itself at position p (a circular convolution whose
+// inputs and outputs lie in opposite halves of the period, so that only lags 1 .. 2 lx - 1 occur), and the odd
+// frequency half is negated, so that the even/odd recombination of the column pass returns the second half of
+// the period.
 hipError_t launch_spectrum(int lx, int lz, const Cx<double>* ktab, int nx, int nz, Cx<double>* s1t,
                            Cx<double>* gs64, Cx<float>* gs32, const Cx<double>* tw2x, const Cx<double>* tw2z,
-                           hipStream_t s);
+                           hipStream_t s, bool circ = false);
 // 3D operator: forward-only (dir 0) / inverse-only (dir 1) column transforms over slots of [rows_slot][pz]
 // (dir 0: rows < nrow in, 2L rows out in split order; dir 1: 2L rows in, rows < nrow out); the 3D lag table
 // (K = c1 e^{i k0 r} / r, K(0) = self); its spectrum gs[2][py pz][lx] (u: nx ny nz, F: px py pz complex doubles
@@ -282,6 +293,7 @@ struct lsop_op {
 // One level of the HODLR preconditioner (nodes of `width` grid columns).
 struct hodlr_level {
   int width = 0, lx = 0;                  // node width and its x-FFT length
+  bool half = false;                      // sampling convolves half-node to half-node at period width (lx = width / 2)
   void* V = nullptr;                      // [rank][n] packed right factors (per half-node)
   void* Wp = nullptr;                     // [rank][n] A_{l+1}^{-1} U, packed
   Cx<double>* kinv = nullptr;             // [nodes][2 rank][2 rank] (P K)^{-1}

@@ -70,7 +70,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
                                                                      int nitems, int mulchi,
                                                                      const Cx<T>* __restrict__ tw2, int nodes, int lo,
                                                                      int hi, const Slot<T>* __restrict__ tab,
-                                                                     int trows) {
+                                                                     int trows, RowMap rm) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
   __shared__ Cx<T> sbuf[GPW][2][lds_len<L>()];
@@ -85,7 +85,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
   auto fetch = [&](int base) {
     const int item = base + grp;
     const int it = item < nitems ? item : nitems - 1;
-    const int slot = it / nx, i = it % nx;
+    const int slot = it / rm.ns, i = rm.xa + rm.xs * (it % rm.ns);
     const int node = slot % nodes, vs = slot / nodes;
     const int vi = vidx ? vidx[vs] : vs;
     const size_t row = (size_t)node * nx + i;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
     const int item = base + grp;
     const bool valid = item < nitems;
     const int it = valid ? item : nitems - 1;
-    const int slot = it / nx, i = it % nx;
+    const int slot = it / rm.ns, ii = it % rm.ns;
     Cx<T> a[E], b[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -114,7 +114,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_fwd(const Cx<T>
       b[e] = a[e] * tw_lo<T, L>(stw, p);
     }
     if (base + step < nitems) fetch(base + step);
-    Cx<T>* tr = tmp + ((size_t)slot * trows + i) * (2 * L);
+    Cx<T>* tr = tmp + ((size_t)slot * trows + ii) * (2 * L);
     fft2_regs<T, L, false>(a, b, g, sbuf[grp][0], sbuf[grp][1], stw);
     if (valid) {
 #pragma unroll
@@ -430,7 +430,7 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
                                                                      int nitems, int epi,
                                                                      const Cx<T>* __restrict__ tw2, int nodes, int lo,
                                                                      int hi, const Slot<T>* __restrict__ tab,
-                                                                     int trows) {
+                                                                     int trows, RowMap rm) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<T, L>() / G;
   __shared__ Cx<T> sbuf[GPW][2][lds_len<L>()];
@@ -442,12 +442,12 @@ __global__ __launch_bounds__((rows_threads<T, L>())) void k_rows_inv(const Cx<T>
   for (int base = blockIdx.x * GPW; base < nitems; base += gridDim.x * GPW) {
     const int item = base + grp;
     const int it = item < nitems ? item : nitems - 1;
-    const int slot = it / nx, i = it % nx;
+    const int slot = it / rm.ns, ii = it % rm.ns, i = rm.xa + rm.xs * ii;
     const bool valid = item < nitems && i >= lo && i < hi;
     const int node = slot % nodes, vs = slot / nodes;
     const int vi = vidx ? vidx[vs] : vs;
     const size_t row = (size_t)node * nx + i;
-    const Cx<T>* tr = tmp + ((size_t)slot * trows + i) * (2 * L);
+    const Cx<T>* tr = tmp + ((size_t)slot * trows + ii) * (2 * L);
     Cx<T> acc[E], v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -498,7 +498,8 @@ template <int L>
 __global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_rows(const Cx<double>* __restrict__ ktab,
                                                                            int nx, int nz, int px,
                                                                            Cx<double>* __restrict__ s1t,
-                                                                           const Cx<double>* __restrict__ tw2) {
+                                                                           const Cx<double>* __restrict__ tw2,
+                                                                           int circ) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<double, L>() / G;
   __shared__ Cx<double> sbuf[GPW][2][lds_len<L>()];
@@ -511,7 +512,7 @@ __global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_rows(const
     const int p = base + grp;
     const bool valid = p < px;
     const int pp = valid ? p : px - 1;
-    const int lxp = pp < px - pp ? pp : px - pp;
+    const int lxp = (circ || pp < px - pp) ? pp : px - pp;
     Cx<double> a[E], b[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -537,12 +538,13 @@ __global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_rows(const
   }
 }
 
-// Column pass: full-length transform of s1t[c][0..px) -> gs[h][c][m] scaled.
+// Column pass: full-length transform of s1t[c][0..px) -> gs[h][c][m] scaled (the odd half h = 1 by
+// scale_odd).
 template <int L>
 __global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_cols(const Cx<double>* __restrict__ s1t,
                                                                            int pz, Cx<double>* __restrict__ gs64,
                                                                            Cx<float>* __restrict__ gs32,
-                                                                           double scale,
+                                                                           double scale, double scale_odd,
                                                                            const Cx<double>* __restrict__ tw2) {
   using P = FftPlan<L>;
   constexpr int G = P::G, E = P::E, GPW = rows_threads<double, L>() / G;
@@ -570,7 +572,7 @@ __global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_cols(const
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int m = fft_elem<L>(g, e);
-        const Cx<double> va = scale * a[e], vb = scale * b[e];
+        const Cx<double> va = scale * a[e], vb = scale_odd * b[e];
         if (gs64) {
           gs64[(size_t)cc * L + m] = va;
           gs64[((size_t)pz + cc) * L + m] = vb;
@@ -662,20 +664,28 @@ int grid_for_rows(int nitems, int gpw) {
     default: LSOP_DISPATCH_L(L, __VA_ARGS__);              \
   }
 
+// Resolves the defaults of a row map and checks that every row it visits lies in the strip and in tmp.
+static bool row_map_ok(RowMap& rm, int nx, int& trows) {
+  if (rm.ns < 0) rm.ns = nx;
+  if (trows < 0) trows = rm.ns;
+  if (rm.ns < 1 || trows < rm.ns || (rm.xs != 1 && rm.xs != -1)) return false;
+  const long last = (long)rm.xa + (long)rm.xs * (rm.ns - 1);
+  return rm.xa >= 0 && rm.xa < nx && last >= 0 && last < nx;
+}
+
 template <typename T>
 hipError_t launch_rows_fwd(int L, const Cx<T>* x, const T* chi, Cx<T>* tmp, const int* vidx, int nx, int nz,
                            int nslots, bool mulchi, const Cx<T>* tw2, hipStream_t s, int nodes, int lo, int hi,
-                           const Slot<T>* tab, int trows) {
-  const int nitems = nslots * nx;
-  if (nitems <= 0) return hipSuccess;
+                           const Slot<T>* tab, int trows, RowMap rm) {
+  if (nslots <= 0 || nx <= 0) return hipSuccess;
   if (nodes < 1 || nslots % nodes != 0 || (tab && (nodes != 1 || vidx))) return hipErrorInvalidValue;
+  if (!row_map_ok(rm, nx, trows)) return hipErrorInvalidValue;
   if (hi < 0) hi = nx;
-  if (trows < 0) trows = nx;
-  if (trows < nx) return hipErrorInvalidValue;
+  const int nitems = nslots * rm.ns;
   LSOP_DISPATCH_L(L, {
     constexpr int NT = rows_threads<T, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_rows_fwd<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(NT), 0, s, x, chi, tmp, vidx,
-                       nx, nz, nitems, (int)mulchi, tw2, nodes, lo, hi, tab, trows);
+                       nx, nz, nitems, (int)mulchi, tw2, nodes, lo, hi, tab, trows, rm);
   });
   return hipGetLastError();
 }
@@ -744,29 +754,29 @@ hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int n
 template <typename T>
 hipError_t launch_rows_inv(int L, const Cx<T>* tmp, const Cx<T>* x, const T* chi, const Cx<T>* rhs, Cx<T>* y,
                            double* rnorm, const int* vidx, int nx, int nz, int nslots, int epi, const Cx<T>* tw2,
-                           hipStream_t s, int nodes, int lo, int hi, const Slot<T>* tab, int trows) {
-  const int nitems = nslots * nx;
-  if (nitems <= 0) return hipSuccess;
+                           hipStream_t s, int nodes, int lo, int hi, const Slot<T>* tab, int trows, RowMap rm) {
+  if (nslots <= 0 || nx <= 0) return hipSuccess;
   if (nodes < 1 || nslots % nodes != 0 || (tab && (nodes != 1 || vidx))) return hipErrorInvalidValue;
+  if (!row_map_ok(rm, nx, trows)) return hipErrorInvalidValue;
   if (hi < 0) hi = nx;
-  if (trows < 0) trows = nx;
-  if (trows < nx) return hipErrorInvalidValue;
+  const int nitems = nslots * rm.ns;
   LSOP_DISPATCH_L(L, {
     constexpr int NT = rows_threads<T, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_rows_inv<T, LL>), dim3(grid_for_rows(nitems, GPW)), dim3(NT), 0, s, tmp, x, chi, rhs, y,
-                       rnorm, vidx, nx, nz, nitems, epi, tw2, nodes, lo, hi, tab, trows);
+                       rnorm, vidx, nx, nz, nitems, epi, tw2, nodes, lo, hi, tab, trows, rm);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_spectrum(int lx, int lz, const Cx<double>* ktab, int nx, int nz, Cx<double>* s1t,
                            Cx<double>* gs64, Cx<float>* gs32, const Cx<double>* tw2x, const Cx<double>* tw2z,
-                           hipStream_t s) {
+                           hipStream_t s, bool circ) {
   const int px = 2 * lx, pz = 2 * lz;
+  if (circ && nx < px) return hipErrorInvalidValue;  // every lag of the period must be in the table
   LSOP_DISPATCH_L(lz, {
     constexpr int NT = rows_threads<double, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_spec_rows<LL>), dim3(grid_for_rows(px, GPW)), dim3(NT), 0, s, ktab, nx, nz, px, s1t,
-                       tw2z);
+                       tw2z, (int)circ);
   });
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -774,7 +784,7 @@ hipError_t launch_spectrum(int lx, int lz, const Cx<double>* ktab, int nx, int n
   LSOP_DISPATCH_LX(lx, {
     constexpr int NT = rows_threads<double, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_spec_cols<LL>), dim3(grid_for_rows(pz, GPW)), dim3(NT), 0, s, s1t, pz, gs64, gs32, scale,
-                       tw2x);
+                       circ ? -scale : scale, tw2x);
   });
   return hipGetLastError();
 }
@@ -873,12 +883,12 @@ hipError_t launch_incident3(const Cx<double>* ktab, const int* src, const Cx<dou
 
 #define LSOP_INST(T)                                                                                               \
   template hipError_t launch_rows_fwd<T>(int, const Cx<T>*, const T*, Cx<T>*, const int*, int, int, int, bool,    \
-                                         const Cx<T>*, hipStream_t, int, int, int, const Slot<T>*, int);          \
+                                         const Cx<T>*, hipStream_t, int, int, int, const Slot<T>*, int, RowMap);  \
   template hipError_t launch_cols<T>(int, Cx<T>*, const Cx<T>*, int, int, int, bool, const Cx<T>*, hipStream_t,    \
                                      int, int*, const Slot<T>*);                                                  \
   template hipError_t launch_rows_inv<T>(int, const Cx<T>*, const Cx<T>*, const T*, const Cx<T>*, Cx<T>*,        \
                                          double*, const int*, int, int, int, int, const Cx<T>*, hipStream_t, int, \
-                                         int, int, const Slot<T>*, int);                                          \
+                                         int, int, const Slot<T>*, int, RowMap);                                  \
   template hipError_t launch_cols_half<T>(int, int, Cx<T>*, int, int, int, int, const Cx<T>*, hipStream_t);      \
   template hipError_t launch_incident3<T>(const Cx<double>*, const int*, const Cx<double>*, Cx<T>*, int, int,    \
                                           int, int, double, hipStream_t);                                         \
