@@ -132,9 +132,9 @@ hipError_t p_ah_b(const char* name, const Cx<T>* A, int na, const Cx<T>* B, cons
               [&] { return launch_reduce_parts(part, p, (size_t)na * nb, C, alpha, s); });
 }
 
-// Y = X1 + beta X2 + A M (segmented), profiled
-template <typename T>
-hipError_t p_update(const char* name, const Cx<T>* A, int na, const Cx<double>* M, size_t mstride, int nb,
+// Y = X1 + beta X2 + A M (segmented; M in MT), profiled
+template <typename T, typename MT = double>
+hipError_t p_update(const char* name, const Cx<T>* A, int na, const Cx<MT>* M, size_t mstride, int nb,
                     const Cx<T>* X1, const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n, size_t seg,
                     hipStream_t s) {
   if (nb <= 0) return hipSuccess;
@@ -143,10 +143,11 @@ hipError_t p_update(const char* name, const Cx<T>* A, int na, const Cx<double>* 
   const double nsegs = (seg == 0 || seg >= n) ? 1.0 : (double)((n + seg - 1) / seg);
   // the instantiation launch_gemm_update_seg picks
   const int nbt = nb > 32 ? 4 : 2, ga = nb > 32 ? 4 : 8, wpe = nb > 32 ? (sizeof(T) == 4 ? 6 : 3) : 0;
-  return prof(name, fn_name("k_gemm_update_mfma", tname<T>(), nbt, ga, wpe),
-              (double)na * n * e + vecs * nb * (double)n * e + nsegs * na * nb * sizeof(Cx<double>),
+  const std::string types = std::string(tname<T>()) + ", " + tname<MT>();
+  return prof(name, fn_name("k_gemm_update_mfma", types.c_str(), nbt, ga, wpe),
+              (double)na * n * e + vecs * nb * (double)n * e + nsegs * na * nb * sizeof(Cx<MT>),
               8.0 * na * nb * (double)n, nb, s,
-              [&] { return launch_gemm_update_seg<T>(A, na, M, mstride, nb, X1, X2, beta, Y, vidx, n, seg, s); });
+              [&] { return launch_gemm_update_seg<T, MT>(A, na, M, mstride, nb, X1, X2, beta, Y, vidx, n, seg, s); });
 }
 
 // batched C = alpha A B + beta C, profiled
@@ -895,13 +896,15 @@ int hodlr_apply(lsop_precond* pc, const Cx<T>* x, const int* xidx, Cx<T>* y, con
         LSOP_HIP(p_bgemm<float>("hodlr_core_apply", L.kinv32, 2 * r, (size_t)4 * r * r, pc->hG32, m,
                                 (size_t)2 * r * m, pc->hX32, m, (size_t)2 * r * m, nullptr, nullptr, 2 * r, m, 2 * r,
                                 1.0, 0.0, nodes, s));
-        LSOP_HIP(prof("hodlr_core_apply", "k_convert<double, float>", cnt * 24.0, 0.0, (double)cnt, s,
-                      [&] { return launch_convert<double, float>(pc->hX32, pc->hX, cnt, s); }));
+        // the update takes the cores' FP32 products as they are (an FP64 copy would hold the same values)
+        LSOP_HIP(p_update<T, float>("hodlr_apply_update", Wp, r, pc->hX32, (size_t)r * m, m, yb, nullptr, 0.0, yb, yc,
+                                    n, seg, s));
       } else {
         LSOP_HIP(p_bgemm<double>("hodlr_core_apply", L.kinv, 2 * r, (size_t)4 * r * r, pc->hG, m, (size_t)2 * r * m,
                                  pc->hX, m, (size_t)2 * r * m, nullptr, nullptr, 2 * r, m, 2 * r, 1.0, 0.0, nodes, s));
+        LSOP_HIP(p_update<T>("hodlr_apply_update", Wp, r, pc->hX, (size_t)r * m, m, yb, nullptr, 0.0, yb, yc, n, seg,
+                             s));
       }
-      LSOP_HIP(p_update<T>("hodlr_apply_update", Wp, r, pc->hX, (size_t)r * m, m, yb, nullptr, 0.0, yb, yc, n, seg, s));
     }
   }
   return LSOP_OK;

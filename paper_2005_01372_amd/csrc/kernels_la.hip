@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
 }
 
 // Y[vy(b)][k] = X1 + beta X2 + sum_a A[a][k] M[a][b] as out[b][k] = M^T A
-// (segmented form: M for element k is M + (k / seg) * mstride):
+// (segmented form: M for element k is M + (k / seg) * mstride; M in MT, FP64 or T, rounded to T in LDS):
 // each wave owns 16 consecutive k (coalesced B-operand loads and stores) and
 // up to NBT * 16 b (MFMA row tiles, real and imaginary chains); M is staged in
 // LDS GA rows (a) at a time; the A elements and the M rows of the next
@@ -333,10 +333,10 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
 // passes: 4-row blocks at 6 waves run 12% faster than 8-row blocks at the
 // default 4 waves, bit-identical; measured over na = 64-256, nb = 40-256;
 // complex double: 4-row blocks at 3 waves remove the 8-row form's spills).
-template <typename T, int NBT, int GA, int WPE>
+template <typename T, typename MT, int NBT, int GA, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void k_gemm_update_mfma(
     const Cx<T>* __restrict__ A, int na,
-                                                          const Cx<double>* __restrict__ Mm, int nb,
+                                                          const Cx<MT>* __restrict__ Mm, int nb,
                                                           const Cx<T>* X1, const Cx<T>* X2, T beta, Cx<T>* Y,
                                                           const int* __restrict__ vidx, size_t n, size_t seg,
                                                           size_t mstride) {
@@ -363,7 +363,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? W
     constexpr int PER = (GA * BW + 255) / 256;
     const int ab = kk >> 1;
     Cx<T> av[GA / 2];
-    Cx<double> mv[PER];
+    Cx<MT> mv[PER];
 #pragma unroll
     for (int st = 0; st < GA / 2; ++st) {
       const int a = ab + 2 * st;
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? W
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int idx = threadIdx.x + 256 * q, a = idx / BW, b = b0 + idx % BW;
-      mv[q] = (idx < GA * BW && a < na && b < nb) ? Mm[(size_t)a * nb + b] : czero<double>();
+      mv[q] = (idx < GA * BW && a < na && b < nb) ? Mm[(size_t)a * nb + b] : czero<MT>();
     }
     for (int a0 = 0; a0 < na; a0 += GA) {
       __syncthreads();
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? W
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
         const int idx = threadIdx.x + 256 * q, a = a0 + GA + idx / BW, b = b0 + idx % BW;
-        mv[q] = (idx < GA * BW && a < na && b < nb) ? Mm[(size_t)a * nb + b] : czero<double>();
+        mv[q] = (idx < GA * BW && a < na && b < nb) ? Mm[(size_t)a * nb + b] : czero<MT>();
       }
       Cx<T> cur[GA / 2];
 #pragma unroll
@@ -953,8 +953,8 @@ hipError_t launch_gemm_ah_b(const Cx<T>* A, int na, const Cx<T>* B, const int* v
   return launch_gemm_ah_b_seg<T>(A, na, B, vidx, nb, n, n, C, part, ksplit, s, 1.0);
 }
 
-template <typename T>
-hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<double>* M, size_t mstride, int nb,
+template <typename T, typename MT>
+hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<MT>* M, size_t mstride, int nb,
                                   const Cx<T>* X1, const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n,
                                   size_t seg, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
@@ -967,14 +967,14 @@ hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<double>* M, s
   const dim3 grid((unsigned)((n + 63) / 64));
   if (nb > 32) {
     if constexpr (sizeof(T) == 4)
-      hipLaunchKernelGGL((k_gemm_update_mfma<T, 4, 4, 6>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y,
-                         vidx, n, seg, mstride);
+      hipLaunchKernelGGL((k_gemm_update_mfma<T, MT, 4, 4, 6>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta,
+                         Y, vidx, n, seg, mstride);
     else
-      hipLaunchKernelGGL((k_gemm_update_mfma<T, 4, 4, 3>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y,
-                         vidx, n, seg, mstride);
+      hipLaunchKernelGGL((k_gemm_update_mfma<T, MT, 4, 4, 3>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta,
+                         Y, vidx, n, seg, mstride);
   } else {
-    hipLaunchKernelGGL((k_gemm_update_mfma<T, 2, 8, 0>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y, vidx,
-                       n, seg, mstride);
+    hipLaunchKernelGGL((k_gemm_update_mfma<T, MT, 2, 8, 0>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y,
+                       vidx, n, seg, mstride);
   }
   return hipGetLastError();
 }
@@ -982,7 +982,7 @@ hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<double>* M, s
 template <typename T>
 hipError_t launch_gemm_update(const Cx<T>* A, int na, const Cx<double>* M, int nb, const Cx<T>* X1,
                               const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n, hipStream_t s) {
-  return launch_gemm_update_seg<T>(A, na, M, 0, nb, X1, X2, beta, Y, vidx, n, n, s);
+  return launch_gemm_update_seg<T, double>(A, na, M, 0, nb, X1, X2, beta, Y, vidx, n, n, s);
 }
 
 hipError_t launch_gram_orth(const Cx<double>* G, Cx<double>* X, int na, double drop_tol, int* kept, hipStream_t s,
@@ -1115,9 +1115,9 @@ hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, 
                                                const GemmPlan&, Cx<double>*, hipStream_t);                          \
   template hipError_t launch_gemm_update<T>(const Cx<T>*, int, const Cx<double>*, int, const Cx<T>*, const Cx<T>*, \
                                             double, Cx<T>*, const int*, size_t, hipStream_t);                       \
-  template hipError_t launch_gemm_update_seg<T>(const Cx<T>*, int, const Cx<double>*, size_t, int, const Cx<T>*,   \
-                                                const Cx<T>*, double, Cx<T>*, const int*, size_t, size_t,          \
-                                                hipStream_t);                                                       \
+  template hipError_t launch_gemm_update_seg<T, double>(const Cx<T>*, int, const Cx<double>*, size_t, int,       \
+                                                        const Cx<T>*, const Cx<T>*, double, Cx<T>*, const int*,    \
+                                                        size_t, size_t, hipStream_t);                               \
   template hipError_t launch_transpose_convert<T>(const Cx<double>*, Cx<T>*, int, int, hipStream_t);               \
   template hipError_t launch_bgemm<T>(const Cx<T>*, size_t, size_t, const Cx<T>*, size_t, size_t, Cx<T>*, size_t,  \
                                       size_t, const int*, const int*, int, int, int, double, double, int,          \
@@ -1126,6 +1126,9 @@ hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, 
   template hipError_t launch_mask_slots<T>(const Slot<T>*, const int*, int, size_t, hipStream_t);
 LSOP_INST_LA(float)
 LSOP_INST_LA(double)
+template hipError_t launch_gemm_update_seg<float, float>(const Cx<float>*, int, const Cx<float>*, size_t, int,
+                                                         const Cx<float>*, const Cx<float>*, double, Cx<float>*,
+                                                         const int*, size_t, size_t, hipStream_t);
 template hipError_t launch_convert<float, double>(const Cx<double>*, Cx<float>*, size_t, hipStream_t);
 template hipError_t launch_convert<double, float>(const Cx<float>*, Cx<double>*, size_t, hipStream_t);
 
