@@ -113,10 +113,11 @@ int ksub_fill(size_t seg, int nseg, int na, int nb, int ksub, size_t part_cap) {
   return (int)std::max<size_t>(ksub, std::min(want, most));
 }
 
+// C32 != NULL: the products are written rounded to FP32 there instead of C.
 template <typename T>
 hipError_t p_ah_b(const char* name, const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n,
                   size_t seg, Cx<double>* C, Cx<double>* part, int ksub, hipStream_t s, double alpha = 1.0,
-                  size_t part_cap = 0) {
+                  size_t part_cap = 0, Cx<float>* C32 = nullptr) {
   if (na <= 0 || nb <= 0) return hipSuccess;
   {
     const size_t sg = (seg == 0 || seg > n) ? n : seg;
@@ -124,12 +125,16 @@ hipError_t p_ah_b(const char* name, const Cx<T>* A, int na, const Cx<T>* B, cons
   }
   const GemmPlan p = gemm_ah_b_plan(n, seg, ksub);
   const double e = sizeof(Cx<T>), nab = (double)na * nb * sizeof(Cx<double>), parts = (double)p.nseg * p.ksub;
-  hipError_t err = prof(name, fn_name("k_gemm_ah_b_mfma", tname<T>()), (double)(na + nb) * n * e + parts * nab,
-                        8.0 * na * nb * (double)n, nb, s,
-                        [&] { return launch_gemm_ah_b_part<T>(A, na, B, vidx, nb, n, p, part, s); });
-  if (err != hipSuccess) return err;
-  return prof(name, "k_reduce_parts", (parts + p.nseg) * nab, 2.0 * parts * na * nb, nb, s,
-              [&] { return launch_reduce_parts(part, p, (size_t)na * nb, C, alpha, s); });
+  // FP32 results from one chunk per segment: the products themselves, no reduction launch
+  const bool direct = C32 && p.ksub == 1 && alpha == 1.0;
+  hipError_t err = prof(name, fn_name("k_gemm_ah_b_mfma", tname<T>()),
+                        (double)(na + nb) * n * e + (direct ? 0.5 : 1.0) * parts * nab, 8.0 * na * nb * (double)n, nb,
+                        s, [&] {
+                          return launch_gemm_ah_b_part<T>(A, na, B, vidx, nb, n, p, part, s, direct ? C32 : nullptr);
+                        });
+  if (err != hipSuccess || direct) return err;
+  return prof(name, "k_reduce_parts", (parts + (C32 ? 0.5 : 1.0) * p.nseg) * nab, 2.0 * parts * na * nb, nb, s,
+              [&] { return launch_reduce_parts(part, p, (size_t)na * nb, C, alpha, s, C32); });
 }
 
 // Y = X1 + beta X2 + A M (segmented; M in MT), profiled
@@ -886,13 +891,12 @@ int hodlr_apply(lsop_precond* pc, const Cx<T>* x, const int* xidx, Cx<T>* y, con
       const int ksub = hodlr_ksub(pc, seg, nseg);
       const Cx<T>* V = reinterpret_cast<const Cx<T>*>(L.V);
       const Cx<T>* Wp = reinterpret_cast<const Cx<T>*>(L.Wp);
-      LSOP_HIP(p_ah_b<T>("hodlr_apply_ah_b", V, r, yb, yc, m, n, seg, pc->hG, pc->part, ksub, s, 1.0, pc->part_cap));
       if constexpr (std::is_same<T, float>::value) {
         // the update rounds the core's output to FP32 anyway: the core product runs on the fp32 matrix cores
-        // (K^{-1} inverted in FP64, applied from its FP32 copy)
-        const size_t cnt = (size_t)nseg * r * m;
-        LSOP_HIP(prof("hodlr_core_apply", "k_convert<float, double>", cnt * 24.0, 0.0, (double)cnt, s,
-                      [&] { return launch_convert<float, double>(pc->hG, pc->hG32, cnt, s); }));
+        // (K^{-1} inverted in FP64, applied from its FP32 copy) on the inner products summed in FP64 and rounded
+        // to FP32 by their reduction
+        LSOP_HIP(p_ah_b<T>("hodlr_apply_ah_b", V, r, yb, yc, m, n, seg, pc->hG, pc->part, ksub, s, 1.0,
+                           pc->part_cap, pc->hG32));
         LSOP_HIP(p_bgemm<float>("hodlr_core_apply", L.kinv32, 2 * r, (size_t)4 * r * r, pc->hG32, m,
                                 (size_t)2 * r * m, pc->hX32, m, (size_t)2 * r * m, nullptr, nullptr, 2 * r, m, 2 * r,
                                 1.0, 0.0, nodes, s));
@@ -900,6 +904,8 @@ int hodlr_apply(lsop_precond* pc, const Cx<T>* x, const int* xidx, Cx<T>* y, con
         LSOP_HIP(p_update<T, float>("hodlr_apply_update", Wp, r, pc->hX32, (size_t)r * m, m, yb, nullptr, 0.0, yb, yc,
                                     n, seg, s));
       } else {
+        LSOP_HIP(p_ah_b<T>("hodlr_apply_ah_b", V, r, yb, yc, m, n, seg, pc->hG, pc->part, ksub, s, 1.0,
+                           pc->part_cap));
         LSOP_HIP(p_bgemm<double>("hodlr_core_apply", L.kinv, 2 * r, (size_t)4 * r * r, pc->hG, m, (size_t)2 * r * m,
                                  pc->hX, m, (size_t)2 * r * m, nullptr, nullptr, 2 * r, m, 2 * r, 1.0, 0.0, nodes, s));
         LSOP_HIP(p_update<T>("hodlr_apply_update", Wp, r, pc->hX, (size_t)r * m, m, yb, nullptr, 0.0, yb, yc, n, seg,

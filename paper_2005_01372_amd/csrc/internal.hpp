@@ -140,11 +140,14 @@ struct GemmPlan {
 };
 GemmPlan gemm_ah_b_plan(size_t n, size_t seg, int ksub);
 // the two launches of the segmented product: partials (nseg * ksub * na * nb) and their reduction
+// out32 != NULL (plans of one chunk per segment only): the products are written rounded to FP32 there, in
+// the layout of the reduced result, instead of the partials.
 template <typename T>
 hipError_t launch_gemm_ah_b_part(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n,
-                                 const GemmPlan& p, Cx<double>* part, hipStream_t s);
+                                 const GemmPlan& p, Cx<double>* part, hipStream_t s, Cx<float>* out32 = nullptr);
+// C32 != NULL: the sums are written rounded to FP32 there (C unused).
 hipError_t launch_reduce_parts(const Cx<double>* part, const GemmPlan& p, size_t count, Cx<double>* C, double alpha,
-                               hipStream_t s);
+                               hipStream_t s, Cx<float>* C32 = nullptr);
 // Segmented form: one na x nb result per segment of `seg` elements of k, at
 // C + sg * na * nb; each segment split into ksub partial chunks (part holds
 // nseg * ksub * na * nb complex doubles).

@@ -140,8 +140,10 @@ __global__ void k_philox_normal(Cx<T>* __restrict__ out, size_t n, uint64_t seed
 
 // ---------------------------------------------------------- C = A^H B (split over n)
 // C[sg][k] = alpha * sum over the ksub partials of segment sg (part[sg * ksub + p][k]).
+// C = alpha * (sum of the ksub partials) per segment; with C32 != NULL the FP64 sum is written rounded to FP32
+// there instead.
 __global__ void k_reduce_parts(const Cx<double>* __restrict__ part, int ksub, int nseg, size_t count,
-                               Cx<double>* __restrict__ C, double alpha) {
+                               Cx<double>* __restrict__ C, double alpha, Cx<float>* __restrict__ C32) {
   const size_t total = count * nseg;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
@@ -149,7 +151,8 @@ __global__ void k_reduce_parts(const Cx<double>* __restrict__ part, int ksub, in
     const Cx<double>* p0 = part + sg * ksub * count + k;
     Cx<double> s = czero<double>();
     for (int p = 0; p < ksub; ++p) s = s + p0[(size_t)p * count];
-    C[idx] = alpha * s;
+    if (C32) C32[idx] = ccast<float>(alpha * s);
+    else C[idx] = alpha * s;
   }
 }
 
@@ -217,7 +220,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict__ A, int na,
                                                         const Cx<T>* __restrict__ B, const int* __restrict__ vidx,
                                                         int nb, size_t n, size_t seg, size_t chunk, int ksub,
-                                                        Cx<double>* __restrict__ part) {
+                                                        Cx<double>* __restrict__ part,
+                                                        Cx<float>* __restrict__ out32) {
   using M = Mfma<T>;
   // reals per LDS row: an even stride, so that (re, im) pairs are stored and read as one aligned pair (the 16
   // row offsets 34 c mod 64 banks are still distinct)
@@ -308,7 +312,9 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
     }
     __syncthreads();
   }
+  // one chunk per segment with out32: the partial is the product, written rounded to FP32
   Cx<double>* p = part + (size_t)ks * na * nb;
+  Cx<float>* p32 = out32 ? out32 + (size_t)ks * na * nb : nullptr;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -317,7 +323,10 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
       for (int r = 0; r < 4; ++r) {
         const int a = a0 + wa + i * 16 + M::row(l, r);
         const int b = b0 + wb + j * 16 + c16;
-        if (a < na && b < nb) p[(size_t)a * nb + b] = Cx<double>{(double)cre[i][j][r], (double)cim[i][j][r]};
+        if (a < na && b < nb) {
+          if (out32) p32[(size_t)a * nb + b] = Cx<float>{(float)cre[i][j][r], (float)cim[i][j][r]};
+          else p[(size_t)a * nb + b] = Cx<double>{(double)cre[i][j][r], (double)cim[i][j][r]};
+        }
       }
 }
 
@@ -921,19 +930,20 @@ GemmPlan gemm_ah_b_plan(size_t n, size_t seg, int ksub) {
 
 template <typename T>
 hipError_t launch_gemm_ah_b_part(const Cx<T>* A, int na, const Cx<T>* B, const int* vidx, int nb, size_t n,
-                                 const GemmPlan& p, Cx<double>* part, hipStream_t s) {
+                                 const GemmPlan& p, Cx<double>* part, hipStream_t s, Cx<float>* out32) {
   if (na <= 0 || nb <= 0) return hipSuccess;
+  if (out32 && p.ksub != 1) return hipErrorInvalidValue;
   dim3 grid((na + GM_T - 1) / GM_T, (nb + GM_T - 1) / GM_T, (unsigned)(p.nseg * p.ksub));
   hipLaunchKernelGGL((k_gemm_ah_b_mfma<T>), grid, dim3(256), 0, s, A, na, B, vidx, nb, n, p.seg, p.chunk, p.ksub,
-                     part);
+                     part, out32);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_parts(const Cx<double>* part, const GemmPlan& p, size_t count, Cx<double>* C, double alpha,
-                               hipStream_t s) {
+                               hipStream_t s, Cx<float>* C32) {
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_parts, dim3(grid1(count * p.nseg, 2048)), dim3(256), 0, s, part, p.ksub, p.nseg, count,
-                     C, alpha);
+                     C, alpha, C32);
   return hipGetLastError();
 }
 
@@ -1112,7 +1122,7 @@ hipError_t launch_axpy_map(const Cx<T>* x, Cx<T>* y, const int* yidx, double a, 
   template hipError_t launch_gemm_ah_b_seg<T>(const Cx<T>*, int, const Cx<T>*, const int*, int, size_t, size_t,     \
                                               Cx<double>*, Cx<double>*, int, hipStream_t, double);                  \
   template hipError_t launch_gemm_ah_b_part<T>(const Cx<T>*, int, const Cx<T>*, const int*, int, size_t,            \
-                                               const GemmPlan&, Cx<double>*, hipStream_t);                          \
+                                               const GemmPlan&, Cx<double>*, hipStream_t, Cx<float>*);              \
   template hipError_t launch_gemm_update<T>(const Cx<T>*, int, const Cx<double>*, int, const Cx<T>*, const Cx<T>*, \
                                             double, Cx<T>*, const int*, size_t, hipStream_t);                       \
   template hipError_t launch_gemm_update_seg<T, double>(const Cx<T>*, int, const Cx<double>*, size_t, int,       \
