@@ -146,10 +146,12 @@ hipError_t p_update(const char* name, const Cx<T>* A, int na, const Cx<MT>* M, s
   const double e = sizeof(Cx<T>);
   const double vecs = 1.0 + (X1 ? 1.0 : 0.0) + (X2 ? 1.0 : 0.0);
   const double nsegs = (seg == 0 || seg >= n) ? 1.0 : (double)((n + seg - 1) / seg);
-  // the instantiation launch_gemm_update_seg picks
+  // the kernel launch_gemm_update_seg picks
   const int nbt = nb > 32 ? 4 : 2, ga = nb > 32 ? 4 : 8, wpe = nb > 32 ? (sizeof(T) == 4 ? 6 : 3) : 0;
   const std::string types = std::string(tname<T>()) + ", " + tname<MT>();
-  return prof(name, fn_name("k_gemm_update_mfma", types.c_str(), nbt, ga, wpe),
+  const std::string kname = (sizeof(T) == 4 && nb > 32) ? fn_name("k_gemm_update_tile", tname<MT>())
+                                                         : fn_name("k_gemm_update_mfma", types.c_str(), nbt, ga, wpe);
+  return prof(name, kname,
               (double)na * n * e + vecs * nb * (double)n * e + nsegs * na * nb * sizeof(Cx<MT>),
               8.0 * na * nb * (double)n, nb, s,
               [&] { return launch_gemm_update_seg<T, MT>(A, na, M, mstride, nb, X1, X2, beta, Y, vidx, n, seg, s); });

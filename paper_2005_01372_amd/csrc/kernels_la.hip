@@ -434,6 +434,123 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? W
   }
 }
 
+// GEMM-tile form of the same update for complex float and nb > 32: a workgroup owns a 64 (b) x 64 (k) tile of Y
+// (four waves of 32 x 32 = 2 x 2 MFMA tiles, real and imaginary chains); M (rounded to FP32) and A are both
+// staged in LDS 16 complex a at a time, the next stage loaded into registers while the current stage's MFMAs
+// run, so a barrier pair covers 64 MFMAs per wave (the per-wave form above: 16).  The tiles of one 64-element k
+// range follow each other on one XCD, so A's re-reads by its b tiles are L2 hits.  LDS rows of 80 complex put
+// the two a rows an MFMA operand spans 32 banks apart.  Measured at n = 1M (standalone, against the form above):
+// na = 256, nb = 128-256 with FP32 M at 6 waves per SIMD 108 -> 118 TFLOP/s; na = 64-192, nb = 64 with FP64 M
+// (no occupancy hint; 6 waves is slower there) 76 -> 86 and 97 -> 110 TFLOP/s.  Results equal the per-wave
+// form's to FP32 rounding (summation order).
+constexpr int UPD_T = 64, UPD_K = 16, UPD_ROW = UPD_T + 16;
+template <typename MT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) == 4 ? 6 : 1))) void
+k_gemm_update_tile(const Cx<float>* __restrict__ A, int na, const Cx<MT>* __restrict__ Mm, int nb,
+                   const Cx<float>* X1, const Cx<float>* X2, float beta, Cx<float>* Y,
+                   const int* __restrict__ vidx, size_t n, size_t seg, size_t mstride) {
+  using MF = Mfma<float>;
+  __shared__ Cx<float> sm[UPD_K * UPD_ROW];
+  __shared__ Cx<float> sx[UPD_K * UPD_ROW];
+  const int nbt = (nb + UPD_T - 1) / UPD_T;
+  const size_t lid = xcd_block(blockIdx.x, gridDim.x);
+  const size_t k0 = (lid / nbt) * UPD_T;
+  const int b0 = (int)(lid % nbt) * UPD_T;
+  Mm += (k0 / seg) * mstride;  // the tile's 64 elements lie in one segment (seg % 64 == 0)
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wb = (w >> 1) * 32, wk = (w & 1) * 32;
+  // loader: thread t -> stage row t / 16, four consecutive columns (t % 16) * 4
+  const int la = threadIdx.x >> 4, lc = (threadIdx.x & 15) * 4;
+  // operand lanes: kk = l / 16 is the real k index of the MFMA (part p of complex a = 2 st + kk / 2)
+  const int kk = l >> 4, c16 = l & 15, p = kk & 1, ah = kk >> 1;
+  typename MF::acc cre[2][2], cim[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cre[i][j] = typename MF::acc{0, 0, 0, 0};
+      cim[i][j] = typename MF::acc{0, 0, 0, 0};
+    }
+  Cx<MT> vm[4];
+  Cx<float> vx[4];
+  const bool vec = (n & 1) == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 && k0 + UPD_T <= n;
+  auto load = [&](int a0) {
+    const int a = a0 + la;
+    const bool ain = a < na;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int b = b0 + lc + q;
+      vm[q] = (ain && b < nb) ? Mm[(size_t)a * nb + b] : czero<MT>();
+    }
+    if (vec) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float4 x = ain ? *reinterpret_cast<const float4*>(A + (size_t)a * n + k0 + lc + 2 * h)
+                             : float4{0.f, 0.f, 0.f, 0.f};
+        vx[2 * h] = Cx<float>{x.x, x.y};
+        vx[2 * h + 1] = Cx<float>{x.z, x.w};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const size_t k = k0 + lc + q;
+        vx[q] = (ain && k < n) ? A[(size_t)a * n + k] : czero<float>();
+      }
+    }
+  };
+  load(0);
+  for (int a0 = 0; a0 < na; a0 += UPD_K) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sm[la * UPD_ROW + lc + q] = ccast<float>(vm[q]);
+      sx[la * UPD_ROW + lc + q] = vx[q];
+    }
+    __syncthreads();
+    if (a0 + UPD_K < na) load(a0 + UPD_K);
+#pragma unroll
+    for (int st = 0; st < UPD_K / 2; ++st) {
+      // out = m a: re = (mr, mi) . (ar, -ai), im = (mr, mi) . (ai, ar) over the interleaved parts
+      const int ar = 2 * st + ah;
+      float mo[2], bre[2], bim[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const Cx<float> m = sm[ar * UPD_ROW + wb + i * 16 + c16];
+        mo[i] = p ? m.im : m.re;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const Cx<float> x = sx[ar * UPD_ROW + wk + j * 16 + c16];
+        bre[j] = p ? -x.im : x.re;
+        bim[j] = p ? x.re : x.im;
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cre[i][j] = MF::mma(mo[i], bre[j], cre[i][j]);
+          cim[i][j] = MF::mma(mo[i], bim[j], cim[i][j]);
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int b = b0 + wb + i * 16 + MF::row(l, r);
+        const size_t k = k0 + wk + j * 16 + c16;
+        if (b < nb && k < n) {
+          const size_t off = (size_t)(vidx ? vidx[b] : b) * n + k;
+          Cx<float> out{cre[i][j][r], cim[i][j][r]};
+          if (X1) out = out + X1[off];
+          if (X2) out = out + beta * X2[off];
+          Y[off] = out;
+        }
+      }
+}
+
 // ------------------------------------------------------- small FP64 kernels
 // Orthonormalising coefficients X (na x na, na <= 64) for Q = Y X from the
 // Gram matrix G = Y^H Y: X = R^{-1} with G = R^H R (Cholesky), so that
@@ -976,10 +1093,11 @@ hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<MT>* M, size_
   }
   const dim3 grid((unsigned)((n + 63) / 64));
   if (nb > 32) {
-    if constexpr (sizeof(T) == 4)
-      hipLaunchKernelGGL((k_gemm_update_mfma<T, MT, 4, 4, 6>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta,
-                         Y, vidx, n, seg, mstride);
-    else
+    if constexpr (sizeof(T) == 4) {
+      const size_t tiles = ((n + UPD_T - 1) / UPD_T) * (size_t)((nb + UPD_T - 1) / UPD_T);
+      hipLaunchKernelGGL((k_gemm_update_tile<MT>), dim3((unsigned)tiles), dim3(256), 0, s, A, na, M, nb, X1, X2,
+                         (T)beta, Y, vidx, n, seg, mstride);
+    } else
       hipLaunchKernelGGL((k_gemm_update_mfma<T, MT, 4, 4, 3>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta,
                          Y, vidx, n, seg, mstride);
   } else {
