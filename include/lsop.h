@@ -31,6 +31,14 @@
  *    and series calls then allocate no device memory.  Batches and the
  *    network keep library-owned memory.  A handle must not be used from two
  *    streams at once.
+ *  - Environment (read when a handle is created; each selects between forms
+ *    that compute the same result, for tests and measurements):
+ *    LSOP_COL_TILE=c               column-pass tile width of new operators
+ *                                  (as lsop_autotune would set it);
+ *    LSOP_HODLR_LEAF_CHUNK=k       HODLR leaves inverted k at a time;
+ *    LSOP_HODLR_PADDED_SAMPLING=1  HODLR sampling convolutions at the
+ *                                  zero-padded period 2W on every level
+ *                                  instead of the node-width period W.
  */
 #ifndef LSOP_H
 #define LSOP_H
