@@ -463,7 +463,7 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
     }
     for (int pass = 0; pass < passes; ++pass) {
       const Cx<T>* src = pass == 0 ? Yb : Qb;
-      Cx<T>* dst = pass == 0 ? Qb : Yb;
+      Cx<T>* dst = Qb;  // the second pass updates the first pass's basis in place (kb <= 64 vectors)
       LSOP_HIP(p_ah_b<T>("orth_gram", src, kb, src, nullptr, kb, n, seg, G, part, ksub, s, 1.0, part_cap));
       LSOP_HIP(prof("orth_coeffs", "k_gram_orth_lds", 2.0 * nseg * kb * kb * sizeof(Cx<double>),
                     8.0 / 3.0 * kb * kb * (double)kb * nseg, nseg, s, [&] {
@@ -473,7 +473,6 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
       LSOP_HIP(p_update<T>("orth_update", src, kb, X, (size_t)kb * kb, kb, nullptr, nullptr, 0.0, dst, nullptr, n, seg,
                            s));
     }
-    if (passes == 2) LSOP_HIP(hipMemcpyAsync(Qb, Yb, sizeof(Cx<T>) * (size_t)kb * n, hipMemcpyDeviceToDevice, s));
   }
   return LSOP_OK;
 }

@@ -161,6 +161,7 @@ hipError_t launch_gemm_update(const Cx<T>* A, int na, const Cx<double>* M, int n
                               const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n, hipStream_t s);
 // Segmented form: element k uses M + (k / seg) * mstride; seg must be a multiple of 64.  M in MT: FP64, or
 // FP32 for complex-float T (coefficients that are FP32 values already, as the cores' FP32 products are).
+// Y may be A itself (in place) when na == nb <= 64.
 template <typename T, typename MT>
 hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<MT>* M, size_t mstride, int nb,
                                   const Cx<T>* X1, const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n,

@@ -344,7 +344,7 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
 // complex double: 4-row blocks at 3 waves remove the 8-row form's spills).
 template <typename T, typename MT, int NBT, int GA, int WPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? WPE : 1))) void k_gemm_update_mfma(
-    const Cx<T>* __restrict__ A, int na,
+    const Cx<T>* A, int na,
                                                           const Cx<MT>* __restrict__ Mm, int nb,
                                                           const Cx<T>* X1, const Cx<T>* X2, T beta, Cx<T>* Y,
                                                           const int* __restrict__ vidx, size_t n, size_t seg,
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? W
 constexpr int UPD_T = 64, UPD_K = 16, UPD_ROW = UPD_T + 16;
 template <typename MT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) == 4 ? 6 : 1))) void
-k_gemm_update_tile(const Cx<float>* __restrict__ A, int na, const Cx<MT>* __restrict__ Mm, int nb,
+k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, int nb,
                    const Cx<float>* X1, const Cx<float>* X2, float beta, Cx<float>* Y,
                    const int* __restrict__ vidx, size_t n, size_t seg, size_t mstride) {
   using MF = Mfma<float>;
@@ -1085,6 +1085,10 @@ hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<MT>* M, size_
                                   const Cx<T>* X1, const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n,
                                   size_t seg, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
+  // Y may be A itself when nb <= 64: then every workgroup covers all vectors of its k range in one pass and
+  // reads all of that range's rows of A (before its last barrier) before it writes any of them
+  if (static_cast<const void*>(Y) == static_cast<const void*>(A) && (nb > 64 || na != nb))
+    return hipErrorInvalidValue;
   if (seg == 0 || seg >= n) {
     seg = n;
     mstride = 0;
