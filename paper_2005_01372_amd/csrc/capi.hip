@@ -707,7 +707,7 @@ int hodlr_subconv(lsop_precond* pc, int lv, bool adj, const Cx<T>* x, Cx<T>* y, 
       int used = 0;
       hipError_t er = launch_cols<T>(L.lx, tmp, lev_gs<T>(L), rows, op->pz(), m * nodes, adj, lev_tw<T>(L), s, 0,
                                      &used);
-      fcol = fn_name("k_cols", tname<T>(), L.lx, used);
+      fcol = L.lx == 1 ? fn_name("k_cols_len1", tname<T>()) : fn_name("k_cols", tname<T>(), L.lx, used);
       return er;
     }));
     LSOP_HIP(prof("hodlr_rows_inv", fn_name("k_rows_inv", tname<T>(), op->lz), m * (np * e + 0.5 * nn * e), 0.0, m, s,
@@ -2370,9 +2370,10 @@ int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
       hodlr_level& L = pc->lev[lv];
       L.width = op->nx >> lv;
       // between the two halves of a node only the x-lags 1 .. width - 1 occur, so a circular convolution of
-      // period width (x-transform pair of length width / 2) is exact where that length is one the FFT engine has
+      // period width (x-transform pair of length width / 2) is exact where that length is one the FFT engine has,
+      // or 1 (width 2: no transform, one spectrum factor per z-frequency)
       const int h = L.width / 2;
-      L.half = L.width % 2 == 0 && h >= 2 && fft_length_sub(h) == h && !padded_sampling;
+      L.half = L.width % 2 == 0 && h >= 1 && (h == 1 || fft_length_sub(h) == h) && !padded_sampling;
       L.lx = L.half ? h : fft_length_sub(L.width);
     }
   }

@@ -270,6 +270,19 @@ __global__ __launch_bounds__(C * FftPlan<L>::G) void k_cols(Cx<T>* __restrict__ 
   tile_out<T, C, NT>(tb, pz, tile, ST, nx);
 }
 
+// Column pass of length 1 (the circular x-period 2 of sub-domain convolutions between half-nodes of one column):
+// the length-1 transforms are the identity and the twiddle of the even/odd recombination is 1, so every column
+// of a slot's single row is multiplied by s0 + s1 (by conj(s0 + s1) for the adjoint).
+template <typename T>
+__global__ void k_cols_len1(Cx<T>* __restrict__ tmp, const Cx<T>* __restrict__ gs, int pz, size_t total, int adj) {
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx % pz);
+    const Cx<T> f = gs[c] + gs[pz + c];
+    tmp[idx] = adj ? cmul_conj(f, tmp[idx]) : f * tmp[idx];
+  }
+}
+
 // Forward-only (DIR 0) and inverse-only (DIR 1) column transforms: the y passes of the 3D operator and the
 // spectrum set-up.  Slot s holds a [rows_slot][pz] array; a workgroup owns C adjacent columns as in k_cols.
 // DIR 0: rows i < nrow are the input (the rest of the padded axis is zero); the length-2L transform is written
@@ -538,6 +551,23 @@ __global__ __launch_bounds__((rows_threads<double, L>())) void k_spec_rows(const
   }
 }
 
+// Length-2 x-transform of s1t[c][0..2) -> gs[h][c] (lx = 1): the sum and the difference of the two positions.
+__global__ void k_spec_len1(const Cx<double>* __restrict__ s1t, int pz, Cx<double>* __restrict__ gs64,
+                            Cx<float>* __restrict__ gs32, double scale, double scale_odd) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < pz; c += gridDim.x * blockDim.x) {
+    const Cx<double> k1 = s1t[2 * (size_t)c], k2 = s1t[2 * (size_t)c + 1];
+    const Cx<double> va = scale * (k1 + k2), vb = scale_odd * (k1 - k2);
+    if (gs64) {
+      gs64[c] = va;
+      gs64[pz + c] = vb;
+    }
+    if (gs32) {
+      gs32[c] = ccast<float>(va);
+      gs32[pz + c] = ccast<float>(vb);
+    }
+  }
+}
+
 // Column pass: full-length transform of s1t[c][0..px) -> gs[h][c][m] scaled (the odd half h = 1 by
 // scale_odd).
 template <int L>
@@ -697,6 +727,15 @@ hipError_t launch_cols(int L, Cx<T>* tmp, const Cx<T>* gs, int nx, int pz, int n
                        hipStream_t s, int tile, int* used, const Slot<T>* tab) {
   if (nslots <= 0) return hipSuccess;
   if (pz % 16 != 0) return hipErrorInvalidValue;  // tile groups of one 128-byte line must divide the row
+  if (L == 1) {  // one row per slot, no transform
+    if (nx != 1 || tab) return hipErrorInvalidValue;
+    if (used) *used = 0;
+    const size_t total = (size_t)nslots * pz;
+    size_t grid = (total + 255) / 256;
+    if (grid > 16384) grid = 16384;
+    hipLaunchKernelGGL((k_cols_len1<T>), dim3((unsigned)grid), dim3(256), 0, s, tmp, gs, pz, total, (int)adj);
+    return hipGetLastError();
+  }
   LSOP_DISPATCH_LX(L, {
     constexpr int CMAX = ColTile<T, LL>::C;
     int C = (tile > 0 && tile < CMAX) ? tile : CMAX;
@@ -781,6 +820,11 @@ hipError_t launch_spectrum(int lx, int lz, const Cx<double>* ktab, int nx, int n
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const double scale = 1.0 / ((double)px * (double)pz);
+  if (lx == 1) {
+    hipLaunchKernelGGL(k_spec_len1, dim3((pz + 255) / 256), dim3(256), 0, s, s1t, pz, gs64, gs32, scale,
+                       circ ? -scale : scale);
+    return hipGetLastError();
+  }
   LSOP_DISPATCH_LX(lx, {
     constexpr int NT = rows_threads<double, LL>(), GPW = NT / FftPlan<LL>::G;
     hipLaunchKernelGGL((k_spec_cols<LL>), dim3(grid_for_rows(pz, GPW)), dim3(NT), 0, s, s1t, pz, gs64, gs32, scale,

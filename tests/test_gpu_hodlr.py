@@ -41,8 +41,12 @@ def probe_rows(levels, r, n, seed):
 
 
 @pytest.mark.parametrize("dtype,levels,r,q,tol", [(lsop.C128, 2, 12, 0, 1e-10), (lsop.C128, 5, 8, 0, 1e-10),
-                                                  (lsop.C128, 6, 6, 0, 1e-10), (lsop.C128, 3, 10, 1, 1e-10)])
+                                                  (lsop.C128, 6, 6, 0, 1e-10), (lsop.C128, 3, 10, 1, 1e-10),
+                                                  (lsop.C128, 6, 6, 1, 1e-10)])
 def test_hodlr_apply_matches_oracle(dtype, levels, r, q, tol):
+    """H x against the oracle's nested solve of the same probe rows.  Six levels on the 64^2 grid reach nodes of
+    width 2, whose half-node convolutions have a circular x-period of 2 (no x-transform: one spectrum factor per
+    z-frequency), with (q = 1) and without power iterations."""
     announce(f"hodlr apply dtype={dtype} levels={levels} r={r} q={q}")
     w = layered(64)
     prob = O.Problem(w.vel, w.h, w.freq, w.c0)
