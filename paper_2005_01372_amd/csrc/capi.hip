@@ -2353,15 +2353,23 @@ int pc_plan(lsop_op* op, const lsop_precond_params* p, lsop_precond* pc) {
     const int nl = pc->leaf_w * op->nz;
     pc->maxseg = pc->nleaf;
     pc->ksub_cap = std::max(512, pc->maxseg);
-    // FP64 leaf workspace: up to 2 GiB of leaf matrices per chunk plus the recursion temporaries
-    const size_t per_leaf = (size_t)nl * nl * sizeof(Cx<double>);
-    pc->leaf_chunk = (int)std::max<size_t>(1, std::min<size_t>(pc->nleaf, ((size_t)2 << 30) / per_leaf));
+    // leaf workspace, in the leaves' precision (FP32 for complex-FP32 preconditioners): up to 16 GiB of leaf
+    // matrices and recursion temporaries per chunk.  Chunks are inverted one after the other, and every launch of
+    // the recursion covers the whole chunk: 1024 one-column leaves of 1024 cells at complex FP32 (13.7 GB) take
+    // one chunk, so the 64 x 64 base factorisations run 1024 workgroups per launch (128 with 128-leaf chunks,
+    // half the CUs idle).
+    const size_t esz_leaf = pc->dt == LSOP_C64 ? sizeof(Cx<float>) : sizeof(Cx<double>);
+    size_t tmp1 = 0;
+    (void)block_inverse_temps(nl, 1, &tmp1);
+    const size_t per_leaf = ((size_t)nl * nl + tmp1) * esz_leaf;
+    pc->leaf_chunk = (int)std::max<size_t>(1, std::min<size_t>(pc->nleaf, ((size_t)16 << 30) / per_leaf));
     if (const char* lc = getenv("LSOP_HODLR_LEAF_CHUNK"))  // smaller chunks (exercises the chunked leaf build)
       pc->leaf_chunk = std::max(1, std::min(pc->leaf_chunk, atoi(lc)));
     size_t lw = 0;
     (void)block_inverse_temps(nl, pc->leaf_chunk, &lw);
     lw += (size_t)pc->leaf_chunk * nl * nl;
-    pc->lwork_elems = lw;
+    // allocated in complex-double units
+    pc->lwork_elems = (lw * esz_leaf + sizeof(Cx<double>) - 1) / sizeof(Cx<double>);
     pc->lev.resize(levels);
     // the zero-padded sampling form on every level (both forms give the same samples; compared in tests)
     const char* pad_env = getenv("LSOP_HODLR_PADDED_SAMPLING");
