@@ -694,6 +694,7 @@ def main():
         statuses[i.status_name] = statuses.get(i.status_name, 0) + 1
     iters = [i.iters for i in info]
     col_tile, pc_bytes = op.info().col_tile, pc.info()[2]
+    op_lx, op_lz = op.info().lx, op.info().lz
 
     # the plain FP64 series on the same GPU (untimed): its own solves/s, and every timed solution's relative
     # error against it
@@ -746,6 +747,24 @@ def main():
     fft_ms = sum(by_use[k]["ms"] for k in passes)
     fft_gbps = fft_bytes / (fft_ms / 1e3) / 1e9 if fft_ms > 0 else None
     vec_applies = by_use["lsop_cols"]["items"] if "lsop_cols" in by_use else 0
+    # the same passes against the compulsory bytes (each vector read and written once: 2 N^2 e) and the
+    # counter-measured bytes (each pass's algorithmic bytes times its kernel's measured ratio, when the committed
+    # counters were taken on the current sources)
+    fft_conv = None
+    if fft_ms > 0:
+        e = {"c64": 8, "c128": 16}.get(args.dtype)
+        t = "float" if args.dtype == "c64" else "double"
+        names = {"lsop_rows_fwd": f"k_rows_fwd<{t}, {op_lz}>", "lsop_cols": f"k_cols<{t}, {op_lx}, {col_tile}>",
+                 "lsop_rows_inv": f"k_rows_inv<{t}, {op_lz}>"}
+        ratios = {k: load_traffic(names[k]) for k in passes} if e else {}
+        traffic = sum(ratios[k] * by_use[k]["bytes"] for k in passes) if e and all(
+            ratios[k] is not None for k in passes) else None
+        compulsory = 2.0 * w.nx * w.nz * e * vec_applies if e else None
+        fft_conv = {"kernels": [names[k] for k in passes], "vector_applications": vec_applies,
+                    "ms": round(fft_ms, 3), "algorithmic_GB": round(fft_bytes / 1e9, 3),
+                    "traffic_GB": None if traffic is None else round(traffic / 1e9, 3),
+                    "compulsory_GB": None if compulsory is None else round(compulsory / 1e9, 3),
+                    "compulsory_GBps": None if compulsory is None else round(compulsory / (fft_ms / 1e3) / 1e9, 1)}
     growth = [(i.rel_residual / i.rel_residual0) ** (1.0 / i.iters) for i in info if i.iters > 0
               and i.rel_residual0 > 0 and np.isfinite(i.rel_residual)]
     if args.pc == "hodlr":
@@ -777,6 +796,7 @@ def main():
         "col_tile": col_tile, "preconditioner_bytes": pc_bytes,
         "hbm_copy_GBps_measured": round(copy_gbps, 1),
         "fft_conv_frac_of_measured_copy": None if fft_gbps is None else round(fft_gbps / copy_gbps, 4),
+        "fft_conv": fft_conv,
         "fp64_series": fp64,
         "roofline": roof, "kernels": kernels, "ms_per_step_by_use": uses,
     }
