@@ -159,8 +159,8 @@ def roofline_for(name, st):
     t = "double" if "<double" in name else "float"
     if name.startswith(("k_conv_fwd", "k_conv_wgrad")):
         t = "bf16"   # bf16 operands on the matrix cores, FP32 accumulation
-    mfma = name.startswith(("k_bgemm_mfma", "k_gemm_ah_b_mfma", "k_gemm_update_mfma", "k_gemm_update_tile", "k_conv_fwd",
-                            "k_conv_wgrad"))
+    mfma = name.startswith(("k_bgemm_mfma", "k_gemm_ah_b_mfma", "k_gemm_ah_b_narrow", "k_gemm_update_mfma",
+                            "k_gemm_update_tile", "k_conv_fwd", "k_conv_wgrad"))
     small = name.startswith(("k_lu_inverse", "k_gram_orth"))
     out = {"kernel": name, "avg_launch_ms": round(avg_s * 1e3, 4), "launches": st["launches"],
            "algorithmic_bytes_per_launch": bpl, "algorithmic_flops_per_launch": fpl}

@@ -127,7 +127,7 @@ hipError_t p_ah_b(const char* name, const Cx<T>* A, int na, const Cx<T>* B, cons
   const double e = sizeof(Cx<T>), nab = (double)na * nb * sizeof(Cx<double>), parts = (double)p.nseg * p.ksub;
   // FP32 results from one chunk per segment: the products themselves, no reduction launch
   const bool direct = C32 && p.ksub == 1 && alpha == 1.0;
-  hipError_t err = prof(name, fn_name("k_gemm_ah_b_mfma", tname<T>()),
+  hipError_t err = prof(name, fn_name(nb <= 16 ? "k_gemm_ah_b_narrow" : "k_gemm_ah_b_mfma", tname<T>()),
                         (double)(na + nb) * n * e + (direct ? 0.5 : 1.0) * parts * nab, 8.0 * na * nb * (double)n, nb,
                         s, [&] {
                           return launch_gemm_ah_b_part<T>(A, na, B, vidx, nb, n, p, part, s, direct ? C32 : nullptr);

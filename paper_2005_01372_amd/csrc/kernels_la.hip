@@ -216,33 +216,34 @@ __device__ __forceinline__ unsigned xcd_block(unsigned id, unsigned total) {
   return (total % 8u) ? id : (id % 8u) * (total / 8u) + id / 8u;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict__ A, int na,
-                                                        const Cx<T>* __restrict__ B, const int* __restrict__ vidx,
-                                                        int nb, size_t n, size_t seg, size_t chunk, int ksub,
-                                                        Cx<double>* __restrict__ part,
-                                                        Cx<float>* __restrict__ out32) {
+// BT: the b extent of a workgroup's tile, 64 (four waves of 32 x 32 = 2 x 2 MFMA tiles) or 16 for at most 16
+// vectors (four waves of 16 a x 16 b: a 64-wide b tile would leave three quarters of its MFMAs on zeros).
+template <typename T, int BT>
+__device__ __forceinline__ void ah_b_body(const Cx<T>* __restrict__ A, int na, const Cx<T>* __restrict__ B,
+                                          const int* __restrict__ vidx, int nb, size_t n, size_t seg, size_t chunk,
+                                          int ksub, Cx<double>* __restrict__ part, Cx<float>* __restrict__ out32) {
   using M = Mfma<T>;
+  constexpr int NI = BT == GM_T ? 2 : 1, NJ = NI;
   // reals per LDS row: an even stride, so that (re, im) pairs are stored and read as one aligned pair (the 16
   // row offsets 34 c mod 64 banks are still distinct)
   constexpr int SROW = 2 * GM_K + 2;
   __shared__ __align__(16) T sa[GM_T * SROW];
-  __shared__ __align__(16) T sb[GM_T * SROW];
+  __shared__ __align__(16) T sb[BT * SROW];
   const unsigned lid = xcd_block(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z),
                                  gridDim.x * gridDim.y * gridDim.z);
-  const int a0 = (int)(lid % gridDim.x) * GM_T, b0 = (int)((lid / gridDim.x) % gridDim.y) * GM_T;
+  const int a0 = (int)(lid % gridDim.x) * GM_T, b0 = (int)((lid / gridDim.x) % gridDim.y) * BT;
   const int ks = (int)(lid / (gridDim.x * gridDim.y));
   const size_t seg_b = (size_t)(ks / ksub) * seg;
   const size_t seg_e = seg_b + seg < n ? seg_b + seg : n;
   const size_t k_begin = seg_b + (size_t)(ks % ksub) * chunk;
   const size_t k_end = k_begin + chunk < seg_e ? k_begin + chunk : seg_e;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wa = (w >> 1) * 32, wb = (w & 1) * 32;
-  typename M::acc cre[2][2], cim[2][2];
+  const int wa = BT == GM_T ? (w >> 1) * 32 : w * 16, wb = BT == GM_T ? (w & 1) * 32 : 0;
+  typename M::acc cre[NI][NJ], cim[NI][NJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       cre[i][j] = typename M::acc{0, 0, 0, 0};
       cim[i][j] = typename M::acc{0, 0, 0, 0};
     }
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
   const int lr = threadIdx.x >> 2, lk = (threadIdx.x & 3) * 4;
   const Cx<T>* arow = (a0 + lr < na) ? A + (size_t)(a0 + lr) * n : nullptr;
   const int vb = b0 + lr;
-  const Cx<T>* brow = (vb < nb) ? B + (size_t)(vidx ? vidx[vb] : vb) * n : nullptr;
+  const Cx<T>* brow = (lr < BT && vb < nb) ? B + (size_t)(vidx ? vidx[vb] : vb) * n : nullptr;
   const int kk = l >> 4, c16 = l & 15;
   // the next stage's operands are loaded into registers while the current stage's MFMAs run; complex FP32
   // runs of 4 in range are loaded 16 bytes at a time (aligned when A and B are 16-byte aligned and n and
@@ -286,26 +287,26 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       *reinterpret_cast<Cx<T>*>(&sa[lr * SROW + 2 * (lk + q)]) = va[q];
-      *reinterpret_cast<Cx<T>*>(&sb[lr * SROW + 2 * (lk + q)]) = vb2[q];
+      if (lr < BT) *reinterpret_cast<Cx<T>*>(&sb[lr * SROW + 2 * (lk + q)]) = vb2[q];
     }
     __syncthreads();
     if (kb + GM_K < k_end) load(kb + GM_K);
 #pragma unroll
     for (int st = 0; st < GM_K / 2; ++st) {
       const int col = 4 * st + kk;
-      T av[2], bre[2], bim[2];
+      T av[NI], bre[NJ], bim[NJ];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) av[i] = sa[(wa + i * 16 + c16) * SROW + col];
+      for (int i = 0; i < NI; ++i) av[i] = sa[(wa + i * 16 + c16) * SROW + col];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < NJ; ++j) {
         const Cx<T> v = *reinterpret_cast<const Cx<T>*>(&sb[(wb + j * 16 + c16) * SROW + (col & ~1)]);
         bre[j] = (kk & 1) ? v.im : v.re;
         bim[j] = (kk & 1) ? -v.re : v.im;
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < NJ; ++j) {
           cre[i][j] = M::mma(av[i], bre[j], cre[i][j]);
           cim[i][j] = M::mma(av[i], bim[j], cim[i][j]);
         }
@@ -316,9 +317,9 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
   Cx<double>* p = part + (size_t)ks * na * nb;
   Cx<float>* p32 = out32 ? out32 + (size_t)ks * na * nb : nullptr;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a = a0 + wa + i * 16 + M::row(l, r);
@@ -328,6 +329,24 @@ __global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict_
           else p[(size_t)a * nb + b] = Cx<double>{(double)cre[i][j][r], (double)cim[i][j][r]};
         }
       }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict__ A, int na,
+                                                        const Cx<T>* __restrict__ B, const int* __restrict__ vidx,
+                                                        int nb, size_t n, size_t seg, size_t chunk, int ksub,
+                                                        Cx<double>* __restrict__ part,
+                                                        Cx<float>* __restrict__ out32) {
+  ah_b_body<T, GM_T>(A, na, B, vidx, nb, n, seg, chunk, ksub, part, out32);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_ah_b_narrow(const Cx<T>* __restrict__ A, int na,
+                                                          const Cx<T>* __restrict__ B, const int* __restrict__ vidx,
+                                                          int nb, size_t n, size_t seg, size_t chunk, int ksub,
+                                                          Cx<double>* __restrict__ part,
+                                                          Cx<float>* __restrict__ out32) {
+  ah_b_body<T, 16>(A, na, B, vidx, nb, n, seg, chunk, ksub, part, out32);
 }
 
 // Y[vy(b)][k] = X1 + beta X2 + sum_a A[a][k] M[a][b] as out[b][k] = M^T A
@@ -1050,9 +1069,15 @@ hipError_t launch_gemm_ah_b_part(const Cx<T>* A, int na, const Cx<T>* B, const i
                                  const GemmPlan& p, Cx<double>* part, hipStream_t s, Cx<float>* out32) {
   if (na <= 0 || nb <= 0) return hipSuccess;
   if (out32 && p.ksub != 1) return hipErrorInvalidValue;
-  dim3 grid((na + GM_T - 1) / GM_T, (nb + GM_T - 1) / GM_T, (unsigned)(p.nseg * p.ksub));
-  hipLaunchKernelGGL((k_gemm_ah_b_mfma<T>), grid, dim3(256), 0, s, A, na, B, vidx, nb, n, p.seg, p.chunk, p.ksub,
-                     part, out32);
+  if (nb <= 16) {  // one 16-wide b tile (see ah_b_body)
+    dim3 grid((na + GM_T - 1) / GM_T, 1, (unsigned)(p.nseg * p.ksub));
+    hipLaunchKernelGGL((k_gemm_ah_b_narrow<T>), grid, dim3(256), 0, s, A, na, B, vidx, nb, n, p.seg, p.chunk,
+                       p.ksub, part, out32);
+  } else {
+    dim3 grid((na + GM_T - 1) / GM_T, (nb + GM_T - 1) / GM_T, (unsigned)(p.nseg * p.ksub));
+    hipLaunchKernelGGL((k_gemm_ah_b_mfma<T>), grid, dim3(256), 0, s, A, na, B, vidx, nb, n, p.seg, p.chunk, p.ksub,
+                       part, out32);
+  }
   return hipGetLastError();
 }
 
