@@ -147,7 +147,7 @@ hipError_t p_update(const char* name, const Cx<T>* A, int na, const Cx<MT>* M, s
   const double vecs = 1.0 + (X1 ? 1.0 : 0.0) + (X2 ? 1.0 : 0.0);
   const double nsegs = (seg == 0 || seg >= n) ? 1.0 : (double)((n + seg - 1) / seg);
   // the kernel launch_gemm_update_seg picks
-  const int nbt = nb > 32 ? 4 : 2, ga = nb > 32 ? 4 : 8, wpe = nb > 32 ? (sizeof(T) == 4 ? 6 : 3) : 0;
+  const int nbt = nb > 32 ? 4 : nb > 16 ? 2 : 1, ga = nb > 32 ? 4 : 8, wpe = nb > 32 ? (sizeof(T) == 4 ? 6 : 3) : 0;
   const std::string types = std::string(tname<T>()) + ", " + tname<MT>();
   const std::string kname = (sizeof(T) == 4 && nb > 32) ? fn_name("k_gemm_update_tile", tname<MT>())
                                                          : fn_name("k_gemm_update_mfma", types.c_str(), nbt, ga, wpe);

@@ -1129,8 +1129,11 @@ hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<MT>* M, size_
     } else
       hipLaunchKernelGGL((k_gemm_update_mfma<T, MT, 4, 4, 3>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta,
                          Y, vidx, n, seg, mstride);
-  } else {
+  } else if (nb > 16) {
     hipLaunchKernelGGL((k_gemm_update_mfma<T, MT, 2, 8, 0>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y,
+                       vidx, n, seg, mstride);
+  } else {  // one 16-wide b tile: a second one would run its MFMAs on zeros
+    hipLaunchKernelGGL((k_gemm_update_mfma<T, MT, 1, 8, 0>), grid, dim3(256), 0, s, A, na, M, nb, X1, X2, (T)beta, Y,
                        vidx, n, seg, mstride);
   }
   return hipGetLastError();
