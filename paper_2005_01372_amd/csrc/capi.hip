@@ -988,7 +988,7 @@ int hodlr_build(lsop_precond* pc, const double* omega, hipStream_t s) {
   lsop_op* op = pc->op;
   const int r = pc->rank;
   const size_t n = op->n();
-  // build-only workspace: sampling buffers and the FP64 leaf workspace, taken from and returned to the
+  // build-only workspace: sampling buffers and the leaf workspace, taken from and returned to the
   // stream-ordered pool of stream s (no device-wide synchronisation, so builds on other streams keep running),
   // or carved from the operator's attached workspace (after the sub-domain spectra, which use its start as
   // their intermediate earlier on the same stream)
@@ -2412,7 +2412,7 @@ int pc_buffers(lsop_precond* pc, Alloc& a) {
     }
     return st ? LSOP_ENOMEM : LSOP_OK;
   }
-  // HODLR: the FP64 leaf workspace and the sampling buffers U, Y live only during precond_build
+  // HODLR: the leaf workspace and the sampling buffers U, Y live only during precond_build
   const int nl = pc->leaf_w * op->nz;
   st |= dev_alloc(a, &pc->dinv, esz * (size_t)pc->nleaf * nl * nl);
   st |= dev_alloc(a, &pc->hy, esz * (size_t)pc->tcap * n);
@@ -2444,7 +2444,7 @@ int pc_buffers(lsop_precond* pc, Alloc& a) {
   return st ? LSOP_ENOMEM : LSOP_OK;
 }
 
-// Transient workspace of precond_build: HODLR sampling buffers and FP64 leaf workspace (or the sub-domain
+// Transient workspace of precond_build: HODLR sampling buffers and leaf workspace (or the sub-domain
 // spectrum intermediate, if larger); none for the other kinds.
 size_t pc_build_ws_bytes(const lsop_precond* pc) {
   if (pc->kind != LSOP_PC_HODLR) return 0;

@@ -322,7 +322,8 @@ struct lsop_precond {
   int levels = 0, leaf_w = 0, nleaf = 0, leaf_chunk = 0;
   std::vector<hodlr_level> lev;
   void* dinv = nullptr;                   // [nleaf][nl][nl] transposed leaf inverses
-  Cx<double>* lwork = nullptr;            // FP64 leaf workspace (leaf_chunk matrices + recursion temporaries)
+  Cx<double>* lwork = nullptr;            // leaf workspace (leaf_chunk matrices + recursion temporaries, in the
+                                          // leaves' precision; allocated in complex-double units)
   size_t lwork_elems = 0;
   void* hy = nullptr;                     // [tcap][n] apply / series temporary
   Cx<double>*hG = nullptr, *hX = nullptr;  // per-segment products [maxseg][rank][tcap]
