@@ -102,6 +102,10 @@ std::string fn_name(const char* base, const char* t, int a = -1, int b = -1, int
   return f + ">";
 }
 
+// Real flops per complex multiply-add of a GEMM kernel: 6 for the complex FP32 kernels, which take Gauss's 3M
+// form (three real products), 8 for the two-chain form.
+double cmac_flops(bool three_m) { return three_m ? 6.0 : 8.0; }
+
 // C = alpha A^H B (segmented) as its two profiled launches
 // Chunks per segment for C = A^H B: the caller's ksub, raised for launches with few 64 x 64 output tiles until
 // there are about 2048 workgroups (8 per CU), while chunks keep at least 1024 elements and the partials fit the
@@ -128,7 +132,8 @@ hipError_t p_ah_b(const char* name, const Cx<T>* A, int na, const Cx<T>* B, cons
   // FP32 results from one chunk per segment: the products themselves, no reduction launch
   const bool direct = C32 && p.ksub == 1 && alpha == 1.0;
   hipError_t err = prof(name, fn_name(nb <= 16 ? "k_gemm_ah_b_narrow" : "k_gemm_ah_b_mfma", tname<T>()),
-                        (double)(na + nb) * n * e + (direct ? 0.5 : 1.0) * parts * nab, 8.0 * na * nb * (double)n, nb,
+                        (double)(na + nb) * n * e + (direct ? 0.5 : 1.0) * parts * nab,
+                        cmac_flops(sizeof(T) == 4) * na * nb * (double)n, nb,
                         s, [&] {
                           return launch_gemm_ah_b_part<T>(A, na, B, vidx, nb, n, p, part, s, direct ? C32 : nullptr);
                         });
@@ -153,7 +158,7 @@ hipError_t p_update(const char* name, const Cx<T>* A, int na, const Cx<MT>* M, s
                                                          : fn_name("k_gemm_update_mfma", types.c_str(), nbt, ga, wpe);
   return prof(name, kname,
               (double)na * n * e + vecs * nb * (double)n * e + nsegs * na * nb * sizeof(Cx<MT>),
-              8.0 * na * nb * (double)n, nb, s,
+              cmac_flops(sizeof(T) == 4 && nb > 32) * na * nb * (double)n, nb, s,
               [&] { return launch_gemm_update_seg<T, MT>(A, na, M, mstride, nb, X1, X2, beta, Y, vidx, n, seg, s); });
 }
 
@@ -164,7 +169,8 @@ hipError_t p_bgemm(const char* name, const Cx<T>* A, size_t lda, size_t sA, cons
                    double alpha, double beta, int batch, hipStream_t s) {
   const double e = sizeof(Cx<T>);
   const double bytes = (double)batch * ((double)M * K + (double)K * N + (double)M * N * (beta != 0.0 ? 2.0 : 1.0)) * e;
-  return prof(name, fn_name("k_bgemm_mfma", tname<T>()), bytes, 8.0 * M * N * (double)K * batch, batch, s, [&] {
+  return prof(name, fn_name("k_bgemm_mfma", tname<T>()), bytes, cmac_flops(sizeof(T) == 4) * M * N * (double)K * batch,
+              batch, s, [&] {
     return launch_bgemm<T>(A, lda, sA, B, ldb, sB, C, ldc, sC, mapa, mapc, M, N, K, alpha, beta, batch, s);
   });
 }

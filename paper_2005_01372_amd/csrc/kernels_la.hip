@@ -164,6 +164,9 @@ __global__ void k_reduce_parts(const Cx<double>* __restrict__ part, int ksub, in
 // (re, im) operands: with A'[.][2k + p] the p-th component of a_k,
 //   conj(a) b:  re = sum_kk A'[kk] (br, bi)[kk],  im = sum_kk A'[kk] (bi, -br)[kk]
 //   m a (no conj, m on the left):  re = (mr, -mi) . (ar, ai),  im = (mi, mr) . (ar, ai).
+// The FP32 inner product instead takes three real products per complex one (Gauss's 3M form): over
+// complex k, t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar - ai)(br + bi), and then conj(a) b has
+// re = t1 + t2 and im = t3 - t1 + t2; three quarters of the matrix-core work of the two chains.
 typedef float lsop_f4 __attribute__((ext_vector_type(4)));
 typedef double lsop_d4 __attribute__((ext_vector_type(4)));
 
@@ -239,13 +242,15 @@ __device__ __forceinline__ void ah_b_body(const Cx<T>* __restrict__ A, int na, c
   const size_t k_end = k_begin + chunk < seg_e ? k_begin + chunk : seg_e;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wa = BT == GM_T ? (w >> 1) * 32 : w * 16, wb = BT == GM_T ? (w & 1) * 32 : 0;
-  typename M::acc cre[NI][NJ], cim[NI][NJ];
+  constexpr bool G3 = sizeof(T) == 4;  // 3M form (FP32)
+  typename M::acc cre[NI][NJ], cim[NI][NJ], c3[G3 ? NI : 1][G3 ? NJ : 1];
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       cre[i][j] = typename M::acc{0, 0, 0, 0};
       cim[i][j] = typename M::acc{0, 0, 0, 0};
+      if constexpr (G3) c3[i][j] = typename M::acc{0, 0, 0, 0};
     }
   // loader: thread t -> row t / 4, complex k (t % 4) * 4 .. +4
   const int lr = threadIdx.x >> 2, lk = (threadIdx.x & 3) * 4;
@@ -291,6 +296,38 @@ __device__ __forceinline__ void ah_b_body(const Cx<T>* __restrict__ A, int na, c
     }
     __syncthreads();
     if (kb + GM_K < k_end) load(kb + GM_K);
+    if constexpr (G3) {
+      // lane (c16, kk) takes complex k = 4 st + kk: cre, cim, c3 accumulate t1, t2, t3
+#pragma unroll
+      for (int st = 0; st < GM_K / 4; ++st) {
+        const int col = 2 * (4 * st + kk);
+        T ar[NI], ai[NI], as[NI], br[NJ], bi[NJ], bs[NJ];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          const Cx<T> v = *reinterpret_cast<const Cx<T>*>(&sa[(wa + i * 16 + c16) * SROW + col]);
+          ar[i] = v.re;
+          ai[i] = v.im;
+          as[i] = v.re - v.im;
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          const Cx<T> v = *reinterpret_cast<const Cx<T>*>(&sb[(wb + j * 16 + c16) * SROW + col]);
+          br[j] = v.re;
+          bi[j] = v.im;
+          bs[j] = v.re + v.im;
+        }
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) {
+            cre[i][j] = M::mma(ar[i], br[j], cre[i][j]);
+            cim[i][j] = M::mma(ai[i], bi[j], cim[i][j]);
+            c3[i][j] = M::mma(as[i], bs[j], c3[i][j]);
+          }
+      }
+      __syncthreads();
+      continue;
+    }
 #pragma unroll
     for (int st = 0; st < GM_K / 2; ++st) {
       const int col = 4 * st + kk;
@@ -312,6 +349,16 @@ __device__ __forceinline__ void ah_b_body(const Cx<T>* __restrict__ A, int na, c
         }
     }
     __syncthreads();
+  }
+  if constexpr (G3) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const typename M::acc t1 = cre[i][j], t2 = cim[i][j];
+        cre[i][j] = t1 + t2;
+        cim[i][j] = c3[i][j] - t1 + t2;
+      }
   }
   // one chunk per segment with out32: the partial is the product, written rounded to FP32
   Cx<double>* p = part + (size_t)ks * na * nb;
@@ -464,7 +511,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? W
 // form's to FP32 rounding (summation order).
 constexpr int UPD_T = 64, UPD_K = 16, UPD_ROW = UPD_T + 16;
 template <typename MT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) == 4 ? 6 : 1))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) == 4 ? 5 : 1))) void
 k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, int nb,
                    const Cx<float>* X1, const Cx<float>* X2, float beta, Cx<float>* Y,
                    const int* __restrict__ vidx, size_t n, size_t seg, size_t mstride) {
@@ -480,15 +527,17 @@ k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, in
   const int wb = (w >> 1) * 32, wk = (w & 1) * 32;
   // loader: thread t -> stage row t / 16, four consecutive columns (t % 16) * 4
   const int la = threadIdx.x >> 4, lc = (threadIdx.x & 15) * 4;
-  // operand lanes: kk = l / 16 is the real k index of the MFMA (part p of complex a = 2 st + kk / 2)
-  const int kk = l >> 4, c16 = l & 15, p = kk & 1, ah = kk >> 1;
-  typename MF::acc cre[2][2], cim[2][2];
+  // operand lanes: kk = l / 16 is the MFMA's k index, complex a = 4 st + kk.  Gauss's 3M form: t1 = sum mr xr,
+  // t2 = sum mi xi, t3 = sum (mr + mi)(xr + xi) in c1, c2, c3; m x = (t1 - t2, t3 - t1 - t2).
+  const int kk = l >> 4, c16 = l & 15;
+  typename MF::acc c1[2][2], c2[2][2], c3[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      cre[i][j] = typename MF::acc{0, 0, 0, 0};
-      cim[i][j] = typename MF::acc{0, 0, 0, 0};
+      c1[i][j] = typename MF::acc{0, 0, 0, 0};
+      c2[i][j] = typename MF::acc{0, 0, 0, 0};
+      c3[i][j] = typename MF::acc{0, 0, 0, 0};
     }
   Cx<MT> vm[4];
   Cx<float> vx[4];
@@ -527,27 +576,30 @@ k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, in
     __syncthreads();
     if (a0 + UPD_K < na) load(a0 + UPD_K);
 #pragma unroll
-    for (int st = 0; st < UPD_K / 2; ++st) {
-      // out = m a: re = (mr, mi) . (ar, -ai), im = (mr, mi) . (ai, ar) over the interleaved parts
-      const int ar = 2 * st + ah;
-      float mo[2], bre[2], bim[2];
+    for (int st = 0; st < UPD_K / 4; ++st) {
+      const int ar = 4 * st + kk;
+      float mr[2], mi[2], ms[2], xr[2], xi[2], xs[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const Cx<float> m = sm[ar * UPD_ROW + wb + i * 16 + c16];
-        mo[i] = p ? m.im : m.re;
+        mr[i] = m.re;
+        mi[i] = m.im;
+        ms[i] = m.re + m.im;
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const Cx<float> x = sx[ar * UPD_ROW + wk + j * 16 + c16];
-        bre[j] = p ? -x.im : x.re;
-        bim[j] = p ? x.re : x.im;
+        xr[j] = x.re;
+        xi[j] = x.im;
+        xs[j] = x.re + x.im;
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          cre[i][j] = MF::mma(mo[i], bre[j], cre[i][j]);
-          cim[i][j] = MF::mma(mo[i], bim[j], cim[i][j]);
+          c1[i][j] = MF::mma(mr[i], xr[j], c1[i][j]);
+          c2[i][j] = MF::mma(mi[i], xi[j], c2[i][j]);
+          c3[i][j] = MF::mma(ms[i], xs[j], c3[i][j]);
         }
     }
     __syncthreads();
@@ -562,7 +614,8 @@ k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, in
         const size_t k = k0 + wk + j * 16 + c16;
         if (b < nb && k < n) {
           const size_t off = (size_t)(vidx ? vidx[b] : b) * n + k;
-          Cx<float> out{cre[i][j][r], cim[i][j][r]};
+          const float t1 = c1[i][j][r], t2 = c2[i][j][r];
+          Cx<float> out{t1 - t2, c3[i][j][r] - t1 - t2};
           if (X1) out = out + X1[off];
           if (X2) out = out + beta * X2[off];
           Y[off] = out;
@@ -879,7 +932,8 @@ __global__ __launch_bounds__(256) void k_identity_deviation(const Cx<double>* __
 // (mapa ? mapa[m] : m) * lda + b * sA, row m of C likewise through mapc (the
 // maps address vectors of a batch through an index list).  Tile 64 x 64 per workgroup of four waves
 // (2 x 2 MFMA tiles each, real and imaginary chains over interleaved (re, im)
-// operands: re = sum (ar br - ai bi), im = sum (ar bi + ai br)).
+// operands: re = sum (ar br - ai bi), im = sum (ar bi + ai br)).  Complex FP32 takes Gauss's 3M form
+// instead: t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar + ai)(br + bi), a b = (t1 - t2, t3 - t1 - t2).
 template <typename T>
 __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, size_t sA, const Cx<T>* B,
                                                     size_t ldb, size_t sB, Cx<T>* C, size_t ldc, size_t sC,
@@ -897,13 +951,15 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
   const int n0 = (int)(lid % gridDim.x) * GM_T, m0 = (int)((lid / gridDim.x) % gridDim.y) * GM_T;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-  typename MF::acc cre[2][2], cim[2][2];
+  constexpr bool G3 = sizeof(T) == 4;  // 3M form (FP32)
+  typename MF::acc cre[2][2], cim[2][2], c3[G3 ? 2 : 1][G3 ? 2 : 1];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       cre[i][j] = typename MF::acc{0, 0, 0, 0};
       cim[i][j] = typename MF::acc{0, 0, 0, 0};
+      if constexpr (G3) c3[i][j] = typename MF::acc{0, 0, 0, 0};
     }
   // A loader: thread t -> row t / 4, k (t % 4) * 4 .. +4 ; B loader: k t / 16, n (t % 16) * 4 .. +4
   const int ar = threadIdx.x >> 2, ak = (threadIdx.x & 3) * 4;
@@ -955,6 +1011,38 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
     }
     __syncthreads();
     if (kb + GM_K < K) load(kb + GM_K);
+    if constexpr (G3) {
+      // lane (c16, kk) takes complex k = 4 st + kk: cre, cim, c3 accumulate t1, t2, t3
+#pragma unroll
+      for (int st = 0; st < GM_K / 4; ++st) {
+        const int col = 2 * (4 * st + kk);
+        T xr[2], xi[2], xs[2], yr[2], yi[2], ys[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const Cx<T> v = *reinterpret_cast<const Cx<T>*>(&sa[(wm + i * 16 + c16) * SROW + col]);
+          xr[i] = v.re;
+          xi[i] = v.im;
+          xs[i] = v.re + v.im;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const Cx<T> v = *reinterpret_cast<const Cx<T>*>(&sb[(wn + j * 16 + c16) * SROW + col]);
+          yr[j] = v.re;
+          yi[j] = v.im;
+          ys[j] = v.re + v.im;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            cre[i][j] = MF::mma(xr[i], yr[j], cre[i][j]);
+            cim[i][j] = MF::mma(xi[i], yi[j], cim[i][j]);
+            c3[i][j] = MF::mma(xs[i], ys[j], c3[i][j]);
+          }
+      }
+      __syncthreads();
+      continue;
+    }
 #pragma unroll
     for (int st = 0; st < GM_K / 2; ++st) {
       const int col = 4 * st + kk;
@@ -976,6 +1064,16 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
         }
     }
     __syncthreads();
+  }
+  if constexpr (G3) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const typename MF::acc t1 = cre[i][j], t2 = cim[i][j];
+        cre[i][j] = t1 - t2;
+        cim[i][j] = c3[i][j] - t1 - t2;
+      }
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
