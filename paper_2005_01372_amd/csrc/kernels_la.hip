@@ -378,12 +378,12 @@ __device__ __forceinline__ void ah_b_body(const Cx<T>* __restrict__ A, int na, c
       }
 }
 
+// complex FP32 at 5 waves per SIMD (96 registers, no spills; 4 without the hint)
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_ah_b_mfma(const Cx<T>* __restrict__ A, int na,
-                                                        const Cx<T>* __restrict__ B, const int* __restrict__ vidx,
-                                                        int nb, size_t n, size_t seg, size_t chunk, int ksub,
-                                                        Cx<double>* __restrict__ part,
-                                                        Cx<float>* __restrict__ out32) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 5 : 1))) void
+k_gemm_ah_b_mfma(const Cx<T>* __restrict__ A, int na, const Cx<T>* __restrict__ B, const int* __restrict__ vidx, int nb,
+                 size_t n, size_t seg, size_t chunk, int ksub, Cx<double>* __restrict__ part,
+                 Cx<float>* __restrict__ out32) {
   ah_b_body<T, GM_T>(A, na, B, vidx, nb, n, seg, chunk, ksub, part, out32);
 }
 
@@ -501,17 +501,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE > 0 ? W
 }
 
 // GEMM-tile form of the same update for complex float and nb > 32: a workgroup owns a 64 (b) x 64 (k) tile of Y
-// (four waves of 32 x 32 = 2 x 2 MFMA tiles, real and imaginary chains); M (rounded to FP32) and A are both
+// (four waves of 32 x 32 = 2 x 2 MFMA tiles, three chains of the 3M form); M (rounded to FP32) and A are both
 // staged in LDS 16 complex a at a time, the next stage loaded into registers while the current stage's MFMAs
-// run, so a barrier pair covers 64 MFMAs per wave (the per-wave form above: 16).  The tiles of one 64-element k
-// range follow each other on one XCD, so A's re-reads by its b tiles are L2 hits.  LDS rows of 80 complex put
-// the two a rows an MFMA operand spans 32 banks apart.  Measured at n = 1M (standalone, against the form above):
-// na = 256, nb = 128-256 with FP32 M at 6 waves per SIMD 108 -> 118 TFLOP/s; na = 64-192, nb = 64 with FP64 M
-// (no occupancy hint; 6 waves is slower there) 76 -> 86 and 97 -> 110 TFLOP/s.  Results equal the per-wave
-// form's to FP32 rounding (summation order).
+// run, so a barrier pair covers 48 MFMAs per wave.  The tiles of one 64-element k range follow each other on one
+// XCD, so A's re-reads by its b tiles are L2 hits.  LDS rows of 80 complex put the a rows that one MFMA operand
+// spans 32 banks apart in turn.  Measured at n = 1M (standalone, two-chain form, against the per-wave form
+// above): na = 256, nb = 128-256 with FP32 M at 6 waves per SIMD 108 -> 118 TFLOP/s; na = 64-192, nb = 64 with
+// FP64 M (no occupancy hint; 6 waves was slower there) 76 -> 86 and 97 -> 110 TFLOP/s.  The 3M form needs 16
+// more registers (10 spilled at 6 waves); both instantiations run at 5 waves per SIMD.
 constexpr int UPD_T = 64, UPD_K = 16, UPD_ROW = UPD_T + 16;
 template <typename MT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(MT) == 4 ? 5 : 1))) void
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void
 k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, int nb,
                    const Cx<float>* X1, const Cx<float>* X2, float beta, Cx<float>* Y,
                    const int* __restrict__ vidx, size_t n, size_t seg, size_t mstride) {
