@@ -100,11 +100,13 @@ def test_hodlr_power_iterations_from_a_level_match_oracle(qfrom):
         assert rel(hs.apply(x), h0.apply(x)) <= 1e-13
 
 
-@pytest.mark.parametrize("nx,nz,levels,r,q", [(64, 64, 3, 12, 0), (16, 1024, 4, 16, 1)])
-def test_hodlr_fp32_apply_matches_oracle(nx, nz, levels, r, q):
+@pytest.mark.parametrize("nx,nz,levels,r,q,nv", [(64, 64, 3, 12, 0, 4), (16, 1024, 4, 16, 1, 4), (64, 64, 3, 40, 1, 40)])
+def test_hodlr_fp32_apply_matches_oracle(nx, nz, levels, r, q, nv):
     """Complex FP32 against the oracle, including leaves of one grid column of 1024 cells (a 4-level tree on a
-    16 x 1024 strip, q = 1).  Bound: 1.5 x the measured FP32-vs-FP64 spread of the same probes, at most 1e-4."""
-    announce(f"hodlr fp32 {nx}x{nz} levels={levels} r={r} q={q}")
+    16 x 1024 strip, q = 1), and 40 vectors at rank 40: more than 32 vectors and orthonormalisation columns take
+    the tile-form update, and the inner product its 64-wide vector tile, both in the 3M form.  Bound: 1.5 x the
+    measured FP32-vs-FP64 spread of the same probes, at most 1e-4."""
+    announce(f"hodlr fp32 {nx}x{nz} levels={levels} r={r} q={q} nv={nv}")
     w = synth.model_layered_salt(n=64, h=10.0, freq=15.0, seed=2, nsrc=1)
     if (nx, nz) != (64, 64):
         rng = np.random.default_rng(4)
@@ -113,7 +115,7 @@ def test_hodlr_fp32_apply_matches_oracle(nx, nz, levels, r, q):
     prob = O.Problem(w.vel, w.h, w.freq, w.c0)
     om = probe_rows(levels, r, prob.n, 23)
     hs = HD.HodlrSolve(prob, r, levels, probes=lambda d: om[d * r:(d + 1) * r], q=q)
-    x = synth.random_vectors((4, nx, nz), 9)
+    x = synth.random_vectors((nv, nx, nz), 9)
     ref = hs.apply(x)
     out = {}
     for dtype, tdt in ((lsop.C128, torch.complex128), (lsop.C64, torch.complex64)):

@@ -62,6 +62,24 @@ def test_precond_fp32_odd_cell_count_matches_oracle():
     assert rel(host(pc.apply(dev(x, torch.complex64))), H.apply(x)) <= 2e-5
 
 
+def test_precond_fp32_many_vectors_matches_oracle():
+    """Complex FP32 at rank 96 applied to 40 vectors: the build's first 64-column block and the apply's U Z(.)
+    take the tile-form update (more than 32 vectors), the projection of the second block and W^H x the inner
+    product's 64-wide vector tile, both in the 3M form (three real products per complex one)."""
+    announce("precond apply fp32 rank 96, 40 vectors")
+    w = cfg1(48)
+    prob = O.Problem(w.vel, w.h, w.freq, w.c0)
+    r = 96
+    om = synth.gaussian_probes(prob.n, r, 13)
+    H = O.LowRankPreconditioner.build(prob, om.reshape(r, 48, 48))
+    op = make_op(w, lsop.C64, 8)
+    pc = lsop.Preconditioner(op, lsop.PC_LOWRANK, rank=r)
+    pc.build(torch.as_tensor(om).cuda())
+    assert pc.info()[0] == r
+    x = synth.random_vectors((40, 48, 48), 6)
+    assert rel(host(pc.apply(dev(x, torch.complex64))), H.apply(x)) <= 2e-5
+
+
 def test_precond_rank_above_128_matches_oracle():
     """Z = (I - W^H U)^{-1} of more than 128 probes takes the pivoted Gauss-Jordan in global memory, whose
     thread layout (one column per thread, fewer threads than 2 * rank) differs from the small-block kernel."""
