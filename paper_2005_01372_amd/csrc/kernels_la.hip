@@ -191,7 +191,8 @@ struct Mfma<double> {
 
 // C[a][b] partials = sum_k conj(A[a][k]) B[vb][k] over one k-chunk.  Tile
 // 64 (a) x 64 (b) per workgroup of four waves (each 32 x 32 = 2 x 2 MFMA
-// tiles, real and imaginary chains); operands staged in LDS 16 complex k at a time.
+// tiles; three chains of the 3M form in FP32, real and imaginary chains in FP64);
+// operands staged in LDS 16 complex k at a time.
 // The k range is cut into segments of `seg` elements (block-diagonal inner
 // products: one result per segment), each into ksub chunks; z-block ks covers
 // chunk ks % ksub of segment ks / ksub.
