@@ -517,8 +517,8 @@ k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, in
                    const Cx<float>* X1, const Cx<float>* X2, float beta, Cx<float>* Y,
                    const int* __restrict__ vidx, size_t n, size_t seg, size_t mstride) {
   using MF = Mfma<float>;
-  __shared__ Cx<float> sm[UPD_K * UPD_ROW];
-  __shared__ Cx<float> sx[UPD_K * UPD_ROW];
+  __shared__ __align__(16) Cx<float> sm[UPD_K * UPD_ROW];
+  __shared__ __align__(16) Cx<float> sx[UPD_K * UPD_ROW];
   const int nbt = (nb + UPD_T - 1) / UPD_T;
   const size_t lid = xcd_block(blockIdx.x, gridDim.x);
   const size_t k0 = (lid / nbt) * UPD_T;
@@ -526,8 +526,11 @@ k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, in
   Mm += (k0 / seg) * mstride;  // the tile's 64 elements lie in one segment (seg % 64 == 0)
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wb = (w >> 1) * 32, wk = (w & 1) * 32;
-  // loader: thread t -> stage row t / 16, four consecutive columns (t % 16) * 4
-  const int la = threadIdx.x >> 4, lc = (threadIdx.x & 15) * 4;
+  // loader: thread t -> stage row t / 16, columns lj, lj + 1 and 32 + lj, 33 + lj (lj = 2 (t % 16)), each pair
+  // stored to LDS as 16 bytes: the 16 lanes of a store pass then cover the 64 banks once (with four consecutive
+  // columns per thread, lanes 8 apart met on the same banks), and each global load stays 256 contiguous bytes
+  const int la = threadIdx.x >> 4, lj = (threadIdx.x & 15) * 2;
+  auto lcol = [&](int q) { return lj + (q & 1) + 32 * (q >> 1); };
   // operand lanes: kk = l / 16 is the MFMA's k index, complex a = 4 st + kk.  Gauss's 3M form: t1 = sum mr xr,
   // t2 = sum mi xi, t3 = sum (mr + mi)(xr + xi) in c1, c2, c3; m x = (t1 - t2, t3 - t1 - t2).
   const int kk = l >> 4, c16 = l & 15;
@@ -548,13 +551,13 @@ k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, in
     const bool ain = a < na;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int b = b0 + lc + q;
+      const int b = b0 + lcol(q);
       vm[q] = (ain && b < nb) ? Mm[(size_t)a * nb + b] : czero<MT>();
     }
     if (vec) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const float4 x = ain ? *reinterpret_cast<const float4*>(A + (size_t)a * n + k0 + lc + 2 * h)
+        const float4 x = ain ? *reinterpret_cast<const float4*>(A + (size_t)a * n + k0 + lj + 32 * h)
                              : float4{0.f, 0.f, 0.f, 0.f};
         vx[2 * h] = Cx<float>{x.x, x.y};
         vx[2 * h + 1] = Cx<float>{x.z, x.w};
@@ -562,7 +565,7 @@ k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, in
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const size_t k = k0 + lc + q;
+        const size_t k = k0 + lcol(q);
         vx[q] = (ain && k < n) ? A[(size_t)a * n + k] : czero<float>();
       }
     }
@@ -570,9 +573,11 @@ k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, in
   load(0);
   for (int a0 = 0; a0 < na; a0 += UPD_K) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      sm[la * UPD_ROW + lc + q] = ccast<float>(vm[q]);
-      sx[la * UPD_ROW + lc + q] = vx[q];
+    for (int h = 0; h < 2; ++h) {
+      const Cx<float> m0 = ccast<float>(vm[2 * h]), m1 = ccast<float>(vm[2 * h + 1]);
+      *reinterpret_cast<float4*>(&sm[la * UPD_ROW + lj + 32 * h]) = float4{m0.re, m0.im, m1.re, m1.im};
+      *reinterpret_cast<float4*>(&sx[la * UPD_ROW + lj + 32 * h]) =
+          float4{vx[2 * h].re, vx[2 * h].im, vx[2 * h + 1].re, vx[2 * h + 1].im};
     }
     __syncthreads();
     if (a0 + UPD_K < na) load(a0 + UPD_K);
