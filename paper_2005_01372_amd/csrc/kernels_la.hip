@@ -967,9 +967,14 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
       cim[i][j] = typename MF::acc{0, 0, 0, 0};
       if constexpr (G3) c3[i][j] = typename MF::acc{0, 0, 0, 0};
     }
-  // A loader: thread t -> row t / 4, k (t % 4) * 4 .. +4 ; B loader: k t / 16, n (t % 16) * 4 .. +4
+  // A loader: thread t -> row t / 4, k (t % 4) * 4 .. +4 ; B loader: k t / 16 and four n, bn + BQ q (q < 4).
+  // Complex FP32 takes four consecutive n (bn = 4 (t % 16), BQ = 1: two 16-byte loads); complex FP64, which
+  // loads element-wise, takes bn = t % 16 and BQ = 16, so that its transposed LDS stores of a pass fall on
+  // distinct banks (consecutive n put lanes 8 apart on the same banks; 3-4% faster).  For FP32 the 16-byte
+  // loads weigh more than the conflicts: the element-wise form was 12% slower.
+  constexpr int BQ = sizeof(T) == 4 ? 1 : 16;
   const int ar = threadIdx.x >> 2, ak = (threadIdx.x & 3) * 4;
-  const int bk = threadIdx.x >> 4, bn = (threadIdx.x & 15) * 4;
+  const int bk = threadIdx.x >> 4, bn = sizeof(T) == 4 ? (threadIdx.x & 15) * 4 : threadIdx.x & 15;
   const Cx<T>* arow = nullptr;
   if (m0 + ar < M) arow = A + bt * sA + (size_t)(mapa ? mapa[m0 + ar] : m0 + ar) * lda;
   const Cx<T>* bbase = B + bt * sB;
@@ -1005,7 +1010,7 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        vb[q] = (kb2 < K && nn0 + q < N) ? bbase[(size_t)kb2 * ldb + nn0 + q] : czero<T>();
+        vb[q] = (kb2 < K && nn0 + BQ * q < N) ? bbase[(size_t)kb2 * ldb + nn0 + BQ * q] : czero<T>();
     }
   };
   load(0);
@@ -1013,7 +1018,7 @@ __global__ __launch_bounds__(256) void k_bgemm_mfma(const Cx<T>* A, size_t lda, 
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       *reinterpret_cast<Cx<T>*>(&sa[ar * SROW + 2 * (ak + q)]) = va[q];
-      *reinterpret_cast<Cx<T>*>(&sb[(bn + q) * SROW + 2 * bk]) = vb[q];
+      *reinterpret_cast<Cx<T>*>(&sb[(bn + BQ * q) * SROW + 2 * bk]) = vb[q];
     }
     __syncthreads();
     if (kb + GM_K < K) load(kb + GM_K);
