@@ -444,7 +444,8 @@ int check_op(const lsop_op* op) {
 // classical Gram-Schmidt), then orthonormalised by Cholesky-QR run twice in the
 // metric of its FP64 Gram matrix.  A column is dropped (numerically
 // dependent) when its remaining norm falls below a fixed fraction of its norm
-// before any projection.  G, X, R: FP64 scratch of nseg * r * 64 entries each;
+// before any projection (its squared norm per segment, written to R as FP64
+// reals).  G, X, R: FP64 scratch of nseg * r * 64 entries each;
 // kept[(block) * nseg + sg] receives the kept column counts of the final pass.
 // full = false (an intermediate basis of the power iteration, whose only use is
 // the next sample: its span matters, not how orthonormal it is) projects once
@@ -460,8 +461,11 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
     const int kb = std::min(B, r - c0);
     Cx<T>* Yb = Y + (size_t)c0 * n;
     Cx<T>* Qb = Q + (size_t)c0 * n;
-    if (c0 > 0) {  // reference Gram of the block before projection
-      LSOP_HIP(p_ah_b<T>("orth_gram", Yb, kb, Yb, nullptr, kb, n, seg, R, part, ksub, s, 1.0, part_cap));
+    if (c0 > 0) {  // squared column norms of the block before projection, per segment (the drop test's reference)
+      LSOP_HIP(prof("orth_norms", fn_name("k_seg_colnorm2", tname<T>()), (double)kb * n * e, 4.0 * kb * (double)n, kb,
+                    s, [&] {
+                      return launch_seg_colnorm2<T>(Yb, kb, n, seg, nseg, reinterpret_cast<double*>(R), s);
+                    }));
     }
     for (int pass = 0; pass < passes && c0 > 0; ++pass) {
       LSOP_HIP(p_ah_b<T>("orth_project", Q, c0, Yb, nullptr, kb, n, seg, G, part, ksub, s, -1.0, part_cap));
@@ -474,7 +478,8 @@ int orth_blocks(Cx<T>* Y, Cx<T>* Q, int r, size_t n, size_t seg, int nseg, int k
       LSOP_HIP(prof("orth_coeffs", "k_gram_orth_lds", 2.0 * nseg * kb * kb * sizeof(Cx<double>),
                     8.0 / 3.0 * kb * kb * (double)kb * nseg, nseg, s, [&] {
                       return launch_gram_orth(G, X, kb, pass == 0 ? tol : 1e-6, kept + (c0 / B) * nseg, s, nseg,
-                                              (pass == 0 && c0 > 0) ? R : nullptr);
+                                              (pass == 0 && c0 > 0) ? reinterpret_cast<const double*>(R)
+                                                                    : nullptr);
                     }));
       LSOP_HIP(p_update<T>("orth_update", src, kb, X, (size_t)kb * kb, kb, nullptr, nullptr, 0.0, dst, nullptr, n, seg,
                            s));

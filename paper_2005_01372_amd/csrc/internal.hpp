@@ -167,9 +167,12 @@ hipError_t launch_gemm_update_seg(const Cx<T>* A, int na, const Cx<MT>* M, size_
                                   const Cx<T>* X1, const Cx<T>* X2, double beta, Cx<T>* Y, const int* vidx, size_t n,
                                   size_t seg, hipStream_t s);
 // small FP64 dense kernels (one workgroup per batch entry, entries na * na apart); gram_orth: na <= 64
-// gref (optional): Gram matrices whose diagonals are the drop references (default: G's own)
+// gnorm (optional): the drop test's reference squared column norms, na per batch entry (default: G's own diagonal)
 hipError_t launch_gram_orth(const Cx<double>* G, Cx<double>* X, int na, double drop_tol, int* kept, hipStream_t s,
-                            int batch = 1, const Cx<double>* gref = nullptr);
+                            int batch = 1, const double* gnorm = nullptr);
+// out[sg * na + c] = squared 2-norm of row c of Y (na rows of n) over segment sg (nseg segments of seg elements)
+template <typename T>
+hipError_t launch_seg_colnorm2(const Cx<T>* Y, int na, size_t n, size_t seg, int nseg, double* out, hipStream_t s);
 // Z_b = (I - M_b)^{-1} (plain = false) or M_b^{-1} (plain = true); M_b = M + b * sm (leading dimension ldm),
 // Z_b likewise (may alias M_b); work: batch * 2 na^2 complex doubles when na > 64; singular[b] set to 1 on
 // failure (the caller clears it).

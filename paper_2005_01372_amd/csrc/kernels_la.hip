@@ -635,18 +635,39 @@ k_gemm_update_tile(const Cx<float>* A, int na, const Cx<MT>* __restrict__ Mm, in
 // X^H G X = I.  A column whose Schur-complement diagonal (its G-norm^2 after
 // projection on the kept earlier columns) is <= drop_tol * R_kk is dropped: its
 // row of R and its column of X are zero and it takes no part in later
-// eliminations; R = gref (the Gram matrix of the columns before an earlier
-// projection) or G itself.  One workgroup of four waves per batch entry b (G_b,
-// X_b, R_b at b * na * na, kept[b]).  The right-looking factorisation is run
+// eliminations; R_kk is gnorm[b][k] (the squared norm of column k before an
+// earlier projection, na per batch entry) or G's own diagonal.  One workgroup
+// of four waves per batch entry b (G_b, X_b at b * na * na, kept[b]).  The right-looking factorisation is run
 // as row operations on [G | I] in LDS: step k scales row k by 1 / sqrt(d_k)
 // (wave 0), then every later row i subtracts conj(R_ki) times it (rows split
 // over the waves, lane = column); the upper triangle of the left block becomes
 // R and the right block R^{-H} = X^H.  Two barriers per column.
 constexpr int SMALL_NA = 64;
 
+// out[sg * na + c] = sum over the segment's elements k of |Y[c][k]|^2, in FP64 (the reference norms of the
+// drop test above): one workgroup per (column c, segment sg), workgroup id sg * na + c; a fixed summation order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_seg_colnorm2(const Cx<T>* __restrict__ Y, int na, size_t n, size_t seg,
+                                                       double* __restrict__ out) {
+  const int c = (int)(blockIdx.x % (unsigned)na);
+  const size_t sg = blockIdx.x / (unsigned)na;
+  const size_t b = sg * seg, e = b + seg < n ? b + seg : n;
+  const Cx<T>* y = Y + (size_t)c * n;
+  double acc = 0.0;
+  for (size_t k = b + threadIdx.x; k < e; k += blockDim.x) {
+    const Cx<T> v = y[k];
+    acc += (double)v.re * v.re + (double)v.im * v.im;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) out[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 __global__ __launch_bounds__(256) void k_gram_orth_lds(const Cx<double>* __restrict__ Gg, Cx<double>* __restrict__ Xg,
                                                         int na, double drop_tol, int* kept,
-                                                        const Cx<double>* __restrict__ gref) {
+                                                        const double* __restrict__ gnorm) {
   constexpr int ES = SMALL_NA + 1;  // row stride of E (odd: the transposed read at the end is conflict-free)
   __shared__ Cx<double> S[SMALL_NA * SMALL_NA];  // G, reduced in place (upper triangle: R)
   __shared__ Cx<double> E[SMALL_NA * ES];        // I, taken to R^{-H} by the same row operations
@@ -658,7 +679,7 @@ __global__ __launch_bounds__(256) void k_gram_orth_lds(const Cx<double>* __restr
     S[i * SMALL_NA + c] = Gg[off + idx];
     E[i * ES + c] = Cx<double>{i == c ? 1.0 : 0.0, 0.0};
   }
-  if (t < na) g0[t] = (gref ? gref : Gg)[off + (size_t)t * na + t].re;
+  if (t < na) g0[t] = gnorm ? gnorm[(size_t)blockIdx.x * na + t] : Gg[off + (size_t)t * na + t].re;
   __syncthreads();
   int nkept = 0;
   for (int k = 0; k < na; ++k) {
@@ -1255,12 +1276,22 @@ hipError_t launch_gemm_update(const Cx<T>* A, int na, const Cx<double>* M, int n
 }
 
 hipError_t launch_gram_orth(const Cx<double>* G, Cx<double>* X, int na, double drop_tol, int* kept, hipStream_t s,
-                            int batch, const Cx<double>* gref) {
+                            int batch, const double* gnorm) {
   if (batch <= 0) return hipSuccess;
   if (na < 1 || na > SMALL_NA) return hipErrorInvalidValue;  // callers orthonormalise in blocks of <= 64 columns
-  hipLaunchKernelGGL(k_gram_orth_lds, dim3(batch), dim3(256), 0, s, G, X, na, drop_tol, kept, gref);
+  hipLaunchKernelGGL(k_gram_orth_lds, dim3(batch), dim3(256), 0, s, G, X, na, drop_tol, kept, gnorm);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_seg_colnorm2(const Cx<T>* Y, int na, size_t n, size_t seg, int nseg, double* out, hipStream_t s) {
+  if (na <= 0 || nseg <= 0) return hipSuccess;
+  if (seg == 0 || (size_t)nseg * seg < n || (size_t)(nseg - 1) * seg >= n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_seg_colnorm2<T>, dim3((unsigned)(na * nseg)), dim3(256), 0, s, Y, na, n, seg, out);
+  return hipGetLastError();
+}
+template hipError_t launch_seg_colnorm2<float>(const Cx<float>*, int, size_t, size_t, int, double*, hipStream_t);
+template hipError_t launch_seg_colnorm2<double>(const Cx<double>*, int, size_t, size_t, int, double*, hipStream_t);
 
 hipError_t launch_lu_inverse(const Cx<double>* M, size_t ldm, size_t sm, Cx<double>* Z, size_t ldz, size_t sz,
                              Cx<double>* work, int na, bool plain, int* singular, int batch, hipStream_t s) {
