@@ -164,9 +164,10 @@ __global__ void k_reduce_parts(const Cx<double>* __restrict__ part, int ksub, in
 // (re, im) operands: with A'[.][2k + p] the p-th component of a_k,
 //   conj(a) b:  re = sum_kk A'[kk] (br, bi)[kk],  im = sum_kk A'[kk] (bi, -br)[kk]
 //   m a (no conj, m on the left):  re = (mr, -mi) . (ar, ai),  im = (mi, mr) . (ar, ai).
-// The FP32 inner product instead takes three real products per complex one (Gauss's 3M form): over
-// complex k, t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar - ai)(br + bi), and then conj(a) b has
-// re = t1 + t2 and im = t3 - t1 + t2; three quarters of the matrix-core work of the two chains.
+// The complex FP32 kernels below (segmented inner product, tile-form update, batched GEMM) instead take
+// three real products per complex one (Gauss's 3M form): over complex k, t1 = sum ar br, t2 = sum ai bi and
+// t3 = sum (ar - ai)(br + bi) give conj(a) b = (t1 + t2, t3 - t1 + t2); with t3 = sum (ar + ai)(br + bi),
+// a b = (t1 - t2, t3 - t1 - t2).  Three quarters of the matrix-core work of the two chains.
 typedef float lsop_f4 __attribute__((ext_vector_type(4)));
 typedef double lsop_d4 __attribute__((ext_vector_type(4)));
 
