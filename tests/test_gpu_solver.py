@@ -80,6 +80,37 @@ def test_precond_fp32_many_vectors_matches_oracle():
     assert rel(host(pc.apply(dev(x, torch.complex64))), H.apply(x)) <= 2e-5
 
 
+@pytest.mark.parametrize("dtype", [lsop.C64, lsop.C128])
+def test_profiler_counts_gemm_flops_of_each_form(dtype):
+    """The library's profiler, whose counts the bench's roofline divides by kernel time, counts 6 real flops per
+    complex multiply-add for the complex-FP32 GEMMs (Gauss's 3M form: three real products per complex one) and 8
+    for complex FP64 (real and imaginary chains): W^H x and U (Z .) of a rank-96 preconditioner on 40 vectors."""
+    announce(f"profiler gemm flops dtype={dtype}")
+    w = cfg1(48)
+    r, nv, n = 96, 40, 48 * 48
+    om = synth.gaussian_probes(n, r, 13)
+    op = make_op(w, dtype, 8)
+    pc = lsop.Preconditioner(op, lsop.PC_LOWRANK, rank=r)
+    pc.build(torch.as_tensor(om).cuda())
+    tdt = torch.complex64 if dtype == lsop.C64 else torch.complex128
+    x = dev(synth.random_vectors((nv, 48, 48), 6), tdt)
+    torch.cuda.synchronize()
+    lsop.profile_reset()
+    lsop.profile_enable(True)
+    try:
+        pc.apply(x)
+        torch.cuda.synchronize()
+        ks = lsop.profile_read(by_kernel=True)
+    finally:
+        lsop.profile_enable(False)
+    per = (6.0 if dtype == lsop.C64 else 8.0) * r * nv * n
+    t = "float" if dtype == lsop.C64 else "double"
+    ahb = ks[f"k_gemm_ah_b_mfma<{t}>"]
+    assert ahb["launches"] == 1 and ahb["flops"] == per, ahb
+    upd = "k_gemm_update_tile<double>" if dtype == lsop.C64 else "k_gemm_update_mfma<double, double, 4, 4, 3>"
+    assert ks[upd]["launches"] == 1 and ks[upd]["flops"] == per, (upd, sorted(ks))
+
+
 def test_precond_rank_above_128_matches_oracle():
     """Z = (I - W^H U)^{-1} of more than 128 probes takes the pivoted Gauss-Jordan in global memory, whose
     thread layout (one column per thread, fewer threads than 2 * rank) differs from the small-block kernel."""
